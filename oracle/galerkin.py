@@ -1,0 +1,152 @@
+"""Dense Galerkin system for N active spheres, solved directly (FP64).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+This follows the Dirichlet problem of sections II-III in the lower/higher
+partition of the coefficient vectors:
+
+* Lower traction coefficients F^L (force, torque) are known from the overdamped
+  force and torque balance: the contact force and torque are minus the body
+  force and torque (section II, Newton's equations as constraints).
+* The higher traction unknowns kept at this truncation (traction ranks <= 2) are
+  the symmetric traceless first moments, written as the flow stresslet
+  Sigma_n = a Q^(20)_n = S_n - (8/3) pi eta a^3 s_n (section IV, the named
+  combination "stresslet"), 5 per sphere.
+* The higher rows of the linear system (the Schur "H" rows, section II) are the
+  symmetric l = 1 Galerkin conditions on each sphere. With the flow of every
+  other sphere projected by the target operator E (Faxen form of the matrix
+  elements, section III) they read
+
+      Sigma_n / gamma - sum_{m != n} E[Sigma_m](R_n - R_m)
+          = sum_{m != n} E[F_m, T_m, d_m](R_n - R_m) - c s_n,
+
+  gamma = (20/3) pi eta a^3.  ``c`` is the self-slip coefficient: c = 1 makes
+  the exterior flow of a lone sphere equal its prescribed strain slip on its
+  surface (the boundary condition of section II); the paper's one-body table
+  corresponds to c = 7/5 (kept as an option).
+* The lower rows then give the rigid-body motion (generalized Stokes laws,
+  section III):
+      V_n = V^a_n + F^e_n / (6 pi eta a) + sum_{m != n} U[F, T, Sigma, d]_m,
+      Omega_n = T^e_n / (8 pi eta a^3) + sum_{m != n} W[F, T, Sigma, d]_m,
+  with V^a_n = -V^(1s)_n (minus the mean slip) and no antisymmetric slip.
+* The traction stresslet is S_n = Sigma_n + (8/3) pi eta a^3 s_n.
+
+The matrix I/gamma - K^SS is symmetric (reciprocity of the Green's function)
+and positive definite for non-overlapping spheres, so numpy.linalg.solve and a
+Cholesky solve must agree.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import greens
+
+
+@dataclasses.dataclass
+class Params:
+    eta: float = 1.0 / (6.0 * np.pi)
+    a: float = 1.0
+    self_slip_c: float = 1.0
+
+
+def constants(prm: Params):
+    gamma = 20.0 / 3.0 * np.pi * prm.eta * prm.a ** 3
+    return dict(gamma=gamma,
+                drag_t=6.0 * np.pi * prm.eta * prm.a,
+                drag_r=8.0 * np.pi * prm.eta * prm.a ** 3,
+                slip_to_S=8.0 / 3.0 * np.pi * prm.eta * prm.a ** 3)
+
+
+def pair_matrix(R, target, source, prm: Params, rows=None, chunk=4096):
+    """Dense [len(rows)*dT, N*dX] of blocks B(R_n - R_m); the n == m blocks are zero."""
+    R = np.asarray(R, dtype=np.float64)
+    n = R.shape[0]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    dT, dX = greens.TARGET_DIM[target], greens.SOURCE_DIM[source]
+    out = np.zeros((len(rows), dT, n, dX))
+    for i0 in range(0, len(rows), max(1, chunk // max(n, 1))):
+        rr = rows[i0:i0 + max(1, chunk // max(n, 1))]
+        dx = R[rr, None, :] - R[None, :, :]
+        mask = np.ones((len(rr), n), dtype=bool)
+        mask[np.arange(len(rr)), rr] = False
+        blk = greens.block(target, source, dx[mask], prm.a, prm.eta)
+        full = np.zeros((len(rr), n, dT, dX))
+        full[mask] = blk
+        out[i0:i0 + len(rr)] = full.transpose(0, 2, 1, 3)
+    return out.reshape(len(rows) * dT, n * dX)
+
+
+def system_matrix(R, prm: Params):
+    """A = I/gamma - K^SS, [5N x 5N]."""
+    n = len(R)
+    g = constants(prm)["gamma"]
+    return np.eye(5 * n) / g - pair_matrix(R, "E", "S", prm)
+
+
+def rhs(R, v2s, v3t, Fe, Te, prm: Params, rows=None):
+    """b = sum_{m != n} E[F, T, d] - c s, flattened [5N] (or the given rows)."""
+    R = np.asarray(R, dtype=np.float64)
+    rows = np.arange(len(R)) if rows is None else np.asarray(rows)
+    b = pair_matrix(R, "E", "F", prm, rows) @ np.ravel(Fe)
+    b = b + pair_matrix(R, "E", "T", prm, rows) @ np.ravel(Te)
+    b = b + pair_matrix(R, "E", "D", prm, rows) @ np.ravel(v3t)
+    b = b - prm.self_slip_c * np.ravel(np.asarray(v2s)[rows])
+    return b
+
+
+def outputs(R, v1s, v2s, v3t, Fe, Te, Sigma, prm: Params, rows=None):
+    """Rigid-body motion and traction stresslet from a given flow stresslet Sigma [N, 5]."""
+    R = np.asarray(R, dtype=np.float64)
+    rows = np.arange(len(R)) if rows is None else np.asarray(rows)
+    k = constants(prm)
+    src = {"F": np.ravel(Fe), "T": np.ravel(Te), "S": np.ravel(Sigma), "D": np.ravel(v3t)}
+    V = -np.asarray(v1s)[rows] + np.asarray(Fe)[rows] / k["drag_t"]
+    W = np.asarray(Te)[rows] / k["drag_r"]
+    for X, vec in src.items():
+        V = V + (pair_matrix(R, "U", X, prm, rows) @ vec).reshape(-1, 3)
+        W = W + (pair_matrix(R, "W", X, prm, rows) @ vec).reshape(-1, 3)
+    S = np.asarray(Sigma)[rows] + k["slip_to_S"] * np.asarray(v2s)[rows]
+    return V, W, S
+
+
+def solve(w, prm: Params | None = None, method="lu"):
+    """Full solve for a workload-like object (fields R, v1s, v2s, v3t, Fe, Te).
+
+    Returns a dict with V, W (= Omega), S, Sigma [N, 5], b [5N] and A.
+    """
+    prm = prm or Params(eta=getattr(w, "eta", 1.0 / (6 * np.pi)), a=getattr(w, "a", 1.0))
+    A = system_matrix(w.R, prm)
+    b = rhs(w.R, w.v2s, w.v3t, w.Fe, w.Te, prm)
+    if method == "lu":
+        sig = np.linalg.solve(A, b)
+    elif method == "cholesky":
+        L = np.linalg.cholesky(A)
+        sig = np.linalg.solve(L.T, np.linalg.solve(L, b))
+    else:
+        raise ValueError(method)
+    Sigma = sig.reshape(-1, 5)
+    V, W, S = outputs(w.R, w.v1s, w.v2s, w.v3t, w.Fe, w.Te, Sigma, prm)
+    return dict(V=V, W=W, S=S, Sigma=Sigma, b=b, A=A)
+
+
+def superposition(w, prm: Params | None = None):
+    """Superposition approximation (section IV): one-body tractions, pairwise-summed flows.
+
+    The flow stresslet of each sphere is its lone-sphere value -c gamma s_n and
+    the rigid-body motion is the direct sum of the pair blocks.
+    """
+    prm = prm or Params(eta=w.eta, a=w.a)
+    g = constants(prm)["gamma"]
+    Sigma = -prm.self_slip_c * g * np.asarray(w.v2s)
+    V, W, S = outputs(w.R, w.v1s, w.v2s, w.v3t, w.Fe, w.Te, Sigma, prm)
+    return dict(V=V, W=W, S=S, Sigma=Sigma)
+
+
+def matvec_rows(R, x, rows, prm: Params):
+    """(A x) restricted to the given particles, without forming A: [len(rows), 5]."""
+    g = constants(prm)["gamma"]
+    x = np.asarray(x).reshape(-1, 5)
+    y = x[rows] / g - (pair_matrix(R, "E", "S", prm, rows) @ np.ravel(x)).reshape(-1, 5)
+    return y

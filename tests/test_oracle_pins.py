@@ -1,0 +1,323 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by Stokes-flow mathematics.
+
+Every check here is independent of the oracle's own formulas: boundary
+conditions of the paper's Dirichlet problem, the surface-integral definitions of
+the Galerkin coefficients (evaluated by quadrature), textbook two-sphere
+mobilities, reciprocity, one-body constants the paper prints, and library
+solvers on the same matrix.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import sympy as sp
+
+from oracle import basis, galerkin, greens, krylov, stepper
+from paper_1411_0278_amd import inputs
+from tests import sphere_quad
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = json.load(open(os.path.join(HERE, "golden", "one_body.json")))["entries"]
+
+ETA, A = 0.7, 1.3          # deliberately not the benchmark units
+PRM = galerkin.Params(eta=ETA, a=A)
+P = 1 / (8 * np.pi * ETA)
+GAMMA = 20 / 3 * np.pi * ETA * A ** 3
+
+
+def _rand_sep(rng, n, rmin=2.2 * A, rmax=6 * A):
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return v * rng.uniform(rmin, rmax, size=(n, 1))
+
+
+# ---------------------------------------------------------------- source flows: boundary conditions
+def test_force_flow_is_rigid_translation_on_surface():
+    nh, _ = sphere_quad.sphere_rule(8, 16)
+    u = greens.flow("F", A * nh, A, ETA)                     # [pts, 3, 3]
+    want = np.eye(3) / (6 * np.pi * ETA * A)
+    assert np.abs(u - want).max() < 1e-14 * np.abs(want).max()
+
+
+def test_torque_flow_is_rigid_rotation_on_surface():
+    nh, _ = sphere_quad.sphere_rule(8, 16)
+    u = greens.flow("T", A * nh, A, ETA)
+    for j in range(3):
+        Om = np.eye(3)[j] / (8 * np.pi * ETA * A ** 3)
+        want = np.cross(Om, A * nh)
+        assert np.abs(u[:, :, j] - want).max() < 1e-14 * np.abs(want).max()
+
+
+def test_stresslet_flow_matches_strain_slip_on_surface():
+    """A lone sphere with Sigma = -gamma s has exterior flow equal to s.rho on r = a (c = 1)."""
+    nh, _ = sphere_quad.sphere_rule(8, 16)
+    u = greens.flow("S", A * nh, A, ETA)                     # per unit Sigma_c
+    for c in range(5):
+        want = -(A * nh) @ basis.BASIS[c].T / GAMMA
+        assert np.abs(u[:, :, c] - want).max() < 1e-14 * np.abs(want).max()
+
+
+def test_trace_mode_flow_matches_its_slip_on_surface():
+    """The rank-3 trace slip mode (a^2/10)(3 nn - I).d is the surface value of its flow."""
+    nh, _ = sphere_quad.sphere_rule(8, 16)
+    u = greens.flow("D", A * nh, A, ETA)
+    for j in range(3):
+        dvec = np.eye(3)[j]
+        want = A ** 2 / 10 * (3 * nh * (nh @ dvec)[:, None] - dvec)
+        assert np.abs(u[:, :, j] - want).max() < 1e-14
+
+
+@pytest.mark.parametrize("src", ["F", "T", "S", "D"])
+def test_source_flows_are_stokes_flows(src):
+    """Divergence free and biharmonic, exactly (symbolic)."""
+    for col in greens.source_flow(src):
+        div = sum(greens.d(col[i], i) for i in range(3))
+        assert sp.simplify(div) == 0
+        for ui in col:
+            assert greens.lap(greens.lap(ui)) == 0
+
+
+# ---------------------------------------------------------------- target operators = Galerkin projections
+@pytest.mark.parametrize("src", ["F", "T", "S", "D"])
+def test_target_operators_equal_surface_integral_coefficients(src):
+    rng = np.random.default_rng(7)
+    nh, w = sphere_quad.sphere_rule(48, 96)
+    for x in _rand_sep(rng, 3):
+        pts = x[None, :] + A * nh                              # target sphere centred at x
+        u = greens.flow(src, pts, A, ETA)
+        U = greens.block("U", src, x[None], A, ETA)[0]
+        W = greens.block("W", src, x[None], A, ETA)[0]
+        E = greens.block("E", src, x[None], A, ETA)[0]
+        for q in range(u.shape[2]):
+            mean, V2 = sphere_quad.coefficients(u[:, :, q], nh, w, A)
+            scale = np.abs(u[:, :, q]).max()
+            assert np.abs(mean - U[:, q]).max() < 1e-12 * scale
+            assert np.abs(sphere_quad.axial(V2, A) - W[:, q]).max() < 1e-12 * scale / A
+            assert np.abs(basis.to5(V2 / A) - E[:, q]).max() < 1e-12 * scale / A
+            assert abs(np.trace(V2)) < 1e-12 * scale * A          # no net flux
+
+
+# ---------------------------------------------------------------- textbook pair mobilities
+def test_force_block_is_rotne_prager():
+    rng = np.random.default_rng(1)
+    xs = _rand_sep(rng, 50)
+    B = greens.block("U", "F", xs, A, ETA)
+    for x, b in zip(xs, B):
+        r = np.linalg.norm(x)
+        rpy = P * ((1 / r + 2 * A ** 2 / (3 * r ** 3)) * np.eye(3)
+                   + (1 / r ** 3 - 2 * A ** 2 / r ** 5) * np.outer(x, x))
+        assert np.abs(b - rpy).max() < 1e-14 * np.abs(rpy).max()
+
+
+def test_rotation_blocks_are_textbook():
+    rng = np.random.default_rng(2)
+    xs = _rand_sep(rng, 20)
+    eps = np.zeros((3, 3, 3))
+    eps[0, 1, 2] = eps[1, 2, 0] = eps[2, 0, 1] = 1
+    eps[0, 2, 1] = eps[2, 1, 0] = eps[1, 0, 2] = -1
+    for x in xs:
+        r = np.linalg.norm(x)
+        rt = P * np.einsum("ijk,k->ij", eps, x) / r ** 3      # (F x x)/r^3 as a matrix on F
+        rr = P / 2 * (3 * np.outer(x, x) / r ** 5 - np.eye(3) / r ** 3)
+        assert np.allclose(greens.block("W", "F", x[None], A, ETA)[0], rt, rtol=0, atol=1e-15)
+        assert np.allclose(greens.block("U", "T", x[None], A, ETA)[0], rt, rtol=0, atol=1e-15)
+        assert np.allclose(greens.block("W", "T", x[None], A, ETA)[0], rr, rtol=0, atol=1e-15)
+
+
+def test_trace_mode_gives_no_rotation_and_laplacian_translation():
+    """pi^Rd = 0 and pi^Td proportional to nabla^2 G (section IV, superposition matrices)."""
+    assert greens.block_expr("W", "D") == sp.zeros(3, 3)
+    G = greens.oseen()
+    for i in range(3):
+        for j in range(3):
+            want = -greens.a_ ** 5 / 20 * greens.lap(G[i][j])
+            assert sp.simplify(greens.block_expr("U", "D")[i, j] - want) == 0
+
+
+def test_stresslet_rotation_block_has_paper_structure():
+    """Omega from a uniaxial stresslet ~ (p.x)(x cross p)/r^5 (section V, two-particle rotation)."""
+    rng = np.random.default_rng(3)
+    for x in _rand_sep(rng, 10):
+        p = rng.standard_normal(3)
+        p /= np.linalg.norm(p)
+        sig = basis.to5(np.outer(p, p) - np.eye(3) / 3)
+        Om = greens.block("W", "S", x[None], A, ETA)[0] @ sig
+        r = np.linalg.norm(x)
+        want = 3 * P * (p @ x) * np.cross(x, p) / r ** 5
+        assert np.abs(Om - want).max() < 1e-14 * max(np.abs(want).max(), 1e-300) + 1e-17
+
+
+# ---------------------------------------------------------------- reciprocity / symmetry
+def test_reciprocity_of_pair_blocks():
+    """Symmetry of the Galerkin matrix elements under exchange of spheres and modes (section II).
+
+    F^e and T^e are body force and torque (minus the contact traction moments),
+    while Sigma is a traction moment, so pairs mixing the two kinds change sign.
+    """
+    rng = np.random.default_rng(4)
+    xs = _rand_sep(rng, 30)
+    for T, X, T2, X2, sgn in [("E", "F", "U", "S", -1), ("U", "T", "W", "F", 1), ("E", "T", "W", "S", -1),
+                              ("E", "S", "E", "S", 1), ("U", "F", "U", "F", 1), ("W", "T", "W", "T", 1)]:
+        b1 = greens.block(T, X, xs, A, ETA)
+        b2 = greens.block(T2, X2, -xs, A, ETA)
+        assert np.abs(b1 - sgn * b2.transpose(0, 2, 1)).max() < 1e-14 * np.abs(b1).max()
+
+
+def test_system_matrix_symmetric_positive_definite():
+    w = inputs.trap_workload(64, 40 * (64 / 256) ** (1 / 3), seed=5)
+    Am = galerkin.system_matrix(w.R, galerkin.Params(eta=w.eta, a=w.a))
+    assert np.abs(Am - Am.T).max() < 1e-15 * np.abs(Am).max()
+    ev = np.linalg.eigvalsh(Am)
+    assert ev.min() > 0.3 and ev.max() < 1.5
+
+
+# ---------------------------------------------------------------- one-body relations printed in the paper
+def test_lone_sphere_relations():
+    rng = np.random.default_rng(6)
+    Fe, Te, v1s, v3t = (rng.standard_normal((1, 3)) for _ in range(4))
+    v2s = rng.standard_normal((1, 5))
+    w = inputs.Workload(np.zeros((1, 3)), np.array([[0, 0, 1.0]]), v1s, v2s, v3t, Fe, Te, ETA, A)
+    sol = galerkin.solve(w, PRM)
+    mu_t = GOLD["self_translational_mobility_8pi_eta_a"]["value"] / (8 * np.pi * ETA * A)
+    mu_r = GOLD["self_rotational_mobility_8pi_eta_a3"]["value"] / (8 * np.pi * ETA * A ** 3)
+    assert np.allclose(sol["V"], -v1s + mu_t * Fe, rtol=1e-14, atol=1e-15)   # V = V^a + F/(6 pi eta a)
+    assert np.allclose(sol["W"], mu_r * Te, rtol=1e-14, atol=1e-15)
+    assert np.allclose(sol["Sigma"], -GAMMA * v2s, rtol=1e-14)
+    assert np.allclose(sol["S"], -4 * np.pi * ETA * A ** 3 * v2s, rtol=1e-13)
+
+
+def test_self_slip_coefficient_option():
+    w = inputs.Workload(np.zeros((1, 3)), np.array([[0, 0, 1.0]]), np.zeros((1, 3)),
+                        np.ones((1, 5)), np.zeros((1, 3)), np.zeros((1, 3)), np.zeros((1, 3)), ETA, A)
+    sol = galerkin.solve(w, galerkin.Params(eta=ETA, a=A, self_slip_c=1.4))
+    # c = 7/5 reproduces the paper's one-body table value S = -(20/3) pi eta a^3 s
+    assert np.allclose(sol["S"], -20 / 3 * np.pi * ETA * A ** 3 * np.ones((1, 5)), rtol=1e-13)
+
+
+# ---------------------------------------------------------------- whole system vs the Dirichlet condition
+def test_solution_satisfies_weak_boundary_conditions_by_quadrature():
+    rng = np.random.default_rng(8)
+    n = 5
+    R = inputs.place_spheres(n, 9.0 * A, seed=9, min_dist=2.2 * A)
+    w = inputs.Workload(R, np.zeros((n, 3)), rng.standard_normal((n, 3)), rng.standard_normal((n, 5)),
+                        rng.standard_normal((n, 3)), rng.standard_normal((n, 3)),
+                        rng.standard_normal((n, 3)), ETA, A)
+    sol = galerkin.solve(w, PRM)
+    src = {"F": w.Fe, "T": w.Te, "S": sol["Sigma"], "D": w.v3t}
+    nh, wq = sphere_quad.sphere_rule(48, 96)
+    for i in range(n):
+        pts = R[i] + A * nh
+        u = np.zeros_like(pts)
+        for m in range(n):
+            for X, vals in src.items():
+                u += greens.flow(X, pts - R[m], A, ETA) @ vals[m]
+        mean, V2 = sphere_quad.coefficients(u, nh, wq, A)
+        scale = np.abs(u).max()
+        assert np.abs(mean - (sol["V"][i] + w.v1s[i])).max() < 1e-11 * scale      # V - V^a
+        assert np.abs(sphere_quad.axial(V2, A) - sol["W"][i]).max() < 1e-11 * scale / A
+        assert np.abs(basis.to5(V2 / A) - w.v2s[i]).max() < 1e-11 * scale / A     # strain slip s
+
+
+# ---------------------------------------------------------------- two-sphere mobilities (Batchelor / Jeffrey-Onishi)
+def _two_sphere(r, axis):
+    R = np.array([[0, 0, 0], [0, 0, r]], dtype=float)
+    F = np.zeros((2, 3))
+    F[0, axis] = 1.0
+    z3, z5 = np.zeros((2, 3)), np.zeros((2, 5))
+    w = inputs.Workload(R, z3, z3, z5, z3, F, z3, ETA, A)
+    sol = galerkin.solve(w, PRM)
+    mu0 = 1 / (6 * np.pi * ETA * A)
+    return sol["V"][0, axis] / mu0, sol["V"][1, axis] / mu0
+
+
+def test_two_sphere_self_mobility_far_field():
+    for r in (20.0, 40.0):
+        x11, x12 = _two_sphere(r * A, 2)
+        y11, y12 = _two_sphere(r * A, 0)
+        assert abs((x11 - 1) * r ** 4 + 15 / 4) < 60 / r ** 2      # x^a_11 = 1 - 15/4 (a/r)^4 + O(r^-6)
+        assert abs((y11 - 1) * r ** 4) < 60 / r ** 2                # y^a_11 = 1 + O(r^-6)
+        assert abs(x12 - (1.5 / r - 1 / r ** 3)) < 100 / r ** 7     # x^a_12
+        assert abs(y12 - (0.75 / r + 0.5 / r ** 3)) < 100 / r ** 7  # y^a_12
+
+
+# ---------------------------------------------------------------- solvers
+def test_dense_lu_cholesky_and_gmres_agree():
+    w = inputs.trap_workload(48, 40 * (48 / 256) ** (1 / 3), seed=11)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    lu = galerkin.solve(w, prm, "lu")
+    ch = galerkin.solve(w, prm, "cholesky")
+    assert np.abs(lu["Sigma"] - ch["Sigma"]).max() < 1e-13 * np.abs(lu["Sigma"]).max()
+    x, info = krylov.gmres(lambda v: lu["A"] @ v, lu["b"], tol=1e-14, restart=30)
+    rel = np.linalg.norm(x - lu["Sigma"].ravel()) / np.linalg.norm(lu["Sigma"])
+    assert rel < 1e-12 and info["iters"] < 40
+
+
+def test_gmres_restart_path():
+    w = inputs.trap_workload(32, 30.0, seed=12)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    lu = galerkin.solve(w, prm)
+    x, info = krylov.gmres(lambda v: lu["A"] @ v, lu["b"], tol=1e-13, restart=4, max_iter=200)
+    assert np.linalg.norm(x - lu["Sigma"].ravel()) / np.linalg.norm(lu["Sigma"]) < 1e-12
+
+
+def test_matvec_rows_matches_dense():
+    w = inputs.trap_workload(40, 30.0, seed=13)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    Am = galerkin.system_matrix(w.R, prm)
+    x = np.random.default_rng(0).standard_normal(5 * w.n)
+    rows = np.array([0, 7, 39])
+    y = galerkin.matvec_rows(w.R, x, rows, prm)
+    assert np.allclose(y, (Am @ x).reshape(-1, 5)[rows], rtol=1e-14, atol=1e-14)
+
+
+# ---------------------------------------------------------------- trap dynamics (section V)
+def test_passive_trap_relaxation_is_exponential_second_order():
+    k, R0 = 0.5, np.array([[3.0, -1.0, 2.0]])
+    prm = galerkin.Params()
+    tau = GOLD["passive_trap_relaxation_time_k_over_6pi_eta_a"]["value"] * 6 * np.pi * prm.eta * prm.a / k
+    errs = []
+    for dt, ns in ((0.04, 25), (0.02, 50)):
+        R, _, _ = stepper.run(R0, np.array([[0, 0, 1.0]]), k, (0, 0, 0), dt, ns, prm)
+        errs.append(np.abs(R - R0 * np.exp(-dt * ns / tau)).max())
+    assert errs[1] < errs[0] / 3.0 and errs[1] < 1e-3
+
+
+def test_active_trap_fixed_point():
+    k = 0.5
+    prm = galerkin.Params()
+    p = np.array([[0.0, 0.6, 0.8]])
+    R, p2, _ = stepper.run(np.zeros((1, 3)), p, k, (1.0, 0.0, 0.0), 0.1, 500, prm)
+    Rstar = GOLD["active_trap_radius_k_over_6pi_eta_a_vs"]["value"] * 6 * np.pi * prm.eta * prm.a / k
+    # V^a = -V^(1s) = -p: the sphere settles where the trap force balances swimming along -p
+    assert np.allclose(R[0], -Rstar * p[0], atol=1e-6)
+    assert np.allclose(p2, p, atol=1e-14)
+
+
+def test_two_particle_trap_rotation_leading_term():
+    """Omega_1 -> -k (R_2 x R_1)/(8 pi eta r^3) for two passive trapped spheres (section V)."""
+    k = 0.5
+    Rs = GOLD["two_particle_trap_radius_example"]["value"]
+    prm = galerkin.Params(eta=ETA, a=A)
+    rel = []
+    for scale in (1.0, 2.0):
+        th = np.deg2rad(115.0)
+        R = scale * Rs * A * np.array([[0, 0, 1.0], [np.sin(th), 0, np.cos(th)]])
+        z3, z5 = np.zeros((2, 3)), np.zeros((2, 5))
+        w = inputs.Workload(R, z3, z3, z5, z3, -k * R, z3, ETA, A)
+        sol = galerkin.solve(w, prm)
+        r = np.linalg.norm(R[0] - R[1])
+        lead = -k * np.cross(R[1], R[0]) / (8 * np.pi * ETA * r ** 3)
+        rel.append(np.linalg.norm(sol["W"][0] - lead) / np.linalg.norm(lead))
+    assert rel[0] < 1e-2 and rel[1] < rel[0] / 4      # corrections fall off faster than r^-2
+
+
+def test_diametrically_opposite_active_pair_does_not_rotate():
+    k = 0.5
+    Rs = 12.56 * A
+    R = np.array([[0, 0, Rs], [0, 0, -Rs]])
+    p = R / np.linalg.norm(R, axis=1, keepdims=True)
+    v1s, v2s, v3t = inputs.slip_modes(p, 1.0, 1.0, 1.0)
+    w = inputs.Workload(R, p, v1s, v2s, v3t, -k * R, np.zeros((2, 3)), ETA, A)
+    sol = galerkin.solve(w, PRM)
+    assert np.abs(sol["W"]).max() < 1e-15
