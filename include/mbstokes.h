@@ -1,0 +1,178 @@
+/*
+ * mbstokes.h - C ABI of the many-body active-sphere Stokes solver (MI355X / gfx950).
+ *
+ * Method: Galerkin discretisation of the boundary-integral equation of Stokes
+ * flow for N spheres of radius a with active (Dirichlet) slip, Singh, Ghose &
+ * Adhikari, "Many-body microhydrodynamics of colloidal particles with active
+ * boundary layers" (arXiv:1411.0278).
+ *
+ *   - Known lower traction coefficients: the contact force and torque balance
+ *     the body force F^e and torque T^e (section II, overdamped Newton's
+ *     equations as constraints).
+ *   - Unknown higher coefficients kept at this truncation (traction ranks <= 2,
+ *     i.e. force, torque and stresslet): the flow stresslet
+ *     Sigma_n = a Q^(20)_n (section IV, named combinations), 5 per sphere.
+ *   - Linear system: the symmetric l = 1 Galerkin rows (section II, Schur
+ *     "higher" rows; section III, off-diagonal matrix elements as derivatives of
+ *     the Green's function with the finite-size operators F^l):
+ *        Sigma_n / gamma - sum_{m != n} E[Sigma_m] = sum_{m != n} E[F, T, d] - c s_n,
+ *     gamma = (20/3) pi eta a^3, solved matrix-free by GMRES.
+ *   - Outputs: rigid-body motion by the generalized Stokes laws (section III),
+ *        V_n = V^a_n + F^e_n/(6 pi eta a) + sum_{m != n} U[F, T, Sigma, d],
+ *        Omega_n = T^e_n/(8 pi eta a^3) + sum_{m != n} W[F, T, Sigma],
+ *     with V^a_n = -V^(1s)_n, and the traction stresslet S_n = Sigma_n + (8/3) pi eta a^3 s_n.
+ *
+ * Conventions for every entry point below:
+ *   - Arrays are caller-owned, contiguous, row-major, particle-major, IEEE
+ *     binary64, and live in DEVICE memory of the context's GPU (for example
+ *     torch.float64 CUDA tensors). Vectors are [n x 3]; symmetric traceless
+ *     rank-2 quantities (s, Sigma, S, strains) are [n x 5] in the orthonormal
+ *     basis  B0 = (xx - yy)/sqrt2, B1 = (2zz - xx - yy)/sqrt6,
+ *     B2 = (xy + yx)/sqrt2, B3 = (xz + zx)/sqrt2, B4 = (yz + zy)/sqrt2.
+ *   - Optional inputs may be NULL, meaning zero.
+ *   - Work is enqueued on `stream` (NULL = the default stream); every call
+ *     returns after its work on that stream has completed.
+ *   - Return value: MBS_OK or a negative error code; the message for the last
+ *     failure on the context is available from mbs_last_error. No C++
+ *     exception crosses this interface. On an error no output is written
+ *     unless the description says otherwise.
+ *   - A context may be used by one host thread at a time; calls on one context
+ *     are serialised by the caller.
+ */
+#ifndef MBSTOKES_H
+#define MBSTOKES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MBS_OK            0
+#define MBS_EINVAL       -1  /* bad argument: NULL required pointer, n < 1, bad option, non-finite value */
+#define MBS_ENOCONV      -2  /* iteration cap reached; outputs hold the last iterate, stats->rel_resid is set */
+#define MBS_EOVERLAP     -3  /* two centres closer than 2a (only when check_overlap is set) */
+#define MBS_EUNSUPPORTED -4  /* option not supported (for example lmax != 2) */
+#define MBS_ENOMEM       -5  /* device allocation failed */
+#define MBS_EHIP         -6  /* HIP runtime error; the HIP message is in mbs_last_error */
+
+#define MBS_FP64   0   /* pair blocks and Krylov arithmetic in binary64 */
+#define MBS_MIXED  1   /* binary32 pair blocks with compensated accumulation inside a binary64
+                          iterative refinement; residuals and corrections in binary64 */
+#define MBS_FP32   1   /* precision selector of mbs_matvec: binary32 pair blocks */
+
+#define MBS_GUESS_ZERO     0   /* Sigma^0 = 0 */
+#define MBS_GUESS_DIAG     1   /* Sigma^0 = gamma b: the one-body (diagonal) solve of the system */
+#define MBS_GUESS_LEARNED  2   /* Sigma^0 = gamma b + MLP(neighbourhood), needs mbs_warmstart_load */
+#define MBS_GUESS_USER     3   /* Sigma^0 = the caller's sigma0 */
+
+typedef struct mbs_params {
+  double  eta;           /* viscosity (> 0) */
+  double  a;             /* sphere radius (> 0) */
+  double  tol;           /* stop when ||b - A Sigma||_2 / ||b||_2 <= tol (binary64 residual) */
+  double  self_slip_c;   /* c in "- c s_n": 1 = lone sphere meets its strain slip exactly;
+                            1.4 reproduces the paper's one-body stresslet table */
+  double  inner_tol;     /* MBS_MIXED: relative tolerance of each inner binary32 GMRES solve */
+  int32_t lmax;          /* traction truncation rank; only 2 (force, torque, stresslet) */
+  int32_t max_iter;      /* cap on GMRES iterations (all restarts, inner iterations included) */
+  int32_t restart;       /* GMRES restart length m, 1..64 */
+  int32_t precision;     /* MBS_FP64 or MBS_MIXED */
+  int32_t guess;         /* MBS_GUESS_* */
+  int32_t check_overlap; /* nonzero: mbs_solve fails with MBS_EOVERLAP if some |R_n - R_m| < 2a */
+  int32_t tile;          /* pair-kernel launch shape: 0 = tuned default, else an index from mbs_autotune */
+  int32_t reserved;
+} mbs_params;
+
+typedef struct mbs_stats {
+  int32_t iters;          /* GMRES iterations (Arnoldi steps), all restarts and refinements */
+  int32_t refinements;    /* MBS_MIXED outer refinement steps */
+  int32_t fp64_matvecs;   /* binary64 operator applications */
+  int32_t fp32_matvecs;   /* binary32 operator applications */
+  double  rel_resid;      /* final ||b - A Sigma||_2 / ||b||_2, evaluated in binary64 */
+  double  t_total_ms;     /* device time of the whole call */
+  double  t_rhs_ms;       /* right-hand side pass */
+  double  t_iter_ms;      /* guess + iterations + refinement residuals */
+  double  t_out_ms;       /* rigid-body output pass */
+  double  pair_blocks;    /* pair-block evaluations performed (all passes) */
+} mbs_stats;
+
+typedef struct mbs_ctx mbs_ctx;
+
+/* Fill *prm with the defaults: eta = 1/(6 pi), a = 1, tol = 1e-10, c = 1, inner_tol = 1e-5,
+   lmax = 2, max_iter = 300, restart = 30, MBS_FP64, MBS_GUESS_ZERO, no overlap check. */
+void mbs_default_params(mbs_params* prm);
+
+/* Create a context on HIP device `device`. *ctx receives the handle (NULL on failure).
+   The context owns its device workspace (grown on demand, freed by mbs_destroy). */
+int mbs_create(mbs_ctx** ctx, int device, const mbs_params* prm);
+void mbs_destroy(mbs_ctx* ctx);
+/* Replace the parameters of an existing context (validated as in mbs_create). */
+int mbs_set_params(mbs_ctx* ctx, const mbs_params* prm);
+/* Message of the last failure on ctx ("" if none); valid until the next call on ctx.
+   With ctx == NULL: the message of the last failed mbs_create on this thread. */
+const char* mbs_last_error(const mbs_ctx* ctx);
+
+/* Full solve (sections II-III): Sigma from the stresslet rows, then V, Omega, S.
+     R      [n x 3]  sphere centres
+     p      [n x 3]  unit orientations (read by the learned warm start; may be NULL otherwise)
+     v1s    [n x 3]  mean slip mode V^(1s); V^a = -V^(1s)
+     v2s    [n x 5]  symmetric traceless linear slip mode s = V^(2s)
+     v3t    [n x 3]  rank-3 trace slip mode d = V^(3t) (a fixed source, exterior flow
+                     (a^5/10)(3 x^ x^ - I).d / r^3)
+     Fe, Te [n x 3]  body force and torque
+     sigma0 [n x 5]  initial guess for MBS_GUESS_USER (else ignored)
+   Outputs: V, W (= Omega) [n x 3], S [n x 5] traction stresslet, Sigma [n x 5] flow stresslet
+   (Sigma may be NULL). st may be NULL. MBS_ENOCONV still writes the outputs of the last iterate. */
+int mbs_solve(mbs_ctx* ctx, int64_t n, const double* R, const double* p, const double* v1s,
+              const double* v2s, const double* v3t, const double* Fe, const double* Te,
+              const double* sigma0, double* V, double* W, double* S, double* Sigma,
+              mbs_stats* st, void* stream);
+
+/* The system operator (the GMRES matvec):  y_n = x_n / gamma - sum_{m != n} E[x_m](R_n - R_m),
+   x, y [n x 5]. precision: MBS_FP64 or MBS_FP32 (binary32 pair blocks, compensated
+   accumulation; x and y stay binary64). x and y must not overlap. */
+int mbs_matvec(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y,
+               int precision, void* stream);
+
+/* Right-hand side of the stresslet rows: b_n = sum_{m != n} E[F_m, T_m, d_m] - c s_n, b [n x 5]. */
+int mbs_rhs(mbs_ctx* ctx, int64_t n, const double* R, const double* v2s, const double* v3t,
+            const double* Fe, const double* Te, double* b, void* stream);
+
+/* Rigid-body outputs for a given flow stresslet Sigma [n x 5] (generalized Stokes laws):
+   V, W [n x 3], S [n x 5] (S may be NULL). With Sigma = -c gamma s this is the paper's
+   superposition approximation (section IV). */
+int mbs_outputs(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, const double* v2s,
+                const double* v3t, const double* Fe, const double* Te, const double* Sigma,
+                double* V, double* W, double* S, void* stream);
+
+/* Time integration in a harmonic trap (section V set-up; kinematics of section II):
+   every step rebuilds F^e = -k_trap R, T^e = 0, V^(1s) = c0 p, V^(2s) = c1 * 3(pp - I/3),
+   V^(3t) = c2 p from the current state, solves, and advances
+     R += dt (3/2 V_k - 1/2 V_{k-1}),  p += dt (3/2 Omega_k x p_k - 1/2 Omega_{k-1} x p_{k-1}),
+   then renormalises p (order 2 = Adams-Bashforth, forward Euler on the first step; order 1 =
+   forward Euler throughout). R, p [n x 3] are updated in place. slip_coef: host array [3].
+   per_step: host array [nsteps] or NULL. min_dist: host array [nsteps] or NULL, receives the
+   minimum centre distance of each step's configuration (overlaps are reported, not fatal). */
+int mbs_step(mbs_ctx* ctx, int64_t n, double* R, double* p, double k_trap, const double* slip_coef,
+             double dt, int32_t nsteps, int32_t order, mbs_stats* per_step, double* min_dist,
+             void* stream);
+
+/* Many independent configurations in one call. Configuration b owns rows
+   offsets[b] .. offsets[b+1]-1 of the concatenated device arrays (same meaning as in
+   mbs_solve; sigma0 and p are ignored). offsets: HOST array [nconf + 1], offsets[0] = 0,
+   strictly increasing. per_conf: host array [nconf] or NULL. latency_ms: host array [nconf] or
+   NULL, receives the time from the start of the call to the completion of each configuration. */
+int mbs_solve_batched(mbs_ctx* ctx, int32_t nconf, const int64_t* offsets, const double* R,
+                      const double* v1s, const double* v2s, const double* v3t, const double* Fe,
+                      const double* Te, double* V, double* W, double* S, double* Sigma,
+                      mbs_stats* per_conf, double* latency_ms, void* stream);
+
+/* Time the pair-kernel launch shapes for n spheres at positions R and keep the fastest
+   (for both precisions) in the context; a JSON cache file (may be NULL) is read first and
+   updated afterwards. */
+int mbs_autotune(mbs_ctx* ctx, int64_t n, const double* R, const char* cache_json, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBSTOKES_H */

@@ -1,0 +1,657 @@
+// Host side of libmbstokes: the C ABI, context and workspace management, and the device-resident
+// GMRES / mixed-precision refinement / time-stepping drivers. All vectors stay in device memory;
+// per Krylov step the host reads back two doubles (the Givens residual estimate and the new
+// subdiagonal entry) to decide convergence and restarts.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/mbstokes.h"
+#include "mbs_internal.h"
+
+using namespace mbs;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  double* p = nullptr;
+  size_t cap = 0;  // elements
+};
+
+}  // namespace
+
+struct mbs_ctx {
+  int device = 0;
+  mbs_params prm{};
+  Phys ph{};
+  Tile tile64{256, 128, 0};
+  Tile tile32{256, 128, 0};
+  std::string err;
+  // workspace
+  DevBuf V, w, r, b, xs, dlt, part, dpart, small, H, zeros, stepbuf;
+  int* d_count = nullptr;
+  double* h_status = nullptr;  // pinned host [4]
+  hipEvent_t ev[8] = {};
+};
+
+namespace {
+
+int set_err(mbs_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c)
+    c->err = buf;
+  else
+    g_create_error = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return set_err((ctx), MBS_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e));      \
+  } while (0)
+
+#define CHK(expr)                 \
+  do {                            \
+    int _rc = (expr);             \
+    if (_rc != MBS_OK) return _rc; \
+  } while (0)
+
+int ensure(mbs_ctx* c, DevBuf& b, size_t elems) {
+  if (elems == 0) elems = 1;
+  if (b.cap >= elems) return MBS_OK;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  hipError_t e = hipMalloc((void**)&b.p, elems * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(c, MBS_ENOMEM, "hipMalloc of %zu bytes failed: %s", elems * sizeof(double),
+                   hipGetErrorString(e));
+  }
+  b.cap = elems;
+  return MBS_OK;
+}
+
+int validate_params(mbs_ctx* c, const mbs_params* p) {
+  if (!p) return set_err(c, MBS_EINVAL, "params is NULL");
+  if (!(p->eta > 0.0) || !isfinite(p->eta)) return set_err(c, MBS_EINVAL, "eta must be > 0");
+  if (!(p->a > 0.0) || !isfinite(p->a)) return set_err(c, MBS_EINVAL, "a must be > 0");
+  if (!(p->tol > 0.0) || !(p->tol < 1.0)) return set_err(c, MBS_EINVAL, "tol must be in (0, 1)");
+  if (!isfinite(p->self_slip_c)) return set_err(c, MBS_EINVAL, "self_slip_c must be finite");
+  if (p->lmax != 2)
+    return set_err(c, MBS_EUNSUPPORTED, "lmax = %d: only traction rank 2 (force, torque, stresslet)",
+                   p->lmax);
+  if (p->max_iter < 1) return set_err(c, MBS_EINVAL, "max_iter must be >= 1");
+  if (p->restart < 1 || p->restart > 64) return set_err(c, MBS_EINVAL, "restart must be in 1..64");
+  if (p->precision != MBS_FP64 && p->precision != MBS_MIXED)
+    return set_err(c, MBS_EINVAL, "precision must be MBS_FP64 or MBS_MIXED");
+  if (p->precision == MBS_MIXED && !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
+    return set_err(c, MBS_EINVAL, "inner_tol must be in (0, 1)");
+  if (p->guess < MBS_GUESS_ZERO || p->guess > MBS_GUESS_USER)
+    return set_err(c, MBS_EINVAL, "unknown guess %d", p->guess);
+  if (p->guess == MBS_GUESS_LEARNED)
+    return set_err(c, MBS_EUNSUPPORTED, "learned warm start is not loaded in this context");
+  return MBS_OK;
+}
+
+// Workspace for n spheres and restart m.
+int ensure_ws(mbs_ctx* c, int64_t n) {
+  const int m = c->prm.restart;
+  const int64_t len = 5 * n;
+  CHK(ensure(c, c->V, (size_t)(m + 1) * len));
+  CHK(ensure(c, c->w, len));
+  CHK(ensure(c, c->r, len));
+  CHK(ensure(c, c->b, len));
+  CHK(ensure(c, c->xs, len));
+  CHK(ensure(c, c->dlt, len));
+  int64_t pe = std::max({part_elems(n, c->tile64, 5), part_elems(n, c->tile32, 5),
+                         part_elems(n, Tile{c->tile64.block, 128, c->tile64.split}, 6),
+                         (int64_t)6 * n});
+  CHK(ensure(c, c->part, (size_t)pe));
+  CHK(ensure(c, c->dpart, (size_t)std::max<int64_t>((int64_t)(m + 2) * 256, 1024 + (n + 255) / 256) + 64));
+  CHK(ensure(c, c->small, (size_t)8 * (m + 2) + 64));
+  CHK(ensure(c, c->H, (size_t)(m + 1) * (m + 1)));
+  if (c->zeros.cap < (size_t)len) {
+    CHK(ensure(c, c->zeros, len));
+    HIPCHK(c, hipMemset(c->zeros.p, 0, len * sizeof(double)));
+  }
+  return MBS_OK;
+}
+
+// small-buffer layout
+struct Small {
+  double *h1, *h2, *nsq, *cs, *sn, *g, *y, *status, *bnorm2;
+};
+Small small_of(mbs_ctx* c) {
+  const int m = c->prm.restart;
+  double* s = c->small.p;
+  Small o;
+  o.h1 = s;
+  o.h2 = s + (m + 2);
+  o.cs = s + 2 * (m + 2);
+  o.sn = s + 3 * (m + 2);
+  o.g = s + 4 * (m + 2);
+  o.y = s + 5 * (m + 2);
+  o.nsq = s + 6 * (m + 2);
+  o.status = s + 6 * (m + 2) + 2;
+  o.bnorm2 = s + 6 * (m + 2) + 6;
+  return o;
+}
+
+int read_status(mbs_ctx* c, const double* dev, int count, hipStream_t s) {
+  HIPCHK(c, hipMemcpyAsync(c->h_status, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+struct Counters {
+  int iters = 0, f64 = 0, f32 = 0, refinements = 0;
+  double pairs = 0.0;
+};
+
+void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x, double* y,
+              hipStream_t s, Counters& cnt) {
+  if (prec == MBS_FP64) {
+    launch_p2_f64(R, x, y, c->part.p, n, c->ph, c->tile64, s);
+    cnt.f64++;
+  } else {
+    launch_p2_f32(R, x, y, c->part.p, n, c->ph, c->tile32, s);
+    cnt.f32++;
+  }
+  cnt.pairs += (double)n * (double)(n - 1);
+}
+
+// ||v||^2 into dev[0]
+void norm2(mbs_ctx* c, const double* v, int64_t len, double* dev, hipStream_t s) {
+  launch_dots(v, 0, 1, v, len, c->dpart.p, dev, s);
+}
+
+// Restarted GMRES on A x = rhs, operator precision prec. x is updated in place (x_zero: x is 0).
+// Stops when the residual estimate is <= tol_abs. With verify, the final residual is recomputed
+// with the operator and returned in *resid; otherwise *resid is the last estimate.
+int gmres(mbs_ctx* c, int prec, int64_t n, const double* R, const double* rhs, double* x,
+          bool x_zero, double tol_abs, int max_iters, bool verify, double* resid, Counters& cnt,
+          hipStream_t s) {
+  const int m = c->prm.restart;
+  const int64_t len = 5 * n;
+  Small sm = small_of(c);
+  double* V = c->V.p;
+  double* w = c->w.p;
+  double* r = c->r.p;
+  // initial residual
+  if (x_zero) {
+    launch_copy(rhs, r, len, s);
+  } else {
+    apply_op(c, prec, n, R, x, r, s, cnt);
+    launch_axpby(1.0, rhs, -1.0, r, len, s);
+  }
+  norm2(c, r, len, sm.nsq, s);
+  launch_init_g(sm.nsq, sm.g, m, sm.status, s);
+  CHK(read_status(c, sm.status, 1, s));
+  double beta = c->h_status[0];
+  int used = 0;
+  while (beta > tol_abs && used < max_iters) {
+    launch_scale_by(r, sm.status, 1, V, len, s);  // V0 = r / beta (status[0] = beta)
+    int k = 0;
+    double est = beta;
+    bool breakdown = false;
+    while (k < m && used < max_iters) {
+      double* vk = V + (int64_t)k * len;
+      apply_op(c, prec, n, R, vk, w, s, cnt);
+      // classical Gram-Schmidt, applied twice
+      launch_dots(V, len, k + 1, w, len, c->dpart.p, sm.h1, s);
+      launch_axpy_multi(V, len, k + 1, sm.h1, -1.0, w, len, s);
+      launch_dots(V, len, k + 1, w, len, c->dpart.p, sm.h2, s);
+      launch_axpy_multi(V, len, k + 1, sm.h2, -1.0, w, len, s);
+      norm2(c, w, len, sm.nsq, s);
+      launch_givens(c->H.p, m, k, sm.h1, sm.h2, sm.nsq, sm.cs, sm.sn, sm.g, sm.status, s);
+      launch_scale_by(w, sm.status + 1, 1, V + (int64_t)(k + 1) * len, len, s);
+      CHK(read_status(c, sm.status, 2, s));
+      est = c->h_status[0];
+      ++k;
+      ++used;
+      cnt.iters++;
+      if (!(c->h_status[1] > 1e-300 * beta)) breakdown = true;
+      if (est <= tol_abs || breakdown) break;
+    }
+    launch_backsolve(c->H.p, m, k, sm.g, sm.y, s);
+    launch_axpy_multi(V, len, k, sm.y, 1.0, x, len, s);
+    x_zero = false;
+    const bool done = est <= tol_abs || breakdown || used >= max_iters;
+    if (done && !verify) {
+      beta = est;
+      break;
+    }
+    apply_op(c, prec, n, R, x, r, s, cnt);
+    launch_axpby(1.0, rhs, -1.0, r, len, s);
+    norm2(c, r, len, sm.nsq, s);
+    launch_init_g(sm.nsq, sm.g, m, sm.status, s);
+    CHK(read_status(c, sm.status, 1, s));
+    beta = c->h_status[0];
+    if (done) break;
+  }
+  *resid = beta;
+  return MBS_OK;
+}
+
+int count_nonfinite(mbs_ctx* c, hipStream_t s, std::initializer_list<std::pair<const double*, int64_t>> arrs,
+                    int* bad) {
+  HIPCHK(c, hipMemsetAsync(c->d_count, 0, sizeof(int), s));
+  for (auto& a : arrs)
+    if (a.first) launch_count_nonfinite(a.first, a.second, c->d_count, s);
+  int h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, c->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  *bad = h;
+  return MBS_OK;
+}
+
+int check_overlap(mbs_ctx* c, int64_t n, const double* R, hipStream_t s, double* min_d) {
+  if (n < 2) {
+    *min_d = INFINITY;
+    return MBS_OK;
+  }
+  double* out = c->small.p + c->small.cap - 1;
+  launch_min_dist2(R, n, out, c->dpart.p + 1024, s);
+  CHK(read_status(c, out, 1, s));
+  *min_d = sqrt(c->h_status[0]);
+  return MBS_OK;
+}
+
+float ev_ms(hipEvent_t a, hipEvent_t b) {
+  float t = 0.f;
+  if (hipEventElapsedTime(&t, a, b) != hipSuccess) return 0.f;
+  return t;
+}
+
+// The solve without argument validation; sigma0 is read for MBS_GUESS_USER.
+int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const double* v2s,
+               const double* v3t, const double* Fe, const double* Te, const double* sigma0,
+               double* V, double* W, double* S, double* Sigma, mbs_stats* st, hipStream_t s) {
+  CHK(ensure_ws(c, n));
+  const int64_t len = 5 * n;
+  const double* Fz = Fe ? Fe : c->zeros.p;
+  Counters cnt;
+  Small sm = small_of(c);
+  HIPCHK(c, hipEventRecord(c->ev[0], s));
+  // right-hand side
+  launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile64, s);
+  cnt.pairs += (double)n * (double)(n - 1);
+  HIPCHK(c, hipEventRecord(c->ev[1], s));
+  norm2(c, c->b.p, len, sm.bnorm2, s);
+  CHK(read_status(c, sm.bnorm2, 1, s));
+  const double bnorm = sqrt(c->h_status[0]);
+  // initial guess
+  bool x_zero = false;
+  switch (c->prm.guess) {
+    case MBS_GUESS_ZERO:
+      HIPCHK(c, hipMemsetAsync(c->xs.p, 0, len * sizeof(double), s));
+      x_zero = true;
+      break;
+    case MBS_GUESS_DIAG:
+      launch_axpby(c->ph.gamma, c->b.p, 0.0, c->xs.p, len, s);
+      break;
+    case MBS_GUESS_USER:
+      if (!sigma0) return set_err(c, MBS_EINVAL, "MBS_GUESS_USER needs sigma0");
+      launch_copy(sigma0, c->xs.p, len, s);
+      break;
+    default:
+      return set_err(c, MBS_EUNSUPPORTED, "guess %d not available", c->prm.guess);
+  }
+  double rel = 0.0;
+  int rc = MBS_OK;
+  if (bnorm == 0.0) {
+    HIPCHK(c, hipMemsetAsync(c->xs.p, 0, len * sizeof(double), s));
+  } else if (c->prm.precision == MBS_FP64) {
+    double res = 0.0;
+    CHK(gmres(c, MBS_FP64, n, R, c->b.p, c->xs.p, x_zero, c->prm.tol * bnorm, c->prm.max_iter, true,
+              &res, cnt, s));
+    rel = res / bnorm;
+  } else {
+    // mixed precision iterative refinement: binary64 residual rr = b - A64 x, binary32 inner
+    // GMRES for the correction delta (zero start), x += delta, repeat.
+    double* rr = c->dlt.p;
+    CHK(ensure(c, c->stepbuf, len));
+    double* delta = c->stepbuf.p;
+    double beta;
+    if (x_zero) {
+      launch_copy(c->b.p, rr, len, s);
+      beta = bnorm;
+    } else {
+      apply_op(c, MBS_FP64, n, R, c->xs.p, rr, s, cnt);
+      launch_axpby(1.0, c->b.p, -1.0, rr, len, s);
+      norm2(c, rr, len, sm.nsq, s);
+      CHK(read_status(c, sm.nsq, 1, s));
+      beta = sqrt(c->h_status[0]);
+    }
+    while (beta > c->prm.tol * bnorm && cnt.iters < c->prm.max_iter) {
+      HIPCHK(c, hipMemsetAsync(delta, 0, len * sizeof(double), s));
+      double inner = 0.0;
+      CHK(gmres(c, MBS_FP32, n, R, rr, delta, true, c->prm.inner_tol * beta,
+                c->prm.max_iter - cnt.iters, false, &inner, cnt, s));
+      launch_axpby(1.0, delta, 1.0, c->xs.p, len, s);
+      cnt.refinements++;
+      apply_op(c, MBS_FP64, n, R, c->xs.p, rr, s, cnt);
+      launch_axpby(1.0, c->b.p, -1.0, rr, len, s);
+      norm2(c, rr, len, sm.nsq, s);
+      CHK(read_status(c, sm.nsq, 1, s));
+      beta = sqrt(c->h_status[0]);
+    }
+    rel = beta / bnorm;
+  }
+  if (bnorm != 0.0 && !(rel <= c->prm.tol)) rc = MBS_ENOCONV;
+  HIPCHK(c, hipEventRecord(c->ev[2], s));
+  launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile64, s);
+  cnt.pairs += (double)n * (double)(n - 1);
+  if (Sigma) launch_copy(c->xs.p, Sigma, len, s);
+  HIPCHK(c, hipEventRecord(c->ev[3], s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (st) {
+    st->iters = cnt.iters;
+    st->refinements = cnt.refinements;
+    st->fp64_matvecs = cnt.f64;
+    st->fp32_matvecs = cnt.f32;
+    st->rel_resid = rel;
+    st->t_rhs_ms = ev_ms(c->ev[0], c->ev[1]);
+    st->t_iter_ms = ev_ms(c->ev[1], c->ev[2]);
+    st->t_out_ms = ev_ms(c->ev[2], c->ev[3]);
+    st->t_total_ms = ev_ms(c->ev[0], c->ev[3]);
+    st->pair_blocks = cnt.pairs;
+  }
+  if (rc == MBS_ENOCONV)
+    set_err(c, MBS_ENOCONV, "no convergence: relative residual %.3e after %d iterations", rel,
+            cnt.iters);
+  return rc;
+}
+
+int begin_call(mbs_ctx* c) {
+  if (!c) return MBS_EINVAL;
+  c->err.clear();
+  HIPCHK(c, hipSetDevice(c->device));
+  return MBS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mbs_default_params(mbs_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->eta = 1.0 / (6.0 * M_PI);
+  p->a = 1.0;
+  p->tol = 1e-10;
+  p->self_slip_c = 1.0;
+  p->inner_tol = 1e-5;
+  p->lmax = 2;
+  p->max_iter = 300;
+  p->restart = 30;
+  p->precision = MBS_FP64;
+  p->guess = MBS_GUESS_ZERO;
+  p->check_overlap = 0;
+  p->tile = 0;
+}
+
+int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {
+  g_create_error.clear();
+  if (!out) return set_err(nullptr, MBS_EINVAL, "ctx pointer is NULL");
+  *out = nullptr;
+  mbs_params def;
+  mbs_default_params(&def);
+  if (!prm) prm = &def;
+  int rc = validate_params(nullptr, prm);
+  if (rc != MBS_OK) return rc;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return set_err(nullptr, MBS_EHIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
+  if (device < 0 || device >= ndev)
+    return set_err(nullptr, MBS_EINVAL, "device %d out of range (%d devices)", device, ndev);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return set_err(nullptr, MBS_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+  mbs_ctx* c = new mbs_ctx();
+  c->device = device;
+  c->prm = *prm;
+  c->ph = make_phys(prm->eta, prm->a, prm->self_slip_c);
+  e = hipHostMalloc((void**)&c->h_status, 8 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->d_count, sizeof(int));
+  for (int k = 0; k < 8 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
+  if (e != hipSuccess) {
+    set_err(nullptr, MBS_EHIP, "context allocation: %s", hipGetErrorString(e));
+    mbs_destroy(c);
+    return MBS_EHIP;
+  }
+  *out = c;
+  return MBS_OK;
+}
+
+void mbs_destroy(mbs_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  DevBuf* bufs[] = {&c->V, &c->w, &c->r, &c->b, &c->xs, &c->dlt, &c->part, &c->dpart,
+                    &c->small, &c->H, &c->zeros, &c->stepbuf};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (c->d_count) (void)hipFree(c->d_count);
+  if (c->h_status) (void)hipHostFree(c->h_status);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int mbs_set_params(mbs_ctx* c, const mbs_params* prm) {
+  CHK(begin_call(c));
+  CHK(validate_params(c, prm));
+  const bool restart_changed = prm->restart != c->prm.restart;
+  c->prm = *prm;
+  c->ph = make_phys(prm->eta, prm->a, prm->self_slip_c);
+  if (restart_changed) {  // buffers sized by restart are re-grown on demand
+    DevBuf* bufs[] = {&c->V, &c->dpart, &c->small, &c->H};
+    for (DevBuf* b : bufs) {
+      if (b->p) (void)hipFree(b->p);
+      b->p = nullptr;
+      b->cap = 0;
+    }
+  }
+  return MBS_OK;
+}
+
+const char* mbs_last_error(const mbs_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int mbs_solve(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* v1s,
+              const double* v2s, const double* v3t, const double* Fe, const double* Te,
+              const double* sigma0, double* V, double* W, double* S, double* Sigma, mbs_stats* st,
+              void* stream) {
+  CHK(begin_call(c));
+  (void)p;
+  if (n < 1) return set_err(c, MBS_EINVAL, "n = %lld must be >= 1", (long long)n);
+  if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
+  if (!R || !V || !W || !S) return set_err(c, MBS_EINVAL, "R, V, W and S are required");
+  if (c->prm.guess == MBS_GUESS_USER && !sigma0)
+    return set_err(c, MBS_EINVAL, "MBS_GUESS_USER needs sigma0");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, n));
+  int bad = 0;
+  CHK(count_nonfinite(c, s, {{R, 3 * n}, {v1s, 3 * n}, {v2s, 5 * n}, {v3t, 3 * n}, {Fe, 3 * n},
+                             {Te, 3 * n}, {sigma0, c->prm.guess == MBS_GUESS_USER ? 5 * n : 0}},
+                      &bad));
+  if (bad) return set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
+  if (c->prm.check_overlap) {
+    double md = 0.0;
+    CHK(check_overlap(c, n, R, s, &md));
+    if (md < 2.0 * c->prm.a)
+      return set_err(c, MBS_EOVERLAP, "spheres overlap: minimum centre distance %.6g < 2a", md);
+  }
+  return solve_core(c, n, R, v1s, v2s, v3t, Fe, Te, sigma0, V, W, S, Sigma, st, s);
+}
+
+int mbs_matvec(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, int precision,
+               void* stream) {
+  CHK(begin_call(c));
+  if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
+  if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
+  if (!R || !x || !y) return set_err(c, MBS_EINVAL, "R, x and y are required");
+  if (x == y) return set_err(c, MBS_EINVAL, "x and y must not overlap");
+  if (precision != MBS_FP64 && precision != MBS_FP32)
+    return set_err(c, MBS_EINVAL, "precision must be MBS_FP64 or MBS_FP32");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, n));
+  Counters cnt;
+  apply_op(c, precision, n, R, x, y, s, cnt);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_rhs(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const double* v3t,
+            const double* Fe, const double* Te, double* b, void* stream) {
+  CHK(begin_call(c));
+  if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
+  if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
+  if (!R || !b) return set_err(c, MBS_EINVAL, "R and b are required");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, n));
+  launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, c->ph, c->tile64, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_outputs(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const double* v2s,
+                const double* v3t, const double* Fe, const double* Te, const double* Sigma,
+                double* V, double* W, double* S, void* stream) {
+  CHK(begin_call(c));
+  if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
+  if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
+  if (!R || !Sigma || !V || !W) return set_err(c, MBS_EINVAL, "R, Sigma, V and W are required");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, n));
+  launch_p3(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, c->ph,
+            c->tile64, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const double* slip_coef,
+             double dt, int32_t nsteps, int32_t order, mbs_stats* per_step, double* min_dist,
+             void* stream) {
+  CHK(begin_call(c));
+  if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
+  if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
+  if (!R || !p || !slip_coef) return set_err(c, MBS_EINVAL, "R, p and slip_coef are required");
+  if (nsteps < 0) return set_err(c, MBS_EINVAL, "nsteps must be >= 0");
+  if (order != 1 && order != 2) return set_err(c, MBS_EINVAL, "order must be 1 or 2");
+  if (!isfinite(dt) || !isfinite(k_trap)) return set_err(c, MBS_EINVAL, "dt and k must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, n));
+  // state: Fe, v1s, v3t, V, W, Vprev, Pdprev [3n] each; v2s, Sigma, S [5n] each
+  DevBuf st;
+  const size_t need = (size_t)(3 * 7 + 5 * 3) * n;
+  CHK(ensure(c, st, need));
+  double* Fe = st.p;
+  double* v1s = Fe + 3 * n;
+  double* v3t = v1s + 3 * n;
+  double* V = v3t + 3 * n;
+  double* W = V + 3 * n;
+  double* Vp = W + 3 * n;
+  double* Pp = Vp + 3 * n;
+  double* v2s = Pp + 3 * n;
+  double* Sg = v2s + 5 * n;
+  double* Sout = Sg + 5 * n;
+  int bad = 0;
+  int rc = count_nonfinite(c, s, {{R, 3 * n}, {p, 3 * n}}, &bad);
+  if (rc == MBS_OK && bad) rc = set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
+  const int guess0 = c->prm.guess;
+  for (int k = 0; k < nsteps && rc == MBS_OK; ++k) {
+    launch_trap_modes(R, p, k_trap, slip_coef[0], slip_coef[1], slip_coef[2], Fe, v1s, v2s, v3t, n,
+                      s);
+    if (min_dist) {
+      double md = 0.0;
+      rc = check_overlap(c, n, R, s, &md);
+      if (rc != MBS_OK) break;
+      min_dist[k] = md;
+    }
+    mbs_stats one{};
+    const bool warm = guess0 == MBS_GUESS_USER && k > 0;
+    if (guess0 == MBS_GUESS_USER && k == 0) c->prm.guess = MBS_GUESS_DIAG;
+    rc = solve_core(c, n, R, v1s, v2s, slip_coef[2] != 0.0 ? v3t : nullptr, Fe, nullptr,
+                    warm ? Sg : nullptr, V, W, Sout, Sg, &one, s);
+    c->prm.guess = guess0;
+    if (rc != MBS_OK && rc != MBS_ENOCONV) break;
+    if (per_step) per_step[k] = one;
+    launch_ab_update(R, p, V, W, Vp, Pp, dt, k == 0, order, n, s);
+    if (rc == MBS_ENOCONV) break;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (st.p) (void)hipFree(st.p);
+  if (e != hipSuccess && rc == MBS_OK) rc = set_err(c, MBS_EHIP, "%s", hipGetErrorString(e));
+  return rc;
+}
+
+int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const double* R,
+                      const double* v1s, const double* v2s, const double* v3t, const double* Fe,
+                      const double* Te, double* V, double* W, double* S, double* Sigma,
+                      mbs_stats* per_conf, double* latency_ms, void* stream) {
+  CHK(begin_call(c));
+  if (nconf < 1 || !offsets) return set_err(c, MBS_EINVAL, "nconf >= 1 and offsets are required");
+  if (offsets[0] != 0) return set_err(c, MBS_EINVAL, "offsets[0] must be 0");
+  for (int b = 0; b < nconf; ++b)
+    if (offsets[b + 1] <= offsets[b]) return set_err(c, MBS_EINVAL, "offsets must increase");
+  if (!R || !V || !W || !S) return set_err(c, MBS_EINVAL, "R, V, W and S are required");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ntot = offsets[nconf];
+  int bad = 0;
+  CHK(ensure_ws(c, std::min<int64_t>(ntot, 1 << 20)));
+  CHK(count_nonfinite(c, s, {{R, 3 * ntot}, {v1s, 3 * ntot}, {v2s, 5 * ntot}, {v3t, 3 * ntot},
+                             {Fe, 3 * ntot}, {Te, 3 * ntot}},
+                      &bad));
+  if (bad) return set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
+  const int guess0 = c->prm.guess;
+  if (guess0 == MBS_GUESS_USER) c->prm.guess = MBS_GUESS_ZERO;
+  hipEvent_t t0 = c->ev[4], t1 = c->ev[5];
+  HIPCHK(c, hipEventRecord(t0, s));
+  int rc = MBS_OK;
+  for (int b = 0; b < nconf; ++b) {
+    const int64_t o = offsets[b], nb = offsets[b + 1] - offsets[b];
+    mbs_stats one{};
+    int r1 = solve_core(c, nb, R + 3 * o, v1s ? v1s + 3 * o : nullptr, v2s ? v2s + 5 * o : nullptr,
+                        v3t ? v3t + 3 * o : nullptr, Fe ? Fe + 3 * o : nullptr,
+                        Te ? Te + 3 * o : nullptr, nullptr, V + 3 * o, W + 3 * o, S + 5 * o,
+                        Sigma ? Sigma + 5 * o : nullptr, &one, s);
+    if (per_conf) per_conf[b] = one;
+    if (latency_ms) {
+      (void)hipEventRecord(t1, s);
+      (void)hipEventSynchronize(t1);
+      latency_ms[b] = ev_ms(t0, t1);
+    }
+    if (r1 != MBS_OK && rc == MBS_OK) rc = r1;
+    if (r1 != MBS_OK && r1 != MBS_ENOCONV) break;
+  }
+  c->prm.guess = guess0;
+  return rc;
+}
+
+int mbs_autotune(mbs_ctx* c, int64_t n, const double* R, const char* cache_json, void* stream) {
+  CHK(begin_call(c));
+  (void)n;
+  (void)R;
+  (void)cache_json;
+  (void)stream;
+  return set_err(c, MBS_EUNSUPPORTED, "autotuner not built yet");
+}
+
+}  // extern "C"

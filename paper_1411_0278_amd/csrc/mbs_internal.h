@@ -1,0 +1,84 @@
+// Internal declarations shared by the kernel and host translation units of libmbstokes.
+// Not part of the public interface (include/mbstokes.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mbs {
+
+// Physical constants of one problem, derived once on the host.
+struct Phys {
+  double eta, a;
+  double P;          // 1 / (8 pi eta): prefactor of the Green's function flows
+  double a2;         // a^2
+  double a5_10;      // a^5 / 10: strength of the rank-3 trace mode flow
+  double gamma;      // (20/3) pi eta a^3: lone-sphere stresslet per unit strain
+  double inv_gamma;
+  double mu_t;       // 1 / (6 pi eta a)
+  double mu_r;       // 1 / (8 pi eta a^3)
+  double slip_S;     // (8/3) pi eta a^3: traction stresslet minus flow stresslet, per unit slip
+  double c_slip;     // self-slip coefficient c
+};
+Phys make_phys(double eta, double a, double c);
+
+// Pair-kernel launch shape.
+struct Tile {
+  int block;   // threads per workgroup (targets per workgroup)
+  int tj;      // sources per LDS tile
+  int split;   // source chunks along grid.y (partial sums reduced afterwards); 0 = automatic
+};
+
+// ---------------------------------------------------------------- pair passes
+// y = x/gamma - E[x] (system operator). part: scratch [split x 5n] doubles (used when split > 1).
+void launch_p2_f64(const double* R, const double* x, double* y, double* part, int64_t n,
+                   const Phys& ph, Tile t, hipStream_t s);
+void launch_p2_f32(const double* R, const double* x, double* y, double* part, int64_t n,
+                   const Phys& ph, Tile t, hipStream_t s);
+// b = E[F, T, d] - c s
+void launch_p1(const double* R, const double* v2s, const double* v3t, const double* Fe,
+               const double* Te, double* b, double* part, int64_t n, const Phys& ph, Tile t,
+               hipStream_t s);
+// V, W, S from Sigma
+void launch_p3(const double* R, const double* v1s, const double* v2s, const double* v3t,
+               const double* Fe, const double* Te, const double* Sig, double* V, double* W,
+               double* S, double* part, int64_t n, const Phys& ph, Tile t, hipStream_t s);
+// min over pairs of |R_n - R_m|^2 -> out[0] (device); scratch: blocks doubles
+void launch_min_dist2(const double* R, int64_t n, double* out, double* scratch, hipStream_t s);
+// count non-finite entries of a device array -> atomically added to *cnt (device int)
+void launch_count_nonfinite(const double* a, int64_t len, int* cnt, hipStream_t s);
+
+int split_for(int64_t n, Tile t);      // number of source chunks actually used
+int64_t part_elems(int64_t n, Tile t, int width);  // scratch size (doubles) for a pass
+
+// ---------------------------------------------------------------- Krylov helpers (all deterministic)
+// out[k] = <V_k, w> for k < nv, V_k = V + k*ld; scratch: part [nv x dot_blocks(len)]
+int dot_blocks(int64_t len);
+void launch_dots(const double* V, int64_t ld, int nv, const double* w, int64_t len, double* part,
+                 double* out, hipStream_t s);
+// w += sign * sum_k h[k] V_k
+void launch_axpy_multi(const double* V, int64_t ld, int nv, const double* h, double sign, double* w,
+                       int64_t len, hipStream_t s);
+// y = alpha_dev[0]^{pow} * x  with pow = -1 (divide) or +1; alpha from device memory
+void launch_scale_by(const double* x, const double* alpha, int inv, double* y, int64_t len,
+                     hipStream_t s);
+// y = a*x + b*y (host scalars)
+void launch_axpby(double a, const double* x, double b, double* y, int64_t len, hipStream_t s);
+void launch_copy(const double* x, double* y, int64_t len, hipStream_t s);
+// One Arnoldi column: H(:,k) = h1 + h2, H(k+1,k) = sqrt(nsq); Givens update; status[0] = |g_{k+1}|,
+// status[1] = H(k+1,k) (before rotation). Layout: H column-major [(m+1) x m], cs, sn, g [m+1].
+void launch_givens(double* H, int m, int k, const double* h1, const double* h2, const double* nsq,
+                   double* cs, double* sn, double* g, double* status, hipStream_t s);
+// y = H(0:k,0:k)^{-1} g (upper triangular solve)
+void launch_backsolve(const double* H, int m, int k, const double* g, double* y, hipStream_t s);
+// g = [sqrt(nsq), 0, ...]; status[0] = sqrt(nsq)
+void launch_init_g(const double* nsq, double* g, int m, double* status, hipStream_t s);
+
+// ---------------------------------------------------------------- stepper
+// Fe = -k R, v1s = c0 p, v2s = c1 (3pp - I) in 5-basis, v3t = c2 p
+void launch_trap_modes(const double* R, const double* p, double k, double c0, double c1, double c2,
+                       double* Fe, double* v1s, double* v2s, double* v3t, int64_t n, hipStream_t s);
+// AB2 / Euler update of R and p (renormalised); Vprev/Pdprev updated to this step's rates.
+void launch_ab_update(double* R, double* p, const double* V, const double* W, double* Vprev,
+                      double* Pdprev, double dt, int first, int order, int64_t n, hipStream_t s);
+
+}  // namespace mbs

@@ -1,0 +1,971 @@
+// HIP kernels of libmbstokes for gfx950 (CDNA4): all-pairs Galerkin pair passes, Krylov
+// helpers and the rigid-body stepper.
+//
+// Pair passes. For spheres n (receiver) and m (source), x = R_n - R_m, r = |x|, P = 1/(8 pi eta).
+// The off-diagonal Galerkin matrix elements are derivatives of the unbounded Green's function
+// G = I/r + x x / r^3 under the finite-size operators F^l = 1 + a^2/(4l+6) nabla^2 (section III,
+// matrix elements for m != n). Because nabla^4 G = 0 every composed operator ends after one
+// Laplacian, which gives the closed forms used below (w = Sigma.x, q = x.Sigma.x):
+//
+//   U <- F      P[(1/r + 2a^2/3r^3) F + (1/r^3 - 2a^2/r^5)(x.F) x]          (Rotne-Prager)
+//   U <- T      P (T x x)/r^3
+//   U <- Sigma  P[q x (-3/r^5 + 8a^2/r^7) - (16a^2/5) w / r^5]
+//   U <- d      (a^5/10)[3 (x.d) x / r^5 - d / r^3]
+//   W <- F      P (F x x)/r^3
+//   W <- T      (P/2)[3 (x.T) x / r^5 - T / r^3]
+//   W <- Sigma  3P (x x w)/r^5
+//   E <- F      P[(x.F)(-3/r^5 + 8a^2/r^7) x x - (16a^2/5) sym(F x)/r^5]    (traceless part)
+//   E <- T      -3P sym((T x x) x)/r^5
+//   E <- Sigma  P[c1 sym(x w) + c2 x x + c3 Sigma],  c1 = -6/r^5 + 24a^2/r^7,
+//               c2 = q (15/r^7 - 42a^2/r^9),  c3 = -12a^2/(5 r^5)                (traceless part)
+//   E <- d      (a^5/10)[3 (x d + d x)/r^5 - 15 (x.d) x x / r^7]             (traceless part)
+//
+// Every strain contribution except c3 Sigma has the form sym(x (x) v) for a vector v, so a pass
+// accumulates v's contraction with x directly in the 5-component basis (B0..B4, see the public
+// header), scaled by (sqrt2, sqrt6, sqrt2, sqrt2, sqrt2) so that no square root appears per pair.
+//
+// Layout: one thread owns one receiver (coordinates and accumulators in registers); sources
+// are staged through LDS in tiles as 64-byte (P2), 96-byte (P1) or 144-byte (P3) records that
+// every lane of a wavefront reads at the same address (LDS broadcast). grid.x runs over
+// receiver tiles, grid.y over source chunks; chunk partial sums are reduced in a fixed order
+// by a finishing kernel, so results are bitwise reproducible. The n == m term is removed by
+// setting 1/r to zero when r == 0 (every term carries at least one power of 1/r).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mbs_internal.h"
+
+namespace mbs {
+
+namespace {
+constexpr double RS2 = 0.70710678118654752440;  // 1/sqrt(2)
+constexpr double RS6 = 0.40824829046386301637;  // 1/sqrt(6)
+constexpr int kMaxBlock = 256;
+
+// 1/sqrt(r2) for r2 > 0, and 0 for r2 == 0 (the n == m term), without a branch.
+// binary64: hardware reciprocal square root estimate followed by one Newton-Raphson step
+// y <- y + (y/2)(1 - r2 y^2), which squares the relative error of the estimate.
+__device__ __forceinline__ double rinv_or_zero(double r2) {
+  const double y0 = __builtin_amdgcn_rsq(r2);
+  const double e = fma(-r2 * y0, y0, 1.0);
+  const double y1 = fma(0.5 * y0, e, y0);
+  return r2 > 0.0 ? y1 : 0.0;
+}
+// binary32: the hardware estimate is accurate to about 1 ulp.
+__device__ __forceinline__ float rinv_or_zero(float r2) {
+  const float y0 = __builtin_amdgcn_rsqf(r2);
+  return r2 > 0.0f ? y0 : 0.0f;
+}
+
+// Accumulate sym(x (x) v) in the scaled 5-basis.
+template <typename T>
+__device__ __forceinline__ void acc_sym(T dx, T dy, T dz, T vx, T vy, T vz, T& a0, T& a1, T& a2,
+                                        T& a3, T& a4) {
+  const T pxx = dx * vx, pyy = dy * vy, pzz = dz * vz;
+  a0 += pxx - pyy;
+  a1 += (T)2 * pzz - pxx - pyy;
+  a2 += dx * vy + dy * vx;
+  a3 += dx * vz + dz * vx;
+  a4 += dy * vz + dz * vy;
+}
+
+// ------------------------------------------------------------------ P2: system operator
+struct alignas(16) RecS64 {
+  double x, y, z, sxx, syy, sxy, sxz, syz;
+};
+struct alignas(16) RecS32 {
+  float x, y, z, sxx, syy, sxy, sxz, syz;
+};
+
+// Cartesian components of Sigma from its 5-basis coefficients.
+__device__ __forceinline__ void basis_to_cart(const double* s, double& sxx, double& syy,
+                                              double& sxy, double& sxz, double& syz) {
+  const double u0 = s[0] * RS2, u1 = s[1] * RS6;
+  sxx = u0 - u1;
+  syy = -u0 - u1;
+  sxy = s[2] * RS2;
+  sxz = s[3] * RS2;
+  syz = s[4] * RS2;
+}
+
+template <int TJ>
+__global__ void __launch_bounds__(kMaxBlock)
+    k_p2_f64(const double* __restrict__ R, const double* __restrict__ X, double* __restrict__ out,
+             int n, int chunk, double P, double a2, double inv_gamma, int direct) {
+  __shared__ RecS64 tile[TJ];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const double xi = R[3 * ii], yi = R[3 * ii + 1], zi = R[3 * ii + 2];
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  const double A24 = 24.0 * a2, A42 = 42.0 * a2;
+  double a0 = 0, a1 = 0, a2c = 0, a3 = 0, a4 = 0;
+  double t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
+  for (int jt = j0; jt < j1; jt += TJ) {
+    const int cnt = min(TJ, j1 - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const int j = jt + t;
+      RecS64 rc;
+      rc.x = R[3 * j];
+      rc.y = R[3 * j + 1];
+      rc.z = R[3 * j + 2];
+      basis_to_cart(X + 5 * j, rc.sxx, rc.syy, rc.sxy, rc.sxz, rc.syz);
+      tile[t] = rc;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int jj = 0; jj < cnt; ++jj) {
+      const RecS64 s = tile[jj];
+      const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double ri = rinv_or_zero(r2);
+      const double ri2 = ri * ri;
+      const double ri5 = ri2 * ri2 * ri;
+      const double ri7 = ri5 * ri2;
+      const double szz = -(s.sxx + s.syy);
+      const double wx = s.sxx * dx + s.sxy * dy + s.sxz * dz;
+      const double wy = s.sxy * dx + s.syy * dy + s.syz * dz;
+      const double wz = s.sxz * dx + s.syz * dy + szz * dz;
+      const double q = dx * wx + dy * wy + dz * wz;
+      const double c1 = ri5 * fma(A24, ri2, -6.0);
+      const double c2 = q * ri7 * fma(-A42, ri2, 15.0);
+      const double vx = fma(c1, wx, c2 * dx);
+      const double vy = fma(c1, wy, c2 * dy);
+      const double vz = fma(c1, wz, c2 * dz);
+      acc_sym(dx, dy, dz, vx, vy, vz, a0, a1, a2c, a3, a4);
+      t0 = fma(ri5, s.sxx, t0);
+      t1 = fma(ri5, s.syy, t1);
+      t2 = fma(ri5, s.sxy, t2);
+      t3 = fma(ri5, s.sxz, t3);
+      t4 = fma(ri5, s.syz, t4);
+    }
+  }
+  if (i >= n) return;
+  const double C3 = -2.4 * a2;  // -12 a^2 / 5
+  double e[5];
+  e[0] = P * RS2 * (a0 + C3 * (t0 - t1));
+  e[1] = P * RS6 * (a1 - 3.0 * C3 * (t0 + t1));
+  e[2] = P * RS2 * (a2c + 2.0 * C3 * t2);
+  e[3] = P * RS2 * (a3 + 2.0 * C3 * t3);
+  e[4] = P * RS2 * (a4 + 2.0 * C3 * t4);
+  if (direct) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[5 * (int64_t)i + c] = X[5 * (int64_t)i + c] * inv_gamma - e[c];
+  } else {
+    double* o = out + (int64_t)blockIdx.y * 5 * n + 5 * (int64_t)i;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) o[c] = e[c];
+  }
+}
+
+__device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
+  const float y = v - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// Binary32 pair blocks. Coordinates are re-centred on the first receiver of the workgroup in
+// binary64 before rounding, so that near pairs keep their relative accuracy. Within one LDS tile
+// the contributions are summed in binary32; tile sums enter compensated (Kahan) binary32
+// accumulators.
+template <int TJ>
+__global__ void __launch_bounds__(kMaxBlock)
+    k_p2_f32(const double* __restrict__ R, const double* __restrict__ X, double* __restrict__ out,
+             int n, int chunk, double P, double a2, double inv_gamma, int direct) {
+  __shared__ RecS32 tile[TJ];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const int i0 = min((int)(blockIdx.x * blockDim.x), n - 1);
+  const double ox = R[3 * i0], oy = R[3 * i0 + 1], oz = R[3 * i0 + 2];
+  const float xi = (float)(R[3 * ii] - ox), yi = (float)(R[3 * ii + 1] - oy),
+              zi = (float)(R[3 * ii + 2] - oz);
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  const float A24 = (float)(24.0 * a2), A42 = (float)(42.0 * a2);
+  float s_a[5] = {0, 0, 0, 0, 0}, c_a[5] = {0, 0, 0, 0, 0};
+  float s_t[5] = {0, 0, 0, 0, 0}, c_t[5] = {0, 0, 0, 0, 0};
+  for (int jt = j0; jt < j1; jt += TJ) {
+    const int cnt = min(TJ, j1 - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const int j = jt + t;
+      double sxx, syy, sxy, sxz, syz;
+      basis_to_cart(X + 5 * j, sxx, syy, sxy, sxz, syz);
+      RecS32 rc;
+      rc.x = (float)(R[3 * j] - ox);
+      rc.y = (float)(R[3 * j + 1] - oy);
+      rc.z = (float)(R[3 * j + 2] - oz);
+      rc.sxx = (float)sxx;
+      rc.syy = (float)syy;
+      rc.sxy = (float)sxy;
+      rc.sxz = (float)sxz;
+      rc.syz = (float)syz;
+      tile[t] = rc;
+    }
+    __syncthreads();
+    float a0 = 0, a1 = 0, a2c = 0, a3 = 0, a4 = 0;
+    float t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
+#pragma unroll 2
+    for (int jj = 0; jj < cnt; ++jj) {
+      const RecS32 s = tile[jj];
+      const float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      const float ri = rinv_or_zero(r2);
+      const float ri2 = ri * ri;
+      const float ri5 = ri2 * ri2 * ri;
+      const float ri7 = ri5 * ri2;
+      const float szz = -(s.sxx + s.syy);
+      const float wx = s.sxx * dx + s.sxy * dy + s.sxz * dz;
+      const float wy = s.sxy * dx + s.syy * dy + s.syz * dz;
+      const float wz = s.sxz * dx + s.syz * dy + szz * dz;
+      const float q = dx * wx + dy * wy + dz * wz;
+      const float c1 = ri5 * fmaf(A24, ri2, -6.0f);
+      const float c2 = q * ri7 * fmaf(-A42, ri2, 15.0f);
+      const float vx = fmaf(c1, wx, c2 * dx);
+      const float vy = fmaf(c1, wy, c2 * dy);
+      const float vz = fmaf(c1, wz, c2 * dz);
+      acc_sym(dx, dy, dz, vx, vy, vz, a0, a1, a2c, a3, a4);
+      t0 = fmaf(ri5, s.sxx, t0);
+      t1 = fmaf(ri5, s.syy, t1);
+      t2 = fmaf(ri5, s.sxy, t2);
+      t3 = fmaf(ri5, s.sxz, t3);
+      t4 = fmaf(ri5, s.syz, t4);
+    }
+    kahan_add(s_a[0], c_a[0], a0);
+    kahan_add(s_a[1], c_a[1], a1);
+    kahan_add(s_a[2], c_a[2], a2c);
+    kahan_add(s_a[3], c_a[3], a3);
+    kahan_add(s_a[4], c_a[4], a4);
+    kahan_add(s_t[0], c_t[0], t0);
+    kahan_add(s_t[1], c_t[1], t1);
+    kahan_add(s_t[2], c_t[2], t2);
+    kahan_add(s_t[3], c_t[3], t3);
+    kahan_add(s_t[4], c_t[4], t4);
+  }
+  if (i >= n) return;
+  double A[5], Tt[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    A[c] = (double)s_a[c] - (double)c_a[c];
+    Tt[c] = (double)s_t[c] - (double)c_t[c];
+  }
+  const double C3 = -2.4 * a2;
+  double e[5];
+  e[0] = P * RS2 * (A[0] + C3 * (Tt[0] - Tt[1]));
+  e[1] = P * RS6 * (A[1] - 3.0 * C3 * (Tt[0] + Tt[1]));
+  e[2] = P * RS2 * (A[2] + 2.0 * C3 * Tt[2]);
+  e[3] = P * RS2 * (A[3] + 2.0 * C3 * Tt[3]);
+  e[4] = P * RS2 * (A[4] + 2.0 * C3 * Tt[4]);
+  if (direct) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[5 * (int64_t)i + c] = X[5 * (int64_t)i + c] * inv_gamma - e[c];
+  } else {
+    double* o = out + (int64_t)blockIdx.y * 5 * n + 5 * (int64_t)i;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) o[c] = e[c];
+  }
+}
+
+// y = x/gamma - sum_s part[s]
+__global__ void k_p2_finish(const double* __restrict__ X, const double* __restrict__ part,
+                            double* __restrict__ y, int64_t len, int split, double inv_gamma) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  double acc = 0.0;
+  for (int s = 0; s < split; ++s) acc += part[s * len + k];
+  y[k] = X[k] * inv_gamma - acc;
+}
+
+// ------------------------------------------------------------------ P1: right-hand side
+struct alignas(16) RecF {
+  double x, y, z, fx, fy, fz, tx, ty, tz, dx, dy, dz;
+};
+
+template <int TJ, bool HAS_T, bool HAS_D>
+__global__ void __launch_bounds__(kMaxBlock)
+    k_p1(const double* __restrict__ R, const double* __restrict__ Fe, const double* __restrict__ Te,
+         const double* __restrict__ D, const double* __restrict__ v2s, double* __restrict__ out,
+         int n, int chunk, double P, double a2, double a5_10, double cslip, int direct) {
+  __shared__ RecF tile[TJ];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const double xi = R[3 * ii], yi = R[3 * ii + 1], zi = R[3 * ii + 2];
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  const double A8 = 8.0 * a2, B16 = -3.2 * a2;  // 8a^2, -(16/5) a^2
+  double a0 = 0, a1 = 0, a2c = 0, a3 = 0, a4 = 0;
+  for (int jt = j0; jt < j1; jt += TJ) {
+    const int cnt = min(TJ, j1 - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const int j = jt + t;
+      RecF rc;
+      rc.x = R[3 * j];
+      rc.y = R[3 * j + 1];
+      rc.z = R[3 * j + 2];
+      rc.fx = P * Fe[3 * j];
+      rc.fy = P * Fe[3 * j + 1];
+      rc.fz = P * Fe[3 * j + 2];
+      if (HAS_T) {
+        rc.tx = P * Te[3 * j];
+        rc.ty = P * Te[3 * j + 1];
+        rc.tz = P * Te[3 * j + 2];
+      } else {
+        rc.tx = rc.ty = rc.tz = 0.0;
+      }
+      if (HAS_D) {
+        rc.dx = a5_10 * D[3 * j];
+        rc.dy = a5_10 * D[3 * j + 1];
+        rc.dz = a5_10 * D[3 * j + 2];
+      } else {
+        rc.dx = rc.dy = rc.dz = 0.0;
+      }
+      tile[t] = rc;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int jj = 0; jj < cnt; ++jj) {
+      const RecF& s = tile[jj];
+      const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double ri = rinv_or_zero(r2);
+      const double ri2 = ri * ri;
+      const double ri5 = ri2 * ri2 * ri;
+      const double ri7 = ri5 * ri2;
+      const double xF = dx * s.fx + dy * s.fy + dz * s.fz;
+      double alpha = xF * ri5 * fma(A8, ri2, -3.0);
+      const double beta = B16 * ri5;
+      double vx = fma(beta, s.fx, alpha * dx);
+      double vy = fma(beta, s.fy, alpha * dy);
+      double vz = fma(beta, s.fz, alpha * dz);
+      if (HAS_T) {  // -3 (T x x) / r^5
+        const double m3 = -3.0 * ri5;
+        vx = fma(m3, s.ty * dz - s.tz * dy, vx);
+        vy = fma(m3, s.tz * dx - s.tx * dz, vy);
+        vz = fma(m3, s.tx * dy - s.ty * dx, vz);
+      }
+      if (HAS_D) {  // 6 d / r^5 - 15 (x.d) x / r^7
+        const double xd = -15.0 * ri7 * (dx * s.dx + dy * s.dy + dz * s.dz);
+        const double six = 6.0 * ri5;
+        vx = fma(six, s.dx, fma(xd, dx, vx));
+        vy = fma(six, s.dy, fma(xd, dy, vy));
+        vz = fma(six, s.dz, fma(xd, dz, vz));
+      }
+      acc_sym(dx, dy, dz, vx, vy, vz, a0, a1, a2c, a3, a4);
+    }
+  }
+  if (i >= n) return;
+  double e[5] = {RS2 * a0, RS6 * a1, RS2 * a2c, RS2 * a3, RS2 * a4};
+  if (direct) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+      out[5 * (int64_t)i + c] = e[c] - (v2s ? cslip * v2s[5 * (int64_t)i + c] : 0.0);
+  } else {
+    double* o = out + (int64_t)blockIdx.y * 5 * n + 5 * (int64_t)i;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) o[c] = e[c];
+  }
+}
+
+__global__ void k_p1_finish(const double* __restrict__ part, const double* __restrict__ v2s,
+                            double* __restrict__ b, int64_t len, int split, double cslip) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  double acc = 0.0;
+  for (int s = 0; s < split; ++s) acc += part[s * len + k];
+  b[k] = acc - (v2s ? cslip * v2s[k] : 0.0);
+}
+
+// ------------------------------------------------------------------ P3: rigid-body outputs
+struct alignas(16) RecO {
+  double x, y, z, fx, fy, fz, tx, ty, tz, sxx, syy, sxy, sxz, syz, dx, dy, dz, pad;
+};
+
+template <int TJ, bool HAS_T, bool HAS_D>
+__global__ void __launch_bounds__(kMaxBlock)
+    k_p3(const double* __restrict__ R, const double* __restrict__ Fe, const double* __restrict__ Te,
+         const double* __restrict__ Sig, const double* __restrict__ D, double* __restrict__ out,
+         int n, int chunk, double P, double a2, double a5_10) {
+  __shared__ RecO tile[TJ];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const double xi = R[3 * ii], yi = R[3 * ii + 1], zi = R[3 * ii + 2];
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  const double A2_2 = 2.0 * a2, A2_23 = 2.0 * a2 / 3.0, A8 = 8.0 * a2, B16 = -3.2 * a2;
+  double ux = 0, uy = 0, uz = 0, wx_ = 0, wy_ = 0, wz_ = 0;
+  for (int jt = j0; jt < j1; jt += TJ) {
+    const int cnt = min(TJ, j1 - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const int j = jt + t;
+      RecO rc;
+      rc.x = R[3 * j];
+      rc.y = R[3 * j + 1];
+      rc.z = R[3 * j + 2];
+      rc.fx = P * Fe[3 * j];
+      rc.fy = P * Fe[3 * j + 1];
+      rc.fz = P * Fe[3 * j + 2];
+      if (HAS_T) {
+        rc.tx = P * Te[3 * j];
+        rc.ty = P * Te[3 * j + 1];
+        rc.tz = P * Te[3 * j + 2];
+      } else {
+        rc.tx = rc.ty = rc.tz = 0.0;
+      }
+      double sxx, syy, sxy, sxz, syz;
+      basis_to_cart(Sig + 5 * j, sxx, syy, sxy, sxz, syz);
+      rc.sxx = P * sxx;
+      rc.syy = P * syy;
+      rc.sxy = P * sxy;
+      rc.sxz = P * sxz;
+      rc.syz = P * syz;
+      if (HAS_D) {
+        rc.dx = a5_10 * D[3 * j];
+        rc.dy = a5_10 * D[3 * j + 1];
+        rc.dz = a5_10 * D[3 * j + 2];
+      } else {
+        rc.dx = rc.dy = rc.dz = 0.0;
+      }
+      rc.pad = 0.0;
+      tile[t] = rc;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int jj = 0; jj < cnt; ++jj) {
+      const RecO& s = tile[jj];
+      const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double ri = rinv_or_zero(r2);
+      const double ri2 = ri * ri;
+      const double ri3 = ri2 * ri;
+      const double ri5 = ri3 * ri2;
+      const double szz = -(s.sxx + s.syy);
+      const double wx = s.sxx * dx + s.sxy * dy + s.sxz * dz;
+      const double wy = s.sxy * dx + s.syy * dy + s.syz * dz;
+      const double wz = s.sxz * dx + s.syz * dy + szz * dz;
+      const double q = dx * wx + dy * wy + dz * wz;
+      const double xF = dx * s.fx + dy * s.fy + dz * s.fz;
+      double cx = xF * fma(-A2_2, ri5, ri3) + q * ri5 * fma(A8, ri2, -3.0);
+      const double cF = fma(A2_23, ri3, ri);
+      const double cw = B16 * ri5;
+      if (HAS_D) cx = fma(3.0 * ri5, dx * s.dx + dy * s.dy + dz * s.dz, cx);
+      ux = fma(cx, dx, fma(cF, s.fx, fma(cw, wx, ux)));
+      uy = fma(cx, dy, fma(cF, s.fy, fma(cw, wy, uy)));
+      uz = fma(cx, dz, fma(cF, s.fz, fma(cw, wz, uz)));
+      // rotation: x cross (-F/r^3 + 3 w / r^5)
+      const double gx = fma(3.0 * ri5, wx, -ri3 * s.fx);
+      const double gy = fma(3.0 * ri5, wy, -ri3 * s.fy);
+      const double gz = fma(3.0 * ri5, wz, -ri3 * s.fz);
+      wx_ += dy * gz - dz * gy;
+      wy_ += dz * gx - dx * gz;
+      wz_ += dx * gy - dy * gx;
+      if (HAS_T) {
+        // U += (T x x)/r^3 ; W += 1.5 (x.T) x / r^5 - 0.5 T / r^3
+        ux = fma(ri3, s.ty * dz - s.tz * dy, ux);
+        uy = fma(ri3, s.tz * dx - s.tx * dz, uy);
+        uz = fma(ri3, s.tx * dy - s.ty * dx, uz);
+        const double xT = 1.5 * ri5 * (dx * s.tx + dy * s.ty + dz * s.tz);
+        const double h = -0.5 * ri3;
+        wx_ = fma(xT, dx, fma(h, s.tx, wx_));
+        wy_ = fma(xT, dy, fma(h, s.ty, wy_));
+        wz_ = fma(xT, dz, fma(h, s.tz, wz_));
+      }
+      if (HAS_D) {  // U += -d / r^3 (the (x.d) x part is in cx)
+        ux = fma(-ri3, s.dx, ux);
+        uy = fma(-ri3, s.dy, uy);
+        uz = fma(-ri3, s.dz, uz);
+      }
+    }
+  }
+  if (i >= n) return;
+  double* o = out + (int64_t)blockIdx.y * 6 * n + 6 * (int64_t)i;
+  o[0] = ux;
+  o[1] = uy;
+  o[2] = uz;
+  o[3] = wx_;
+  o[4] = wy_;
+  o[5] = wz_;
+}
+
+__global__ void k_p3_finish(const double* __restrict__ part, int split, int64_t n,
+                            const double* __restrict__ v1s, const double* __restrict__ v2s,
+                            const double* __restrict__ Fe, const double* __restrict__ Te,
+                            const double* __restrict__ Sig, double* __restrict__ V,
+                            double* __restrict__ W, double* __restrict__ S, double mu_t,
+                            double mu_r, double slip_S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int s = 0; s < split; ++s) {
+    const double* p = part + (int64_t)s * 6 * n + 6 * i;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += p[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    V[3 * i + c] = acc[c] + mu_t * Fe[3 * i + c] - (v1s ? v1s[3 * i + c] : 0.0);
+    W[3 * i + c] = acc[3 + c] + (Te ? mu_r * Te[3 * i + c] : 0.0);
+  }
+  if (S) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) S[5 * i + c] = Sig[5 * i + c] + (v2s ? slip_S * v2s[5 * i + c] : 0.0);
+  }
+}
+
+// ------------------------------------------------------------------ overlap monitor
+template <int TJ>
+__global__ void __launch_bounds__(kMaxBlock)
+    k_min_dist2(const double* __restrict__ R, int n, double* __restrict__ blockmin) {
+  __shared__ double tx[TJ], ty[TJ], tz[TJ];
+  __shared__ double red[kMaxBlock];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const double xi = R[3 * ii], yi = R[3 * ii + 1], zi = R[3 * ii + 2];
+  double best = INFINITY;
+  for (int jt = 0; jt < n; jt += TJ) {
+    const int cnt = min(TJ, n - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      tx[t] = R[3 * (jt + t)];
+      ty[t] = R[3 * (jt + t) + 1];
+      tz[t] = R[3 * (jt + t) + 2];
+    }
+    __syncthreads();
+    for (int jj = 0; jj < cnt; ++jj) {
+      const double dx = xi - tx[jj], dy = yi - ty[jj], dz = zi - tz[jj];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (jt + jj != ii) best = fmin(best, r2);
+    }
+  }
+  red[threadIdx.x] = (i < n) ? best : INFINITY;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blockmin[blockIdx.x] = red[0];
+}
+
+__global__ void k_min_finish(const double* __restrict__ blockmin, int nb, double* __restrict__ out) {
+  __shared__ double red[kMaxBlock];
+  double best = INFINITY;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) best = fmin(best, blockmin[k]);
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ void k_count_nonfinite(const double* __restrict__ a, int64_t len, int* __restrict__ cnt) {
+  __shared__ int red[kMaxBlock];
+  int bad = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < len;
+       k += (int64_t)gridDim.x * blockDim.x)
+    bad += isfinite(a[k]) ? 0 : 1;
+  red[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0) atomicAdd(cnt, red[0]);
+}
+
+// ------------------------------------------------------------------ Krylov helpers
+constexpr int kDotThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  // wavefront reduction (64 lanes), then across the 4 wavefronts of the block through LDS
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int k = 0; k < nw; ++k) s += red[k];
+  }
+  return s;
+}
+
+// part[k * gridDim.x + b] = sum over block b's range of V_k . w
+__global__ void __launch_bounds__(kDotThreads)
+    k_dots(const double* __restrict__ V, int64_t ld, const double* __restrict__ w, int64_t len,
+           int64_t per, double* __restrict__ part) {
+  __shared__ double red[kDotThreads / 64];
+  const int k = blockIdx.y;
+  const double* v = V + (int64_t)k * ld;
+  const int64_t beg = (int64_t)blockIdx.x * per;
+  const int64_t end = min(len, beg + per);
+  double acc = 0.0;
+  for (int64_t t = beg + threadIdx.x; t < end; t += blockDim.x) acc = fma(v[t], w[t], acc);
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) part[(int64_t)k * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kDotThreads)
+    k_dots_finish(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double red[kDotThreads / 64];
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[(int64_t)k * nb + b];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) out[k] = s;
+}
+
+__global__ void k_axpy_multi(const double* __restrict__ V, int64_t ld, int nv,
+                             const double* __restrict__ h, double sign, double* __restrict__ w,
+                             int64_t len) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= len) return;
+  double acc = 0.0;
+  for (int k = 0; k < nv; ++k) acc = fma(h[k], V[(int64_t)k * ld + t], acc);
+  w[t] = fma(sign, acc, w[t]);
+}
+
+__global__ void k_scale_by(const double* __restrict__ x, const double* __restrict__ alpha, int inv,
+                           double* __restrict__ y, int64_t len) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= len) return;
+  const double al = alpha[0];
+  if (inv) {
+    y[t] = al > 0.0 ? x[t] / al : 0.0;
+  } else {
+    y[t] = al * x[t];
+  }
+}
+
+__global__ void k_axpby(double a, const double* __restrict__ x, double b, double* __restrict__ y,
+                        int64_t len) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= len) return;
+  y[t] = a * x[t] + (b == 0.0 ? 0.0 : b * y[t]);
+}
+
+__global__ void k_copy(const double* __restrict__ x, double* __restrict__ y, int64_t len) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < len) y[t] = x[t];
+}
+
+__global__ void k_givens(double* __restrict__ H, int m, int k, const double* __restrict__ h1,
+                         const double* __restrict__ h2, const double* __restrict__ nsq,
+                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                         double* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* col = H + (int64_t)k * (m + 1);
+  for (int i = 0; i <= k; ++i) col[i] = h1[i] + (h2 ? h2[i] : 0.0);
+  const double hk1 = sqrt(fmax(nsq[0], 0.0));
+  col[k + 1] = hk1;
+  status[1] = hk1;
+  for (int i = 0; i < k; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double den = hypot(col[k], hk1);
+  if (den > 0.0) {
+    cs[k] = col[k] / den;
+    sn[k] = hk1 / den;
+  } else {
+    cs[k] = 1.0;
+    sn[k] = 0.0;
+  }
+  col[k] = den;
+  col[k + 1] = 0.0;
+  g[k + 1] = -sn[k] * g[k];
+  g[k] = cs[k] * g[k];
+  status[0] = fabs(g[k + 1]);
+}
+
+__global__ void k_backsolve(const double* __restrict__ H, int m, int k, const double* __restrict__ g,
+                            double* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int j = i + 1; j < k; ++j) s -= H[(int64_t)j * (m + 1) + i] * y[j];
+    const double d = H[(int64_t)i * (m + 1) + i];
+    y[i] = d != 0.0 ? s / d : 0.0;
+  }
+}
+
+__global__ void k_init_g(const double* __restrict__ nsq, double* __restrict__ g, int m,
+                         double* __restrict__ status) {
+  const int t = threadIdx.x;
+  const double beta = sqrt(fmax(nsq[0], 0.0));
+  for (int k = t; k <= m; k += blockDim.x) g[k] = (k == 0) ? beta : 0.0;
+  if (t == 0) {
+    status[0] = beta;
+    status[1] = beta;
+  }
+}
+
+// ------------------------------------------------------------------ stepper
+__global__ void k_trap_modes(const double* __restrict__ R, const double* __restrict__ p, double k,
+                             double c0, double c1, double c2, double* __restrict__ Fe,
+                             double* __restrict__ v1s, double* __restrict__ v2s,
+                             double* __restrict__ v3t, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double px = p[3 * i], py = p[3 * i + 1], pz = p[3 * i + 2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) Fe[3 * i + c] = -k * R[3 * i + c];
+  v1s[3 * i] = c0 * px;
+  v1s[3 * i + 1] = c0 * py;
+  v1s[3 * i + 2] = c0 * pz;
+  // 3 (p p - I/3) in the 5-basis
+  v2s[5 * i + 0] = c1 * 3.0 * RS2 * (px * px - py * py);
+  v2s[5 * i + 1] = c1 * 3.0 * RS6 * (2.0 * pz * pz - px * px - py * py);
+  v2s[5 * i + 2] = c1 * 6.0 * RS2 * px * py;
+  v2s[5 * i + 3] = c1 * 6.0 * RS2 * px * pz;
+  v2s[5 * i + 4] = c1 * 6.0 * RS2 * py * pz;
+  v3t[3 * i] = c2 * px;
+  v3t[3 * i + 1] = c2 * py;
+  v3t[3 * i + 2] = c2 * pz;
+}
+
+__global__ void k_ab_update(double* __restrict__ R, double* __restrict__ p,
+                            const double* __restrict__ V, const double* __restrict__ W,
+                            double* __restrict__ Vprev, double* __restrict__ Pdprev, double dt,
+                            int first, int order, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double px = p[3 * i], py = p[3 * i + 1], pz = p[3 * i + 2];
+  const double wx = W[3 * i], wy = W[3 * i + 1], wz = W[3 * i + 2];
+  const double pd[3] = {wy * pz - wz * py, wz * px - wx * pz, wx * py - wy * px};
+  double q[3] = {px, py, pz};
+  const bool euler = first || order == 1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double v = V[3 * i + c];
+    if (euler) {
+      R[3 * i + c] += dt * v;
+      q[c] += dt * pd[c];
+    } else {
+      R[3 * i + c] += dt * (1.5 * v - 0.5 * Vprev[3 * i + c]);
+      q[c] += dt * (1.5 * pd[c] - 0.5 * Pdprev[3 * i + c]);
+    }
+    Vprev[3 * i + c] = v;
+    Pdprev[3 * i + c] = pd[c];
+  }
+  const double inv = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) p[3 * i + c] = q[c] * inv;
+}
+
+inline unsigned nblk(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+Phys make_phys(double eta, double a, double c) {
+  Phys p;
+  p.eta = eta;
+  p.a = a;
+  p.P = 1.0 / (8.0 * M_PI * eta);
+  p.a2 = a * a;
+  p.a5_10 = a * a * a * a * a / 10.0;
+  p.gamma = 20.0 / 3.0 * M_PI * eta * a * a * a;
+  p.inv_gamma = 1.0 / p.gamma;
+  p.mu_t = 1.0 / (6.0 * M_PI * eta * a);
+  p.mu_r = 1.0 / (8.0 * M_PI * eta * a * a * a);
+  p.slip_S = 8.0 / 3.0 * M_PI * eta * a * a * a;
+  p.c_slip = c;
+  return p;
+}
+
+static int normalize_block(int b) { return (b == 64 || b == 128 || b == 256) ? b : 256; }
+static int normalize_tj(int tj) { return (tj == 64 || tj == 128 || tj == 256) ? tj : 128; }
+
+int split_for(int64_t n, Tile t) {
+  const int b = normalize_block(t.block);
+  const int tj = normalize_tj(t.tj);
+  const int64_t ntile_i = (n + b - 1) / b;
+  const int64_t max_split = std::max<int64_t>(1, (n + tj - 1) / tj);
+  int64_t s = t.split;
+  if (s <= 0) {
+    // aim at >= 2048 workgroups (8 per CU on 256 CUs) while keeping chunks >= one LDS tile
+    s = (2048 + ntile_i - 1) / ntile_i;
+  }
+  s = std::min<int64_t>(std::max<int64_t>(s, 1), max_split);
+  return (int)s;
+}
+
+int64_t part_elems(int64_t n, Tile t, int width) {
+  const int s = split_for(n, t);
+  return s > 1 ? (int64_t)s * width * n : 0;
+}
+
+template <int TJ>
+static void p2_dispatch(bool f32, const double* R, const double* x, double* y, double* part,
+                        int64_t n, const Phys& ph, int b, int split, hipStream_t s) {
+  const int chunk = (int)((n + split - 1) / split);
+  dim3 grid(nblk(n, b), split);
+  double* out = split > 1 ? part : y;
+  const int direct = split > 1 ? 0 : 1;
+  if (f32)
+    hipLaunchKernelGGL(k_p2_f32<TJ>, grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P, ph.a2,
+                       ph.inv_gamma, direct);
+  else
+    hipLaunchKernelGGL(k_p2_f64<TJ>, grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P, ph.a2,
+                       ph.inv_gamma, direct);
+  if (split > 1)
+    hipLaunchKernelGGL(k_p2_finish, dim3(nblk(5 * n, 256)), dim3(256), 0, s, x, part, y, 5 * n,
+                       split, ph.inv_gamma);
+}
+
+static void p2_any(bool f32, const double* R, const double* x, double* y, double* part, int64_t n,
+                   const Phys& ph, Tile t, hipStream_t s) {
+  const int b = normalize_block(t.block);
+  const int tj = normalize_tj(t.tj);
+  const int split = split_for(n, t);
+  if (tj == 64)
+    p2_dispatch<64>(f32, R, x, y, part, n, ph, b, split, s);
+  else if (tj == 128)
+    p2_dispatch<128>(f32, R, x, y, part, n, ph, b, split, s);
+  else
+    p2_dispatch<256>(f32, R, x, y, part, n, ph, b, split, s);
+}
+
+void launch_p2_f64(const double* R, const double* x, double* y, double* part, int64_t n,
+                   const Phys& ph, Tile t, hipStream_t s) {
+  p2_any(false, R, x, y, part, n, ph, t, s);
+}
+void launch_p2_f32(const double* R, const double* x, double* y, double* part, int64_t n,
+                   const Phys& ph, Tile t, hipStream_t s) {
+  p2_any(true, R, x, y, part, n, ph, t, s);
+}
+
+void launch_p1(const double* R, const double* v2s, const double* v3t, const double* Fe,
+               const double* Te, double* b, double* part, int64_t n, const Phys& ph, Tile t,
+               hipStream_t s) {
+  constexpr int TJ = 128;
+  const int bs = normalize_block(t.block);
+  Tile tt = t;
+  tt.tj = TJ;
+  const int split = split_for(n, tt);
+  const int chunk = (int)((n + split - 1) / split);
+  dim3 grid(nblk(n, bs), split);
+  double* out = split > 1 ? part : b;
+  const int direct = split > 1 ? 0 : 1;
+#define MBS_P1(HT, HD)                                                                           \
+  hipLaunchKernelGGL((k_p1<TJ, HT, HD>), grid, dim3(bs), 0, s, R, Fe, Te, v3t, v2s, out, (int)n, \
+                     chunk, ph.P, ph.a2, ph.a5_10, ph.c_slip, direct)
+  if (Te && v3t)
+    MBS_P1(true, true);
+  else if (Te)
+    MBS_P1(true, false);
+  else if (v3t)
+    MBS_P1(false, true);
+  else
+    MBS_P1(false, false);
+#undef MBS_P1
+  if (split > 1)
+    hipLaunchKernelGGL(k_p1_finish, dim3(nblk(5 * n, 256)), dim3(256), 0, s, part, v2s, b, 5 * n,
+                       split, ph.c_slip);
+}
+
+void launch_p3(const double* R, const double* v1s, const double* v2s, const double* v3t,
+               const double* Fe, const double* Te, const double* Sig, double* V, double* W,
+               double* S, double* part, int64_t n, const Phys& ph, Tile t, hipStream_t s) {
+  constexpr int TJ = 128;
+  const int bs = normalize_block(t.block);
+  Tile tt = t;
+  tt.tj = TJ;
+  // the output pass always goes through the partial buffer (6 values per receiver and chunk)
+  const int split = split_for(n, tt);
+  const int chunk = (int)((n + split - 1) / split);
+  dim3 grid(nblk(n, bs), split);
+#define MBS_P3(HT, HD)                                                                          \
+  hipLaunchKernelGGL((k_p3<TJ, HT, HD>), grid, dim3(bs), 0, s, R, Fe, Te, Sig, v3t, part, (int)n, \
+                     chunk, ph.P, ph.a2, ph.a5_10)
+  if (Te && v3t)
+    MBS_P3(true, true);
+  else if (Te)
+    MBS_P3(true, false);
+  else if (v3t)
+    MBS_P3(false, true);
+  else
+    MBS_P3(false, false);
+#undef MBS_P3
+  hipLaunchKernelGGL(k_p3_finish, dim3(nblk(n, 256)), dim3(256), 0, s, part, split, n, v1s, v2s, Fe,
+                     Te, Sig, V, W, S, ph.mu_t, ph.mu_r, ph.slip_S);
+}
+
+void launch_min_dist2(const double* R, int64_t n, double* out, double* scratch, hipStream_t s) {
+  const unsigned nb = nblk(n, 256);
+  hipLaunchKernelGGL(k_min_dist2<256>, dim3(nb), dim3(256), 0, s, R, (int)n, scratch);
+  hipLaunchKernelGGL(k_min_finish, dim3(1), dim3(256), 0, s, scratch, (int)nb, out);
+}
+
+void launch_count_nonfinite(const double* a, int64_t len, int* cnt, hipStream_t s) {
+  if (len <= 0) return;
+  const unsigned nb = std::min<unsigned>(nblk(len, 256), 1024u);
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(nb), dim3(256), 0, s, a, len, cnt);
+}
+
+int dot_blocks(int64_t len) {
+  int64_t b = (len + 2047) / 2048;
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 256);
+}
+
+void launch_dots(const double* V, int64_t ld, int nv, const double* w, int64_t len, double* part,
+                 double* out, hipStream_t s) {
+  const int nb = dot_blocks(len);
+  const int64_t per = (len + nb - 1) / nb;
+  hipLaunchKernelGGL(k_dots, dim3(nb, nv), dim3(kDotThreads), 0, s, V, ld, w, len, per, part);
+  hipLaunchKernelGGL(k_dots_finish, dim3(nv), dim3(kDotThreads), 0, s, part, nb, out);
+}
+
+void launch_axpy_multi(const double* V, int64_t ld, int nv, const double* h, double sign, double* w,
+                       int64_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_multi, dim3(nblk(len, 256)), dim3(256), 0, s, V, ld, nv, h, sign, w,
+                     len);
+}
+
+void launch_scale_by(const double* x, const double* alpha, int inv, double* y, int64_t len,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_by, dim3(nblk(len, 256)), dim3(256), 0, s, x, alpha, inv, y, len);
+}
+
+void launch_axpby(double a, const double* x, double b, double* y, int64_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(nblk(len, 256)), dim3(256), 0, s, a, x, b, y, len);
+}
+
+void launch_copy(const double* x, double* y, int64_t len, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(nblk(len, 256)), dim3(256), 0, s, x, y, len);
+}
+
+void launch_givens(double* H, int m, int k, const double* h1, const double* h2, const double* nsq,
+                   double* cs, double* sn, double* g, double* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, H, m, k, h1, h2, nsq, cs, sn, g, status);
+}
+
+void launch_backsolve(const double* H, int m, int k, const double* g, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, H, m, k, g, y);
+}
+
+void launch_init_g(const double* nsq, double* g, int m, double* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_g, dim3(1), dim3(64), 0, s, nsq, g, m, status);
+}
+
+void launch_trap_modes(const double* R, const double* p, double k, double c0, double c1, double c2,
+                       double* Fe, double* v1s, double* v2s, double* v3t, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_trap_modes, dim3(nblk(n, 256)), dim3(256), 0, s, R, p, k, c0, c1, c2, Fe, v1s,
+                     v2s, v3t, n);
+}
+
+void launch_ab_update(double* R, double* p, const double* V, const double* W, double* Vprev,
+                      double* Pdprev, double dt, int first, int order, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_ab_update, dim3(nblk(n, 256)), dim3(256), 0, s, R, p, V, W, Vprev, Pdprev, dt,
+                     first, order, n);
+}
+
+}  // namespace mbs

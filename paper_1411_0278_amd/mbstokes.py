@@ -1,0 +1,248 @@
+"""Python binding of libmbstokes (ctypes): argument marshalling only.
+
+Every call goes through the C ABI declared in include/mbstokes.h; the arithmetic runs in the
+library's HIP kernels. Tensors are torch float64 CUDA tensors (device memory of the context's
+GPU); the current torch stream is passed to the library. If the shared library is missing or
+no GPU is present, the calls raise instead of computing anything elsewhere.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmbstokes.so")
+
+MBS_OK, MBS_EINVAL, MBS_ENOCONV, MBS_EOVERLAP, MBS_EUNSUPPORTED, MBS_ENOMEM, MBS_EHIP = 0, -1, -2, -3, -4, -5, -6
+ERROR_NAMES = {MBS_EINVAL: "MBS_EINVAL", MBS_ENOCONV: "MBS_ENOCONV", MBS_EOVERLAP: "MBS_EOVERLAP",
+               MBS_EUNSUPPORTED: "MBS_EUNSUPPORTED", MBS_ENOMEM: "MBS_ENOMEM", MBS_EHIP: "MBS_EHIP"}
+MBS_FP64, MBS_MIXED, MBS_FP32 = 0, 1, 1
+MBS_GUESS_ZERO, MBS_GUESS_DIAG, MBS_GUESS_LEARNED, MBS_GUESS_USER = 0, 1, 2, 3
+
+EXPORTS = ("mbs_default_params", "mbs_create", "mbs_destroy", "mbs_set_params", "mbs_last_error",
+           "mbs_solve", "mbs_matvec", "mbs_rhs", "mbs_outputs", "mbs_step", "mbs_solve_batched",
+           "mbs_autotune")
+
+
+class MbsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("a", ctypes.c_double), ("tol", ctypes.c_double),
+                ("self_slip_c", ctypes.c_double), ("inner_tol", ctypes.c_double),
+                ("lmax", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("guess", ctypes.c_int32),
+                ("check_overlap", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("refinements", ctypes.c_int32),
+                ("fp64_matvecs", ctypes.c_int32), ("fp32_matvecs", ctypes.c_int32),
+                ("rel_resid", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("t_rhs_ms", ctypes.c_double), ("t_iter_ms", ctypes.c_double),
+                ("t_out_ms", ctypes.c_double), ("pair_blocks", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libmbstokes.so not found at {path}: build it with "
+                           "`python -m paper_1411_0278_amd.build` (no fallback path exists)")
+    lib = ctypes.CDLL(path)
+    P, D, I32, I64, VP = ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.mbs_default_params.argtypes = [ctypes.POINTER(Params)]
+    lib.mbs_default_params.restype = None
+    lib.mbs_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(Params)]
+    lib.mbs_create.restype = ctypes.c_int
+    lib.mbs_destroy.argtypes = [P]
+    lib.mbs_destroy.restype = None
+    lib.mbs_set_params.argtypes = [P, ctypes.POINTER(Params)]
+    lib.mbs_set_params.restype = ctypes.c_int
+    lib.mbs_last_error.argtypes = [P]
+    lib.mbs_last_error.restype = ctypes.c_char_p
+    lib.mbs_solve.argtypes = [P, I64] + [P] * 12 + [ctypes.POINTER(Stats), VP]
+    lib.mbs_solve.restype = ctypes.c_int
+    lib.mbs_matvec.argtypes = [P, I64, P, P, P, ctypes.c_int, VP]
+    lib.mbs_matvec.restype = ctypes.c_int
+    lib.mbs_rhs.argtypes = [P, I64, P, P, P, P, P, P, VP]
+    lib.mbs_rhs.restype = ctypes.c_int
+    lib.mbs_outputs.argtypes = [P, I64] + [P] * 10 + [VP]
+    lib.mbs_outputs.restype = ctypes.c_int
+    lib.mbs_step.argtypes = [P, I64, P, P, D, ctypes.POINTER(ctypes.c_double), D, I32, I32,
+                             ctypes.POINTER(Stats), ctypes.POINTER(ctypes.c_double), VP]
+    lib.mbs_step.restype = ctypes.c_int
+    lib.mbs_solve_batched.argtypes = [P, I32, ctypes.POINTER(ctypes.c_int64)] + [P] * 10 + [
+        ctypes.POINTER(Stats), ctypes.POINTER(ctypes.c_double), VP]
+    lib.mbs_solve_batched.restype = ctypes.c_int
+    lib.mbs_autotune.argtypes = [P, I64, P, ctypes.c_char_p, VP]
+    lib.mbs_autotune.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def default_params(**kw) -> Params:
+    lib = load()
+    p = Params()
+    lib.mbs_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t, n=None, width=None, name="array"):
+    """Device pointer of a float64 CUDA tensor (None -> NULL), with shape checks."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name}: expected a torch.float64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if n is not None and width is not None and tuple(t.shape) != (n, width):
+        raise ValueError(f"{name}: expected shape ({n}, {width}), got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A solver context on one GPU (wraps mbs_create / mbs_destroy)."""
+
+    def __init__(self, device: int = 0, **params):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: libmbstokes runs only on the device")
+        self.lib = load()
+        self.device = device
+        self.params = default_params(**params)
+        h = ctypes.c_void_p()
+        torch.cuda.set_device(device)
+        rc = self.lib.mbs_create(ctypes.byref(h), device, ctypes.byref(self.params))
+        if rc != MBS_OK:
+            raise MbsError(rc, self.lib.mbs_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mbs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != MBS_OK and rc not in allow:
+            raise MbsError(rc, self.lib.mbs_last_error(self.h).decode())
+        return rc
+
+    def set_params(self, **kw):
+        for k, v in kw.items():
+            if not hasattr(self.params, k):
+                raise AttributeError(k)
+            setattr(self.params, k, v)
+        self._check(self.lib.mbs_set_params(self.h, ctypes.byref(self.params)))
+
+    # ------------------------------------------------------------------ entry points
+    def mbs_solve(self, R, p=None, v1s=None, v2s=None, v3t=None, Fe=None, Te=None, sigma0=None,
+                  V=None, W=None, S=None, Sigma=None, allow_noconv=False):
+        import torch
+        n = R.shape[0]
+        V = torch.empty((n, 3), dtype=torch.float64, device=R.device) if V is None else V
+        W = torch.empty((n, 3), dtype=torch.float64, device=R.device) if W is None else W
+        S = torch.empty((n, 5), dtype=torch.float64, device=R.device) if S is None else S
+        st = Stats()
+        rc = self.lib.mbs_solve(self.h, n, _ptr(R, n, 3, "R"), _ptr(p, n, 3, "p"), _ptr(v1s, n, 3, "v1s"),
+                                _ptr(v2s, n, 5, "v2s"), _ptr(v3t, n, 3, "v3t"), _ptr(Fe, n, 3, "Fe"),
+                                _ptr(Te, n, 3, "Te"), _ptr(sigma0, n, 5, "sigma0"), _ptr(V, n, 3, "V"),
+                                _ptr(W, n, 3, "W"), _ptr(S, n, 5, "S"), _ptr(Sigma, n, 5, "Sigma"),
+                                ctypes.byref(st), _stream())
+        self._check(rc, (MBS_ENOCONV,) if allow_noconv else ())
+        return V, W, S, st.as_dict()
+
+    def mbs_matvec(self, R, x, y=None, precision=MBS_FP64):
+        import torch
+        n = R.shape[0]
+        y = torch.empty((n, 5), dtype=torch.float64, device=R.device) if y is None else y
+        self._check(self.lib.mbs_matvec(self.h, n, _ptr(R, n, 3, "R"), _ptr(x, n, 5, "x"),
+                                        _ptr(y, n, 5, "y"), precision, _stream()))
+        return y
+
+    def mbs_rhs(self, R, v2s=None, v3t=None, Fe=None, Te=None, b=None):
+        import torch
+        n = R.shape[0]
+        b = torch.empty((n, 5), dtype=torch.float64, device=R.device) if b is None else b
+        self._check(self.lib.mbs_rhs(self.h, n, _ptr(R, n, 3, "R"), _ptr(v2s, n, 5, "v2s"),
+                                     _ptr(v3t, n, 3, "v3t"), _ptr(Fe, n, 3, "Fe"), _ptr(Te, n, 3, "Te"),
+                                     _ptr(b, n, 5, "b"), _stream()))
+        return b
+
+    def mbs_outputs(self, R, Sigma, v1s=None, v2s=None, v3t=None, Fe=None, Te=None, V=None, W=None, S=None):
+        import torch
+        n = R.shape[0]
+        V = torch.empty((n, 3), dtype=torch.float64, device=R.device) if V is None else V
+        W = torch.empty((n, 3), dtype=torch.float64, device=R.device) if W is None else W
+        S = torch.empty((n, 5), dtype=torch.float64, device=R.device) if S is None else S
+        self._check(self.lib.mbs_outputs(self.h, n, _ptr(R, n, 3, "R"), _ptr(v1s, n, 3, "v1s"),
+                                         _ptr(v2s, n, 5, "v2s"), _ptr(v3t, n, 3, "v3t"), _ptr(Fe, n, 3, "Fe"),
+                                         _ptr(Te, n, 3, "Te"), _ptr(Sigma, n, 5, "Sigma"), _ptr(V, n, 3, "V"),
+                                         _ptr(W, n, 3, "W"), _ptr(S, n, 5, "S"), _stream()))
+        return V, W, S
+
+    def mbs_step(self, R, p, k_trap, slip_coef, dt, nsteps, order=2, want_min_dist=False,
+                 allow_noconv=False):
+        n = R.shape[0]
+        coef = (ctypes.c_double * 3)(*slip_coef)
+        stats = (Stats * max(nsteps, 1))()
+        md = (ctypes.c_double * max(nsteps, 1))() if want_min_dist else None
+        rc = self.lib.mbs_step(self.h, n, _ptr(R, n, 3, "R"), _ptr(p, n, 3, "p"), float(k_trap), coef,
+                               float(dt), int(nsteps), int(order), stats, md, _stream())
+        self._check(rc, (MBS_ENOCONV,) if allow_noconv else ())
+        return [stats[k].as_dict() for k in range(nsteps)], (list(md)[:nsteps] if md is not None else None)
+
+    def mbs_solve_batched(self, offsets, R, v1s=None, v2s=None, v3t=None, Fe=None, Te=None,
+                          V=None, W=None, S=None, Sigma=None):
+        import torch
+        nconf = len(offsets) - 1
+        ntot = int(offsets[-1])
+        off = (ctypes.c_int64 * (nconf + 1))(*[int(o) for o in offsets])
+        V = torch.empty((ntot, 3), dtype=torch.float64, device=R.device) if V is None else V
+        W = torch.empty((ntot, 3), dtype=torch.float64, device=R.device) if W is None else W
+        S = torch.empty((ntot, 5), dtype=torch.float64, device=R.device) if S is None else S
+        stats = (Stats * nconf)()
+        lat = (ctypes.c_double * nconf)()
+        rc = self.lib.mbs_solve_batched(self.h, nconf, off, _ptr(R, ntot, 3, "R"), _ptr(v1s, ntot, 3, "v1s"),
+                                        _ptr(v2s, ntot, 5, "v2s"), _ptr(v3t, ntot, 3, "v3t"),
+                                        _ptr(Fe, ntot, 3, "Fe"), _ptr(Te, ntot, 3, "Te"), _ptr(V, ntot, 3, "V"),
+                                        _ptr(W, ntot, 3, "W"), _ptr(S, ntot, 5, "S"),
+                                        _ptr(Sigma, ntot, 5, "Sigma"), stats, lat, _stream())
+        self._check(rc)
+        return V, W, S, [stats[b].as_dict() for b in range(nconf)], list(lat)
+
+
+def to_device(w, device="cuda"):
+    """Copy a paper_1411_0278_amd.inputs.Workload's arrays to float64 device tensors."""
+    import torch
+    f = lambda a: torch.as_tensor(a, dtype=torch.float64).contiguous().to(device)
+    return dict(R=f(w.R), p=f(w.p), v1s=f(w.v1s), v2s=f(w.v2s), v3t=f(w.v3t), Fe=f(w.Fe), Te=f(w.Te))

@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI: the library loads and exports what the header declares."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1411_0278_amd import mbstokes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mbstokes.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mbs_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_bound_entry_points():
+    assert set(declared_functions()) == set(mbstokes.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(mbstokes.LIB_PATH):
+        pytest.skip("libmbstokes.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(mbstokes.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", mbstokes.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r"\bT (mbs_[a-z_0-9]+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_default_params_and_struct_layout():
+    if not os.path.exists(mbstokes.LIB_PATH):
+        pytest.skip("libmbstokes.so not built")
+    p = mbstokes.default_params()
+    assert p.lmax == 2 and p.restart == 30 and abs(p.tol - 1e-10) < 1e-25
+    assert abs(p.eta * 6 * 3.141592653589793 - 1) < 1e-15 and p.a == 1.0
+    assert ctypes.sizeof(mbstokes.Params) == 5 * 8 + 8 * 4
+    assert ctypes.sizeof(mbstokes.Stats) == 4 * 4 + 6 * 8
+
+
+def test_create_without_gpu_fails_cleanly():
+    """Without a visible device mbs_create returns an error code, never a context."""
+    if not os.path.exists(mbstokes.LIB_PATH):
+        pytest.skip("libmbstokes.so not built")
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    lib = mbstokes.load()
+    h = ctypes.c_void_p()
+    p = mbstokes.default_params()
+    rc = lib.mbs_create(ctypes.byref(h), 0, ctypes.byref(p))
+    assert rc != 0 and not h.value
+    assert len(lib.mbs_last_error(None)) > 0
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1411_0278_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", txt, flags=re.M), f
+                assert "oracle/" not in txt, f

@@ -1,0 +1,241 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on seeded synthetic inputs.
+
+Tolerances:
+* binary64 pair passes (matvec, right-hand side, outputs): the two sides sum the same O(N)
+  terms in different orders and with fused multiply-adds; the error is a few ulps of the sum
+  of |terms|, so 1e-13 relative (max-norm) is used.
+* binary64 solve: ||X_gpu - X_oracle||_F / ||X_oracle||_F <= 1e-10 per output X in
+  {V, Omega, S, Sigma} with the GMRES tolerance 1e-12 (condition number ~1.8).
+* binary32 pair blocks: unit roundoff 6e-8; each block is a product of ~10 rounded factors
+  and the receiver sum cancels partially, so 2e-5 normwise relative is used.
+* mixed-precision solve: 1e-9 per output (binary64 residual 1e-11).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import galerkin, krylov, stepper  # noqa: E402
+from paper_1411_0278_amd import inputs, mbstokes  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to(DEV)
+
+
+def _rel(got, want):
+    got = got.detach().cpu().numpy() if hasattr(got, "detach") else np.asarray(got)
+    return np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+
+
+def _maxrel(got, want):
+    got = got.detach().cpu().numpy() if hasattr(got, "detach") else np.asarray(got)
+    return np.abs(got - want).max() / max(np.abs(want).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mbstokes.Context(0)
+    yield c
+    c.close()
+
+
+def _workload(n, seed, v3t=1.0, torque=True):
+    side = max(8.0, (n / 0.004) ** (1 / 3))
+    w = inputs.trap_workload(n, side, seed, v3t=v3t)
+    if torque:
+        w.Te = np.random.default_rng(seed + 99).standard_normal((n, 3))
+    return w
+
+
+SIZES = [1, 2, 3, 63, 255, 256, 257, 700]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_matvec_f64_matches_oracle(ctx, n):
+    print(f"matvec_f64 n={n}", flush=True)
+    w = _workload(n, seed=100 + n)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    x = np.random.default_rng(n).standard_normal((n, 5))
+    A = galerkin.system_matrix(w.R, prm)
+    want = (A @ x.ravel()).reshape(n, 5)
+    got = ctx.mbs_matvec(_t(w.R), _t(x))
+    assert _maxrel(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("n", [2, 257, 700])
+def test_matvec_f32_matches_oracle(ctx, n):
+    print(f"matvec_f32 n={n}", flush=True)
+    w = _workload(n, seed=200 + n)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    x = np.random.default_rng(n).standard_normal((n, 5))
+    want = (galerkin.system_matrix(w.R, prm) @ x.ravel()).reshape(n, 5)
+    got = ctx.mbs_matvec(_t(w.R), _t(x), precision=mbstokes.MBS_FP32)
+    assert _rel(got, want) < 2e-5
+
+
+def test_matvec_is_bitwise_deterministic(ctx):
+    w = _workload(1500, seed=5)
+    x = _t(np.random.default_rng(1).standard_normal((w.n, 5)))
+    R = _t(w.R)
+    y1 = ctx.mbs_matvec(R, x).clone()
+    y2 = ctx.mbs_matvec(R, x).clone()
+    assert torch.equal(y1, y2)
+
+
+@pytest.mark.parametrize("n", [1, 2, 255, 257, 700])
+def test_rhs_matches_oracle(ctx, n):
+    print(f"rhs n={n}", flush=True)
+    w = _workload(n, seed=300 + n)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    want = galerkin.rhs(w.R, w.v2s, w.v3t, w.Fe, w.Te, prm).reshape(n, 5)
+    got = ctx.mbs_rhs(_t(w.R), _t(w.v2s), _t(w.v3t), _t(w.Fe), _t(w.Te))
+    assert _maxrel(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 2, 255, 257, 700])
+def test_outputs_match_oracle(ctx, n):
+    print(f"outputs n={n}", flush=True)
+    w = _workload(n, seed=400 + n)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    Sig = np.random.default_rng(n).standard_normal((n, 5))
+    V, W, S = galerkin.outputs(w.R, w.v1s, w.v2s, w.v3t, w.Fe, w.Te, Sig, prm)
+    gV, gW, gS = ctx.mbs_outputs(_t(w.R), _t(Sig), _t(w.v1s), _t(w.v2s), _t(w.v3t), _t(w.Fe), _t(w.Te))
+    assert _maxrel(gV, V) < 1e-13
+    assert _maxrel(gW, W) < 1e-13
+    assert _maxrel(gS, S) < 1e-14
+
+
+def test_null_optional_inputs_mean_zero(ctx):
+    w = _workload(40, seed=7, v3t=0.0, torque=False)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    want = galerkin.rhs(w.R, w.v2s, w.v3t, np.zeros_like(w.Fe), w.Te, prm).reshape(w.n, 5)
+    got = ctx.mbs_rhs(_t(w.R), _t(w.v2s), None, None, None)
+    assert _maxrel(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("guess", [mbstokes.MBS_GUESS_ZERO, mbstokes.MBS_GUESS_DIAG])
+def test_solve_config0_fp64(ctx, guess):
+    print(f"solve cfg0 fp64 guess={guess}", flush=True)
+    w = inputs.config0()
+    ref = galerkin.solve(w)
+    ctx.set_params(tol=1e-12, precision=mbstokes.MBS_FP64, guess=guess)
+    d = mbstokes.to_device(w, DEV)
+    Sig = torch.empty((w.n, 5), dtype=torch.float64, device=DEV)
+    V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"], Sigma=Sig)
+    for got, want in ((V, ref["V"]), (W, ref["W"]), (S, ref["S"]), (Sig, ref["Sigma"])):
+        assert _rel(got, want) < 1e-10
+    assert st["rel_resid"] <= 1e-12 and st["iters"] < 30
+    ctx.set_params(tol=1e-10, guess=mbstokes.MBS_GUESS_ZERO)
+
+
+def test_solve_mixed_precision(ctx):
+    w = _workload(300, seed=11)
+    ref = galerkin.solve(w)
+    ctx.set_params(tol=1e-11, precision=mbstokes.MBS_MIXED, inner_tol=1e-5)
+    d = mbstokes.to_device(w, DEV)
+    Sig = torch.empty((w.n, 5), dtype=torch.float64, device=DEV)
+    V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"], Sigma=Sig)
+    ctx.set_params(tol=1e-10, precision=mbstokes.MBS_FP64)
+    for got, want in ((V, ref["V"]), (W, ref["W"]), (S, ref["S"]), (Sig, ref["Sigma"])):
+        assert _rel(got, want) < 1e-9
+    assert st["rel_resid"] <= 1e-11 and st["refinements"] >= 1 and st["fp32_matvecs"] > 0
+
+
+def test_solve_user_guess_and_restarts(ctx):
+    w = _workload(200, seed=12)
+    ref = galerkin.solve(w)
+    ctx.set_params(tol=1e-12, restart=5, guess=mbstokes.MBS_GUESS_USER)
+    d = mbstokes.to_device(w, DEV)
+    s0 = _t(ref["Sigma"] * (1 + 1e-3 * np.random.default_rng(0).standard_normal(ref["Sigma"].shape)))
+    V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"], sigma0=s0)
+    ctx.set_params(tol=1e-10, restart=30, guess=mbstokes.MBS_GUESS_ZERO)
+    assert _rel(V, ref["V"]) < 1e-10 and _rel(S, ref["S"]) < 1e-10
+
+
+def test_lone_sphere(ctx):
+    w = inputs.Workload(np.zeros((1, 3)), np.array([[0, 0, 1.0]]), np.array([[0.3, -0.2, 1.0]]),
+                        np.array([[0.1, 0.2, 0.3, 0.4, 0.5]]), np.zeros((1, 3)), np.array([[1.0, 2, 3]]),
+                        np.array([[0.5, 0, 0]]))
+    ref = galerkin.solve(w)
+    d = mbstokes.to_device(w, DEV)
+    V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
+    assert _maxrel(V, ref["V"]) < 1e-15 and _maxrel(W, ref["W"]) < 1e-15 and _maxrel(S, ref["S"]) < 1e-15
+
+
+# ---------------------------------------------------------------- error contract
+def test_errors(ctx):
+    w = _workload(20, seed=13)
+    d = mbstokes.to_device(w, DEV)
+    with pytest.raises(mbstokes.MbsError) as e:
+        bad = d["R"].clone()
+        bad[3, 1] = float("nan")
+        ctx.mbs_solve(bad, d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+    assert e.value.code == mbstokes.MBS_EINVAL
+    ctx.set_params(check_overlap=1)
+    with pytest.raises(mbstokes.MbsError) as e:
+        R = d["R"].clone()
+        R[1] = R[0] + torch.tensor([1.0, 0.5, 0.0], dtype=torch.float64, device=DEV)
+        ctx.mbs_solve(R, d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+    assert e.value.code == mbstokes.MBS_EOVERLAP
+    ctx.set_params(check_overlap=0, max_iter=1, tol=1e-14)
+    V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None, allow_noconv=True)
+    assert st["iters"] == 1 and st["rel_resid"] > 1e-14
+    with pytest.raises(mbstokes.MbsError) as e:
+        ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+    assert e.value.code == mbstokes.MBS_ENOCONV
+    ctx.set_params(max_iter=300, tol=1e-10)
+    with pytest.raises(mbstokes.MbsError) as e:
+        ctx.set_params(lmax=3)
+    assert e.value.code == mbstokes.MBS_EUNSUPPORTED
+    ctx.params.lmax = 2
+    lib = mbstokes.load()
+    rc = lib.mbs_matvec(ctx.h, 0, None, None, None, 0, None)
+    assert rc == mbstokes.MBS_EINVAL
+
+
+# ---------------------------------------------------------------- time stepping
+def test_stepper_matches_oracle(ctx):
+    w = _workload(64, seed=14, torque=False)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    Rw, pw, _ = stepper.run(w.R, w.p, 0.5, (1.0, 1.0, 1.0), 0.01, 3, prm)
+    R, p = _t(w.R), _t(w.p)
+    ctx.set_params(tol=1e-13)
+    stats, md = ctx.mbs_step(R, p, 0.5, (1.0, 1.0, 1.0), 0.01, 3, order=2, want_min_dist=True)
+    ctx.set_params(tol=1e-10)
+    assert _maxrel(R, Rw) < 1e-12 and _maxrel(p, pw) < 1e-12
+    dmin = min(np.linalg.norm(w.R[i] - w.R[j]) for i in range(w.n) for j in range(i))
+    assert abs(md[0] - dmin) < 1e-12
+
+
+# ---------------------------------------------------------------- batched
+def test_batched_matches_individual_oracle_solves(ctx):
+    ws = [_workload(n, seed=500 + n, v3t=0.0, torque=False) for n in (64, 90, 130, 33)]
+    off = np.cumsum([0] + [w.n for w in ws])
+    cat = lambda f: _t(np.concatenate([getattr(w, f) for w in ws]))
+    ctx.set_params(tol=1e-12)
+    V, W, S, stats, lat = ctx.mbs_solve_batched(off, cat("R"), cat("v1s"), cat("v2s"), None, cat("Fe"), None)
+    ctx.set_params(tol=1e-10)
+    for b, w in enumerate(ws):
+        ref = galerkin.solve(w)
+        sl = slice(off[b], off[b + 1])
+        assert _rel(V[sl], ref["V"]) < 1e-10 and _rel(W[sl], ref["W"]) < 1e-10 and _rel(S[sl], ref["S"]) < 1e-10
+    assert all(l > 0 for l in lat) and lat == sorted(lat)
+
+
+# ---------------------------------------------------------------- full size, sampled
+@pytest.mark.slow
+def test_matvec_full_size_sampled_rows(ctx):
+    w = inputs.config2()
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    x = np.random.default_rng(3).standard_normal((w.n, 5))
+    print(f"matvec n={w.n} fp64+fp32, 24 sampled rows vs oracle", flush=True)
+    y = ctx.mbs_matvec(_t(w.R), _t(x)).cpu().numpy()
+    y32 = ctx.mbs_matvec(_t(w.R), _t(x), precision=mbstokes.MBS_FP32).cpu().numpy()
+    rows = np.random.default_rng(4).choice(w.n, 24, replace=False)
+    want = galerkin.matvec_rows(w.R, x, rows, prm)
+    assert _maxrel(y[rows], want) < 1e-12
+    assert _rel(y32[rows], want) < 5e-5
