@@ -1,0 +1,180 @@
+#!/usr/bin/env python
+"""Benchmark of the many-body active-sphere solve on one MI355X.
+
+One step = one full solve of the trap workload to a binary64 relative residual of 1e-10:
+right-hand side pass, initial guess, GMRES (or mixed-precision refinement), output pass.
+Default workload: N = 100000 spheres, cube of side 430, seed 1000 (number density 1.26e-3),
+mean and strain slip along random orientations, trap force -0.5 R.
+
+Prints ONE JSON line. `value` is the pair-block evaluation rate of the headline solve
+(all passes, inputs resident in device memory); `ms_per_step` is its time to solution.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair-blocks/s; time to 1e-10 residual at N=1e5, plain FP64 vs mixed+warm start"
+FP64_PEAK_TF = 78.6     # MI355X vector FP64
+FP32_PEAK_TF = 157.3    # MI355X vector FP32 (published figure, counts packed FP32)
+# algorithmic FLOP per pair block of the system operator as implemented (FMA = 2, rsqrt = 1):
+# differences 3, r^2 5, 1/r 1, powers 4, Szz 1, w 15, q 5, c1 3, c2 4, v 9, sym(x v) 21, c3 terms 10
+P2_FLOP_PER_PAIR = 81
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--side", type=float, default=430.0)
+    ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--headline", default="mixed_diag", choices=["plain_fp64", "mixed_diag", "fp64_diag"])
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    p = os.path.join(ROOT, "paper_1411_0278_amd", "csrc", "mbs_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, n):
+    """HBM bytes per launch from committed PMC summaries, if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(f"{kernel}@n{n}")
+    except Exception:
+        return None
+    if not rec or rec.get("source_sha") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_variant(ctx, d, mb, name, precision, guess, steps, warmup):
+    import torch
+    ctx.set_params(precision=precision, guess=guess, tol=1e-10)
+    args = (d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
+    for k in range(warmup):
+        ctx.mbs_solve(*args)
+        print(f"bench: {name} warmup {k + 1}/{warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(steps):
+        _, _, _, st = ctx.mbs_solve(*args)
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"bench: {name} {steps} solves in {dt:.3f} s", file=sys.stderr, flush=True)
+    pairs = sum(s["pair_blocks"] for s in stats)
+    return dict(name=name, seconds=dt, ms_per_step=1e3 * dt / steps, pair_blocks_per_s=pairs / dt,
+                iters=stats[-1]["iters"], refinements=stats[-1]["refinements"],
+                fp64_matvecs=stats[-1]["fp64_matvecs"], fp32_matvecs=stats[-1]["fp32_matvecs"],
+                rel_resid=max(s["rel_resid"] for s in stats),
+                t_op64_ms=sum(s["t_op64_ms"] for s in stats), t_op32_ms=sum(s["t_op32_ms"] for s in stats),
+                n_op64=sum(s["fp64_matvecs"] for s in stats), n_op32=sum(s["fp32_matvecs"] for s in stats),
+                t_rhs_ms=stats[-1]["t_rhs_ms"], t_out_ms=stats[-1]["t_out_ms"],
+                t_iter_ms=stats[-1]["t_iter_ms"])
+
+
+def roofline(v, n):
+    """Dominant kernel of the step: the operator application with the larger summed time."""
+    use32 = v["t_op32_ms"] > v["t_op64_ms"]
+    t_ms, cnt = (v["t_op32_ms"], v["n_op32"]) if use32 else (v["t_op64_ms"], v["n_op64"])
+    if cnt == 0 or t_ms <= 0:
+        return None
+    per_launch_s = t_ms / cnt / 1e3
+    flop = P2_FLOP_PER_PAIR * n * (n - 1)
+    achieved = flop / per_launch_s / 1e12
+    peak = FP32_PEAK_TF if use32 else FP64_PEAK_TF
+    kernel = "k_p2_f32" if use32 else "k_p2_f64"
+    return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic(kernel, n), "avg_launch_ms": round(per_launch_s * 1e3, 4),
+            "flop_per_pair": P2_FLOP_PER_PAIR}
+
+
+def cpu_baseline(w, seconds):
+    """The oracle's system-operator rows on host cores: pair-blocks/s on a bounded row sample."""
+    import numpy as np
+
+    from oracle import galerkin
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    x = np.random.default_rng(0).standard_normal((w.n, 5))
+    galerkin.matvec_rows(w.R, x, np.array([0]), prm)  # builds the symbolic blocks (untimed)
+    rows_done = 0
+    rng = np.random.default_rng(1)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        rows = rng.choice(w.n, 4, replace=False)
+        galerkin.matvec_rows(w.R, x, rows, prm)
+        rows_done += len(rows)
+    dt = time.perf_counter() - t0
+    return {"value": rows_done * (w.n - 1) / dt, "unit": "pair-blocks/s", "cores": 1, "kind": "oracle",
+            "sample": f"{rows_done} rows of the system operator against all {w.n} sources "
+                      f"({rows_done * (w.n - 1):.3g} pair blocks, {dt:.1f} s, numpy single thread)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part "
+                                   "of this build (the row-sharded design is described in DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+    print(f"bench: generating workload n={a.n} side={a.side} seed={a.seed}", file=sys.stderr, flush=True)
+    w = inputs.trap_workload(a.n, a.side, a.seed)
+    d = mbstokes.to_device(w, "cuda:0")
+    ctx = mbstokes.Context(0)
+    variants = {}
+    plan = [("plain_fp64", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_ZERO),
+            ("fp64_diag", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_DIAG),
+            ("mixed_diag", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG)]
+    for name, prec, guess in plan:
+        steps = a.steps if name in (a.headline, "plain_fp64") else max(1, min(a.steps, 2))
+        variants[name] = time_variant(ctx, d, mbstokes, name, prec, guess, steps, a.warmup)
+    head = variants[a.headline]
+    out = {
+        "metric": METRIC,
+        "value": head["pair_blocks_per_s"],
+        "unit": "pair-blocks/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head["n_op32"] else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"trap spheres N={a.n} cube side {a.side:g} seed {a.seed}, "
+                               f"slip V1s=p V2s=3(pp-I/3), F=-0.5R, solve to 1e-10",
+                   "n": a.n, "headline": a.headline, "tol": 1e-10},
+        "roofline": roofline(head, a.n),
+        "time_to_1e-10_ms": {k: round(v["ms_per_step"], 3) for k, v in variants.items()},
+        "variants": variants,
+    }
+    if not a.skip_cpu:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -94,6 +94,8 @@ typedef struct mbs_stats {
   double  t_iter_ms;      /* guess + iterations + refinement residuals */
   double  t_out_ms;       /* rigid-body output pass */
   double  pair_blocks;    /* pair-block evaluations performed (all passes) */
+  double  t_op64_ms;      /* summed device time of the binary64 operator applications */
+  double  t_op32_ms;      /* summed device time of the binary32 operator applications */
 } mbs_stats;
 
 typedef struct mbs_ctx mbs_ctx;

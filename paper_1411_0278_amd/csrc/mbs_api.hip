@@ -40,6 +40,12 @@ struct mbs_ctx {
   int* d_count = nullptr;
   double* h_status = nullptr;  // pinned host [4]
   hipEvent_t ev[8] = {};
+  // event pairs bracketing operator applications inside a solve (harvested after each sync)
+  static constexpr int kRing = 4;
+  hipEvent_t opev[2 * kRing] = {};
+  int op_prec[kRing] = {};
+  int npend = 0;
+  double t_op[2] = {0.0, 0.0};  // summed binary64 / binary32 operator time of the current call
 };
 
 namespace {
@@ -152,9 +158,20 @@ Small small_of(mbs_ctx* c) {
   return o;
 }
 
+// Accumulate the elapsed times of completed operator applications (call after a sync).
+void harvest_ops(mbs_ctx* c) {
+  for (int k = 0; k < c->npend; ++k) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, c->opev[2 * k], c->opev[2 * k + 1]) == hipSuccess)
+      c->t_op[c->op_prec[k] == MBS_FP64 ? 0 : 1] += t;
+  }
+  c->npend = 0;
+}
+
 int read_status(mbs_ctx* c, const double* dev, int count, hipStream_t s) {
   HIPCHK(c, hipMemcpyAsync(c->h_status, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  harvest_ops(c);
   return MBS_OK;
 }
 
@@ -165,6 +182,13 @@ struct Counters {
 
 void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x, double* y,
               hipStream_t s, Counters& cnt) {
+  if (c->npend == mbs_ctx::kRing) {
+    (void)hipStreamSynchronize(s);
+    harvest_ops(c);
+  }
+  const int slot = c->npend++;
+  c->op_prec[slot] = prec;
+  (void)hipEventRecord(c->opev[2 * slot], s);
   if (prec == MBS_FP64) {
     launch_p2_f64(R, x, y, c->part.p, n, c->ph, c->tile64, s);
     cnt.f64++;
@@ -172,6 +196,7 @@ void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x,
     launch_p2_f32(R, x, y, c->part.p, n, c->ph, c->tile32, s);
     cnt.f32++;
   }
+  (void)hipEventRecord(c->opev[2 * slot + 1], s);
   cnt.pairs += (double)n * (double)(n - 1);
 }
 
@@ -287,6 +312,8 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const 
   const double* Fz = Fe ? Fe : c->zeros.p;
   Counters cnt;
   Small sm = small_of(c);
+  c->npend = 0;
+  c->t_op[0] = c->t_op[1] = 0.0;
   HIPCHK(c, hipEventRecord(c->ev[0], s));
   // right-hand side
   launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile64, s);
@@ -360,7 +387,10 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const 
   if (Sigma) launch_copy(c->xs.p, Sigma, len, s);
   HIPCHK(c, hipEventRecord(c->ev[3], s));
   HIPCHK(c, hipStreamSynchronize(s));
+  harvest_ops(c);
   if (st) {
+    st->t_op64_ms = c->t_op[0];
+    st->t_op32_ms = c->t_op[1];
     st->iters = cnt.iters;
     st->refinements = cnt.refinements;
     st->fp64_matvecs = cnt.f64;
@@ -429,6 +459,7 @@ int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {
   e = hipHostMalloc((void**)&c->h_status, 8 * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc((void**)&c->d_count, sizeof(int));
   for (int k = 0; k < 8 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
+  for (int k = 0; k < 2 * mbs_ctx::kRing && e == hipSuccess; ++k) e = hipEventCreate(&c->opev[k]);
   if (e != hipSuccess) {
     set_err(nullptr, MBS_EHIP, "context allocation: %s", hipGetErrorString(e));
     mbs_destroy(c);
@@ -448,6 +479,8 @@ void mbs_destroy(mbs_ctx* c) {
   if (c->d_count) (void)hipFree(c->d_count);
   if (c->h_status) (void)hipHostFree(c->h_status);
   for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->opev)
     if (e) (void)hipEventDestroy(e);
   delete c;
 }
@@ -510,9 +543,11 @@ int mbs_matvec(mbs_ctx* c, int64_t n, const double* R, const double* x, double* 
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
   Counters cnt;
+  c->npend = 0;
   apply_op(c, precision, n, R, x, y, s, cnt);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
+  c->npend = 0;
   return MBS_OK;
 }
 

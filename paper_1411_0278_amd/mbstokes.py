@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
                 ("fp64_matvecs", ctypes.c_int32), ("fp32_matvecs", ctypes.c_int32),
                 ("rel_resid", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("t_rhs_ms", ctypes.c_double), ("t_iter_ms", ctypes.c_double),
-                ("t_out_ms", ctypes.c_double), ("pair_blocks", ctypes.c_double)]
+                ("t_out_ms", ctypes.c_double), ("pair_blocks", ctypes.c_double),
+                ("t_op64_ms", ctypes.c_double), ("t_op32_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
