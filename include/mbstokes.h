@@ -79,7 +79,8 @@ typedef struct mbs_params {
   int32_t precision;     /* MBS_FP64 or MBS_MIXED */
   int32_t guess;         /* MBS_GUESS_* */
   int32_t check_overlap; /* nonzero: mbs_solve fails with MBS_EOVERLAP if some |R_n - R_m| < 2a */
-  int32_t tile;          /* pair-kernel launch shape: 0 = tuned default, else an index from mbs_autotune */
+  int32_t tile;          /* pair-kernel launch shape: 0 = autotuned (or default), k > 0 = entry k-1
+                            of the candidate table (see mbs_autotune) */
   int32_t reserved;
 } mbs_params;
 
@@ -169,10 +170,15 @@ int mbs_solve_batched(mbs_ctx* ctx, int32_t nconf, const int64_t* offsets, const
                       const double* Te, double* V, double* W, double* S, double* Sigma,
                       mbs_stats* per_conf, double* latency_ms, void* stream);
 
-/* Time the pair-kernel launch shapes for n spheres at positions R and keep the fastest
-   (for both precisions) in the context; a JSON cache file (may be NULL) is read first and
-   updated afterwards. */
-int mbs_autotune(mbs_ctx* ctx, int64_t n, const double* R, const char* cache_json, void* stream);
+/* Autotuner: time every pair-kernel launch shape of the library's candidate table (LDS-tiled
+   and scalar-streamed sources, workgroup sizes, source splits) for n spheres at positions R, in
+   both precisions, and use the fastest in this context (unless params.tile forces a shape).
+   cache_json (may be NULL): a flat JSON object; if it holds an entry for this device and size
+   class (n rounded down to a power of two) nothing is timed, otherwise the choice and its time
+   are written back. chosen: host int32[2] or NULL, receives the table indices (binary64,
+   binary32); params.tile = index + 1 forces that shape. */
+int mbs_autotune(mbs_ctx* ctx, int64_t n, const double* R, const char* cache_json, int32_t* chosen,
+                 void* stream);
 
 #ifdef __cplusplus
 }

@@ -32,11 +32,13 @@ struct mbs_ctx {
   int device = 0;
   mbs_params prm{};
   Phys ph{};
-  Tile tile64{256, 128, 0};
-  Tile tile32{256, 128, 0};
+  Tile tile64 = kTileTable[0];  // pair-kernel shapes in use (autotuned or forced by params.tile)
+  Tile tile32 = kTileTable[0];
+  int tuned64 = 0, tuned32 = 0;  // autotuner choices (indices into kTileTable)
+  Tile tile_pass = Tile{0, 256, 128, 4096};  // shape of the right-hand-side and output passes
   std::string err;
   // workspace
-  DevBuf V, w, r, b, xs, dlt, part, dpart, small, H, zeros, stepbuf;
+  DevBuf V, w, r, b, xs, dlt, part, dpart, small, H, zeros, stepbuf, srcbuf, orig;
   int* d_count = nullptr;
   double* h_status = nullptr;  // pinned host [4]
   hipEvent_t ev[8] = {};
@@ -111,7 +113,18 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
     return set_err(c, MBS_EINVAL, "unknown guess %d", p->guess);
   if (p->guess == MBS_GUESS_LEARNED)
     return set_err(c, MBS_EUNSUPPORTED, "learned warm start is not loaded in this context");
+  if (p->tile < 0 || p->tile > kTileCount)
+    return set_err(c, MBS_EINVAL, "tile must be in 0..%d", kTileCount);
   return MBS_OK;
+}
+
+void apply_tiles(mbs_ctx* c) {
+  if (c->prm.tile > 0) {
+    c->tile64 = c->tile32 = kTileTable[c->prm.tile - 1];
+  } else {
+    c->tile64 = kTileTable[c->tuned64];
+    c->tile32 = kTileTable[c->tuned32];
+  }
 }
 
 // Workspace for n spheres and restart m.
@@ -124,10 +137,10 @@ int ensure_ws(mbs_ctx* c, int64_t n) {
   CHK(ensure(c, c->b, len));
   CHK(ensure(c, c->xs, len));
   CHK(ensure(c, c->dlt, len));
-  int64_t pe = std::max({part_elems(n, c->tile64, 5), part_elems(n, c->tile32, 5),
-                         part_elems(n, Tile{c->tile64.block, 128, c->tile64.split}, 6),
-                         (int64_t)6 * n});
+  const int64_t pe = part_elems_max(n);
   CHK(ensure(c, c->part, (size_t)pe));
+  CHK(ensure(c, c->srcbuf, (size_t)8 * n));
+  CHK(ensure(c, c->orig, 4));
   CHK(ensure(c, c->dpart, (size_t)std::max<int64_t>((int64_t)(m + 2) * 256, 1024 + (n + 255) / 256) + 64));
   CHK(ensure(c, c->small, (size_t)8 * (m + 2) + 64));
   CHK(ensure(c, c->H, (size_t)(m + 1) * (m + 1)));
@@ -190,10 +203,10 @@ void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x,
   c->op_prec[slot] = prec;
   (void)hipEventRecord(c->opev[2 * slot], s);
   if (prec == MBS_FP64) {
-    launch_p2_f64(R, x, y, c->part.p, n, c->ph, c->tile64, s);
+    launch_p2(false, R, x, y, c->part.p, c->srcbuf.p, c->orig.p, n, c->ph, c->tile64, s);
     cnt.f64++;
   } else {
-    launch_p2_f32(R, x, y, c->part.p, n, c->ph, c->tile32, s);
+    launch_p2(true, R, x, y, c->part.p, c->srcbuf.p, c->orig.p, n, c->ph, c->tile32, s);
     cnt.f32++;
   }
   (void)hipEventRecord(c->opev[2 * slot + 1], s);
@@ -316,7 +329,7 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const 
   c->t_op[0] = c->t_op[1] = 0.0;
   HIPCHK(c, hipEventRecord(c->ev[0], s));
   // right-hand side
-  launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile64, s);
+  launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
   cnt.pairs += (double)n * (double)(n - 1);
   HIPCHK(c, hipEventRecord(c->ev[1], s));
   norm2(c, c->b.p, len, sm.bnorm2, s);
@@ -382,7 +395,7 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const 
   }
   if (bnorm != 0.0 && !(rel <= c->prm.tol)) rc = MBS_ENOCONV;
   HIPCHK(c, hipEventRecord(c->ev[2], s));
-  launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile64, s);
+  launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
   cnt.pairs += (double)n * (double)(n - 1);
   if (Sigma) launch_copy(c->xs.p, Sigma, len, s);
   HIPCHK(c, hipEventRecord(c->ev[3], s));
@@ -456,6 +469,7 @@ int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {
   c->device = device;
   c->prm = *prm;
   c->ph = make_phys(prm->eta, prm->a, prm->self_slip_c);
+  apply_tiles(c);
   e = hipHostMalloc((void**)&c->h_status, 8 * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc((void**)&c->d_count, sizeof(int));
   for (int k = 0; k < 8 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
@@ -473,7 +487,7 @@ void mbs_destroy(mbs_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   DevBuf* bufs[] = {&c->V, &c->w, &c->r, &c->b, &c->xs, &c->dlt, &c->part, &c->dpart,
-                    &c->small, &c->H, &c->zeros, &c->stepbuf};
+                    &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->d_count) (void)hipFree(c->d_count);
@@ -491,6 +505,7 @@ int mbs_set_params(mbs_ctx* c, const mbs_params* prm) {
   const bool restart_changed = prm->restart != c->prm.restart;
   c->prm = *prm;
   c->ph = make_phys(prm->eta, prm->a, prm->self_slip_c);
+  apply_tiles(c);
   if (restart_changed) {  // buffers sized by restart are re-grown on demand
     DevBuf* bufs[] = {&c->V, &c->dpart, &c->small, &c->H};
     for (DevBuf* b : bufs) {
@@ -559,7 +574,7 @@ int mbs_rhs(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const dou
   if (!R || !b) return set_err(c, MBS_EINVAL, "R and b are required");
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
-  launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, c->ph, c->tile64, s);
+  launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, c->ph, c->tile_pass, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;
@@ -575,7 +590,7 @@ int mbs_outputs(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
   launch_p3(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, c->ph,
-            c->tile64, s);
+            c->tile_pass, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;
@@ -680,13 +695,107 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   return rc;
 }
 
-int mbs_autotune(mbs_ctx* c, int64_t n, const double* R, const char* cache_json, void* stream) {
+int mbs_autotune(mbs_ctx* c, int64_t n, const double* R, const char* cache_json, int32_t* chosen,
+                 void* stream) {
   CHK(begin_call(c));
-  (void)n;
-  (void)R;
-  (void)cache_json;
-  (void)stream;
-  return set_err(c, MBS_EUNSUPPORTED, "autotuner not built yet");
+  if (n < 2 || !R) return set_err(c, MBS_EINVAL, "autotune needs n >= 2 and R");
+  if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, n));
+  int bucket = 0;
+  while ((int64_t(1) << (bucket + 1)) <= n) ++bucket;
+  char key64[64], key32[64];
+  snprintf(key64, sizeof key64, "gfx950:f64:n2^%d", bucket);
+  snprintf(key32, sizeof key32, "gfx950:f32:n2^%d", bucket);
+  // cache: a flat JSON object of "key": value pairs
+  std::vector<std::pair<std::string, double>> kv;
+  if (cache_json) {
+    FILE* f = fopen(cache_json, "r");
+    if (f) {
+      std::string txt;
+      char buf[4096];
+      size_t got;
+      while ((got = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, got);
+      fclose(f);
+      size_t pos = 0;
+      while ((pos = txt.find('"', pos)) != std::string::npos) {
+        const size_t e = txt.find('"', pos + 1);
+        if (e == std::string::npos) break;
+        const std::string k = txt.substr(pos + 1, e - pos - 1);
+        const size_t colon = txt.find(':', e);
+        if (colon == std::string::npos) break;
+        kv.emplace_back(k, strtod(txt.c_str() + colon + 1, nullptr));
+        pos = txt.find_first_of(",}", colon);
+        if (pos == std::string::npos) break;
+      }
+    }
+  }
+  auto lookup = [&](const char* k, int* out) {
+    for (auto& p : kv)
+      if (p.first == k && p.second >= 0 && p.second < kTileCount) {
+        *out = (int)p.second;
+        return true;
+      }
+    return false;
+  };
+  int best[2] = {0, 0};
+  double best_ms[2] = {0.0, 0.0};
+  const bool cached = lookup(key64, &best[0]) && lookup(key32, &best[1]);
+  if (!cached) {
+    const int64_t len = 5 * n;
+    HIPCHK(c, hipMemsetAsync(c->xs.p, 0, len * sizeof(double), s));
+    for (int prec = 0; prec < 2; ++prec) {
+      double bt = 1e300;
+      for (int k = 0; k < kTileCount; ++k) {
+        const Tile t = kTileTable[k];
+        // one warm-up launch, then the mean of three timed launches
+        launch_p2(prec == 1, R, c->xs.p, c->w.p, c->part.p, c->srcbuf.p, c->orig.p, n, c->ph, t, s);
+        HIPCHK(c, hipEventRecord(c->ev[6], s));
+        for (int r = 0; r < 3; ++r)
+          launch_p2(prec == 1, R, c->xs.p, c->w.p, c->part.p, c->srcbuf.p, c->orig.p, n, c->ph, t, s);
+        HIPCHK(c, hipEventRecord(c->ev[7], s));
+        HIPCHK(c, hipEventSynchronize(c->ev[7]));
+        HIPCHK(c, hipGetLastError());
+        const double ms = ev_ms(c->ev[6], c->ev[7]) / 3.0;
+        if (ms < bt) {
+          bt = ms;
+          best[prec] = k;
+        }
+      }
+      best_ms[prec] = bt;
+    }
+    if (cache_json) {
+      bool f64 = false, f32 = false;
+      for (auto& p : kv) {
+        if (p.first == key64) p.second = best[0], f64 = true;
+        if (p.first == key32) p.second = best[1], f32 = true;
+      }
+      if (!f64) kv.emplace_back(key64, best[0]);
+      if (!f32) kv.emplace_back(key32, best[1]);
+      char mk[96];
+      snprintf(mk, sizeof mk, "%s:ms", key64);
+      kv.emplace_back(mk, best_ms[0]);
+      snprintf(mk, sizeof mk, "%s:ms", key32);
+      kv.emplace_back(mk, best_ms[1]);
+      FILE* f = fopen(cache_json, "w");
+      if (f) {
+        fprintf(f, "{\n");
+        for (size_t k = 0; k < kv.size(); ++k)
+          fprintf(f, "  \"%s\": %.17g%s\n", kv[k].first.c_str(), kv[k].second,
+                  k + 1 < kv.size() ? "," : "");
+        fprintf(f, "}\n");
+        fclose(f);
+      }
+    }
+  }
+  c->tuned64 = best[0];
+  c->tuned32 = best[1];
+  apply_tiles(c);
+  if (chosen) {
+    chosen[0] = best[0];
+    chosen[1] = best[1];
+  }
+  return MBS_OK;
 }
 
 }  // extern "C"

@@ -23,17 +23,20 @@ Phys make_phys(double eta, double a, double c);
 
 // Pair-kernel launch shape.
 struct Tile {
-  int block;   // threads per workgroup (targets per workgroup)
-  int tj;      // sources per LDS tile
-  int split;   // source chunks along grid.y (partial sums reduced afterwards); 0 = automatic
+  int variant;  // 0: sources staged through LDS tiles; 1: sources streamed by scalar (SGPR) loads
+  int block;    // threads per workgroup = receivers per workgroup (64, 128 or 256)
+  int tj;       // sources per LDS tile (variant 0; 64, 128 or 256)
+  int wgs;      // target workgroup count used to split the sources along grid.y (0 = 2048)
 };
+// Candidate shapes timed by the autotuner; entry 0 is the default.
+extern const Tile kTileTable[];
+extern const int kTileCount;
 
 // ---------------------------------------------------------------- pair passes
-// y = x/gamma - E[x] (system operator). part: scratch [split x 5n] doubles (used when split > 1).
-void launch_p2_f64(const double* R, const double* x, double* y, double* part, int64_t n,
-                   const Phys& ph, Tile t, hipStream_t s);
-void launch_p2_f32(const double* R, const double* x, double* y, double* part, int64_t n,
-                   const Phys& ph, Tile t, hipStream_t s);
+// y = x/gamma - E[x] (system operator). part: scratch [split x 5n] doubles (used when split > 1);
+// src: scratch of 8n doubles (packed source records, variant 1); orig: 4 doubles of scratch.
+void launch_p2(bool f32, const double* R, const double* x, double* y, double* part, double* src,
+               double* orig, int64_t n, const Phys& ph, Tile t, hipStream_t s);
 // b = E[F, T, d] - c s
 void launch_p1(const double* R, const double* v2s, const double* v3t, const double* Fe,
                const double* Te, double* b, double* part, int64_t n, const Phys& ph, Tile t,
@@ -47,8 +50,9 @@ void launch_min_dist2(const double* R, int64_t n, double* out, double* scratch, 
 // count non-finite entries of a device array -> atomically added to *cnt (device int)
 void launch_count_nonfinite(const double* a, int64_t len, int* cnt, hipStream_t s);
 
-int split_for(int64_t n, Tile t);      // number of source chunks actually used
-int64_t part_elems(int64_t n, Tile t, int width);  // scratch size (doubles) for a pass
+int tile_block(Tile t);                      // receivers per workgroup actually used
+int split_for(int64_t n, Tile t, int tj);    // number of source chunks actually used
+int64_t part_elems_max(int64_t n);           // scratch size (doubles) covering every pass and shape
 
 // ---------------------------------------------------------------- Krylov helpers (all deterministic)
 // out[k] = <V_k, w> for k < nv, V_k = V + k*ld; scratch: part [nv x dot_blocks(len)]

@@ -34,250 +34,12 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "mbs_device.h"
 #include "mbs_internal.h"
 
 namespace mbs {
 
 namespace {
-constexpr double RS2 = 0.70710678118654752440;  // 1/sqrt(2)
-constexpr double RS6 = 0.40824829046386301637;  // 1/sqrt(6)
-constexpr int kMaxBlock = 256;
-
-// 1/sqrt(r2) for r2 > 0, and 0 for r2 == 0 (the n == m term), without a branch.
-// binary64: hardware reciprocal square root estimate followed by one Newton-Raphson step
-// y <- y + (y/2)(1 - r2 y^2), which squares the relative error of the estimate.
-__device__ __forceinline__ double rinv_or_zero(double r2) {
-  const double y0 = __builtin_amdgcn_rsq(r2);
-  const double e = fma(-r2 * y0, y0, 1.0);
-  const double y1 = fma(0.5 * y0, e, y0);
-  return r2 > 0.0 ? y1 : 0.0;
-}
-// binary32: the hardware estimate is accurate to about 1 ulp.
-__device__ __forceinline__ float rinv_or_zero(float r2) {
-  const float y0 = __builtin_amdgcn_rsqf(r2);
-  return r2 > 0.0f ? y0 : 0.0f;
-}
-
-// Accumulate sym(x (x) v) in the scaled 5-basis.
-template <typename T>
-__device__ __forceinline__ void acc_sym(T dx, T dy, T dz, T vx, T vy, T vz, T& a0, T& a1, T& a2,
-                                        T& a3, T& a4) {
-  const T pxx = dx * vx, pyy = dy * vy, pzz = dz * vz;
-  a0 += pxx - pyy;
-  a1 += (T)2 * pzz - pxx - pyy;
-  a2 += dx * vy + dy * vx;
-  a3 += dx * vz + dz * vx;
-  a4 += dy * vz + dz * vy;
-}
-
-// ------------------------------------------------------------------ P2: system operator
-struct alignas(16) RecS64 {
-  double x, y, z, sxx, syy, sxy, sxz, syz;
-};
-struct alignas(16) RecS32 {
-  float x, y, z, sxx, syy, sxy, sxz, syz;
-};
-
-// Cartesian components of Sigma from its 5-basis coefficients.
-__device__ __forceinline__ void basis_to_cart(const double* s, double& sxx, double& syy,
-                                              double& sxy, double& sxz, double& syz) {
-  const double u0 = s[0] * RS2, u1 = s[1] * RS6;
-  sxx = u0 - u1;
-  syy = -u0 - u1;
-  sxy = s[2] * RS2;
-  sxz = s[3] * RS2;
-  syz = s[4] * RS2;
-}
-
-template <int TJ>
-__global__ void __launch_bounds__(kMaxBlock)
-    k_p2_f64(const double* __restrict__ R, const double* __restrict__ X, double* __restrict__ out,
-             int n, int chunk, double P, double a2, double inv_gamma, int direct) {
-  __shared__ RecS64 tile[TJ];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ii = i < n ? i : n - 1;
-  const double xi = R[3 * ii], yi = R[3 * ii + 1], zi = R[3 * ii + 2];
-  const int j0 = blockIdx.y * chunk;
-  const int j1 = min(n, j0 + chunk);
-  const double A24 = 24.0 * a2, A42 = 42.0 * a2;
-  double a0 = 0, a1 = 0, a2c = 0, a3 = 0, a4 = 0;
-  double t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
-  for (int jt = j0; jt < j1; jt += TJ) {
-    const int cnt = min(TJ, j1 - jt);
-    __syncthreads();
-    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-      const int j = jt + t;
-      RecS64 rc;
-      rc.x = R[3 * j];
-      rc.y = R[3 * j + 1];
-      rc.z = R[3 * j + 2];
-      basis_to_cart(X + 5 * j, rc.sxx, rc.syy, rc.sxy, rc.sxz, rc.syz);
-      tile[t] = rc;
-    }
-    __syncthreads();
-#pragma unroll 2
-    for (int jj = 0; jj < cnt; ++jj) {
-      const RecS64 s = tile[jj];
-      const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      const double ri = rinv_or_zero(r2);
-      const double ri2 = ri * ri;
-      const double ri5 = ri2 * ri2 * ri;
-      const double ri7 = ri5 * ri2;
-      const double szz = -(s.sxx + s.syy);
-      const double wx = s.sxx * dx + s.sxy * dy + s.sxz * dz;
-      const double wy = s.sxy * dx + s.syy * dy + s.syz * dz;
-      const double wz = s.sxz * dx + s.syz * dy + szz * dz;
-      const double q = dx * wx + dy * wy + dz * wz;
-      const double c1 = ri5 * fma(A24, ri2, -6.0);
-      const double c2 = q * ri7 * fma(-A42, ri2, 15.0);
-      const double vx = fma(c1, wx, c2 * dx);
-      const double vy = fma(c1, wy, c2 * dy);
-      const double vz = fma(c1, wz, c2 * dz);
-      acc_sym(dx, dy, dz, vx, vy, vz, a0, a1, a2c, a3, a4);
-      t0 = fma(ri5, s.sxx, t0);
-      t1 = fma(ri5, s.syy, t1);
-      t2 = fma(ri5, s.sxy, t2);
-      t3 = fma(ri5, s.sxz, t3);
-      t4 = fma(ri5, s.syz, t4);
-    }
-  }
-  if (i >= n) return;
-  const double C3 = -2.4 * a2;  // -12 a^2 / 5
-  double e[5];
-  e[0] = P * RS2 * (a0 + C3 * (t0 - t1));
-  e[1] = P * RS6 * (a1 - 3.0 * C3 * (t0 + t1));
-  e[2] = P * RS2 * (a2c + 2.0 * C3 * t2);
-  e[3] = P * RS2 * (a3 + 2.0 * C3 * t3);
-  e[4] = P * RS2 * (a4 + 2.0 * C3 * t4);
-  if (direct) {
-#pragma unroll
-    for (int c = 0; c < 5; ++c) out[5 * (int64_t)i + c] = X[5 * (int64_t)i + c] * inv_gamma - e[c];
-  } else {
-    double* o = out + (int64_t)blockIdx.y * 5 * n + 5 * (int64_t)i;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) o[c] = e[c];
-  }
-}
-
-__device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
-  const float y = v - c;
-  const float t = s + y;
-  c = (t - s) - y;
-  s = t;
-}
-
-// Binary32 pair blocks. Coordinates are re-centred on the first receiver of the workgroup in
-// binary64 before rounding, so that near pairs keep their relative accuracy. Within one LDS tile
-// the contributions are summed in binary32; tile sums enter compensated (Kahan) binary32
-// accumulators.
-template <int TJ>
-__global__ void __launch_bounds__(kMaxBlock)
-    k_p2_f32(const double* __restrict__ R, const double* __restrict__ X, double* __restrict__ out,
-             int n, int chunk, double P, double a2, double inv_gamma, int direct) {
-  __shared__ RecS32 tile[TJ];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ii = i < n ? i : n - 1;
-  const int i0 = min((int)(blockIdx.x * blockDim.x), n - 1);
-  const double ox = R[3 * i0], oy = R[3 * i0 + 1], oz = R[3 * i0 + 2];
-  const float xi = (float)(R[3 * ii] - ox), yi = (float)(R[3 * ii + 1] - oy),
-              zi = (float)(R[3 * ii + 2] - oz);
-  const int j0 = blockIdx.y * chunk;
-  const int j1 = min(n, j0 + chunk);
-  const float A24 = (float)(24.0 * a2), A42 = (float)(42.0 * a2);
-  float s_a[5] = {0, 0, 0, 0, 0}, c_a[5] = {0, 0, 0, 0, 0};
-  float s_t[5] = {0, 0, 0, 0, 0}, c_t[5] = {0, 0, 0, 0, 0};
-  for (int jt = j0; jt < j1; jt += TJ) {
-    const int cnt = min(TJ, j1 - jt);
-    __syncthreads();
-    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-      const int j = jt + t;
-      double sxx, syy, sxy, sxz, syz;
-      basis_to_cart(X + 5 * j, sxx, syy, sxy, sxz, syz);
-      RecS32 rc;
-      rc.x = (float)(R[3 * j] - ox);
-      rc.y = (float)(R[3 * j + 1] - oy);
-      rc.z = (float)(R[3 * j + 2] - oz);
-      rc.sxx = (float)sxx;
-      rc.syy = (float)syy;
-      rc.sxy = (float)sxy;
-      rc.sxz = (float)sxz;
-      rc.syz = (float)syz;
-      tile[t] = rc;
-    }
-    __syncthreads();
-    float a0 = 0, a1 = 0, a2c = 0, a3 = 0, a4 = 0;
-    float t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
-#pragma unroll 2
-    for (int jj = 0; jj < cnt; ++jj) {
-      const RecS32 s = tile[jj];
-      const float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-      const float r2 = dx * dx + dy * dy + dz * dz;
-      const float ri = rinv_or_zero(r2);
-      const float ri2 = ri * ri;
-      const float ri5 = ri2 * ri2 * ri;
-      const float ri7 = ri5 * ri2;
-      const float szz = -(s.sxx + s.syy);
-      const float wx = s.sxx * dx + s.sxy * dy + s.sxz * dz;
-      const float wy = s.sxy * dx + s.syy * dy + s.syz * dz;
-      const float wz = s.sxz * dx + s.syz * dy + szz * dz;
-      const float q = dx * wx + dy * wy + dz * wz;
-      const float c1 = ri5 * fmaf(A24, ri2, -6.0f);
-      const float c2 = q * ri7 * fmaf(-A42, ri2, 15.0f);
-      const float vx = fmaf(c1, wx, c2 * dx);
-      const float vy = fmaf(c1, wy, c2 * dy);
-      const float vz = fmaf(c1, wz, c2 * dz);
-      acc_sym(dx, dy, dz, vx, vy, vz, a0, a1, a2c, a3, a4);
-      t0 = fmaf(ri5, s.sxx, t0);
-      t1 = fmaf(ri5, s.syy, t1);
-      t2 = fmaf(ri5, s.sxy, t2);
-      t3 = fmaf(ri5, s.sxz, t3);
-      t4 = fmaf(ri5, s.syz, t4);
-    }
-    kahan_add(s_a[0], c_a[0], a0);
-    kahan_add(s_a[1], c_a[1], a1);
-    kahan_add(s_a[2], c_a[2], a2c);
-    kahan_add(s_a[3], c_a[3], a3);
-    kahan_add(s_a[4], c_a[4], a4);
-    kahan_add(s_t[0], c_t[0], t0);
-    kahan_add(s_t[1], c_t[1], t1);
-    kahan_add(s_t[2], c_t[2], t2);
-    kahan_add(s_t[3], c_t[3], t3);
-    kahan_add(s_t[4], c_t[4], t4);
-  }
-  if (i >= n) return;
-  double A[5], Tt[5];
-#pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    A[c] = (double)s_a[c] - (double)c_a[c];
-    Tt[c] = (double)s_t[c] - (double)c_t[c];
-  }
-  const double C3 = -2.4 * a2;
-  double e[5];
-  e[0] = P * RS2 * (A[0] + C3 * (Tt[0] - Tt[1]));
-  e[1] = P * RS6 * (A[1] - 3.0 * C3 * (Tt[0] + Tt[1]));
-  e[2] = P * RS2 * (A[2] + 2.0 * C3 * Tt[2]);
-  e[3] = P * RS2 * (A[3] + 2.0 * C3 * Tt[3]);
-  e[4] = P * RS2 * (A[4] + 2.0 * C3 * Tt[4]);
-  if (direct) {
-#pragma unroll
-    for (int c = 0; c < 5; ++c) out[5 * (int64_t)i + c] = X[5 * (int64_t)i + c] * inv_gamma - e[c];
-  } else {
-    double* o = out + (int64_t)blockIdx.y * 5 * n + 5 * (int64_t)i;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) o[c] = e[c];
-  }
-}
-
-// y = x/gamma - sum_s part[s]
-__global__ void k_p2_finish(const double* __restrict__ X, const double* __restrict__ part,
-                            double* __restrict__ y, int64_t len, int split, double inv_gamma) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= len) return;
-  double acc = 0.0;
-  for (int s = 0; s < split; ++s) acc += part[s * len + k];
-  y[k] = X[k] * inv_gamma - acc;
-}
 
 // ------------------------------------------------------------------ P1: right-hand side
 struct alignas(16) RecF {
@@ -296,7 +58,8 @@ __global__ void __launch_bounds__(kMaxBlock)
   const int j0 = blockIdx.y * chunk;
   const int j1 = min(n, j0 + chunk);
   const double A8 = 8.0 * a2, B16 = -3.2 * a2;  // 8a^2, -(16/5) a^2
-  double a0 = 0, a1 = 0, a2c = 0, a3 = 0, a4 = 0;
+  // raw moments x_i v_j of the per-pair vector v (traceless projection once per receiver)
+  double pxx = 0, pyy = 0, pzz = 0, qxy = 0, qxz = 0, qyz = 0;
   for (int jt = j0; jt < j1; jt += TJ) {
     const int cnt = min(TJ, j1 - jt);
     __syncthreads();
@@ -330,12 +93,12 @@ __global__ void __launch_bounds__(kMaxBlock)
     for (int jj = 0; jj < cnt; ++jj) {
       const RecF& s = tile[jj];
       const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
       const double ri = rinv_or_zero(r2);
       const double ri2 = ri * ri;
       const double ri5 = ri2 * ri2 * ri;
       const double ri7 = ri5 * ri2;
-      const double xF = dx * s.fx + dy * s.fy + dz * s.fz;
+      const double xF = fma(dx, s.fx, fma(dy, s.fy, dz * s.fz));
       double alpha = xF * ri5 * fma(A8, ri2, -3.0);
       const double beta = B16 * ri5;
       double vx = fma(beta, s.fx, alpha * dx);
@@ -354,11 +117,16 @@ __global__ void __launch_bounds__(kMaxBlock)
         vy = fma(six, s.dy, fma(xd, dy, vy));
         vz = fma(six, s.dz, fma(xd, dz, vz));
       }
-      acc_sym(dx, dy, dz, vx, vy, vz, a0, a1, a2c, a3, a4);
+      pxx = fma(dx, vx, pxx);
+      pyy = fma(dy, vy, pyy);
+      pzz = fma(dz, vz, pzz);
+      qxy = fma(dx, vy, fma(dy, vx, qxy));
+      qxz = fma(dx, vz, fma(dz, vx, qxz));
+      qyz = fma(dy, vz, fma(dz, vy, qyz));
     }
   }
   if (i >= n) return;
-  double e[5] = {RS2 * a0, RS6 * a1, RS2 * a2c, RS2 * a3, RS2 * a4};
+  double e[5] = {RS2 * (pxx - pyy), RS6 * (2.0 * pzz - pxx - pyy), RS2 * qxy, RS2 * qxz, RS2 * qyz};
   if (direct) {
 #pragma unroll
     for (int c = 0; c < 5; ++c)
@@ -438,17 +206,17 @@ __global__ void __launch_bounds__(kMaxBlock)
     for (int jj = 0; jj < cnt; ++jj) {
       const RecO& s = tile[jj];
       const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
       const double ri = rinv_or_zero(r2);
       const double ri2 = ri * ri;
       const double ri3 = ri2 * ri;
       const double ri5 = ri3 * ri2;
       const double szz = -(s.sxx + s.syy);
-      const double wx = s.sxx * dx + s.sxy * dy + s.sxz * dz;
-      const double wy = s.sxy * dx + s.syy * dy + s.syz * dz;
-      const double wz = s.sxz * dx + s.syz * dy + szz * dz;
-      const double q = dx * wx + dy * wy + dz * wz;
-      const double xF = dx * s.fx + dy * s.fy + dz * s.fz;
+      const double wx = fma(s.sxx, dx, fma(s.sxy, dy, s.sxz * dz));
+      const double wy = fma(s.sxy, dx, fma(s.syy, dy, s.syz * dz));
+      const double wz = fma(s.sxz, dx, fma(s.syz, dy, szz * dz));
+      const double q = fma(dx, wx, fma(dy, wy, dz * wz));
+      const double xF = fma(dx, s.fx, fma(dy, s.fy, dz * s.fz));
       double cx = xF * fma(-A2_2, ri5, ri3) + q * ri5 * fma(A8, ri2, -3.0);
       const double cF = fma(A2_23, ri3, ri);
       const double cw = B16 * ri5;
@@ -460,9 +228,9 @@ __global__ void __launch_bounds__(kMaxBlock)
       const double gx = fma(3.0 * ri5, wx, -ri3 * s.fx);
       const double gy = fma(3.0 * ri5, wy, -ri3 * s.fy);
       const double gz = fma(3.0 * ri5, wz, -ri3 * s.fz);
-      wx_ += dy * gz - dz * gy;
-      wy_ += dz * gx - dx * gz;
-      wz_ += dx * gy - dy * gx;
+      wx_ = fma(dy, gz, fma(-dz, gy, wx_));
+      wy_ = fma(dz, gx, fma(-dx, gz, wy_));
+      wz_ = fma(dx, gy, fma(-dy, gx, wz_));
       if (HAS_T) {
         // U += (T x x)/r^3 ; W += 1.5 (x.T) x / r^5 - 0.5 T / r^3
         ux = fma(ri3, s.ty * dz - s.tz * dy, ux);
@@ -781,76 +549,12 @@ Phys make_phys(double eta, double a, double c) {
   return p;
 }
 
-static int normalize_block(int b) { return (b == 64 || b == 128 || b == 256) ? b : 256; }
-static int normalize_tj(int tj) { return (tj == 64 || tj == 128 || tj == 256) ? tj : 128; }
-
-int split_for(int64_t n, Tile t) {
-  const int b = normalize_block(t.block);
-  const int tj = normalize_tj(t.tj);
-  const int64_t ntile_i = (n + b - 1) / b;
-  const int64_t max_split = std::max<int64_t>(1, (n + tj - 1) / tj);
-  int64_t s = t.split;
-  if (s <= 0) {
-    // aim at >= 2048 workgroups (8 per CU on 256 CUs) while keeping chunks >= one LDS tile
-    s = (2048 + ntile_i - 1) / ntile_i;
-  }
-  s = std::min<int64_t>(std::max<int64_t>(s, 1), max_split);
-  return (int)s;
-}
-
-int64_t part_elems(int64_t n, Tile t, int width) {
-  const int s = split_for(n, t);
-  return s > 1 ? (int64_t)s * width * n : 0;
-}
-
-template <int TJ>
-static void p2_dispatch(bool f32, const double* R, const double* x, double* y, double* part,
-                        int64_t n, const Phys& ph, int b, int split, hipStream_t s) {
-  const int chunk = (int)((n + split - 1) / split);
-  dim3 grid(nblk(n, b), split);
-  double* out = split > 1 ? part : y;
-  const int direct = split > 1 ? 0 : 1;
-  if (f32)
-    hipLaunchKernelGGL(k_p2_f32<TJ>, grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P, ph.a2,
-                       ph.inv_gamma, direct);
-  else
-    hipLaunchKernelGGL(k_p2_f64<TJ>, grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P, ph.a2,
-                       ph.inv_gamma, direct);
-  if (split > 1)
-    hipLaunchKernelGGL(k_p2_finish, dim3(nblk(5 * n, 256)), dim3(256), 0, s, x, part, y, 5 * n,
-                       split, ph.inv_gamma);
-}
-
-static void p2_any(bool f32, const double* R, const double* x, double* y, double* part, int64_t n,
-                   const Phys& ph, Tile t, hipStream_t s) {
-  const int b = normalize_block(t.block);
-  const int tj = normalize_tj(t.tj);
-  const int split = split_for(n, t);
-  if (tj == 64)
-    p2_dispatch<64>(f32, R, x, y, part, n, ph, b, split, s);
-  else if (tj == 128)
-    p2_dispatch<128>(f32, R, x, y, part, n, ph, b, split, s);
-  else
-    p2_dispatch<256>(f32, R, x, y, part, n, ph, b, split, s);
-}
-
-void launch_p2_f64(const double* R, const double* x, double* y, double* part, int64_t n,
-                   const Phys& ph, Tile t, hipStream_t s) {
-  p2_any(false, R, x, y, part, n, ph, t, s);
-}
-void launch_p2_f32(const double* R, const double* x, double* y, double* part, int64_t n,
-                   const Phys& ph, Tile t, hipStream_t s) {
-  p2_any(true, R, x, y, part, n, ph, t, s);
-}
-
 void launch_p1(const double* R, const double* v2s, const double* v3t, const double* Fe,
                const double* Te, double* b, double* part, int64_t n, const Phys& ph, Tile t,
                hipStream_t s) {
   constexpr int TJ = 128;
-  const int bs = normalize_block(t.block);
-  Tile tt = t;
-  tt.tj = TJ;
-  const int split = split_for(n, tt);
+  const int bs = tile_block(t);
+  const int split = split_for(n, t, TJ);
   const int chunk = (int)((n + split - 1) / split);
   dim3 grid(nblk(n, bs), split);
   double* out = split > 1 ? part : b;
@@ -876,11 +580,9 @@ void launch_p3(const double* R, const double* v1s, const double* v2s, const doub
                const double* Fe, const double* Te, const double* Sig, double* V, double* W,
                double* S, double* part, int64_t n, const Phys& ph, Tile t, hipStream_t s) {
   constexpr int TJ = 128;
-  const int bs = normalize_block(t.block);
-  Tile tt = t;
-  tt.tj = TJ;
+  const int bs = tile_block(t);
   // the output pass always goes through the partial buffer (6 values per receiver and chunk)
-  const int split = split_for(n, tt);
+  const int split = split_for(n, t, TJ);
   const int chunk = (int)((n + split - 1) / split);
   dim3 grid(nblk(n, bs), split);
 #define MBS_P3(HT, HD)                                                                          \

@@ -1,0 +1,390 @@
+// The system operator of the stresslet rows (the GMRES matvec), gfx950:
+//
+//   y_n = x_n / gamma - sum_{m != n} E[x_m](R_n - R_m),
+//   E[Sigma](x) = P [ c1 sym(x w) + c2 x x + c3 Sigma ]  (traceless part),  w = Sigma x, q = x.w,
+//   c1 = -6/r^5 + 24a^2/r^7,  c2 = q (15/r^7 - 42a^2/r^9),  c3 = -12a^2/(5 r^5),
+//
+// the off-diagonal Galerkin element between the symmetric l = 1 modes of two spheres: the
+// finite-size operators F^1 = 1 + a^2/10 nabla^2 of source and receiver applied to the first
+// derivative of the Green's function, reduced with nabla^4 G = 0 (section III).
+//
+// Per pair the receiver accumulates the raw moments x_i v_j of v = c1 w + c2 x (six sums) and
+// r^-5 Sigma (five sums); the traceless 5-basis projection and the constant factors are applied
+// once per receiver. Algorithmic work per pair block: 78 FLOP (FMA = 2, rsqrt = 1): differences
+// 3, r^2 5, 1/r 1, powers 4, Szz 1, w 15, q 5, c1 3, c2 4, v 9, moments 18, r^-5 Sigma 10.
+//
+// Two launch variants share that arithmetic:
+//  * LDS: the workgroup stages source records (position, Cartesian Sigma) through LDS tiles;
+//    every lane reads the same record (broadcast). The binary32 flavour re-centres coordinates on
+//    the workgroup's first receiver (in binary64) before rounding.
+//  * stream: a pack kernel writes one 64-byte (binary64) or 32-byte (binary32) record per source;
+//    the pair kernel walks the records at a wavefront-uniform index, so the compiler issues scalar
+//    loads into SGPRs and no LDS or barrier is involved. The binary32 flavour stores coordinates
+//    relative to the centre of the bounding box.
+// Both split the sources into grid.y chunks whose partial sums a finishing kernel adds in a
+// fixed order (bitwise reproducible). Only ranges that can contain the receiver itself test for
+// r == 0 (n == m term).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "mbs_device.h"
+#include "mbs_internal.h"
+
+namespace mbs {
+
+const Tile kTileTable[] = {
+    {1, 256, 0, 2048}, {1, 128, 0, 2048}, {1, 256, 0, 4096}, {1, 64, 0, 4096},
+    {1, 256, 0, 1024}, {0, 256, 128, 2048}, {0, 256, 256, 2048}, {0, 128, 128, 2048},
+    {0, 256, 128, 4096}, {0, 256, 64, 2048},
+};
+const int kTileCount = sizeof(kTileTable) / sizeof(kTileTable[0]);
+
+namespace {
+
+template <typename T>
+struct alignas(8 * sizeof(T)) Src8 {
+  T x, y, z, sxx, syy, sxy, sxz, syz;
+};
+
+template <typename T>
+struct Mom {  // per-receiver sums
+  T pxx = 0, pyy = 0, pzz = 0, qxy = 0, qxz = 0, qyz = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
+};
+
+template <typename T, bool SELF>
+__device__ __forceinline__ void p2_pair(const Src8<T>& s, T xi, T yi, T zi, T A24, T A42, Mom<T>& m) {
+  const T dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+  const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  const T ri = SELF ? rinv_or_zero(r2) : rsq_nr(r2);
+  const T ri2 = ri * ri;
+  const T ri5 = ri2 * ri2 * ri;
+  const T ri7 = ri5 * ri2;
+  const T szz = -(s.sxx + s.syy);
+  const T wx = fma(s.sxx, dx, fma(s.sxy, dy, s.sxz * dz));
+  const T wy = fma(s.sxy, dx, fma(s.syy, dy, s.syz * dz));
+  const T wz = fma(s.sxz, dx, fma(s.syz, dy, szz * dz));
+  const T q = fma(dx, wx, fma(dy, wy, dz * wz));
+  const T c1 = ri5 * fma(A24, ri2, (T)-6);
+  const T c2 = q * ri7 * fma(-A42, ri2, (T)15);
+  const T vx = fma(c1, wx, c2 * dx);
+  const T vy = fma(c1, wy, c2 * dy);
+  const T vz = fma(c1, wz, c2 * dz);
+  m.pxx = fma(dx, vx, m.pxx);
+  m.pyy = fma(dy, vy, m.pyy);
+  m.pzz = fma(dz, vz, m.pzz);
+  m.qxy = fma(dx, vy, fma(dy, vx, m.qxy));
+  m.qxz = fma(dx, vz, fma(dz, vx, m.qxz));
+  m.qyz = fma(dy, vz, fma(dz, vy, m.qyz));
+  m.t0 = fma(ri5, s.sxx, m.t0);
+  m.t1 = fma(ri5, s.syy, m.t1);
+  m.t2 = fma(ri5, s.sxy, m.t2);
+  m.t3 = fma(ri5, s.sxz, m.t3);
+  m.t4 = fma(ri5, s.syz, m.t4);
+}
+
+// Total over segments: binary64 adds directly; binary32 uses compensated (Kahan) sums.
+template <typename T>
+struct Total;
+template <>
+struct Total<double> {
+  Mom<double> s;
+  __device__ void add(const Mom<double>& m) {
+    s.pxx += m.pxx; s.pyy += m.pyy; s.pzz += m.pzz; s.qxy += m.qxy; s.qxz += m.qxz; s.qyz += m.qyz;
+    s.t0 += m.t0; s.t1 += m.t1; s.t2 += m.t2; s.t3 += m.t3; s.t4 += m.t4;
+  }
+  __device__ void get(double* v) const {
+    const double* p = &s.pxx;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) v[k] = p[k];
+  }
+};
+__device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
+  const float y = v - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+template <>
+struct Total<float> {
+  Mom<float> s, c;
+  __device__ void add(const Mom<float>& m) {
+    kahan_add(s.pxx, c.pxx, m.pxx); kahan_add(s.pyy, c.pyy, m.pyy); kahan_add(s.pzz, c.pzz, m.pzz);
+    kahan_add(s.qxy, c.qxy, m.qxy); kahan_add(s.qxz, c.qxz, m.qxz); kahan_add(s.qyz, c.qyz, m.qyz);
+    kahan_add(s.t0, c.t0, m.t0); kahan_add(s.t1, c.t1, m.t1); kahan_add(s.t2, c.t2, m.t2);
+    kahan_add(s.t3, c.t3, m.t3); kahan_add(s.t4, c.t4, m.t4);
+  }
+  __device__ void get(double* v) const {
+    const float* p = &s.pxx;
+    const float* q = &c.pxx;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) v[k] = (double)p[k] - (double)q[k];
+  }
+};
+
+// Traceless projection and constants; write y (direct) or the chunk partial.
+__device__ __forceinline__ void p2_store(const double* v, int i, int n, const double* __restrict__ X,
+                                         double* __restrict__ out, double P, double a2,
+                                         double inv_gamma, int direct) {
+  const double C3 = -2.4 * a2;  // -12 a^2 / 5
+  const double pxx = v[0], pyy = v[1], pzz = v[2], qxy = v[3], qxz = v[4], qyz = v[5];
+  const double t0 = v[6], t1 = v[7], t2 = v[8], t3 = v[9], t4 = v[10];
+  double e[5];
+  e[0] = P * RS2 * ((pxx - pyy) + C3 * (t0 - t1));
+  e[1] = P * RS6 * ((2.0 * pzz - pxx - pyy) - 3.0 * C3 * (t0 + t1));
+  e[2] = P * RS2 * (qxy + 2.0 * C3 * t2);
+  e[3] = P * RS2 * (qxz + 2.0 * C3 * t3);
+  e[4] = P * RS2 * (qyz + 2.0 * C3 * t4);
+  if (direct) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[5 * (int64_t)i + c] = X[5 * (int64_t)i + c] * inv_gamma - e[c];
+  } else {
+    double* o = out + (int64_t)blockIdx.y * 5 * n + 5 * (int64_t)i;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) o[c] = e[c];
+  }
+}
+
+// ---------------------------------------------------------------- stream variant
+constexpr int kSeg = 64;  // sources per partial sum (binary32: one Kahan update per segment)
+
+template <typename T>
+__global__ void k_pack(const double* __restrict__ R, const double* __restrict__ X,
+                       Src8<T>* __restrict__ src, int n, const double* __restrict__ orig) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double ox = 0.0, oy = 0.0, oz = 0.0;
+  if (orig) {
+    ox = orig[0];
+    oy = orig[1];
+    oz = orig[2];
+  }
+  double sxx, syy, sxy, sxz, syz;
+  basis_to_cart(X + 5 * (int64_t)j, sxx, syy, sxy, sxz, syz);
+  Src8<T> r;
+  r.x = (T)(R[3 * (int64_t)j] - ox);
+  r.y = (T)(R[3 * (int64_t)j + 1] - oy);
+  r.z = (T)(R[3 * (int64_t)j + 2] - oz);
+  r.sxx = (T)sxx;
+  r.syy = (T)syy;
+  r.sxy = (T)sxy;
+  r.sxz = (T)sxz;
+  r.syz = (T)syz;
+  src[j] = r;
+}
+
+// Centre of the bounding box of R -> orig[0..2] (one workgroup).
+__global__ void __launch_bounds__(256) k_bbox(const double* __restrict__ R, int n, double* __restrict__ orig) {
+  __shared__ double lo[3][256], hi[3][256];
+  double l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int j = threadIdx.x; j < n; j += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double v = R[3 * (int64_t)j + c];
+      l[c] = fmin(l[c], v);
+      h[c] = fmax(h[c], v);
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    lo[c][threadIdx.x] = l[c];
+    hi[c][threadIdx.x] = h[c];
+  }
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        lo[c][threadIdx.x] = fmin(lo[c][threadIdx.x], lo[c][threadIdx.x + w]);
+        hi[c][threadIdx.x] = fmax(hi[c][threadIdx.x], hi[c][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) orig[threadIdx.x] = 0.5 * (lo[threadIdx.x][0] + hi[threadIdx.x][0]);
+}
+
+template <typename T, bool SELF>
+__device__ __forceinline__ void stream_range(const Src8<T>* __restrict__ src, int jb, int je, T xi,
+                                             T yi, T zi, T A24, T A42, Total<T>& tot) {
+  for (int j = jb; j < je; j += kSeg) {
+    const int jend = min(je, j + kSeg);
+    Mom<T> m;
+#pragma unroll 2
+    for (int jj = j; jj < jend; ++jj) p2_pair<T, SELF>(src[jj], xi, yi, zi, A24, A42, m);
+    tot.add(m);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxBlock)
+    k_p2_stream(const Src8<T>* __restrict__ src, const double* __restrict__ R,
+                const double* __restrict__ X, double* __restrict__ out, int n, int chunk,
+                const double* __restrict__ orig, double P, double a2, double inv_gamma, int direct) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  double ox = 0.0, oy = 0.0, oz = 0.0;
+  if (orig) {
+    ox = orig[0];
+    oy = orig[1];
+    oz = orig[2];
+  }
+  const T xi = (T)(R[3 * (int64_t)ii] - ox), yi = (T)(R[3 * (int64_t)ii + 1] - oy),
+          zi = (T)(R[3 * (int64_t)ii + 2] - oz);
+  const T A24 = (T)(24.0 * a2), A42 = (T)(42.0 * a2);
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  const int b0 = blockIdx.x * blockDim.x;
+  const int b1 = min(n, b0 + (int)blockDim.x);
+  // sources that can coincide with a receiver of this workgroup: [max(j0,b0), min(j1,b1))
+  const int s0 = max(j0, b0), s1 = min(j1, b1);
+  Total<T> tot;
+  if (s0 < s1) {
+    stream_range<T, false>(src, j0, s0, xi, yi, zi, A24, A42, tot);
+    stream_range<T, true>(src, s0, s1, xi, yi, zi, A24, A42, tot);
+    stream_range<T, false>(src, s1, j1, xi, yi, zi, A24, A42, tot);
+  } else {
+    stream_range<T, false>(src, j0, j1, xi, yi, zi, A24, A42, tot);
+  }
+  if (i >= n) return;
+  double v[11];
+  tot.get(v);
+  p2_store(v, i, n, X, out, P, a2, inv_gamma, direct);
+}
+
+// ---------------------------------------------------------------- LDS variant
+template <typename T, int TJ>
+__global__ void __launch_bounds__(kMaxBlock)
+    k_p2_lds(const double* __restrict__ R, const double* __restrict__ X, double* __restrict__ out,
+             int n, int chunk, double P, double a2, double inv_gamma, int direct) {
+  __shared__ Src8<T> tile[TJ];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const int b0 = blockIdx.x * blockDim.x;
+  const int b1 = min(n, b0 + (int)blockDim.x);
+  // binary32 re-centres on the workgroup's first receiver; binary64 keeps lab coordinates
+  const bool f32 = sizeof(T) == 4;
+  const double ox = f32 ? R[3 * (int64_t)b0] : 0.0, oy = f32 ? R[3 * (int64_t)b0 + 1] : 0.0,
+               oz = f32 ? R[3 * (int64_t)b0 + 2] : 0.0;
+  const T xi = (T)(R[3 * (int64_t)ii] - ox), yi = (T)(R[3 * (int64_t)ii + 1] - oy),
+          zi = (T)(R[3 * (int64_t)ii + 2] - oz);
+  const T A24 = (T)(24.0 * a2), A42 = (T)(42.0 * a2);
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  Total<T> tot;
+  for (int jt = j0; jt < j1; jt += TJ) {
+    const int cnt = min(TJ, j1 - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const int j = jt + t;
+      double sxx, syy, sxy, sxz, syz;
+      basis_to_cart(X + 5 * (int64_t)j, sxx, syy, sxy, sxz, syz);
+      Src8<T> r;
+      r.x = (T)(R[3 * (int64_t)j] - ox);
+      r.y = (T)(R[3 * (int64_t)j + 1] - oy);
+      r.z = (T)(R[3 * (int64_t)j + 2] - oz);
+      r.sxx = (T)sxx;
+      r.syy = (T)syy;
+      r.sxy = (T)sxy;
+      r.sxz = (T)sxz;
+      r.syz = (T)syz;
+      tile[t] = r;
+    }
+    __syncthreads();
+    Mom<T> m;
+    const bool self = jt < b1 && jt + cnt > b0;  // uniform
+    if (self) {
+#pragma unroll 2
+      for (int jj = 0; jj < cnt; ++jj) p2_pair<T, true>(tile[jj], xi, yi, zi, A24, A42, m);
+    } else {
+#pragma unroll 2
+      for (int jj = 0; jj < cnt; ++jj) p2_pair<T, false>(tile[jj], xi, yi, zi, A24, A42, m);
+    }
+    tot.add(m);
+  }
+  if (i >= n) return;
+  double v[11];
+  tot.get(v);
+  p2_store(v, i, n, X, out, P, a2, inv_gamma, direct);
+}
+
+// y = x/gamma - sum_s part[s]
+__global__ void k_p2_finish(const double* __restrict__ X, const double* __restrict__ part,
+                            double* __restrict__ y, int64_t len, int split, double inv_gamma) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  double acc = 0.0;
+  for (int s = 0; s < split; ++s) acc += part[s * len + k];
+  y[k] = X[k] * inv_gamma - acc;
+}
+
+inline unsigned nblk(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
+
+template <typename T>
+void p2_launch(const double* R, const double* x, double* y, double* part, double* srcbuf,
+               double* orig, int64_t n, const Phys& ph, Tile t, hipStream_t s) {
+  const int b = tile_block(t);
+  const int tj = t.variant == 0 ? ((t.tj == 64 || t.tj == 256) ? t.tj : 128) : kSeg;
+  const int split = split_for(n, t, tj);
+  const int chunk = (int)((n + split - 1) / split);
+  dim3 grid(nblk(n, b), split);
+  double* out = split > 1 ? part : y;
+  const int direct = split > 1 ? 0 : 1;
+  if (t.variant == 1) {
+    const bool f32 = sizeof(T) == 4;
+    double* o = f32 ? orig : nullptr;
+    if (f32) hipLaunchKernelGGL(k_bbox, dim3(1), dim3(256), 0, s, R, (int)n, orig);
+    Src8<T>* src = reinterpret_cast<Src8<T>*>(srcbuf);
+    hipLaunchKernelGGL(k_pack<T>, dim3(nblk(n, 256)), dim3(256), 0, s, R, x, src, (int)n, o);
+    hipLaunchKernelGGL(k_p2_stream<T>, grid, dim3(b), 0, s, src, R, x, out, (int)n, chunk, o, ph.P,
+                       ph.a2, ph.inv_gamma, direct);
+  } else if (tj == 64) {
+    hipLaunchKernelGGL((k_p2_lds<T, 64>), grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P, ph.a2,
+                       ph.inv_gamma, direct);
+  } else if (tj == 256) {
+    hipLaunchKernelGGL((k_p2_lds<T, 256>), grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P,
+                       ph.a2, ph.inv_gamma, direct);
+  } else {
+    hipLaunchKernelGGL((k_p2_lds<T, 128>), grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P,
+                       ph.a2, ph.inv_gamma, direct);
+  }
+  if (split > 1)
+    hipLaunchKernelGGL(k_p2_finish, dim3(nblk(5 * n, 256)), dim3(256), 0, s, x, part, y, 5 * n,
+                       split, ph.inv_gamma);
+}
+
+}  // namespace
+
+int tile_block(Tile t) { return (t.block == 64 || t.block == 128 || t.block == 256) ? t.block : 256; }
+
+int split_for(int64_t n, Tile t, int tj) {
+  const int b = tile_block(t);
+  const int64_t ntile_i = (n + b - 1) / b;
+  const int64_t target = t.wgs > 0 ? t.wgs : 2048;
+  const int64_t max_split = std::max<int64_t>(1, (n + std::max(tj, 64) - 1) / std::max(tj, 64));
+  int64_t s = (target + ntile_i - 1) / ntile_i;
+  s = std::min<int64_t>(std::max<int64_t>(s, 1), max_split);
+  return (int)s;
+}
+
+int64_t part_elems_max(int64_t n) {
+  int64_t m = 6 * n;
+  for (int k = 0; k < kTileCount; ++k) {
+    const Tile& t = kTileTable[k];
+    for (int tj : {64, 128, 256}) {
+      const int s = split_for(n, t, tj);
+      if (s > 1) m = std::max<int64_t>(m, (int64_t)s * 6 * n);
+    }
+  }
+  return m;
+}
+
+void launch_p2(bool f32, const double* R, const double* x, double* y, double* part, double* src,
+               double* orig, int64_t n, const Phys& ph, Tile t, hipStream_t s) {
+  if (f32)
+    p2_launch<float>(R, x, y, part, src, orig, n, ph, t, s);
+  else
+    p2_launch<double>(R, x, y, part, src, orig, n, ph, t, s);
+}
+
+}  // namespace mbs

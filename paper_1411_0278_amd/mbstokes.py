@@ -89,7 +89,7 @@ def load(path: str = LIB_PATH):
     lib.mbs_solve_batched.argtypes = [P, I32, ctypes.POINTER(ctypes.c_int64)] + [P] * 10 + [
         ctypes.POINTER(Stats), ctypes.POINTER(ctypes.c_double), VP]
     lib.mbs_solve_batched.restype = ctypes.c_int
-    lib.mbs_autotune.argtypes = [P, I64, P, ctypes.c_char_p, VP]
+    lib.mbs_autotune.argtypes = [P, I64, P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32), VP]
     lib.mbs_autotune.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -240,6 +240,17 @@ class Context:
                                         _ptr(Sigma, ntot, 5, "Sigma"), stats, lat, _stream())
         self._check(rc)
         return V, W, S, [stats[b].as_dict() for b in range(nconf)], list(lat)
+
+
+def _autotune(self, R, cache_json=None):
+    n = R.shape[0]
+    chosen = (ctypes.c_int32 * 2)()
+    self._check(self.lib.mbs_autotune(self.h, n, _ptr(R, n, 3, "R"),
+                                      cache_json.encode() if cache_json else None, chosen, _stream()))
+    return int(chosen[0]), int(chosen[1])
+
+
+Context.mbs_autotune = _autotune
 
 
 def to_device(w, device="cuda"):

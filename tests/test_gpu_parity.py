@@ -77,6 +77,47 @@ def test_matvec_f32_matches_oracle(ctx, n):
     assert _rel(got, want) < 2e-5
 
 
+def _tiles(ctx):
+    k = 1
+    while True:
+        try:
+            ctx.set_params(tile=k)
+        except mbstokes.MbsError:
+            break
+        yield k
+        k += 1
+    ctx.set_params(tile=0)
+
+
+@pytest.mark.parametrize("n", [257, 1300])
+def test_matvec_every_launch_shape(ctx, n):
+    """Every candidate shape of the autotuner (LDS tiles, scalar streaming, splits) agrees."""
+    w = _workload(n, seed=600 + n)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    x = np.random.default_rng(n).standard_normal((n, 5))
+    want = (galerkin.system_matrix(w.R, prm) @ x.ravel()).reshape(n, 5)
+    R, xt = _t(w.R), _t(x)
+    count = 0
+    for k in _tiles(ctx):
+        print(f"matvec n={n} tile={k}", flush=True)
+        assert _maxrel(ctx.mbs_matvec(R, xt), want) < 1e-13, k
+        assert _rel(ctx.mbs_matvec(R, xt, precision=mbstokes.MBS_FP32), want) < 2e-5, k
+        count += 1
+    assert count >= 8
+
+
+def test_autotune_and_cache(ctx, tmp_path):
+    w = _workload(2000, seed=17)
+    R = _t(w.R)
+    cache = str(tmp_path / "tiles.json")
+    a = ctx.mbs_autotune(R, cache)
+    b = ctx.mbs_autotune(R, cache)  # served from the cache
+    assert a == b
+    x = _t(np.random.default_rng(2).standard_normal((w.n, 5)))
+    want = (galerkin.system_matrix(w.R, galerkin.Params()) @ x.cpu().numpy().ravel()).reshape(w.n, 5)
+    assert _maxrel(ctx.mbs_matvec(R, x), want) < 1e-13
+
+
 def test_matvec_is_bitwise_deterministic(ctx):
     w = _workload(1500, seed=5)
     x = _t(np.random.default_rng(1).standard_normal((w.n, 5)))
