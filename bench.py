@@ -39,7 +39,40 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--headline", default="mixed_diag", choices=["plain_fp64", "mixed_diag", "fp64_diag"])
+    ap.add_argument("--profile-matvec", action="store_true",
+                    help="profiling mode: a 256 MiB device copy (counter calibration), then --steps "
+                         "binary64 and --steps binary32 operator applications at the autotuned shapes")
     return ap.parse_args()
+
+
+def profile_matvec(a, w):
+    """Short run for hardware-counter passes: calibration copy, then the two operator kernels."""
+    import torch
+
+    from paper_1411_0278_amd import mbstokes
+    src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)  # 256 MiB read + 256 MiB written
+    torch.cuda.synchronize()
+    R = torch.as_tensor(w.R, dtype=torch.float64).to("cuda:0")
+    x = torch.as_tensor(w.v2s, dtype=torch.float64).contiguous().to("cuda:0")
+    ctx = mbstokes.Context(0)
+    t64, t32 = ctx.mbs_autotune(R, None)
+    times = {}
+    for prec, t in ((mbstokes.MBS_FP64, t64), (mbstokes.MBS_FP32, t32)):
+        ctx.set_params(tile=t + 1)
+        y = ctx.mbs_matvec(R, x, precision=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            ctx.mbs_matvec(R, x, y, precision=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        times["f64" if prec == mbstokes.MBS_FP64 else "f32"] = e0.elapsed_time(e1) / a.steps
+    ctx.close()
+    print(json.dumps({"mode": "profile-matvec", "n": w.n, "tiles": [t64, t32], "ms_per_launch": times,
+                      "copy_bytes": 2 * src.numel() * 8}), flush=True)
 
 
 def kernel_source_hash():
@@ -139,6 +172,9 @@ def main():
     from paper_1411_0278_amd import inputs, mbstokes
     print(f"bench: generating workload n={a.n} side={a.side} seed={a.seed}", file=sys.stderr, flush=True)
     w = inputs.trap_workload(a.n, a.side, a.seed)
+    if a.profile_matvec:
+        profile_matvec(a, w)
+        return
     d = mbstokes.to_device(w, "cuda:0")
     # the workload has no external torque and no rank-3 trace slip: pass NULL (= zero)
     d.pop("Te")
