@@ -63,7 +63,9 @@ extern "C" {
 
 #define MBS_GUESS_ZERO     0   /* Sigma^0 = 0 */
 #define MBS_GUESS_DIAG     1   /* Sigma^0 = gamma b: the one-body (diagonal) solve of the system */
-#define MBS_GUESS_LEARNED  2   /* Sigma^0 = gamma b + MLP(neighbourhood), needs mbs_warmstart_load */
+#define MBS_GUESS_LEARNED  2   /* Sigma^0 = gamma b + net(neighbourhood features); needs a network
+                                  (mbs_warmstart_init/set/load/train), p and n >= 17; in
+                                  mbs_solve_batched it falls back to MBS_GUESS_DIAG */
 #define MBS_GUESS_USER     3   /* Sigma^0 = the caller's sigma0 */
 
 typedef struct mbs_params {
@@ -179,6 +181,44 @@ int mbs_solve_batched(mbs_ctx* ctx, int32_t nconf, const int64_t* offsets, const
    binary32); params.tile = index + 1 forces that shape. */
 int mbs_autotune(mbs_ctx* ctx, int64_t n, const double* R, const char* cache_json, int32_t* chosen,
                  void* stream);
+
+/* ---------------------------------------------------------------- learned warm start
+   A 3-layer perceptron 80 -> 128 -> 128 -> 5 (ReLU) maps the neighbourhood of each sphere to a
+   correction of the one-body guess: MBS_GUESS_LEARNED starts GMRES from Sigma^0 = gamma b + net(f).
+   The network multiplies bfloat16 operands with float32 accumulation on the matrix cores; its
+   float32 master parameters live in the context. Parameter vector (host float32, 27525 values):
+   W1 [80 x 128] row-major (input x output), b1 [128], W2 [128 x 128], b2 [128], W3 [128 x 5], b3 [5]. */
+#define MBS_MLP_NPARAM 27525
+#define MBS_MLP_NFEAT 80
+
+/* Features of the warm start: for each sphere i the 16 nearest other centres j (by distance,
+   ties by smaller index), nearest first, each contributing (R_j - R_i)/|R_j - R_i| (3 values),
+   1/|R_j - R_i| and p_j . p_i: feat [n x 80] float32 DEVICE. nbr (may be NULL): int32 [n x 16]
+   DEVICE receives the neighbour indices. Requires n >= 17. */
+int mbs_features(mbs_ctx* ctx, int64_t n, const double* R, const double* p, float* feat, int32_t* nbr,
+                 void* stream);
+/* Initialise the network: He-uniform weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)) from a 64-bit
+   Mersenne twister seeded with `seed`, zero biases; resets the Adam state. */
+int mbs_warmstart_init(mbs_ctx* ctx, uint64_t seed);
+/* Replace / read the parameters (host float32 [MBS_MLP_NPARAM]); set resets the Adam state. */
+int mbs_warmstart_set(mbs_ctx* ctx, const float* params);
+int mbs_warmstart_get(mbs_ctx* ctx, float* params);
+/* out [m x 5] = net(feat [m x 80]); float32 DEVICE arrays. */
+int mbs_warmstart_forward(mbs_ctx* ctx, int64_t m, const float* feat, float* out, void* stream);
+/* Mean squared error L = sum (net(f) - t)^2 / (5 m) over m <= 65536 samples (feat [m x 80],
+   target [m x 5], float32 DEVICE) and its gradient (host float32 [MBS_MLP_NPARAM], layout as the
+   parameters); *loss (may be NULL) receives L. */
+int mbs_warmstart_grad(mbs_ctx* ctx, int64_t m, const float* feat, const float* target, float* grad,
+                       double* loss, void* stream);
+/* Adam training (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) over `epochs` passes of the m
+   samples in mini-batches of `batch` (16..65536), reshuffled every epoch by a Fisher-Yates
+   permutation from a 64-bit Mersenne twister seeded with `seed`. loss_hist: host [epochs] or NULL,
+   receives the mean training loss of each epoch. */
+int mbs_warmstart_train(mbs_ctx* ctx, int64_t m, const float* feat, const float* target, int32_t epochs,
+                        int32_t batch, double lr, uint64_t seed, double* loss_hist, void* stream);
+/* Write / read the float32 parameters (binary: "MBSW", version 1, count, values). */
+int mbs_warmstart_save(mbs_ctx* ctx, const char* path);
+int mbs_warmstart_load(mbs_ctx* ctx, const char* path);
 
 #ifdef __cplusplus
 }

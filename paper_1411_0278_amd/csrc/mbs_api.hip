@@ -12,8 +12,11 @@
 #include <string>
 #include <vector>
 
+#include <random>
+
 #include "../../include/mbstokes.h"
 #include "mbs_internal.h"
+#include "mbs_mlp.h"
 
 using namespace mbs;
 
@@ -48,6 +51,11 @@ struct mbs_ctx {
   int op_prec[kRing] = {};
   int npend = 0;
   double t_op[2] = {0.0, 0.0};  // summed binary64 / binary32 operator time of the current call
+  // warm-start network: float32 master parameters, gradient, Adam moments, bf16 weight copies,
+  // activation workspace, neighbour lists and features
+  bool mlp_ready = false;
+  int adam_step = 0;
+  DevBuf mlp_w, mlp_g, mlp_m, mlp_v, mlp_wb, mlp_ws, mlp_part, mlp_loss, mlp_idx, knn_buf;
 };
 
 namespace {
@@ -111,8 +119,6 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
     return set_err(c, MBS_EINVAL, "inner_tol must be in (0, 1)");
   if (p->guess < MBS_GUESS_ZERO || p->guess > MBS_GUESS_USER)
     return set_err(c, MBS_EINVAL, "unknown guess %d", p->guess);
-  if (p->guess == MBS_GUESS_LEARNED)
-    return set_err(c, MBS_EUNSUPPORTED, "learned warm start is not loaded in this context");
   if (p->tile < 0 || p->tile > kTileCount)
     return set_err(c, MBS_EINVAL, "tile must be in 0..%d", kTileCount);
   return MBS_OK;
@@ -316,8 +322,162 @@ float ev_ms(hipEvent_t a, hipEvent_t b) {
   return t;
 }
 
+// ---------------------------------------------------------------- warm-start network (host side)
+constexpr int kChunkRows = 65536;  // rows per network pass (bounds the activation workspace)
+
+struct MlpWs {
+  uint16_t *X, *H1, *H2, *dOut, *D2, *D1;
+  float *C1, *C2, *C3, *dOut32, *G2, *G2m, *G1, *G1m;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t mlp_ws_bytes(int rp) {
+  size_t b = 0;
+  b += align256((size_t)rp * kMlpIn * 2);
+  b += 2 * align256((size_t)rp * kMlpHid * 2);      // H1, H2
+  b += align256((size_t)rp * 16 * 2);               // dOut
+  b += 2 * align256((size_t)rp * kMlpHid * 2);      // D2, D1
+  b += 2 * align256((size_t)rp * kMlpHid * 4);      // C1, C2
+  b += align256((size_t)rp * 16 * 4);               // C3
+  b += align256((size_t)rp * kMlpOut * 4);          // dOut32
+  b += 4 * align256((size_t)rp * kMlpHid * 4);      // G2, G2m, G1, G1m
+  return b;
+}
+
+int mlp_ensure(mbs_ctx* c, int rp) {
+  CHK(ensure(c, c->mlp_w, (kMlpParams + 1) / 2 + 8));
+  CHK(ensure(c, c->mlp_g, (kMlpParams + 1) / 2 + 8));
+  CHK(ensure(c, c->mlp_m, (kMlpParams + 1) / 2 + 8));
+  CHK(ensure(c, c->mlp_v, (kMlpParams + 1) / 2 + 8));
+  CHK(ensure(c, c->mlp_wb, (kMlpIn * kMlpHid + kMlpHid * kMlpHid + kMlpHid * 16) / 4 + 64));
+  CHK(ensure(c, c->mlp_ws, mlp_ws_bytes(rp) / 8 + 64));
+  CHK(ensure(c, c->mlp_part, (size_t)64 * kMlpHid * kMlpHid / 2 + 64));
+  CHK(ensure(c, c->mlp_loss, (size_t)mlp_mse_blocks(rp) + 64));
+  return MBS_OK;
+}
+
+MlpWs mlp_carve(mbs_ctx* c, int rp) {
+  char* p = (char*)c->mlp_ws.p;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += align256(bytes);
+    return q;
+  };
+  MlpWs w;
+  w.X = (uint16_t*)take((size_t)rp * kMlpIn * 2);
+  w.H1 = (uint16_t*)take((size_t)rp * kMlpHid * 2);
+  w.H2 = (uint16_t*)take((size_t)rp * kMlpHid * 2);
+  w.dOut = (uint16_t*)take((size_t)rp * 16 * 2);
+  w.D2 = (uint16_t*)take((size_t)rp * kMlpHid * 2);
+  w.D1 = (uint16_t*)take((size_t)rp * kMlpHid * 2);
+  w.C1 = (float*)take((size_t)rp * kMlpHid * 4);
+  w.C2 = (float*)take((size_t)rp * kMlpHid * 4);
+  w.C3 = (float*)take((size_t)rp * 16 * 4);
+  w.dOut32 = (float*)take((size_t)rp * kMlpOut * 4);
+  w.G2 = (float*)take((size_t)rp * kMlpHid * 4);
+  w.G2m = (float*)take((size_t)rp * kMlpHid * 4);
+  w.G1 = (float*)take((size_t)rp * kMlpHid * 4);
+  w.G1m = (float*)take((size_t)rp * kMlpHid * 4);
+  return w;
+}
+
+struct MlpW {
+  float* w;
+  uint16_t *W1, *W2, *W3;
+};
+MlpW mlp_weights(mbs_ctx* c) {
+  MlpW o;
+  o.w = (float*)c->mlp_w.p;
+  o.W1 = (uint16_t*)c->mlp_wb.p;
+  o.W2 = o.W1 + kMlpIn * kMlpHid;
+  o.W3 = o.W2 + kMlpHid * kMlpHid;
+  return o;
+}
+
+int ceil16(int v) { return (v + 15) & ~15; }
+
+// forward pass of `rows` samples (feature rows idx[r] of feat, or r if idx is NULL) -> C3 [rp x 16]
+void mlp_forward_rows(mbs_ctx* c, const float* feat, const int32_t* idx, int rows, const MlpWs& ws,
+                      hipStream_t s) {
+  const int rp = ceil16(rows);
+  MlpW W = mlp_weights(c);
+  float* part = (float*)c->mlp_part.p;
+  mlp_gather_bf16(feat, idx, rows, rp, kMlpIn, ws.X, s);
+  mlp_gemm(ws.X, kMlpIn, false, W.W1, kMlpHid, false, ws.C1, part, rp, kMlpHid, kMlpIn, 1, s);
+  mlp_bias_relu(ws.C1, W.w + kOffB1, rp, kMlpHid, ws.H1, s);
+  mlp_gemm(ws.H1, kMlpHid, false, W.W2, kMlpHid, false, ws.C2, part, rp, kMlpHid, kMlpHid, 1, s);
+  mlp_bias_relu(ws.C2, W.w + kOffB2, rp, kMlpHid, ws.H2, s);
+  mlp_gemm(ws.H2, kMlpHid, false, W.W3, 16, false, ws.C3, part, rp, 16, kMlpHid, 1, s);
+}
+
+// gradient of the batch MSE into c->mlp_g; loss partial sums into c->mlp_loss (+ loss_off)
+void mlp_backward_rows(mbs_ctx* c, const float* target, const int32_t* idx, int rows,
+                       const MlpWs& ws, double* loss_parts, hipStream_t s) {
+  const int rp = ceil16(rows);
+  MlpW W = mlp_weights(c);
+  float* g = (float*)c->mlp_g.p;
+  float* part = (float*)c->mlp_part.p;
+  const int ks = std::max(1, std::min(64, rp / 512));
+  mlp_mse_grad(ws.C3, W.w + kOffB3, target, idx, rows, rp, 1.0 / ((double)rows * kMlpOut), ws.dOut,
+               ws.dOut32, loss_parts, s);
+  // W3, b3
+  mlp_gemm(ws.H2, kMlpHid, true, ws.dOut, 16, false, ws.G2 /*scratch [128 x 16]*/, part, kMlpHid, 16,
+           rp, ks, s);
+  mlp_copy_cols(ws.G2, 16, kMlpHid, kMlpOut, g + kOffW3, s);
+  mlp_colsum(ws.dOut32, rows, kMlpOut, g + kOffB3, s);
+  // through layer 3
+  mlp_gemm(ws.dOut, 16, false, W.W3, 16, true, ws.G2, part, rp, kMlpHid, 16, 1, s);
+  mlp_relu_mask(ws.G2, ws.H2, (int64_t)rp * kMlpHid, ws.D2, ws.G2m, s);
+  mlp_colsum(ws.G2m, rp, kMlpHid, g + kOffB2, s);
+  mlp_gemm(ws.H1, kMlpHid, true, ws.D2, kMlpHid, false, g + kOffW2, part, kMlpHid, kMlpHid, rp, ks, s);
+  // through layer 2
+  mlp_gemm(ws.D2, kMlpHid, false, W.W2, kMlpHid, true, ws.G1, part, rp, kMlpHid, kMlpHid, 1, s);
+  mlp_relu_mask(ws.G1, ws.H1, (int64_t)rp * kMlpHid, ws.D1, ws.G1m, s);
+  mlp_colsum(ws.G1m, rp, kMlpHid, g + kOffB1, s);
+  mlp_gemm(ws.X, kMlpIn, true, ws.D1, kMlpHid, false, g + kOffW1, part, kMlpIn, kMlpHid, rp, ks, s);
+}
+
+// network output for m samples: out [m x 5] float32
+int mlp_forward(mbs_ctx* c, int64_t m, const float* feat, float* out, hipStream_t s) {
+  const int rp_max = (int)std::min<int64_t>(ceil16((int)std::min<int64_t>(m, kChunkRows)), kChunkRows);
+  CHK(mlp_ensure(c, rp_max));
+  MlpWs ws = mlp_carve(c, rp_max);
+  MlpW W = mlp_weights(c);
+  for (int64_t r0 = 0; r0 < m; r0 += kChunkRows) {
+    const int rows = (int)std::min<int64_t>(kChunkRows, m - r0);
+    mlp_forward_rows(c, feat + r0 * kMlpIn, nullptr, rows, ws, s);
+    mlp_out_bias(ws.C3, W.w + kOffB3, rows, out + r0 * kMlpOut, s);
+  }
+  return MBS_OK;
+}
+
+int knn_features(mbs_ctx* c, int64_t n, const double* R, const double* p, float* feat, int32_t* nbr,
+                 hipStream_t s) {
+  launch_knn16(R, (int)n, nbr, s);
+  launch_features(R, p, nbr, (int)n, feat, s);
+  return MBS_OK;
+}
+
+// learned guess: x = gamma b + network(features(R, p))
+int learned_guess(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* b, double* x,
+                  hipStream_t s) {
+  const size_t o_feat = align256((size_t)n * kNeigh * 4);
+  const size_t o_out = o_feat + align256((size_t)n * kMlpIn * 4);
+  const size_t bytes = o_out + (size_t)n * kMlpOut * 4;
+  CHK(ensure(c, c->knn_buf, bytes / 8 + 64));
+  char* base = (char*)c->knn_buf.p;
+  int32_t* nbr = (int32_t*)base;
+  float* feat = (float*)(base + o_feat);
+  float* out = (float*)(base + o_out);
+  CHK(knn_features(c, n, R, p, feat, nbr, s));
+  CHK(mlp_forward(c, n, feat, out, s));
+  launch_guess_learned(b, out, c->ph.gamma, 5 * n, x, s);
+  return MBS_OK;
+}
+
 // The solve without argument validation; sigma0 is read for MBS_GUESS_USER.
-int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const double* v2s,
+int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* v1s, const double* v2s,
                const double* v3t, const double* Fe, const double* Te, const double* sigma0,
                double* V, double* W, double* S, double* Sigma, mbs_stats* st, hipStream_t s) {
   CHK(ensure_ws(c, n));
@@ -348,6 +508,9 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const 
     case MBS_GUESS_USER:
       if (!sigma0) return set_err(c, MBS_EINVAL, "MBS_GUESS_USER needs sigma0");
       launch_copy(sigma0, c->xs.p, len, s);
+      break;
+    case MBS_GUESS_LEARNED:
+      CHK(learned_guess(c, n, R, p, c->b.p, c->xs.p, s));
       break;
     default:
       return set_err(c, MBS_EUNSUPPORTED, "guess %d not available", c->prm.guess);
@@ -487,7 +650,9 @@ void mbs_destroy(mbs_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   DevBuf* bufs[] = {&c->V, &c->w, &c->r, &c->b, &c->xs, &c->dlt, &c->part, &c->dpart,
-                    &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig};
+                    &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig,
+                    &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
+                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->d_count) (void)hipFree(c->d_count);
@@ -543,7 +708,13 @@ int mbs_solve(mbs_ctx* c, int64_t n, const double* R, const double* p, const dou
     if (md < 2.0 * c->prm.a)
       return set_err(c, MBS_EOVERLAP, "spheres overlap: minimum centre distance %.6g < 2a", md);
   }
-  return solve_core(c, n, R, v1s, v2s, v3t, Fe, Te, sigma0, V, W, S, Sigma, st, s);
+  if (c->prm.guess == MBS_GUESS_LEARNED) {
+    if (!c->mlp_ready)
+      return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context (mbs_warmstart_*)");
+    if (!p) return set_err(c, MBS_EINVAL, "the learned guess needs the orientations p");
+    if (n < kNeigh + 1) return set_err(c, MBS_EINVAL, "the learned guess needs n >= %d", kNeigh + 1);
+  }
+  return solve_core(c, n, R, p, v1s, v2s, v3t, Fe, Te, sigma0, V, W, S, Sigma, st, s);
 }
 
 int mbs_matvec(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, int precision,
@@ -638,7 +809,7 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
     mbs_stats one{};
     const bool warm = guess0 == MBS_GUESS_USER && k > 0;
     if (guess0 == MBS_GUESS_USER && k == 0) c->prm.guess = MBS_GUESS_DIAG;
-    rc = solve_core(c, n, R, v1s, v2s, slip_coef[2] != 0.0 ? v3t : nullptr, Fe, nullptr,
+    rc = solve_core(c, n, R, p, v1s, v2s, slip_coef[2] != 0.0 ? v3t : nullptr, Fe, nullptr,
                     warm ? Sg : nullptr, V, W, Sout, Sg, &one, s);
     c->prm.guess = guess0;
     if (rc != MBS_OK && rc != MBS_ENOCONV) break;
@@ -672,13 +843,14 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   if (bad) return set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
   const int guess0 = c->prm.guess;
   if (guess0 == MBS_GUESS_USER) c->prm.guess = MBS_GUESS_ZERO;
+  if (guess0 == MBS_GUESS_LEARNED) c->prm.guess = MBS_GUESS_DIAG;  // no orientations in this call
   hipEvent_t t0 = c->ev[4], t1 = c->ev[5];
   HIPCHK(c, hipEventRecord(t0, s));
   int rc = MBS_OK;
   for (int b = 0; b < nconf; ++b) {
     const int64_t o = offsets[b], nb = offsets[b + 1] - offsets[b];
     mbs_stats one{};
-    int r1 = solve_core(c, nb, R + 3 * o, v1s ? v1s + 3 * o : nullptr, v2s ? v2s + 5 * o : nullptr,
+    int r1 = solve_core(c, nb, R + 3 * o, nullptr, v1s ? v1s + 3 * o : nullptr, v2s ? v2s + 5 * o : nullptr,
                         v3t ? v3t + 3 * o : nullptr, Fe ? Fe + 3 * o : nullptr,
                         Te ? Te + 3 * o : nullptr, nullptr, V + 3 * o, W + 3 * o, S + 5 * o,
                         Sigma ? Sigma + 5 * o : nullptr, &one, s);
@@ -796,6 +968,180 @@ int mbs_autotune(mbs_ctx* c, int64_t n, const double* R, const char* cache_json,
     chosen[1] = best[1];
   }
   return MBS_OK;
+}
+
+int mbs_features(mbs_ctx* c, int64_t n, const double* R, const double* p, float* feat, int32_t* nbr,
+                 void* stream) {
+  CHK(begin_call(c));
+  if (n < kNeigh + 1) return set_err(c, MBS_EINVAL, "features need n >= %d", kNeigh + 1);
+  if (n > (int64_t)INT32_MAX / kMlpIn) return set_err(c, MBS_EINVAL, "n too large");
+  if (!R || !p || !feat) return set_err(c, MBS_EINVAL, "R, p and feat are required");
+  hipStream_t s = (hipStream_t)stream;
+  int32_t* nb = nbr;
+  if (!nb) {
+    CHK(ensure(c, c->knn_buf, (size_t)n * kNeigh / 2 + 64));
+    nb = (int32_t*)c->knn_buf.p;
+  }
+  CHK(knn_features(c, n, R, p, feat, nb, s));
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_warmstart_set(mbs_ctx* c, const float* params) {
+  CHK(begin_call(c));
+  if (!params) return set_err(c, MBS_EINVAL, "params is NULL");
+  for (int k = 0; k < kMlpParams; ++k)
+    if (!isfinite(params[k])) return set_err(c, MBS_EINVAL, "non-finite parameter %d", k);
+  CHK(mlp_ensure(c, 16));
+  MlpW W = mlp_weights(c);
+  HIPCHK(c, hipMemcpy(W.w, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemset(c->mlp_m.p, 0, kMlpParams * sizeof(float)));
+  HIPCHK(c, hipMemset(c->mlp_v.p, 0, kMlpParams * sizeof(float)));
+  mlp_weights_bf16(W.w, W.W1, W.W2, W.W3, nullptr);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipDeviceSynchronize());
+  c->adam_step = 0;
+  c->mlp_ready = true;
+  return MBS_OK;
+}
+
+int mbs_warmstart_init(mbs_ctx* c, uint64_t seed) {
+  CHK(begin_call(c));
+  // He-uniform weights U(-sqrt(6/fan_in), sqrt(6/fan_in)), zero biases
+  std::vector<float> w(kMlpParams, 0.f);
+  std::mt19937_64 gen(seed);
+  auto fill = [&](int off, int fan_in, int count) {
+    std::uniform_real_distribution<double> U(-sqrt(6.0 / fan_in), sqrt(6.0 / fan_in));
+    for (int k = 0; k < count; ++k) w[off + k] = (float)U(gen);
+  };
+  fill(kOffW1, kMlpIn, kMlpIn * kMlpHid);
+  fill(kOffW2, kMlpHid, kMlpHid * kMlpHid);
+  fill(kOffW3, kMlpHid, kMlpHid * kMlpOut);
+  return mbs_warmstart_set(c, w.data());
+}
+
+int mbs_warmstart_get(mbs_ctx* c, float* params) {
+  CHK(begin_call(c));
+  if (!params) return set_err(c, MBS_EINVAL, "params is NULL");
+  if (!c->mlp_ready) return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context");
+  HIPCHK(c, hipMemcpy(params, c->mlp_w.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost));
+  return MBS_OK;
+}
+
+int mbs_warmstart_forward(mbs_ctx* c, int64_t m, const float* feat, float* out, void* stream) {
+  CHK(begin_call(c));
+  if (m < 1 || !feat || !out) return set_err(c, MBS_EINVAL, "m >= 1, feat and out are required");
+  if (m > (int64_t)INT32_MAX / kMlpIn) return set_err(c, MBS_EINVAL, "m too large");
+  if (!c->mlp_ready) return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(mlp_forward(c, m, feat, out, s));
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_warmstart_grad(mbs_ctx* c, int64_t m, const float* feat, const float* target, float* grad,
+                       double* loss, void* stream) {
+  CHK(begin_call(c));
+  if (m < 1 || m > kChunkRows || !feat || !target || !grad)
+    return set_err(c, MBS_EINVAL, "1 <= m <= %d; feat, target and grad are required", kChunkRows);
+  if (!c->mlp_ready) return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context");
+  hipStream_t s = (hipStream_t)stream;
+  const int rows = (int)m, rp = ceil16(rows);
+  CHK(mlp_ensure(c, rp));
+  MlpWs ws = mlp_carve(c, rp);
+  double* lp = (double*)c->mlp_loss.p;
+  mlp_forward_rows(c, feat, nullptr, rows, ws, s);
+  mlp_backward_rows(c, target, nullptr, rows, ws, lp, s);
+  HIPCHK(c, hipGetLastError());
+  const int nb = mlp_mse_blocks(rp);
+  std::vector<double> parts(nb);
+  HIPCHK(c, hipMemcpyAsync(parts.data(), lp, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(grad, c->mlp_g.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  double sum = 0.0;
+  for (double v : parts) sum += v;
+  if (loss) *loss = sum / ((double)rows * kMlpOut);
+  return MBS_OK;
+}
+
+int mbs_warmstart_train(mbs_ctx* c, int64_t m, const float* feat, const float* target, int32_t epochs,
+                        int32_t batch, double lr, uint64_t seed, double* loss_hist, void* stream) {
+  CHK(begin_call(c));
+  if (m < 1 || !feat || !target) return set_err(c, MBS_EINVAL, "m >= 1, feat and target are required");
+  if (m > (int64_t)INT32_MAX / kMlpIn) return set_err(c, MBS_EINVAL, "m too large");
+  if (epochs < 0 || batch < 16 || batch > kChunkRows || !(lr > 0.0))
+    return set_err(c, MBS_EINVAL, "need epochs >= 0, 16 <= batch <= %d, lr > 0", kChunkRows);
+  if (!c->mlp_ready) return set_err(c, MBS_EUNSUPPORTED, "initialise the network first");
+  hipStream_t s = (hipStream_t)stream;
+  const int bp = ceil16(batch);
+  CHK(mlp_ensure(c, bp));
+  const int64_t nbatch = (m + batch - 1) / batch;
+  const int nbl = mlp_mse_blocks(bp);
+  CHK(ensure(c, c->mlp_loss, (size_t)nbatch * nbl + 64));
+  CHK(ensure(c, c->mlp_idx, (size_t)m / 2 + 64));
+  MlpWs ws = mlp_carve(c, bp);
+  MlpW W = mlp_weights(c);
+  int32_t* didx = (int32_t*)c->mlp_idx.p;
+  std::vector<int32_t> perm(m);
+  std::mt19937_64 gen(seed);
+  std::vector<double> parts((size_t)nbatch * nbl);
+  for (int e = 0; e < epochs; ++e) {
+    for (int64_t k = 0; k < m; ++k) perm[k] = (int32_t)k;
+    for (int64_t k = m - 1; k > 0; --k) {  // Fisher-Yates
+      std::uniform_int_distribution<int64_t> U(0, k);
+      std::swap(perm[k], perm[U(gen)]);
+    }
+    HIPCHK(c, hipMemcpyAsync(didx, perm.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemsetAsync(c->mlp_loss.p, 0, (size_t)nbatch * nbl * sizeof(double), s));
+    for (int64_t bi = 0; bi < nbatch; ++bi) {
+      const int rows = (int)std::min<int64_t>(batch, m - bi * batch);
+      const int32_t* idx = didx + bi * batch;
+      mlp_forward_rows(c, feat, idx, rows, ws, s);
+      mlp_backward_rows(c, target, idx, rows, ws, (double*)c->mlp_loss.p + bi * nbl, s);
+      mlp_adam(W.w, (const float*)c->mlp_g.p, (float*)c->mlp_m.p, (float*)c->mlp_v.p, kMlpParams,
+               (float)lr, 0.9f, 0.999f, 1e-8f, ++c->adam_step, s);
+      mlp_weights_bf16(W.w, W.W1, W.W2, W.W3, s);
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(parts.data(), c->mlp_loss.p, parts.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (double v : parts) sum += v;
+    if (loss_hist) loss_hist[e] = sum / ((double)m * kMlpOut);
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_warmstart_save(mbs_ctx* c, const char* path) {
+  CHK(begin_call(c));
+  if (!path) return set_err(c, MBS_EINVAL, "path is NULL");
+  if (!c->mlp_ready) return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context");
+  std::vector<float> w(kMlpParams);
+  HIPCHK(c, hipMemcpy(w.data(), c->mlp_w.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost));
+  FILE* f = fopen(path, "wb");
+  if (!f) return set_err(c, MBS_EINVAL, "cannot write %s", path);
+  const uint32_t hdr[3] = {0x5753424Du /* "MBSW" */, 1u, (uint32_t)kMlpParams};
+  const bool ok = fwrite(hdr, sizeof hdr, 1, f) == 1 && fwrite(w.data(), sizeof(float), kMlpParams, f) == (size_t)kMlpParams;
+  fclose(f);
+  return ok ? MBS_OK : set_err(c, MBS_EINVAL, "short write to %s", path);
+}
+
+int mbs_warmstart_load(mbs_ctx* c, const char* path) {
+  CHK(begin_call(c));
+  if (!path) return set_err(c, MBS_EINVAL, "path is NULL");
+  FILE* f = fopen(path, "rb");
+  if (!f) return set_err(c, MBS_EINVAL, "cannot read %s", path);
+  uint32_t hdr[3] = {0, 0, 0};
+  std::vector<float> w(kMlpParams);
+  const bool ok = fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == 0x5753424Du && hdr[1] == 1u &&
+                  hdr[2] == (uint32_t)kMlpParams && fread(w.data(), sizeof(float), kMlpParams, f) == (size_t)kMlpParams;
+  fclose(f);
+  if (!ok) return set_err(c, MBS_EINVAL, "%s is not a warm-start weight file", path);
+  return mbs_warmstart_set(c, w.data());
 }
 
 }  // extern "C"

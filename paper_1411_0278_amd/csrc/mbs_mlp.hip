@@ -1,0 +1,240 @@
+// Warm-start network on the matrix cores (gfx950): a 80 -> 128 -> 128 -> 5 perceptron with ReLU,
+// bfloat16 operands and float32 accumulation through v_mfma_f32_16x16x16_bf16, plus the
+// kernels of its training step (mean-squared-error gradient, ReLU masks, bias gradients, Adam).
+//
+// Matrices are row-major. Every GEMM is C[M x N] = A[M x K] B[K x N] with M, N, K multiples of 16;
+// one wavefront owns one 16 x 16 tile of C and walks K in steps of 16. MFMA operand layout (wave64):
+// lane l holds A[l % 16][4(l/16) .. 4(l/16)+3], B[4(l/16) .. 4(l/16)+3][l % 16] and returns
+// C[4(l/16) .. 4(l/16)+3][l % 16]. Long K (weight gradients, K = batch) is split over grid.z into
+// partial tiles that a second kernel adds in a fixed order, so every result is reproducible.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mbs_mlp.h"
+
+namespace mbs {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// float32 -> bfloat16, round to nearest, ties to even (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ void __launch_bounds__(64)
+    k_gemm_bf16(const uint16_t* __restrict__ A, int lda, int transA, const uint16_t* __restrict__ B,
+                int ldb, int transB, float* __restrict__ C, int M, int N, int K, int kchunk) {
+  const int lane = threadIdx.x;
+  const int n0 = blockIdx.x * 16, m0 = blockIdx.y * 16;
+  const int r = lane & 15, kb = 4 * (lane >> 4);
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
+    bf16x4 a, b;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = k0 + kb + t;
+      a[t] = (short)(transA ? A[(int64_t)k * lda + m0 + r] : A[(int64_t)(m0 + r) * lda + k]);
+      b[t] = (short)(transB ? B[(int64_t)(n0 + r) * ldb + k] : B[(int64_t)k * ldb + n0 + r]);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  float* Cz = C + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) Cz[(int64_t)(m0 + kb + t) * N + n0 + r] = acc[t];
+}
+
+__global__ void k_sum_partials(const float* __restrict__ P, int parts, int64_t len,
+                               float* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  float s = 0.f;
+  for (int p = 0; p < parts; ++p) s += P[p * len + k];
+  out[k] = s;
+}
+
+// X[r, c] = bf16(feat[idx[r], c]) for r < rows (idx NULL: identity), zero for padded rows.
+__global__ void k_gather_bf16(const float* __restrict__ feat, const int32_t* __restrict__ idx, int rows,
+                              int rows_pad, int cols, uint16_t* __restrict__ X) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)rows_pad * cols) return;
+  const int r = (int)(k / cols), c = (int)(k % cols);
+  float v = 0.f;
+  if (r < rows) v = feat[(int64_t)(idx ? idx[r] : r) * cols + c];
+  X[k] = f2bf(v);
+}
+
+// H = bf16(max(C + b, 0))
+__global__ void k_bias_relu(const float* __restrict__ C, const float* __restrict__ b, int64_t len, int N,
+                            uint16_t* __restrict__ H) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  H[k] = f2bf(fmaxf(C[k] + b[k % N], 0.f));
+}
+
+// out[r, 0:5] = C[r, 0:5] + b3
+__global__ void k_out_bias(const float* __restrict__ C, const float* __restrict__ b3, int rows,
+                           float* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)rows * kMlpOut) return;
+  const int r = (int)(k / kMlpOut), c = (int)(k % kMlpOut);
+  out[k] = C[(int64_t)r * 16 + c] + b3[c];
+}
+
+// dOut = 2 (out - T) / (count * 5) into bf16 [rows_pad x 16] (zero padding) and float32 [rows x 5];
+// loss_part[block] = sum of squared errors of the block.
+__global__ void __launch_bounds__(256)
+    k_mse_grad(const float* __restrict__ C, const float* __restrict__ b3, const float* __restrict__ T,
+               const int32_t* __restrict__ idx, int rows, int rows_pad, double scale,
+               uint16_t* __restrict__ dOut, float* __restrict__ dOut32, double* __restrict__ loss_part) {
+  __shared__ double red[256];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double sq = 0.0;
+  if (k < (int64_t)rows_pad * 16) {
+    const int r = (int)(k >> 4), c = (int)(k & 15);
+    float g = 0.f;
+    if (r < rows && c < kMlpOut) {
+      const float o = C[k] + b3[c];
+      const float t = T[(int64_t)(idx ? idx[r] : r) * kMlpOut + c];
+      const float d = o - t;
+      sq = (double)d * (double)d;
+      g = (float)(2.0 * scale) * d;
+      dOut32[(int64_t)r * kMlpOut + c] = g;
+    }
+    dOut[k] = f2bf(g);
+  }
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+// D = bf16(H > 0 ? G : 0), G32 = the float32 masked value (for the bias gradient)
+__global__ void k_relu_mask(const float* __restrict__ G, const uint16_t* __restrict__ H, int64_t len,
+                            uint16_t* __restrict__ D, float* __restrict__ G32) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  const float g = (H[k] & 0x7FFFu) != 0 && !(H[k] & 0x8000u) ? G[k] : 0.f;
+  D[k] = f2bf(g);
+  G32[k] = g;
+}
+
+// out[c] = sum_r M[r, c] (fixed order; one thread per column)
+__global__ void k_colsum(const float* __restrict__ M, int rows, int cols, float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += M[(int64_t)r * cols + c];
+  out[c] = s;
+}
+
+// copy the [rows x ldsrc] float tile's first cols columns into dst [rows x cols]
+__global__ void k_copy_cols(const float* __restrict__ src, int ldsrc, int rows, int cols,
+                            float* __restrict__ dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)rows * cols) return;
+  const int r = (int)(k / cols), c = (int)(k % cols);
+  dst[k] = src[(int64_t)r * ldsrc + c];
+}
+
+// Adam (Kingma & Ba) on the float32 master parameters, then refresh of the bf16 weight copies.
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float gk = g[k];
+  const float mk = b1 * m[k] + (1.f - b1) * gk;
+  const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+// bf16 copies: W1 [80x128], W2 [128x128], W3 [128x16] (columns 5..15 zero)
+__global__ void k_weights_bf16(const float* __restrict__ w, uint16_t* __restrict__ W1,
+                               uint16_t* __restrict__ W2, uint16_t* __restrict__ W3) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < kMlpIn * kMlpHid) W1[k] = f2bf(w[kOffW1 + k]);
+  if (k < kMlpHid * kMlpHid) W2[k] = f2bf(w[kOffW2 + k]);
+  if (k < kMlpHid * 16) {
+    const int r = k >> 4, c = k & 15;
+    W3[k] = c < kMlpOut ? f2bf(w[kOffW3 + r * kMlpOut + c]) : (uint16_t)0;
+  }
+}
+
+inline unsigned nblk(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
+
+}  // namespace
+
+void mlp_gemm(const uint16_t* A, int lda, bool tA, const uint16_t* B, int ldb, bool tB, float* C,
+              float* partial, int M, int N, int K, int ksplit, hipStream_t s) {
+  const int kchunk = ((K / 16 + ksplit - 1) / ksplit) * 16;
+  const int parts = (K + kchunk - 1) / kchunk;
+  float* out = parts > 1 ? partial : C;
+  hipLaunchKernelGGL(k_gemm_bf16, dim3(N / 16, M / 16, parts), dim3(64), 0, s, A, lda, (int)tA, B, ldb,
+                     (int)tB, out, M, N, K, kchunk);
+  if (parts > 1)
+    hipLaunchKernelGGL(k_sum_partials, dim3(nblk((int64_t)M * N, 256)), dim3(256), 0, s, partial,
+                       parts, (int64_t)M * N, C);
+}
+
+void mlp_gather_bf16(const float* feat, const int32_t* idx, int rows, int rows_pad, int cols,
+                     uint16_t* X, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_bf16, dim3(nblk((int64_t)rows_pad * cols, 256)), dim3(256), 0, s, feat,
+                     idx, rows, rows_pad, cols, X);
+}
+
+void mlp_bias_relu(const float* C, const float* b, int rows_pad, int N, uint16_t* H, hipStream_t s) {
+  const int64_t len = (int64_t)rows_pad * N;
+  hipLaunchKernelGGL(k_bias_relu, dim3(nblk(len, 256)), dim3(256), 0, s, C, b, len, N, H);
+}
+
+void mlp_out_bias(const float* C, const float* b3, int rows, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_out_bias, dim3(nblk((int64_t)rows * kMlpOut, 256)), dim3(256), 0, s, C, b3,
+                     rows, out);
+}
+
+int mlp_mse_blocks(int rows_pad) { return (int)nblk((int64_t)rows_pad * 16, 256); }
+
+void mlp_mse_grad(const float* C, const float* b3, const float* T, const int32_t* idx, int rows,
+                  int rows_pad, double scale, uint16_t* dOut, float* dOut32, double* loss_part,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_mse_grad, dim3(mlp_mse_blocks(rows_pad)), dim3(256), 0, s, C, b3, T, idx, rows,
+                     rows_pad, scale, dOut, dOut32, loss_part);
+}
+
+void mlp_relu_mask(const float* G, const uint16_t* H, int64_t len, uint16_t* D, float* G32,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_relu_mask, dim3(nblk(len, 256)), dim3(256), 0, s, G, H, len, D, G32);
+}
+
+void mlp_colsum(const float* M, int rows, int cols, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum, dim3(nblk(cols, 64)), dim3(64), 0, s, M, rows, cols, out);
+}
+
+void mlp_copy_cols(const float* src, int ldsrc, int rows, int cols, float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_cols, dim3(nblk((int64_t)rows * cols, 256)), dim3(256), 0, s, src, ldsrc,
+                     rows, cols, dst);
+}
+
+void mlp_adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
+              float eps, int step, hipStream_t s) {
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+void mlp_weights_bf16(const float* w, uint16_t* W1, uint16_t* W2, uint16_t* W3, hipStream_t s) {
+  hipLaunchKernelGGL(k_weights_bf16, dim3(nblk(kMlpHid * kMlpHid, 256)), dim3(256), 0, s, w, W1, W2, W3);
+}
+
+}  // namespace mbs

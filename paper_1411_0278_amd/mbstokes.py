@@ -22,7 +22,10 @@ MBS_GUESS_ZERO, MBS_GUESS_DIAG, MBS_GUESS_LEARNED, MBS_GUESS_USER = 0, 1, 2, 3
 
 EXPORTS = ("mbs_default_params", "mbs_create", "mbs_destroy", "mbs_set_params", "mbs_last_error",
            "mbs_solve", "mbs_matvec", "mbs_rhs", "mbs_outputs", "mbs_step", "mbs_solve_batched",
-           "mbs_autotune")
+           "mbs_autotune", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
+           "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
+           "mbs_warmstart_load")
+MLP_NPARAM, MLP_NFEAT = 27525, 80
 
 
 class MbsError(RuntimeError):
@@ -91,6 +94,21 @@ def load(path: str = LIB_PATH):
     lib.mbs_solve_batched.restype = ctypes.c_int
     lib.mbs_autotune.argtypes = [P, I64, P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32), VP]
     lib.mbs_autotune.restype = ctypes.c_int
+    FP = ctypes.POINTER(ctypes.c_float)
+    lib.mbs_features.argtypes = [P, I64, P, P, P, P, VP]
+    lib.mbs_warmstart_init.argtypes = [P, ctypes.c_uint64]
+    lib.mbs_warmstart_set.argtypes = [P, FP]
+    lib.mbs_warmstart_get.argtypes = [P, FP]
+    lib.mbs_warmstart_forward.argtypes = [P, I64, P, P, VP]
+    lib.mbs_warmstart_grad.argtypes = [P, I64, P, P, FP, ctypes.POINTER(ctypes.c_double), VP]
+    lib.mbs_warmstart_train.argtypes = [P, I64, P, P, I32, I32, D, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_double), VP]
+    lib.mbs_warmstart_save.argtypes = [P, ctypes.c_char_p]
+    lib.mbs_warmstart_load.argtypes = [P, ctypes.c_char_p]
+    for name in ("mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
+                 "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
+                 "mbs_warmstart_load"):
+        getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -106,13 +124,14 @@ def default_params(**kw) -> Params:
     return p
 
 
-def _ptr(t, n=None, width=None, name="array"):
-    """Device pointer of a float64 CUDA tensor (None -> NULL), with shape checks."""
+def _ptr(t, n=None, width=None, name="array", dtype=None):
+    """Device pointer of a CUDA tensor (None -> NULL), with dtype and shape checks (float64 default)."""
     if t is None:
         return None
     import torch
-    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
-        raise TypeError(f"{name}: expected a torch.float64 CUDA tensor")
+    dtype = dtype or torch.float64
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda:
+        raise TypeError(f"{name}: expected a {dtype} CUDA tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name}: must be contiguous")
     if n is not None and width is not None and tuple(t.shape) != (n, width):
@@ -251,6 +270,87 @@ def _autotune(self, R, cache_json=None):
 
 
 Context.mbs_autotune = _autotune
+
+
+def _features(self, R, p, want_nbr=False):
+    import torch
+    n = R.shape[0]
+    feat = torch.empty((n, MLP_NFEAT), dtype=torch.float32, device=R.device)
+    nbr = torch.empty((n, 16), dtype=torch.int32, device=R.device) if want_nbr else None
+    self._check(self.lib.mbs_features(self.h, n, _ptr(R, n, 3, "R"), _ptr(p, n, 3, "p"),
+                                      _ptr(feat, n, MLP_NFEAT, "feat", torch.float32),
+                                      _ptr(nbr, n, 16, "nbr", torch.int32), _stream()))
+    return (feat, nbr) if want_nbr else feat
+
+
+def _ws_init(self, seed=0):
+    self._check(self.lib.mbs_warmstart_init(self.h, int(seed)))
+
+
+def _ws_set(self, params):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    if a.size != MLP_NPARAM:
+        raise ValueError(f"expected {MLP_NPARAM} parameters")
+    self._check(self.lib.mbs_warmstart_set(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+
+def _ws_get(self):
+    import numpy as np
+    a = np.empty(MLP_NPARAM, dtype=np.float32)
+    self._check(self.lib.mbs_warmstart_get(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return a
+
+
+def _ws_forward(self, feat):
+    import torch
+    m = feat.shape[0]
+    out = torch.empty((m, 5), dtype=torch.float32, device=feat.device)
+    self._check(self.lib.mbs_warmstart_forward(self.h, m, _ptr(feat, m, MLP_NFEAT, "feat", torch.float32),
+                                               _ptr(out, m, 5, "out", torch.float32), _stream()))
+    return out
+
+
+def _ws_grad(self, feat, target):
+    import numpy as np
+    import torch
+    m = feat.shape[0]
+    g = np.empty(MLP_NPARAM, dtype=np.float32)
+    loss = ctypes.c_double()
+    self._check(self.lib.mbs_warmstart_grad(self.h, m, _ptr(feat, m, MLP_NFEAT, "feat", torch.float32),
+                                            _ptr(target, m, 5, "target", torch.float32),
+                                            g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                            ctypes.byref(loss), _stream()))
+    return loss.value, g
+
+
+def _ws_train(self, feat, target, epochs, batch=4096, lr=1e-3, seed=0):
+    import torch
+    m = feat.shape[0]
+    hist = (ctypes.c_double * max(epochs, 1))()
+    self._check(self.lib.mbs_warmstart_train(self.h, m, _ptr(feat, m, MLP_NFEAT, "feat", torch.float32),
+                                             _ptr(target, m, 5, "target", torch.float32), int(epochs),
+                                             int(batch), float(lr), int(seed), hist, _stream()))
+    return list(hist)[:epochs]
+
+
+def _ws_save(self, path):
+    self._check(self.lib.mbs_warmstart_save(self.h, str(path).encode()))
+
+
+def _ws_load(self, path):
+    self._check(self.lib.mbs_warmstart_load(self.h, str(path).encode()))
+
+
+Context.mbs_features = _features
+Context.mbs_warmstart_init = _ws_init
+Context.mbs_warmstart_set = _ws_set
+Context.mbs_warmstart_get = _ws_get
+Context.mbs_warmstart_forward = _ws_forward
+Context.mbs_warmstart_grad = _ws_grad
+Context.mbs_warmstart_train = _ws_train
+Context.mbs_warmstart_save = _ws_save
+Context.mbs_warmstart_load = _ws_load
 
 
 def to_device(w, device="cuda"):

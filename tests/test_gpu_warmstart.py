@@ -1,0 +1,123 @@
+"""Learned warm start on the GPU against the CPU oracle (oracle/mlp.py).
+
+Tolerances:
+* neighbour lists: identical (ties by index on both sides); features: float32 rounding of
+  binary64 values, 1e-6 relative.
+* forward: both sides round inputs, weights and hidden activations to bfloat16; the GPU sums
+  float32, the oracle float64, so an activation that lies within a float32 rounding of a bfloat16
+  rounding boundary can round to the neighbouring bfloat16 value (one bfloat16 ulp, 2^-8
+  relative) on one side only. This is rare and bounded: 2e-3 normwise relative.
+* gradient: every backward product also takes bfloat16 operands on the GPU (deltas rounded,
+  2^-9 relative each, three layers deep), the oracle keeps float64 deltas: 2e-2 normwise
+  relative per parameter block.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import galerkin, mlp  # noqa: E402
+from paper_1411_0278_amd import inputs, mbstokes  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mbstokes.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("n", [17, 300, 1500])
+def test_features_match_oracle(ctx, n):
+    print(f"features n={n}", flush=True)
+    w = inputs.trap_workload(n, (n / 0.004) ** (1 / 3) + 8, seed=700 + n)
+    R = torch.as_tensor(w.R).to(DEV)
+    p = torch.as_tensor(w.p).to(DEV)
+    feat, nbr = ctx.mbs_features(R, p, want_nbr=True)
+    f_or, nb_or = mlp.features(w.R, w.p)
+    assert np.array_equal(nbr.cpu().numpy(), nb_or)
+    assert np.abs(feat.cpu().numpy() - f_or).max() <= 1e-6 * np.abs(f_or).max()
+
+
+def _random_params(seed):
+    rng = np.random.default_rng(seed)
+    P = {}
+    for name, shp in mlp.SHAPES:
+        fan = shp[0] if len(shp) == 2 else 1
+        P[name] = rng.uniform(-1, 1, size=shp) * (np.sqrt(6.0 / fan) if len(shp) == 2 else 0.1)
+    return mlp.pack(P).astype(np.float32)
+
+
+def test_forward_matches_oracle(ctx):
+    flat = _random_params(1)
+    ctx.mbs_warmstart_set(flat)
+    assert np.array_equal(ctx.mbs_warmstart_get(), flat)
+    X = np.random.default_rng(2).standard_normal((1000, 80)).astype(np.float32)
+    out = ctx.mbs_warmstart_forward(torch.as_tensor(X).to(DEV)).cpu().numpy()
+    want, _ = mlp.forward(flat.astype(np.float64), X)
+    assert _rel(out, want) < 2e-3
+
+
+def test_forward_large_batch_chunks(ctx):
+    flat = _random_params(3)
+    ctx.mbs_warmstart_set(flat)
+    X = np.random.default_rng(4).standard_normal((70001, 80)).astype(np.float32)
+    out = ctx.mbs_warmstart_forward(torch.as_tensor(X).to(DEV)).cpu().numpy()
+    rows = np.r_[0:5, 65530:65545, 69990:70001]
+    want, _ = mlp.forward(flat.astype(np.float64), X[rows])
+    assert _rel(out[rows], want) < 2e-3
+
+
+def test_gradient_matches_oracle(ctx):
+    flat = _random_params(5)
+    ctx.mbs_warmstart_set(flat)
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((999, 80)).astype(np.float32)
+    T = rng.standard_normal((999, 5)).astype(np.float32)
+    loss, g = ctx.mbs_warmstart_grad(torch.as_tensor(X).to(DEV), torch.as_tensor(T).to(DEV))
+    l_or, g_or = mlp.loss_grad(flat.astype(np.float64), X, T.astype(np.float64))
+    assert abs(loss - l_or) <= 2e-3 * l_or
+    off = 0
+    for name, shp in mlp.SHAPES:
+        sz = int(np.prod(shp))
+        assert _rel(g[off:off + sz], g_or[off:off + sz]) < 2e-2, name
+        off += sz
+
+
+def test_training_reduces_loss_and_is_reproducible(ctx, tmp_path):
+    rng = np.random.default_rng(7)
+    teacher = _random_params(8)
+    X = rng.standard_normal((20000, 80)).astype(np.float32)
+    T, _ = mlp.forward(teacher.astype(np.float64), X, quantize=False)
+    Xd, Td = torch.as_tensor(X).to(DEV), torch.as_tensor(T.astype(np.float32)).to(DEV)
+    res = []
+    for _ in range(2):
+        ctx.mbs_warmstart_init(11)
+        hist = ctx.mbs_warmstart_train(Xd, Td, epochs=8, batch=1000, lr=2e-3, seed=5)
+        res.append((hist, ctx.mbs_warmstart_get()))
+    assert res[0][0] == res[1][0] and np.array_equal(res[0][1], res[1][1])
+    hist = res[0][0]
+    assert hist[-1] < 0.5 * hist[0], hist
+    path = tmp_path / "w.bin"
+    ctx.mbs_warmstart_save(path)
+    ctx.mbs_warmstart_init(0)
+    ctx.mbs_warmstart_load(path)
+    assert np.array_equal(ctx.mbs_warmstart_get(), res[0][1])
+
+
+def test_learned_guess_solve_matches_oracle(ctx):
+    w = inputs.trap_workload(200, 40.0 * (200 / 256) ** (1 / 3), seed=9)
+    ref = galerkin.solve(w)
+    ctx.mbs_warmstart_set(_random_params(10) * 0.05)
+    ctx.set_params(tol=1e-12, guess=mbstokes.MBS_GUESS_LEARNED)
+    d = mbstokes.to_device(w, DEV)
+    V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
+    ctx.set_params(tol=1e-10, guess=mbstokes.MBS_GUESS_ZERO)
+    assert _rel(V.cpu().numpy(), ref["V"]) < 1e-10 and _rel(S.cpu().numpy(), ref["S"]) < 1e-10

@@ -321,3 +321,56 @@ def test_diametrically_opposite_active_pair_does_not_rotate():
     w = inputs.Workload(R, p, v1s, v2s, v3t, -k * R, np.zeros((2, 3)), ETA, A)
     sol = galerkin.solve(w, PRM)
     assert np.abs(sol["W"]).max() < 1e-15
+
+
+# ---------------------------------------------------------------- warm-start network and features
+def test_bf16_rounding_is_round_to_nearest_even():
+    """bfloat16 keeps 8 significant bits: the spacing just above 1 is 2^-7."""
+    from oracle import mlp
+    v = np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 3 * 2 ** -9, 1.0 + 2 ** -9, -2.5, 3.0e-3])
+    got = mlp.bf16(v)
+    assert got[0] == 1.0                      # tie between 1 and 1 + 2^-7: the even mantissa (1)
+    assert got[1] == 1.0 + 2 ** -6            # tie between 1 + 2^-7 and 1 + 2^-6: the even one
+    assert got[2] == 1.0 + 2 ** -7            # nearer to 1 + 2^-7
+    assert got[3] == 1.0                      # nearer to 1
+    assert got[4] == -2.5
+    assert abs(got[5] - 3.0e-3) <= 3.0e-3 * 2 ** -8
+
+
+def test_mlp_gradient_matches_finite_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(0)
+    flat = rng.standard_normal(mlp.N_PARAM) * 0.2
+    X = rng.standard_normal((7, mlp.N_IN))
+    T = rng.standard_normal((7, mlp.N_OUT))
+    loss, g = mlp.loss_grad(flat, X, T, quantize=False)
+    idx = rng.choice(mlp.N_PARAM, 60, replace=False)
+    h = 1e-6
+    for k in idx:
+        e = np.zeros(mlp.N_PARAM)
+        e[k] = h
+        fd = (mlp.loss_grad(flat + e, X, T, quantize=False)[0] - mlp.loss_grad(flat - e, X, T, quantize=False)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])) + 1e-9, (k, fd, g[k])
+
+
+def test_mlp_parameter_count_and_shapes():
+    from oracle import mlp
+    assert mlp.N_PARAM == 80 * 128 + 128 + 128 * 128 + 128 + 128 * 5 + 5 == 27525
+    flat = np.arange(mlp.N_PARAM, dtype=float)
+    assert np.array_equal(mlp.pack(mlp.unpack(flat)), flat)
+
+
+def test_knn_and_features_brute_force():
+    from oracle import mlp
+    rng = np.random.default_rng(3)
+    R = rng.uniform(-5, 5, size=(40, 3))
+    p = rng.standard_normal((40, 3))
+    p /= np.linalg.norm(p, axis=1, keepdims=True)
+    f, nb = mlp.features(R, p)
+    for i in (0, 17, 39):
+        d = [(np.sum((R[j] - R[i]) ** 2), j) for j in range(40) if j != i]
+        d.sort()
+        assert [j for _, j in d[:16]] == list(nb[i])
+        j = nb[i, 0]
+        r = np.linalg.norm(R[j] - R[i])
+        assert np.allclose(f[i, :5], list((R[j] - R[i]) / r) + [1 / r, p[j] @ p[i]], rtol=1e-15)
