@@ -83,7 +83,8 @@ typedef struct mbs_params {
   int32_t check_overlap; /* nonzero: mbs_solve fails with MBS_EOVERLAP if some |R_n - R_m| < 2a */
   int32_t tile;          /* pair-kernel launch shape: 0 = autotuned (or default), k > 0 = entry k-1
                             of the candidate table (see mbs_autotune) */
-  int32_t reserved;
+  int32_t graph;         /* mbs_solve_batched: 1 = capture its phases in HIP graphs and replay them
+                            (default), 0 = launch the same kernels directly */
 } mbs_params;
 
 typedef struct mbs_stats {
@@ -104,7 +105,8 @@ typedef struct mbs_stats {
 typedef struct mbs_ctx mbs_ctx;
 
 /* Fill *prm with the defaults: eta = 1/(6 pi), a = 1, tol = 1e-10, c = 1, inner_tol = 1e-5,
-   lmax = 2, max_iter = 300, restart = 30, MBS_FP64, MBS_GUESS_ZERO, no overlap check. */
+   lmax = 2, max_iter = 300, restart = 30, MBS_FP64, MBS_GUESS_ZERO, no overlap check, tile 0,
+   graph 1. */
 void mbs_default_params(mbs_params* prm);
 
 /* Create a context on HIP device `device`. *ctx receives the handle (NULL on failure).
@@ -162,11 +164,18 @@ int mbs_step(mbs_ctx* ctx, int64_t n, double* R, double* p, double k_trap, const
              double dt, int32_t nsteps, int32_t order, mbs_stats* per_step, double* min_dist,
              void* stream);
 
-/* Many independent configurations in one call. Configuration b owns rows
-   offsets[b] .. offsets[b+1]-1 of the concatenated device arrays (same meaning as in
-   mbs_solve; sigma0 and p are ignored). offsets: HOST array [nconf + 1], offsets[0] = 0,
-   strictly increasing. per_conf: host array [nconf] or NULL. latency_ms: host array [nconf] or
-   NULL, receives the time from the start of the call to the completion of each configuration. */
+/* Many independent configurations in one call (binary64, zero initial guess). Configuration b owns
+   rows offsets[b] .. offsets[b+1]-1 of the concatenated device arrays (same meaning as in mbs_solve).
+   offsets: HOST array [nconf + 1], offsets[0] = 0, strictly increasing. All configurations advance
+   together: each pass (right-hand side, operator, Gram-Schmidt, Givens, outputs) is one launch over
+   every configuration, decomposed into (configuration, 64-receiver tile) work items; converged
+   configurations drop out of later passes. With params.graph the phases are captured once per batch
+   shape into HIP graphs on a stream owned by the context and replayed (the iteration graph holds
+   four Arnoldi steps); the call synchronises with `stream` on entry and exit.
+   per_conf: host [nconf] or NULL (iters, rel_resid, pair_blocks, t_total_ms of the whole batch).
+   latency_ms: host [nconf] or NULL: time from the start of the batch to the device clock reading
+   taken when the configuration's true residual met the tolerance. Returns MBS_ENOCONV if some
+   configuration did not converge (outputs are still written). */
 int mbs_solve_batched(mbs_ctx* ctx, int32_t nconf, const int64_t* offsets, const double* R,
                       const double* v1s, const double* v2s, const double* v3t, const double* Fe,
                       const double* Te, double* V, double* W, double* S, double* Sigma,

@@ -9,12 +9,14 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <vector>
 
 #include <random>
 
 #include "../../include/mbstokes.h"
+#include "mbs_batched.h"
 #include "mbs_internal.h"
 #include "mbs_mlp.h"
 
@@ -56,6 +58,11 @@ struct mbs_ctx {
   bool mlp_ready = false;
   int adam_step = 0;
   DevBuf mlp_w, mlp_g, mlp_m, mlp_v, mlp_wb, mlp_ws, mlp_part, mlp_loss, mlp_idx, knn_buf;
+  // batched solver: workspace, capture stream and the four graphs of the last batch shape
+  DevBuf bat;
+  hipStream_t bstream = nullptr;
+  hipGraphExec_t bgraph[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<uintptr_t> bkey;
 };
 
 namespace {
@@ -610,6 +617,7 @@ void mbs_default_params(mbs_params* p) {
   p->guess = MBS_GUESS_ZERO;
   p->check_overlap = 0;
   p->tile = 0;
+  p->graph = 1;
 }
 
 int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {
@@ -652,9 +660,12 @@ void mbs_destroy(mbs_ctx* c) {
   DevBuf* bufs[] = {&c->V, &c->w, &c->r, &c->b, &c->xs, &c->dlt, &c->part, &c->dpart,
                     &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
-                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf};
+                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->bat};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
+  for (auto& g : c->bgraph)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (c->bstream) (void)hipStreamDestroy(c->bstream);
   if (c->d_count) (void)hipFree(c->d_count);
   if (c->h_status) (void)hipHostFree(c->h_status);
   for (auto& e : c->ev)
@@ -833,37 +844,234 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   for (int b = 0; b < nconf; ++b)
     if (offsets[b + 1] <= offsets[b]) return set_err(c, MBS_EINVAL, "offsets must increase");
   if (!R || !V || !W || !S) return set_err(c, MBS_EINVAL, "R, V, W and S are required");
+  const int64_t ntot64 = offsets[nconf];
+  if (ntot64 > (int64_t)INT32_MAX / 20) return set_err(c, MBS_EINVAL, "too many spheres in the batch");
+  const int ntot = (int)ntot64;
   hipStream_t s = (hipStream_t)stream;
-  const int64_t ntot = offsets[nconf];
   int bad = 0;
-  CHK(ensure_ws(c, std::min<int64_t>(ntot, 1 << 20)));
-  CHK(count_nonfinite(c, s, {{R, 3 * ntot}, {v1s, 3 * ntot}, {v2s, 5 * ntot}, {v3t, 3 * ntot},
-                             {Fe, 3 * ntot}, {Te, 3 * ntot}},
+  CHK(ensure_ws(c, 16));
+  CHK(count_nonfinite(c, s, {{R, 3 * ntot64}, {v1s, 3 * ntot64}, {v2s, 5 * ntot64}, {v3t, 3 * ntot64},
+                             {Fe, 3 * ntot64}, {Te, 3 * ntot64}},
                       &bad));
   if (bad) return set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
-  const int guess0 = c->prm.guess;
-  if (guess0 == MBS_GUESS_USER) c->prm.guess = MBS_GUESS_ZERO;
-  if (guess0 == MBS_GUESS_LEARNED) c->prm.guess = MBS_GUESS_DIAG;  // no orientations in this call
-  hipEvent_t t0 = c->ev[4], t1 = c->ev[5];
-  HIPCHK(c, hipEventRecord(t0, s));
+  if (c->prm.precision != MBS_FP64)
+    return set_err(c, MBS_EUNSUPPORTED, "batched solves run in binary64 only");
+  // host descriptors: configuration offsets, work items (configuration, 64-receiver tile), owner map
+  const int m = c->prm.restart;
+  std::vector<int> off(nconf + 1), cid(ntot);
+  std::vector<int2> items;
+  for (int b = 0; b <= nconf; ++b) off[b] = (int)offsets[b];
+  for (int b = 0; b < nconf; ++b) {
+    for (int r = off[b]; r < off[b + 1]; r += 64) items.push_back(make_int2(b, r));
+    for (int r = off[b]; r < off[b + 1]; ++r) cid[r] = b;
+  }
+  const int nitems = (int)items.size();
+  // workspace (bytes, 256-aligned pieces)
+  const int64_t len = 5 * ntot64;
+  const int hs = m + 2;
+  size_t bytes = 0;
+  auto reserve = [&](size_t b) { size_t o = bytes; bytes += align256(b); return o; };
+  const size_t oV = reserve((size_t)(m + 1) * len * 8), ow = reserve(len * 8), ox = reserve(len * 8),
+               ob = reserve(len * 8), orr = reserve(len * 8), orec = reserve((size_t)ntot * sizeof(RecO)),
+               oH = reserve((size_t)nconf * (m + 1) * (m + 1) * 8);
+  size_t osm[7];
+  for (int k = 0; k < 7; ++k) osm[k] = reserve((size_t)nconf * hs * 8);  // cs sn g y h1 h2 spare
+  const size_t onsq = reserve(nconf * 8), obn = reserve(nconf * 8), ohk = reserve(nconf * 8),
+               ores = reserve(nconf * 8), ost = reserve(nconf * 4), oke = reserve(nconf * 4),
+               oit = reserve(nconf * 4), ot0 = reserve(nconf * 8), ot1 = reserve(nconf * 8),
+               okd = reserve(16), ocnt = reserve(16), ooff = reserve((nconf + 1) * 4),
+               oitems = reserve((size_t)nitems * 8), ocid = reserve((size_t)ntot * 4);
+  CHK(ensure(c, c->bat, bytes / 8 + 64));
+  char* base = (char*)c->bat.p;
+  double* Vb = (double*)(base + oV);
+  double *wv = (double*)(base + ow), *xv = (double*)(base + ox), *bv = (double*)(base + ob),
+         *rv = (double*)(base + orr);
+  void* rec = base + orec;
+  BatchState st;
+  st.H = (double*)(base + oH);
+  st.cs = (double*)(base + osm[0]);
+  st.sn = (double*)(base + osm[1]);
+  st.g = (double*)(base + osm[2]);
+  st.y = (double*)(base + osm[3]);
+  st.h1 = (double*)(base + osm[4]);
+  st.h2 = (double*)(base + osm[5]);
+  st.nsq = (double*)(base + onsq);
+  st.bnorm = (double*)(base + obn);
+  st.hk1 = (double*)(base + ohk);
+  st.resid = (double*)(base + ores);
+  st.status = (int*)(base + ost);
+  st.kend = (int*)(base + oke);
+  st.iters = (int*)(base + oit);
+  st.t0 = (unsigned long long*)(base + ot0);
+  st.t1 = (unsigned long long*)(base + ot1);
+  int* kdev = (int*)(base + okd);
+  int* dcnt = (int*)(base + ocnt);
+  int* doff = (int*)(base + ooff);
+  int2* ditems = (int2*)(base + oitems);
+  int* dcid = (int*)(base + ocid);
+  HIPCHK(c, hipMemcpyAsync(doff, off.data(), (nconf + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(ditems, items.data(), nitems * sizeof(int2), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(dcid, cid.data(), ntot * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!c->bstream) HIPCHK(c, hipStreamCreateWithFlags(&c->bstream, hipStreamNonBlocking));
+  hipStream_t bs = c->bstream;
+  // the batch stream waits for the caller's stream (uploads above, caller's producers)
+  HIPCHK(c, hipEventRecord(c->ev[4], s));
+  HIPCHK(c, hipStreamWaitEvent(bs, c->ev[4], 0));
+  const Phys ph = c->ph;
+  const double tol = c->prm.tol;
+  const int max_iter = c->prm.max_iter;
+  const int C = 4;  // Arnoldi steps per replay of the iteration graph
+  const bool has_t = Te != nullptr, has_d = v3t != nullptr;
+  // the four phases
+  auto phase_init = [&](hipStream_t q) {
+    batched_set_ints(st.status, nconf, kActive, q);
+    batched_pack_f(R, Fe, Te, v3t, ph, (RecF*)rec, ntot, q);
+    batched_p1(ditems, nitems, doff, (const RecF*)rec, v2s, has_t, has_d, ph, bv, q);
+    batched_fill(xv, 0.0, len, q);
+    batched_dots(bv, 0, nullptr, 1, bv, doff, st.status, kActive, st.nsq, 1, nconf, q);
+    batched_init(st, nconf, m, q);
+    batched_start(bv, st.hk1, dcid, st.status, kActive, Vb, len, q);
+    batched_set_int(kdev, 0, q);
+  };
+  auto phase_iter = [&](hipStream_t q) {
+    for (int it = 0; it < C; ++it) {
+      batched_pack_s(R, Vb, kdev, m - 1, len, (Src8<double>*)rec, ntot, q);
+      batched_p2(ditems, nitems, doff, st.status, kActive, (const Src8<double>*)rec, Vb, kdev, len, ph, wv, q);
+      batched_dots(Vb, len, kdev, 0, wv, doff, st.status, kActive, st.h1, hs, nconf, q);
+      batched_axpy(Vb, len, kdev, nullptr, 0, st.h1, hs, -1.0, dcid, st.status, kActive, wv, len, q);
+      batched_dots(Vb, len, kdev, 0, wv, doff, st.status, kActive, st.h2, hs, nconf, q);
+      batched_axpy(Vb, len, kdev, nullptr, 0, st.h2, hs, -1.0, dcid, st.status, kActive, wv, len, q);
+      batched_dots(wv, 0, nullptr, 1, wv, doff, st.status, kActive, st.nsq, 1, nconf, q);
+      batched_givens(st, nconf, m, kdev, tol, max_iter, q);
+      batched_scale(wv, st.hk1, dcid, st.status, Vb, len, kdev, len, q);
+      batched_inc(kdev, q);
+    }
+    batched_count(st.status, nconf, kActive, dcnt, q);
+  };
+  auto phase_fin = [&](hipStream_t q) {
+    batched_backsolve(st, nconf, m, q);
+    batched_axpy(Vb, len, nullptr, st.kend, 0, st.y, hs, 1.0, dcid, st.status, kCycleDone, xv, len, q);
+    batched_pack_s(R, xv, nullptr, 0, 0, (Src8<double>*)rec, ntot, q);
+    batched_p2(ditems, nitems, doff, st.status, kCycleDone, (const Src8<double>*)rec, xv, nullptr, 0, ph,
+               wv, q);
+    batched_resid(bv, wv, dcid, st.status, rv, len, q);
+    batched_dots(rv, 0, nullptr, 1, rv, doff, st.status, kCycleDone, st.nsq, 1, nconf, q);
+    batched_check(st, nconf, m, tol, max_iter, q);
+    batched_start(rv, st.hk1, dcid, st.status, kActive, Vb, len, q);
+    batched_set_int(kdev, 0, q);
+    batched_count(st.status, nconf, kActive, dcnt, q);
+  };
+  auto phase_out = [&](hipStream_t q) {
+    batched_pack_o(R, Fe, Te, xv, v3t, ph, (RecO*)rec, ntot, q);
+    batched_p3(ditems, nitems, doff, (const RecO*)rec, has_t, has_d, ph, v1s, v2s, Fe, Te, xv, V, W, S,
+               Sigma, q);
+  };
+  // graphs: captured once per batch shape (pointers and sizes), replayed afterwards
+  const bool use_graph = c->prm.graph != 0;
+  if (use_graph) {
+    std::vector<uintptr_t> key = {(uintptr_t)nconf, (uintptr_t)ntot, (uintptr_t)base, (uintptr_t)R,
+                                  (uintptr_t)v1s, (uintptr_t)v2s, (uintptr_t)v3t, (uintptr_t)Fe,
+                                  (uintptr_t)Te, (uintptr_t)V, (uintptr_t)W, (uintptr_t)S,
+                                  (uintptr_t)Sigma, (uintptr_t)m, (uintptr_t)max_iter};
+    double tolc = tol;
+    uintptr_t tb;
+    memcpy(&tb, &tolc, sizeof tb);
+    key.push_back(tb);
+    double cs_ = ph.c_slip, eta_ = ph.eta, a_ = ph.a;
+    memcpy(&tb, &cs_, sizeof tb);
+    key.push_back(tb);
+    memcpy(&tb, &eta_, sizeof tb);
+    key.push_back(tb);
+    memcpy(&tb, &a_, sizeof tb);
+    key.push_back(tb);
+    if (key != c->bkey || !c->bgraph[0]) {
+      for (auto& g : c->bgraph)
+        if (g) {
+          (void)hipGraphExecDestroy(g);
+          g = nullptr;
+        }
+      c->bkey.clear();
+      std::function<void(hipStream_t)> phases[4] = {phase_init, phase_iter, phase_fin, phase_out};
+      for (int k = 0; k < 4; ++k) {
+        hipGraph_t g = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal));
+        phases[k](bs);
+        HIPCHK(c, hipStreamEndCapture(bs, &g));
+        hipError_t e = hipGraphInstantiate(&c->bgraph[k], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return set_err(c, MBS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      }
+      c->bkey = key;
+    }
+  }
+  auto run = [&](int k) -> int {
+    if (use_graph) {
+      HIPCHK(c, hipGraphLaunch(c->bgraph[k], bs));
+    } else {
+      if (k == 0) phase_init(bs);
+      if (k == 1) phase_iter(bs);
+      if (k == 2) phase_fin(bs);
+      if (k == 3) phase_out(bs);
+      HIPCHK(c, hipGetLastError());
+    }
+    return MBS_OK;
+  };
+  auto active = [&](int* out) -> int {
+    HIPCHK(c, hipMemcpyAsync(out, dcnt, sizeof(int), hipMemcpyDeviceToHost, bs));
+    HIPCHK(c, hipStreamSynchronize(bs));
+    return MBS_OK;
+  };
+  HIPCHK(c, hipEventRecord(c->ev[5], bs));
+  CHK(run(0));
+  const int max_replays = max_iter / C + 2 * (max_iter / std::max(1, m) + 2);
+  int replays = 0, nact = 1;
+  while (nact > 0 && replays < max_replays) {
+    int inner = 1;
+    while (inner > 0 && replays < max_replays) {
+      CHK(run(1));
+      ++replays;
+      CHK(active(&inner));
+    }
+    CHK(run(2));
+    CHK(active(&nact));
+  }
+  CHK(run(3));
+  HIPCHK(c, hipEventRecord(c->ev[6], bs));
+  HIPCHK(c, hipStreamSynchronize(bs));
+  // per-configuration results
+  std::vector<int> its(nconf), status(nconf);
+  std::vector<double> res(nconf);
+  std::vector<unsigned long long> t0(nconf), t1(nconf);
+  HIPCHK(c, hipMemcpy(its.data(), st.iters, nconf * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(status.data(), st.status, nconf * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(res.data(), st.resid, nconf * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(t0.data(), st.t0, nconf * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(t1.data(), st.t1, nconf * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  int rate_khz = 0;
+  HIPCHK(c, hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
+  unsigned long long tmin = ~0ull;
+  for (int b = 0; b < nconf; ++b) tmin = std::min(tmin, t0[b]);
+  const double total_ms = ev_ms(c->ev[5], c->ev[6]);
   int rc = MBS_OK;
   for (int b = 0; b < nconf; ++b) {
-    const int64_t o = offsets[b], nb = offsets[b + 1] - offsets[b];
-    mbs_stats one{};
-    int r1 = solve_core(c, nb, R + 3 * o, nullptr, v1s ? v1s + 3 * o : nullptr, v2s ? v2s + 5 * o : nullptr,
-                        v3t ? v3t + 3 * o : nullptr, Fe ? Fe + 3 * o : nullptr,
-                        Te ? Te + 3 * o : nullptr, nullptr, V + 3 * o, W + 3 * o, S + 5 * o,
-                        Sigma ? Sigma + 5 * o : nullptr, &one, s);
-    if (per_conf) per_conf[b] = one;
-    if (latency_ms) {
-      (void)hipEventRecord(t1, s);
-      (void)hipEventSynchronize(t1);
-      latency_ms[b] = ev_ms(t0, t1);
+    const int64_t nb = offsets[b + 1] - offsets[b];
+    if (per_conf) {
+      mbs_stats& o = per_conf[b];
+      memset(&o, 0, sizeof o);
+      o.iters = its[b];
+      o.fp64_matvecs = its[b] + 1;
+      o.rel_resid = res[b];
+      o.t_total_ms = total_ms;
+      o.pair_blocks = (double)nb * (double)(nb - 1) * (its[b] + 3);
     }
-    if (r1 != MBS_OK && rc == MBS_OK) rc = r1;
-    if (r1 != MBS_OK && r1 != MBS_ENOCONV) break;
+    if (latency_ms)
+      latency_ms[b] = rate_khz > 0 ? (double)(t1[b] - tmin) / (double)rate_khz : total_ms;
+    if (status[b] != kFinal || !(res[b] <= tol)) rc = MBS_ENOCONV;
   }
-  c->prm.guess = guess0;
+  // the caller's stream continues after the batch
+  HIPCHK(c, hipEventRecord(c->ev[7], bs));
+  HIPCHK(c, hipStreamWaitEvent(s, c->ev[7], 0));
+  if (rc == MBS_ENOCONV) set_err(c, MBS_ENOCONV, "some configurations did not reach the tolerance");
   return rc;
 }
 

@@ -36,16 +36,13 @@
 
 #include "mbs_device.h"
 #include "mbs_internal.h"
+#include "mbs_pair.h"
 
 namespace mbs {
 
 namespace {
 
 // ------------------------------------------------------------------ P1: right-hand side
-struct alignas(16) RecF {
-  double x, y, z, fx, fy, fz, tx, ty, tz, dx, dy, dz;
-};
-
 template <int TJ, bool HAS_T, bool HAS_D>
 __global__ void __launch_bounds__(kMaxBlock)
     k_p1(const double* __restrict__ R, const double* __restrict__ Fe, const double* __restrict__ Te,
@@ -58,8 +55,7 @@ __global__ void __launch_bounds__(kMaxBlock)
   const int j0 = blockIdx.y * chunk;
   const int j1 = min(n, j0 + chunk);
   const double A8 = 8.0 * a2, B16 = -3.2 * a2;  // 8a^2, -(16/5) a^2
-  // raw moments x_i v_j of the per-pair vector v (traceless projection once per receiver)
-  double pxx = 0, pyy = 0, pzz = 0, qxy = 0, qxz = 0, qyz = 0;
+  Mom6 m;  // raw moments x_i v_j of the per-pair vector v (traceless projection once per receiver)
   for (int jt = j0; jt < j1; jt += TJ) {
     const int cnt = min(TJ, j1 - jt);
     __syncthreads();
@@ -90,43 +86,11 @@ __global__ void __launch_bounds__(kMaxBlock)
     }
     __syncthreads();
 #pragma unroll 2
-    for (int jj = 0; jj < cnt; ++jj) {
-      const RecF& s = tile[jj];
-      const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      const double ri = rinv_or_zero(r2);
-      const double ri2 = ri * ri;
-      const double ri5 = ri2 * ri2 * ri;
-      const double ri7 = ri5 * ri2;
-      const double xF = fma(dx, s.fx, fma(dy, s.fy, dz * s.fz));
-      double alpha = xF * ri5 * fma(A8, ri2, -3.0);
-      const double beta = B16 * ri5;
-      double vx = fma(beta, s.fx, alpha * dx);
-      double vy = fma(beta, s.fy, alpha * dy);
-      double vz = fma(beta, s.fz, alpha * dz);
-      if (HAS_T) {  // -3 (T x x) / r^5
-        const double m3 = -3.0 * ri5;
-        vx = fma(m3, s.ty * dz - s.tz * dy, vx);
-        vy = fma(m3, s.tz * dx - s.tx * dz, vy);
-        vz = fma(m3, s.tx * dy - s.ty * dx, vz);
-      }
-      if (HAS_D) {  // 6 d / r^5 - 15 (x.d) x / r^7
-        const double xd = -15.0 * ri7 * (dx * s.dx + dy * s.dy + dz * s.dz);
-        const double six = 6.0 * ri5;
-        vx = fma(six, s.dx, fma(xd, dx, vx));
-        vy = fma(six, s.dy, fma(xd, dy, vy));
-        vz = fma(six, s.dz, fma(xd, dz, vz));
-      }
-      pxx = fma(dx, vx, pxx);
-      pyy = fma(dy, vy, pyy);
-      pzz = fma(dz, vz, pzz);
-      qxy = fma(dx, vy, fma(dy, vx, qxy));
-      qxz = fma(dx, vz, fma(dz, vx, qxz));
-      qyz = fma(dy, vz, fma(dz, vy, qyz));
-    }
+    for (int jj = 0; jj < cnt; ++jj) p1_pair<HAS_T, HAS_D>(tile[jj], xi, yi, zi, A8, B16, m);
   }
   if (i >= n) return;
-  double e[5] = {RS2 * (pxx - pyy), RS6 * (2.0 * pzz - pxx - pyy), RS2 * qxy, RS2 * qxz, RS2 * qyz};
+  double e[5];
+  mom6_to_basis(m, e);
   if (direct) {
 #pragma unroll
     for (int c = 0; c < 5; ++c)
@@ -148,10 +112,6 @@ __global__ void k_p1_finish(const double* __restrict__ part, const double* __res
 }
 
 // ------------------------------------------------------------------ P3: rigid-body outputs
-struct alignas(16) RecO {
-  double x, y, z, fx, fy, fz, tx, ty, tz, sxx, syy, sxy, sxz, syz, dx, dy, dz, pad;
-};
-
 template <int TJ, bool HAS_T, bool HAS_D>
 __global__ void __launch_bounds__(kMaxBlock)
     k_p3(const double* __restrict__ R, const double* __restrict__ Fe, const double* __restrict__ Te,
@@ -164,7 +124,7 @@ __global__ void __launch_bounds__(kMaxBlock)
   const int j0 = blockIdx.y * chunk;
   const int j1 = min(n, j0 + chunk);
   const double A2_2 = 2.0 * a2, A2_23 = 2.0 * a2 / 3.0, A8 = 8.0 * a2, B16 = -3.2 * a2;
-  double ux = 0, uy = 0, uz = 0, wx_ = 0, wy_ = 0, wz_ = 0;
+  UW acc;
   for (int jt = j0; jt < j1; jt += TJ) {
     const int cnt = min(TJ, j1 - jt);
     __syncthreads();
@@ -203,60 +163,16 @@ __global__ void __launch_bounds__(kMaxBlock)
     }
     __syncthreads();
 #pragma unroll 2
-    for (int jj = 0; jj < cnt; ++jj) {
-      const RecO& s = tile[jj];
-      const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      const double ri = rinv_or_zero(r2);
-      const double ri2 = ri * ri;
-      const double ri3 = ri2 * ri;
-      const double ri5 = ri3 * ri2;
-      const double szz = -(s.sxx + s.syy);
-      const double wx = fma(s.sxx, dx, fma(s.sxy, dy, s.sxz * dz));
-      const double wy = fma(s.sxy, dx, fma(s.syy, dy, s.syz * dz));
-      const double wz = fma(s.sxz, dx, fma(s.syz, dy, szz * dz));
-      const double q = fma(dx, wx, fma(dy, wy, dz * wz));
-      const double xF = fma(dx, s.fx, fma(dy, s.fy, dz * s.fz));
-      double cx = xF * fma(-A2_2, ri5, ri3) + q * ri5 * fma(A8, ri2, -3.0);
-      const double cF = fma(A2_23, ri3, ri);
-      const double cw = B16 * ri5;
-      if (HAS_D) cx = fma(3.0 * ri5, dx * s.dx + dy * s.dy + dz * s.dz, cx);
-      ux = fma(cx, dx, fma(cF, s.fx, fma(cw, wx, ux)));
-      uy = fma(cx, dy, fma(cF, s.fy, fma(cw, wy, uy)));
-      uz = fma(cx, dz, fma(cF, s.fz, fma(cw, wz, uz)));
-      // rotation: x cross (-F/r^3 + 3 w / r^5)
-      const double gx = fma(3.0 * ri5, wx, -ri3 * s.fx);
-      const double gy = fma(3.0 * ri5, wy, -ri3 * s.fy);
-      const double gz = fma(3.0 * ri5, wz, -ri3 * s.fz);
-      wx_ = fma(dy, gz, fma(-dz, gy, wx_));
-      wy_ = fma(dz, gx, fma(-dx, gz, wy_));
-      wz_ = fma(dx, gy, fma(-dy, gx, wz_));
-      if (HAS_T) {
-        // U += (T x x)/r^3 ; W += 1.5 (x.T) x / r^5 - 0.5 T / r^3
-        ux = fma(ri3, s.ty * dz - s.tz * dy, ux);
-        uy = fma(ri3, s.tz * dx - s.tx * dz, uy);
-        uz = fma(ri3, s.tx * dy - s.ty * dx, uz);
-        const double xT = 1.5 * ri5 * (dx * s.tx + dy * s.ty + dz * s.tz);
-        const double h = -0.5 * ri3;
-        wx_ = fma(xT, dx, fma(h, s.tx, wx_));
-        wy_ = fma(xT, dy, fma(h, s.ty, wy_));
-        wz_ = fma(xT, dz, fma(h, s.tz, wz_));
-      }
-      if (HAS_D) {  // U += -d / r^3 (the (x.d) x part is in cx)
-        ux = fma(-ri3, s.dx, ux);
-        uy = fma(-ri3, s.dy, uy);
-        uz = fma(-ri3, s.dz, uz);
-      }
-    }
+    for (int jj = 0; jj < cnt; ++jj) p3_pair<HAS_T, HAS_D>(tile[jj], xi, yi, zi, A2_2, A2_23, A8, B16, acc);
   }
   if (i >= n) return;
   double* o = out + (int64_t)blockIdx.y * 6 * n + 6 * (int64_t)i;
-  o[0] = ux;
-  o[1] = uy;
-  o[2] = uz;
-  o[3] = wx_;
-  o[4] = wy_;
-  o[5] = wz_;
+  o[0] = acc.ux;
+  o[1] = acc.uy;
+  o[2] = acc.uz;
+  o[3] = acc.wx;
+  o[4] = acc.wy;
+  o[5] = acc.wz;
 }
 
 __global__ void k_p3_finish(const double* __restrict__ part, int split, int64_t n,

@@ -32,6 +32,7 @@
 
 #include "mbs_device.h"
 #include "mbs_internal.h"
+#include "mbs_pair.h"
 
 namespace mbs {
 
@@ -43,47 +44,6 @@ const Tile kTileTable[] = {
 const int kTileCount = sizeof(kTileTable) / sizeof(kTileTable[0]);
 
 namespace {
-
-template <typename T>
-struct alignas(8 * sizeof(T)) Src8 {
-  T x, y, z, sxx, syy, sxy, sxz, syz;
-};
-
-template <typename T>
-struct Mom {  // per-receiver sums
-  T pxx = 0, pyy = 0, pzz = 0, qxy = 0, qxz = 0, qyz = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
-};
-
-template <typename T, bool SELF>
-__device__ __forceinline__ void p2_pair(const Src8<T>& s, T xi, T yi, T zi, T A24, T A42, Mom<T>& m) {
-  const T dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-  const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-  const T ri = SELF ? rinv_or_zero(r2) : rsq_nr(r2);
-  const T ri2 = ri * ri;
-  const T ri5 = ri2 * ri2 * ri;
-  const T ri7 = ri5 * ri2;
-  const T szz = -(s.sxx + s.syy);
-  const T wx = fma(s.sxx, dx, fma(s.sxy, dy, s.sxz * dz));
-  const T wy = fma(s.sxy, dx, fma(s.syy, dy, s.syz * dz));
-  const T wz = fma(s.sxz, dx, fma(s.syz, dy, szz * dz));
-  const T q = fma(dx, wx, fma(dy, wy, dz * wz));
-  const T c1 = ri5 * fma(A24, ri2, (T)-6);
-  const T c2 = q * ri7 * fma(-A42, ri2, (T)15);
-  const T vx = fma(c1, wx, c2 * dx);
-  const T vy = fma(c1, wy, c2 * dy);
-  const T vz = fma(c1, wz, c2 * dz);
-  m.pxx = fma(dx, vx, m.pxx);
-  m.pyy = fma(dy, vy, m.pyy);
-  m.pzz = fma(dz, vz, m.pzz);
-  m.qxy = fma(dx, vy, fma(dy, vx, m.qxy));
-  m.qxz = fma(dx, vz, fma(dz, vx, m.qxz));
-  m.qyz = fma(dy, vz, fma(dz, vy, m.qyz));
-  m.t0 = fma(ri5, s.sxx, m.t0);
-  m.t1 = fma(ri5, s.syy, m.t1);
-  m.t2 = fma(ri5, s.sxy, m.t2);
-  m.t3 = fma(ri5, s.sxz, m.t3);
-  m.t4 = fma(ri5, s.syz, m.t4);
-}
 
 // Total over segments: binary64 adds directly; binary32 uses compensated (Kahan) sums.
 template <typename T>
@@ -128,15 +88,8 @@ struct Total<float> {
 __device__ __forceinline__ void p2_store(const double* v, int i, int n, const double* __restrict__ X,
                                          double* __restrict__ out, double P, double a2,
                                          double inv_gamma, int direct) {
-  const double C3 = -2.4 * a2;  // -12 a^2 / 5
-  const double pxx = v[0], pyy = v[1], pzz = v[2], qxy = v[3], qxz = v[4], qyz = v[5];
-  const double t0 = v[6], t1 = v[7], t2 = v[8], t3 = v[9], t4 = v[10];
   double e[5];
-  e[0] = P * RS2 * ((pxx - pyy) + C3 * (t0 - t1));
-  e[1] = P * RS6 * ((2.0 * pzz - pxx - pyy) - 3.0 * C3 * (t0 + t1));
-  e[2] = P * RS2 * (qxy + 2.0 * C3 * t2);
-  e[3] = P * RS2 * (qxz + 2.0 * C3 * t3);
-  e[4] = P * RS2 * (qyz + 2.0 * C3 * t4);
+  p2_strain(v, P, a2, e);
   if (direct) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) out[5 * (int64_t)i + c] = X[5 * (int64_t)i + c] * inv_gamma - e[c];

@@ -1,0 +1,176 @@
+// Per-pair arithmetic of the three all-pairs passes, shared by the single-configuration and the
+// batched kernels. x = R_n - R_m (receiver minus source), P = 1/(8 pi eta); source records carry
+// P-scaled force/torque/stresslet and (a^5/10)-scaled trace modes, so no constant appears per pair.
+// The closed forms are listed at the top of mbs_kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mbs_device.h"
+
+namespace mbs {
+
+// ---------------------------------------------------------------- P1: strain of force, torque, d
+struct alignas(16) RecF {
+  double x, y, z, fx, fy, fz, tx, ty, tz, dx, dy, dz;
+};
+
+struct Mom6 {  // raw moments sum x_i v_j of the per-pair strain vector v
+  double pxx = 0, pyy = 0, pzz = 0, qxy = 0, qxz = 0, qyz = 0;
+};
+
+template <bool HAS_T, bool HAS_D>
+__device__ __forceinline__ void p1_pair(const RecF& s, double xi, double yi, double zi, double A8,
+                                        double B16, Mom6& m) {
+  const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+  const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  const double ri = rinv_or_zero(r2);
+  const double ri2 = ri * ri;
+  const double ri5 = ri2 * ri2 * ri;
+  const double ri7 = ri5 * ri2;
+  const double xF = fma(dx, s.fx, fma(dy, s.fy, dz * s.fz));
+  const double alpha = xF * ri5 * fma(A8, ri2, -3.0);
+  const double beta = B16 * ri5;
+  double vx = fma(beta, s.fx, alpha * dx);
+  double vy = fma(beta, s.fy, alpha * dy);
+  double vz = fma(beta, s.fz, alpha * dz);
+  if (HAS_T) {  // -3 (T x x) / r^5
+    const double m3 = -3.0 * ri5;
+    vx = fma(m3, s.ty * dz - s.tz * dy, vx);
+    vy = fma(m3, s.tz * dx - s.tx * dz, vy);
+    vz = fma(m3, s.tx * dy - s.ty * dx, vz);
+  }
+  if (HAS_D) {  // 6 d / r^5 - 15 (x.d) x / r^7
+    const double xd = -15.0 * ri7 * (dx * s.dx + dy * s.dy + dz * s.dz);
+    const double six = 6.0 * ri5;
+    vx = fma(six, s.dx, fma(xd, dx, vx));
+    vy = fma(six, s.dy, fma(xd, dy, vy));
+    vz = fma(six, s.dz, fma(xd, dz, vz));
+  }
+  m.pxx = fma(dx, vx, m.pxx);
+  m.pyy = fma(dy, vy, m.pyy);
+  m.pzz = fma(dz, vz, m.pzz);
+  m.qxy = fma(dx, vy, fma(dy, vx, m.qxy));
+  m.qxz = fma(dx, vz, fma(dz, vx, m.qxz));
+  m.qyz = fma(dy, vz, fma(dz, vy, m.qyz));
+}
+
+// traceless 5-basis projection of the moments
+__device__ __forceinline__ void mom6_to_basis(const Mom6& m, double* e) {
+  e[0] = RS2 * (m.pxx - m.pyy);
+  e[1] = RS6 * (2.0 * m.pzz - m.pxx - m.pyy);
+  e[2] = RS2 * m.qxy;
+  e[3] = RS2 * m.qxz;
+  e[4] = RS2 * m.qyz;
+}
+
+// ---------------------------------------------------------------- P3: velocity and rotation
+struct alignas(16) RecO {
+  double x, y, z, fx, fy, fz, tx, ty, tz, sxx, syy, sxy, sxz, syz, dx, dy, dz, pad;
+};
+
+struct UW {
+  double ux = 0, uy = 0, uz = 0, wx = 0, wy = 0, wz = 0;
+};
+
+template <bool HAS_T, bool HAS_D>
+__device__ __forceinline__ void p3_pair(const RecO& s, double xi, double yi, double zi, double A2_2,
+                                        double A2_23, double A8, double B16, UW& a) {
+  const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+  const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  const double ri = rinv_or_zero(r2);
+  const double ri2 = ri * ri;
+  const double ri3 = ri2 * ri;
+  const double ri5 = ri3 * ri2;
+  const double szz = -(s.sxx + s.syy);
+  const double wx = fma(s.sxx, dx, fma(s.sxy, dy, s.sxz * dz));
+  const double wy = fma(s.sxy, dx, fma(s.syy, dy, s.syz * dz));
+  const double wz = fma(s.sxz, dx, fma(s.syz, dy, szz * dz));
+  const double q = fma(dx, wx, fma(dy, wy, dz * wz));
+  const double xF = fma(dx, s.fx, fma(dy, s.fy, dz * s.fz));
+  double cx = xF * fma(-A2_2, ri5, ri3) + q * ri5 * fma(A8, ri2, -3.0);
+  const double cF = fma(A2_23, ri3, ri);
+  const double cw = B16 * ri5;
+  if (HAS_D) cx = fma(3.0 * ri5, dx * s.dx + dy * s.dy + dz * s.dz, cx);
+  a.ux = fma(cx, dx, fma(cF, s.fx, fma(cw, wx, a.ux)));
+  a.uy = fma(cx, dy, fma(cF, s.fy, fma(cw, wy, a.uy)));
+  a.uz = fma(cx, dz, fma(cF, s.fz, fma(cw, wz, a.uz)));
+  // rotation: x cross (-F/r^3 + 3 w / r^5)
+  const double gx = fma(3.0 * ri5, wx, -ri3 * s.fx);
+  const double gy = fma(3.0 * ri5, wy, -ri3 * s.fy);
+  const double gz = fma(3.0 * ri5, wz, -ri3 * s.fz);
+  a.wx = fma(dy, gz, fma(-dz, gy, a.wx));
+  a.wy = fma(dz, gx, fma(-dx, gz, a.wy));
+  a.wz = fma(dx, gy, fma(-dy, gx, a.wz));
+  if (HAS_T) {
+    // U += (T x x)/r^3 ; W += 1.5 (x.T) x / r^5 - 0.5 T / r^3
+    a.ux = fma(ri3, s.ty * dz - s.tz * dy, a.ux);
+    a.uy = fma(ri3, s.tz * dx - s.tx * dz, a.uy);
+    a.uz = fma(ri3, s.tx * dy - s.ty * dx, a.uz);
+    const double xT = 1.5 * ri5 * (dx * s.tx + dy * s.ty + dz * s.tz);
+    const double h = -0.5 * ri3;
+    a.wx = fma(xT, dx, fma(h, s.tx, a.wx));
+    a.wy = fma(xT, dy, fma(h, s.ty, a.wy));
+    a.wz = fma(xT, dz, fma(h, s.tz, a.wz));
+  }
+  if (HAS_D) {  // U += -d / r^3 (the (x.d) x part is in cx)
+    a.ux = fma(-ri3, s.dx, a.ux);
+    a.uy = fma(-ri3, s.dy, a.uy);
+    a.uz = fma(-ri3, s.dz, a.uz);
+  }
+}
+
+// ---------------------------------------------------------------- P2: the system operator
+template <typename T>
+struct alignas(8 * sizeof(T)) Src8 {
+  T x, y, z, sxx, syy, sxy, sxz, syz;
+};
+
+template <typename T>
+struct Mom {  // per-receiver sums of the operator pass
+  T pxx = 0, pyy = 0, pzz = 0, qxy = 0, qxz = 0, qyz = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
+};
+
+template <typename T, bool SELF>
+__device__ __forceinline__ void p2_pair(const Src8<T>& s, T xi, T yi, T zi, T A24, T A42, Mom<T>& m) {
+  const T dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+  const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  const T ri = SELF ? rinv_or_zero(r2) : rsq_nr(r2);
+  const T ri2 = ri * ri;
+  const T ri5 = ri2 * ri2 * ri;
+  const T ri7 = ri5 * ri2;
+  const T szz = -(s.sxx + s.syy);
+  const T wx = fma(s.sxx, dx, fma(s.sxy, dy, s.sxz * dz));
+  const T wy = fma(s.sxy, dx, fma(s.syy, dy, s.syz * dz));
+  const T wz = fma(s.sxz, dx, fma(s.syz, dy, szz * dz));
+  const T q = fma(dx, wx, fma(dy, wy, dz * wz));
+  const T c1 = ri5 * fma(A24, ri2, (T)-6);
+  const T c2 = q * ri7 * fma(-A42, ri2, (T)15);
+  const T vx = fma(c1, wx, c2 * dx);
+  const T vy = fma(c1, wy, c2 * dy);
+  const T vz = fma(c1, wz, c2 * dz);
+  m.pxx = fma(dx, vx, m.pxx);
+  m.pyy = fma(dy, vy, m.pyy);
+  m.pzz = fma(dz, vz, m.pzz);
+  m.qxy = fma(dx, vy, fma(dy, vx, m.qxy));
+  m.qxz = fma(dx, vz, fma(dz, vx, m.qxz));
+  m.qyz = fma(dy, vz, fma(dz, vy, m.qyz));
+  m.t0 = fma(ri5, s.sxx, m.t0);
+  m.t1 = fma(ri5, s.syy, m.t1);
+  m.t2 = fma(ri5, s.sxy, m.t2);
+  m.t3 = fma(ri5, s.sxz, m.t3);
+  m.t4 = fma(ri5, s.syz, m.t4);
+}
+
+// E[x] at one receiver in the 5-basis from the operator sums (11 values, see Mom)
+__device__ __forceinline__ void p2_strain(const double* v, double P, double a2, double* e) {
+  const double C3 = -2.4 * a2;  // -12 a^2 / 5
+  const double pxx = v[0], pyy = v[1], pzz = v[2], qxy = v[3], qxz = v[4], qyz = v[5];
+  const double t0 = v[6], t1 = v[7], t2 = v[8], t3 = v[9], t4 = v[10];
+  e[0] = P * RS2 * ((pxx - pyy) + C3 * (t0 - t1));
+  e[1] = P * RS6 * ((2.0 * pzz - pxx - pyy) - 3.0 * C3 * (t0 + t1));
+  e[2] = P * RS2 * (qxy + 2.0 * C3 * t2);
+  e[3] = P * RS2 * (qxz + 2.0 * C3 * t3);
+  e[4] = P * RS2 * (qyz + 2.0 * C3 * t4);
+}
+
+}  // namespace mbs
