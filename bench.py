@@ -38,7 +38,14 @@ def parse():
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--headline", default="mixed_diag", choices=["plain_fp64", "mixed_diag", "fp64_diag"])
+    ap.add_argument("--headline", default="mixed_learned",
+                    choices=["plain_fp64", "fp64_diag", "mixed_diag", "fp64_learned", "mixed_learned"])
+    ap.add_argument("--skip-warmstart", action="store_true", help="no learned warm start (no training)")
+    ap.add_argument("--warmstart-configs", type=int, default=200)
+    ap.add_argument("--warmstart-epochs", type=int, default=10)
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-stepper", action="store_true")
+    ap.add_argument("--stepper-steps", type=int, default=1000)
     ap.add_argument("--profile-matvec", action="store_true",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then --steps "
                          "binary64 and --steps binary32 operator applications at the autotuned shapes")
@@ -140,6 +147,66 @@ def roofline(v, n):
             "flop_per_pair": P2_FLOP_PER_PAIR}
 
 
+def bench_batched(ctx, a):
+    """512 independent configurations, N log-uniform in [64, 4096], density 0.004, one batched call."""
+    import numpy as np
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+    t0 = time.perf_counter()
+    ws = inputs.config3()
+    off = np.cumsum([0] + [w.n for w in ws])
+    cat = lambda f: torch.as_tensor(np.concatenate([getattr(w, f) for w in ws])).to("cuda:0")
+    R, v1s, v2s, Fe = cat("R"), cat("v1s"), cat("v2s"), cat("Fe")
+    print(f"bench: batched workload of {len(ws)} configurations ({int(off[-1])} spheres) built in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-10)
+    ctx.mbs_solve_batched(off, R, v1s, v2s, None, Fe, None)      # capture + warm-up
+    torch.cuda.synchronize()
+    reps = 3
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        V, W, S, stats, lat = ctx.mbs_solve_batched(off, R, v1s, v2s, None, Fe, None)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / reps
+    lat = np.array(lat)
+    pairs = sum(st["pair_blocks"] for st in stats)
+    return {"configs": len(ws), "spheres": int(off[-1]), "ms_per_batch": 1e3 * dt,
+            "configs_per_s": len(ws) / dt, "pair_blocks_per_s": pairs / dt,
+            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+            "max_iters": int(max(st["iters"] for st in stats)),
+            "max_rel_resid": float(max(st["rel_resid"] for st in stats))}
+
+
+def bench_stepper(ctx, a):
+    """N = 1e4 trap, slip (V1s, V2s, V3t) = (p, 3(pp - I/3), p), Adams-Bashforth dt = 0.01."""
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+    w = inputs.config1()
+    out = {"n": w.n, "steps": a.stepper_steps, "dt": 0.01}
+    for name, prec in (("fp64", mbstokes.MBS_FP64), ("mixed", mbstokes.MBS_MIXED)):
+        R = torch.as_tensor(w.R).to("cuda:0")
+        p = torch.as_tensor(w.p).to("cuda:0")
+        ctx.set_params(precision=prec, guess=mbstokes.MBS_GUESS_USER, tol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats, md = ctx.mbs_step(R, p, 0.5, (1.0, 1.0, 1.0), 0.01, a.stepper_steps, order=2,
+                                 want_min_dist=True, allow_noconv=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        first_overlap = next((k for k, v in enumerate(md) if v < 2.0), None)
+        out[name] = {"seconds": dt, "ms_per_step": 1e3 * dt / max(1, len(stats)),
+                     "mean_iters": sum(s["iters"] for s in stats) / max(1, len(stats)),
+                     "fp64_matvecs": sum(s["fp64_matvecs"] for s in stats),
+                     "fp32_matvecs": sum(s["fp32_matvecs"] for s in stats),
+                     "max_rel_resid": max(s["rel_resid"] for s in stats),
+                     "first_overlap_step": first_overlap, "min_distance_last": md[-1] if md else None}
+        print(f"bench: stepper {name} {len(stats)} steps in {dt:.2f} s", file=sys.stderr, flush=True)
+    ctx.set_params(guess=mbstokes.MBS_GUESS_ZERO, precision=mbstokes.MBS_FP64)
+    return out
+
+
 def cpu_baseline(w, seconds):
     """The oracle's system-operator rows on host cores: pair-blocks/s on a bounded row sample."""
     import numpy as np
@@ -185,12 +252,36 @@ def main():
     print(f"bench: autotuned pair-kernel shapes {tiles} in {time.perf_counter() - t_tune:.1f} s",
           file=sys.stderr, flush=True)
     variants = {}
+    extra = {}
     plan = [("plain_fp64", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_ZERO),
             ("fp64_diag", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_DIAG),
             ("mixed_diag", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG)]
+    if not a.skip_warmstart:
+        from paper_1411_0278_amd import warmstart
+        print("bench: training the warm-start network", file=sys.stderr, flush=True)
+        rep = warmstart.train_pipeline(ctx, a.warmstart_configs, max(1, a.warmstart_configs // 20),
+                                       a.warmstart_epochs,
+                                       log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+        plan += [("fp64_learned", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_LEARNED),
+                 ("mixed_learned", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_LEARNED)]
+        # surrogate error of the guesses against the converged solution of this workload
+        ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-12)
+        sig = torch.empty((a.n, 5), dtype=torch.float64, device="cuda:0")
+        ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None, Sigma=sig)
+        rep["surrogate_rel_err"] = {
+            "zero": 1.0,
+            "diag": warmstart.surrogate_error(ctx, d, sig, mbstokes.MBS_GUESS_DIAG),
+            "learned": warmstart.surrogate_error(ctx, d, sig, mbstokes.MBS_GUESS_LEARNED)}
+        extra["warmstart"] = rep
+    elif a.headline.endswith("learned"):
+        a.headline = "mixed_diag"
     for name, prec, guess in plan:
         steps = a.steps if name in (a.headline, "plain_fp64") else max(1, min(a.steps, 2))
         variants[name] = time_variant(ctx, d, mbstokes, name, prec, guess, steps, a.warmup)
+    if not a.skip_batched:
+        extra["batched"] = bench_batched(ctx, a)
+    if not a.skip_stepper:
+        extra["stepper"] = bench_stepper(ctx, a)
     head = variants[a.headline]
     out = {
         "metric": METRIC,
@@ -210,7 +301,10 @@ def main():
                    "n": a.n, "headline": a.headline, "tol": 1e-10, "tiles": list(tiles)},
         "roofline": roofline(head, a.n),
         "time_to_1e-10_ms": {k: round(v["ms_per_step"], 3) for k, v in variants.items()},
+        "iterations": {k: v["iters"] for k, v in variants.items()},
+        "speedup_vs_plain_fp64": round(variants["plain_fp64"]["ms_per_step"] / head["ms_per_step"], 4),
         "variants": variants,
+        **extra,
     }
     if not a.skip_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)

@@ -225,6 +225,17 @@ int mbs_warmstart_grad(mbs_ctx* ctx, int64_t m, const float* feat, const float* 
    receives the mean training loss of each epoch. */
 int mbs_warmstart_train(mbs_ctx* ctx, int64_t m, const float* feat, const float* target, int32_t epochs,
                         int32_t batch, double lr, uint64_t seed, double* loss_hist, void* stream);
+/* Training target of the network for a converged flow stresslet Sigma [n x 5] (binary64 DEVICE):
+   target = Sigma - gamma b as float32 [n x 5] DEVICE, b the right-hand side of the same inputs
+   (arguments as in mbs_rhs). */
+int mbs_warmstart_target(mbs_ctx* ctx, int64_t n, const double* R, const double* v2s, const double* v3t,
+                         const double* Fe, const double* Te, const double* Sigma, float* target,
+                         void* stream);
+/* The initial iterate the solver would start from (sigma0 [n x 5] binary64 DEVICE) for
+   guess = MBS_GUESS_ZERO (0), MBS_GUESS_DIAG (gamma b) or MBS_GUESS_LEARNED (gamma b + net). */
+int mbs_initial_guess(mbs_ctx* ctx, int64_t n, const double* R, const double* p, const double* v2s,
+                      const double* v3t, const double* Fe, const double* Te, int32_t guess,
+                      double* sigma0, void* stream);
 /* Write / read the float32 parameters (binary: "MBSW", version 1, count, values). */
 int mbs_warmstart_save(mbs_ctx* ctx, const char* path);
 int mbs_warmstart_load(mbs_ctx* ctx, const char* path);

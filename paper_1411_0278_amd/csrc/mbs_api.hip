@@ -542,7 +542,10 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const do
       launch_copy(c->b.p, rr, len, s);
       beta = bnorm;
     } else {
-      apply_op(c, MBS_FP64, n, R, c->xs.p, rr, s, cnt);
+      // The first residual only feeds the first inner solve, whose target (inner_tol) lies far above
+      // the binary32 operator error, so it is formed with the binary32 operator; every later residual,
+      // including the certified final one, is binary64.
+      apply_op(c, MBS_FP32, n, R, c->xs.p, rr, s, cnt);
       launch_axpby(1.0, c->b.p, -1.0, rr, len, s);
       norm2(c, rr, len, sm.nsq, s);
       CHK(read_status(c, sm.nsq, 1, s));
@@ -1350,6 +1353,47 @@ int mbs_warmstart_load(mbs_ctx* c, const char* path) {
   fclose(f);
   if (!ok) return set_err(c, MBS_EINVAL, "%s is not a warm-start weight file", path);
   return mbs_warmstart_set(c, w.data());
+}
+
+int mbs_initial_guess(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* v2s,
+                      const double* v3t, const double* Fe, const double* Te, int32_t guess,
+                      double* sigma0, void* stream) {
+  CHK(begin_call(c));
+  if (n < 1 || !R || !sigma0) return set_err(c, MBS_EINVAL, "n >= 1, R and sigma0 are required");
+  if (n > (int64_t)INT32_MAX / kMlpIn) return set_err(c, MBS_EINVAL, "n too large");
+  if (guess != MBS_GUESS_ZERO && guess != MBS_GUESS_DIAG && guess != MBS_GUESS_LEARNED)
+    return set_err(c, MBS_EINVAL, "guess must be MBS_GUESS_ZERO, _DIAG or _LEARNED");
+  if (guess == MBS_GUESS_LEARNED) {
+    if (!c->mlp_ready) return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context");
+    if (!p || n < kNeigh + 1) return set_err(c, MBS_EINVAL, "the learned guess needs p and n >= %d", kNeigh + 1);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, n));
+  launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
+  if (guess == MBS_GUESS_ZERO)
+    launch_axpby(0.0, c->b.p, 0.0, sigma0, 5 * n, s);
+  else if (guess == MBS_GUESS_DIAG)
+    launch_axpby(c->ph.gamma, c->b.p, 0.0, sigma0, 5 * n, s);
+  else
+    CHK(learned_guess(c, n, R, p, c->b.p, sigma0, s));
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_warmstart_target(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const double* v3t,
+                         const double* Fe, const double* Te, const double* Sigma, float* target,
+                         void* stream) {
+  CHK(begin_call(c));
+  if (n < 1 || !R || !Sigma || !target) return set_err(c, MBS_EINVAL, "n >= 1, R, Sigma, target required");
+  if (n > (int64_t)INT32_MAX / kMlpIn) return set_err(c, MBS_EINVAL, "n too large");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, n));
+  launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
+  launch_target(Sigma, c->b.p, c->ph.gamma, 5 * n, target, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
 }
 
 }  // extern "C"

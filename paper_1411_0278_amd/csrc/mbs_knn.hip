@@ -89,9 +89,21 @@ __global__ void k_guess_learned(const double* __restrict__ b, const float* __res
   if (k < len) x[k] = gamma * b[k] + (double)out[k];
 }
 
+// target of the network: Sigma - gamma b (float32)
+__global__ void k_target(const double* __restrict__ Sig, const double* __restrict__ b, double gamma,
+                         int64_t len, float* __restrict__ t) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < len) t[k] = (float)(Sig[k] - gamma * b[k]);
+}
+
 inline unsigned nblk(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
 
 }  // namespace
+
+void launch_target(const double* Sig, const double* b, double gamma, int64_t len, float* t,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_target, dim3(nblk(len, 256)), dim3(256), 0, s, Sig, b, gamma, len, t);
+}
 
 void launch_knn16(const double* R, int n, int32_t* nbr, hipStream_t s) {
   hipLaunchKernelGGL(k_knn16, dim3(nblk(n, 256)), dim3(256), 0, s, R, n, nbr);

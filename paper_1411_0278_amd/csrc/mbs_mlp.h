@@ -44,4 +44,8 @@ void launch_features(const double* R, const double* p, const int32_t* nbr, int n
 void launch_guess_learned(const double* b, const float* out, double gamma, int64_t len, double* x,
                           hipStream_t s);
 
+// target of the network from a converged flow stresslet: t = Sigma - gamma b (float32)
+void launch_target(const double* Sig, const double* b, double gamma, int64_t len, float* t,
+                   hipStream_t s);
+
 }  // namespace mbs

@@ -24,7 +24,7 @@ EXPORTS = ("mbs_default_params", "mbs_create", "mbs_destroy", "mbs_set_params", 
            "mbs_solve", "mbs_matvec", "mbs_rhs", "mbs_outputs", "mbs_step", "mbs_solve_batched",
            "mbs_autotune", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
            "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
-           "mbs_warmstart_load")
+           "mbs_warmstart_load", "mbs_warmstart_target", "mbs_initial_guess")
 MLP_NPARAM, MLP_NFEAT = 27525, 80
 
 
@@ -105,7 +105,9 @@ def load(path: str = LIB_PATH):
                                         ctypes.POINTER(ctypes.c_double), VP]
     lib.mbs_warmstart_save.argtypes = [P, ctypes.c_char_p]
     lib.mbs_warmstart_load.argtypes = [P, ctypes.c_char_p]
-    for name in ("mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
+    lib.mbs_warmstart_target.argtypes = [P, I64] + [P] * 7 + [VP]
+    lib.mbs_initial_guess.argtypes = [P, I64] + [P] * 6 + [I32, P, VP]
+    for name in ("mbs_warmstart_target", "mbs_initial_guess", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
                  "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
                  "mbs_warmstart_load"):
         getattr(lib, name).restype = ctypes.c_int
@@ -342,6 +344,30 @@ def _ws_load(self, path):
     self._check(self.lib.mbs_warmstart_load(self.h, str(path).encode()))
 
 
+def _ws_target(self, R, Sigma, v2s=None, v3t=None, Fe=None, Te=None):
+    import torch
+    n = R.shape[0]
+    t = torch.empty((n, 5), dtype=torch.float32, device=R.device)
+    self._check(self.lib.mbs_warmstart_target(self.h, n, _ptr(R, n, 3, "R"), _ptr(v2s, n, 5, "v2s"),
+                                              _ptr(v3t, n, 3, "v3t"), _ptr(Fe, n, 3, "Fe"), _ptr(Te, n, 3, "Te"),
+                                              _ptr(Sigma, n, 5, "Sigma"), _ptr(t, n, 5, "target", torch.float32),
+                                              _stream()))
+    return t
+
+
+def _initial_guess(self, R, guess, p=None, v2s=None, v3t=None, Fe=None, Te=None):
+    import torch
+    n = R.shape[0]
+    out = torch.empty((n, 5), dtype=torch.float64, device=R.device)
+    self._check(self.lib.mbs_initial_guess(self.h, n, _ptr(R, n, 3, "R"), _ptr(p, n, 3, "p"),
+                                           _ptr(v2s, n, 5, "v2s"), _ptr(v3t, n, 3, "v3t"), _ptr(Fe, n, 3, "Fe"),
+                                           _ptr(Te, n, 3, "Te"), int(guess), _ptr(out, n, 5, "sigma0"),
+                                           _stream()))
+    return out
+
+
+Context.mbs_warmstart_target = _ws_target
+Context.mbs_initial_guess = _initial_guess
 Context.mbs_features = _features
 Context.mbs_warmstart_init = _ws_init
 Context.mbs_warmstart_set = _ws_set
