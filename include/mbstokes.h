@@ -75,6 +75,10 @@ typedef struct mbs_params {
   double  self_slip_c;   /* c in "- c s_n": 1 = lone sphere meets its strain slip exactly;
                             1.4 reproduces the paper's one-body stresslet table */
   double  inner_tol;     /* MBS_MIXED: relative tolerance of each inner binary32 GMRES solve */
+  double  near_cutoff;   /* > 0: right-precondition GMRES with M^{-1} = gamma (I + gamma K_near), K_near
+                            the operator's blocks of pairs closer than near_cutoff (centre distance;
+                            at most 32 neighbours per sphere); 0 = no preconditioner (default).
+                            The solution is unchanged; mbs_solve_batched ignores it. */
   int32_t lmax;          /* traction truncation rank; only 2 (force, torque, stresslet) */
   int32_t max_iter;      /* cap on GMRES iterations (all restarts, inner iterations included) */
   int32_t restart;       /* GMRES restart length m, 1..64 */
@@ -140,6 +144,10 @@ int mbs_solve(mbs_ctx* ctx, int64_t n, const double* R, const double* p, const d
    accumulation; x and y stay binary64). x and y must not overlap. */
 int mbs_matvec(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y,
                int precision, void* stream);
+
+/* The near-field preconditioner on its own: y = gamma x + gamma^2 K_near x (x, y [n x 5] binary64
+   DEVICE, params.near_cutoff > 0). */
+int mbs_precond_apply(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y, void* stream);
 
 /* Right-hand side of the stresslet rows: b_n = sum_{m != n} E[F_m, T_m, d_m] - c s_n, b [n x 5]. */
 int mbs_rhs(mbs_ctx* ctx, int64_t n, const double* R, const double* v2s, const double* v3t,

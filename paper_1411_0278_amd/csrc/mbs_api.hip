@@ -43,7 +43,8 @@ struct mbs_ctx {
   Tile tile_pass = Tile{0, 256, 128, 4096};  // shape of the right-hand-side and output passes
   std::string err;
   // workspace
-  DevBuf V, w, r, b, xs, dlt, part, dpart, small, H, zeros, stepbuf, srcbuf, orig;
+  DevBuf V, w, r, b, xs, dlt, part, dpart, small, H, zeros, stepbuf, srcbuf, orig, near, zt;
+  bool near_ready = false;  // neighbour lists of the current solve are built
   int* d_count = nullptr;
   double* h_status = nullptr;  // pinned host [4]
   hipEvent_t ev[8] = {};
@@ -126,6 +127,8 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
     return set_err(c, MBS_EINVAL, "inner_tol must be in (0, 1)");
   if (p->guess < MBS_GUESS_ZERO || p->guess > MBS_GUESS_USER)
     return set_err(c, MBS_EINVAL, "unknown guess %d", p->guess);
+  if (!(p->near_cutoff >= 0.0) || !isfinite(p->near_cutoff))
+    return set_err(c, MBS_EINVAL, "near_cutoff must be finite and >= 0");
   if (p->tile < 0 || p->tile > kTileCount)
     return set_err(c, MBS_EINVAL, "tile must be in 0..%d", kTileCount);
   return MBS_OK;
@@ -154,6 +157,8 @@ int ensure_ws(mbs_ctx* c, int64_t n) {
   CHK(ensure(c, c->part, (size_t)pe));
   CHK(ensure(c, c->srcbuf, (size_t)8 * n));
   CHK(ensure(c, c->orig, 4));
+  CHK(ensure(c, c->zt, len));
+  if (c->prm.near_cutoff > 0.0) CHK(ensure(c, c->near, (size_t)(kNearCap + 1) * n / 2 + 64));
   CHK(ensure(c, c->dpart, (size_t)std::max<int64_t>((int64_t)(m + 2) * 256, 1024 + (n + 255) / 256) + 64));
   CHK(ensure(c, c->small, (size_t)8 * (m + 2) + 64));
   CHK(ensure(c, c->H, (size_t)(m + 1) * (m + 1)));
@@ -234,10 +239,22 @@ void norm2(mbs_ctx* c, const double* v, int64_t len, double* dev, hipStream_t s)
 // Restarted GMRES on A x = rhs, operator precision prec. x is updated in place (x_zero: x is 0).
 // Stops when the residual estimate is <= tol_abs. With verify, the final residual is recomputed
 // with the operator and returned in *resid; otherwise *resid is the last estimate.
+// near-field preconditioner lists for the current positions
+void near_prepare(mbs_ctx* c, int64_t n, const double* R, hipStream_t s) {
+  int* cntp = (int*)c->near.p;
+  launch_near_build(R, n, c->prm.near_cutoff, cntp, cntp + n, s);
+  c->near_ready = true;
+}
+void near_apply(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, hipStream_t s) {
+  const int* cntp = (const int*)c->near.p;
+  launch_near_apply(R, x, cntp, cntp + n, n, c->ph, y, s);
+}
+
 int gmres(mbs_ctx* c, int prec, int64_t n, const double* R, const double* rhs, double* x,
           bool x_zero, double tol_abs, int max_iters, bool verify, double* resid, Counters& cnt,
           hipStream_t s) {
   const int m = c->prm.restart;
+  const bool pc = c->prm.near_cutoff > 0.0 && c->near_ready;  // right preconditioning: A M^{-1} u = r
   const int64_t len = 5 * n;
   Small sm = small_of(c);
   double* V = c->V.p;
@@ -262,7 +279,12 @@ int gmres(mbs_ctx* c, int prec, int64_t n, const double* R, const double* rhs, d
     bool breakdown = false;
     while (k < m && used < max_iters) {
       double* vk = V + (int64_t)k * len;
-      apply_op(c, prec, n, R, vk, w, s, cnt);
+      if (pc) {
+        near_apply(c, n, R, vk, c->zt.p, s);
+        apply_op(c, prec, n, R, c->zt.p, w, s, cnt);
+      } else {
+        apply_op(c, prec, n, R, vk, w, s, cnt);
+      }
       // classical Gram-Schmidt, applied twice
       launch_dots(V, len, k + 1, w, len, c->dpart.p, sm.h1, s);
       launch_axpy_multi(V, len, k + 1, sm.h1, -1.0, w, len, s);
@@ -280,7 +302,14 @@ int gmres(mbs_ctx* c, int prec, int64_t n, const double* R, const double* rhs, d
       if (est <= tol_abs || breakdown) break;
     }
     launch_backsolve(c->H.p, m, k, sm.g, sm.y, s);
-    launch_axpy_multi(V, len, k, sm.y, 1.0, x, len, s);
+    if (pc) {  // x += M^{-1} (V y)
+      launch_axpby(0.0, w, 0.0, c->zt.p, len, s);
+      launch_axpy_multi(V, len, k, sm.y, 1.0, c->zt.p, len, s);
+      near_apply(c, n, R, c->zt.p, w, s);
+      launch_axpby(1.0, w, 1.0, x, len, s);
+    } else {
+      launch_axpy_multi(V, len, k, sm.y, 1.0, x, len, s);
+    }
     x_zero = false;
     const bool done = est <= tol_abs || breakdown || used >= max_iters;
     if (done && !verify) {
@@ -494,7 +523,9 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const do
   Small sm = small_of(c);
   c->npend = 0;
   c->t_op[0] = c->t_op[1] = 0.0;
+  c->near_ready = false;
   HIPCHK(c, hipEventRecord(c->ev[0], s));
+  if (c->prm.near_cutoff > 0.0) near_prepare(c, n, R, s);
   // right-hand side
   launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
   cnt.pairs += (double)n * (double)(n - 1);
@@ -613,6 +644,7 @@ void mbs_default_params(mbs_params* p) {
   p->tol = 1e-10;
   p->self_slip_c = 1.0;
   p->inner_tol = 1e-5;
+  p->near_cutoff = 0.0;
   p->lmax = 2;
   p->max_iter = 300;
   p->restart = 30;
@@ -661,7 +693,7 @@ void mbs_destroy(mbs_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   DevBuf* bufs[] = {&c->V, &c->w, &c->r, &c->b, &c->xs, &c->dlt, &c->part, &c->dpart,
-                    &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig,
+                    &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig, &c->near, &c->zt,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
                     &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->bat};
   for (DevBuf* b : bufs)
@@ -1391,6 +1423,22 @@ int mbs_warmstart_target(mbs_ctx* c, int64_t n, const double* R, const double* v
   CHK(ensure_ws(c, n));
   launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
   launch_target(Sigma, c->b.p, c->ph.gamma, 5 * n, target, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_precond_apply(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, void* stream) {
+  CHK(begin_call(c));
+  if (n < 1 || !R || !x || !y) return set_err(c, MBS_EINVAL, "n >= 1, R, x and y are required");
+  if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
+  if (x == y) return set_err(c, MBS_EINVAL, "x and y must not overlap");
+  if (!(c->prm.near_cutoff > 0.0)) return set_err(c, MBS_EINVAL, "params.near_cutoff must be > 0");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, n));
+  near_prepare(c, n, R, s);
+  near_apply(c, n, R, x, y, s);
+  c->near_ready = false;
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;

@@ -50,6 +50,13 @@ void launch_min_dist2(const double* R, int64_t n, double* out, double* scratch, 
 // count non-finite entries of a device array -> atomically added to *cnt (device int)
 void launch_count_nonfinite(const double* a, int64_t len, int* cnt, hipStream_t s);
 
+// near-field preconditioner: neighbour lists within rc (at most kNearCap per sphere) and
+// y = gamma x + gamma^2 K_near x
+constexpr int kNearCap = 32;
+void launch_near_build(const double* R, int64_t n, double rc, int* cnt, int* list, hipStream_t s);
+void launch_near_apply(const double* R, const double* x, const int* cnt, const int* list, int64_t n,
+                       const Phys& ph, double* y, hipStream_t s);
+
 int tile_block(Tile t);                      // receivers per workgroup actually used
 int split_for(int64_t n, Tile t, int tj);    // number of source chunks actually used
 int64_t part_elems_max(int64_t n);           // scratch size (doubles) covering every pass and shape

@@ -24,7 +24,7 @@ EXPORTS = ("mbs_default_params", "mbs_create", "mbs_destroy", "mbs_set_params", 
            "mbs_solve", "mbs_matvec", "mbs_rhs", "mbs_outputs", "mbs_step", "mbs_solve_batched",
            "mbs_autotune", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
            "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
-           "mbs_warmstart_load", "mbs_warmstart_target", "mbs_initial_guess")
+           "mbs_warmstart_load", "mbs_warmstart_target", "mbs_initial_guess", "mbs_precond_apply")
 MLP_NPARAM, MLP_NFEAT = 27525, 80
 
 
@@ -37,6 +37,7 @@ class MbsError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("a", ctypes.c_double), ("tol", ctypes.c_double),
                 ("self_slip_c", ctypes.c_double), ("inner_tol", ctypes.c_double),
+                ("near_cutoff", ctypes.c_double),
                 ("lmax", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("guess", ctypes.c_int32),
                 ("check_overlap", ctypes.c_int32), ("tile", ctypes.c_int32),
@@ -106,6 +107,8 @@ def load(path: str = LIB_PATH):
     lib.mbs_warmstart_save.argtypes = [P, ctypes.c_char_p]
     lib.mbs_warmstart_load.argtypes = [P, ctypes.c_char_p]
     lib.mbs_warmstart_target.argtypes = [P, I64] + [P] * 7 + [VP]
+    lib.mbs_precond_apply.argtypes = [P, I64, P, P, P, VP]
+    lib.mbs_precond_apply.restype = ctypes.c_int
     lib.mbs_initial_guess.argtypes = [P, I64] + [P] * 6 + [I32, P, VP]
     for name in ("mbs_warmstart_target", "mbs_initial_guess", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
                  "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
@@ -366,6 +369,16 @@ def _initial_guess(self, R, guess, p=None, v2s=None, v3t=None, Fe=None, Te=None)
     return out
 
 
+def _precond_apply(self, R, x):
+    import torch
+    n = R.shape[0]
+    y = torch.empty((n, 5), dtype=torch.float64, device=R.device)
+    self._check(self.lib.mbs_precond_apply(self.h, n, _ptr(R, n, 3, "R"), _ptr(x, n, 5, "x"),
+                                           _ptr(y, n, 5, "y"), _stream()))
+    return y
+
+
+Context.mbs_precond_apply = _precond_apply
 Context.mbs_warmstart_target = _ws_target
 Context.mbs_initial_guess = _initial_guess
 Context.mbs_features = _features

@@ -321,3 +321,38 @@ def test_matvec_full_size_sampled_rows(ctx):
     want = galerkin.matvec_rows(w.R, x, rows, prm)
     assert _maxrel(y[rows], want) < 1e-12
     assert _rel(y32[rows], want) < 5e-5
+
+
+# ---------------------------------------------------------------- near-field preconditioner
+def test_precond_apply_matches_oracle(ctx):
+    w = _workload(400, seed=21)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    rc = 7.0
+    x = np.random.default_rng(5).standard_normal((w.n, 5))
+    K = galerkin.pair_matrix(w.R, "E", "S", prm)
+    D = np.linalg.norm(w.R[:, None] - w.R[None], axis=2)
+    near = (D < rc) & (D > 0)
+    assert near.sum(1).max() <= 32
+    Kn = K * np.kron(near, np.ones((5, 5)))
+    g = galerkin.constants(prm)["gamma"]
+    want = (g * x.ravel() + g * g * (Kn @ x.ravel())).reshape(-1, 5)
+    ctx.set_params(near_cutoff=rc)
+    got = ctx.mbs_precond_apply(_t(w.R), _t(x))
+    ctx.set_params(near_cutoff=0.0)
+    assert _maxrel(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("precision", [mbstokes.MBS_FP64, mbstokes.MBS_MIXED])
+def test_preconditioned_solve_matches_oracle_in_fewer_iterations(ctx, precision):
+    w = inputs.config0()
+    ref = galerkin.solve(w)
+    d = mbstokes.to_device(w, DEV)
+    its = {}
+    for rc in (0.0, 6.0):
+        ctx.set_params(tol=1e-11, precision=precision, near_cutoff=rc, guess=mbstokes.MBS_GUESS_DIAG)
+        V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
+        tol = 1e-10 if precision == mbstokes.MBS_FP64 else 1e-9
+        assert _rel(V, ref["V"]) < tol and _rel(W, ref["W"]) < tol and _rel(S, ref["S"]) < tol
+        its[rc] = st["iters"]
+    ctx.set_params(tol=1e-10, precision=mbstokes.MBS_FP64, near_cutoff=0.0, guess=mbstokes.MBS_GUESS_ZERO)
+    assert its[6.0] < its[0.0], its
