@@ -38,8 +38,11 @@ def parse():
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--headline", default="mixed_learned",
-                    choices=["plain_fp64", "fp64_diag", "mixed_diag", "fp64_learned", "mixed_learned"])
+    ap.add_argument("--headline", default="mixed_learned_pc",
+                    choices=["plain_fp64", "fp64_diag", "mixed_diag", "fp64_learned", "mixed_learned",
+                             "fp64_pc", "mixed_pc", "mixed_learned_pc"])
+    ap.add_argument("--near-cutoff", type=float, default=6.0,
+                    help="near-field preconditioner cutoff (centre distance) of the *_pc variants")
     ap.add_argument("--skip-warmstart", action="store_true", help="no learned warm start (no training)")
     ap.add_argument("--warmstart-configs", type=int, default=200)
     ap.add_argument("--warmstart-epochs", type=int, default=10)
@@ -103,9 +106,9 @@ def measured_traffic(kernel, n):
     return rec.get("bytes_per_launch")
 
 
-def time_variant(ctx, d, mb, name, precision, guess, steps, warmup):
+def time_variant(ctx, d, mb, name, precision, guess, steps, warmup, near_cutoff=0.0):
     import torch
-    ctx.set_params(precision=precision, guess=guess, tol=1e-10)
+    ctx.set_params(precision=precision, guess=guess, tol=1e-10, near_cutoff=near_cutoff)
     args = (d["R"], d["p"], d["v1s"], d["v2s"], d.get("v3t"), d["Fe"], d.get("Te"))
     for k in range(warmup):
         ctx.mbs_solve(*args)
@@ -184,11 +187,12 @@ def bench_stepper(ctx, a):
 
     from paper_1411_0278_amd import inputs, mbstokes
     w = inputs.config1()
-    out = {"n": w.n, "steps": a.stepper_steps, "dt": 0.01}
+    out = {"n": w.n, "steps": a.stepper_steps, "dt": 0.01, "near_cutoff": a.near_cutoff,
+           "guess": "previous step's stresslet (first step: one-body)"}
     for name, prec in (("fp64", mbstokes.MBS_FP64), ("mixed", mbstokes.MBS_MIXED)):
         R = torch.as_tensor(w.R).to("cuda:0")
         p = torch.as_tensor(w.p).to("cuda:0")
-        ctx.set_params(precision=prec, guess=mbstokes.MBS_GUESS_USER, tol=1e-10)
+        ctx.set_params(precision=prec, guess=mbstokes.MBS_GUESS_USER, tol=1e-10, near_cutoff=a.near_cutoff)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         stats, md = ctx.mbs_step(R, p, 0.5, (1.0, 1.0, 1.0), 0.01, a.stepper_steps, order=2,
@@ -253,19 +257,23 @@ def main():
           file=sys.stderr, flush=True)
     variants = {}
     extra = {}
-    plan = [("plain_fp64", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_ZERO),
-            ("fp64_diag", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_DIAG),
-            ("mixed_diag", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG)]
+    rc = a.near_cutoff
+    plan = [("plain_fp64", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_ZERO, 0.0),
+            ("fp64_diag", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_DIAG, 0.0),
+            ("mixed_diag", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG, 0.0),
+            ("fp64_pc", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_DIAG, rc),
+            ("mixed_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG, rc)]
     if not a.skip_warmstart:
         from paper_1411_0278_amd import warmstart
         print("bench: training the warm-start network", file=sys.stderr, flush=True)
         rep = warmstart.train_pipeline(ctx, a.warmstart_configs, max(1, a.warmstart_configs // 20),
                                        a.warmstart_epochs,
                                        log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
-        plan += [("fp64_learned", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_LEARNED),
-                 ("mixed_learned", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_LEARNED)]
+        plan += [("fp64_learned", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_LEARNED, 0.0),
+                 ("mixed_learned", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_LEARNED, 0.0),
+                 ("mixed_learned_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_LEARNED, rc)]
         # surrogate error of the guesses against the converged solution of this workload
-        ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-12)
+        ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-12, near_cutoff=rc)
         sig = torch.empty((a.n, 5), dtype=torch.float64, device="cuda:0")
         ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None, Sigma=sig)
         rep["surrogate_rel_err"] = {
@@ -273,11 +281,12 @@ def main():
             "diag": warmstart.surrogate_error(ctx, d, sig, mbstokes.MBS_GUESS_DIAG),
             "learned": warmstart.surrogate_error(ctx, d, sig, mbstokes.MBS_GUESS_LEARNED)}
         extra["warmstart"] = rep
-    elif a.headline.endswith("learned"):
-        a.headline = "mixed_diag"
-    for name, prec, guess in plan:
+    elif "learned" in a.headline:
+        a.headline = "mixed_pc"
+    for name, prec, guess, cut in plan:
         steps = a.steps if name in (a.headline, "plain_fp64") else max(1, min(a.steps, 2))
-        variants[name] = time_variant(ctx, d, mbstokes, name, prec, guess, steps, a.warmup)
+        variants[name] = time_variant(ctx, d, mbstokes, name, prec, guess, steps, a.warmup, cut)
+        variants[name]["near_cutoff"] = cut
     if not a.skip_batched:
         extra["batched"] = bench_batched(ctx, a)
     if not a.skip_stepper:
@@ -298,7 +307,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"trap spheres N={a.n} cube side {a.side:g} seed {a.seed}, "
                                f"slip V1s=p V2s=3(pp-I/3), F=-0.5R, solve to 1e-10",
-                   "n": a.n, "headline": a.headline, "tol": 1e-10, "tiles": list(tiles)},
+                   "n": a.n, "headline": a.headline, "tol": 1e-10, "tiles": list(tiles),
+                   "near_cutoff": rc},
         "roofline": roofline(head, a.n),
         "time_to_1e-10_ms": {k: round(v["ms_per_step"], 3) for k, v in variants.items()},
         "iterations": {k: v["iters"] for k, v in variants.items()},
