@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--headline", default="mixed_learned_pc",
+    ap.add_argument("--headline", default="mixed_pc",
                     choices=["plain_fp64", "fp64_diag", "mixed_diag", "fp64_learned", "mixed_learned",
                              "fp64_pc", "mixed_pc", "mixed_learned_pc"])
     ap.add_argument("--near-cutoff", type=float, default=6.0,
@@ -182,32 +182,46 @@ def bench_batched(ctx, a):
 
 
 def bench_stepper(ctx, a):
-    """N = 1e4 trap, slip (V1s, V2s, V3t) = (p, 3(pp - I/3), p), Adams-Bashforth dt = 0.01."""
+    """N = 1e4 trap, slip (V1s, V2s, V3t) = (p, 3(pp - I/3), p), Adams-Bashforth dt = 0.01, as specified.
+
+    The specified trap is stiff for this box (k = 0.5 pulls the cloud in at speeds of order 100 and
+    nothing keeps spheres apart), so spheres overlap within a few steps; the run continues (each
+    step still solves the Galerkin system of the current positions) and reports the first overlap
+    step and how many steps met the tolerance. Per-step solve time comes from the library's events.
+    """
     import torch
 
     from paper_1411_0278_amd import inputs, mbstokes
     w = inputs.config1()
     out = {"n": w.n, "steps": a.stepper_steps, "dt": 0.01, "near_cutoff": a.near_cutoff,
-           "guess": "previous step's stresslet (first step: one-body)"}
+           "guess": "previous step's stresslet (first step: one-body)", "max_iter_per_step": 60}
     for name, prec in (("fp64", mbstokes.MBS_FP64), ("mixed", mbstokes.MBS_MIXED)):
         R = torch.as_tensor(w.R).to("cuda:0")
         p = torch.as_tensor(w.p).to("cuda:0")
-        ctx.set_params(precision=prec, guess=mbstokes.MBS_GUESS_USER, tol=1e-10, near_cutoff=a.near_cutoff)
+        ctx.set_params(precision=prec, guess=mbstokes.MBS_GUESS_USER, tol=1e-10, near_cutoff=a.near_cutoff,
+                       max_iter=60)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         stats, md = ctx.mbs_step(R, p, 0.5, (1.0, 1.0, 1.0), 0.01, a.stepper_steps, order=2,
                                  want_min_dist=True, allow_noconv=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        first_overlap = next((k for k, v in enumerate(md) if v < 2.0), None)
-        out[name] = {"seconds": dt, "ms_per_step": 1e3 * dt / max(1, len(stats)),
-                     "mean_iters": sum(s["iters"] for s in stats) / max(1, len(stats)),
-                     "fp64_matvecs": sum(s["fp64_matvecs"] for s in stats),
-                     "fp32_matvecs": sum(s["fp32_matvecs"] for s in stats),
-                     "max_rel_resid": max(s["rel_resid"] for s in stats),
-                     "first_overlap_step": first_overlap, "min_distance_last": md[-1] if md else None}
-        print(f"bench: stepper {name} {len(stats)} steps in {dt:.2f} s", file=sys.stderr, flush=True)
-    ctx.set_params(guess=mbstokes.MBS_GUESS_ZERO, precision=mbstokes.MBS_FP64)
+        done = [s for s in stats if s["t_total_ms"] > 0]
+        nd = len(done)
+        first_overlap = next((k for k, v in enumerate(md[:nd]) if v < 2.0), None)
+        phys = done[:first_overlap] if first_overlap is not None else done
+        out[name] = {"steps_completed": nd, "seconds": dt, "ms_per_step": 1e3 * dt / max(1, nd),
+                     "solve_ms_per_step_before_overlap": (sum(s["t_total_ms"] for s in phys) / len(phys))
+                     if phys else None,
+                     "iters_per_step_before_overlap": (sum(s["iters"] for s in phys) / len(phys)) if phys else None,
+                     "steps_converged": sum(1 for s in done if s["rel_resid"] <= 1e-10),
+                     "mean_iters": sum(s["iters"] for s in done) / max(1, nd),
+                     "fp64_matvecs": sum(s["fp64_matvecs"] for s in done),
+                     "fp32_matvecs": sum(s["fp32_matvecs"] for s in done),
+                     "first_overlap_step": first_overlap,
+                     "min_distance_last": md[nd - 1] if nd else None}
+        print(f"bench: stepper {name} {nd} steps in {dt:.2f} s", file=sys.stderr, flush=True)
+    ctx.set_params(guess=mbstokes.MBS_GUESS_ZERO, precision=mbstokes.MBS_FP64, max_iter=300)
     return out
 
 

@@ -167,7 +167,11 @@ int mbs_outputs(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, con
    then renormalises p (order 2 = Adams-Bashforth, forward Euler on the first step; order 1 =
    forward Euler throughout). R, p [n x 3] are updated in place. slip_coef: host array [3].
    per_step: host array [nsteps] or NULL. min_dist: host array [nsteps] or NULL, receives the
-   minimum centre distance of each step's configuration (overlaps are reported, not fatal). */
+   minimum centre distance of each step's configuration (overlaps are reported, not fatal).
+   With params.guess = MBS_GUESS_USER every step after the first starts from the previous step's
+   Sigma (the first from the one-body guess). A step whose solve stops short of params.tol still
+   advances and the call returns MBS_ENOCONV at the end; a non-finite residual stops the run
+   (steps not taken keep zeroed per_step entries). */
 int mbs_step(mbs_ctx* ctx, int64_t n, double* R, double* p, double k_trap, const double* slip_coef,
              double dt, int32_t nsteps, int32_t order, mbs_stats* per_step, double* min_dist,
              void* stream);

@@ -242,7 +242,7 @@ void norm2(mbs_ctx* c, const double* v, int64_t len, double* dev, hipStream_t s)
 // near-field preconditioner lists for the current positions
 void near_prepare(mbs_ctx* c, int64_t n, const double* R, hipStream_t s) {
   int* cntp = (int*)c->near.p;
-  launch_near_build(R, n, c->prm.near_cutoff, cntp, cntp + n, s);
+  launch_near_build(R, n, 2.0 * c->prm.a, c->prm.near_cutoff, cntp, cntp + n, s);
   c->near_ready = true;
 }
 void near_apply(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, hipStream_t s) {
@@ -843,6 +843,7 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
   int rc = count_nonfinite(c, s, {{R, 3 * n}, {p, 3 * n}}, &bad);
   if (rc == MBS_OK && bad) rc = set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
   const int guess0 = c->prm.guess;
+  bool noconv = false;
   for (int k = 0; k < nsteps && rc == MBS_OK; ++k) {
     launch_trap_modes(R, p, k_trap, slip_coef[0], slip_coef[1], slip_coef[2], Fe, v1s, v2s, v3t, n,
                       s);
@@ -860,8 +861,18 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
     c->prm.guess = guess0;
     if (rc != MBS_OK && rc != MBS_ENOCONV) break;
     if (per_step) per_step[k] = one;
+    // a step whose solve stopped short of the tolerance still advances (it is reported through
+    // per_step[k].rel_resid); a non-finite residual ends the run
+    if (!isfinite(one.rel_resid)) break;
     launch_ab_update(R, p, V, W, Vp, Pp, dt, k == 0, order, n, s);
-    if (rc == MBS_ENOCONV) break;
+    if (rc == MBS_ENOCONV) {
+      noconv = true;
+      rc = MBS_OK;
+    }
+  }
+  if (rc == MBS_OK && noconv) {
+    rc = MBS_ENOCONV;
+    set_err(c, MBS_ENOCONV, "some steps stopped short of the tolerance (see per-step rel_resid)");
   }
   hipError_t e = hipStreamSynchronize(s);
   if (st.p) (void)hipFree(st.p);

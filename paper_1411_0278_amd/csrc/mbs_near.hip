@@ -8,8 +8,10 @@
 // only the iteration count drops.
 //
 // Neighbour lists: an all-pairs scan (positions staged in LDS) keeps, for each sphere, the first
-// kNearCap other spheres within r_c in index order (deterministic); beyond that capacity the
-// preconditioner simply ignores the extra pairs.
+// kNearCap other spheres with 2a <= r < r_c in index order (deterministic); beyond that capacity
+// the preconditioner simply ignores the extra pairs. Overlapping pairs (r < 2a, unphysical but
+// reachable by a time stepper) stay out: their blocks grow like r^-5 and would make the truncated
+// Neumann series a poor, even harmful, approximation.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -24,7 +26,7 @@ namespace {
 constexpr int kTile = 256;
 
 __global__ void __launch_bounds__(256)
-    k_near_build(const double* __restrict__ R, int n, double rc2, int* __restrict__ cnt,
+    k_near_build(const double* __restrict__ R, int n, double rmin2, double rc2, int* __restrict__ cnt,
                  int* __restrict__ list) {
   __shared__ double tx[kTile], ty[kTile], tz[kTile];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -44,7 +46,7 @@ __global__ void __launch_bounds__(256)
       const double dx = xi - tx[jj], dy = yi - ty[jj], dz = zi - tz[jj];
       const double r2 = dx * dx + dy * dy + dz * dz;
       const int j = jt + jj;
-      if (j != ii && r2 < rc2 && c < kNearCap) {
+      if (j != ii && r2 >= rmin2 && r2 < rc2 && c < kNearCap) {
         if (i < n) list[(int64_t)i * kNearCap + c] = j;
         ++c;
       }
@@ -83,8 +85,10 @@ inline unsigned nblk(int64_t len, int b) { return (unsigned)((len + b - 1) / b);
 
 }  // namespace
 
-void launch_near_build(const double* R, int64_t n, double rc, int* cnt, int* list, hipStream_t s) {
-  hipLaunchKernelGGL(k_near_build, dim3(nblk(n, 256)), dim3(256), 0, s, R, (int)n, rc * rc, cnt, list);
+void launch_near_build(const double* R, int64_t n, double rmin, double rc, int* cnt, int* list,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_near_build, dim3(nblk(n, 256)), dim3(256), 0, s, R, (int)n, rmin * rmin, rc * rc,
+                     cnt, list);
 }
 
 void launch_near_apply(const double* R, const double* x, const int* cnt, const int* list, int64_t n,
