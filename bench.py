@@ -87,7 +87,7 @@ def profile_matvec(a, w):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("mbs_p2.hip", "mbs_device.h"):
+    for f in ("mbs_p2.hip", "mbs_pair.h", "mbs_device.h"):
         h.update(open(os.path.join(ROOT, "paper_1411_0278_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -17,6 +17,7 @@
 
 #include "../../include/mbstokes.h"
 #include "mbs_batched.h"
+#include "mbs_grid.h"
 #include "mbs_internal.h"
 #include "mbs_mlp.h"
 
@@ -59,6 +60,8 @@ struct mbs_ctx {
   bool mlp_ready = false;
   int adam_step = 0;
   DevBuf mlp_w, mlp_g, mlp_m, mlp_v, mlp_wb, mlp_ws, mlp_part, mlp_loss, mlp_idx, knn_buf;
+  // cell grid of the centres behind both neighbour searches (near-field lists, nearest neighbours)
+  DevBuf grid;
   // batched solver: workspace, capture stream and the four graphs of the last batch shape
   DevBuf bat;
   hipStream_t bstream = nullptr;
@@ -240,10 +243,25 @@ void norm2(mbs_ctx* c, const double* v, int64_t len, double* dev, hipStream_t s)
 // Stops when the residual estimate is <= tol_abs. With verify, the final residual is recomputed
 // with the operator and returned in *resid; otherwise *resid is the last estimate.
 // near-field preconditioner lists for the current positions
-void near_prepare(mbs_ctx* c, int64_t n, const double* R, hipStream_t s) {
+// cell grid of R with cell edge >= h_min and at most max_cells cells, in the context's workspace
+int grid_of(mbs_ctx* c, int64_t n, const double* R, double h_min, int64_t max_cells, GridView* g,
+            hipStream_t s) {
+  const size_t bytes = grid_ws_bytes((int)n, max_cells);
+  CHK(ensure(c, c->grid, bytes / 8 + 64));
+  HIPCHK(c, grid_build(R, (int)n, h_min, max_cells, c->grid.p, c->grid.cap * 8, g, s));
+  return MBS_OK;
+}
+
+// near-field preconditioner lists for the current positions (grid cells of edge >= r_c, at most
+// about two cells per sphere)
+int near_prepare(mbs_ctx* c, int64_t n, const double* R, hipStream_t s) {
+  GridView g;
+  CHK(grid_of(c, n, R, c->prm.near_cutoff, 2 * n + 64, &g, s));
   int* cntp = (int*)c->near.p;
-  launch_near_build(R, n, 2.0 * c->prm.a, c->prm.near_cutoff, cntp, cntp + n, s);
+  launch_near_build(g, R, 2.0 * c->prm.a, c->prm.near_cutoff, cntp, cntp + n, s);
+  HIPCHK(c, hipGetLastError());
   c->near_ready = true;
+  return MBS_OK;
 }
 void near_apply(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, hipStream_t s) {
   const int* cntp = (const int*)c->near.p;
@@ -461,16 +479,16 @@ void mlp_backward_rows(mbs_ctx* c, const float* target, const int32_t* idx, int 
   mlp_gemm(ws.H2, kMlpHid, true, ws.dOut, 16, false, ws.G2 /*scratch [128 x 16]*/, part, kMlpHid, 16,
            rp, ks, s);
   mlp_copy_cols(ws.G2, 16, kMlpHid, kMlpOut, g + kOffW3, s);
-  mlp_colsum(ws.dOut32, rows, kMlpOut, g + kOffB3, s);
+  mlp_colsum(ws.dOut32, rows, kMlpOut, g + kOffB3, part, s);
   // through layer 3
   mlp_gemm(ws.dOut, 16, false, W.W3, 16, true, ws.G2, part, rp, kMlpHid, 16, 1, s);
   mlp_relu_mask(ws.G2, ws.H2, (int64_t)rp * kMlpHid, ws.D2, ws.G2m, s);
-  mlp_colsum(ws.G2m, rp, kMlpHid, g + kOffB2, s);
+  mlp_colsum(ws.G2m, rp, kMlpHid, g + kOffB2, part, s);
   mlp_gemm(ws.H1, kMlpHid, true, ws.D2, kMlpHid, false, g + kOffW2, part, kMlpHid, kMlpHid, rp, ks, s);
   // through layer 2
   mlp_gemm(ws.D2, kMlpHid, false, W.W2, kMlpHid, true, ws.G1, part, rp, kMlpHid, kMlpHid, 1, s);
   mlp_relu_mask(ws.G1, ws.H1, (int64_t)rp * kMlpHid, ws.D1, ws.G1m, s);
-  mlp_colsum(ws.G1m, rp, kMlpHid, g + kOffB1, s);
+  mlp_colsum(ws.G1m, rp, kMlpHid, g + kOffB1, part, s);
   mlp_gemm(ws.X, kMlpIn, true, ws.D1, kMlpHid, false, g + kOffW1, part, kMlpIn, kMlpHid, rp, ks, s);
 }
 
@@ -490,8 +508,13 @@ int mlp_forward(mbs_ctx* c, int64_t m, const float* feat, float* out, hipStream_
 
 int knn_features(mbs_ctx* c, int64_t n, const double* R, const double* p, float* feat, int32_t* nbr,
                  hipStream_t s) {
-  launch_knn16(R, (int)n, nbr, s);
+  // cells of edge >= a holding about eight centres each: the 16th neighbour is usually inside the
+  // 27 cells around a sphere's own
+  GridView g;
+  CHK(grid_of(c, n, R, c->prm.a, std::max<int64_t>(64, n / 8), &g, s));
+  launch_knn16(g, nbr, s);
   launch_features(R, p, nbr, (int)n, feat, s);
+  HIPCHK(c, hipGetLastError());
   return MBS_OK;
 }
 
@@ -525,7 +548,7 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const do
   c->t_op[0] = c->t_op[1] = 0.0;
   c->near_ready = false;
   HIPCHK(c, hipEventRecord(c->ev[0], s));
-  if (c->prm.near_cutoff > 0.0) near_prepare(c, n, R, s);
+  if (c->prm.near_cutoff > 0.0) CHK(near_prepare(c, n, R, s));
   // right-hand side
   launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
   cnt.pairs += (double)n * (double)(n - 1);
@@ -695,7 +718,7 @@ void mbs_destroy(mbs_ctx* c) {
   DevBuf* bufs[] = {&c->V, &c->w, &c->r, &c->b, &c->xs, &c->dlt, &c->part, &c->dpart,
                     &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig, &c->near, &c->zt,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
-                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->bat};
+                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->bat};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& g : c->bgraph)
@@ -1447,7 +1470,7 @@ int mbs_precond_apply(mbs_ctx* c, int64_t n, const double* R, const double* x, d
   if (!(c->prm.near_cutoff > 0.0)) return set_err(c, MBS_EINVAL, "params.near_cutoff must be > 0");
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
-  near_prepare(c, n, R, s);
+  CHK(near_prepare(c, n, R, s));
   near_apply(c, n, R, x, y, s);
   c->near_ready = false;
   HIPCHK(c, hipGetLastError());

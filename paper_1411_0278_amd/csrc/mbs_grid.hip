@@ -1,0 +1,227 @@
+// Cell grid over the sphere centres (gfx950): bounding box, cell keys, stable radix sort by Morton
+// key, per-cell ranges and the centres in sorted order. Five small launches plus the sort; O(n).
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+#include <math.h>
+#include <stdint.h>
+
+#include "mbs_grid.h"
+
+namespace mbs {
+namespace {
+
+constexpr int kBoxParts = 256;  // workgroups of the bounding-box reduction (one per partial)
+constexpr int kKeyBits = 3 * kGridAxisBits;
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+inline unsigned nblk(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
+
+// 10-bit coordinate -> bits 0, 3, 6, ... of a 30-bit word, and back
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030c30c3u;
+  v = (v | (v >> 4)) & 0x0300f00fu;
+  v = (v | (v >> 8)) & 0x030000ffu;
+  v = (v | (v >> 16)) & 0x3ffu;
+  return v;
+}
+
+// per-workgroup min and max of the centres -> part[b][6]
+__global__ void __launch_bounds__(256) k_box_part(const double* __restrict__ R, int n, double* __restrict__ part) {
+  __shared__ double red[6][256];
+  double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double x = R[3 * (int64_t)i + d];
+      v[d] = fmin(v[d], x);
+      v[3 + d] = fmax(v[3 + d], x);
+    }
+  }
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) red[d][t] = v[d];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        red[d][t] = fmin(red[d][t], red[d][t + w]);
+        red[3 + d][t] = fmax(red[3 + d][t], red[3 + d][t + w]);
+      }
+    }
+    __syncthreads();
+  }
+  if (t < 6) part[6 * blockIdx.x + t] = red[t][0];
+}
+
+// bounding box -> cell edge and counts: edge >= h_min, at most max_cells cells, at most 1024 per axis
+__global__ void __launch_bounds__(256) k_grid_params(const double* __restrict__ part, double h_min,
+                                                     int64_t max_cells, GridHdr* __restrict__ hdr) {
+  __shared__ double red[6][kBoxParts];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) red[d][t] = part[6 * t + d];
+  __syncthreads();
+  for (int w = kBoxParts / 2; w > 0; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        red[d][t] = fmin(red[d][t], red[d][t + w]);
+        red[3 + d][t] = fmax(red[3 + d][t], red[3 + d][t + w]);
+      }
+    }
+    __syncthreads();
+  }
+  if (t != 0) return;
+  double lo[3], ext[3];
+  bool ok = true;
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = red[d][0];
+    ext[d] = red[3 + d][0] - red[d][0];
+    ok = ok && isfinite(lo[d]) && isfinite(ext[d]);
+  }
+  GridHdr H;
+  int g[3] = {1, 1, 1};
+  double h = 1.0;
+  if (ok) {
+    const double emax = fmax(ext[0], fmax(ext[1], ext[2]));
+    // a relative margin keeps pairs closer than h_min within one cell of each other after rounding
+    h = fmax(h_min, emax / (double)((1 << kGridAxisBits) - 1)) * (1.0 + 1e-9);
+    h = fmax(h, cbrt(fmax(ext[0], h) * fmax(ext[1], h) * fmax(ext[2], h) / (double)max_cells));
+    for (int it = 0; it < 512; ++it) {
+      for (int d = 0; d < 3; ++d) g[d] = (int)(ext[d] / h) + 1;
+      if ((int64_t)g[0] * g[1] * g[2] <= max_cells) break;
+      h *= 1.0905077326652577;  // 2^(1/8)
+    }
+    if ((int64_t)g[0] * g[1] * g[2] > max_cells) g[0] = g[1] = g[2] = 1;
+  } else {
+    lo[0] = lo[1] = lo[2] = 0.0;
+  }
+  for (int d = 0; d < 3; ++d) {
+    H.lo[d] = lo[d];
+    H.g[d] = g[d];
+  }
+  H.h = h;
+  H.inv_h = 1.0 / h;
+  H.pad = 0;
+  *hdr = H;
+}
+
+__global__ void k_cell_keys(const double* __restrict__ R, int n, const GridHdr* __restrict__ hdr,
+                            uint32_t* __restrict__ key, int32_t* __restrict__ idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const GridHdr H = *hdr;
+  const int cx = grid_cell1(R[3 * (int64_t)i], H.lo[0], H.inv_h, H.g[0]);
+  const int cy = grid_cell1(R[3 * (int64_t)i + 1], H.lo[1], H.inv_h, H.g[1]);
+  const int cz = grid_cell1(R[3 * (int64_t)i + 2], H.lo[2], H.inv_h, H.g[2]);
+  key[i] = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+  idx[i] = i;
+}
+
+__global__ void k_clear_cells(int32_t* __restrict__ start, int32_t* __restrict__ end, int64_t cells) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cells) return;
+  start[c] = 0;
+  end[c] = 0;
+}
+
+__global__ void k_cell_ranges(const uint32_t* __restrict__ key, const int32_t* __restrict__ perm,
+                              const double* __restrict__ R, int n, const GridHdr* __restrict__ hdr,
+                              int32_t* __restrict__ start, int32_t* __restrict__ end, double* __restrict__ Rs) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const GridHdr H = *hdr;
+  const uint32_t kk = key[k];
+  const int64_t i = perm[k];
+  Rs[4 * (int64_t)k] = R[3 * i];
+  Rs[4 * (int64_t)k + 1] = R[3 * i + 1];
+  Rs[4 * (int64_t)k + 2] = R[3 * i + 2];
+  Rs[4 * (int64_t)k + 3] = 0.0;
+  const int c = grid_linear(H, (int)compact3(kk), (int)compact3(kk >> 1), (int)compact3(kk >> 2));
+  if (k == 0 || key[k - 1] != kk) start[c] = k;
+  if (k == n - 1 || key[k + 1] != kk) end[c] = k + 1;
+}
+
+struct Layout {
+  size_t hdr, part, key_in, key, idx_in, perm, Rs, start, end, tmp, tmp_bytes, total;
+};
+
+Layout layout(int n, int64_t max_cells) {
+  Layout L{};
+  size_t o = 0;
+  L.hdr = o;
+  o += align256(sizeof(GridHdr));
+  L.part = o;
+  o += align256(sizeof(double) * 6 * kBoxParts);
+  L.key_in = o;
+  o += align256(sizeof(uint32_t) * n);
+  L.key = o;
+  o += align256(sizeof(uint32_t) * n);
+  L.idx_in = o;
+  o += align256(sizeof(int32_t) * n);
+  L.perm = o;
+  o += align256(sizeof(int32_t) * n);
+  L.Rs = o;
+  o += align256(sizeof(double) * 4 * n);
+  L.start = o;
+  o += align256(sizeof(int32_t) * max_cells);
+  L.end = o;
+  o += align256(sizeof(int32_t) * max_cells);
+  size_t tb = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (const int32_t*)nullptr, (int32_t*)nullptr, n, 0, kKeyBits);
+  L.tmp = o;
+  L.tmp_bytes = align256(tb) + 256;
+  o += L.tmp_bytes;
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+size_t grid_ws_bytes(int n, int64_t max_cells) { return layout(n, max_cells).total; }
+
+hipError_t grid_build(const double* R, int n, double h_min, int64_t max_cells, void* ws, size_t ws_bytes,
+                      GridView* view, hipStream_t s) {
+  if (n < 1 || max_cells < 1 || !(h_min > 0.0)) return hipErrorInvalidValue;
+  const Layout L = layout(n, max_cells);
+  if (ws_bytes < L.total) return hipErrorInvalidValue;
+  char* b = (char*)ws;
+  GridHdr* hdr = (GridHdr*)(b + L.hdr);
+  double* part = (double*)(b + L.part);
+  uint32_t* key_in = (uint32_t*)(b + L.key_in);
+  uint32_t* key = (uint32_t*)(b + L.key);
+  int32_t* idx_in = (int32_t*)(b + L.idx_in);
+  int32_t* perm = (int32_t*)(b + L.perm);
+  double* Rs = (double*)(b + L.Rs);
+  int32_t* start = (int32_t*)(b + L.start);
+  int32_t* end = (int32_t*)(b + L.end);
+  hipLaunchKernelGGL(k_box_part, dim3(kBoxParts), dim3(256), 0, s, R, n, part);
+  hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(kBoxParts), 0, s, part, h_min, max_cells, hdr);
+  hipLaunchKernelGGL(k_cell_keys, dim3(nblk(n, 256)), dim3(256), 0, s, R, n, hdr, key_in, idx_in);
+  size_t tb = L.tmp_bytes;
+  hipError_t e = hipcub::DeviceRadixSort::SortPairs((void*)(b + L.tmp), tb, key_in, key, idx_in, perm, n, 0,
+                                                    kKeyBits, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_clear_cells, dim3(nblk(max_cells, 256)), dim3(256), 0, s, start, end, max_cells);
+  hipLaunchKernelGGL(k_cell_ranges, dim3(nblk(n, 256)), dim3(256), 0, s, key, perm, R, n, hdr, start, end, Rs);
+  view->hdr = hdr;
+  view->Rs = Rs;
+  view->perm = perm;
+  view->start = start;
+  view->end = end;
+  view->n = n;
+  return hipGetLastError();
+}
+
+}  // namespace mbs

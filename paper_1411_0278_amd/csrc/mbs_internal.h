@@ -53,7 +53,9 @@ void launch_count_nonfinite(const double* a, int64_t len, int* cnt, hipStream_t 
 // near-field preconditioner: neighbour lists within rc (at most kNearCap per sphere) and
 // y = gamma x + gamma^2 K_near x
 constexpr int kNearCap = 32;
-void launch_near_build(const double* R, int64_t n, double rmin, double rc, int* cnt, int* list,
+// (lists from a cell grid of the centres with cell edge >= rc)
+struct GridView;
+void launch_near_build(const GridView& g, const double* R, double rmin, double rc, int* cnt, int* list,
                        hipStream_t s);
 void launch_near_apply(const double* R, const double* x, const int* cnt, const int* list, int64_t n,
                        const Phys& ph, double* y, hipStream_t s);

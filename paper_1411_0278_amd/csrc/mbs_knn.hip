@@ -1,67 +1,84 @@
 // Neighbourhood features of the learned warm start (gfx950): the 16 nearest other centres of every
-// sphere by an all-pairs scan (the same all-pairs traversal as the operator: positions staged in LDS
-// tiles, one receiver per thread), kept as a sorted list of (distance^2, index) in registers; ties
-// are broken by the smaller index so the result is unique. Features per neighbour, nearest first:
-// (R_j - R_i)/|R_j - R_i|, 1/|R_j - R_i|, p_j . p_i.
+// sphere from a search of the cell grid, kept as a sorted list of (distance^2, index) in registers;
+// ties are broken by the smaller index so the result is unique. Features per neighbour, nearest
+// first: (R_j - R_i)/|R_j - R_i|, 1/|R_j - R_i|, p_j . p_i.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
+#include "mbs_grid.h"
 #include "mbs_mlp.h"
 
 namespace mbs {
 namespace {
 
-constexpr int kTile = 256;
-
 __device__ __forceinline__ bool before(double d, int j, double bd, int bj) {
   return d < bd || (d == bd && j < bj);
 }
 
-__global__ void __launch_bounds__(256) k_knn16(const double* __restrict__ R, int n, int32_t* __restrict__ nbr) {
-  __shared__ double tx[kTile], ty[kTile], tz[kTile];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ii = i < n ? i : n - 1;
-  const double xi = R[3 * (int64_t)ii], yi = R[3 * (int64_t)ii + 1], zi = R[3 * (int64_t)ii + 2];
+// One sphere per thread, threads in cell (Morton) order so a wavefront scans overlapping cells.
+// The cells are visited in shells of growing Chebyshev radius s around the sphere's own cell; a
+// sphere in a cell outside shell s is at least s*h away, so the search ends once the 16th distance
+// is below that bound (or every cell has been visited).
+__global__ void __launch_bounds__(256) k_knn16(GridView G, int32_t* __restrict__ nbr) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= G.n) return;
+  const GridHdr H = *G.hdr;
+  const int i = G.perm[k];
+  const double xi = G.Rs[4 * (int64_t)k], yi = G.Rs[4 * (int64_t)k + 1], zi = G.Rs[4 * (int64_t)k + 2];
+  const int cx = grid_cell1(xi, H.lo[0], H.inv_h, H.g[0]);
+  const int cy = grid_cell1(yi, H.lo[1], H.inv_h, H.g[1]);
+  const int cz = grid_cell1(zi, H.lo[2], H.inv_h, H.g[2]);
+  const int smax = max(max(max(cx, H.g[0] - 1 - cx), max(cy, H.g[1] - 1 - cy)), max(cz, H.g[2] - 1 - cz));
   double bd[kNeigh];
   int bj[kNeigh];
 #pragma unroll
-  for (int k = 0; k < kNeigh; ++k) {
-    bd[k] = INFINITY;
-    bj[k] = 0x7fffffff;
+  for (int q = 0; q < kNeigh; ++q) {
+    bd[q] = INFINITY;
+    bj[q] = 0x7fffffff;
   }
-  for (int jt = 0; jt < n; jt += kTile) {
-    const int cnt = min(kTile, n - jt);
-    __syncthreads();
-    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-      tx[t] = R[3 * (int64_t)(jt + t)];
-      ty[t] = R[3 * (int64_t)(jt + t) + 1];
-      tz[t] = R[3 * (int64_t)(jt + t) + 2];
-    }
-    __syncthreads();
-    for (int jj = 0; jj < cnt; ++jj) {
-      const int j = jt + jj;
-      const double dx = tx[jj] - xi, dy = ty[jj] - yi, dz = tz[jj] - zi;
-      const double d2 = dx * dx + dy * dy + dz * dz;
-      if (j != ii && before(d2, j, bd[kNeigh - 1], bj[kNeigh - 1])) {
-        double d = d2;
-        int id = j;
+  for (int sh = 0; sh <= smax; ++sh) {
+    for (int dz = -sh; dz <= sh; ++dz) {
+      const int z = cz + dz;
+      if (z < 0 || z >= H.g[2]) continue;
+      for (int dy = -sh; dy <= sh; ++dy) {
+        const int y = cy + dy;
+        if (y < 0 || y >= H.g[1]) continue;
+        // rows inside the shell contribute only their two end cells
+        const int step = (sh > 0 && abs(dz) < sh && abs(dy) < sh) ? 2 * sh : 1;
+        for (int dx = -sh; dx <= sh; dx += step) {
+          const int x = cx + dx;
+          if (x < 0 || x >= H.g[0]) continue;
+          const int c = grid_linear(H, x, y, z);
+          const int e = G.end[c];
+          for (int k2 = G.start[c]; k2 < e; ++k2) {
+            const int j = G.perm[k2];
+            const double ddx = G.Rs[4 * (int64_t)k2] - xi, ddy = G.Rs[4 * (int64_t)k2 + 1] - yi,
+                         ddz = G.Rs[4 * (int64_t)k2 + 2] - zi;
+            const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            if (j != i && before(d2, j, bd[kNeigh - 1], bj[kNeigh - 1])) {
+              double d = d2;
+              int id = j;
 #pragma unroll
-        for (int k = 0; k < kNeigh; ++k) {  // insert, keeping the list sorted
-          const bool lt = before(d, id, bd[k], bj[k]);
-          const double od = bd[k];
-          const int oj = bj[k];
-          bd[k] = lt ? d : od;
-          bj[k] = lt ? id : oj;
-          d = lt ? od : d;
-          id = lt ? oj : id;
+              for (int q = 0; q < kNeigh; ++q) {  // insert, keeping the list sorted
+                const bool lt = before(d, id, bd[q], bj[q]);
+                const double od = bd[q];
+                const int oj = bj[q];
+                bd[q] = lt ? d : od;
+                bj[q] = lt ? id : oj;
+                d = lt ? od : d;
+                id = lt ? oj : id;
+              }
+            }
+          }
         }
       }
     }
+    const double reach = sh * H.h * (1.0 - 1e-9);
+    if (bd[kNeigh - 1] < reach * reach) break;
   }
-  if (i >= n) return;
 #pragma unroll
-  for (int k = 0; k < kNeigh; ++k) nbr[(int64_t)i * kNeigh + k] = bj[k];
+  for (int q = 0; q < kNeigh; ++q) nbr[(int64_t)i * kNeigh + q] = bj[q];
 }
 
 __global__ void k_features(const double* __restrict__ R, const double* __restrict__ p,
@@ -105,8 +122,8 @@ void launch_target(const double* Sig, const double* b, double gamma, int64_t len
   hipLaunchKernelGGL(k_target, dim3(nblk(len, 256)), dim3(256), 0, s, Sig, b, gamma, len, t);
 }
 
-void launch_knn16(const double* R, int n, int32_t* nbr, hipStream_t s) {
-  hipLaunchKernelGGL(k_knn16, dim3(nblk(n, 256)), dim3(256), 0, s, R, n, nbr);
+void launch_knn16(const GridView& g, int32_t* nbr, hipStream_t s) {
+  hipLaunchKernelGGL(k_knn16, dim3(nblk(g.n, 256)), dim3(256), 0, s, g, nbr);
 }
 
 void launch_features(const double* R, const double* p, const int32_t* nbr, int n, float* feat,

@@ -29,14 +29,17 @@ void mlp_mse_grad(const float* C, const float* b3, const float* T, const int32_t
                   hipStream_t s);
 void mlp_relu_mask(const float* G, const uint16_t* H, int64_t len, uint16_t* D, float* G32,
                    hipStream_t s);
-void mlp_colsum(const float* M, int rows, int cols, float* out, hipStream_t s);
+// column sums of M [rows x cols] -> out [cols]; partial: scratch of min(256, ceil(rows/128)) x cols floats
+void mlp_colsum(const float* M, int rows, int cols, float* out, float* partial, hipStream_t s);
 void mlp_copy_cols(const float* src, int ldsrc, int rows, int cols, float* dst, hipStream_t s);
 void mlp_adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
               float eps, int step, hipStream_t s);
 void mlp_weights_bf16(const float* w, uint16_t* W1, uint16_t* W2, uint16_t* W3, hipStream_t s);
 
-// 16 nearest other centres of every sphere (ties by index), nearest first: nbr [n x 16]
-void launch_knn16(const double* R, int n, int32_t* nbr, hipStream_t s);
+// 16 nearest other centres of every sphere (ties by index), nearest first: nbr [n x 16], from a
+// cell grid of the centres
+struct GridView;
+void launch_knn16(const GridView& g, int32_t* nbr, hipStream_t s);
 // features [n x 80] float32 from the neighbour lists
 void launch_features(const double* R, const double* p, const int32_t* nbr, int n, float* feat,
                      hipStream_t s);

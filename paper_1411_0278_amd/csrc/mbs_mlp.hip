@@ -8,6 +8,8 @@
 // C[4(l/16) .. 4(l/16)+3][l % 16]. Long K (weight gradients, K = batch) is split over grid.z into
 // partial tiles that a second kernel adds in a fixed order, so every result is reproducible.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -129,12 +131,19 @@ __global__ void k_relu_mask(const float* __restrict__ G, const uint16_t* __restr
 }
 
 // out[c] = sum_r M[r, c] (fixed order; one thread per column)
-__global__ void k_colsum(const float* __restrict__ M, int rows, int cols, float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// column sums of M [rows x cols], stage 1: workgroup (column block, row chunk) -> partial[chunk][col]
+__global__ void __launch_bounds__(256) k_colsum_part(const float* __restrict__ M, int rows, int cols,
+                                                     int chunk, float* __restrict__ partial) {
+  __shared__ float red[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + tx;
+  const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += M[(int64_t)r * cols + c];
-  out[c] = s;
+  if (c < cols)
+    for (int r = r0 + ty; r < r1; r += 4) s += M[(int64_t)r * cols + c];
+  red[ty][tx] = s;
+  __syncthreads();
+  if (ty == 0 && c < cols) partial[(int64_t)blockIdx.y * cols + c] = ((red[0][tx] + red[1][tx]) + red[2][tx]) + red[3][tx];
 }
 
 // copy the [rows x ldsrc] float tile's first cols columns into dst [rows x cols]
@@ -218,8 +227,13 @@ void mlp_relu_mask(const float* G, const uint16_t* H, int64_t len, uint16_t* D, 
   hipLaunchKernelGGL(k_relu_mask, dim3(nblk(len, 256)), dim3(256), 0, s, G, H, len, D, G32);
 }
 
-void mlp_colsum(const float* M, int rows, int cols, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3(nblk(cols, 64)), dim3(64), 0, s, M, rows, cols, out);
+void mlp_colsum(const float* M, int rows, int cols, float* out, float* partial, hipStream_t s) {
+  const int parts = std::max(1, std::min(256, (rows + 127) / 128));
+  const int chunk = (rows + parts - 1) / parts;
+  hipLaunchKernelGGL(k_colsum_part, dim3(nblk(cols, 64), parts), dim3(256), 0, s, M, rows, cols, chunk,
+                     partial);
+  hipLaunchKernelGGL(k_sum_partials, dim3(nblk(cols, 256)), dim3(256), 0, s, partial, parts, (int64_t)cols,
+                     out);
 }
 
 void mlp_copy_cols(const float* src, int ldsrc, int rows, int cols, float* dst, hipStream_t s) {

@@ -7,9 +7,9 @@
 // costs one sparse pass over a few neighbours per sphere. The solution x = M^{-1} u is unchanged;
 // only the iteration count drops.
 //
-// Neighbour lists: an all-pairs scan (positions staged in LDS) keeps, for each sphere, the first
-// kNearCap other spheres with 2a <= r < r_c in index order (deterministic); beyond that capacity
-// the preconditioner simply ignores the extra pairs. Overlapping pairs (r < 2a, unphysical but
+// Neighbour lists: a search of the cell grid keeps, for each sphere, the kNearCap other spheres of
+// smallest index with 2a <= r < r_c, in index order (deterministic); beyond that capacity the
+// preconditioner simply ignores the extra pairs. Overlapping pairs (r < 2a, unphysical but
 // reachable by a time stepper) stay out: their blocks grow like r^-5 and would make the truncated
 // Neumann series a poor, even harmful, approximation.
 #include <hip/hip_runtime.h>
@@ -17,17 +17,29 @@
 #include <stdint.h>
 
 #include "mbs_device.h"
+#include "mbs_grid.h"
 #include "mbs_internal.h"
 #include "mbs_pair.h"
 
 namespace mbs {
 namespace {
 
+// Grids with fewer cells than this are crowded (a collapsed cluster: most spheres within r_c of
+// most others); there an all-pairs scan through LDS is cheaper than walking the cells, so the build
+// launches both kernels and each returns at once unless the grid is of its kind.
+constexpr int kDenseCells = 128;
 constexpr int kTile = 256;
 
-__global__ void __launch_bounds__(256)
-    k_near_build(const double* __restrict__ R, int n, double rmin2, double rc2, int* __restrict__ cnt,
-                 int* __restrict__ list) {
+__device__ __forceinline__ bool grid_dense(const GridHdr* hdr) {
+  return (int64_t)hdr->g[0] * hdr->g[1] * hdr->g[2] < kDenseCells;
+}
+
+// All-pairs variant: sources in index order, so the first kNearCap partners are the smallest.
+__global__ void __launch_bounds__(256) k_near_build_dense(const double* __restrict__ R, int n,
+                                                          const GridHdr* __restrict__ hdr, double rmin2,
+                                                          double rc2, int* __restrict__ cnt,
+                                                          int* __restrict__ list) {
+  if (!grid_dense(hdr)) return;
   __shared__ double tx[kTile], ty[kTile], tz[kTile];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int ii = i < n ? i : n - 1;
@@ -53,6 +65,56 @@ __global__ void __launch_bounds__(256)
     }
   }
   if (i < n) cnt[i] = c;
+}
+
+// One sphere per thread, threads in cell (Morton) order. The cell edge is at least r_c, so every
+// partner lies in the 27 cells around the sphere's own. The list is a sorted register array that
+// keeps the kNearCap smallest partner indices (an insertion network, taken only by candidates
+// below the current largest), so a crowded neighbourhood costs one compare per extra candidate.
+__global__ void __launch_bounds__(256)
+    k_near_build(GridView G, double rmin2, double rc2, int* __restrict__ cnt, int* __restrict__ list) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= G.n || grid_dense(G.hdr)) return;
+  const GridHdr H = *G.hdr;
+  const int i = G.perm[k];
+  const double xi = G.Rs[4 * (int64_t)k], yi = G.Rs[4 * (int64_t)k + 1], zi = G.Rs[4 * (int64_t)k + 2];
+  const int cx = grid_cell1(xi, H.lo[0], H.inv_h, H.g[0]);
+  const int cy = grid_cell1(yi, H.lo[1], H.inv_h, H.g[1]);
+  const int cz = grid_cell1(zi, H.lo[2], H.inv_h, H.g[2]);
+  int L[kNearCap];
+#pragma unroll
+  for (int q = 0; q < kNearCap; ++q) L[q] = 0x7fffffff;
+  int c = 0;
+  for (int z = max(cz - 1, 0); z <= min(cz + 1, H.g[2] - 1); ++z)
+    for (int y = max(cy - 1, 0); y <= min(cy + 1, H.g[1] - 1); ++y)
+      for (int x = max(cx - 1, 0); x <= min(cx + 1, H.g[0] - 1); ++x) {
+        const int cell = grid_linear(H, x, y, z);
+        const int e = G.end[cell];
+        for (int k2 = G.start[cell]; k2 < e; ++k2) {
+          const int j = G.perm[k2];
+          const double dx = xi - G.Rs[4 * (int64_t)k2], dy = yi - G.Rs[4 * (int64_t)k2 + 1],
+                       dz = zi - G.Rs[4 * (int64_t)k2 + 2];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (j == i || !(r2 >= rmin2 && r2 < rc2)) continue;
+          ++c;
+          if (j < L[kNearCap - 1]) {
+            int v = j;
+#pragma unroll
+            for (int q = 0; q < kNearCap; ++q) {
+              const bool lt = v < L[q];
+              const int o = L[q];
+              L[q] = lt ? v : o;
+              v = lt ? o : v;
+            }
+          }
+        }
+      }
+  c = min(c, kNearCap);
+  int* out = list + (int64_t)i * kNearCap;
+#pragma unroll
+  for (int q = 0; q < kNearCap; ++q)
+    if (q < c) out[q] = L[q];
+  cnt[i] = c;
 }
 
 // y = gamma x + gamma^2 K_near x
@@ -85,10 +147,11 @@ inline unsigned nblk(int64_t len, int b) { return (unsigned)((len + b - 1) / b);
 
 }  // namespace
 
-void launch_near_build(const double* R, int64_t n, double rmin, double rc, int* cnt, int* list,
+void launch_near_build(const GridView& g, const double* R, double rmin, double rc, int* cnt, int* list,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_near_build, dim3(nblk(n, 256)), dim3(256), 0, s, R, (int)n, rmin * rmin, rc * rc,
-                     cnt, list);
+  hipLaunchKernelGGL(k_near_build, dim3(nblk(g.n, 256)), dim3(256), 0, s, g, rmin * rmin, rc * rc, cnt, list);
+  hipLaunchKernelGGL(k_near_build_dense, dim3(nblk(g.n, 256)), dim3(256), 0, s, R, g.n, g.hdr, rmin * rmin,
+                     rc * rc, cnt, list);
 }
 
 void launch_near_apply(const double* R, const double* x, const int* cnt, const int* list, int64_t n,

@@ -342,6 +342,56 @@ def test_precond_apply_matches_oracle(ctx):
     assert _maxrel(got, want) < 1e-13
 
 
+def _near_reference(R, x, rc, a, prm, cap=32):
+    """gamma x + gamma^2 K_near x with K_near over the pairs 2a <= r < rc, each sphere keeping the
+    cap partners of smallest index; blocks from the oracle's pair block for exactly those pairs."""
+    from oracle import greens
+    g = galerkin.constants(prm)["gamma"]
+    out = g * x.copy()
+    counts = []
+    for i in range(len(R)):
+        D = np.linalg.norm(R[i] - R, axis=1)
+        js = [j for j in np.nonzero((D >= 2 * a) & (D < rc))[0] if j != i][:cap]
+        counts.append(len(js))
+        if js:
+            blk = greens.block("E", "S", R[i] - R[js], prm.a, prm.eta)
+            out[i] += g * g * np.einsum("kab,kb->a", blk, x[js])
+    return out, np.array(counts)
+
+
+@pytest.mark.parametrize("case", ["lattice_rc_on_shell", "lattice_over_capacity", "overlapping_pair", "lone",
+                                  "cells_over_capacity"])
+def test_precond_apply_hard_geometries(ctx, case):
+    """Pairs exactly at r_c are out (strict), lists over capacity keep the 32 smallest indices,
+    overlapping pairs are out, a lone sphere gets gamma x. The small sets take the all-pairs build
+    (few grid cells), the 14^3 lattice the cell walk."""
+    print(f"precond geometry={case}", flush=True)
+    a = 1.0
+    prm = galerkin.Params(eta=1 / (6 * np.pi), a=a)
+    lat = np.array([[x, y, z] for x in range(6) for y in range(6) for z in range(6)], float) * 2.5
+    if case == "lattice_rc_on_shell":
+        R, rc = lat, 5.0
+    elif case == "lattice_over_capacity":
+        R, rc = lat, 5.6
+    elif case == "cells_over_capacity":
+        R, rc = np.array([[x, y, z] for x in range(14) for y in range(14) for z in range(14)], float) * 2.5, 5.6
+    elif case == "overlapping_pair":
+        R = np.r_[lat[:60], [[0.0, 0.0, 1.5]]]
+        rc = 6.0
+    else:
+        R, rc = np.zeros((1, 3)), 6.0
+    x = np.random.default_rng(6).standard_normal((len(R), 5))
+    want, counts = _near_reference(R, x, rc, a, prm)
+    if case.endswith("over_capacity"):
+        assert counts.max() == 32
+    ctx.set_params(near_cutoff=rc)
+    try:
+        got = ctx.mbs_precond_apply(_t(R), _t(x))
+    finally:
+        ctx.set_params(near_cutoff=0.0)
+    assert _maxrel(got, want) < 1e-13
+
+
 @pytest.mark.parametrize("precision", [mbstokes.MBS_FP64, mbstokes.MBS_MIXED])
 def test_preconditioned_solve_matches_oracle_in_fewer_iterations(ctx, precision):
     w = inputs.config0()

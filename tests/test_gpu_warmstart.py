@@ -46,6 +46,35 @@ def test_features_match_oracle(ctx, n):
     assert np.abs(feat.cpu().numpy() - f_or).max() <= 1e-6 * np.abs(f_or).max()
 
 
+def _geometry(name):
+    """Centre sets that stress the cell-grid search: exact distance ties, a flat or a linear set
+    (one cell across), far-apart clusters with an isolated outlier, the smallest n."""
+    rng = np.random.default_rng(11)
+    if name == "lattice":
+        return np.array([[x, y, z] for x in range(7) for y in range(7) for z in range(7)], float) * 3.0
+    if name == "flat":
+        return np.c_[rng.uniform(-40, 40, (400, 2)), np.zeros(400)]
+    if name == "line":
+        return np.c_[np.arange(60) * 2.5, np.zeros(60), np.zeros(60)]
+    if name == "clusters":
+        return np.r_[rng.normal(0, 4, (250, 3)), rng.normal(300, 4, (250, 3)), [[1500.0, -700.0, 9.0]]]
+    if name == "n17":
+        return rng.uniform(-6, 6, (17, 3))
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["lattice", "flat", "line", "clusters", "n17"])
+def test_neighbours_match_oracle_on_hard_geometries(ctx, name):
+    print(f"features geometry={name}", flush=True)
+    Rn = _geometry(name)
+    pn = np.random.default_rng(12).standard_normal(Rn.shape)
+    pn /= np.linalg.norm(pn, axis=1, keepdims=True)
+    feat, nbr = ctx.mbs_features(torch.as_tensor(Rn).to(DEV), torch.as_tensor(pn).to(DEV), want_nbr=True)
+    f_or, nb_or = mlp.features(Rn, pn)
+    assert np.array_equal(nbr.cpu().numpy(), nb_or)
+    assert np.abs(feat.cpu().numpy() - f_or).max() <= 1e-6 * np.abs(f_or).max()
+
+
 def _random_params(seed):
     rng = np.random.default_rng(seed)
     P = {}
