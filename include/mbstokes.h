@@ -74,7 +74,8 @@ typedef struct mbs_params {
   double  tol;           /* stop when ||b - A Sigma||_2 / ||b||_2 <= tol (binary64 residual) */
   double  self_slip_c;   /* c in "- c s_n": 1 = lone sphere meets its strain slip exactly;
                             1.4 reproduces the paper's one-body stresslet table */
-  double  inner_tol;     /* MBS_MIXED: relative tolerance of each inner binary32 GMRES solve */
+  double  inner_tol;     /* MBS_MIXED: relative tolerance of each inner binary32 GMRES solve (an
+                            inner solve also stops once its residual is below 0.3 tol |b|) */
   double  near_cutoff;   /* > 0: right-precondition GMRES with M^{-1} = gamma (I + gamma K_near), K_near
                             the operator's blocks of pairs closer than near_cutoff (centre distance;
                             at most 32 neighbours per sphere); 0 = no preconditioner (default).
