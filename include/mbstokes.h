@@ -100,11 +100,15 @@ typedef struct mbs_stats {
   double  rel_resid;      /* final ||b - A Sigma||_2 / ||b||_2, evaluated in binary64 */
   double  t_total_ms;     /* device time of the whole call */
   double  t_rhs_ms;       /* right-hand side pass */
-  double  t_iter_ms;      /* guess + iterations + refinement residuals */
-  double  t_out_ms;       /* rigid-body output pass */
+  double  t_iter_ms;      /* guess + iterations + refinement residuals (with the fused pass) */
+  double  t_out_ms;       /* the pass that produced the rigid-body outputs */
   double  pair_blocks;    /* pair-block evaluations performed (all passes) */
   double  t_op64_ms;      /* summed device time of the binary64 operator applications */
   double  t_op32_ms;      /* summed device time of the binary32 operator applications */
+  int32_t out_fused;      /* 1: the final binary64 residual and the outputs came from one fused pass
+                             over the pairs (not counted in fp64_matvecs / t_op64_ms); 0: separate
+                             output pass */
+  int32_t reserved;
 } mbs_stats;
 
 typedef struct mbs_ctx mbs_ctx;

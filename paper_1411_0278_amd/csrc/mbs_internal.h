@@ -45,6 +45,11 @@ void launch_p1(const double* R, const double* v2s, const double* v3t, const doub
 void launch_p3(const double* R, const double* v1s, const double* v2s, const double* v3t,
                const double* Fe, const double* Te, const double* Sig, double* V, double* W,
                double* S, double* part, int64_t n, const Phys& ph, Tile t, hipStream_t s);
+// the output pass fused with one binary64 operator application on the same Sigma:
+// V, W, S as launch_p3 and y = Sigma/gamma - E[Sigma]; part: scratch [split x 11n] doubles
+void launch_p23(const double* R, const double* v1s, const double* v2s, const double* v3t,
+                const double* Fe, const double* Te, const double* Sig, double* y, double* V, double* W,
+                double* S, double* part, int64_t n, const Phys& ph, Tile t, hipStream_t s);
 // min over pairs of |R_n - R_m|^2 -> out[0] (device); scratch: blocks doubles
 void launch_min_dist2(const double* R, int64_t n, double* out, double* scratch, hipStream_t s);
 // count non-finite entries of a device array -> atomically added to *cnt (device int)

@@ -112,6 +112,43 @@ __global__ void k_p1_finish(const double* __restrict__ part, const double* __res
 }
 
 // ------------------------------------------------------------------ P3: rigid-body outputs
+// One source record of the output pass: position, P-scaled force, torque and stresslet
+// (Cartesian), (a^5/10)-scaled rank-3 trace mode.
+template <bool HAS_T, bool HAS_D>
+__device__ __forceinline__ RecO make_reco(const double* __restrict__ R, const double* __restrict__ Fe,
+                                          const double* __restrict__ Te, const double* __restrict__ Sig,
+                                          const double* __restrict__ D, int j, double P, double a5_10) {
+  RecO rc;
+  rc.x = R[3 * (int64_t)j];
+  rc.y = R[3 * (int64_t)j + 1];
+  rc.z = R[3 * (int64_t)j + 2];
+  rc.fx = P * Fe[3 * (int64_t)j];
+  rc.fy = P * Fe[3 * (int64_t)j + 1];
+  rc.fz = P * Fe[3 * (int64_t)j + 2];
+  if (HAS_T) {
+    rc.tx = P * Te[3 * (int64_t)j];
+    rc.ty = P * Te[3 * (int64_t)j + 1];
+    rc.tz = P * Te[3 * (int64_t)j + 2];
+  } else {
+    rc.tx = rc.ty = rc.tz = 0.0;
+  }
+  double sxx, syy, sxy, sxz, syz;
+  basis_to_cart(Sig + 5 * (int64_t)j, sxx, syy, sxy, sxz, syz);
+  rc.sxx = P * sxx;
+  rc.syy = P * syy;
+  rc.sxy = P * sxy;
+  rc.sxz = P * sxz;
+  rc.syz = P * syz;
+  if (HAS_D) {
+    rc.dx = a5_10 * D[3 * (int64_t)j];
+    rc.dy = a5_10 * D[3 * (int64_t)j + 1];
+    rc.dz = a5_10 * D[3 * (int64_t)j + 2];
+  } else {
+    rc.dx = rc.dy = rc.dz = 0.0;
+  }
+  rc.pad = 0.0;
+  return rc;
+}
 template <int TJ, bool HAS_T, bool HAS_D>
 __global__ void __launch_bounds__(kMaxBlock)
     k_p3(const double* __restrict__ R, const double* __restrict__ Fe, const double* __restrict__ Te,
@@ -128,39 +165,8 @@ __global__ void __launch_bounds__(kMaxBlock)
   for (int jt = j0; jt < j1; jt += TJ) {
     const int cnt = min(TJ, j1 - jt);
     __syncthreads();
-    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-      const int j = jt + t;
-      RecO rc;
-      rc.x = R[3 * j];
-      rc.y = R[3 * j + 1];
-      rc.z = R[3 * j + 2];
-      rc.fx = P * Fe[3 * j];
-      rc.fy = P * Fe[3 * j + 1];
-      rc.fz = P * Fe[3 * j + 2];
-      if (HAS_T) {
-        rc.tx = P * Te[3 * j];
-        rc.ty = P * Te[3 * j + 1];
-        rc.tz = P * Te[3 * j + 2];
-      } else {
-        rc.tx = rc.ty = rc.tz = 0.0;
-      }
-      double sxx, syy, sxy, sxz, syz;
-      basis_to_cart(Sig + 5 * j, sxx, syy, sxy, sxz, syz);
-      rc.sxx = P * sxx;
-      rc.syy = P * syy;
-      rc.sxy = P * sxy;
-      rc.sxz = P * sxz;
-      rc.syz = P * syz;
-      if (HAS_D) {
-        rc.dx = a5_10 * D[3 * j];
-        rc.dy = a5_10 * D[3 * j + 1];
-        rc.dz = a5_10 * D[3 * j + 2];
-      } else {
-        rc.dx = rc.dy = rc.dz = 0.0;
-      }
-      rc.pad = 0.0;
-      tile[t] = rc;
-    }
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x)
+      tile[t] = make_reco<HAS_T, HAS_D>(R, Fe, Te, Sig, D, jt + t, P, a5_10);
     __syncthreads();
 #pragma unroll 2
     for (int jj = 0; jj < cnt; ++jj) p3_pair<HAS_T, HAS_D>(tile[jj], xi, yi, zi, A2_2, A2_23, A8, B16, acc);
@@ -193,6 +199,93 @@ __global__ void k_p3_finish(const double* __restrict__ part, int split, int64_t 
   for (int c = 0; c < 3; ++c) {
     V[3 * i + c] = acc[c] + mu_t * Fe[3 * i + c] - (v1s ? v1s[3 * i + c] : 0.0);
     W[3 * i + c] = acc[3 + c] + (Te ? mu_r * Te[3 * i + c] : 0.0);
+  }
+  if (S) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) S[5 * i + c] = Sig[5 * i + c] + (v2s ? slip_S * v2s[5 * i + c] : 0.0);
+  }
+}
+
+// ------------------------------------------------------------------ fused output + operator pass
+// The output pass and one binary64 operator application on the same stresslet share the pair
+// geometry (separation, powers of 1/r, w = Sigma x, q = x.w), so one pass yields both the rigid-body
+// sums and y = Sigma/gamma - E[Sigma]: used for the final residual of a solve. Per receiver and
+// source chunk it stores the 5 strain components then the 6 velocity/rotation sums.
+template <int TJ, bool HAS_T, bool HAS_D>
+__global__ void __launch_bounds__(kMaxBlock)
+    k_p23(const double* __restrict__ R, const double* __restrict__ Fe, const double* __restrict__ Te,
+          const double* __restrict__ Sig, const double* __restrict__ D, double* __restrict__ out,
+          int n, int chunk, double P, double a2, double a5_10) {
+  __shared__ RecO tile[TJ];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const int b0 = blockIdx.x * blockDim.x;
+  const int b1 = min(n, b0 + (int)blockDim.x);
+  const double xi = R[3 * (int64_t)ii], yi = R[3 * (int64_t)ii + 1], zi = R[3 * (int64_t)ii + 2];
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  const double A2_2 = 2.0 * a2, A2_23 = 2.0 * a2 / 3.0, A8 = 8.0 * a2, B16 = -3.2 * a2;
+  const double A24 = 24.0 * a2, A42 = 42.0 * a2;
+  UW acc;
+  Mom<double> m;
+  for (int jt = j0; jt < j1; jt += TJ) {
+    const int cnt = min(TJ, j1 - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x)
+      tile[t] = make_reco<HAS_T, HAS_D>(R, Fe, Te, Sig, D, jt + t, P, a5_10);
+    __syncthreads();
+    const bool self = jt < b1 && jt + cnt > b0;  // uniform: only these tiles can hold r = 0
+    if (self) {
+      for (int jj = 0; jj < cnt; ++jj) {
+        Geo g;
+        pair_geo<true>(tile[jj], xi, yi, zi, g);
+        p3_acc<HAS_T, HAS_D>(tile[jj], g, A2_2, A2_23, A8, B16, acc);
+        p2_acc(tile[jj], g, A24, A42, m);
+      }
+    } else {
+      for (int jj = 0; jj < cnt; ++jj) {
+        Geo g;
+        pair_geo<false>(tile[jj], xi, yi, zi, g);
+        p3_acc<HAS_T, HAS_D>(tile[jj], g, A2_2, A2_23, A8, B16, acc);
+        p2_acc(tile[jj], g, A24, A42, m);
+      }
+    }
+  }
+  if (i >= n) return;
+  const double v[11] = {m.pxx, m.pyy, m.pzz, m.qxy, m.qxz, m.qyz, m.t0, m.t1, m.t2, m.t3, m.t4};
+  double e[5];
+  p2_strain(v, 1.0, a2, e);
+  double* o = out + (int64_t)blockIdx.y * 11 * n + 11 * (int64_t)i;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) o[c] = e[c];
+  o[5] = acc.ux;
+  o[6] = acc.uy;
+  o[7] = acc.uz;
+  o[8] = acc.wx;
+  o[9] = acc.wy;
+  o[10] = acc.wz;
+}
+
+__global__ void k_p23_finish(const double* __restrict__ part, int split, int64_t n,
+                             const double* __restrict__ v1s, const double* __restrict__ v2s,
+                             const double* __restrict__ Fe, const double* __restrict__ Te,
+                             const double* __restrict__ Sig, double* __restrict__ y,
+                             double* __restrict__ V, double* __restrict__ W, double* __restrict__ S,
+                             double inv_gamma, double mu_t, double mu_r, double slip_S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int s = 0; s < split; ++s) {
+    const double* p = part + (int64_t)s * 11 * n + 11 * i;
+#pragma unroll
+    for (int c = 0; c < 11; ++c) acc[c] += p[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) y[5 * i + c] = Sig[5 * i + c] * inv_gamma - acc[c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    V[3 * i + c] = acc[5 + c] + mu_t * Fe[3 * i + c] - (v1s ? v1s[3 * i + c] : 0.0);
+    W[3 * i + c] = acc[8 + c] + (Te ? mu_r * Te[3 * i + c] : 0.0);
   }
   if (S) {
 #pragma unroll
@@ -515,6 +608,30 @@ void launch_p3(const double* R, const double* v1s, const double* v2s, const doub
 #undef MBS_P3
   hipLaunchKernelGGL(k_p3_finish, dim3(nblk(n, 256)), dim3(256), 0, s, part, split, n, v1s, v2s, Fe,
                      Te, Sig, V, W, S, ph.mu_t, ph.mu_r, ph.slip_S);
+}
+
+void launch_p23(const double* R, const double* v1s, const double* v2s, const double* v3t,
+                const double* Fe, const double* Te, const double* Sig, double* y, double* V, double* W,
+                double* S, double* part, int64_t n, const Phys& ph, Tile t, hipStream_t s) {
+  constexpr int TJ = 128;
+  const int bs = tile_block(t);
+  const int split = split_for(n, t, TJ);
+  const int chunk = (int)((n + split - 1) / split);
+  dim3 grid(nblk(n, bs), split);
+#define MBS_P23(HT, HD)                                                                          \
+  hipLaunchKernelGGL((k_p23<TJ, HT, HD>), grid, dim3(bs), 0, s, R, Fe, Te, Sig, v3t, part, (int)n, \
+                     chunk, ph.P, ph.a2, ph.a5_10)
+  if (Te && v3t)
+    MBS_P23(true, true);
+  else if (Te)
+    MBS_P23(true, false);
+  else if (v3t)
+    MBS_P23(false, true);
+  else
+    MBS_P23(false, false);
+#undef MBS_P23
+  hipLaunchKernelGGL(k_p23_finish, dim3(nblk(n, 256)), dim3(256), 0, s, part, split, n, v1s, v2s, Fe, Te,
+                     Sig, y, V, W, S, ph.inv_gamma, ph.mu_t, ph.mu_r, ph.slip_S);
 }
 
 void launch_min_dist2(const double* R, int64_t n, double* out, double* scratch, hipStream_t s) {

@@ -321,12 +321,13 @@ int split_for(int64_t n, Tile t, int tj) {
 }
 
 int64_t part_elems_max(int64_t n) {
-  int64_t m = 6 * n;
+  // up to 11 values per receiver and chunk (the fused output + operator pass)
+  int64_t m = 11 * n;
   for (int k = 0; k < kTileCount; ++k) {
     const Tile& t = kTileTable[k];
     for (int tj : {64, 128, 256}) {
       const int s = split_for(n, t, tj);
-      if (s > 1) m = std::max<int64_t>(m, (int64_t)s * 6 * n);
+      if (s > 1) m = std::max<int64_t>(m, (int64_t)s * 11 * n);
     }
   }
   return m;

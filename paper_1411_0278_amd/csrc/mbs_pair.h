@@ -72,20 +72,34 @@ struct UW {
   double ux = 0, uy = 0, uz = 0, wx = 0, wy = 0, wz = 0;
 };
 
-template <bool HAS_T, bool HAS_D>
-__device__ __forceinline__ void p3_pair(const RecO& s, double xi, double yi, double zi, double A2_2,
-                                        double A2_23, double A8, double B16, UW& a) {
-  const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-  const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-  const double ri = rinv_or_zero(r2);
-  const double ri2 = ri * ri;
-  const double ri3 = ri2 * ri;
-  const double ri5 = ri3 * ri2;
+// Pair geometry shared by the output pass and the fused output + operator pass: separation, powers
+// of 1/r (all zero for r = 0 when SELF) and w = Sigma x, q = x.w of the source stresslet.
+struct Geo {
+  double dx, dy, dz, ri, ri2, ri3, ri5, wx, wy, wz, q;
+};
+
+template <bool SELF>
+__device__ __forceinline__ void pair_geo(const RecO& s, double xi, double yi, double zi, Geo& g) {
+  g.dx = xi - s.x;
+  g.dy = yi - s.y;
+  g.dz = zi - s.z;
+  const double r2 = fma(g.dx, g.dx, fma(g.dy, g.dy, g.dz * g.dz));
+  g.ri = SELF ? rinv_or_zero(r2) : rsq_nr(r2);
+  g.ri2 = g.ri * g.ri;
+  g.ri3 = g.ri2 * g.ri;
+  g.ri5 = g.ri3 * g.ri2;
   const double szz = -(s.sxx + s.syy);
-  const double wx = fma(s.sxx, dx, fma(s.sxy, dy, s.sxz * dz));
-  const double wy = fma(s.sxy, dx, fma(s.syy, dy, s.syz * dz));
-  const double wz = fma(s.sxz, dx, fma(s.syz, dy, szz * dz));
-  const double q = fma(dx, wx, fma(dy, wy, dz * wz));
+  g.wx = fma(s.sxx, g.dx, fma(s.sxy, g.dy, s.sxz * g.dz));
+  g.wy = fma(s.sxy, g.dx, fma(s.syy, g.dy, s.syz * g.dz));
+  g.wz = fma(s.sxz, g.dx, fma(s.syz, g.dy, szz * g.dz));
+  g.q = fma(g.dx, g.wx, fma(g.dy, g.wy, g.dz * g.wz));
+}
+
+template <bool HAS_T, bool HAS_D>
+__device__ __forceinline__ void p3_acc(const RecO& s, const Geo& g, double A2_2, double A2_23, double A8,
+                                       double B16, UW& a) {
+  const double dx = g.dx, dy = g.dy, dz = g.dz, ri = g.ri, ri2 = g.ri2, ri3 = g.ri3, ri5 = g.ri5;
+  const double wx = g.wx, wy = g.wy, wz = g.wz, q = g.q;
   const double xF = fma(dx, s.fx, fma(dy, s.fy, dz * s.fz));
   double cx = xF * fma(-A2_2, ri5, ri3) + q * ri5 * fma(A8, ri2, -3.0);
   const double cF = fma(A2_23, ri3, ri);
@@ -117,6 +131,14 @@ __device__ __forceinline__ void p3_pair(const RecO& s, double xi, double yi, dou
     a.uy = fma(-ri3, s.dy, a.uy);
     a.uz = fma(-ri3, s.dz, a.uz);
   }
+}
+
+template <bool HAS_T, bool HAS_D>
+__device__ __forceinline__ void p3_pair(const RecO& s, double xi, double yi, double zi, double A2_2,
+                                        double A2_23, double A8, double B16, UW& a) {
+  Geo g;
+  pair_geo<true>(s, xi, yi, zi, g);
+  p3_acc<HAS_T, HAS_D>(s, g, A2_2, A2_23, A8, B16, a);
 }
 
 // ---------------------------------------------------------------- P2: the system operator
@@ -159,6 +181,28 @@ __device__ __forceinline__ void p2_pair(const Src8<T>& s, T xi, T yi, T zi, T A2
   m.t2 = fma(ri5, s.sxy, m.t2);
   m.t3 = fma(ri5, s.sxz, m.t3);
   m.t4 = fma(ri5, s.syz, m.t4);
+}
+
+// Operator sums of one pair (the arithmetic of p2_pair) from the geometry already formed for the
+// output pass; the record's stresslet carries the factor P, so the projection takes P = 1.
+__device__ __forceinline__ void p2_acc(const RecO& s, const Geo& g, double A24, double A42, Mom<double>& m) {
+  const double ri7 = g.ri5 * g.ri2;
+  const double c1 = g.ri5 * fma(A24, g.ri2, -6.0);
+  const double c2 = g.q * ri7 * fma(-A42, g.ri2, 15.0);
+  const double vx = fma(c1, g.wx, c2 * g.dx);
+  const double vy = fma(c1, g.wy, c2 * g.dy);
+  const double vz = fma(c1, g.wz, c2 * g.dz);
+  m.pxx = fma(g.dx, vx, m.pxx);
+  m.pyy = fma(g.dy, vy, m.pyy);
+  m.pzz = fma(g.dz, vz, m.pzz);
+  m.qxy = fma(g.dx, vy, fma(g.dy, vx, m.qxy));
+  m.qxz = fma(g.dx, vz, fma(g.dz, vx, m.qxz));
+  m.qyz = fma(g.dy, vz, fma(g.dz, vy, m.qyz));
+  m.t0 = fma(g.ri5, s.sxx, m.t0);
+  m.t1 = fma(g.ri5, s.syy, m.t1);
+  m.t2 = fma(g.ri5, s.sxy, m.t2);
+  m.t3 = fma(g.ri5, s.sxz, m.t3);
+  m.t4 = fma(g.ri5, s.syz, m.t4);
 }
 
 // E[x] at one receiver in the 5-basis from the operator sums (11 values, see Mom)

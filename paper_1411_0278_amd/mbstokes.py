@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
                 ("rel_resid", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("t_rhs_ms", ctypes.c_double), ("t_iter_ms", ctypes.c_double),
                 ("t_out_ms", ctypes.c_double), ("pair_blocks", ctypes.c_double),
-                ("t_op64_ms", ctypes.c_double), ("t_op32_ms", ctypes.c_double)]
+                ("t_op64_ms", ctypes.c_double), ("t_op32_ms", ctypes.c_double),
+                ("out_fused", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -41,7 +41,7 @@ def test_default_params_and_struct_layout():
     assert p.lmax == 2 and p.restart == 30 and abs(p.tol - 1e-10) < 1e-25
     assert abs(p.eta * 6 * 3.141592653589793 - 1) < 1e-15 and p.a == 1.0
     assert ctypes.sizeof(mbstokes.Params) == 6 * 8 + 8 * 4
-    assert ctypes.sizeof(mbstokes.Stats) == 4 * 4 + 8 * 8
+    assert ctypes.sizeof(mbstokes.Stats) == 4 * 4 + 8 * 8 + 2 * 4
 
 
 def test_create_without_gpu_fails_cleanly():

@@ -170,6 +170,7 @@ def test_solve_config0_fp64(ctx, guess):
     for got, want in ((V, ref["V"]), (W, ref["W"]), (S, ref["S"]), (Sig, ref["Sigma"])):
         assert _rel(got, want) < 1e-10
     assert st["rel_resid"] <= 1e-12 and st["iters"] < 30
+    assert st["out_fused"] == 1  # the verified final residual also produced the outputs
     ctx.set_params(tol=1e-10, guess=mbstokes.MBS_GUESS_ZERO)
 
 
@@ -184,6 +185,32 @@ def test_solve_mixed_precision(ctx):
     for got, want in ((V, ref["V"]), (W, ref["W"]), (S, ref["S"]), (Sig, ref["Sigma"])):
         assert _rel(got, want) < 1e-9
     assert st["rel_resid"] <= 1e-11 and st["refinements"] >= 1 and st["fp32_matvecs"] > 0
+
+
+@pytest.mark.parametrize("precision", [mbstokes.MBS_FP64, mbstokes.MBS_MIXED])
+@pytest.mark.parametrize("torque", [False, True])
+def test_fused_final_pass_matches_separate_passes(ctx, precision, torque):
+    """The final residual fused with the output pass: its outputs equal the separate output pass on
+    the returned stresslet, and the reported residual equals b - A Sigma formed from the separate
+    right-hand side and operator passes."""
+    print(f"fused final pass precision={precision} torque={torque}", flush=True)
+    w = _workload(500, seed=31, torque=torque)
+    d = mbstokes.to_device(w, DEV)
+    ctx.set_params(tol=1e-10, precision=precision, guess=mbstokes.MBS_GUESS_DIAG)
+    try:
+        Sig = torch.empty((w.n, 5), dtype=torch.float64, device=DEV)
+        V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"], Sigma=Sig)
+    finally:
+        ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO)
+    assert st["out_fused"] == 1
+    gV, gW, gS = ctx.mbs_outputs(d["R"], Sig, d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
+    assert _maxrel(V, gV.cpu().numpy()) < 1e-13
+    assert _maxrel(W, gW.cpu().numpy()) < 1e-13
+    assert _maxrel(S, gS.cpu().numpy()) < 1e-14
+    b = ctx.mbs_rhs(d["R"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
+    r = b - ctx.mbs_matvec(d["R"], Sig)
+    rel = float(r.norm() / b.norm())
+    assert abs(rel - st["rel_resid"]) <= 1e-3 * rel + 1e-15
 
 
 def test_solve_user_guess_and_restarts(ctx):
