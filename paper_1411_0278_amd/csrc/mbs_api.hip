@@ -975,6 +975,11 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
     for (int r = off[b]; r < off[b + 1]; r += 64) items.push_back(make_int2(b, r));
     for (int r = off[b]; r < off[b + 1]; ++r) cid[r] = b;
   }
+  // largest configurations first: an item's work is its configuration's size, and workgroups start
+  // in index order, so the long items start early and the short ones fill the tail of each pass
+  std::stable_sort(items.begin(), items.end(), [&](const int2& u, const int2& v) {
+    return off[u.x + 1] - off[u.x] > off[v.x + 1] - off[v.x];
+  });
   const int nitems = (int)items.size();
   // workspace (bytes, 256-aligned pieces)
   const int64_t len = 5 * ntot64;

@@ -111,6 +111,7 @@ __global__ void __launch_bounds__(kItem)
   const double xi = rec[ii].x, yi = rec[ii].y, zi = rec[ii].z;
   const double A8 = 8.0 * a2, B16 = -3.2 * a2;
   Mom6 m;
+#pragma unroll 2
   for (int j = o0; j < o1; ++j) p1_pair<HAS_T, HAS_D>(rec[j], xi, yi, zi, A8, B16, m);
   if (i >= o1) return;
   double e[5];
@@ -134,8 +135,10 @@ __global__ void __launch_bounds__(kItem)
   const double A24 = 24.0 * a2, A42 = 42.0 * a2;
   Mom<double> m;
   const int s0 = it.y, s1 = min(o1, it.y + kItem);  // sources that can be the receiver itself
+#pragma unroll 2
   for (int j = o0; j < s0; ++j) p2_pair<double, false>(src[j], xi, yi, zi, A24, A42, m);
   for (int j = s0; j < s1; ++j) p2_pair<double, true>(src[j], xi, yi, zi, A24, A42, m);
+#pragma unroll 2
   for (int j = s1; j < o1; ++j) p2_pair<double, false>(src[j], xi, yi, zi, A24, A42, m);
   if (i >= o1) return;
   const double* x = X + (kdev ? (int64_t)kdev[0] * ld : 0);
@@ -160,6 +163,7 @@ __global__ void __launch_bounds__(kItem)
   const double xi = rec[ii].x, yi = rec[ii].y, zi = rec[ii].z;
   const double A2_2 = 2.0 * a2, A2_23 = 2.0 * a2 / 3.0, A8 = 8.0 * a2, B16 = -3.2 * a2;
   UW a;
+#pragma unroll 2
   for (int j = o0; j < o1; ++j) p3_pair<HAS_T, HAS_D>(rec[j], xi, yi, zi, A2_2, A2_23, A8, B16, a);
   if (i >= o1) return;
   const double u[6] = {a.ux, a.uy, a.uz, a.wx, a.wy, a.wz};
