@@ -163,22 +163,28 @@ def bench_batched(ctx, a):
     R, v1s, v2s, Fe = cat("R"), cat("v1s"), cat("v2s"), cat("Fe")
     print(f"bench: batched workload of {len(ws)} configurations ({int(off[-1])} spheres) built in "
           f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-10)
-    ctx.mbs_solve_batched(off, R, v1s, v2s, None, Fe, None)      # capture + warm-up
-    torch.cuda.synchronize()
-    reps = 3
-    t1 = time.perf_counter()
-    for _ in range(reps):
-        V, W, S, stats, lat = ctx.mbs_solve_batched(off, R, v1s, v2s, None, Fe, None)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t1) / reps
-    lat = np.array(lat)
-    pairs = sum(st["pair_blocks"] for st in stats)
-    return {"configs": len(ws), "spheres": int(off[-1]), "ms_per_batch": 1e3 * dt,
-            "configs_per_s": len(ws) / dt, "pair_blocks_per_s": pairs / dt,
-            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
-            "max_iters": int(max(st["iters"] for st in stats)),
-            "max_rel_resid": float(max(st["rel_resid"] for st in stats))}
+    def run(rc):
+        ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-10, near_cutoff=rc)
+        ctx.mbs_solve_batched(off, R, v1s, v2s, None, Fe, None)      # capture + warm-up
+        torch.cuda.synchronize()
+        reps = 3
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            V, W, S, stats, lat = ctx.mbs_solve_batched(off, R, v1s, v2s, None, Fe, None)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / reps
+        lat = np.array(lat)
+        pairs = sum(st["pair_blocks"] for st in stats)
+        return {"configs": len(ws), "spheres": int(off[-1]), "near_cutoff": rc, "ms_per_batch": 1e3 * dt,
+                "configs_per_s": len(ws) / dt, "pair_blocks_per_s": pairs / dt,
+                "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+                "max_iters": int(max(st["iters"] for st in stats)),
+                "max_rel_resid": float(max(st["rel_resid"] for st in stats))}
+
+    out = run(a.near_cutoff)
+    out["without_preconditioner"] = run(0.0)
+    ctx.set_params(near_cutoff=0.0)
+    return out
 
 
 def bench_stepper(ctx, a):

@@ -64,8 +64,8 @@ extern "C" {
 #define MBS_GUESS_ZERO     0   /* Sigma^0 = 0 */
 #define MBS_GUESS_DIAG     1   /* Sigma^0 = gamma b: the one-body (diagonal) solve of the system */
 #define MBS_GUESS_LEARNED  2   /* Sigma^0 = gamma b + net(neighbourhood features); needs a network
-                                  (mbs_warmstart_init/set/load/train), p and n >= 17; in
-                                  mbs_solve_batched it falls back to MBS_GUESS_DIAG */
+                                  (mbs_warmstart_init/set/load/train), p and n >= 17
+                                  (mbs_solve_batched always starts from zero) */
 #define MBS_GUESS_USER     3   /* Sigma^0 = the caller's sigma0 */
 
 typedef struct mbs_params {
@@ -78,8 +78,10 @@ typedef struct mbs_params {
                             inner solve also stops once its residual is below 0.3 tol |b|) */
   double  near_cutoff;   /* > 0: right-precondition GMRES with M^{-1} = gamma (I + gamma K_near), K_near
                             the operator's blocks of pairs closer than near_cutoff (centre distance;
-                            at most 32 neighbours per sphere); 0 = no preconditioner (default).
-                            The solution is unchanged; mbs_solve_batched ignores it. */
+                            at most 32 neighbours per sphere, the smallest indices; pairs closer
+                            than 2a are left out); 0 = no preconditioner (default). The solution
+                            is unchanged. Applies to mbs_solve, mbs_step and mbs_solve_batched
+                            (there within each configuration). */
   int32_t lmax;          /* traction truncation rank; only 2 (force, torque, stresslet) */
   int32_t max_iter;      /* cap on GMRES iterations (all restarts, inner iterations included) */
   int32_t restart;       /* GMRES restart length m, 1..64 */
@@ -181,7 +183,8 @@ int mbs_step(mbs_ctx* ctx, int64_t n, double* R, double* p, double k_trap, const
              double dt, int32_t nsteps, int32_t order, mbs_stats* per_step, double* min_dist,
              void* stream);
 
-/* Many independent configurations in one call (binary64, zero initial guess). Configuration b owns
+/* Many independent configurations in one call (binary64, zero initial guess, near-field
+   preconditioner when params.near_cutoff > 0). Configuration b owns
    rows offsets[b] .. offsets[b+1]-1 of the concatenated device arrays (same meaning as in mbs_solve).
    offsets: HOST array [nconf + 1], offsets[0] = 0, strictly increasing. All configurations advance
    together: each pass (right-hand side, operator, Gram-Schmidt, Givens, outputs) is one launch over

@@ -996,6 +996,10 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
                oit = reserve(nconf * 4), ot0 = reserve(nconf * 8), ot1 = reserve(nconf * 8),
                okd = reserve(16), ocnt = reserve(16), ooff = reserve((nconf + 1) * 4),
                oitems = reserve((size_t)nitems * 8), ocid = reserve((size_t)ntot * 4);
+  // near-field preconditioner: lists (counts, then kNearCap entries per sphere) and two vectors
+  const bool pc = c->prm.near_cutoff > 0.0;
+  const size_t onear = pc ? reserve((size_t)ntot * (kNearCap + 1) * 4) : 0,
+               ozt = pc ? reserve(len * 8) : 0, out_ = pc ? reserve(len * 8) : 0;
   CHK(ensure(c, c->bat, bytes / 8 + 64));
   char* base = (char*)c->bat.p;
   double* Vb = (double*)(base + oV);
@@ -1024,6 +1028,11 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   int* doff = (int*)(base + ooff);
   int2* ditems = (int2*)(base + oitems);
   int* dcid = (int*)(base + ocid);
+  int* ncnt = pc ? (int*)(base + onear) : nullptr;
+  int* nlist = pc ? ncnt + ntot : nullptr;
+  double* zt = pc ? (double*)(base + ozt) : nullptr;
+  double* ut = pc ? (double*)(base + out_) : nullptr;
+  const double near_rc = c->prm.near_cutoff, near_rmin = 2.0 * c->prm.a;
   HIPCHK(c, hipMemcpyAsync(doff, off.data(), (nconf + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(ditems, items.data(), nitems * sizeof(int2), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(dcid, cid.data(), ntot * sizeof(int), hipMemcpyHostToDevice, s));
@@ -1042,6 +1051,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
     batched_set_ints(st.status, nconf, kActive, q);
     batched_pack_f(R, Fe, Te, v3t, ph, (RecF*)rec, ntot, q);
     batched_p1(ditems, nitems, doff, (const RecF*)rec, v2s, has_t, has_d, ph, bv, q);
+    if (pc) batched_near_build(ditems, nitems, doff, R, near_rmin, near_rc, ncnt, nlist, q);
     batched_fill(xv, 0.0, len, q);
     batched_dots(bv, 0, nullptr, 1, bv, doff, st.status, kActive, st.nsq, 1, nconf, q);
     batched_init(st, nconf, m, q);
@@ -1050,8 +1060,16 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   };
   auto phase_iter = [&](hipStream_t q) {
     for (int it = 0; it < C; ++it) {
-      batched_pack_s(R, Vb, kdev, m - 1, len, (Src8<double>*)rec, ntot, q);
-      batched_p2(ditems, nitems, doff, st.status, kActive, (const Src8<double>*)rec, Vb, kdev, len, ph, wv, q);
+      if (pc) {  // right preconditioning: w = A M^{-1} v_k
+        launch_near_apply(R, Vb, ncnt, nlist, ntot, ph, zt, q, kdev, len);
+        batched_pack_s(R, zt, nullptr, 0, 0, (Src8<double>*)rec, ntot, q);
+        batched_p2(ditems, nitems, doff, st.status, kActive, (const Src8<double>*)rec, zt, nullptr, 0, ph, wv,
+                   q);
+      } else {
+        batched_pack_s(R, Vb, kdev, m - 1, len, (Src8<double>*)rec, ntot, q);
+        batched_p2(ditems, nitems, doff, st.status, kActive, (const Src8<double>*)rec, Vb, kdev, len, ph, wv,
+                   q);
+      }
       batched_dots(Vb, len, kdev, 0, wv, doff, st.status, kActive, st.h1, hs, nconf, q);
       batched_axpy(Vb, len, kdev, nullptr, 0, st.h1, hs, -1.0, dcid, st.status, kActive, wv, len, q);
       batched_dots(Vb, len, kdev, 0, wv, doff, st.status, kActive, st.h2, hs, nconf, q);
@@ -1065,7 +1083,14 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   };
   auto phase_fin = [&](hipStream_t q) {
     batched_backsolve(st, nconf, m, q);
-    batched_axpy(Vb, len, nullptr, st.kend, 0, st.y, hs, 1.0, dcid, st.status, kCycleDone, xv, len, q);
+    if (pc) {  // x += M^{-1} (V y) for the configurations that ended a cycle (zero elsewhere)
+      batched_fill(ut, 0.0, len, q);
+      batched_axpy(Vb, len, nullptr, st.kend, 0, st.y, hs, 1.0, dcid, st.status, kCycleDone, ut, len, q);
+      launch_near_apply(R, ut, ncnt, nlist, ntot, ph, zt, q);
+      launch_axpby(1.0, zt, 1.0, xv, len, q);
+    } else {
+      batched_axpy(Vb, len, nullptr, st.kend, 0, st.y, hs, 1.0, dcid, st.status, kCycleDone, xv, len, q);
+    }
     batched_pack_s(R, xv, nullptr, 0, 0, (Src8<double>*)rec, ntot, q);
     batched_p2(ditems, nitems, doff, st.status, kCycleDone, (const Src8<double>*)rec, xv, nullptr, 0, ph,
                wv, q);
@@ -1092,8 +1117,10 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
     uintptr_t tb;
     memcpy(&tb, &tolc, sizeof tb);
     key.push_back(tb);
-    double cs_ = ph.c_slip, eta_ = ph.eta, a_ = ph.a;
+    double cs_ = ph.c_slip, eta_ = ph.eta, a_ = ph.a, rc_ = near_rc;
     memcpy(&tb, &cs_, sizeof tb);
+    key.push_back(tb);
+    memcpy(&tb, &rc_, sizeof tb);
     key.push_back(tb);
     memcpy(&tb, &eta_, sizeof tb);
     key.push_back(tb);

@@ -19,6 +19,9 @@ struct BatchState {  // device arrays indexed by configuration (stride m+2 or (m
   unsigned long long *t0, *t1;
 };
 
+// near-field lists within each configuration (pairs 2a <= r < rc, first kNearCap in index order)
+void batched_near_build(const int2* items, int nitems, const int* off, const double* R, double rmin,
+                        double rc, int* cnt, int* list, hipStream_t s);
 void batched_pack_f(const double* R, const double* Fe, const double* Te, const double* D,
                     const Phys& ph, RecF* rec, int ntot, hipStream_t s);
 void batched_p1(const int2* items, int nitems, const int* off, const RecF* rec, const double* v2s,

@@ -148,6 +148,26 @@ __global__ void __launch_bounds__(kItem)
   for (int c = 0; c < 5; ++c) y[5 * (int64_t)i + c] = x[5 * (int64_t)i + c] * inv_gamma - e[c];
 }
 
+// Near-field lists of every configuration (partners only within the sphere's own configuration):
+// each work item scans its configuration's centres in index order, so a list holds the first
+// kNearCap partners with 2a <= r < r_c, as the single-configuration build does.
+__global__ void __launch_bounds__(kItem)
+    k_bnear(const int2* __restrict__ items, const int* __restrict__ off, const double* __restrict__ R,
+            double rmin2, double rc2, int* __restrict__ cnt, int* __restrict__ list) {
+  const int2 it = items[blockIdx.x];
+  const int o0 = off[it.x], o1 = off[it.x + 1];
+  const int i = it.y + threadIdx.x;
+  if (i >= o1) return;
+  const double xi = R[3 * (int64_t)i], yi = R[3 * (int64_t)i + 1], zi = R[3 * (int64_t)i + 2];
+  int c = 0;
+  for (int j = o0; j < o1; ++j) {
+    const double dx = xi - R[3 * (int64_t)j], dy = yi - R[3 * (int64_t)j + 1], dz = zi - R[3 * (int64_t)j + 2];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (j != i && r2 >= rmin2 && r2 < rc2 && c < kNearCap) list[(int64_t)i * kNearCap + c++] = j;
+  }
+  cnt[i] = c;
+}
+
 // outputs for every configuration
 template <bool HAS_T, bool HAS_D>
 __global__ void __launch_bounds__(kItem)
@@ -190,23 +210,23 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
-// h[b][i] = <V_i, w> over configuration b's segment, i < nv (nv = kdev + 1 or 1)
+// h[b][i] = <V_i, w> over configuration b's segment, i < nv (nv = kdev + 1 or nv_fixed): one
+// workgroup per (configuration, vector), so a batch keeps the whole GPU busy even when a few large
+// configurations dominate; w of a configuration stays in L2 across its vectors.
 __global__ void __launch_bounds__(256)
     k_bdots(const double* __restrict__ V, int64_t ld, const int* __restrict__ kdev, int nv_fixed,
             const double* __restrict__ w, const int* __restrict__ off, const int* __restrict__ status,
             int want, double* __restrict__ h, int hstride) {
   __shared__ double red[4];
-  const int b = blockIdx.x;
-  if (status[b] != want) return;
+  const int b = blockIdx.x, i = blockIdx.y;
   const int nv = kdev ? kdev[0] + 1 : nv_fixed;
+  if (i >= nv || status[b] != want) return;  // uniform over the workgroup
   const int64_t s0 = 5 * (int64_t)off[b], s1 = 5 * (int64_t)off[b + 1];
-  for (int i = 0; i < nv; ++i) {
-    const double* v = V + (int64_t)i * ld;
-    double acc = 0.0;
-    for (int64_t t = s0 + threadIdx.x; t < s1; t += blockDim.x) acc = fma(v[t], w[t], acc);
-    const double sum = block_sum256(acc, red);
-    if (threadIdx.x == 0) h[(int64_t)b * hstride + i] = sum;
-  }
+  const double* v = V + (int64_t)i * ld;
+  double acc = 0.0;
+  for (int64_t t = s0 + threadIdx.x; t < s1; t += blockDim.x) acc = fma(v[t], w[t], acc);
+  const double sum = block_sum256(acc, red);
+  if (threadIdx.x == 0) h[(int64_t)b * hstride + i] = sum;
 }
 
 // w += sign * sum_{i < nv} h[b][i] V_i for elements of configurations with status `want`
@@ -424,6 +444,11 @@ void batched_p2(const int2* items, int nitems, const int* off, const int* status
                      ld, ph.P, ph.a2, ph.inv_gamma, y);
 }
 
+void batched_near_build(const int2* items, int nitems, const int* off, const double* R, double rmin,
+                        double rc, int* cnt, int* list, hipStream_t s) {
+  hipLaunchKernelGGL(k_bnear, dim3(nitems), dim3(kItem), 0, s, items, off, R, rmin * rmin, rc * rc, cnt, list);
+}
+
 void batched_pack_o(const double* R, const double* Fe, const double* Te, const double* Sig,
                     const double* D, const Phys& ph, RecO* rec, int ntot, hipStream_t s) {
   hipLaunchKernelGGL(k_bpack_o, dim3(nblk(ntot, 256)), dim3(256), 0, s, R, Fe, Te, Sig, D, ph.P,
@@ -451,8 +476,10 @@ void batched_p3(const int2* items, int nitems, const int* off, const RecO* rec, 
 void batched_dots(const double* V, int64_t ld, const int* kdev, int nv_fixed, const double* w,
                   const int* off, const int* status, int want, double* h, int hstride, int nconf,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_bdots, dim3(nconf), dim3(256), 0, s, V, ld, kdev, nv_fixed, w, off, status, want,
-                     h, hstride);
+  // with kdev the vector count is read on the device; hstride = m + 2 bounds it by m + 1
+  const int nv_max = kdev ? hstride - 1 : nv_fixed;
+  hipLaunchKernelGGL(k_bdots, dim3(nconf, nv_max), dim3(256), 0, s, V, ld, kdev, nv_fixed, w, off, status,
+                     want, h, hstride);
 }
 
 void batched_axpy(const double* V, int64_t ld, const int* kdev, const int* nvb, int nv_fixed,

@@ -117,12 +117,15 @@ __global__ void __launch_bounds__(256)
   cnt[i] = c;
 }
 
-// y = gamma x + gamma^2 K_near x
-__global__ void k_near_apply(const double* __restrict__ R, const double* __restrict__ X,
-                             const int* __restrict__ cnt, const int* __restrict__ list, int n, double P,
-                             double a2, double gamma, double* __restrict__ Y) {
+// y = gamma x + gamma^2 K_near x; x = X + kdev[0] * ld when kdev is given (a Krylov vector whose
+// index lives on the device)
+__global__ void k_near_apply(const double* __restrict__ R, const double* __restrict__ X0,
+                             const int* __restrict__ kdev, int64_t ld, const int* __restrict__ cnt,
+                             const int* __restrict__ list, int n, double P, double a2, double gamma,
+                             double* __restrict__ Y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const double* __restrict__ X = X0 + (kdev ? (int64_t)kdev[0] * ld : 0);
   const double xi = R[3 * (int64_t)i], yi = R[3 * (int64_t)i + 1], zi = R[3 * (int64_t)i + 2];
   const double A24 = 24.0 * a2, A42 = 42.0 * a2;
   Mom<double> m;
@@ -155,9 +158,9 @@ void launch_near_build(const GridView& g, const double* R, double rmin, double r
 }
 
 void launch_near_apply(const double* R, const double* x, const int* cnt, const int* list, int64_t n,
-                       const Phys& ph, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, cnt, list, (int)n, ph.P,
-                     ph.a2, ph.gamma, y);
+                       const Phys& ph, double* y, hipStream_t s, const int* kdev, int64_t ld) {
+  hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, kdev, ld, cnt, list, (int)n,
+                     ph.P, ph.a2, ph.gamma, y);
 }
 
 }  // namespace mbs
