@@ -389,7 +389,9 @@ int check_overlap(mbs_ctx* c, int64_t n, const double* R, hipStream_t s, double*
     return MBS_OK;
   }
   double* out = c->small.p + c->small.cap - 1;
-  launch_min_dist2(R, n, out, c->dpart.p + 1024, s);
+  GridView g;  // cells of edge >= 3a, at most about two per sphere
+  CHK(grid_of(c, n, R, 3.0 * c->prm.a, 2 * n + 64, &g, s));
+  launch_min_dist2(g, R, n, out, c->dpart.p + 1024, s);
   CHK(read_status(c, out, 1, s));
   *min_d = sqrt(c->h_status[0]);
   return MBS_OK;

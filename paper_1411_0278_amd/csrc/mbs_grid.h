@@ -18,6 +18,8 @@ struct GridHdr {
   double h;      // cell edge
   double inv_h;
   int g[3];      // cells per axis
+  int maxocc;    // most spheres in one cell
+  int n;         // spheres
   int pad;
 };
 
@@ -38,6 +40,16 @@ __device__ __forceinline__ int grid_cell1(double x, double lo, double inv_h, int
 
 __device__ __forceinline__ int grid_linear(const GridHdr& H, int x, int y, int z) {
   return (z * H.g[1] + y) * H.g[0] + x;
+}
+
+// A grid is crowded when it has few cells or one cell holds at least 1/8 of all spheres (a
+// collapsed cluster): a sphere's 27 cells then hold a large share of all spheres, and an all-pairs
+// scan through LDS beats walking the cells. The searches launch both variants and each returns at
+// once unless the grid (read on the device) is of its kind.
+constexpr int kDenseCells = 128;
+
+__device__ __forceinline__ bool grid_dense(const GridHdr* hdr) {
+  return (int64_t)hdr->g[0] * hdr->g[1] * hdr->g[2] < kDenseCells || 8 * (int64_t)hdr->maxocc >= hdr->n;
 }
 
 // Workspace bytes for a grid of n centres and at most max_cells cells.

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) k_box_part(const double* __restrict__ R, 
 }
 
 // bounding box -> cell edge and counts: edge >= h_min, at most max_cells cells, at most 1024 per axis
-__global__ void __launch_bounds__(256) k_grid_params(const double* __restrict__ part, double h_min,
+__global__ void __launch_bounds__(256) k_grid_params(const double* __restrict__ part, int n, double h_min,
                                                      int64_t max_cells, GridHdr* __restrict__ hdr) {
   __shared__ double red[6][kBoxParts];
   const int t = threadIdx.x;
@@ -112,6 +112,8 @@ __global__ void __launch_bounds__(256) k_grid_params(const double* __restrict__ 
   }
   H.h = h;
   H.inv_h = 1.0 / h;
+  H.maxocc = 0;  // raised by the range kernel
+  H.n = n;
   H.pad = 0;
   *hdr = H;
 }
@@ -136,7 +138,7 @@ __global__ void k_clear_cells(int32_t* __restrict__ start, int32_t* __restrict__
 }
 
 __global__ void k_cell_ranges(const uint32_t* __restrict__ key, const int32_t* __restrict__ perm,
-                              const double* __restrict__ R, int n, const GridHdr* __restrict__ hdr,
+                              const double* __restrict__ R, int n, GridHdr* __restrict__ hdr,
                               int32_t* __restrict__ start, int32_t* __restrict__ end, double* __restrict__ Rs) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
@@ -149,7 +151,18 @@ __global__ void k_cell_ranges(const uint32_t* __restrict__ key, const int32_t* _
   Rs[4 * (int64_t)k + 3] = 0.0;
   const int c = grid_linear(H, (int)compact3(kk), (int)compact3(kk >> 1), (int)compact3(kk >> 2));
   if (k == 0 || key[k - 1] != kk) start[c] = k;
-  if (k == n - 1 || key[k + 1] != kk) end[c] = k + 1;
+  if (k == n - 1 || key[k + 1] != kk) {
+    end[c] = k + 1;
+    int lo = 0, hi = k;  // first position of this key (binary search in the sorted keys)
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (key[mid] < kk)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    atomicMax(&hdr->maxocc, k + 1 - lo);
+  }
 }
 
 struct Layout {
@@ -207,7 +220,7 @@ hipError_t grid_build(const double* R, int n, double h_min, int64_t max_cells, v
   int32_t* start = (int32_t*)(b + L.start);
   int32_t* end = (int32_t*)(b + L.end);
   hipLaunchKernelGGL(k_box_part, dim3(kBoxParts), dim3(256), 0, s, R, n, part);
-  hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(kBoxParts), 0, s, part, h_min, max_cells, hdr);
+  hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(kBoxParts), 0, s, part, n, h_min, max_cells, hdr);
   hipLaunchKernelGGL(k_cell_keys, dim3(nblk(n, 256)), dim3(256), 0, s, R, n, hdr, key_in, idx_in);
   size_t tb = L.tmp_bytes;
   hipError_t e = hipcub::DeviceRadixSort::SortPairs((void*)(b + L.tmp), tb, key_in, key, idx_in, perm, n, 0,

@@ -50,8 +50,11 @@ void launch_p3(const double* R, const double* v1s, const double* v2s, const doub
 void launch_p23(const double* R, const double* v1s, const double* v2s, const double* v3t,
                 const double* Fe, const double* Te, const double* Sig, double* y, double* V, double* W,
                 double* S, double* part, int64_t n, const Phys& ph, Tile t, hipStream_t s);
-// min over pairs of |R_n - R_m|^2 -> out[0] (device); scratch: blocks doubles
-void launch_min_dist2(const double* R, int64_t n, double* out, double* scratch, hipStream_t s);
+// min over pairs of |R_n - R_m|^2 -> out[0] (device), from the cell grid g of R (exact: an
+// all-pairs scan takes over when no pair is closer than one cell edge); scratch: ceil(n/256) doubles
+struct GridView;
+void launch_min_dist2(const GridView& g, const double* R, int64_t n, double* out, double* scratch,
+                      hipStream_t s);
 // count non-finite entries of a device array -> atomically added to *cnt (device int)
 void launch_count_nonfinite(const double* a, int64_t len, int* cnt, hipStream_t s);
 

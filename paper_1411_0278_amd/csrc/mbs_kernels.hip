@@ -35,6 +35,7 @@
 #include <stdint.h>
 
 #include "mbs_device.h"
+#include "mbs_grid.h"
 #include "mbs_internal.h"
 #include "mbs_pair.h"
 
@@ -296,7 +297,10 @@ __global__ void k_p23_finish(const double* __restrict__ part, int split, int64_t
 // ------------------------------------------------------------------ overlap monitor
 template <int TJ>
 __global__ void __launch_bounds__(kMaxBlock)
-    k_min_dist2(const double* __restrict__ R, int n, double* __restrict__ blockmin) {
+    k_min_dist2(const double* __restrict__ R, int n, double* __restrict__ blockmin,
+                const double* __restrict__ have, const GridHdr* __restrict__ hdr) {
+  // nothing to do when the grid search already found a pair closer than one cell edge
+  if (have[0] < hdr->h * hdr->h) return;
   __shared__ double tx[TJ], ty[TJ], tz[TJ];
   __shared__ double red[kMaxBlock];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -327,7 +331,50 @@ __global__ void __launch_bounds__(kMaxBlock)
   if (threadIdx.x == 0) blockmin[blockIdx.x] = red[0];
 }
 
-__global__ void k_min_finish(const double* __restrict__ blockmin, int nb, double* __restrict__ out) {
+// Minimum over the 27 cells around each sphere's own (cell edge h): exact whenever some pair is
+// closer than h, since every such pair lies in those cells. A crowded grid yields +inf here, which
+// hands the search to the all-pairs scan.
+__global__ void __launch_bounds__(256) k_min_grid(GridView G, double* __restrict__ blockmin) {
+  if (grid_dense(G.hdr)) {  // crowded grid: leave it to the all-pairs scan
+    if (threadIdx.x == 0) blockmin[blockIdx.x] = INFINITY;
+    return;
+  }
+  __shared__ double red[256];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  double best = INFINITY;
+  if (k < G.n) {
+    const GridHdr H = *G.hdr;
+    const int i = G.perm[k];
+    const double xi = G.Rs[4 * (int64_t)k], yi = G.Rs[4 * (int64_t)k + 1], zi = G.Rs[4 * (int64_t)k + 2];
+    const int cx = grid_cell1(xi, H.lo[0], H.inv_h, H.g[0]);
+    const int cy = grid_cell1(yi, H.lo[1], H.inv_h, H.g[1]);
+    const int cz = grid_cell1(zi, H.lo[2], H.inv_h, H.g[2]);
+    for (int z = max(cz - 1, 0); z <= min(cz + 1, H.g[2] - 1); ++z)
+      for (int y = max(cy - 1, 0); y <= min(cy + 1, H.g[1] - 1); ++y)
+        for (int x = max(cx - 1, 0); x <= min(cx + 1, H.g[0] - 1); ++x) {
+          const int c = grid_linear(H, x, y, z);
+          const int e = G.end[c];
+          for (int k2 = G.start[c]; k2 < e; ++k2) {
+            const double dx = xi - G.Rs[4 * (int64_t)k2], dy = yi - G.Rs[4 * (int64_t)k2 + 1],
+                         dz = zi - G.Rs[4 * (int64_t)k2 + 2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (G.perm[k2] != i) best = fmin(best, r2);
+          }
+        }
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blockmin[blockIdx.x] = red[0];
+}
+
+// out[0] = min of the partials; with hdr: only when out[0] (the grid result) is not below h^2
+__global__ void k_min_finish(const double* __restrict__ blockmin, int nb, double* __restrict__ out,
+                             const GridHdr* __restrict__ hdr) {
+  if (hdr && out[0] < hdr->h * hdr->h) return;
   __shared__ double red[kMaxBlock];
   double best = INFINITY;
   for (int k = threadIdx.x; k < nb; k += blockDim.x) best = fmin(best, blockmin[k]);
@@ -634,10 +681,15 @@ void launch_p23(const double* R, const double* v1s, const double* v2s, const dou
                      Sig, y, V, W, S, ph.inv_gamma, ph.mu_t, ph.mu_r, ph.slip_S);
 }
 
-void launch_min_dist2(const double* R, int64_t n, double* out, double* scratch, hipStream_t s) {
+void launch_min_dist2(const GridView& g, const double* R, int64_t n, double* out, double* scratch,
+                      hipStream_t s) {
   const unsigned nb = nblk(n, 256);
-  hipLaunchKernelGGL(k_min_dist2<256>, dim3(nb), dim3(256), 0, s, R, (int)n, scratch);
-  hipLaunchKernelGGL(k_min_finish, dim3(1), dim3(256), 0, s, scratch, (int)nb, out);
+  // grid search first; the all-pairs scan runs (and replaces the result) only if it found no pair
+  // closer than one cell edge
+  hipLaunchKernelGGL(k_min_grid, dim3(nb), dim3(256), 0, s, g, scratch);
+  hipLaunchKernelGGL(k_min_finish, dim3(1), dim3(256), 0, s, scratch, (int)nb, out, nullptr);
+  hipLaunchKernelGGL(k_min_dist2<256>, dim3(nb), dim3(256), 0, s, R, (int)n, scratch, out, g.hdr);
+  hipLaunchKernelGGL(k_min_finish, dim3(1), dim3(256), 0, s, scratch, (int)nb, out, g.hdr);
 }
 
 void launch_count_nonfinite(const double* a, int64_t len, int* cnt, hipStream_t s) {

@@ -24,15 +24,7 @@
 namespace mbs {
 namespace {
 
-// Grids with fewer cells than this are crowded (a collapsed cluster: most spheres within r_c of
-// most others); there an all-pairs scan through LDS is cheaper than walking the cells, so the build
-// launches both kernels and each returns at once unless the grid is of its kind.
-constexpr int kDenseCells = 128;
 constexpr int kTile = 256;
-
-__device__ __forceinline__ bool grid_dense(const GridHdr* hdr) {
-  return (int64_t)hdr->g[0] * hdr->g[1] * hdr->g[2] < kDenseCells;
-}
 
 // All-pairs variant: sources in index order, so the first kNearCap partners are the smallest.
 __global__ void __launch_bounds__(256) k_near_build_dense(const double* __restrict__ R, int n,

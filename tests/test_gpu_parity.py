@@ -279,6 +279,30 @@ def test_stepper_matches_oracle(ctx):
     assert abs(md[0] - dmin) < 1e-12
 
 
+@pytest.mark.parametrize("case", ["random", "dilute_lattice", "pair", "clustered"])
+def test_minimum_distance_monitor(ctx, case):
+    """The per-step minimum centre distance: cell-grid search when some pair is closer than a cell
+    edge, all-pairs scan otherwise (a dilute lattice), exact either way."""
+    print(f"min distance case={case}", flush=True)
+    rng = np.random.default_rng(21)
+    if case == "random":
+        Rn = _workload(900, seed=22).R
+    elif case == "dilute_lattice":
+        Rn = np.array([[x, y, z] for x in range(4) for y in range(4) for z in range(4)], float) * 20.0
+        Rn[5] += [0.0, 0.0, 3.5]  # one pair at 16.5: the closest, still farther than any cell edge
+    elif case == "pair":
+        Rn = np.array([[0.0, 0.0, 0.0], [3.0, 4.0, 0.0]])
+    else:
+        Rn = np.r_[rng.normal(0, 3, (200, 3)), rng.normal(500, 3, (200, 3))]
+    pn = rng.standard_normal(Rn.shape)
+    pn /= np.linalg.norm(pn, axis=1, keepdims=True)
+    R, p = _t(Rn), _t(pn)
+    _, md = ctx.mbs_step(R, p, 0.0, (0.0, 0.0, 0.0), 0.0, 1, order=1, want_min_dist=True)
+    D = np.linalg.norm(Rn[:, None] - Rn[None], axis=2)
+    D[np.arange(len(Rn)), np.arange(len(Rn))] = np.inf
+    assert abs(md[0] - D.min()) <= 1e-12 * D.min()
+
+
 # ---------------------------------------------------------------- batched
 def _batch(ws):
     off = np.cumsum([0] + [w.n for w in ws])
