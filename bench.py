@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--warmstart-epochs", type=int, default=10)
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-stepper", action="store_true")
+    ap.add_argument("--skip-kernels", action="store_true", help="skip the per-size pair-pass timings")
     ap.add_argument("--stepper-steps", type=int, default=1000)
     ap.add_argument("--profile-matvec", action="store_true",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then --steps "
@@ -150,6 +151,54 @@ def roofline(v, n):
             "flop_per_pair": P2_FLOP_PER_PAIR}
 
 
+def bench_kernels(ctx, a):
+    """Pair-pass throughput on their own: the operator (binary64 and binary32) at N = 256, 10^4 and
+    10^5 (each with its own autotuned shape), and the right-hand-side and output passes at 10^5.
+    Median of 5 launches after 2 warm-ups, HIP events on the launch stream."""
+    import statistics
+
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+
+    def median_ms(fn):
+        for _ in range(2):
+            fn()
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return statistics.median(ts)
+
+    out = {}
+    for label, w in (("n256", inputs.config0()), ("n10000", inputs.config1()),
+                     ("n100000", inputs.trap_workload(a.n, a.side, a.seed))):
+        d = mbstokes.to_device(w, "cuda:0")
+        n = w.n
+        tiles = ctx.mbs_autotune(d["R"], None)
+        x = d["v2s"].contiguous()
+        y = torch.empty_like(x)
+        row = {"tiles": list(tiles)}
+        for name, prec in (("p2_f64", mbstokes.MBS_FP64), ("p2_f32", mbstokes.MBS_FP32)):
+            ms = median_ms(lambda: ctx.mbs_matvec(d["R"], x, y, precision=prec))
+            row[name] = {"ms": round(ms, 4), "pair_blocks_per_s": n * (n - 1) / (ms * 1e-3),
+                         "tflops_algorithmic": round(P2_FLOP_PER_PAIR * n * (n - 1) / (ms * 1e-3) / 1e12, 3)}
+        if n == a.n:
+            # as in the benchmark solve: no torque, no rank-3 slip
+            ms = median_ms(lambda: ctx.mbs_rhs(d["R"], d["v2s"], None, d["Fe"], None))
+            row["p1"] = {"ms": round(ms, 4), "pair_blocks_per_s": n * (n - 1) / (ms * 1e-3)}
+            sig = torch.randn((n, 5), dtype=torch.float64, device="cuda:0")
+            ms = median_ms(lambda: ctx.mbs_outputs(d["R"], sig, d["v1s"], d["v2s"], None, d["Fe"], None))
+            row["p3"] = {"ms": round(ms, 4), "pair_blocks_per_s": n * (n - 1) / (ms * 1e-3)}
+        out[label] = row
+        print(f"bench: pair passes at {label} timed", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_batched(ctx, a):
     """512 independent configurations, N log-uniform in [64, 4096], density 0.004, one batched call."""
     import numpy as np
@@ -201,6 +250,7 @@ def bench_stepper(ctx, a):
     w = inputs.config1()
     out = {"n": w.n, "steps": a.stepper_steps, "dt": 0.01, "near_cutoff": a.near_cutoff,
            "guess": "previous step's stresslet (first step: one-body)", "max_iter_per_step": 60}
+    ctx.mbs_autotune(torch.as_tensor(w.R).to("cuda:0"), None)  # pair-kernel shapes for this N
     for name, prec in (("fp64", mbstokes.MBS_FP64), ("mixed", mbstokes.MBS_MIXED)):
         R = torch.as_tensor(w.R).to("cuda:0")
         p = torch.as_tensor(w.p).to("cuda:0")
@@ -280,6 +330,7 @@ def main():
     rc = a.near_cutoff
     plan = [("plain_fp64", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_ZERO, 0.0),
             ("fp64_diag", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_DIAG, 0.0),
+            ("mixed_zero", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_ZERO, 0.0),
             ("mixed_diag", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG, 0.0),
             ("fp64_pc", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_DIAG, rc),
             ("mixed_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG, rc)]
@@ -309,6 +360,8 @@ def main():
         variants[name]["near_cutoff"] = cut
     if not a.skip_batched:
         extra["batched"] = bench_batched(ctx, a)
+    if not a.skip_kernels:
+        extra["pair_passes"] = bench_kernels(ctx, a)
     if not a.skip_stepper:
         extra["stepper"] = bench_stepper(ctx, a)
     head = variants[a.headline]

@@ -1,0 +1,94 @@
+"""Accuracy of the benchmark-size solves against the oracle.
+
+* Standalone subsets: the 2000 spheres nearest the trap centre of the N = 10^4 (with the rank-3
+  trace slip) and N = 10^5 workloads, solved as their own systems; the oracle's dense solutions
+  are stored in tests/golden/ by tests/golden/make_subset_golden.py (oracle only). Bars: binary64
+  solve 1e-10 and mixed precision 1e-9 per output (relative Frobenius norm).
+* The full N = 10^5 solution, checked row by row: for sampled spheres the oracle recomputes the
+  binary64 residual rows (b - A Sigma)_n and the rigid-body motion from the GPU's Sigma.
+"""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import galerkin  # noqa: E402
+from paper_1411_0278_amd import inputs, mbstokes  # noqa: E402
+
+DEV = "cuda:0"
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mbstokes.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(got, want):
+    got = got.detach().cpu().numpy() if hasattr(got, "detach") else np.asarray(got)
+    return np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+
+
+def _subset(name):
+    w = inputs.config1() if name.startswith("cfg1") else inputs.config2()
+    return inputs.nearest_to_origin(w, 2000)
+
+
+@pytest.mark.parametrize("name", ["cfg1_subset2000", "cfg2_subset2000"])
+@pytest.mark.parametrize("method", ["fp64", "mixed_pc"])
+def test_subset_standalone_matches_oracle(ctx, name, method):
+    print(f"subset {name} {method}", flush=True)
+    ref = np.load(os.path.join(GOLDEN, name + ".npz"))
+    w = _subset(name)
+    sha = hashlib.sha256(np.ascontiguousarray(w.R, dtype=np.float64).tobytes()).hexdigest()[:16]
+    assert str(ref["centres_sha"]) == sha, "inputs changed: rerun tests/golden/make_subset_golden.py"
+    d = mbstokes.to_device(w, DEV)
+    if method == "fp64":
+        ctx.set_params(precision=mbstokes.MBS_FP64, tol=1e-12, guess=mbstokes.MBS_GUESS_DIAG)
+        bar = 1e-10
+    else:
+        ctx.set_params(precision=mbstokes.MBS_MIXED, tol=1e-11, guess=mbstokes.MBS_GUESS_DIAG, near_cutoff=6.0)
+        bar = 1e-9
+    try:
+        Sig = torch.empty((w.n, 5), dtype=torch.float64, device=DEV)
+        V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"], Sigma=Sig)
+    finally:
+        ctx.set_params(precision=mbstokes.MBS_FP64, tol=1e-10, guess=mbstokes.MBS_GUESS_ZERO, near_cutoff=0.0)
+    errs = {k: _rel(g, ref[k]) for k, g in (("V", V), ("W", W), ("S", S), ("Sigma", Sig))}
+    print(f"  errors {errs} iters {st['iters']}", flush=True)
+    assert all(e < bar for e in errs.values()), errs
+
+
+@pytest.mark.slow
+def test_full_size_solution_rows_match_oracle(ctx):
+    """N = 10^5, mixed precision with the near-field preconditioner (the benchmark's headline)."""
+    w = inputs.config2()
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    d = mbstokes.to_device(w, DEV)
+    ctx.set_params(precision=mbstokes.MBS_MIXED, tol=1e-10, guess=mbstokes.MBS_GUESS_DIAG, near_cutoff=6.0)
+    try:
+        Sig = torch.empty((w.n, 5), dtype=torch.float64, device=DEV)
+        V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None, Sigma=Sig)
+    finally:
+        ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, near_cutoff=0.0)
+    assert st["rel_resid"] <= 1e-10
+    sig = Sig.cpu().numpy()
+    rows = np.sort(np.random.default_rng(8).choice(w.n, 6, replace=False))
+    print(f"full-size rows {rows.tolist()}: oracle residual rows", flush=True)
+    zeros = np.zeros_like(w.Fe)
+    b = galerkin.rhs(w.R, w.v2s, zeros, w.Fe, zeros, prm, rows).reshape(-1, 5)
+    r = b - galerkin.matvec_rows(w.R, sig, rows, prm)
+    # the global relative residual is <= 1e-10; sampled rows stay within a small multiple of it
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-8
+    print("  oracle output rows", flush=True)
+    Vo, Wo, So = galerkin.outputs(w.R, w.v1s, w.v2s, zeros, w.Fe, zeros, sig, prm, rows)
+    Vg, Wg, Sg = V.cpu().numpy()[rows], W.cpu().numpy()[rows], S.cpu().numpy()[rows]
+    assert np.abs(Vg - Vo).max() <= 1e-11 * np.abs(Vo).max()
+    assert np.abs(Wg - Wo).max() <= 1e-11 * np.abs(Wo).max()
+    assert np.abs(Sg - So).max() <= 1e-14 * np.abs(So).max()
