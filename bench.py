@@ -230,7 +230,13 @@ def bench_batched(ctx, a):
                 "max_iters": int(max(st["iters"] for st in stats)),
                 "max_rel_resid": float(max(st["rel_resid"] for st in stats))}
 
+    t_tune = time.perf_counter()
+    item, item_ms = ctx.mbs_autotune_batched(off, R)
+    print(f"bench: batched work items of {item} receivers (autotuned in {time.perf_counter() - t_tune:.2f} s)",
+          file=sys.stderr, flush=True)
     out = run(a.near_cutoff)
+    out["item_receivers"] = item
+    out["item_pass_ms"] = {str(k): round(v, 4) for k, v in item_ms.items()}
     out["without_preconditioner"] = run(0.0)
     ctx.set_params(near_cutoff=0.0)
     return out

@@ -92,6 +92,9 @@ typedef struct mbs_params {
                             of the candidate table (see mbs_autotune) */
   int32_t graph;         /* mbs_solve_batched: 1 = capture its phases in HIP graphs and replay them
                             (default), 0 = launch the same kernels directly */
+  int32_t batch_item;    /* mbs_solve_batched: receivers per work item (64, 128 or 256); 0 = the
+                            context's choice (mbs_autotune_batched, else 64) */
+  int32_t reserved;      /* set to 0 */
 } mbs_params;
 
 typedef struct mbs_stats {
@@ -210,6 +213,14 @@ int mbs_solve_batched(mbs_ctx* ctx, int32_t nconf, const int64_t* offsets, const
    binary32); params.tile = index + 1 forces that shape. */
 int mbs_autotune(mbs_ctx* ctx, int64_t n, const double* R, const char* cache_json, int32_t* chosen,
                  void* stream);
+
+/* Time the batched operator pass on this batch (offsets and R as in mbs_solve_batched) with work
+   items of 64, 128 and 256 receivers, and use the fastest in this context for later
+   mbs_solve_batched calls (unless params.batch_item forces a size). chosen: host int32 or NULL,
+   receives the item size; ms: host double[3] or NULL, receives the average pass time of each
+   candidate. The call synchronises with `stream`. */
+int mbs_autotune_batched(mbs_ctx* ctx, int32_t nconf, const int64_t* offsets, const double* R,
+                         int32_t* chosen, double* ms, void* stream);
 
 /* ---------------------------------------------------------------- learned warm start
    A 3-layer perceptron 80 -> 128 -> 128 -> 5 (ReLU) maps the neighbourhood of each sphere to a

@@ -63,7 +63,8 @@ struct mbs_ctx {
   // cell grid of the centres behind both neighbour searches (near-field lists, nearest neighbours)
   DevBuf grid;
   // batched solver: workspace, capture stream and the four graphs of the last batch shape
-  DevBuf bat;
+  DevBuf bat, btune;
+  int bitem = 64;  // receivers per batched work item (mbs_autotune_batched's choice)
   hipStream_t bstream = nullptr;
   hipGraphExec_t bgraph[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<uintptr_t> bkey;
@@ -134,6 +135,8 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
     return set_err(c, MBS_EINVAL, "near_cutoff must be finite and >= 0");
   if (p->tile < 0 || p->tile > kTileCount)
     return set_err(c, MBS_EINVAL, "tile must be in 0..%d", kTileCount);
+  if (p->batch_item != 0 && p->batch_item != 64 && p->batch_item != 128 && p->batch_item != 256)
+    return set_err(c, MBS_EINVAL, "batch_item must be 0, 64, 128 or 256");
   return MBS_OK;
 }
 
@@ -719,6 +722,7 @@ void mbs_default_params(mbs_params* p) {
   p->check_overlap = 0;
   p->tile = 0;
   p->graph = 1;
+  p->batch_item = 0;
 }
 
 int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {
@@ -761,7 +765,7 @@ void mbs_destroy(mbs_ctx* c) {
   DevBuf* bufs[] = {&c->V, &c->w, &c->r, &c->b, &c->xs, &c->dlt, &c->part, &c->dpart,
                     &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig, &c->near, &c->zt,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
-                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->bat};
+                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->bat, &c->btune};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& g : c->bgraph)
@@ -946,18 +950,39 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
   return rc;
 }
 
+namespace {
+
+// Work items (configuration, first receiver) of `item` receivers each, largest configurations
+// first: an item's work is its configuration's size, and workgroups start in index order, so the
+// long items start early and the short ones fill the tail of each pass.
+void batch_items(const std::vector<int>& off, int nconf, int item, std::vector<int2>& items) {
+  items.clear();
+  for (int b = 0; b < nconf; ++b)
+    for (int r = off[b]; r < off[b + 1]; r += item) items.push_back(make_int2(b, r));
+  std::stable_sort(items.begin(), items.end(), [&](const int2& u, const int2& v) {
+    return off[u.x + 1] - off[u.x] > off[v.x + 1] - off[v.x];
+  });
+}
+
+int check_offsets(mbs_ctx* c, int32_t nconf, const int64_t* offsets) {
+  if (nconf < 1 || !offsets) return set_err(c, MBS_EINVAL, "nconf >= 1 and offsets are required");
+  if (offsets[0] != 0) return set_err(c, MBS_EINVAL, "offsets[0] must be 0");
+  for (int b = 0; b < nconf; ++b)
+    if (offsets[b + 1] <= offsets[b]) return set_err(c, MBS_EINVAL, "offsets must increase");
+  if (offsets[nconf] > (int64_t)INT32_MAX / 20) return set_err(c, MBS_EINVAL, "too many spheres in the batch");
+  return MBS_OK;
+}
+
+}  // namespace
+
 int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const double* R,
                       const double* v1s, const double* v2s, const double* v3t, const double* Fe,
                       const double* Te, double* V, double* W, double* S, double* Sigma,
                       mbs_stats* per_conf, double* latency_ms, void* stream) {
   CHK(begin_call(c));
-  if (nconf < 1 || !offsets) return set_err(c, MBS_EINVAL, "nconf >= 1 and offsets are required");
-  if (offsets[0] != 0) return set_err(c, MBS_EINVAL, "offsets[0] must be 0");
-  for (int b = 0; b < nconf; ++b)
-    if (offsets[b + 1] <= offsets[b]) return set_err(c, MBS_EINVAL, "offsets must increase");
+  CHK(check_offsets(c, nconf, offsets));
   if (!R || !V || !W || !S) return set_err(c, MBS_EINVAL, "R, V, W and S are required");
   const int64_t ntot64 = offsets[nconf];
-  if (ntot64 > (int64_t)INT32_MAX / 20) return set_err(c, MBS_EINVAL, "too many spheres in the batch");
   const int ntot = (int)ntot64;
   hipStream_t s = (hipStream_t)stream;
   int bad = 0;
@@ -973,15 +998,10 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   std::vector<int> off(nconf + 1), cid(ntot);
   std::vector<int2> items;
   for (int b = 0; b <= nconf; ++b) off[b] = (int)offsets[b];
-  for (int b = 0; b < nconf; ++b) {
-    for (int r = off[b]; r < off[b + 1]; r += 64) items.push_back(make_int2(b, r));
+  const int item = c->prm.batch_item ? c->prm.batch_item : c->bitem;
+  for (int b = 0; b < nconf; ++b)
     for (int r = off[b]; r < off[b + 1]; ++r) cid[r] = b;
-  }
-  // largest configurations first: an item's work is its configuration's size, and workgroups start
-  // in index order, so the long items start early and the short ones fill the tail of each pass
-  std::stable_sort(items.begin(), items.end(), [&](const int2& u, const int2& v) {
-    return off[u.x + 1] - off[u.x] > off[v.x + 1] - off[v.x];
-  });
+  batch_items(off, nconf, item, items);
   const int nitems = (int)items.size();
   // workspace (bytes, 256-aligned pieces)
   const int64_t len = 5 * ntot64;
@@ -1052,8 +1072,8 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   auto phase_init = [&](hipStream_t q) {
     batched_set_ints(st.status, nconf, kActive, q);
     batched_pack_f(R, Fe, Te, v3t, ph, (RecF*)rec, ntot, q);
-    batched_p1(ditems, nitems, doff, (const RecF*)rec, v2s, has_t, has_d, ph, bv, q);
-    if (pc) batched_near_build(ditems, nitems, doff, R, near_rmin, near_rc, ncnt, nlist, q);
+    batched_p1(ditems, nitems, item, doff, (const RecF*)rec, v2s, has_t, has_d, ph, bv, q);
+    if (pc) batched_near_build(ditems, nitems, item, doff, R, near_rmin, near_rc, ncnt, nlist, q);
     batched_fill(xv, 0.0, len, q);
     batched_dots(bv, 0, nullptr, 1, bv, doff, st.status, kActive, st.nsq, 1, nconf, q);
     batched_init(st, nconf, m, q);
@@ -1065,11 +1085,11 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
       if (pc) {  // right preconditioning: w = A M^{-1} v_k
         launch_near_apply(R, Vb, ncnt, nlist, ntot, ph, zt, q, kdev, len);
         batched_pack_s(R, zt, nullptr, 0, 0, (Src8<double>*)rec, ntot, q);
-        batched_p2(ditems, nitems, doff, st.status, kActive, (const Src8<double>*)rec, zt, nullptr, 0, ph, wv,
+        batched_p2(ditems, nitems, item, doff, st.status, kActive, (const Src8<double>*)rec, zt, nullptr, 0, ph, wv,
                    q);
       } else {
         batched_pack_s(R, Vb, kdev, m - 1, len, (Src8<double>*)rec, ntot, q);
-        batched_p2(ditems, nitems, doff, st.status, kActive, (const Src8<double>*)rec, Vb, kdev, len, ph, wv,
+        batched_p2(ditems, nitems, item, doff, st.status, kActive, (const Src8<double>*)rec, Vb, kdev, len, ph, wv,
                    q);
       }
       batched_dots(Vb, len, kdev, 0, wv, doff, st.status, kActive, st.h1, hs, nconf, q);
@@ -1094,7 +1114,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
       batched_axpy(Vb, len, nullptr, st.kend, 0, st.y, hs, 1.0, dcid, st.status, kCycleDone, xv, len, q);
     }
     batched_pack_s(R, xv, nullptr, 0, 0, (Src8<double>*)rec, ntot, q);
-    batched_p2(ditems, nitems, doff, st.status, kCycleDone, (const Src8<double>*)rec, xv, nullptr, 0, ph,
+    batched_p2(ditems, nitems, item, doff, st.status, kCycleDone, (const Src8<double>*)rec, xv, nullptr, 0, ph,
                wv, q);
     batched_resid(bv, wv, dcid, st.status, rv, len, q);
     batched_dots(rv, 0, nullptr, 1, rv, doff, st.status, kCycleDone, st.nsq, 1, nconf, q);
@@ -1105,7 +1125,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   };
   auto phase_out = [&](hipStream_t q) {
     batched_pack_o(R, Fe, Te, xv, v3t, ph, (RecO*)rec, ntot, q);
-    batched_p3(ditems, nitems, doff, (const RecO*)rec, has_t, has_d, ph, v1s, v2s, Fe, Te, xv, V, W, S,
+    batched_p3(ditems, nitems, item, doff, (const RecO*)rec, has_t, has_d, ph, v1s, v2s, Fe, Te, xv, V, W, S,
                Sigma, q);
   };
   // graphs: captured once per batch shape (pointers and sizes), replayed afterwards
@@ -1124,6 +1144,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
     key.push_back(tb);
     memcpy(&tb, &rc_, sizeof tb);
     key.push_back(tb);
+    key.push_back((uintptr_t)item);
     memcpy(&tb, &eta_, sizeof tb);
     key.push_back(tb);
     memcpy(&tb, &a_, sizeof tb);
@@ -1217,6 +1238,59 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   HIPCHK(c, hipStreamWaitEvent(s, c->ev[7], 0));
   if (rc == MBS_ENOCONV) set_err(c, MBS_ENOCONV, "some configurations did not reach the tolerance");
   return rc;
+}
+
+int mbs_autotune_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const double* R, int32_t* chosen,
+                         double* ms, void* stream) {
+  CHK(begin_call(c));
+  CHK(check_offsets(c, nconf, offsets));
+  if (!R) return set_err(c, MBS_EINVAL, "R is required");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, 16));
+  const int ntot = (int)offsets[nconf];
+  const int64_t len = 5 * (int64_t)ntot;
+  std::vector<int> off(nconf + 1);
+  for (int b = 0; b <= nconf; ++b) off[b] = (int)offsets[b];
+  // scratch: source records, x (zero), y, items (sized for the smallest item), offsets, status
+  size_t bytes = 0;
+  auto reserve = [&](size_t b) { size_t o = bytes; bytes += align256(b); return o; };
+  const size_t orec = reserve((size_t)ntot * sizeof(Src8<double>)), ox = reserve(len * 8), oy = reserve(len * 8),
+               oit = reserve(((size_t)ntot / 64 + nconf + 1) * sizeof(int2)), ooff = reserve((nconf + 1) * 4),
+               ost = reserve((size_t)nconf * 4);
+  CHK(ensure(c, c->btune, bytes / 8 + 64));
+  char* base = (char*)c->btune.p;
+  Src8<double>* rec = (Src8<double>*)(base + orec);
+  double *x = (double*)(base + ox), *y = (double*)(base + oy);
+  int2* ditems = (int2*)(base + oit);
+  int *doff = (int*)(base + ooff), *dst = (int*)(base + ost);
+  HIPCHK(c, hipMemcpyAsync(doff, off.data(), (nconf + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  batched_set_ints(dst, nconf, kActive, s);  // every configuration takes part
+  batched_fill(x, 0.0, len, s);
+  batched_pack_s(R, x, nullptr, 0, 0, rec, ntot, s);
+  const int cand[3] = {64, 128, 256};
+  double best = 0.0;
+  int pick = 64;
+  std::vector<int2> items;
+  for (int k = 0; k < 3; ++k) {
+    batch_items(off, nconf, cand[k], items);
+    HIPCHK(c, hipMemcpyAsync(ditems, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    const int ni = (int)items.size();
+    batched_p2(ditems, ni, cand[k], doff, dst, kActive, rec, x, nullptr, 0, c->ph, y, s);  // warm-up
+    HIPCHK(c, hipEventRecord(c->ev[0], s));
+    for (int r = 0; r < 3; ++r) batched_p2(ditems, ni, cand[k], doff, dst, kActive, rec, x, nullptr, 0, c->ph, y, s);
+    HIPCHK(c, hipEventRecord(c->ev[1], s));
+    HIPCHK(c, hipEventSynchronize(c->ev[1]));
+    const double t = ev_ms(c->ev[0], c->ev[1]) / 3.0;
+    if (ms) ms[k] = t;
+    if (k == 0 || t < best) {
+      best = t;
+      pick = cand[k];
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  c->bitem = pick;
+  if (chosen) *chosen = pick;
+  return MBS_OK;
 }
 
 int mbs_autotune(mbs_ctx* c, int64_t n, const double* R, const char* cache_json, int32_t* chosen,

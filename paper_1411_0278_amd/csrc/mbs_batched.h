@@ -20,20 +20,20 @@ struct BatchState {  // device arrays indexed by configuration (stride m+2 or (m
 };
 
 // near-field lists within each configuration (pairs 2a <= r < rc, first kNearCap in index order)
-void batched_near_build(const int2* items, int nitems, const int* off, const double* R, double rmin,
+void batched_near_build(const int2* items, int nitems, int item, const int* off, const double* R, double rmin,
                         double rc, int* cnt, int* list, hipStream_t s);
 void batched_pack_f(const double* R, const double* Fe, const double* Te, const double* D,
                     const Phys& ph, RecF* rec, int ntot, hipStream_t s);
-void batched_p1(const int2* items, int nitems, const int* off, const RecF* rec, const double* v2s,
+void batched_p1(const int2* items, int nitems, int item, const int* off, const RecF* rec, const double* v2s,
                 bool has_t, bool has_d, const Phys& ph, double* b, hipStream_t s);
 void batched_pack_s(const double* R, const double* X, const int* kdev, int maxk, int64_t ld,
                     Src8<double>* src, int ntot, hipStream_t s);
-void batched_p2(const int2* items, int nitems, const int* off, const int* status, int want,
+void batched_p2(const int2* items, int nitems, int item, const int* off, const int* status, int want,
                 const Src8<double>* src, const double* X, const int* kdev, int64_t ld, const Phys& ph,
                 double* y, hipStream_t s);
 void batched_pack_o(const double* R, const double* Fe, const double* Te, const double* Sig,
                     const double* D, const Phys& ph, RecO* rec, int ntot, hipStream_t s);
-void batched_p3(const int2* items, int nitems, const int* off, const RecO* rec, bool has_t, bool has_d,
+void batched_p3(const int2* items, int nitems, int item, const int* off, const RecO* rec, bool has_t, bool has_d,
                 const Phys& ph, const double* v1s, const double* v2s, const double* Fe,
                 const double* Te, const double* Sig, double* V, double* W, double* S, double* SigOut,
                 hipStream_t s);

@@ -21,7 +21,11 @@
 namespace mbs {
 namespace {
 
-constexpr int kItem = 64;  // receivers per work item
+constexpr int kItemMax = 256;  // receivers per work item: blockDim.x, 64, 128 or 256
+
+// A wavefront whose first receiver lies past its configuration has nothing to do (uniform exit; the
+// item kernels have no barriers).
+__device__ __forceinline__ bool wave_idle(int first, int o1) { return first + (int)(threadIdx.x & ~63u) >= o1; }
 
 inline unsigned nblk(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
 
@@ -101,11 +105,12 @@ __global__ void k_bpack_s(const double* __restrict__ R, const double* __restrict
 
 // b = E[F, T, d] - c s for every configuration
 template <bool HAS_T, bool HAS_D>
-__global__ void __launch_bounds__(kItem)
+__global__ void __launch_bounds__(kItemMax)
     k_bp1(const int2* __restrict__ items, const int* __restrict__ off, const RecF* __restrict__ rec,
           const double* __restrict__ v2s, double cslip, double a2, double* __restrict__ b) {
   const int2 it = items[blockIdx.x];
   const int o0 = off[it.x], o1 = off[it.x + 1];
+  if (wave_idle(it.y, o1)) return;
   const int i = it.y + threadIdx.x;
   const int ii = i < o1 ? i : o1 - 1;
   const double xi = rec[ii].x, yi = rec[ii].y, zi = rec[ii].z;
@@ -121,7 +126,7 @@ __global__ void __launch_bounds__(kItem)
 }
 
 // y = x/gamma - E[x] for the configurations whose status equals `want`
-__global__ void __launch_bounds__(kItem)
+__global__ void __launch_bounds__(kItemMax)
     k_bp2(const int2* __restrict__ items, const int* __restrict__ off, const int* __restrict__ status,
           int want, const Src8<double>* __restrict__ src, const double* __restrict__ X,
           const int* __restrict__ kdev, int64_t ld, double P, double a2, double inv_gamma,
@@ -129,12 +134,13 @@ __global__ void __launch_bounds__(kItem)
   const int2 it = items[blockIdx.x];
   if (status[it.x] != want) return;
   const int o0 = off[it.x], o1 = off[it.x + 1];
+  if (wave_idle(it.y, o1)) return;
   const int i = it.y + threadIdx.x;
   const int ii = i < o1 ? i : o1 - 1;
   const double xi = src[ii].x, yi = src[ii].y, zi = src[ii].z;
   const double A24 = 24.0 * a2, A42 = 42.0 * a2;
   Mom<double> m;
-  const int s0 = it.y, s1 = min(o1, it.y + kItem);  // sources that can be the receiver itself
+  const int s0 = it.y, s1 = min(o1, it.y + (int)blockDim.x);  // sources that can be the receiver itself
 #pragma unroll 2
   for (int j = o0; j < s0; ++j) p2_pair<double, false>(src[j], xi, yi, zi, A24, A42, m);
   for (int j = s0; j < s1; ++j) p2_pair<double, true>(src[j], xi, yi, zi, A24, A42, m);
@@ -151,7 +157,7 @@ __global__ void __launch_bounds__(kItem)
 // Near-field lists of every configuration (partners only within the sphere's own configuration):
 // each work item scans its configuration's centres in index order, so a list holds the first
 // kNearCap partners with 2a <= r < r_c, as the single-configuration build does.
-__global__ void __launch_bounds__(kItem)
+__global__ void __launch_bounds__(kItemMax)
     k_bnear(const int2* __restrict__ items, const int* __restrict__ off, const double* __restrict__ R,
             double rmin2, double rc2, int* __restrict__ cnt, int* __restrict__ list) {
   const int2 it = items[blockIdx.x];
@@ -170,7 +176,7 @@ __global__ void __launch_bounds__(kItem)
 
 // outputs for every configuration
 template <bool HAS_T, bool HAS_D>
-__global__ void __launch_bounds__(kItem)
+__global__ void __launch_bounds__(kItemMax)
     k_bp3(const int2* __restrict__ items, const int* __restrict__ off, const RecO* __restrict__ rec,
           double a2, double mu_t, double mu_r, double slip_S, const double* __restrict__ v1s,
           const double* __restrict__ v2s, const double* __restrict__ Fe, const double* __restrict__ Te,
@@ -178,6 +184,7 @@ __global__ void __launch_bounds__(kItem)
           double* __restrict__ S, double* __restrict__ SigOut) {
   const int2 it = items[blockIdx.x];
   const int o0 = off[it.x], o1 = off[it.x + 1];
+  if (wave_idle(it.y, o1)) return;
   const int i = it.y + threadIdx.x;
   const int ii = i < o1 ? i : o1 - 1;
   const double xi = rec[ii].x, yi = rec[ii].y, zi = rec[ii].z;
@@ -416,10 +423,10 @@ void batched_pack_f(const double* R, const double* Fe, const double* Te, const d
                      rec, ntot);
 }
 
-void batched_p1(const int2* items, int nitems, const int* off, const RecF* rec, const double* v2s,
+void batched_p1(const int2* items, int nitems, int item, const int* off, const RecF* rec, const double* v2s,
                 bool has_t, bool has_d, const Phys& ph, double* b, hipStream_t s) {
 #define MBS_BP1(HT, HD)                                                                          \
-  hipLaunchKernelGGL((k_bp1<HT, HD>), dim3(nitems), dim3(kItem), 0, s, items, off, rec, v2s,     \
+  hipLaunchKernelGGL((k_bp1<HT, HD>), dim3(nitems), dim3(item), 0, s, items, off, rec, v2s,     \
                      ph.c_slip, ph.a2, b)
   if (has_t && has_d)
     MBS_BP1(true, true);
@@ -437,16 +444,16 @@ void batched_pack_s(const double* R, const double* X, const int* kdev, int maxk,
   hipLaunchKernelGGL(k_bpack_s, dim3(nblk(ntot, 256)), dim3(256), 0, s, R, X, kdev, maxk, ld, src, ntot);
 }
 
-void batched_p2(const int2* items, int nitems, const int* off, const int* status, int want,
+void batched_p2(const int2* items, int nitems, int item, const int* off, const int* status, int want,
                 const Src8<double>* src, const double* X, const int* kdev, int64_t ld, const Phys& ph,
                 double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_bp2, dim3(nitems), dim3(kItem), 0, s, items, off, status, want, src, X, kdev,
+  hipLaunchKernelGGL(k_bp2, dim3(nitems), dim3(item), 0, s, items, off, status, want, src, X, kdev,
                      ld, ph.P, ph.a2, ph.inv_gamma, y);
 }
 
-void batched_near_build(const int2* items, int nitems, const int* off, const double* R, double rmin,
+void batched_near_build(const int2* items, int nitems, int item, const int* off, const double* R, double rmin,
                         double rc, int* cnt, int* list, hipStream_t s) {
-  hipLaunchKernelGGL(k_bnear, dim3(nitems), dim3(kItem), 0, s, items, off, R, rmin * rmin, rc * rc, cnt, list);
+  hipLaunchKernelGGL(k_bnear, dim3(nitems), dim3(item), 0, s, items, off, R, rmin * rmin, rc * rc, cnt, list);
 }
 
 void batched_pack_o(const double* R, const double* Fe, const double* Te, const double* Sig,
@@ -455,12 +462,12 @@ void batched_pack_o(const double* R, const double* Fe, const double* Te, const d
                      ph.a5_10, rec, ntot);
 }
 
-void batched_p3(const int2* items, int nitems, const int* off, const RecO* rec, bool has_t, bool has_d,
+void batched_p3(const int2* items, int nitems, int item, const int* off, const RecO* rec, bool has_t, bool has_d,
                 const Phys& ph, const double* v1s, const double* v2s, const double* Fe,
                 const double* Te, const double* Sig, double* V, double* W, double* S, double* SigOut,
                 hipStream_t s) {
 #define MBS_BP3(HT, HD)                                                                              \
-  hipLaunchKernelGGL((k_bp3<HT, HD>), dim3(nitems), dim3(kItem), 0, s, items, off, rec, ph.a2,      \
+  hipLaunchKernelGGL((k_bp3<HT, HD>), dim3(nitems), dim3(item), 0, s, items, off, rec, ph.a2,      \
                      ph.mu_t, ph.mu_r, ph.slip_S, v1s, v2s, Fe, Te, Sig, V, W, S, SigOut)
   if (has_t && has_d)
     MBS_BP3(true, true);

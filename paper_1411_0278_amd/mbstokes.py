@@ -22,7 +22,7 @@ MBS_GUESS_ZERO, MBS_GUESS_DIAG, MBS_GUESS_LEARNED, MBS_GUESS_USER = 0, 1, 2, 3
 
 EXPORTS = ("mbs_default_params", "mbs_create", "mbs_destroy", "mbs_set_params", "mbs_last_error",
            "mbs_solve", "mbs_matvec", "mbs_rhs", "mbs_outputs", "mbs_step", "mbs_solve_batched",
-           "mbs_autotune", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
+           "mbs_autotune", "mbs_autotune_batched", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
            "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
            "mbs_warmstart_load", "mbs_warmstart_target", "mbs_initial_guess", "mbs_precond_apply")
 MLP_NPARAM, MLP_NFEAT = 27525, 80
@@ -41,7 +41,7 @@ class Params(ctypes.Structure):
                 ("lmax", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("guess", ctypes.c_int32),
                 ("check_overlap", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("graph", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("batch_item", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -96,6 +96,9 @@ def load(path: str = LIB_PATH):
     lib.mbs_solve_batched.restype = ctypes.c_int
     lib.mbs_autotune.argtypes = [P, I64, P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32), VP]
     lib.mbs_autotune.restype = ctypes.c_int
+    lib.mbs_autotune_batched.argtypes = [P, I32, ctypes.POINTER(ctypes.c_int64), P, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_double), VP]
+    lib.mbs_autotune_batched.restype = ctypes.c_int
     FP = ctypes.POINTER(ctypes.c_float)
     lib.mbs_features.argtypes = [P, I64, P, P, P, P, VP]
     lib.mbs_warmstart_init.argtypes = [P, ctypes.c_uint64]
@@ -265,6 +268,19 @@ class Context:
                                         _ptr(Sigma, ntot, 5, "Sigma"), stats, lat, _stream())
         self._check(rc)
         return V, W, S, [stats[b].as_dict() for b in range(nconf)], list(lat)
+
+
+def _autotune_batched(self, offsets, R):
+    nconf = len(offsets) - 1
+    off = (ctypes.c_int64 * (nconf + 1))(*[int(o) for o in offsets])
+    chosen = ctypes.c_int32()
+    ms = (ctypes.c_double * 3)()
+    self._check(self.lib.mbs_autotune_batched(self.h, nconf, off, _ptr(R, int(offsets[-1]), 3, "R"),
+                                              ctypes.byref(chosen), ms, _stream()))
+    return int(chosen.value), {64: ms[0], 128: ms[1], 256: ms[2]}
+
+
+Context.mbs_autotune_batched = _autotune_batched
 
 
 def _autotune(self, R, cache_json=None):

@@ -310,12 +310,16 @@ def _batch(ws):
     return off, cat
 
 
-def test_batched_matches_individual_oracle_solves(ctx):
-    ws = [_workload(n, seed=500 + n, v3t=0.0, torque=False) for n in (64, 90, 130, 33, 1, 2)]
+@pytest.mark.parametrize("item", [64, 128, 256])
+def test_batched_matches_individual_oracle_solves(ctx, item):
+    print(f"batched item={item}", flush=True)
+    ws = [_workload(n, seed=500 + n, v3t=0.0, torque=False) for n in (64, 90, 130, 33, 1, 2, 300)]
     off, cat = _batch(ws)
-    ctx.set_params(tol=1e-12)
-    V, W, S, stats, lat = ctx.mbs_solve_batched(off, cat("R"), cat("v1s"), cat("v2s"), None, cat("Fe"), None)
-    ctx.set_params(tol=1e-10)
+    ctx.set_params(tol=1e-12, batch_item=item)
+    try:
+        V, W, S, stats, lat = ctx.mbs_solve_batched(off, cat("R"), cat("v1s"), cat("v2s"), None, cat("Fe"), None)
+    finally:
+        ctx.set_params(tol=1e-10, batch_item=0)
     for b, w in enumerate(ws):
         ref = galerkin.solve(w)
         sl = slice(off[b], off[b + 1])
@@ -363,6 +367,18 @@ def test_batched_preconditioned_matches_oracle_in_fewer_iterations(ctx, graph):
             assert _rel(got, want) < 1e-10
         assert stats[b]["rel_resid"] <= 1e-12
     assert sum(st["iters"] for st in stats) < sum(st["iters"] for st in plain)
+
+
+def test_batched_autotune_picks_an_item_size(ctx):
+    sizes = inputs.batched_sizes(20, 64, 900, seed=4242)
+    ws = [_workload(int(n), seed=12_000 + b, v3t=0.0, torque=False) for b, n in enumerate(sizes)]
+    off, cat = _batch(ws)
+    item, ms = ctx.mbs_autotune_batched(off, cat("R"))
+    assert item in (64, 128, 256) and all(t > 0 for t in ms.values()) and ms[item] == min(ms.values())
+    V, W, S, stats, lat = ctx.mbs_solve_batched(off, cat("R"), cat("v1s"), cat("v2s"), None, cat("Fe"), None)
+    for b in (0, 7, 19):
+        ref = galerkin.solve(ws[b])
+        assert _rel(V[off[b]:off[b + 1]], ref["V"]) < 1e-9
 
 
 def test_batched_graph_replays_equal_direct_launches(ctx):
