@@ -26,6 +26,7 @@ FP32_PEAK_TF = 157.3    # MI355X vector FP32 (published figure, counts packed FP
 # algorithmic FLOP per pair block of the system operator as implemented (FMA = 2, rsqrt = 1):
 # differences 3, r^2 5, 1/r 1, powers 4, Szz 1, w 15, q 5, c1 3, c2 4, v 9, moments 18, r^-5 Sigma 10
 P2_FLOP_PER_PAIR = 78
+FLOW_FLOP_PER_PAIR = 68  # field-point flow from force and flow stresslet (no torque, no rank-3 mode)
 
 
 def parse():
@@ -194,6 +195,12 @@ def bench_kernels(ctx, a):
             sig = torch.randn((n, 5), dtype=torch.float64, device="cuda:0")
             ms = median_ms(lambda: ctx.mbs_outputs(d["R"], sig, d["v1s"], d["v2s"], None, d["Fe"], None))
             row["p3"] = {"ms": round(ms, 4), "pair_blocks_per_s": n * (n - 1) / (ms * 1e-3)}
+            # flow at as many field points as spheres (uniform in the cube; timing only)
+            gen = torch.Generator(device="cuda:0").manual_seed(5)
+            X = (torch.rand((n, 3), dtype=torch.float64, device="cuda:0", generator=gen) - 0.5) * a.side
+            ms = median_ms(lambda: ctx.mbs_flow(X, d["R"], sig, Fe=d["Fe"]))
+            row["flow"] = {"ms": round(ms, 4), "field_points": n, "pair_blocks_per_s": n * n / (ms * 1e-3),
+                           "tflops_algorithmic": round(FLOW_FLOP_PER_PAIR * n * n / (ms * 1e-3) / 1e12, 3)}
         out[label] = row
         print(f"bench: pair passes at {label} timed", file=sys.stderr, flush=True)
     return out

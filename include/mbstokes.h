@@ -170,6 +170,17 @@ int mbs_outputs(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, con
                 const double* v3t, const double* Fe, const double* Te, const double* Sigma,
                 double* V, double* W, double* S, void* stream);
 
+/* Flow of the suspension at m field points X [m x 3] (section III: the exterior flow is the sum
+   over spheres of the flows of their force F^e (with the finite-size factor 1 + a^2/6 nabla^2),
+   torque (rotlet), flow stresslet Sigma (with 1 + a^2/10 nabla^2) and rank-3 trace mode d =
+   V^(3t); no finite-size operator acts at the field point). Typically Sigma is the solution of
+   mbs_solve for the same spheres. n, R, Fe, Te, Sigma, v3t: as in mbs_solve (Fe, Te, v3t may be
+   NULL = zero). U: [m x 3]. Field points should lie outside every sphere (inside, the result is
+   the exterior formula, not the rigid-body motion); a field point exactly on a centre gets no
+   contribution from that sphere. */
+int mbs_flow(mbs_ctx* ctx, int64_t m, const double* X, int64_t n, const double* R, const double* Fe,
+             const double* Te, const double* Sigma, const double* v3t, double* U, void* stream);
+
 /* Time integration in a harmonic trap (section V set-up; kinematics of section II):
    every step rebuilds F^e = -k_trap R, T^e = 0, V^(1s) = c0 p, V^(2s) = c1 * 3(pp - I/3),
    V^(3t) = c2 p from the current state, solves, and advances

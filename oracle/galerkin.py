@@ -144,6 +144,22 @@ def superposition(w, prm: Params | None = None):
     return dict(V=V, W=W, S=S, Sigma=Sigma)
 
 
+def flow_field(X, R, Fe, Te, Sigma, v3t, prm: Params):
+    """Exterior flow at field points X [M, 3] (section III): the sum over spheres m of the source
+    flows of its force, torque, flow stresslet and rank-3 trace mode at X - R_m, each carrying its
+    own finite-size operator and none at the field point. None stands for an absent source."""
+    X = np.asarray(X, dtype=np.float64).reshape(-1, 3)
+    R = np.asarray(R, dtype=np.float64).reshape(-1, 3)
+    u = np.zeros_like(X)
+    sources = {"F": Fe, "T": Te, "S": Sigma, "D": v3t}
+    for m in range(R.shape[0]):
+        dx = X - R[m]
+        for kind, vals in sources.items():
+            if vals is not None:
+                u += greens.flow(kind, dx, prm.a, prm.eta) @ np.asarray(vals, dtype=np.float64)[m]
+    return u
+
+
 def matvec_rows(R, x, rows, prm: Params):
     """(A x) restricted to the given particles, without forming A: [len(rows), 5]."""
     g = constants(prm)["gamma"]

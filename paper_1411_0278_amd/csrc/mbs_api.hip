@@ -883,6 +883,21 @@ int mbs_outputs(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const
   return MBS_OK;
 }
 
+int mbs_flow(mbs_ctx* c, int64_t m, const double* X, int64_t n, const double* R, const double* Fe,
+             const double* Te, const double* Sigma, const double* v3t, double* U, void* stream) {
+  CHK(begin_call(c));
+  if (m < 1 || n < 1) return set_err(c, MBS_EINVAL, "m and n must be >= 1");
+  if (m > (int64_t)INT32_MAX / 12 || n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "m or n too large");
+  if (!X || !R || !Sigma || !U) return set_err(c, MBS_EINVAL, "X, R, Sigma and U are required");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, n));  // (zeros stand in for absent forces)
+  CHK(ensure(c, c->part, (size_t)flow_split(m, n, c->tile_pass) * 3 * m + 64));
+  launch_flow(X, m, R, Fe ? Fe : c->zeros.p, Te, Sigma, v3t, U, c->part.p, n, c->ph, c->tile_pass, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
 int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const double* slip_coef,
              double dt, int32_t nsteps, int32_t order, mbs_stats* per_step, double* min_dist,
              void* stream) {

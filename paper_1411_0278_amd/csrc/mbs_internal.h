@@ -50,6 +50,12 @@ void launch_p3(const double* R, const double* v1s, const double* v2s, const doub
 void launch_p23(const double* R, const double* v1s, const double* v2s, const double* v3t,
                 const double* Fe, const double* Te, const double* Sig, double* y, double* V, double* W,
                 double* S, double* part, int64_t n, const Phys& ph, Tile t, hipStream_t s);
+// flow U [m x 3] at field points X [m x 3] from n spheres (force, torque, flow stresslet, rank-3
+// trace mode; Te and v3t may be NULL); part: scratch of flow_split(m, n, t) x 3m doubles
+int flow_split(int64_t m, int64_t n, Tile t);
+void launch_flow(const double* X, int64_t m, const double* R, const double* Fe, const double* Te,
+                 const double* Sig, const double* v3t, double* U, double* part, int64_t n, const Phys& ph,
+                 Tile t, hipStream_t s);
 // min over pairs of |R_n - R_m|^2 -> out[0] (device), from the cell grid g of R (exact: an
 // all-pairs scan takes over when no pair is closer than one cell edge); scratch: ceil(n/256) doubles
 struct GridView;

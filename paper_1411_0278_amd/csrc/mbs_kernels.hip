@@ -294,6 +294,74 @@ __global__ void k_p23_finish(const double* __restrict__ part, int split, int64_t
   }
 }
 
+// ------------------------------------------------------------------ flow at field points
+// u(x) = sum_m of the source flows of sphere m at x - R_m (section III: force with its finite-size
+// factor 1 + a^2/6 nabla^2, rotlet, flow stresslet with 1 + a^2/10 nabla^2, rank-3 trace mode);
+// no finite-size operator acts at the field point:
+//   F: P[(1/r + a^2/(3 r^3)) F + (1/r^3 - a^2/r^5)(x.F) x]      T: P (T x x)/r^3
+//   Sigma: P[q x (-3/r^5 + 3a^2/r^7) - (6a^2/5) w / r^5]        d: (a^5/10)[3 (x.d) x/r^5 - d/r^3]
+// with w = Sigma x, q = x.w. Per (field point, sphere) pair about 70 FLOP. One field point per
+// thread, sphere records through LDS tiles, sphere chunks along grid.y summed in a fixed order.
+template <int TJ, bool HAS_T, bool HAS_D>
+__global__ void __launch_bounds__(kMaxBlock)
+    k_flow(const double* __restrict__ X, int m, const double* __restrict__ R, const double* __restrict__ Fe,
+           const double* __restrict__ Te, const double* __restrict__ Sig, const double* __restrict__ D,
+           double* __restrict__ out, int n, int chunk, double P, double a2, double a5_10) {
+  __shared__ RecO tile[TJ];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < m ? i : m - 1;
+  const double xi = X[3 * (int64_t)ii], yi = X[3 * (int64_t)ii + 1], zi = X[3 * (int64_t)ii + 2];
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  const double A2_3 = a2 / 3.0, A6_5 = 1.2 * a2, A3 = 3.0 * a2;
+  double ux = 0.0, uy = 0.0, uz = 0.0;
+  for (int jt = j0; jt < j1; jt += TJ) {
+    const int cnt = min(TJ, j1 - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x)
+      tile[t] = make_reco<HAS_T, HAS_D>(R, Fe, Te, Sig, D, jt + t, P, a5_10);
+    __syncthreads();
+#pragma unroll 2
+    for (int jj = 0; jj < cnt; ++jj) {
+      const RecO& sr = tile[jj];
+      Geo g;
+      pair_geo<true>(sr, xi, yi, zi, g);  // a field point on a centre gets no contribution from it
+      const double ri7 = g.ri5 * g.ri2;
+      const double xF = fma(g.dx, sr.fx, fma(g.dy, sr.fy, g.dz * sr.fz));
+      double cx = xF * fma(-a2, g.ri5, g.ri3) + g.q * fma(A3, ri7, -3.0 * g.ri5);
+      const double cF = fma(A2_3, g.ri3, g.ri);
+      const double cw = -A6_5 * g.ri5;
+      if (HAS_D) cx = fma(3.0 * g.ri5, g.dx * sr.dx + g.dy * sr.dy + g.dz * sr.dz, cx);
+      ux = fma(cx, g.dx, fma(cF, sr.fx, fma(cw, g.wx, ux)));
+      uy = fma(cx, g.dy, fma(cF, sr.fy, fma(cw, g.wy, uy)));
+      uz = fma(cx, g.dz, fma(cF, sr.fz, fma(cw, g.wz, uz)));
+      if (HAS_T) {
+        ux = fma(g.ri3, sr.ty * g.dz - sr.tz * g.dy, ux);
+        uy = fma(g.ri3, sr.tz * g.dx - sr.tx * g.dz, uy);
+        uz = fma(g.ri3, sr.tx * g.dy - sr.ty * g.dx, uz);
+      }
+      if (HAS_D) {
+        ux = fma(-g.ri3, sr.dx, ux);
+        uy = fma(-g.ri3, sr.dy, uy);
+        uz = fma(-g.ri3, sr.dz, uz);
+      }
+    }
+  }
+  if (i >= m) return;
+  double* o = out + (int64_t)blockIdx.y * 3 * m + 3 * (int64_t)i;
+  o[0] = ux;
+  o[1] = uy;
+  o[2] = uz;
+}
+
+__global__ void k_flow_finish(const double* __restrict__ part, int split, int64_t len, double* __restrict__ U) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  double acc = 0.0;
+  for (int s = 0; s < split; ++s) acc += part[s * len + k];
+  U[k] = acc;
+}
+
 // ------------------------------------------------------------------ overlap monitor
 template <int TJ>
 __global__ void __launch_bounds__(kMaxBlock)
@@ -679,6 +747,37 @@ void launch_p23(const double* R, const double* v1s, const double* v2s, const dou
 #undef MBS_P23
   hipLaunchKernelGGL(k_p23_finish, dim3(nblk(n, 256)), dim3(256), 0, s, part, split, n, v1s, v2s, Fe, Te,
                      Sig, y, V, W, S, ph.inv_gamma, ph.mu_t, ph.mu_r, ph.slip_S);
+}
+
+int flow_split(int64_t m, int64_t n, Tile t) {
+  // enough workgroups to fill the GPU: field-point tiles times sphere chunks of >= 128 spheres
+  const int64_t ntile = (m + tile_block(t) - 1) / tile_block(t);
+  const int64_t target = t.wgs > 0 ? t.wgs : 2048;
+  const int64_t s = (target + ntile - 1) / ntile;
+  return (int)std::min<int64_t>(std::max<int64_t>(s, 1), std::max<int64_t>(1, (n + 127) / 128));
+}
+
+void launch_flow(const double* X, int64_t m, const double* R, const double* Fe, const double* Te,
+                 const double* Sig, const double* v3t, double* U, double* part, int64_t n, const Phys& ph,
+                 Tile t, hipStream_t s) {
+  constexpr int TJ = 128;
+  const int bs = tile_block(t);
+  const int split = flow_split(m, n, t);
+  const int chunk = (int)((n + split - 1) / split);
+  dim3 grid(nblk(m, bs), split);
+#define MBS_FLOW(HT, HD)                                                                               \
+  hipLaunchKernelGGL((k_flow<TJ, HT, HD>), grid, dim3(bs), 0, s, X, (int)m, R, Fe, Te, Sig, v3t, part, (int)n, \
+                     chunk, ph.P, ph.a2, ph.a5_10)
+  if (Te && v3t)
+    MBS_FLOW(true, true);
+  else if (Te)
+    MBS_FLOW(true, false);
+  else if (v3t)
+    MBS_FLOW(false, true);
+  else
+    MBS_FLOW(false, false);
+#undef MBS_FLOW
+  hipLaunchKernelGGL(k_flow_finish, dim3(nblk(3 * m, 256)), dim3(256), 0, s, part, split, 3 * m, U);
 }
 
 void launch_min_dist2(const GridView& g, const double* R, int64_t n, double* out, double* scratch,

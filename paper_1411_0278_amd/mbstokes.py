@@ -21,7 +21,7 @@ MBS_FP64, MBS_MIXED, MBS_FP32 = 0, 1, 1
 MBS_GUESS_ZERO, MBS_GUESS_DIAG, MBS_GUESS_LEARNED, MBS_GUESS_USER = 0, 1, 2, 3
 
 EXPORTS = ("mbs_default_params", "mbs_create", "mbs_destroy", "mbs_set_params", "mbs_last_error",
-           "mbs_solve", "mbs_matvec", "mbs_rhs", "mbs_outputs", "mbs_step", "mbs_solve_batched",
+           "mbs_solve", "mbs_matvec", "mbs_rhs", "mbs_outputs", "mbs_flow", "mbs_step", "mbs_solve_batched",
            "mbs_autotune", "mbs_autotune_batched", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
            "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
            "mbs_warmstart_load", "mbs_warmstart_target", "mbs_initial_guess", "mbs_precond_apply")
@@ -88,6 +88,8 @@ def load(path: str = LIB_PATH):
     lib.mbs_rhs.restype = ctypes.c_int
     lib.mbs_outputs.argtypes = [P, I64] + [P] * 10 + [VP]
     lib.mbs_outputs.restype = ctypes.c_int
+    lib.mbs_flow.argtypes = [P, I64, P, I64, P, P, P, P, P, P, VP]
+    lib.mbs_flow.restype = ctypes.c_int
     lib.mbs_step.argtypes = [P, I64, P, P, D, ctypes.POINTER(ctypes.c_double), D, I32, I32,
                              ctypes.POINTER(Stats), ctypes.POINTER(ctypes.c_double), VP]
     lib.mbs_step.restype = ctypes.c_int
@@ -238,6 +240,15 @@ class Context:
                                          _ptr(Te, n, 3, "Te"), _ptr(Sigma, n, 5, "Sigma"), _ptr(V, n, 3, "V"),
                                          _ptr(W, n, 3, "W"), _ptr(S, n, 5, "S"), _stream()))
         return V, W, S
+
+    def mbs_flow(self, X, R, Sigma, Fe=None, Te=None, v3t=None, U=None):
+        import torch
+        m, n = X.shape[0], R.shape[0]
+        U = torch.empty((m, 3), dtype=torch.float64, device=X.device) if U is None else U
+        self._check(self.lib.mbs_flow(self.h, m, _ptr(X, m, 3, "X"), n, _ptr(R, n, 3, "R"), _ptr(Fe, n, 3, "Fe"),
+                                      _ptr(Te, n, 3, "Te"), _ptr(Sigma, n, 5, "Sigma"), _ptr(v3t, n, 3, "v3t"),
+                                      _ptr(U, m, 3, "U"), _stream()))
+        return U
 
     def mbs_step(self, R, p, k_trap, slip_coef, dt, nsteps, order=2, want_min_dist=False,
                  allow_noconv=False):

@@ -150,6 +150,54 @@ def test_outputs_match_oracle(ctx, n):
     assert _maxrel(gS, S) < 1e-14
 
 
+def _field_points(R, m, seed, a=1.0):
+    """m points spread over the spheres' box, none inside a sphere."""
+    rng = np.random.default_rng(seed)
+    lo, hi = R.min(0) - 3.0, R.max(0) + 3.0
+    pts = []
+    while len(pts) < m:
+        X = rng.uniform(lo, hi, (2 * m, 3))
+        D = np.linalg.norm(X[:, None] - R[None], axis=2).min(1)
+        pts.extend(X[D > 1.05 * a])
+    return np.array(pts[:m])
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (2, 257), (300, 1000), (700, 64)])
+@pytest.mark.parametrize("full", [False, True])
+def test_flow_field_matches_oracle(ctx, n, m, full):
+    print(f"flow field n={n} m={m} full={full}", flush=True)
+    w = _workload(n, seed=950 + n, v3t=1.0 if full else 0.0, torque=full)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    Sig = np.random.default_rng(n + m).standard_normal((n, 5))
+    X = _field_points(w.R, m, seed=m)
+    Te, v3t = (w.Te, w.v3t) if full else (None, None)
+    want = galerkin.flow_field(X, w.R, w.Fe, Te, Sig, v3t, prm)
+    got = ctx.mbs_flow(_t(X), _t(w.R), _t(Sig), Fe=_t(w.Fe), Te=_t(Te) if full else None,
+                       v3t=_t(v3t) if full else None)
+    assert _maxrel(got, want) < 1e-13
+
+
+def test_flow_field_of_a_solution_meets_the_sphere_velocity(ctx):
+    """On a sphere's surface the flow of the solved suspension averages to the sphere's V - V^a
+    (the weak Dirichlet condition of the l = 0 mode), here with the GPU solve and the GPU flow."""
+    w = _workload(40, seed=961, v3t=1.0, torque=True)
+    d = mbstokes.to_device(w, DEV)
+    ctx.set_params(tol=1e-13)
+    try:
+        Sig = torch.empty((w.n, 5), dtype=torch.float64, device=DEV)
+        V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"], Sigma=Sig)
+    finally:
+        ctx.set_params(tol=1e-10)
+    from tests import sphere_quad
+    nh, wq = sphere_quad.sphere_rule(48, 96)
+    i = 7
+    pts = w.R[i] + w.a * nh
+    u = ctx.mbs_flow(_t(pts), d["R"], Sig, Fe=d["Fe"], Te=d["Te"], v3t=d["v3t"]).cpu().numpy()
+    mean, _ = sphere_quad.coefficients(u, nh, wq, w.a)
+    want = V.cpu().numpy()[i] + w.v1s[i]
+    assert np.abs(mean - want).max() < 1e-9 * np.abs(u).max()
+
+
 def test_null_optional_inputs_mean_zero(ctx):
     w = _workload(40, seed=7, v3t=0.0, torque=False)
     prm = galerkin.Params(eta=w.eta, a=w.a)

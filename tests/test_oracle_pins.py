@@ -204,14 +204,11 @@ def test_solution_satisfies_weak_boundary_conditions_by_quadrature():
                         rng.standard_normal((n, 3)), rng.standard_normal((n, 3)),
                         rng.standard_normal((n, 3)), ETA, A)
     sol = galerkin.solve(w, PRM)
-    src = {"F": w.Fe, "T": w.Te, "S": sol["Sigma"], "D": w.v3t}
     nh, wq = sphere_quad.sphere_rule(48, 96)
     for i in range(n):
         pts = R[i] + A * nh
-        u = np.zeros_like(pts)
-        for m in range(n):
-            for X, vals in src.items():
-                u += greens.flow(X, pts - R[m], A, ETA) @ vals[m]
+        # the suspension's flow on sphere i's surface (the oracle's field-point evaluation)
+        u = galerkin.flow_field(pts, R, w.Fe, w.Te, sol["Sigma"], w.v3t, PRM)
         mean, V2 = sphere_quad.coefficients(u, nh, wq, A)
         scale = np.abs(u).max()
         assert np.abs(mean - (sol["V"][i] + w.v1s[i])).max() < 1e-11 * scale      # V - V^a
