@@ -294,6 +294,56 @@ def bench_stepper(ctx, a):
     return out
 
 
+def bench_paper_trap(ctx, a):
+    """The trap of section V: 10^4 active spheres spread over the sphere R* = 1256.6a, pointing out
+    (the stable state without interactions); AB2 with dt = 2 (tau_r = 8 pi eta a / k = 1675.5).
+    Superposition approximation (the paper's own equations of motion) up to 8 tau_r, and the full
+    many-body solve up to tau_r. Reports per-step time and, at t = tau_r, 2 tau_r, 8 tau_r, the mean
+    p.R/|R| (1 at the start), the mean |R|/R* and the share of spheres pointing inward."""
+    import numpy as np
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+    w = inputs.paper_trap_workload()
+    rstar = 1256.6
+    k = -w.Fe[0, 0] / w.R[0, 0]
+    tau_r = (8.0 * np.pi * w.eta * w.a) / k
+    dt = 2.0
+    per = int(round(tau_r / dt))
+    coef = (-1.0, 0.0, 0.0)
+
+    def snapshot(R, p, t):
+        Rn, pn = R.cpu().numpy(), p.cpu().numpy()
+        r = np.linalg.norm(Rn, axis=1)
+        pr = (pn * Rn).sum(1) / r
+        return {"t_over_tau_r": round(t / tau_r, 3), "mean_p_dot_rhat": float(pr.mean()),
+                "mean_radius_over_Rstar": float(r.mean() / rstar), "inward_share": float((pr < 0).mean())}
+
+    out = {"n": w.n, "Rstar_over_a": rstar, "k": k, "tau_r": tau_r, "dt": dt, "slip": "V^a = p (mean slip only)"}
+    for mode, sup, horizon in (("superposition", 1, (1, 2, 8)), ("many_body", 0, (1,))):
+        R = torch.as_tensor(w.R).to("cuda:0")
+        p = torch.as_tensor(w.p).to("cuda:0")
+        ctx.set_params(superposition=sup, precision=mbstokes.MBS_MIXED, guess=mbstokes.MBS_GUESS_USER,
+                       tol=1e-10, near_cutoff=0.0, max_iter=60)
+        snaps, done, secs, steps = [snapshot(R, p, 0.0)], 0, 0.0, 0
+        for mult in horizon:
+            todo = mult * per - done
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, md = ctx.mbs_step(R, p, k, coef, dt, todo, order=2, want_min_dist=True, allow_noconv=True)
+            torch.cuda.synchronize()
+            secs += time.perf_counter() - t0
+            steps += todo
+            done = mult * per
+            s = snapshot(R, p, done * dt)
+            s["min_distance"] = float(min(md))
+            snaps.append(s)
+        out[mode] = {"steps": steps, "seconds": secs, "ms_per_step": 1e3 * secs / steps, "snapshots": snaps}
+        print(f"bench: paper trap {mode} {steps} steps in {secs:.1f} s", file=sys.stderr, flush=True)
+    ctx.set_params(superposition=0, precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, max_iter=300)
+    return out
+
+
 def cpu_baseline(w, seconds):
     """The oracle's system-operator rows on host cores: pair-blocks/s on a bounded row sample."""
     import numpy as np
@@ -377,6 +427,7 @@ def main():
         extra["pair_passes"] = bench_kernels(ctx, a)
     if not a.skip_stepper:
         extra["stepper"] = bench_stepper(ctx, a)
+        extra["paper_trap"] = bench_paper_trap(ctx, a)
     head = variants[a.headline]
     out = {
         "metric": METRIC,

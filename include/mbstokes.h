@@ -94,7 +94,9 @@ typedef struct mbs_params {
                             (default), 0 = launch the same kernels directly */
   int32_t batch_item;    /* mbs_solve_batched: receivers per work item (64, 128 or 256); 0 = the
                             context's choice (mbs_autotune_batched, else 64) */
-  int32_t reserved;      /* set to 0 */
+  int32_t superposition; /* nonzero: mbs_solve and mbs_step use the superposition approximation of
+                            section IV instead of solving: Sigma_n = -c gamma s_n (lone-sphere
+                            stresslets), outputs by the direct sum; 0 = the many-body solve */
 } mbs_params;
 
 typedef struct mbs_stats {

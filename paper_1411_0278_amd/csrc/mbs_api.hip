@@ -578,6 +578,23 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const do
   c->t_op[0] = c->t_op[1] = 0.0;
   c->near_ready = false;
   HIPCHK(c, hipEventRecord(c->ev[0], s));
+  if (c->prm.superposition) {
+    // superposition approximation (section IV): every sphere keeps its lone-sphere stresslet
+    // Sigma_n = -c gamma s_n, no system is solved, the motion is the direct sum of the pair flows
+    launch_axpby(-c->ph.c_slip * c->ph.gamma, v2s ? v2s : c->zeros.p, 0.0, c->xs.p, len, s);
+    HIPCHK(c, hipEventRecord(c->ev[1], s));
+    HIPCHK(c, hipEventRecord(c->ev[2], s));
+    launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
+    if (Sigma) launch_copy(c->xs.p, Sigma, len, s);
+    HIPCHK(c, hipEventRecord(c->ev[3], s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (st) {
+      memset(st, 0, sizeof(*st));
+      st->t_out_ms = st->t_total_ms = ev_ms(c->ev[2], c->ev[3]);
+      st->pair_blocks = (double)n * (double)(n - 1);
+    }
+    return MBS_OK;
+  }
   if (c->prm.near_cutoff > 0.0) CHK(near_prepare(c, n, R, s));
   // right-hand side
   launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
@@ -723,6 +740,7 @@ void mbs_default_params(mbs_params* p) {
   p->tile = 0;
   p->graph = 1;
   p->batch_item = 0;
+  p->superposition = 0;
 }
 
 int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {

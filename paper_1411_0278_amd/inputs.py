@@ -145,6 +145,26 @@ def trap_workload(n: int, side: float, seed: int, k: float = TRAP_K, v3t: float 
     return Workload(R, p, v1s, v2s, v3, -k * R, np.zeros_like(R), name=name or f"trap_n{n}_L{side:g}_s{seed}")
 
 
+def sphere_points(n: int, radius: float) -> np.ndarray:
+    """n quasi-uniform points on a sphere (golden-angle spiral), deterministic."""
+    k = np.arange(n, dtype=np.float64) + 0.5
+    z = 1.0 - 2.0 * k / n
+    rho = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = np.pi * (3.0 - np.sqrt(5.0)) * k
+    return radius * np.stack([rho * np.cos(phi), rho * np.sin(phi), z], axis=1)
+
+
+def paper_trap_workload(n: int = 10_000, radius_in_a: float = 1256.6, vs: float = 1.0) -> Workload:
+    """The trap set-up of section V: active spheres spread uniformly over the sphere of radius
+    R* = 6 pi eta a v_s / k (their stable state without interactions), each pointing outward, so the
+    self-propulsion V^a = v_s p balances the trap force -k R. Only the mean slip is set (V^(1s) = -v_s p); the stresslet and rank-3 strengths are not given."""
+    R = sphere_points(n, radius_in_a * RADIUS)
+    p = R / np.linalg.norm(R, axis=1, keepdims=True)
+    k = 6.0 * math.pi * ETA * RADIUS * vs / (radius_in_a * RADIUS)
+    v1s, v2s, v3 = slip_modes(p, -vs, 0.0, 0.0)
+    return Workload(R, p, v1s, v2s, v3, -k * R, np.zeros_like(R), name=f"paper_trap_n{n}_R{radius_in_a:g}")
+
+
 # The benchmark configurations (sizes, boxes, seeds).
 def config0(seed: int = 0) -> Workload:
     """N = 256 in a cube of side 40 (number density 0.004); mean + strain slip; trap k = 0.5."""

@@ -351,6 +351,53 @@ def test_minimum_distance_monitor(ctx, case):
     assert abs(md[0] - D.min()) <= 1e-12 * D.min()
 
 
+# ---------------------------------------------------------------- superposition approximation
+def test_superposition_matches_oracle(ctx):
+    w = _workload(300, seed=71, v3t=1.0, torque=True)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    ref = galerkin.superposition(w, prm)
+    d = mbstokes.to_device(w, DEV)
+    ctx.set_params(superposition=1)
+    try:
+        Sig = torch.empty((w.n, 5), dtype=torch.float64, device=DEV)
+        V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"], Sigma=Sig)
+    finally:
+        ctx.set_params(superposition=0)
+    for got, want in ((V, ref["V"]), (W, ref["W"]), (S, ref["S"]), (Sig, ref["Sigma"])):
+        assert _maxrel(got, want) < 1e-13
+    assert st["iters"] == 0
+
+
+def test_superposition_stepper_matches_oracle(ctx):
+    w = _workload(64, seed=72, torque=False)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    Rw, pw, _ = stepper.run(w.R, w.p, 0.5, (1.0, 1.0, 1.0), 0.01, 3, prm, superposition=True)
+    R, p = _t(w.R), _t(w.p)
+    ctx.set_params(superposition=1)
+    try:
+        ctx.mbs_step(R, p, 0.5, (1.0, 1.0, 1.0), 0.01, 3, order=2)
+    finally:
+        ctx.set_params(superposition=0)
+    assert _maxrel(R, Rw) < 1e-12 and _maxrel(p, pw) < 1e-12
+
+
+@pytest.mark.parametrize("superposition", [0, 1])
+def test_antipodal_active_pair_keeps_its_orientation(ctx, superposition):
+    """Two active spheres at opposite points of the trap sphere R* = 12.56a, pointing outward
+    (section V): the interactions are along the axis, so nothing rotates and both stay on it."""
+    rs = 12.56
+    Rn = np.array([[0.0, 0.0, rs], [0.0, 0.0, -rs]])
+    pn = Rn / rs
+    R, p = _t(Rn), _t(pn)
+    ctx.set_params(superposition=superposition, tol=1e-12)
+    try:
+        ctx.mbs_step(R, p, 1.0 / rs, (-1.0, 0.0, 0.0), 0.5, 40, order=2)
+    finally:
+        ctx.set_params(superposition=0, tol=1e-10)
+    assert np.abs(p.cpu().numpy() - pn).max() < 1e-14
+    assert np.abs(R.cpu().numpy()[:, :2]).max() < 1e-12
+
+
 # ---------------------------------------------------------------- batched
 def _batch(ws):
     off = np.cumsum([0] + [w.n for w in ws])
