@@ -32,6 +32,20 @@ struct DevBuf {
   size_t cap = 0;  // elements
 };
 
+// Graphs of the Arnoldi steps k = 0..m-1 of one (size, positions, precision, workspace) key.
+struct StepGraphs {
+  std::vector<uintptr_t> key, seen;
+  hipGraphExec_t g[64] = {};
+  void reset() {
+    for (auto& e : g)
+      if (e) {
+        (void)hipGraphExecDestroy(e);
+        e = nullptr;
+      }
+    key.clear();
+  }
+};
+
 }  // namespace
 
 struct mbs_ctx {
@@ -62,6 +76,9 @@ struct mbs_ctx {
   DevBuf mlp_w, mlp_g, mlp_m, mlp_v, mlp_wb, mlp_ws, mlp_part, mlp_loss, mlp_idx, knn_buf;
   // cell grid of the centres behind both neighbour searches (near-field lists, nearest neighbours)
   DevBuf grid;
+  // single-configuration GMRES: Arnoldi steps captured as graphs (per precision), see step_graphs
+  StepGraphs sgraph[2];
+  hipStream_t gstream = nullptr;
   // batched solver: workspace, capture stream and the four graphs of the last batch shape
   DevBuf bat, btune;
   int bitem = 64;  // receivers per batched work item (mbs_autotune_batched's choice)
@@ -227,14 +244,17 @@ struct OutPass {
 };
 
 void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x, double* y,
-              hipStream_t s, Counters& cnt) {
-  if (c->npend == mbs_ctx::kRing) {
-    (void)hipStreamSynchronize(s);
-    harvest_ops(c);
+              hipStream_t s, Counters& cnt, bool timed = true) {
+  int slot = -1;
+  if (timed) {  // (not inside a graph capture)
+    if (c->npend == mbs_ctx::kRing) {
+      (void)hipStreamSynchronize(s);
+      harvest_ops(c);
+    }
+    slot = c->npend++;
+    c->op_prec[slot] = prec;
+    (void)hipEventRecord(c->opev[2 * slot], s);
   }
-  const int slot = c->npend++;
-  c->op_prec[slot] = prec;
-  (void)hipEventRecord(c->opev[2 * slot], s);
   if (prec == MBS_FP64) {
     launch_p2(false, R, x, y, c->part.p, c->srcbuf.p, c->orig.p, n, c->ph, c->tile64, s);
     cnt.f64++;
@@ -242,7 +262,7 @@ void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x,
     launch_p2(true, R, x, y, c->part.p, c->srcbuf.p, c->orig.p, n, c->ph, c->tile32, s);
     cnt.f32++;
   }
-  (void)hipEventRecord(c->opev[2 * slot + 1], s);
+  if (timed) (void)hipEventRecord(c->opev[2 * slot + 1], s);
   cnt.pairs += (double)n * (double)(n - 1);
 }
 
@@ -291,6 +311,59 @@ void near_apply(mbs_ctx* c, int64_t n, const double* R, const double* x, double*
   launch_near_apply(R, x, cntp, cntp + n, n, c->ph, y, s);
 }
 
+// Small systems are bound by launch and synchronisation latency, so their Arnoldi steps are
+// captured into graphs (one per step index k, the kernels' pointers and sizes fixed) and replayed.
+// A key seen for the first time runs eagerly; from its second use (the stepper, repeated solves of
+// one configuration) the steps are captured once and replayed. Any change of size, positions
+// pointer, precision, preconditioning, launch shape or workspace drops the graphs.
+constexpr int64_t kGraphMaxN = 32768;
+
+uintptr_t dbits(double v) {
+  uintptr_t b = 0;
+  memcpy(&b, &v, sizeof(v) < sizeof(b) ? sizeof(v) : sizeof(b));
+  return b;
+}
+
+StepGraphs* step_graphs(mbs_ctx* c, int prec, int64_t n, const double* R, bool pc) {
+  if (!c->prm.graph || n > kGraphMaxN) return nullptr;
+  const Tile t = prec == MBS_FP64 ? c->tile64 : c->tile32;
+  const std::vector<uintptr_t> key = {
+      (uintptr_t)n, (uintptr_t)R, (uintptr_t)pc, (uintptr_t)t.variant, (uintptr_t)t.block, (uintptr_t)t.tj,
+      (uintptr_t)t.wgs, (uintptr_t)c->prm.restart, (uintptr_t)c->V.p, (uintptr_t)c->w.p, (uintptr_t)c->zt.p,
+      (uintptr_t)c->H.p, (uintptr_t)c->small.p, (uintptr_t)c->dpart.p, (uintptr_t)c->part.p,
+      (uintptr_t)c->srcbuf.p, (uintptr_t)c->orig.p, (uintptr_t)c->near.p, dbits(c->ph.P), dbits(c->ph.a2),
+      dbits(c->ph.gamma), dbits(c->ph.inv_gamma)};
+  StepGraphs& G = c->sgraph[prec == MBS_FP64 ? 0 : 1];
+  if (key == G.key) return &G;
+  G.reset();
+  if (key == G.seen) {
+    G.key = key;
+    return &G;
+  }
+  G.seen = key;
+  return nullptr;
+}
+
+// Launch Arnoldi step k from its graph, capturing it first if needed (on a stream of the context).
+template <typename Fn>
+int launch_step_graph(mbs_ctx* c, StepGraphs& G, int k, Fn enqueue, hipStream_t s) {
+  if (!G.g[k]) {
+    if (!c->gstream) HIPCHK(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+    enqueue(c->gstream);
+    HIPCHK(c, hipStreamEndCapture(c->gstream, &g));
+    hipError_t e = hipGraphInstantiate(&G.g[k], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      G.g[k] = nullptr;
+      return set_err(c, MBS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+  }
+  HIPCHK(c, hipGraphLaunch(G.g[k], s));
+  return MBS_OK;
+}
+
 int gmres(mbs_ctx* c, int prec, int64_t n, const double* R, const double* rhs, double* x,
           bool x_zero, double tol_abs, int max_iters, bool verify, double* resid, Counters& cnt,
           hipStream_t s, OutPass* out = nullptr) {
@@ -301,6 +374,7 @@ int gmres(mbs_ctx* c, int prec, int64_t n, const double* R, const double* rhs, d
   double* V = c->V.p;
   double* w = c->w.p;
   double* r = c->r.p;
+  StepGraphs* sg = step_graphs(c, prec, n, R, pc);
   // initial residual
   if (x_zero) {
     launch_copy(rhs, r, len, s);
@@ -319,21 +393,31 @@ int gmres(mbs_ctx* c, int prec, int64_t n, const double* R, const double* rhs, d
     double est = beta;
     bool breakdown = false;
     while (k < m && used < max_iters) {
-      double* vk = V + (int64_t)k * len;
-      if (pc) {
-        near_apply(c, n, R, vk, c->zt.p, s);
-        apply_op(c, prec, n, R, c->zt.p, w, s, cnt);
+      // Arnoldi step k: w = A (M^{-1}) v_k, classical Gram-Schmidt applied twice, Givens update
+      auto step = [&, k](hipStream_t q, bool timed, Counters& ct) {
+        double* vk = V + (int64_t)k * len;
+        if (pc) {
+          near_apply(c, n, R, vk, c->zt.p, q);
+          apply_op(c, prec, n, R, c->zt.p, w, q, ct, timed);
+        } else {
+          apply_op(c, prec, n, R, vk, w, q, ct, timed);
+        }
+        launch_dots(V, len, k + 1, w, len, c->dpart.p, sm.h1, q);
+        launch_axpy_multi(V, len, k + 1, sm.h1, -1.0, w, len, q);
+        launch_dots(V, len, k + 1, w, len, c->dpart.p, sm.h2, q);
+        launch_axpy_multi(V, len, k + 1, sm.h2, -1.0, w, len, q);
+        norm2(c, w, len, sm.nsq, q);
+        launch_givens(c->H.p, m, k, sm.h1, sm.h2, sm.nsq, sm.cs, sm.sn, sm.g, sm.status, q);
+        launch_scale_by(w, sm.status + 1, 1, V + (int64_t)(k + 1) * len, len, q);
+      };
+      if (sg) {
+        Counters scratch;  // the capture's own counts are not the replays'
+        CHK(launch_step_graph(c, *sg, k, [&](hipStream_t q) { step(q, false, scratch); }, s));
+        (prec == MBS_FP64 ? cnt.f64 : cnt.f32)++;
+        cnt.pairs += (double)n * (double)(n - 1);
       } else {
-        apply_op(c, prec, n, R, vk, w, s, cnt);
+        step(s, true, cnt);
       }
-      // classical Gram-Schmidt, applied twice
-      launch_dots(V, len, k + 1, w, len, c->dpart.p, sm.h1, s);
-      launch_axpy_multi(V, len, k + 1, sm.h1, -1.0, w, len, s);
-      launch_dots(V, len, k + 1, w, len, c->dpart.p, sm.h2, s);
-      launch_axpy_multi(V, len, k + 1, sm.h2, -1.0, w, len, s);
-      norm2(c, w, len, sm.nsq, s);
-      launch_givens(c->H.p, m, k, sm.h1, sm.h2, sm.nsq, sm.cs, sm.sn, sm.g, sm.status, s);
-      launch_scale_by(w, sm.status + 1, 1, V + (int64_t)(k + 1) * len, len, s);
       CHK(read_status(c, sm.status, 2, s));
       est = c->h_status[0];
       ++k;
@@ -788,6 +872,8 @@ void mbs_destroy(mbs_ctx* c) {
     if (b->p) (void)hipFree(b->p);
   for (auto& g : c->bgraph)
     if (g) (void)hipGraphExecDestroy(g);
+  for (auto& sg : c->sgraph) sg.reset();
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   if (c->bstream) (void)hipStreamDestroy(c->bstream);
   if (c->d_count) (void)hipFree(c->d_count);
   if (c->h_status) (void)hipHostFree(c->h_status);

@@ -261,6 +261,32 @@ def test_fused_final_pass_matches_separate_passes(ctx, precision, torque):
     assert abs(rel - st["rel_resid"]) <= 1e-3 * rel + 1e-15
 
 
+@pytest.mark.parametrize("precision", [mbstokes.MBS_FP64, mbstokes.MBS_MIXED])
+@pytest.mark.parametrize("near_cutoff", [0.0, 6.0])
+def test_solve_graph_replays_equal_eager_solves(ctx, precision, near_cutoff):
+    """Small systems replay captured Arnoldi steps from the second solve of one configuration on:
+    every replay (with other work and synchronisations in between) equals the eager solve bit for
+    bit."""
+    print(f"graph replays precision={precision} near_cutoff={near_cutoff}", flush=True)
+    w = _workload(700, seed=41)
+    d = mbstokes.to_device(w, DEV)
+    args = (d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
+    ctx.set_params(graph=0, precision=precision, near_cutoff=near_cutoff, tol=1e-12,
+                   guess=mbstokes.MBS_GUESS_DIAG, restart=6)
+    try:
+        V0, W0, S0, st0 = ctx.mbs_solve(*args)
+        ctx.set_params(graph=1)
+        for rep in range(4):   # new key (eager), then capture, then replays
+            V, W, S, st = ctx.mbs_solve(*args)
+            torch.cuda.synchronize()
+            _ = ctx.mbs_matvec(d["R"][:50].contiguous(), torch.ones((50, 5), dtype=torch.float64, device=DEV))
+            assert torch.equal(V, V0) and torch.equal(W, W0) and torch.equal(S, S0), rep
+            assert st["iters"] == st0["iters"] and st["rel_resid"] == st0["rel_resid"], rep
+    finally:
+        ctx.set_params(graph=1, precision=mbstokes.MBS_FP64, near_cutoff=0.0, tol=1e-10,
+                       guess=mbstokes.MBS_GUESS_ZERO, restart=30)
+
+
 def test_solve_user_guess_and_restarts(ctx):
     w = _workload(200, seed=12)
     ref = galerkin.solve(w)
