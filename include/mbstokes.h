@@ -90,8 +90,11 @@ typedef struct mbs_params {
   int32_t check_overlap; /* nonzero: mbs_solve fails with MBS_EOVERLAP if some |R_n - R_m| < 2a */
   int32_t tile;          /* pair-kernel launch shape: 0 = autotuned (or default), k > 0 = entry k-1
                             of the candidate table (see mbs_autotune) */
-  int32_t graph;         /* mbs_solve_batched: 1 = capture its phases in HIP graphs and replay them
-                            (default), 0 = launch the same kernels directly */
+  int32_t graph;         /* 1 (default): mbs_solve_batched captures its phases in HIP graphs and
+                            replays them; mbs_solve / mbs_step with n <= 32768 capture the GMRES
+                            Arnoldi steps from the second solve with the same sizes, positions
+                            pointer and workspace on (operator timings t_op*_ms then cover only the
+                            eagerly launched applications); 0 = launch the same kernels directly */
   int32_t batch_item;    /* mbs_solve_batched: receivers per work item (64, 128 or 256); 0 = the
                             context's choice (mbs_autotune_batched, else 64) */
   int32_t superposition; /* nonzero: mbs_solve and mbs_step use the superposition approximation of
