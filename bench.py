@@ -326,11 +326,13 @@ def bench_paper_trap(ctx, a):
         ctx.set_params(superposition=sup, precision=mbstokes.MBS_MIXED, guess=mbstokes.MBS_GUESS_USER,
                        tol=1e-10, near_cutoff=0.0, max_iter=60)
         snaps, done, secs, steps = [snapshot(R, p, 0.0)], 0, 0.0, 0
+        hist = torch.zeros(11 * w.n, dtype=torch.float64, device="cuda:0")  # integrator history
         for mult in horizon:
             todo = mult * per - done
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, md = ctx.mbs_step(R, p, k, coef, dt, todo, order=2, want_min_dist=True, allow_noconv=True)
+            _, md = ctx.mbs_step(R, p, k, coef, dt, todo, order=2, want_min_dist=True, allow_noconv=True,
+                                 hist=hist, hist_valid=done > 0)
             torch.cuda.synchronize()
             secs += time.perf_counter() - t0
             steps += todo

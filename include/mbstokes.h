@@ -197,10 +197,15 @@ int mbs_flow(mbs_ctx* ctx, int64_t m, const double* X, int64_t n, const double* 
    With params.guess = MBS_GUESS_USER every step after the first starts from the previous step's
    Sigma (the first from the one-body guess). A step whose solve stops short of params.tol still
    advances and the call returns MBS_ENOCONV at the end; a non-finite residual stops the run
-   (steps not taken keep zeroed per_step entries). */
+   (steps not taken keep zeroed per_step entries).
+   hist: DEVICE [11 n] or NULL, the integrator's history (previous step's V [n x 3], Omega x p
+   [n x 3], Sigma [n x 5], in that order). On return it holds the history after the last step.
+   With hist_valid nonzero the call continues a run instead of starting one: the first step is an
+   Adams-Bashforth step with that history and starts from that Sigma, so N steps in one call and
+   N1 + N2 steps in two calls (history passed on) give identical results. */
 int mbs_step(mbs_ctx* ctx, int64_t n, double* R, double* p, double k_trap, const double* slip_coef,
-             double dt, int32_t nsteps, int32_t order, mbs_stats* per_step, double* min_dist,
-             void* stream);
+             double dt, int32_t nsteps, int32_t order, double* hist, int32_t hist_valid,
+             mbs_stats* per_step, double* min_dist, void* stream);
 
 /* Many independent configurations in one call (binary64, zero initial guess, near-field
    preconditioner when params.near_cutoff > 0). Configuration b owns

@@ -58,7 +58,7 @@ struct mbs_ctx {
   Tile tile_pass = Tile{0, 256, 128, 4096};  // shape of the right-hand-side and output passes
   std::string err;
   // workspace
-  DevBuf V, w, r, b, xs, dlt, part, dpart, small, H, zeros, stepbuf, srcbuf, orig, near, zt;
+  DevBuf V, w, r, b, xs, dlt, part, dpart, small, H, zeros, stepbuf, srcbuf, orig, near, zt, stepstate;
   bool near_ready = false;  // neighbour lists of the current solve are built
   int* d_count = nullptr;
   double* h_status = nullptr;  // pinned host [4]
@@ -866,6 +866,7 @@ void mbs_destroy(mbs_ctx* c) {
   (void)hipSetDevice(c->device);
   DevBuf* bufs[] = {&c->V, &c->w, &c->r, &c->b, &c->xs, &c->dlt, &c->part, &c->dpart,
                     &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig, &c->near, &c->zt,
+                    &c->stepstate,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
                     &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->bat, &c->btune};
   for (DevBuf* b : bufs)
@@ -1003,8 +1004,8 @@ int mbs_flow(mbs_ctx* c, int64_t m, const double* X, int64_t n, const double* R,
 }
 
 int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const double* slip_coef,
-             double dt, int32_t nsteps, int32_t order, mbs_stats* per_step, double* min_dist,
-             void* stream) {
+             double dt, int32_t nsteps, int32_t order, double* hist, int32_t hist_valid,
+             mbs_stats* per_step, double* min_dist, void* stream) {
   CHK(begin_call(c));
   if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
   if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
@@ -1012,13 +1013,14 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
   if (nsteps < 0) return set_err(c, MBS_EINVAL, "nsteps must be >= 0");
   if (order != 1 && order != 2) return set_err(c, MBS_EINVAL, "order must be 1 or 2");
   if (!isfinite(dt) || !isfinite(k_trap)) return set_err(c, MBS_EINVAL, "dt and k must be finite");
+  if (hist_valid && !hist) return set_err(c, MBS_EINVAL, "hist_valid needs hist");
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
-  // state: Fe, v1s, v3t, V, W, Vprev, Pdprev [3n] each; v2s, Sigma, S [5n] each
-  DevBuf st;
+  // state: Fe, v1s, v3t, V, W, Vprev, Pdprev [3n] each; v2s, Sigma, S [5n] each. Vprev, Pdprev and
+  // Sigma are the history that hist carries in and out (in that order, 11n values).
   const size_t need = (size_t)(3 * 7 + 5 * 3) * n;
-  CHK(ensure(c, st, need));
-  double* Fe = st.p;
+  CHK(ensure(c, c->stepstate, need));
+  double* Fe = c->stepstate.p;
   double* v1s = Fe + 3 * n;
   double* v3t = v1s + 3 * n;
   double* V = v3t + 3 * n;
@@ -1033,6 +1035,11 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
   if (rc == MBS_OK && bad) rc = set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
   const int guess0 = c->prm.guess;
   bool noconv = false;
+  if (rc == MBS_OK && hist_valid) {  // resume: the previous step's V, Omega x p and Sigma
+    launch_copy(hist, Vp, 3 * n, s);
+    launch_copy(hist + 3 * n, Pp, 3 * n, s);
+    launch_copy(hist + 6 * n, Sg, 5 * n, s);
+  }
   for (int k = 0; k < nsteps && rc == MBS_OK; ++k) {
     launch_trap_modes(R, p, k_trap, slip_coef[0], slip_coef[1], slip_coef[2], Fe, v1s, v2s, v3t, n,
                       s);
@@ -1043,8 +1050,9 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
       min_dist[k] = md;
     }
     mbs_stats one{};
-    const bool warm = guess0 == MBS_GUESS_USER && k > 0;
-    if (guess0 == MBS_GUESS_USER && k == 0) c->prm.guess = MBS_GUESS_DIAG;
+    const bool first = k == 0 && !hist_valid;  // no history yet: one-body guess, Euler step
+    const bool warm = guess0 == MBS_GUESS_USER && !first;
+    if (guess0 == MBS_GUESS_USER && first) c->prm.guess = MBS_GUESS_DIAG;
     rc = solve_core(c, n, R, p, v1s, v2s, slip_coef[2] != 0.0 ? v3t : nullptr, Fe, nullptr,
                     warm ? Sg : nullptr, V, W, Sout, Sg, &one, s);
     c->prm.guess = guess0;
@@ -1053,7 +1061,7 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
     // a step whose solve stopped short of the tolerance still advances (it is reported through
     // per_step[k].rel_resid); a non-finite residual ends the run
     if (!isfinite(one.rel_resid)) break;
-    launch_ab_update(R, p, V, W, Vp, Pp, dt, k == 0, order, n, s);
+    launch_ab_update(R, p, V, W, Vp, Pp, dt, first, order, n, s);
     if (rc == MBS_ENOCONV) {
       noconv = true;
       rc = MBS_OK;
@@ -1063,8 +1071,12 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
     rc = MBS_ENOCONV;
     set_err(c, MBS_ENOCONV, "some steps stopped short of the tolerance (see per-step rel_resid)");
   }
+  if (hist && (rc == MBS_OK || rc == MBS_ENOCONV) && (nsteps > 0 || hist_valid)) {
+    launch_copy(Vp, hist, 3 * n, s);
+    launch_copy(Pp, hist + 3 * n, 3 * n, s);
+    launch_copy(Sg, hist + 6 * n, 5 * n, s);
+  }
   hipError_t e = hipStreamSynchronize(s);
-  if (st.p) (void)hipFree(st.p);
   if (e != hipSuccess && rc == MBS_OK) rc = set_err(c, MBS_EHIP, "%s", hipGetErrorString(e));
   return rc;
 }

@@ -90,7 +90,7 @@ def load(path: str = LIB_PATH):
     lib.mbs_outputs.restype = ctypes.c_int
     lib.mbs_flow.argtypes = [P, I64, P, I64, P, P, P, P, P, P, VP]
     lib.mbs_flow.restype = ctypes.c_int
-    lib.mbs_step.argtypes = [P, I64, P, P, D, ctypes.POINTER(ctypes.c_double), D, I32, I32,
+    lib.mbs_step.argtypes = [P, I64, P, P, D, ctypes.POINTER(ctypes.c_double), D, I32, I32, P, I32,
                              ctypes.POINTER(Stats), ctypes.POINTER(ctypes.c_double), VP]
     lib.mbs_step.restype = ctypes.c_int
     lib.mbs_solve_batched.argtypes = [P, I32, ctypes.POINTER(ctypes.c_int64)] + [P] * 10 + [
@@ -251,13 +251,15 @@ class Context:
         return U
 
     def mbs_step(self, R, p, k_trap, slip_coef, dt, nsteps, order=2, want_min_dist=False,
-                 allow_noconv=False):
+                 allow_noconv=False, hist=None, hist_valid=False):
+        """hist: float64 device tensor [11 n] (V, Omega x p, Sigma of the previous step) or None."""
         n = R.shape[0]
         coef = (ctypes.c_double * 3)(*slip_coef)
         stats = (Stats * max(nsteps, 1))()
         md = (ctypes.c_double * max(nsteps, 1))() if want_min_dist else None
         rc = self.lib.mbs_step(self.h, n, _ptr(R, n, 3, "R"), _ptr(p, n, 3, "p"), float(k_trap), coef,
-                               float(dt), int(nsteps), int(order), stats, md, _stream())
+                               float(dt), int(nsteps), int(order), _ptr(hist.reshape(11 * n, 1) if hist is not None else None, 11 * n, 1, "hist"),
+                               int(bool(hist_valid)), stats, md, _stream())
         self._check(rc, (MBS_ENOCONV,) if allow_noconv else ())
         return [stats[k].as_dict() for k in range(nsteps)], (list(md)[:nsteps] if md is not None else None)
 

@@ -67,3 +67,18 @@ def test_product_path_does_not_import_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", txt, flags=re.M), f
                 assert "oracle/" not in txt, f
+
+
+def test_trap_checkpoint_roundtrip(tmp_path):
+    """The checkpoint format: plain arrays in a .npz, read back without pickling."""
+    import numpy as np
+
+    from paper_1411_0278_amd import trap
+    rng = np.random.default_rng(0)
+    R, p, hist = rng.standard_normal((7, 3)), rng.standard_normal((7, 3)), rng.standard_normal(77)
+    path = str(tmp_path / "ck.npz")
+    trap.save_checkpoint(path, 12, R, p, hist, 0.5, (1.0, 0.5, 0.0), 0.01, 2)
+    ck = trap.load_checkpoint(path)
+    assert int(ck["step"]) == 12 and int(ck["order"]) == 2 and float(ck["dt"]) == 0.01
+    assert np.array_equal(ck["R"], R) and np.array_equal(ck["p"], p) and np.array_equal(ck["hist"], hist)
+    assert tuple(ck["slip_coef"]) == (1.0, 0.5, 0.0) and float(ck["k_trap"]) == 0.5

@@ -353,6 +353,27 @@ def test_stepper_matches_oracle(ctx):
     assert abs(md[0] - dmin) < 1e-12
 
 
+@pytest.mark.parametrize("guess", [mbstokes.MBS_GUESS_USER, mbstokes.MBS_GUESS_DIAG])
+def test_stepper_resume_from_checkpoint_is_bitwise(ctx, tmp_path, guess):
+    """10 steps in one run equal 4 steps + checkpoint file + resume for 6 steps, bit for bit (the
+    Adams-Bashforth history and the previous Sigma travel with the checkpoint)."""
+    from paper_1411_0278_amd import trap
+    w = _workload(200, seed=44)
+    ctx.set_params(guess=guess, tol=1e-12)
+    try:
+        R1, p1 = _t(w.R), _t(w.p)
+        trap.run(ctx, R1, p1, 0.5, (1.0, 1.0, 1.0), 0.01, 10)
+        R2, p2 = _t(w.R), _t(w.p)
+        path = str(tmp_path / "ck.npz")
+        trap.run(ctx, R2, p2, 0.5, (1.0, 1.0, 1.0), 0.01, 4, checkpoint_every=2, path=path)
+        R3, p3, _, _, step = trap.resume(ctx, path, 6)
+    finally:
+        ctx.set_params(guess=mbstokes.MBS_GUESS_ZERO, tol=1e-10)
+    assert step == 10
+    assert torch.equal(R1, R3) and torch.equal(p1, p3)
+    assert not torch.equal(R1, _t(w.R))
+
+
 @pytest.mark.parametrize("case", ["random", "dilute_lattice", "pair", "clustered"])
 def test_minimum_distance_monitor(ctx, case):
     """The per-step minimum centre distance: cell-grid search when some pair is closer than a cell
