@@ -247,10 +247,10 @@ __global__ void __launch_bounds__(kMaxBlock)
     Mom<T> m;
     const bool self = jt < b1 && jt + cnt > b0;  // uniform
     if (self) {
-#pragma unroll 2
+#pragma unroll 8
       for (int jj = 0; jj < cnt; ++jj) p2_pair<T, true>(tile[jj], xi, yi, zi, A24, A42, m);
     } else {
-#pragma unroll 2
+#pragma unroll 8
       for (int jj = 0; jj < cnt; ++jj) p2_pair<T, false>(tile[jj], xi, yi, zi, A24, A42, m);
     }
     tot.add(m);
