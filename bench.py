@@ -41,8 +41,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--headline", default="mixed_pc",
                     choices=["plain_fp64", "fp64_diag", "mixed_diag", "fp64_learned", "mixed_learned",
-                             "fp64_pc", "mixed_pc", "mixed_learned_pc"])
-    ap.add_argument("--near-cutoff", type=float, default=6.0,
+                             "fp64_pc", "mixed_pc", "mixed_diag_pc", "mixed_learned_pc"])
+    ap.add_argument("--near-cutoff", type=float, default=8.0,
                     help="near-field preconditioner cutoff (centre distance) of the *_pc variants")
     ap.add_argument("--skip-warmstart", action="store_true", help="no learned warm start (no training)")
     ap.add_argument("--warmstart-configs", type=int, default=200)
@@ -397,8 +397,9 @@ def main():
             ("fp64_diag", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_DIAG, 0.0),
             ("mixed_zero", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_ZERO, 0.0),
             ("mixed_diag", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG, 0.0),
-            ("fp64_pc", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_DIAG, rc),
-            ("mixed_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG, rc)]
+            ("fp64_pc", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_ZERO, rc),
+            ("mixed_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_ZERO, rc),
+            ("mixed_diag_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG, rc)]
     if not a.skip_warmstart:
         from paper_1411_0278_amd import warmstart
         print("bench: training the warm-start network", file=sys.stderr, flush=True)

@@ -76,8 +76,9 @@ typedef struct mbs_params {
                             1.4 reproduces the paper's one-body stresslet table */
   double  inner_tol;     /* MBS_MIXED: relative tolerance of each inner binary32 GMRES solve (an
                             inner solve also stops once its residual is below 0.3 tol |b|) */
-  double  near_cutoff;   /* > 0: right-precondition GMRES with M^{-1} = gamma (I + gamma K_near), K_near
-                            the operator's blocks of pairs closer than near_cutoff (centre distance;
+  double  near_cutoff;   /* > 0: right-precondition GMRES with M^{-1} = gamma (I + X + X^2), X =
+                            gamma K_near (second-order Neumann series of (I/gamma - K_near)^{-1}),
+                            K_near the operator's blocks of pairs closer than near_cutoff (centre distance;
                             at most 32 neighbours per sphere, the smallest indices; pairs closer
                             than 2a are left out); 0 = no preconditioner (default). The solution
                             is unchanged. Applies to mbs_solve, mbs_step and mbs_solve_batched
@@ -160,8 +161,8 @@ int mbs_solve(mbs_ctx* ctx, int64_t n, const double* R, const double* p, const d
 int mbs_matvec(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y,
                int precision, void* stream);
 
-/* The near-field preconditioner on its own: y = gamma x + gamma^2 K_near x (x, y [n x 5] binary64
-   DEVICE, params.near_cutoff > 0). */
+/* The near-field preconditioner on its own: y = gamma x + gamma^2 K_near x + gamma^3 K_near^2 x
+   (x, y [n x 5] binary64 DEVICE, params.near_cutoff > 0). */
 int mbs_precond_apply(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y, void* stream);
 
 /* Right-hand side of the stresslet rows: b_n = sum_{m != n} E[F_m, T_m, d_m] - c s_n, b [n x 5]. */

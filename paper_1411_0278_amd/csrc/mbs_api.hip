@@ -58,7 +58,7 @@ struct mbs_ctx {
   Tile tile_pass = Tile{0, 256, 128, 4096};  // shape of the right-hand-side and output passes
   std::string err;
   // workspace
-  DevBuf V, w, r, b, xs, dlt, part, dpart, small, H, zeros, stepbuf, srcbuf, orig, near, zt, stepstate;
+  DevBuf V, w, r, b, xs, dlt, part, dpart, small, H, zeros, stepbuf, srcbuf, orig, near, zt, nt, stepstate;
   bool near_ready = false;  // neighbour lists of the current solve are built
   int* d_count = nullptr;
   double* h_status = nullptr;  // pinned host [4]
@@ -181,7 +181,10 @@ int ensure_ws(mbs_ctx* c, int64_t n) {
   CHK(ensure(c, c->srcbuf, (size_t)8 * n));
   CHK(ensure(c, c->orig, 4));
   CHK(ensure(c, c->zt, len));
-  if (c->prm.near_cutoff > 0.0) CHK(ensure(c, c->near, (size_t)(kNearCap + 1) * n / 2 + 64));
+  if (c->prm.near_cutoff > 0.0) {
+    CHK(ensure(c, c->near, (size_t)(kNearCap + 1) * n / 2 + 64));
+    CHK(ensure(c, c->nt, len));
+  }
   CHK(ensure(c, c->dpart, (size_t)std::max<int64_t>((int64_t)(m + 2) * 256, 1024 + (n + 255) / 256) + 64));
   CHK(ensure(c, c->small, (size_t)8 * (m + 2) + 64));
   CHK(ensure(c, c->H, (size_t)(m + 1) * (m + 1)));
@@ -308,7 +311,7 @@ int near_prepare(mbs_ctx* c, int64_t n, const double* R, hipStream_t s) {
 }
 void near_apply(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, hipStream_t s) {
   const int* cntp = (const int*)c->near.p;
-  launch_near_apply(R, x, cntp, cntp + n, n, c->ph, y, s);
+  launch_near_apply(R, x, cntp, cntp + n, n, c->ph, y, s, nullptr, 0, c->nt.p);
 }
 
 // Small systems are bound by launch and synchronisation latency, so their Arnoldi steps are
@@ -329,7 +332,7 @@ StepGraphs* step_graphs(mbs_ctx* c, int prec, int64_t n, const double* R, bool p
   const Tile t = prec == MBS_FP64 ? c->tile64 : c->tile32;
   const std::vector<uintptr_t> key = {
       (uintptr_t)n, (uintptr_t)R, (uintptr_t)pc, (uintptr_t)t.variant, (uintptr_t)t.block, (uintptr_t)t.tj,
-      (uintptr_t)t.wgs, (uintptr_t)c->prm.restart, (uintptr_t)c->V.p, (uintptr_t)c->w.p, (uintptr_t)c->zt.p,
+      (uintptr_t)t.wgs, (uintptr_t)c->prm.restart, (uintptr_t)c->V.p, (uintptr_t)c->w.p, (uintptr_t)c->zt.p, (uintptr_t)c->nt.p,
       (uintptr_t)c->H.p, (uintptr_t)c->small.p, (uintptr_t)c->dpart.p, (uintptr_t)c->part.p,
       (uintptr_t)c->srcbuf.p, (uintptr_t)c->orig.p, (uintptr_t)c->near.p, dbits(c->ph.P), dbits(c->ph.a2),
       dbits(c->ph.gamma), dbits(c->ph.inv_gamma)};
@@ -866,7 +869,7 @@ void mbs_destroy(mbs_ctx* c) {
   (void)hipSetDevice(c->device);
   DevBuf* bufs[] = {&c->V, &c->w, &c->r, &c->b, &c->xs, &c->dlt, &c->part, &c->dpart,
                     &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig, &c->near, &c->zt,
-                    &c->stepstate,
+                    &c->nt, &c->stepstate,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
                     &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->bat, &c->btune};
   for (DevBuf* b : bufs)
@@ -1149,10 +1152,11 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
                oit = reserve(nconf * 4), ot0 = reserve(nconf * 8), ot1 = reserve(nconf * 8),
                okd = reserve(16), ocnt = reserve(16), ooff = reserve((nconf + 1) * 4),
                oitems = reserve((size_t)nitems * 8), ocid = reserve((size_t)ntot * 4);
-  // near-field preconditioner: lists (counts, then kNearCap entries per sphere) and two vectors
+  // near-field preconditioner: lists (counts, then kNearCap entries per sphere) and three vectors
   const bool pc = c->prm.near_cutoff > 0.0;
   const size_t onear = pc ? reserve((size_t)ntot * (kNearCap + 1) * 4) : 0,
-               ozt = pc ? reserve(len * 8) : 0, out_ = pc ? reserve(len * 8) : 0;
+               ozt = pc ? reserve(len * 8) : 0, out_ = pc ? reserve(len * 8) : 0,
+               ont = pc ? reserve(len * 8) : 0;
   CHK(ensure(c, c->bat, bytes / 8 + 64));
   char* base = (char*)c->bat.p;
   double* Vb = (double*)(base + oV);
@@ -1184,6 +1188,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   int* ncnt = pc ? (int*)(base + onear) : nullptr;
   int* nlist = pc ? ncnt + ntot : nullptr;
   double* zt = pc ? (double*)(base + ozt) : nullptr;
+  double* nt = pc ? (double*)(base + ont) : nullptr;
   double* ut = pc ? (double*)(base + out_) : nullptr;
   const double near_rc = c->prm.near_cutoff, near_rmin = 2.0 * c->prm.a;
   HIPCHK(c, hipMemcpyAsync(doff, off.data(), (nconf + 1) * sizeof(int), hipMemcpyHostToDevice, s));
@@ -1214,7 +1219,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   auto phase_iter = [&](hipStream_t q) {
     for (int it = 0; it < C; ++it) {
       if (pc) {  // right preconditioning: w = A M^{-1} v_k
-        launch_near_apply(R, Vb, ncnt, nlist, ntot, ph, zt, q, kdev, len);
+        launch_near_apply(R, Vb, ncnt, nlist, ntot, ph, zt, q, kdev, len, nt);
         batched_pack_s(R, zt, nullptr, 0, 0, (Src8<double>*)rec, ntot, q);
         batched_p2(ditems, nitems, item, doff, st.status, kActive, (const Src8<double>*)rec, zt, nullptr, 0, ph, wv,
                    q);
@@ -1239,7 +1244,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
     if (pc) {  // x += M^{-1} (V y) for the configurations that ended a cycle (zero elsewhere)
       batched_fill(ut, 0.0, len, q);
       batched_axpy(Vb, len, nullptr, st.kend, 0, st.y, hs, 1.0, dcid, st.status, kCycleDone, ut, len, q);
-      launch_near_apply(R, ut, ncnt, nlist, ntot, ph, zt, q);
+      launch_near_apply(R, ut, ncnt, nlist, ntot, ph, zt, q, nullptr, 0, nt);
       launch_axpby(1.0, zt, 1.0, xv, len, q);
     } else {
       batched_axpy(Vb, len, nullptr, st.kend, 0, st.y, hs, 1.0, dcid, st.status, kCycleDone, xv, len, q);

@@ -73,7 +73,8 @@ void launch_near_build(const GridView& g, const double* R, double rmin, double r
                        hipStream_t s);
 // (x = x + kdev[0] * ld when kdev is given)
 void launch_near_apply(const double* R, const double* x, const int* cnt, const int* list, int64_t n,
-                       const Phys& ph, double* y, hipStream_t s, const int* kdev = nullptr, int64_t ld = 0);
+                       const Phys& ph, double* y, hipStream_t s, const int* kdev = nullptr, int64_t ld = 0,
+                       double* tmp = nullptr);
 
 int tile_block(Tile t);                      // receivers per workgroup actually used
 int split_for(int64_t n, Tile t, int tj);    // number of source chunks actually used

@@ -3,9 +3,12 @@
 // The system matrix is A = I/gamma - K with K the all-pairs strain-from-stresslet operator. Its
 // spread around 1/gamma comes mostly from close pairs, so M = I/gamma - K_near, K_near restricted to
 // pairs closer than a cutoff r_c, captures the stiff part. GMRES runs on A M^{-1} with the
-// first-order Neumann approximation M^{-1} v = gamma v + gamma^2 K_near v, which is symmetric and
-// costs one sparse pass over a few neighbours per sphere. The solution x = M^{-1} u is unchanged;
-// only the iteration count drops.
+// second-order Neumann approximation M^{-1} v = gamma (v + X v + X^2 v), X = gamma K_near, formed as
+// t = gamma v + gamma^2 K_near v, then M^{-1} v = gamma v + gamma K_near t: two sparse passes over a
+// few neighbours per sphere. It is symmetric and, unlike the first-order truncation, positive
+// definite for any X (1 + x + x^2 >= 3/4 on every eigenvalue x of the symmetric X); on dilute
+// suspensions it reaches the iteration count of the exact near-field inverse. The solution
+// x = M^{-1} u is unchanged; only the iteration count drops.
 //
 // Neighbour lists: a search of the cell grid keeps, for each sphere, the kNearCap other spheres of
 // smallest index with 2a <= r < r_c, in index order (deterministic); beyond that capacity the
@@ -109,15 +112,16 @@ __global__ void __launch_bounds__(256)
   cnt[i] = c;
 }
 
-// y = gamma x + gamma^2 K_near x; x = X + kdev[0] * ld when kdev is given (a Krylov vector whose
-// index lives on the device)
+// y = alpha x + beta K_near z, z = Z or (Z == NULL) x; x = X + kdev[0] * ld when kdev is given (a
+// Krylov vector whose index lives on the device)
 __global__ void k_near_apply(const double* __restrict__ R, const double* __restrict__ X0,
-                             const int* __restrict__ kdev, int64_t ld, const int* __restrict__ cnt,
-                             const int* __restrict__ list, int n, double P, double a2, double gamma,
-                             double* __restrict__ Y) {
+                             const int* __restrict__ kdev, int64_t ld, const double* __restrict__ Z0,
+                             const int* __restrict__ cnt, const int* __restrict__ list, int n, double P,
+                             double a2, double alpha, double beta, double* __restrict__ Y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double* __restrict__ X = X0 + (kdev ? (int64_t)kdev[0] * ld : 0);
+  const double* __restrict__ Z = Z0 ? Z0 : X;
   const double xi = R[3 * (int64_t)i], yi = R[3 * (int64_t)i + 1], zi = R[3 * (int64_t)i + 2];
   const double A24 = 24.0 * a2, A42 = 42.0 * a2;
   Mom<double> m;
@@ -128,14 +132,13 @@ __global__ void k_near_apply(const double* __restrict__ R, const double* __restr
     s.x = R[3 * (int64_t)j];
     s.y = R[3 * (int64_t)j + 1];
     s.z = R[3 * (int64_t)j + 2];
-    basis_to_cart(X + 5 * (int64_t)j, s.sxx, s.syy, s.sxy, s.sxz, s.syz);
+    basis_to_cart(Z + 5 * (int64_t)j, s.sxx, s.syy, s.sxy, s.sxz, s.syz);
     p2_pair<double, false>(s, xi, yi, zi, A24, A42, m);
   }
   double e[5];
   p2_strain(&m.pxx, P, a2, e);
-  const double g2 = gamma * gamma;
 #pragma unroll
-  for (int q = 0; q < 5; ++q) Y[5 * (int64_t)i + q] = gamma * X[5 * (int64_t)i + q] + g2 * e[q];
+  for (int q = 0; q < 5; ++q) Y[5 * (int64_t)i + q] = alpha * X[5 * (int64_t)i + q] + beta * e[q];
 }
 
 inline unsigned nblk(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
@@ -150,9 +153,17 @@ void launch_near_build(const GridView& g, const double* R, double rmin, double r
 }
 
 void launch_near_apply(const double* R, const double* x, const int* cnt, const int* list, int64_t n,
-                       const Phys& ph, double* y, hipStream_t s, const int* kdev, int64_t ld) {
-  hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, kdev, ld, cnt, list, (int)n,
-                     ph.P, ph.a2, ph.gamma, y);
+                       const Phys& ph, double* y, hipStream_t s, const int* kdev, int64_t ld, double* tmp) {
+  const double g = ph.gamma;
+  if (tmp) {  // second order: t = gamma x + gamma^2 K x, then y = gamma x + gamma K t
+    hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, kdev, ld, nullptr, cnt, list,
+                       (int)n, ph.P, ph.a2, g, g * g, tmp);
+    hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, kdev, ld, tmp, cnt, list,
+                       (int)n, ph.P, ph.a2, g, g, y);
+  } else {
+    hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, kdev, ld, nullptr, cnt, list,
+                       (int)n, ph.P, ph.a2, g, g * g, y);
+  }
 }
 
 }  // namespace mbs

@@ -569,7 +569,8 @@ def test_precond_apply_matches_oracle(ctx):
     assert near.sum(1).max() <= 32
     Kn = K * np.kron(near, np.ones((5, 5)))
     g = galerkin.constants(prm)["gamma"]
-    want = (g * x.ravel() + g * g * (Kn @ x.ravel())).reshape(-1, 5)
+    kx = Kn @ x.ravel()
+    want = (g * x.ravel() + g * g * kx + g ** 3 * (Kn @ kx)).reshape(-1, 5)
     ctx.set_params(near_cutoff=rc)
     got = ctx.mbs_precond_apply(_t(w.R), _t(x))
     ctx.set_params(near_cutoff=0.0)
@@ -577,20 +578,27 @@ def test_precond_apply_matches_oracle(ctx):
 
 
 def _near_reference(R, x, rc, a, prm, cap=32):
-    """gamma x + gamma^2 K_near x with K_near over the pairs 2a <= r < rc, each sphere keeping the
-    cap partners of smallest index; blocks from the oracle's pair block for exactly those pairs."""
+    """gamma x + gamma^2 K_near x + gamma^3 K_near^2 x with K_near over the pairs 2a <= r < rc, each
+    sphere keeping the cap partners of smallest index; blocks from the oracle's pair block for
+    exactly those pairs."""
     from oracle import greens
     g = galerkin.constants(prm)["gamma"]
-    out = g * x.copy()
-    counts = []
+    nbrs, blocks = [], []
     for i in range(len(R)):
         D = np.linalg.norm(R[i] - R, axis=1)
         js = [j for j in np.nonzero((D >= 2 * a) & (D < rc))[0] if j != i][:cap]
-        counts.append(len(js))
-        if js:
-            blk = greens.block("E", "S", R[i] - R[js], prm.a, prm.eta)
-            out[i] += g * g * np.einsum("kab,kb->a", blk, x[js])
-    return out, np.array(counts)
+        nbrs.append(js)
+        blocks.append(greens.block("E", "S", R[i] - R[js], prm.a, prm.eta) if js else None)
+
+    def kn(v):
+        out = np.zeros_like(v)
+        for i, js in enumerate(nbrs):
+            if js:
+                out[i] = np.einsum("kab,kb->a", blocks[i], v[js])
+        return out
+
+    kx = kn(x)
+    return g * x + g * g * kx + g ** 3 * kn(kx), np.array([len(js) for js in nbrs])
 
 
 @pytest.mark.parametrize("case", ["lattice_rc_on_shell", "lattice_over_capacity", "overlapping_pair", "lone",
