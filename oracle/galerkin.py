@@ -85,23 +85,34 @@ def system_matrix(R, prm: Params):
     return np.eye(5 * n) / g - pair_matrix(R, "E", "S", prm)
 
 
-def rhs(R, v2s, v3t, Fe, Te, prm: Params, rows=None):
-    """b = sum_{m != n} E[F, T, d] - c s, flattened [5N] (or the given rows)."""
+def _modes(modes):
+    """Optional fixed sources of the minimal truncation: {"SEPT": gamma [N, 10], "VORT": psi [N, 5],
+    "SPIN": lambda [N, 10]} (absent or None entries are zero)."""
+    return {k: v for k, v in (modes or {}).items() if v is not None}
+
+
+def rhs(R, v2s, v3t, Fe, Te, prm: Params, rows=None, modes=None):
+    """b = sum_{m != n} E[F, T, d (, gamma, psi, lambda)] - c s, flattened [5N] (or the given rows)."""
     R = np.asarray(R, dtype=np.float64)
     rows = np.arange(len(R)) if rows is None else np.asarray(rows)
     b = pair_matrix(R, "E", "F", prm, rows) @ np.ravel(Fe)
     b = b + pair_matrix(R, "E", "T", prm, rows) @ np.ravel(Te)
     b = b + pair_matrix(R, "E", "D", prm, rows) @ np.ravel(v3t)
+    for kind, vals in _modes(modes).items():
+        b = b + pair_matrix(R, "E", kind, prm, rows) @ np.ravel(vals)
     b = b - prm.self_slip_c * np.ravel(np.asarray(v2s)[rows])
     return b
 
 
-def outputs(R, v1s, v2s, v3t, Fe, Te, Sigma, prm: Params, rows=None):
-    """Rigid-body motion and traction stresslet from a given flow stresslet Sigma [N, 5]."""
+def outputs(R, v1s, v2s, v3t, Fe, Te, Sigma, prm: Params, rows=None, modes=None):
+    """Rigid-body motion and traction stresslet from a given flow stresslet Sigma [N, 5]. The
+    septlet, vortlet and spinlet slip modes (``modes``) move no lone sphere (their mean and their
+    mean n x slip vanish); they act on the others through their flows."""
     R = np.asarray(R, dtype=np.float64)
     rows = np.arange(len(R)) if rows is None else np.asarray(rows)
     k = constants(prm)
     src = {"F": np.ravel(Fe), "T": np.ravel(Te), "S": np.ravel(Sigma), "D": np.ravel(v3t)}
+    src.update({kind: np.ravel(vals) for kind, vals in _modes(modes).items()})
     V = -np.asarray(v1s)[rows] + np.asarray(Fe)[rows] / k["drag_t"]
     W = np.asarray(Te)[rows] / k["drag_r"]
     for X, vec in src.items():
@@ -111,14 +122,19 @@ def outputs(R, v1s, v2s, v3t, Fe, Te, Sigma, prm: Params, rows=None):
     return V, W, S
 
 
-def solve(w, prm: Params | None = None, method="lu"):
-    """Full solve for a workload-like object (fields R, v1s, v2s, v3t, Fe, Te).
+def workload_modes(w):
+    """The septlet, vortlet and spinlet slip modes a workload carries (fields gam, psi, lam)."""
+    return {"SEPT": getattr(w, "gam", None), "VORT": getattr(w, "psi", None), "SPIN": getattr(w, "lam", None)}
 
-    Returns a dict with V, W (= Omega), S, Sigma [N, 5], b [5N] and A.
+
+def solve(w, prm: Params | None = None, method="lu"):
+    """Full solve for a workload-like object (fields R, v1s, v2s, v3t, Fe, Te; optionally gam,
+    psi, lam). Returns a dict with V, W (= Omega), S, Sigma [N, 5], b [5N] and A.
     """
     prm = prm or Params(eta=getattr(w, "eta", 1.0 / (6 * np.pi)), a=getattr(w, "a", 1.0))
+    modes = workload_modes(w)
     A = system_matrix(w.R, prm)
-    b = rhs(w.R, w.v2s, w.v3t, w.Fe, w.Te, prm)
+    b = rhs(w.R, w.v2s, w.v3t, w.Fe, w.Te, prm, modes=modes)
     if method == "lu":
         sig = np.linalg.solve(A, b)
     elif method == "cholesky":
@@ -127,7 +143,7 @@ def solve(w, prm: Params | None = None, method="lu"):
     else:
         raise ValueError(method)
     Sigma = sig.reshape(-1, 5)
-    V, W, S = outputs(w.R, w.v1s, w.v2s, w.v3t, w.Fe, w.Te, Sigma, prm)
+    V, W, S = outputs(w.R, w.v1s, w.v2s, w.v3t, w.Fe, w.Te, Sigma, prm, modes=modes)
     return dict(V=V, W=W, S=S, Sigma=Sigma, b=b, A=A)
 
 
@@ -140,18 +156,20 @@ def superposition(w, prm: Params | None = None):
     prm = prm or Params(eta=w.eta, a=w.a)
     g = constants(prm)["gamma"]
     Sigma = -prm.self_slip_c * g * np.asarray(w.v2s)
-    V, W, S = outputs(w.R, w.v1s, w.v2s, w.v3t, w.Fe, w.Te, Sigma, prm)
+    V, W, S = outputs(w.R, w.v1s, w.v2s, w.v3t, w.Fe, w.Te, Sigma, prm, modes=workload_modes(w))
     return dict(V=V, W=W, S=S, Sigma=Sigma)
 
 
-def flow_field(X, R, Fe, Te, Sigma, v3t, prm: Params):
+def flow_field(X, R, Fe, Te, Sigma, v3t, prm: Params, modes=None):
     """Exterior flow at field points X [M, 3] (section III): the sum over spheres m of the source
-    flows of its force, torque, flow stresslet and rank-3 trace mode at X - R_m, each carrying its
-    own finite-size operator and none at the field point. None stands for an absent source."""
+    flows of its force, torque, flow stresslet and rank-3 trace mode (and of the septlet, vortlet
+    and spinlet slip modes in ``modes``) at X - R_m, each carrying its own finite-size operator and
+    none at the field point. None stands for an absent source."""
     X = np.asarray(X, dtype=np.float64).reshape(-1, 3)
     R = np.asarray(R, dtype=np.float64).reshape(-1, 3)
     u = np.zeros_like(X)
     sources = {"F": Fe, "T": Te, "S": Sigma, "D": v3t}
+    sources.update(_modes(modes))
     for m in range(R.shape[0]):
         dx = X - R[m]
         for kind, vals in sources.items():

@@ -24,6 +24,28 @@ component; P = 1/(8 pi eta)):
   surface value is the slip mode itself (a fixed source: its traction is the
   one-body one).
 
+The other irreducible slip modes of the minimal truncation (section IV: the
+quadratic coefficient V^(3) = a^2 [gamma - (2/3) Delta.(eps.psi) + (3/5) Delta.delta d]
+and the rank-3 part lambda of the cubic one, V^(4) contains -(3/4) a^3 Delta.(eps.lambda)),
+contracted with the surface harmonics Y^(2) = 3nn - I and Y^(3) = 15nnn - 3(n delta)_sym
+and the weights 1/6 and 1/90 of the surface expansion, give the slip fields on r = a
+
+  septlet mode gamma (symmetric traceless rank 3):  v = (a^2/2) gamma : n n
+  vortlet mode psi   (symmetric traceless rank 2):  v = -(a^2/3) n x (psi . n)
+  spinlet mode lambda (symmetric traceless rank 3): v = -(a^3/8) n x (lambda : n n)
+
+Each is a fixed source (its traction is the one-body one, as for d). The flows
+below are the decaying Stokes flows that take these values on the sphere:
+
+* ``SEPT``: u_i = (7 a^5/48) F^2 [d_j d_k G_il] gamma_ljk, F^2 = 1 + a^2/14 nabla^2
+  (the sigma = 0, l = 2 row of the irreducible-flow table with its finite-size
+  operator; the amplitude makes the surface value equal the slip);
+* ``VORT``: u = -(a^5/3) x x (psi . x) / r^5 (a degree-2 rotational flow);
+* ``SPIN``: u = -(a^7/8) x x (lambda : x x) / r^7 (a degree-3 rotational flow).
+
+Rank-3 coefficients enter through 10 symmetric components (order of
+``basis.SYM3``), projected on their traceless part; psi uses the 5-basis.
+
 Target projections at the centre of the receiving sphere (the Galerkin
 coefficients of an incident flow, section III; Faxen form):
 
@@ -46,7 +68,7 @@ from . import basis
 x_, y_, z_, r_, a_, P_ = sp.symbols("x y z r a P", positive=True)
 _X = (x_, y_, z_)
 
-SOURCE_DIM = {"F": 3, "T": 3, "S": 5, "D": 3}
+SOURCE_DIM = {"F": 3, "T": 3, "S": 5, "D": 3, "SEPT": 10, "VORT": 5, "SPIN": 10}
 TARGET_DIM = {"U": 3, "W": 3, "E": 5}
 
 
@@ -75,6 +97,24 @@ def faxen(f, l):
 def curl(u):
     return [_canon(d(u[2], 1) - d(u[1], 2)), _canon(d(u[0], 2) - d(u[2], 0)),
             _canon(d(u[1], 0) - d(u[0], 1))]
+
+
+_IDX3 = [(i, j, k) for i in range(3) for j in range(3) for k in range(3)]
+
+
+def _cross(p, q):
+    return [p[1] * q[2] - p[2] * q[1], p[2] * q[0] - p[0] * q[2], p[0] * q[1] - p[1] * q[0]]
+
+
+def _stf3_unit(q):
+    """Symmetric traceless part of the unit symmetric rank-3 tensor of component q (exact)."""
+    T = [[[sp.Integer(0)] * 3 for _ in range(3)] for _ in range(3)]
+    for i, j, k in _IDX3:
+        if tuple(sorted((i, j, k))) == basis.SYM3[q]:
+            T[i][j][k] = sp.Integer(1)
+    t = [sum(T[i][i][k] for i in range(3)) for k in range(3)]
+    return [[[T[i][j][k] - sp.Rational(1, 5) * (int(i == j) * t[k] + int(i == k) * t[j] + int(j == k) * t[i])
+              for k in range(3)] for j in range(3)] for i in range(3)]
 
 
 @functools.lru_cache(maxsize=None)
@@ -110,6 +150,27 @@ def source_flow(kind):
     elif kind == "D":
         for j in range(3):
             cols.append([-a_ ** 5 / 20 * lap(G[i][j]) for i in range(3)])
+    elif kind == "SEPT":
+        for q in range(10):
+            T = _stf3_unit(q)
+            u = []
+            for i in range(3):
+                acc = 0
+                for l, j, k in _IDX3:
+                    if T[l][j][k] != 0:
+                        acc += T[l][j][k] * d(d(G[i][l], j), k)
+                u.append(sp.Rational(7, 48) * a_ ** 5 * faxen(acc, 2))
+            cols.append(u)
+    elif kind == "VORT":
+        for c in range(5):
+            B = [[sp.nsimplify(basis.BASIS[c][i, j], [sp.sqrt(2), sp.sqrt(6)]) for j in range(3)] for i in range(3)]
+            w = [sum(B[i][j] * _X[j] for j in range(3)) for i in range(3)]
+            cols.append([-a_ ** 5 / 3 * e / r_ ** 5 for e in _cross(_X, w)])
+    elif kind == "SPIN":
+        for q in range(10):
+            T = _stf3_unit(q)
+            v = [sum(T[i][j][k] * _X[j] * _X[k] for j in range(3) for k in range(3)) for i in range(3)]
+            cols.append([-a_ ** 7 / 8 * e / r_ ** 7 for e in _cross(_X, v)])
     else:
         raise ValueError(kind)
     return tuple(tuple(_canon(e) for e in col) for col in cols)

@@ -117,6 +117,11 @@ class Workload:
     eta: float = ETA
     a: float = RADIUS
     name: str = ""
+    # optional slip modes of the minimal truncation (None = absent): septlet gamma [n, 10] and
+    # spinlet lambda [n, 10] as symmetric rank-3 components (order SYM3), vortlet psi [n, 5]
+    gam: np.ndarray | None = None
+    psi: np.ndarray | None = None
+    lam: np.ndarray | None = None
 
     @property
     def n(self) -> int:
@@ -124,9 +129,11 @@ class Workload:
 
     def subset(self, idx) -> "Workload":
         idx = np.asarray(idx)
+        cut = lambda v: None if v is None else v[idx].copy()
         return Workload(self.R[idx].copy(), self.p[idx].copy(), self.v1s[idx].copy(),
                         self.v2s[idx].copy(), self.v3t[idx].copy(), self.Fe[idx].copy(),
-                        self.Te[idx].copy(), self.eta, self.a, self.name + "[subset]")
+                        self.Te[idx].copy(), self.eta, self.a, self.name + "[subset]",
+                        cut(self.gam), cut(self.psi), cut(self.lam))
 
 
 def slip_modes(p: np.ndarray, c1: float = 1.0, c2: float = 1.0, c3: float = 0.0):
@@ -135,6 +142,31 @@ def slip_modes(p: np.ndarray, c1: float = 1.0, c2: float = 1.0, c3: float = 0.0)
     pp = p[:, :, None] * p[:, None, :]
     m = 3.0 * (pp - np.eye(3)[None] / 3.0)
     return c1 * p, c2 * sym_to_basis5(m), c3 * p
+
+
+# Rank-3 symmetric tensors as 10 components, in this order of index triples.
+SYM3 = [(0, 0, 0), (0, 0, 1), (0, 0, 2), (0, 1, 1), (0, 1, 2), (0, 2, 2), (1, 1, 1), (1, 1, 2), (1, 2, 2),
+        (2, 2, 2)]
+
+
+def uniaxial_rank3(p: np.ndarray) -> np.ndarray:
+    """[n, 3] unit vectors -> [n, 10]: the symmetric traceless part of p p p,
+    p_i p_j p_k - (delta_ij p_k + delta_ik p_j + delta_jk p_i) / 5, in the SYM3 order."""
+    p = np.asarray(p, dtype=np.float64)
+    out = np.empty((p.shape[0], 10))
+    for q, (i, j, k) in enumerate(SYM3):
+        out[:, q] = (p[:, i] * p[:, j] * p[:, k]
+                     - ((i == j) * p[:, k] + (i == k) * p[:, j] + (j == k) * p[:, i]) / 5.0)
+    return out
+
+
+def higher_slip_modes(p: np.ndarray, c_gam: float = 1.0, c_psi: float = 1.0, c_lam: float = 1.0):
+    """Uniaxial septlet, vortlet and spinlet slip modes along p: gamma = c_gam STF(ppp),
+    psi = c_psi (pp - I/3) (5-basis), lambda = c_lam STF(ppp)."""
+    p = np.asarray(p, dtype=np.float64)
+    pp = p[:, :, None] * p[:, None, :]
+    u3 = uniaxial_rank3(p)
+    return c_gam * u3, c_psi * sym_to_basis5(pp - np.eye(3)[None] / 3.0), c_lam * u3
 
 
 def trap_workload(n: int, side: float, seed: int, k: float = TRAP_K, v3t: float = 0.0,

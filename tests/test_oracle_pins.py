@@ -68,7 +68,52 @@ def test_trace_mode_flow_matches_its_slip_on_surface():
         assert np.abs(u[:, :, j] - want).max() < 1e-14
 
 
-@pytest.mark.parametrize("src", ["F", "T", "S", "D"])
+def _unit_stf3(q):
+    """Symmetric traceless part of the unit symmetric rank-3 tensor of component q (10-component
+    order xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz), built here from its definition."""
+    import itertools
+    idx = [(0, 0, 0), (0, 0, 1), (0, 0, 2), (0, 1, 1), (0, 1, 2), (0, 2, 2), (1, 1, 1), (1, 1, 2), (1, 2, 2),
+           (2, 2, 2)][q]
+    T = np.zeros((3, 3, 3))
+    for perm in itertools.permutations(idx):
+        T[perm] = 1.0
+    t = np.einsum("iik->k", T)
+    for i, j, k in itertools.product(range(3), repeat=3):
+        T[i, j, k] -= ((i == j) * t[k] + (i == k) * t[j] + (j == k) * t[i]) / 5.0
+    assert np.abs(np.einsum("iik->k", T)).max() < 1e-15
+    return T
+
+
+@pytest.mark.parametrize("src", ["SEPT", "VORT", "SPIN"])
+def test_higher_slip_mode_flows_match_their_slip_on_surface(src):
+    """Septlet, vortlet and spinlet slip modes of the minimal truncation: on r = a the flow equals
+    (a^2/2) gamma:nn, -(a^2/3) n x (psi.n) and -(a^3/8) n x (lambda:nn)."""
+    nh, _ = sphere_quad.sphere_rule(8, 16)
+    u = greens.flow(src, A * nh, A, ETA)
+    for q in range(u.shape[2]):
+        if src == "VORT":
+            want = -A ** 2 / 3 * np.cross(nh, nh @ basis.BASIS[q].T)
+        else:
+            Tq = _unit_stf3(q)
+            tnn = np.einsum("ijk,pj,pk->pi", Tq, nh, nh)
+            want = A ** 2 / 2 * tnn if src == "SEPT" else -A ** 3 / 8 * np.cross(nh, tnn)
+        assert np.abs(u[:, :, q] - want).max() < 1e-14 * max(1.0, np.abs(want).max())
+
+
+@pytest.mark.parametrize("src", ["SEPT", "VORT", "SPIN"])
+def test_higher_slip_modes_do_not_move_a_lone_sphere(src):
+    """A force- and torque-free sphere moves with minus the surface mean of its slip and rotates
+    with -(3/2a) times the mean of n x slip; for these modes both vanish, so they add no
+    self term, only pair terms."""
+    nh, w = sphere_quad.sphere_rule(24, 48)
+    u = greens.flow(src, A * nh, A, ETA)
+    for q in range(u.shape[2]):
+        mean = (w[:, None] * u[:, :, q]).sum(0) / (4 * np.pi)
+        rot = (w[:, None] * np.cross(nh, u[:, :, q])).sum(0) / (4 * np.pi)
+        assert np.abs(mean).max() < 1e-15 and np.abs(rot).max() < 1e-15
+
+
+@pytest.mark.parametrize("src", ["F", "T", "S", "D", "SEPT", "VORT", "SPIN"])
 def test_source_flows_are_stokes_flows(src):
     """Divergence free and biharmonic, exactly (symbolic)."""
     for col in greens.source_flow(src):
@@ -79,7 +124,7 @@ def test_source_flows_are_stokes_flows(src):
 
 
 # ---------------------------------------------------------------- target operators = Galerkin projections
-@pytest.mark.parametrize("src", ["F", "T", "S", "D"])
+@pytest.mark.parametrize("src", ["F", "T", "S", "D", "SEPT", "VORT", "SPIN"])
 def test_target_operators_equal_surface_integral_coefficients(src):
     rng = np.random.default_rng(7)
     nh, w = sphere_quad.sphere_rule(48, 96)
@@ -196,19 +241,25 @@ def test_self_slip_coefficient_option():
 
 
 # ---------------------------------------------------------------- whole system vs the Dirichlet condition
-def test_solution_satisfies_weak_boundary_conditions_by_quadrature():
+@pytest.mark.parametrize("higher", [False, True])
+def test_solution_satisfies_weak_boundary_conditions_by_quadrature(higher):
+    """The solved suspension's flow on every sphere has the l = 0 and l = 1 surface moments of the
+    rigid motion plus the slip (with the septlet, vortlet and spinlet modes too, whose own
+    moments of these orders vanish)."""
     rng = np.random.default_rng(8)
     n = 5
     R = inputs.place_spheres(n, 9.0 * A, seed=9, min_dist=2.2 * A)
     w = inputs.Workload(R, np.zeros((n, 3)), rng.standard_normal((n, 3)), rng.standard_normal((n, 5)),
                         rng.standard_normal((n, 3)), rng.standard_normal((n, 3)),
                         rng.standard_normal((n, 3)), ETA, A)
+    if higher:
+        w.gam, w.psi, w.lam = rng.standard_normal((n, 10)), rng.standard_normal((n, 5)), rng.standard_normal((n, 10))
     sol = galerkin.solve(w, PRM)
     nh, wq = sphere_quad.sphere_rule(48, 96)
     for i in range(n):
         pts = R[i] + A * nh
         # the suspension's flow on sphere i's surface (the oracle's field-point evaluation)
-        u = galerkin.flow_field(pts, R, w.Fe, w.Te, sol["Sigma"], w.v3t, PRM)
+        u = galerkin.flow_field(pts, R, w.Fe, w.Te, sol["Sigma"], w.v3t, PRM, modes=galerkin.workload_modes(w))
         mean, V2 = sphere_quad.coefficients(u, nh, wq, A)
         scale = np.abs(u).max()
         assert np.abs(mean - (sol["V"][i] + w.v1s[i])).max() < 1e-11 * scale      # V - V^a
