@@ -187,6 +187,45 @@ int mbs_outputs(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, con
 int mbs_flow(mbs_ctx* ctx, int64_t m, const double* X, int64_t n, const double* R, const double* Fe,
              const double* Te, const double* Sigma, const double* v3t, double* U, void* stream);
 
+/* Higher slip modes of the minimal truncation (section IV), each a fixed source that keeps its
+   one-body traction (as the rank-3 trace mode d does): the septlet mode gamma and the vortlet mode
+   psi (irreducible parts of the quadratic surface-velocity coefficient V^(3)) and the spinlet mode
+   lambda (rank-3 part of the cubic coefficient V^(4)). With n the unit normal of the sphere, its
+   surface velocity gains
+       gamma: (a^2/2) gamma : n n       psi: -(a^2/3) n x (psi . n)       lambda: -(a^3/8) n x (lambda : n n)
+   (the weights 1/6 and 1/90 of the surface expansion times the embeddings of the irreducible parts).
+   A lone sphere does not move with them (the surface means of the slip and of n x slip vanish);
+   they act on the other spheres through their exterior flows (the septlet flow is
+   (7a^5/48)(1 + a^2/14 nabla^2) grad grad G : gamma, the two others are rotational, decaying as
+   r^-3 and r^-4): through the strain in the right-hand side of the stresslet rows and directly in
+   V and Omega.
+     gam, lam [n x 10]  symmetric rank-3 tensors by the components xxx xxy xxz xyy xyz xzz yyy yyz yzz
+                        zzz; only their symmetric traceless part is used
+     psi      [n x 5]   symmetric traceless rank-2 tensor in the 5-basis
+   Any pointer may be NULL (= zero); a NULL mbs_slip_ex* means all three are zero. */
+typedef struct mbs_slip_ex {
+  const double* gam;
+  const double* psi;
+  const double* lam;
+} mbs_slip_ex;
+
+/* mbs_solve, mbs_rhs, mbs_outputs and mbs_flow with the higher slip modes as well (arguments as
+   there; ex as above). Each higher mode present costs one more all-pairs pass in the right-hand
+   side and one in the outputs (all three share one pass). mbs_solve_batched and mbs_step do not
+   take them. */
+int mbs_solve_ex(mbs_ctx* ctx, int64_t n, const double* R, const double* p, const double* v1s,
+                 const double* v2s, const double* v3t, const mbs_slip_ex* ex, const double* Fe,
+                 const double* Te, const double* sigma0, double* V, double* W, double* S, double* Sigma,
+                 mbs_stats* st, void* stream);
+int mbs_rhs_ex(mbs_ctx* ctx, int64_t n, const double* R, const double* v2s, const double* v3t,
+               const mbs_slip_ex* ex, const double* Fe, const double* Te, double* b, void* stream);
+int mbs_outputs_ex(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, const double* v2s,
+                   const double* v3t, const mbs_slip_ex* ex, const double* Fe, const double* Te,
+                   const double* Sigma, double* V, double* W, double* S, void* stream);
+int mbs_flow_ex(mbs_ctx* ctx, int64_t m, const double* X, int64_t n, const double* R, const double* Fe,
+                const double* Te, const double* Sigma, const double* v3t, const mbs_slip_ex* ex, double* U,
+                void* stream);
+
 /* Time integration in a harmonic trap (section V set-up; kinematics of section II):
    every step rebuilds F^e = -k_trap R, T^e = 0, V^(1s) = c0 p, V^(2s) = c1 * 3(pp - I/3),
    V^(3t) = c2 p from the current state, solves, and advances

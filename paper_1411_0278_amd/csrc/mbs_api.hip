@@ -654,9 +654,11 @@ int learned_guess(mbs_ctx* c, int64_t n, const double* R, const double* p, const
 
 // The solve without argument validation; sigma0 is read for MBS_GUESS_USER.
 int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* v1s, const double* v2s,
-               const double* v3t, const double* Fe, const double* Te, const double* sigma0,
+               const double* v3t, const double* Fe, const double* Te, const HighSlip& hi, const double* sigma0,
                double* V, double* W, double* S, double* Sigma, mbs_stats* st, hipStream_t s) {
   CHK(ensure_ws(c, n));
+  const bool high = high_mask(hi) != 0;
+  const int hsplit = high_split(n, n, c->tile_pass);
   const int64_t len = 5 * n;
   const double* Fz = Fe ? Fe : c->zeros.p;
   Counters cnt;
@@ -672,13 +674,14 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const do
     HIPCHK(c, hipEventRecord(c->ev[1], s));
     HIPCHK(c, hipEventRecord(c->ev[2], s));
     launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
+    if (high) launch_high(1, R, n, R, n, hi, V, W, c->part.p, hsplit, c->ph, c->tile_pass, s);
     if (Sigma) launch_copy(c->xs.p, Sigma, len, s);
     HIPCHK(c, hipEventRecord(c->ev[3], s));
     HIPCHK(c, hipStreamSynchronize(s));
     if (st) {
       memset(st, 0, sizeof(*st));
       st->t_out_ms = st->t_total_ms = ev_ms(c->ev[2], c->ev[3]);
-      st->pair_blocks = (double)n * (double)(n - 1);
+      st->pair_blocks = (double)n * (double)(n - 1) * (high ? 2.0 : 1.0);
     }
     return MBS_OK;
   }
@@ -686,6 +689,10 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const do
   // right-hand side
   launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
   cnt.pairs += (double)n * (double)(n - 1);
+  if (high) {  // strain of the septlet, vortlet and spinlet flows
+    launch_high(0, R, n, R, n, hi, c->b.p, nullptr, c->part.p, hsplit, c->ph, c->tile_pass, s);
+    cnt.pairs += (double)n * (double)(n - 1);
+  }
   HIPCHK(c, hipEventRecord(c->ev[1], s));
   norm2(c, c->b.p, len, sm.bnorm2, s);
   CHK(read_status(c, sm.bnorm2, 1, s));
@@ -770,6 +777,10 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const do
   const bool fused = op.valid;  // outputs already formed with the final residual
   if (!fused) {
     launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
+    cnt.pairs += (double)n * (double)(n - 1);
+  }
+  if (high) {  // velocities and rotations from the septlet, vortlet and spinlet flows
+    launch_high(1, R, n, R, n, hi, V, W, c->part.p, hsplit, c->ph, c->tile_pass, s);
     cnt.pairs += (double)n * (double)(n - 1);
   }
   if (Sigma) launch_copy(c->xs.p, Sigma, len, s);
@@ -908,11 +919,24 @@ int mbs_set_params(mbs_ctx* c, const mbs_params* prm) {
 
 const char* mbs_last_error(const mbs_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
-int mbs_solve(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* v1s,
-              const double* v2s, const double* v3t, const double* Fe, const double* Te,
-              const double* sigma0, double* V, double* W, double* S, double* Sigma, mbs_stats* st,
-              void* stream) {
+namespace {
+HighSlip high_of(const mbs_slip_ex* ex) {
+  HighSlip h{nullptr, nullptr, nullptr};
+  if (ex) {
+    h.gam = ex->gam;
+    h.psi = ex->psi;
+    h.lam = ex->lam;
+  }
+  return h;
+}
+}  // namespace
+
+int mbs_solve_ex(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* v1s,
+                 const double* v2s, const double* v3t, const mbs_slip_ex* ex, const double* Fe,
+                 const double* Te, const double* sigma0, double* V, double* W, double* S, double* Sigma,
+                 mbs_stats* st, void* stream) {
   CHK(begin_call(c));
+  const HighSlip hi = high_of(ex);
   (void)p;
   if (n < 1) return set_err(c, MBS_EINVAL, "n = %lld must be >= 1", (long long)n);
   if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
@@ -923,7 +947,8 @@ int mbs_solve(mbs_ctx* c, int64_t n, const double* R, const double* p, const dou
   CHK(ensure_ws(c, n));
   int bad = 0;
   CHK(count_nonfinite(c, s, {{R, 3 * n}, {v1s, 3 * n}, {v2s, 5 * n}, {v3t, 3 * n}, {Fe, 3 * n},
-                             {Te, 3 * n}, {sigma0, c->prm.guess == MBS_GUESS_USER ? 5 * n : 0}},
+                             {Te, 3 * n}, {sigma0, c->prm.guess == MBS_GUESS_USER ? 5 * n : 0},
+                             {hi.gam, 10 * n}, {hi.psi, 5 * n}, {hi.lam, 10 * n}},
                       &bad));
   if (bad) return set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
   if (c->prm.check_overlap) {
@@ -938,8 +963,16 @@ int mbs_solve(mbs_ctx* c, int64_t n, const double* R, const double* p, const dou
     if (!p) return set_err(c, MBS_EINVAL, "the learned guess needs the orientations p");
     if (n < kNeigh + 1) return set_err(c, MBS_EINVAL, "the learned guess needs n >= %d", kNeigh + 1);
   }
-  return solve_core(c, n, R, p, v1s, v2s, v3t, Fe, Te, sigma0, V, W, S, Sigma, st, s);
+  return solve_core(c, n, R, p, v1s, v2s, v3t, Fe, Te, hi, sigma0, V, W, S, Sigma, st, s);
 }
+
+int mbs_solve(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* v1s,
+              const double* v2s, const double* v3t, const double* Fe, const double* Te,
+              const double* sigma0, double* V, double* W, double* S, double* Sigma, mbs_stats* st,
+              void* stream) {
+  return mbs_solve_ex(c, n, R, p, v1s, v2s, v3t, nullptr, Fe, Te, sigma0, V, W, S, Sigma, st, stream);
+}
+
 
 int mbs_matvec(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, int precision,
                void* stream) {
@@ -961,15 +994,42 @@ int mbs_matvec(mbs_ctx* c, int64_t n, const double* R, const double* x, double* 
   return MBS_OK;
 }
 
-int mbs_rhs(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const double* v3t,
-            const double* Fe, const double* Te, double* b, void* stream) {
+int mbs_rhs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const double* v3t,
+               const mbs_slip_ex* ex, const double* Fe, const double* Te, double* b, void* stream) {
   CHK(begin_call(c));
   if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
-  if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
+  if (n > (int64_t)INT32_MAX / 10) return set_err(c, MBS_EINVAL, "n too large");
   if (!R || !b) return set_err(c, MBS_EINVAL, "R and b are required");
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
   launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, c->ph, c->tile_pass, s);
+  const HighSlip hi = high_of(ex);
+  if (high_mask(hi))
+    launch_high(0, R, n, R, n, hi, b, nullptr, c->part.p, high_split(n, n, c->tile_pass), c->ph, c->tile_pass, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_rhs(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const double* v3t,
+            const double* Fe, const double* Te, double* b, void* stream) {
+  return mbs_rhs_ex(c, n, R, v2s, v3t, nullptr, Fe, Te, b, stream);
+}
+
+int mbs_outputs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const double* v2s,
+                   const double* v3t, const mbs_slip_ex* ex, const double* Fe, const double* Te,
+                   const double* Sigma, double* V, double* W, double* S, void* stream) {
+  CHK(begin_call(c));
+  if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
+  if (n > (int64_t)INT32_MAX / 10) return set_err(c, MBS_EINVAL, "n too large");
+  if (!R || !Sigma || !V || !W) return set_err(c, MBS_EINVAL, "R, Sigma, V and W are required");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(ensure_ws(c, n));
+  launch_p3(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, c->ph,
+            c->tile_pass, s);
+  const HighSlip hi = high_of(ex);
+  if (high_mask(hi))
+    launch_high(1, R, n, R, n, hi, V, W, c->part.p, high_split(n, n, c->tile_pass), c->ph, c->tile_pass, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;
@@ -978,14 +1038,23 @@ int mbs_rhs(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const dou
 int mbs_outputs(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const double* v2s,
                 const double* v3t, const double* Fe, const double* Te, const double* Sigma,
                 double* V, double* W, double* S, void* stream) {
+  return mbs_outputs_ex(c, n, R, v1s, v2s, v3t, nullptr, Fe, Te, Sigma, V, W, S, stream);
+}
+
+int mbs_flow_ex(mbs_ctx* c, int64_t m, const double* X, int64_t n, const double* R, const double* Fe,
+                const double* Te, const double* Sigma, const double* v3t, const mbs_slip_ex* ex, double* U,
+                void* stream) {
   CHK(begin_call(c));
-  if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
-  if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
-  if (!R || !Sigma || !V || !W) return set_err(c, MBS_EINVAL, "R, Sigma, V and W are required");
+  if (m < 1 || n < 1) return set_err(c, MBS_EINVAL, "m and n must be >= 1");
+  if (m > (int64_t)INT32_MAX / 12 || n > (int64_t)INT32_MAX / 10) return set_err(c, MBS_EINVAL, "m or n too large");
+  if (!X || !R || !Sigma || !U) return set_err(c, MBS_EINVAL, "X, R, Sigma and U are required");
   hipStream_t s = (hipStream_t)stream;
-  CHK(ensure_ws(c, n));
-  launch_p3(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, c->ph,
-            c->tile_pass, s);
+  CHK(ensure_ws(c, n));  // (zeros stand in for absent forces)
+  const HighSlip hi = high_of(ex);
+  const int hsplit = high_split(m, n, c->tile_pass);
+  CHK(ensure(c, c->part, (size_t)std::max(flow_split(m, n, c->tile_pass), high_mask(hi) ? hsplit : 0) * 3 * m + 64));
+  launch_flow(X, m, R, Fe ? Fe : c->zeros.p, Te, Sigma, v3t, U, c->part.p, n, c->ph, c->tile_pass, s);
+  if (high_mask(hi)) launch_high(2, X, m, R, n, hi, U, nullptr, c->part.p, hsplit, c->ph, c->tile_pass, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;
@@ -993,17 +1062,7 @@ int mbs_outputs(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const
 
 int mbs_flow(mbs_ctx* c, int64_t m, const double* X, int64_t n, const double* R, const double* Fe,
              const double* Te, const double* Sigma, const double* v3t, double* U, void* stream) {
-  CHK(begin_call(c));
-  if (m < 1 || n < 1) return set_err(c, MBS_EINVAL, "m and n must be >= 1");
-  if (m > (int64_t)INT32_MAX / 12 || n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "m or n too large");
-  if (!X || !R || !Sigma || !U) return set_err(c, MBS_EINVAL, "X, R, Sigma and U are required");
-  hipStream_t s = (hipStream_t)stream;
-  CHK(ensure_ws(c, n));  // (zeros stand in for absent forces)
-  CHK(ensure(c, c->part, (size_t)flow_split(m, n, c->tile_pass) * 3 * m + 64));
-  launch_flow(X, m, R, Fe ? Fe : c->zeros.p, Te, Sigma, v3t, U, c->part.p, n, c->ph, c->tile_pass, s);
-  HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipStreamSynchronize(s));
-  return MBS_OK;
+  return mbs_flow_ex(c, m, X, n, R, Fe, Te, Sigma, v3t, nullptr, U, stream);
 }
 
 int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const double* slip_coef,
@@ -1056,7 +1115,7 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
     const bool first = k == 0 && !hist_valid;  // no history yet: one-body guess, Euler step
     const bool warm = guess0 == MBS_GUESS_USER && !first;
     if (guess0 == MBS_GUESS_USER && first) c->prm.guess = MBS_GUESS_DIAG;
-    rc = solve_core(c, n, R, p, v1s, v2s, slip_coef[2] != 0.0 ? v3t : nullptr, Fe, nullptr,
+    rc = solve_core(c, n, R, p, v1s, v2s, slip_coef[2] != 0.0 ? v3t : nullptr, Fe, nullptr, HighSlip{nullptr, nullptr, nullptr},
                     warm ? Sg : nullptr, V, W, Sout, Sg, &one, s);
     c->prm.guess = guess0;
     if (rc != MBS_OK && rc != MBS_ENOCONV) break;

@@ -56,6 +56,20 @@ int flow_split(int64_t m, int64_t n, Tile t);
 void launch_flow(const double* X, int64_t m, const double* R, const double* Fe, const double* Te,
                  const double* Sig, const double* v3t, double* U, double* part, int64_t n, const Phys& ph,
                  Tile t, hipStream_t s);
+// Septlet, vortlet and spinlet slip modes of the minimal truncation (fixed sources): gam and lam
+// [n x 10] symmetric rank-3 components (traceless part used), psi [n x 5] 5-basis; NULL = absent.
+struct HighSlip {
+  const double* gam;
+  const double* psi;
+  const double* lam;
+};
+int high_mask(const HighSlip& h);  // bit 0 gam, bit 1 psi, bit 2 lam
+// One all-pairs pass of the higher modes' sources R [n x 3] at receivers X [m x 3], added into the
+// caller's arrays: target 0 strain (a [m x 5] += E), 1 rigid-body motion (a [m x 3] += U,
+// b [m x 3] += W), 2 flow at field points (a [m x 3] += u). part: scratch of split x 6m doubles.
+int high_split(int64_t m, int64_t n, Tile t);
+void launch_high(int target, const double* X, int64_t m, const double* R, int64_t n, const HighSlip& h,
+                 double* a, double* b, double* part, int split, const Phys& ph, Tile t, hipStream_t s);
 // min over pairs of |R_n - R_m|^2 -> out[0] (device), from the cell grid g of R (exact: an
 // all-pairs scan takes over when no pair is closer than one cell edge); scratch: ceil(n/256) doubles
 struct GridView;

@@ -24,7 +24,8 @@ EXPORTS = ("mbs_default_params", "mbs_create", "mbs_destroy", "mbs_set_params", 
            "mbs_solve", "mbs_matvec", "mbs_rhs", "mbs_outputs", "mbs_flow", "mbs_step", "mbs_solve_batched",
            "mbs_autotune", "mbs_autotune_batched", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
            "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
-           "mbs_warmstart_load", "mbs_warmstart_target", "mbs_initial_guess", "mbs_precond_apply")
+           "mbs_warmstart_load", "mbs_warmstart_target", "mbs_initial_guess", "mbs_precond_apply",
+           "mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex")
 MLP_NPARAM, MLP_NFEAT = 27525, 80
 
 
@@ -42,6 +43,11 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("guess", ctypes.c_int32),
                 ("check_overlap", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("batch_item", ctypes.c_int32), ("superposition", ctypes.c_int32)]
+
+
+class SlipEx(ctypes.Structure):
+    """mbs_slip_ex: septlet gamma [n, 10], vortlet psi [n, 5], spinlet lambda [n, 10] (NULL = zero)."""
+    _fields_ = [("gam", ctypes.c_void_p), ("psi", ctypes.c_void_p), ("lam", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -116,6 +122,13 @@ def load(path: str = LIB_PATH):
     lib.mbs_precond_apply.argtypes = [P, I64, P, P, P, VP]
     lib.mbs_precond_apply.restype = ctypes.c_int
     lib.mbs_initial_guess.argtypes = [P, I64] + [P] * 6 + [I32, P, VP]
+    EX = ctypes.POINTER(SlipEx)
+    lib.mbs_solve_ex.argtypes = [P, I64] + [P] * 5 + [EX] + [P] * 7 + [ctypes.POINTER(Stats), VP]
+    lib.mbs_rhs_ex.argtypes = [P, I64, P, P, P, EX, P, P, P, VP]
+    lib.mbs_outputs_ex.argtypes = [P, I64, P, P, P, P, EX] + [P] * 6 + [VP]
+    lib.mbs_flow_ex.argtypes = [P, I64, P, I64, P, P, P, P, P, EX, P, VP]
+    for name in ("mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("mbs_warmstart_target", "mbs_initial_guess", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
                  "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
                  "mbs_warmstart_load"):
@@ -248,6 +261,66 @@ class Context:
         self._check(self.lib.mbs_flow(self.h, m, _ptr(X, m, 3, "X"), n, _ptr(R, n, 3, "R"), _ptr(Fe, n, 3, "Fe"),
                                       _ptr(Te, n, 3, "Te"), _ptr(Sigma, n, 5, "Sigma"), _ptr(v3t, n, 3, "v3t"),
                                       _ptr(U, m, 3, "U"), _stream()))
+        return U
+
+    # ---- the higher slip modes (septlet gam [n, 10], vortlet psi [n, 5], spinlet lam [n, 10])
+    @staticmethod
+    def _slip_ex(n, gam, psi, lam):
+        ex = SlipEx()
+        ex.gam = _ptr(gam, n, 10, "gam")
+        ex.psi = _ptr(psi, n, 5, "psi")
+        ex.lam = _ptr(lam, n, 10, "lam")
+        return ex
+
+    def mbs_solve_ex(self, R, p=None, v1s=None, v2s=None, v3t=None, gam=None, psi=None, lam=None, Fe=None,
+                     Te=None, sigma0=None, V=None, W=None, S=None, Sigma=None, allow_noconv=False):
+        import torch
+        n = R.shape[0]
+        V = torch.empty((n, 3), dtype=torch.float64, device=R.device) if V is None else V
+        W = torch.empty((n, 3), dtype=torch.float64, device=R.device) if W is None else W
+        S = torch.empty((n, 5), dtype=torch.float64, device=R.device) if S is None else S
+        ex = self._slip_ex(n, gam, psi, lam)
+        st = Stats()
+        rc = self.lib.mbs_solve_ex(self.h, n, _ptr(R, n, 3, "R"), _ptr(p, n, 3, "p"), _ptr(v1s, n, 3, "v1s"),
+                                   _ptr(v2s, n, 5, "v2s"), _ptr(v3t, n, 3, "v3t"), ctypes.byref(ex),
+                                   _ptr(Fe, n, 3, "Fe"), _ptr(Te, n, 3, "Te"), _ptr(sigma0, n, 5, "sigma0"),
+                                   _ptr(V, n, 3, "V"), _ptr(W, n, 3, "W"), _ptr(S, n, 5, "S"),
+                                   _ptr(Sigma, n, 5, "Sigma"), ctypes.byref(st), _stream())
+        self._check(rc, (MBS_ENOCONV,) if allow_noconv else ())
+        return V, W, S, st.as_dict()
+
+    def mbs_rhs_ex(self, R, v2s=None, v3t=None, gam=None, psi=None, lam=None, Fe=None, Te=None, b=None):
+        import torch
+        n = R.shape[0]
+        b = torch.empty((n, 5), dtype=torch.float64, device=R.device) if b is None else b
+        ex = self._slip_ex(n, gam, psi, lam)
+        self._check(self.lib.mbs_rhs_ex(self.h, n, _ptr(R, n, 3, "R"), _ptr(v2s, n, 5, "v2s"), _ptr(v3t, n, 3, "v3t"),
+                                        ctypes.byref(ex), _ptr(Fe, n, 3, "Fe"), _ptr(Te, n, 3, "Te"),
+                                        _ptr(b, n, 5, "b"), _stream()))
+        return b
+
+    def mbs_outputs_ex(self, R, Sigma, v1s=None, v2s=None, v3t=None, gam=None, psi=None, lam=None, Fe=None,
+                       Te=None, V=None, W=None, S=None):
+        import torch
+        n = R.shape[0]
+        V = torch.empty((n, 3), dtype=torch.float64, device=R.device) if V is None else V
+        W = torch.empty((n, 3), dtype=torch.float64, device=R.device) if W is None else W
+        S = torch.empty((n, 5), dtype=torch.float64, device=R.device) if S is None else S
+        ex = self._slip_ex(n, gam, psi, lam)
+        self._check(self.lib.mbs_outputs_ex(self.h, n, _ptr(R, n, 3, "R"), _ptr(v1s, n, 3, "v1s"),
+                                            _ptr(v2s, n, 5, "v2s"), _ptr(v3t, n, 3, "v3t"), ctypes.byref(ex),
+                                            _ptr(Fe, n, 3, "Fe"), _ptr(Te, n, 3, "Te"), _ptr(Sigma, n, 5, "Sigma"),
+                                            _ptr(V, n, 3, "V"), _ptr(W, n, 3, "W"), _ptr(S, n, 5, "S"), _stream()))
+        return V, W, S
+
+    def mbs_flow_ex(self, X, R, Sigma, Fe=None, Te=None, v3t=None, gam=None, psi=None, lam=None, U=None):
+        import torch
+        m, n = X.shape[0], R.shape[0]
+        U = torch.empty((m, 3), dtype=torch.float64, device=X.device) if U is None else U
+        ex = self._slip_ex(n, gam, psi, lam)
+        self._check(self.lib.mbs_flow_ex(self.h, m, _ptr(X, m, 3, "X"), n, _ptr(R, n, 3, "R"), _ptr(Fe, n, 3, "Fe"),
+                                         _ptr(Te, n, 3, "Te"), _ptr(Sigma, n, 5, "Sigma"), _ptr(v3t, n, 3, "v3t"),
+                                         ctypes.byref(ex), _ptr(U, m, 3, "U"), _stream()))
         return U
 
     def mbs_step(self, R, p, k_trap, slip_coef, dt, nsteps, order=2, want_min_dist=False,
@@ -426,4 +499,8 @@ def to_device(w, device="cuda"):
     """Copy a paper_1411_0278_amd.inputs.Workload's arrays to float64 device tensors."""
     import torch
     f = lambda a: torch.as_tensor(a, dtype=torch.float64).contiguous().to(device)
-    return dict(R=f(w.R), p=f(w.p), v1s=f(w.v1s), v2s=f(w.v2s), v3t=f(w.v3t), Fe=f(w.Fe), Te=f(w.Te))
+    d = dict(R=f(w.R), p=f(w.p), v1s=f(w.v1s), v2s=f(w.v2s), v3t=f(w.v3t), Fe=f(w.Fe), Te=f(w.Te))
+    for k in ("gam", "psi", "lam"):  # the higher slip modes, when the workload has them
+        if getattr(w, k, None) is not None:
+            d[k] = f(getattr(w, k))
+    return d

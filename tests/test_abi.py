@@ -42,6 +42,7 @@ def test_default_params_and_struct_layout():
     assert abs(p.eta * 6 * 3.141592653589793 - 1) < 1e-15 and p.a == 1.0
     assert ctypes.sizeof(mbstokes.Params) == 6 * 8 + 10 * 4
     assert ctypes.sizeof(mbstokes.Stats) == 4 * 4 + 8 * 8 + 2 * 4
+    assert ctypes.sizeof(mbstokes.SlipEx) == 3 * 8
 
 
 def test_create_without_gpu_fails_cleanly():
