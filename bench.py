@@ -27,6 +27,10 @@ FP32_PEAK_TF = 157.3    # MI355X vector FP32 (published figure, counts packed FP
 # differences 3, r^2 5, 1/r 1, powers 4, Szz 1, w 15, q 5, c1 3, c2 4, v 9, moments 18, r^-5 Sigma 10
 P2_FLOP_PER_PAIR = 78
 FLOW_FLOP_PER_PAIR = 68  # field-point flow from force and flow stresslet (no torque, no rank-3 mode)
+# the pass of the septlet, vortlet and spinlet slip modes (all three present), per pair, counted from
+# the implemented formulas (FMA = 2, rsqrt = 1): geometry 14; strain target gamma 115, psi 97,
+# lambda 126; motion target 85, 53, 82; flow target 69, 33, 61
+HIGH_FLOP_PER_PAIR = {"strain": 352, "motion": 234, "flow": 177}
 
 
 def parse():
@@ -201,9 +205,47 @@ def bench_kernels(ctx, a):
             ms = median_ms(lambda: ctx.mbs_flow(X, d["R"], sig, Fe=d["Fe"]))
             row["flow"] = {"ms": round(ms, 4), "field_points": n, "pair_blocks_per_s": n * n / (ms * 1e-3),
                            "tflops_algorithmic": round(FLOW_FLOP_PER_PAIR * n * n / (ms * 1e-3) / 1e12, 3)}
+            row["higher_modes"] = bench_higher_modes(ctx, d, w, sig, X, median_ms)
         out[label] = row
         print(f"bench: pair passes at {label} timed", file=sys.stderr, flush=True)
     return out
+
+
+def bench_higher_modes(ctx, d, w, sig, X, median_ms):
+    """The septlet, vortlet and spinlet slip modes (uniaxial along p) at N = 10^5: the pass each
+    extended entry point adds (its time minus that of the plain entry point), and a solve with them."""
+    import time as _time
+
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+    n = w.n
+    g, ps, l = inputs.higher_slip_modes(w.p, 1.0, 1.0, 1.0)
+    f = lambda a_: torch.as_tensor(a_, dtype=torch.float64).contiguous().to("cuda:0")
+    hm = dict(gam=f(g), psi=f(ps), lam=f(l))
+    row = {}
+    base = median_ms(lambda: ctx.mbs_rhs(d["R"], d["v2s"], None, d["Fe"], None))
+    ext = median_ms(lambda: ctx.mbs_rhs_ex(d["R"], d["v2s"], None, Fe=d["Fe"], **hm))
+    row["strain_pass"] = {"ms": round(ext - base, 4), "flop_per_pair": HIGH_FLOP_PER_PAIR["strain"],
+                          "tflops_algorithmic": round(HIGH_FLOP_PER_PAIR["strain"] * n * (n - 1) / ((ext - base) * 1e-3) / 1e12, 3)}
+    base = median_ms(lambda: ctx.mbs_outputs(d["R"], sig, d["v1s"], d["v2s"], None, d["Fe"], None))
+    ext = median_ms(lambda: ctx.mbs_outputs_ex(d["R"], sig, d["v1s"], d["v2s"], None, Fe=d["Fe"], **hm))
+    row["motion_pass"] = {"ms": round(ext - base, 4), "flop_per_pair": HIGH_FLOP_PER_PAIR["motion"],
+                          "tflops_algorithmic": round(HIGH_FLOP_PER_PAIR["motion"] * n * (n - 1) / ((ext - base) * 1e-3) / 1e12, 3)}
+    base = median_ms(lambda: ctx.mbs_flow(X, d["R"], sig, Fe=d["Fe"]))
+    ext = median_ms(lambda: ctx.mbs_flow_ex(X, d["R"], sig, Fe=d["Fe"], **hm))
+    row["flow_pass"] = {"ms": round(ext - base, 4), "flop_per_pair": HIGH_FLOP_PER_PAIR["flow"],
+                        "tflops_algorithmic": round(HIGH_FLOP_PER_PAIR["flow"] * n * n / ((ext - base) * 1e-3) / 1e12, 3)}
+    ctx.set_params(precision=mbstokes.MBS_MIXED, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-10, near_cutoff=8.0)
+    ctx.mbs_solve_ex(d["R"], d["p"], d["v1s"], d["v2s"], None, Fe=d["Fe"], **hm)
+    torch.cuda.synchronize()
+    t0 = _time.perf_counter()
+    V, W, S, st = ctx.mbs_solve_ex(d["R"], d["p"], d["v1s"], d["v2s"], None, Fe=d["Fe"], **hm)
+    torch.cuda.synchronize()
+    row["solve_mixed_pc"] = {"ms": round(1e3 * (_time.perf_counter() - t0), 3), "iters": st["iters"],
+                             "rel_resid": st["rel_resid"]}
+    ctx.set_params(precision=mbstokes.MBS_FP64, near_cutoff=0.0)
+    return row
 
 
 def bench_batched(ctx, a):
