@@ -92,3 +92,44 @@ def test_full_size_solution_rows_match_oracle(ctx):
     assert np.abs(Vg - Vo).max() <= 1e-11 * np.abs(Vo).max()
     assert np.abs(Wg - Wo).max() <= 1e-11 * np.abs(Wo).max()
     assert np.abs(Sg - So).max() <= 1e-14 * np.abs(So).max()
+
+
+def test_batched_config3_matches_oracle(ctx):
+    """The 512-configuration batch (N log-uniform in [64, 4096], density 0.004) solved in one call
+    with the near-field preconditioner: every configuration with N <= 100 against the oracle's
+    dense solve (1e-10 per output), and for every fourth configuration the oracle's binary64
+    residual rows and rigid-body motion of two sampled spheres from the GPU's Sigma."""
+    ws = inputs.config3()
+    off = np.cumsum([0] + [w.n for w in ws])
+    cat = lambda f: torch.as_tensor(np.concatenate([getattr(w, f) for w in ws])).to(DEV)
+    ntot = int(off[-1])
+    print(f"batched config3: {len(ws)} configurations, {ntot} spheres", flush=True)
+    ctx.set_params(tol=1e-12, near_cutoff=8.0)
+    try:
+        Sig = torch.empty((ntot, 5), dtype=torch.float64, device=DEV)
+        V, W, S, stats, _ = ctx.mbs_solve_batched(off, cat("R"), cat("v1s"), cat("v2s"), None, cat("Fe"), None,
+                                                  Sigma=Sig)
+    finally:
+        ctx.set_params(tol=1e-10, near_cutoff=0.0)
+    assert max(s["rel_resid"] for s in stats) <= 1e-12
+    V, W, S, Sig = (t.cpu().numpy() for t in (V, W, S, Sig))
+    dense = 0
+    for b, w in enumerate(ws):
+        sl = slice(off[b], off[b + 1])
+        prm = galerkin.Params(eta=w.eta, a=w.a)
+        z = np.zeros_like(w.Fe)
+        if w.n <= 100:
+            ref = galerkin.solve(w, prm)
+            for k, g in (("V", V[sl]), ("W", W[sl]), ("S", S[sl]), ("Sigma", Sig[sl])):
+                assert _rel(g, ref[k]) < 1e-10, (b, k)
+            dense += 1
+        if b % 4 == 0:
+            rows = np.array([0, w.n // 2]) if w.n > 1 else np.array([0])
+            bb = galerkin.rhs(w.R, w.v2s, z, w.Fe, z, prm, rows).reshape(-1, 5)
+            r = bb - galerkin.matvec_rows(w.R, Sig[sl], rows, prm)
+            assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(bb), b
+            Vo, Wo, _ = galerkin.outputs(w.R, w.v1s, w.v2s, z, w.Fe, z, Sig[sl], prm, rows)
+            assert np.abs(V[sl][rows] - Vo).max() <= 1e-11 * np.abs(Vo).max(), b
+            assert np.abs(W[sl][rows] - Wo).max() <= 1e-11 * max(np.abs(Wo).max(), 1e-300), b
+    print(f"  {dense} dense comparisons, {len(ws[::4])} row checks", flush=True)
+    assert dense > 40
