@@ -95,11 +95,10 @@ def rhs(R, v2s, v3t, Fe, Te, prm: Params, rows=None, modes=None):
     """b = sum_{m != n} E[F, T, d (, gamma, psi, lambda)] - c s, flattened [5N] (or the given rows)."""
     R = np.asarray(R, dtype=np.float64)
     rows = np.arange(len(R)) if rows is None else np.asarray(rows)
-    b = pair_matrix(R, "E", "F", prm, rows) @ np.ravel(Fe)
-    b = b + pair_matrix(R, "E", "T", prm, rows) @ np.ravel(Te)
-    b = b + pair_matrix(R, "E", "D", prm, rows) @ np.ravel(v3t)
-    for kind, vals in _modes(modes).items():
-        b = b + pair_matrix(R, "E", kind, prm, rows) @ np.ravel(vals)
+    b = np.zeros(5 * len(rows))
+    for kind, vals in {"F": Fe, "T": Te, "D": v3t, **_modes(modes)}.items():
+        if vals is not None:  # None stands for an absent source
+            b = b + pair_matrix(R, "E", kind, prm, rows) @ np.ravel(vals)
     b = b - prm.self_slip_c * np.ravel(np.asarray(v2s)[rows])
     return b
 
@@ -111,10 +110,10 @@ def outputs(R, v1s, v2s, v3t, Fe, Te, Sigma, prm: Params, rows=None, modes=None)
     R = np.asarray(R, dtype=np.float64)
     rows = np.arange(len(R)) if rows is None else np.asarray(rows)
     k = constants(prm)
-    src = {"F": np.ravel(Fe), "T": np.ravel(Te), "S": np.ravel(Sigma), "D": np.ravel(v3t)}
-    src.update({kind: np.ravel(vals) for kind, vals in _modes(modes).items()})
-    V = -np.asarray(v1s)[rows] + np.asarray(Fe)[rows] / k["drag_t"]
-    W = np.asarray(Te)[rows] / k["drag_r"]
+    src = {kind: np.ravel(vals) for kind, vals in {"F": Fe, "T": Te, "S": Sigma, "D": v3t, **_modes(modes)}.items()
+           if vals is not None}  # None stands for an absent source
+    V = -np.asarray(v1s)[rows] + (np.asarray(Fe)[rows] / k["drag_t"] if Fe is not None else 0.0)
+    W = np.asarray(Te)[rows] / k["drag_r"] if Te is not None else np.zeros((len(rows), 3))
     for X, vec in src.items():
         V = V + (pair_matrix(R, "U", X, prm, rows) @ vec).reshape(-1, 3)
         W = W + (pair_matrix(R, "W", X, prm, rows) @ vec).reshape(-1, 3)
