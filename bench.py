@@ -46,7 +46,11 @@ def parse():
     ap.add_argument("--headline", default="mixed_pc",
                     choices=["plain_fp64", "fp64_diag", "mixed_diag", "fp64_learned", "mixed_learned",
                              "fp64_pc", "mixed_pc", "mixed_diag_pc", "mixed_learned_pc"])
-    ap.add_argument("--near-cutoff", type=float, default=8.0,
+    ap.add_argument("--near-order", type=int, default=4,
+                    help="Neumann order of the near-field preconditioner in the *_pc variants")
+    ap.add_argument("--aux-near-cutoff", type=float, default=8.0,
+                    help="near-field cutoff of the batched and time-stepping runs (order 2)")
+    ap.add_argument("--near-cutoff", type=float, default=12.0,
                     help="near-field preconditioner cutoff (centre distance) of the *_pc variants")
     ap.add_argument("--skip-warmstart", action="store_true", help="no learned warm start (no training)")
     ap.add_argument("--warmstart-configs", type=int, default=200)
@@ -112,9 +116,10 @@ def measured_traffic(kernel, n):
     return rec.get("bytes_per_launch")
 
 
-def time_variant(ctx, d, mb, name, precision, guess, steps, warmup, near_cutoff=0.0):
+def time_variant(ctx, d, mb, name, precision, guess, steps, warmup, near_cutoff=0.0, near_order=2):
     import torch
-    ctx.set_params(precision=precision, guess=guess, tol=1e-10, near_cutoff=near_cutoff)
+    ctx.set_params(precision=precision, guess=guess, tol=1e-10, near_cutoff=near_cutoff,
+                   near_order=near_order if near_cutoff > 0 else 2)
     args = (d["R"], d["p"], d["v1s"], d["v2s"], d.get("v3t"), d["Fe"], d.get("Te"))
     for k in range(warmup):
         ctx.mbs_solve(*args)
@@ -239,7 +244,8 @@ def bench_higher_modes(ctx, d, w, sig, X, median_ms, cpu_seconds=0.0):
     ext = median_ms(lambda: ctx.mbs_flow_ex(X, d["R"], sig, Fe=d["Fe"], **hm))
     row["flow_pass"] = {"ms": round(ext - base, 4), "flop_per_pair": HIGH_FLOP_PER_PAIR["flow"],
                         "tflops_algorithmic": round(HIGH_FLOP_PER_PAIR["flow"] * n * n / ((ext - base) * 1e-3) / 1e12, 3)}
-    ctx.set_params(precision=mbstokes.MBS_MIXED, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-10, near_cutoff=8.0)
+    ctx.set_params(precision=mbstokes.MBS_MIXED, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-10, near_cutoff=12.0,
+                   near_order=4)
     ctx.mbs_solve_ex(d["R"], d["p"], d["v1s"], d["v2s"], None, Fe=d["Fe"], **hm)
     torch.cuda.synchronize()
     t0 = _time.perf_counter()
@@ -247,7 +253,7 @@ def bench_higher_modes(ctx, d, w, sig, X, median_ms, cpu_seconds=0.0):
     torch.cuda.synchronize()
     row["solve_mixed_pc"] = {"ms": round(1e3 * (_time.perf_counter() - t0), 3), "iters": st["iters"],
                              "rel_resid": st["rel_resid"]}
-    ctx.set_params(precision=mbstokes.MBS_FP64, near_cutoff=0.0)
+    ctx.set_params(precision=mbstokes.MBS_FP64, near_cutoff=0.0, near_order=2)
     if cpu_seconds > 0:
         import numpy as np
 
@@ -283,7 +289,8 @@ def bench_batched(ctx, a):
     print(f"bench: batched workload of {len(ws)} configurations ({int(off[-1])} spheres) built in "
           f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     def run(rc):
-        ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-10, near_cutoff=rc)
+        ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-10, near_cutoff=rc,
+                       near_order=2)
         ctx.mbs_solve_batched(off, R, v1s, v2s, None, Fe, None)      # capture + warm-up
         torch.cuda.synchronize()
         reps = 3
@@ -304,7 +311,7 @@ def bench_batched(ctx, a):
     item, item_ms = ctx.mbs_autotune_batched(off, R)
     print(f"bench: batched work items of {item} receivers (autotuned in {time.perf_counter() - t_tune:.2f} s)",
           file=sys.stderr, flush=True)
-    out = run(a.near_cutoff)
+    out = run(a.aux_near_cutoff)
     out["item_receivers"] = item
     out["item_pass_ms"] = {str(k): round(v, 4) for k, v in item_ms.items()}
     out["without_preconditioner"] = run(0.0)
@@ -324,13 +331,13 @@ def bench_stepper(ctx, a):
 
     from paper_1411_0278_amd import inputs, mbstokes
     w = inputs.config1()
-    out = {"n": w.n, "steps": a.stepper_steps, "dt": 0.01, "near_cutoff": a.near_cutoff,
+    out = {"n": w.n, "steps": a.stepper_steps, "dt": 0.01, "near_cutoff": a.aux_near_cutoff,
            "guess": "previous step's stresslet (first step: one-body)", "max_iter_per_step": 60}
     ctx.mbs_autotune(torch.as_tensor(w.R).to("cuda:0"), None)  # pair-kernel shapes for this N
     for name, prec in (("fp64", mbstokes.MBS_FP64), ("mixed", mbstokes.MBS_MIXED)):
         R = torch.as_tensor(w.R).to("cuda:0")
         p = torch.as_tensor(w.p).to("cuda:0")
-        ctx.set_params(precision=prec, guess=mbstokes.MBS_GUESS_USER, tol=1e-10, near_cutoff=a.near_cutoff,
+        ctx.set_params(precision=prec, guess=mbstokes.MBS_GUESS_USER, tol=1e-10, near_cutoff=a.aux_near_cutoff, near_order=2,
                        max_iter=60)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -473,7 +480,8 @@ def main():
                  ("mixed_learned", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_LEARNED, 0.0),
                  ("mixed_learned_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_LEARNED, rc)]
         # surrogate error of the guesses against the converged solution of this workload
-        ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-12, near_cutoff=rc)
+        ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-12, near_cutoff=rc,
+                       near_order=a.near_order)
         sig = torch.empty((a.n, 5), dtype=torch.float64, device="cuda:0")
         ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None, Sigma=sig)
         rep["surrogate_rel_err"] = {
@@ -485,8 +493,9 @@ def main():
         a.headline = "mixed_pc"
     for name, prec, guess, cut in plan:
         steps = a.steps if name in (a.headline, "plain_fp64") else max(1, min(a.steps, 2))
-        variants[name] = time_variant(ctx, d, mbstokes, name, prec, guess, steps, a.warmup, cut)
+        variants[name] = time_variant(ctx, d, mbstokes, name, prec, guess, steps, a.warmup, cut, a.near_order)
         variants[name]["near_cutoff"] = cut
+        variants[name]["near_order"] = a.near_order if cut > 0 else 0
     if not a.skip_batched:
         extra["batched"] = bench_batched(ctx, a)
     if not a.skip_kernels:
@@ -511,7 +520,7 @@ def main():
         "config": {"workload": f"trap spheres N={a.n} cube side {a.side:g} seed {a.seed}, "
                                f"slip V1s=p V2s=3(pp-I/3), F=-0.5R, solve to 1e-10",
                    "n": a.n, "headline": a.headline, "tol": 1e-10, "tiles": list(tiles),
-                   "near_cutoff": rc},
+                   "near_cutoff": rc, "near_order": a.near_order},
         "roofline": roofline(head, a.n),
         "time_to_1e-10_ms": {k: round(v["ms_per_step"], 3) for k, v in variants.items()},
         "iterations": {k: v["iters"] for k, v in variants.items()},

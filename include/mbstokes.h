@@ -76,8 +76,9 @@ typedef struct mbs_params {
                             1.4 reproduces the paper's one-body stresslet table */
   double  inner_tol;     /* MBS_MIXED: relative tolerance of each inner binary32 GMRES solve (an
                             inner solve also stops once its residual is below 0.3 tol |b|) */
-  double  near_cutoff;   /* > 0: right-precondition GMRES with M^{-1} = gamma (I + X + X^2), X =
-                            gamma K_near (second-order Neumann series of (I/gamma - K_near)^{-1}),
+  double  near_cutoff;   /* > 0: right-precondition GMRES with M^{-1} = gamma (I + X + ... + X^k), X =
+                            gamma K_near (Neumann series of (I/gamma - K_near)^{-1} to the even
+                            order k = near_order),
                             K_near the operator's blocks of pairs closer than near_cutoff (centre distance;
                             at most 32 neighbours per sphere, the smallest indices; pairs closer
                             than 2a are left out); 0 = no preconditioner (default). The solution
@@ -101,6 +102,10 @@ typedef struct mbs_params {
   int32_t superposition; /* nonzero: mbs_solve and mbs_step use the superposition approximation of
                             section IV instead of solving: Sigma_n = -c gamma s_n (lone-sphere
                             stresslets), outputs by the direct sum; 0 = the many-body solve */
+  int32_t near_order;    /* order k of the near-field preconditioner's Neumann series: 2 (default;
+                            0 means 2), 4, 6 or 8 (even orders keep M^{-1} positive definite for
+                            any near block); each order is one sparse pass over the neighbour lists */
+  int32_t reserved;      /* must be 0 */
 } mbs_params;
 
 typedef struct mbs_stats {
@@ -126,7 +131,7 @@ typedef struct mbs_ctx mbs_ctx;
 
 /* Fill *prm with the defaults: eta = 1/(6 pi), a = 1, tol = 1e-10, c = 1, inner_tol = 1e-5,
    lmax = 2, max_iter = 300, restart = 30, MBS_FP64, MBS_GUESS_ZERO, no overlap check, tile 0,
-   graph 1. */
+   graph 1, near_order 2. */
 void mbs_default_params(mbs_params* prm);
 
 /* Create a context on HIP device `device`. *ctx receives the handle (NULL on failure).
@@ -161,8 +166,8 @@ int mbs_solve(mbs_ctx* ctx, int64_t n, const double* R, const double* p, const d
 int mbs_matvec(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y,
                int precision, void* stream);
 
-/* The near-field preconditioner on its own: y = gamma x + gamma^2 K_near x + gamma^3 K_near^2 x
-   (x, y [n x 5] binary64 DEVICE, params.near_cutoff > 0). */
+/* The near-field preconditioner on its own: y = gamma sum_{i <= k} (gamma K_near)^i x, k =
+   params.near_order (x, y [n x 5] binary64 DEVICE, params.near_cutoff > 0). */
 int mbs_precond_apply(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y, void* stream);
 
 /* Right-hand side of the stresslet rows: b_n = sum_{m != n} E[F_m, T_m, d_m] - c s_n, b [n x 5]. */

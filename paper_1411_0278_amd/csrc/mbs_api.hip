@@ -154,6 +154,9 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
     return set_err(c, MBS_EINVAL, "tile must be in 0..%d", kTileCount);
   if (p->batch_item != 0 && p->batch_item != 64 && p->batch_item != 128 && p->batch_item != 256)
     return set_err(c, MBS_EINVAL, "batch_item must be 0, 64, 128 or 256");
+  if (p->near_order != 0 && (p->near_order < 2 || p->near_order > 8 || (p->near_order & 1)))
+    return set_err(c, MBS_EINVAL, "near_order must be 0 (= 2), 2, 4, 6 or 8");
+  if (p->reserved != 0) return set_err(c, MBS_EINVAL, "reserved must be 0");
   return MBS_OK;
 }
 
@@ -183,7 +186,7 @@ int ensure_ws(mbs_ctx* c, int64_t n) {
   CHK(ensure(c, c->zt, len));
   if (c->prm.near_cutoff > 0.0) {
     CHK(ensure(c, c->near, (size_t)(kNearCap + 1) * n / 2 + 64));
-    CHK(ensure(c, c->nt, len));
+    CHK(ensure(c, c->nt, 2 * len));  // the preconditioner's two partial sums
   }
   CHK(ensure(c, c->dpart, (size_t)std::max<int64_t>((int64_t)(m + 2) * 256, 1024 + (n + 255) / 256) + 64));
   CHK(ensure(c, c->small, (size_t)8 * (m + 2) + 64));
@@ -309,9 +312,10 @@ int near_prepare(mbs_ctx* c, int64_t n, const double* R, hipStream_t s) {
   c->near_ready = true;
   return MBS_OK;
 }
+int near_order(const mbs_ctx* c) { return c->prm.near_order ? c->prm.near_order : 2; }
 void near_apply(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, hipStream_t s) {
   const int* cntp = (const int*)c->near.p;
-  launch_near_apply(R, x, cntp, cntp + n, n, c->ph, y, s, nullptr, 0, c->nt.p);
+  launch_near_apply(R, x, cntp, cntp + n, n, c->ph, y, s, nullptr, 0, c->nt.p, near_order(c));
 }
 
 // Small systems are bound by launch and synchronisation latency, so their Arnoldi steps are
@@ -334,7 +338,8 @@ StepGraphs* step_graphs(mbs_ctx* c, int prec, int64_t n, const double* R, bool p
       (uintptr_t)n, (uintptr_t)R, (uintptr_t)pc, (uintptr_t)t.variant, (uintptr_t)t.block, (uintptr_t)t.tj,
       (uintptr_t)t.wgs, (uintptr_t)c->prm.restart, (uintptr_t)c->V.p, (uintptr_t)c->w.p, (uintptr_t)c->zt.p, (uintptr_t)c->nt.p,
       (uintptr_t)c->H.p, (uintptr_t)c->small.p, (uintptr_t)c->dpart.p, (uintptr_t)c->part.p,
-      (uintptr_t)c->srcbuf.p, (uintptr_t)c->orig.p, (uintptr_t)c->near.p, dbits(c->ph.P), dbits(c->ph.a2),
+      (uintptr_t)c->srcbuf.p, (uintptr_t)c->orig.p, (uintptr_t)c->near.p, (uintptr_t)near_order(c),
+      dbits(c->ph.P), dbits(c->ph.a2),
       dbits(c->ph.gamma), dbits(c->ph.inv_gamma)};
   StepGraphs& G = c->sgraph[prec == MBS_FP64 ? 0 : 1];
   if (key == G.key) return &G;
@@ -839,6 +844,8 @@ void mbs_default_params(mbs_params* p) {
   p->graph = 1;
   p->batch_item = 0;
   p->superposition = 0;
+  p->near_order = 2;
+  p->reserved = 0;
 }
 
 int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {
@@ -1215,7 +1222,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   const bool pc = c->prm.near_cutoff > 0.0;
   const size_t onear = pc ? reserve((size_t)ntot * (kNearCap + 1) * 4) : 0,
                ozt = pc ? reserve(len * 8) : 0, out_ = pc ? reserve(len * 8) : 0,
-               ont = pc ? reserve(len * 8) : 0;
+               ont = pc ? reserve(2 * len * 8) : 0;
   CHK(ensure(c, c->bat, bytes / 8 + 64));
   char* base = (char*)c->bat.p;
   double* Vb = (double*)(base + oV);
@@ -1278,7 +1285,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   auto phase_iter = [&](hipStream_t q) {
     for (int it = 0; it < C; ++it) {
       if (pc) {  // right preconditioning: w = A M^{-1} v_k
-        launch_near_apply(R, Vb, ncnt, nlist, ntot, ph, zt, q, kdev, len, nt);
+        launch_near_apply(R, Vb, ncnt, nlist, ntot, ph, zt, q, kdev, len, nt, near_order(c));
         batched_pack_s(R, zt, nullptr, 0, 0, (Src8<double>*)rec, ntot, q);
         batched_p2(ditems, nitems, item, doff, st.status, kActive, (const Src8<double>*)rec, zt, nullptr, 0, ph, wv,
                    q);
@@ -1303,7 +1310,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
     if (pc) {  // x += M^{-1} (V y) for the configurations that ended a cycle (zero elsewhere)
       batched_fill(ut, 0.0, len, q);
       batched_axpy(Vb, len, nullptr, st.kend, 0, st.y, hs, 1.0, dcid, st.status, kCycleDone, ut, len, q);
-      launch_near_apply(R, ut, ncnt, nlist, ntot, ph, zt, q, nullptr, 0, nt);
+      launch_near_apply(R, ut, ncnt, nlist, ntot, ph, zt, q, nullptr, 0, nt, near_order(c));
       launch_axpby(1.0, zt, 1.0, xv, len, q);
     } else {
       batched_axpy(Vb, len, nullptr, st.kend, 0, st.y, hs, 1.0, dcid, st.status, kCycleDone, xv, len, q);
@@ -1340,6 +1347,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
     memcpy(&tb, &rc_, sizeof tb);
     key.push_back(tb);
     key.push_back((uintptr_t)item);
+    key.push_back((uintptr_t)near_order(c));
     memcpy(&tb, &eta_, sizeof tb);
     key.push_back(tb);
     memcpy(&tb, &a_, sizeof tb);

@@ -79,7 +79,8 @@ void launch_min_dist2(const GridView& g, const double* R, int64_t n, double* out
 void launch_count_nonfinite(const double* a, int64_t len, int* cnt, hipStream_t s);
 
 // near-field preconditioner: neighbour lists within rc (at most kNearCap per sphere) and
-// y = gamma x + gamma^2 K_near x
+// y = gamma sum_{i <= order} (gamma K_near)^i x (order >= 2 needs tmp of 10n doubles; order 1 or
+// tmp == NULL: y = gamma x + gamma^2 K_near x)
 constexpr int kNearCap = 32;
 // (lists from a cell grid of the centres with cell edge >= rc)
 struct GridView;
@@ -88,7 +89,7 @@ void launch_near_build(const GridView& g, const double* R, double rmin, double r
 // (x = x + kdev[0] * ld when kdev is given)
 void launch_near_apply(const double* R, const double* x, const int* cnt, const int* list, int64_t n,
                        const Phys& ph, double* y, hipStream_t s, const int* kdev = nullptr, int64_t ld = 0,
-                       double* tmp = nullptr);
+                       double* tmp = nullptr, int order = 2);
 
 int tile_block(Tile t);                      // receivers per workgroup actually used
 int split_for(int64_t n, Tile t, int tj);    // number of source chunks actually used

@@ -3,12 +3,11 @@
 // The system matrix is A = I/gamma - K with K the all-pairs strain-from-stresslet operator. Its
 // spread around 1/gamma comes mostly from close pairs, so M = I/gamma - K_near, K_near restricted to
 // pairs closer than a cutoff r_c, captures the stiff part. GMRES runs on A M^{-1} with the
-// second-order Neumann approximation M^{-1} v = gamma (v + X v + X^2 v), X = gamma K_near, formed as
-// t = gamma v + gamma^2 K_near v, then M^{-1} v = gamma v + gamma K_near t: two sparse passes over a
-// few neighbours per sphere. It is symmetric and, unlike the first-order truncation, positive
-// definite for any X (1 + x + x^2 >= 3/4 on every eigenvalue x of the symmetric X); on dilute
-// suspensions it reaches the iteration count of the exact near-field inverse. The solution
-// x = M^{-1} u is unchanged; only the iteration count drops.
+// Neumann approximation of even order k, M^{-1} v = gamma (v + X v + ... + X^k v), X = gamma K_near,
+// formed by k sparse passes over a few neighbours per sphere (t = gamma v + gamma^2 K_near v, then
+// k - 1 times t <- gamma v + gamma K_near t). It is symmetric and, unlike odd truncations, positive
+// definite for any X (1 + x + ... + x^k > 0 for every real eigenvalue x of the symmetric X when k
+// is even). The solution x = M^{-1} u is unchanged; only the iteration count drops.
 //
 // Neighbour lists: a search of the cell grid keeps, for each sphere, the kNearCap other spheres of
 // smallest index with 2a <= r < r_c, in index order (deterministic); beyond that capacity the
@@ -153,17 +152,29 @@ void launch_near_build(const GridView& g, const double* R, double rmin, double r
 }
 
 void launch_near_apply(const double* R, const double* x, const int* cnt, const int* list, int64_t n,
-                       const Phys& ph, double* y, hipStream_t s, const int* kdev, int64_t ld, double* tmp) {
+                       const Phys& ph, double* y, hipStream_t s, const int* kdev, int64_t ld, double* tmp,
+                       int order) {
   const double g = ph.gamma;
-  if (tmp) {  // second order: t = gamma x + gamma^2 K x, then y = gamma x + gamma K t
-    hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, kdev, ld, nullptr, cnt, list,
-                       (int)n, ph.P, ph.a2, g, g * g, tmp);
-    hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, kdev, ld, tmp, cnt, list,
-                       (int)n, ph.P, ph.a2, g, g, y);
-  } else {
+  if (!tmp || order < 2) {  // first order: y = gamma x + gamma^2 K x
     hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, kdev, ld, nullptr, cnt, list,
                        (int)n, ph.P, ph.a2, g, g * g, y);
+    return;
   }
+  // order k: t_1 = gamma x + gamma^2 K x, t_j = gamma x + gamma K t_{j-1} (= gamma sum_{i<=j} X^i x),
+  // y = t_k; the partial sums ping-pong between the two halves of tmp
+  double* ta = tmp;
+  double* tb = tmp + 5 * n;
+  hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, kdev, ld, nullptr, cnt, list,
+                     (int)n, ph.P, ph.a2, g, g * g, ta);
+  for (int j = 2; j < order; ++j) {
+    hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, kdev, ld, ta, cnt, list,
+                       (int)n, ph.P, ph.a2, g, g, tb);
+    double* t = ta;
+    ta = tb;
+    tb = t;
+  }
+  hipLaunchKernelGGL(k_near_apply, dim3(nblk(n, 128)), dim3(128), 0, s, R, x, kdev, ld, ta, cnt, list,
+                     (int)n, ph.P, ph.a2, g, g, y);
 }
 
 }  // namespace mbs

@@ -262,8 +262,8 @@ def test_fused_final_pass_matches_separate_passes(ctx, precision, torque):
 
 
 @pytest.mark.parametrize("precision", [mbstokes.MBS_FP64, mbstokes.MBS_MIXED])
-@pytest.mark.parametrize("near_cutoff", [0.0, 6.0])
-def test_solve_graph_replays_equal_eager_solves(ctx, precision, near_cutoff):
+@pytest.mark.parametrize("near_cutoff,near_order", [(0.0, 2), (6.0, 2), (10.0, 4)])
+def test_solve_graph_replays_equal_eager_solves(ctx, precision, near_cutoff, near_order):
     """Small systems replay captured Arnoldi steps from the second solve of one configuration on:
     every replay (with other work and synchronisations in between) equals the eager solve bit for
     bit."""
@@ -272,7 +272,7 @@ def test_solve_graph_replays_equal_eager_solves(ctx, precision, near_cutoff):
     d = mbstokes.to_device(w, DEV)
     args = (d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
     ctx.set_params(graph=0, precision=precision, near_cutoff=near_cutoff, tol=1e-12,
-                   guess=mbstokes.MBS_GUESS_DIAG, restart=6)
+                   guess=mbstokes.MBS_GUESS_DIAG, restart=6, near_order=near_order)
     try:
         V0, W0, S0, st0 = ctx.mbs_solve(*args)
         ctx.set_params(graph=1)
@@ -284,7 +284,7 @@ def test_solve_graph_replays_equal_eager_solves(ctx, precision, near_cutoff):
             assert st["iters"] == st0["iters"] and st["rel_resid"] == st0["rel_resid"], rep
     finally:
         ctx.set_params(graph=1, precision=mbstokes.MBS_FP64, near_cutoff=0.0, tol=1e-10,
-                       guess=mbstokes.MBS_GUESS_ZERO, restart=30)
+                       guess=mbstokes.MBS_GUESS_ZERO, restart=30, near_order=2)
 
 
 def test_solve_user_guess_and_restarts(ctx):
@@ -334,6 +334,11 @@ def test_errors(ctx):
         ctx.set_params(lmax=3)
     assert e.value.code == mbstokes.MBS_EUNSUPPORTED
     ctx.params.lmax = 2
+    for bad in (1, 3, 10, -2):
+        with pytest.raises(mbstokes.MbsError) as e:
+            ctx.set_params(near_order=bad)
+        assert e.value.code == mbstokes.MBS_EINVAL
+    ctx.params.near_order = 2
     lib = mbstokes.load()
     rc = lib.mbs_matvec(ctx.h, 0, None, None, None, 0, None)
     assert rc == mbstokes.MBS_EINVAL
@@ -486,8 +491,8 @@ def test_batched_torque_trace_mode_and_restarts(ctx):
         assert stats[b]["iters"] > 4          # went through restarts
 
 
-@pytest.mark.parametrize("graph", [0, 1])
-def test_batched_preconditioned_matches_oracle_in_fewer_iterations(ctx, graph):
+@pytest.mark.parametrize("graph,near_order", [(0, 2), (1, 2), (1, 4)])
+def test_batched_preconditioned_matches_oracle_in_fewer_iterations(ctx, graph, near_order):
     """Near-field right preconditioning inside the batch (lists within each configuration, restarts
     included): same solutions as the oracle, fewer iterations than without it."""
     print(f"batched preconditioned graph={graph}", flush=True)
@@ -497,11 +502,11 @@ def test_batched_preconditioned_matches_oracle_in_fewer_iterations(ctx, graph):
     ctx.set_params(tol=1e-12, graph=graph, restart=5)
     try:
         _, _, _, plain, _ = ctx.mbs_solve_batched(*args)
-        ctx.set_params(near_cutoff=7.0)
+        ctx.set_params(near_cutoff=7.0, near_order=near_order)
         Sig = torch.empty((int(off[-1]), 5), dtype=torch.float64, device=DEV)
         V, W, S, stats, lat = ctx.mbs_solve_batched(*args, Sigma=Sig)
     finally:
-        ctx.set_params(tol=1e-10, graph=1, restart=30, near_cutoff=0.0)
+        ctx.set_params(tol=1e-10, graph=1, restart=30, near_cutoff=0.0, near_order=2)
     for b, w in enumerate(ws):
         ref = galerkin.solve(w)
         sl = slice(off[b], off[b + 1])
@@ -558,7 +563,8 @@ def test_matvec_full_size_sampled_rows(ctx):
 
 
 # ---------------------------------------------------------------- near-field preconditioner
-def test_precond_apply_matches_oracle(ctx):
+@pytest.mark.parametrize("order", [2, 4, 8])
+def test_precond_apply_matches_oracle(ctx, order):
     w = _workload(400, seed=21)
     prm = galerkin.Params(eta=w.eta, a=w.a)
     rc = 7.0
@@ -569,11 +575,16 @@ def test_precond_apply_matches_oracle(ctx):
     assert near.sum(1).max() <= 32
     Kn = K * np.kron(near, np.ones((5, 5)))
     g = galerkin.constants(prm)["gamma"]
-    kx = Kn @ x.ravel()
-    want = (g * x.ravel() + g * g * kx + g ** 3 * (Kn @ kx)).reshape(-1, 5)
-    ctx.set_params(near_cutoff=rc)
-    got = ctx.mbs_precond_apply(_t(w.R), _t(x))
-    ctx.set_params(near_cutoff=0.0)
+    term, want = x.ravel().copy(), x.ravel().copy()
+    for _ in range(order):   # gamma sum_{i <= order} (gamma K_near)^i x
+        term = g * (Kn @ term)
+        want = want + term
+    want = (g * want).reshape(-1, 5)
+    ctx.set_params(near_cutoff=rc, near_order=order)
+    try:
+        got = ctx.mbs_precond_apply(_t(w.R), _t(x))
+    finally:
+        ctx.set_params(near_cutoff=0.0, near_order=2)
     assert _maxrel(got, want) < 1e-13
 
 
@@ -640,11 +651,13 @@ def test_preconditioned_solve_matches_oracle_in_fewer_iterations(ctx, precision)
     ref = galerkin.solve(w)
     d = mbstokes.to_device(w, DEV)
     its = {}
-    for rc in (0.0, 6.0):
-        ctx.set_params(tol=1e-11, precision=precision, near_cutoff=rc, guess=mbstokes.MBS_GUESS_DIAG)
+    for rc, order in ((0.0, 2), (6.0, 2), (10.0, 4)):
+        ctx.set_params(tol=1e-11, precision=precision, near_cutoff=rc, guess=mbstokes.MBS_GUESS_DIAG,
+                       near_order=order)
         V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
         tol = 1e-10 if precision == mbstokes.MBS_FP64 else 1e-9
         assert _rel(V, ref["V"]) < tol and _rel(W, ref["W"]) < tol and _rel(S, ref["S"]) < tol
         its[rc] = st["iters"]
-    ctx.set_params(tol=1e-10, precision=mbstokes.MBS_FP64, near_cutoff=0.0, guess=mbstokes.MBS_GUESS_ZERO)
-    assert its[6.0] < its[0.0], its
+    ctx.set_params(tol=1e-10, precision=mbstokes.MBS_FP64, near_cutoff=0.0, guess=mbstokes.MBS_GUESS_ZERO,
+                   near_order=2)
+    assert its[6.0] < its[0.0] and its[10.0] <= its[6.0], its
