@@ -422,3 +422,37 @@ def test_knn_and_features_brute_force():
         j = nb[i, 0]
         r = np.linalg.norm(R[j] - R[i])
         assert np.allclose(f[i, :5], list((R[j] - R[i]) / r) + [1 / r, p[j] @ p[i]], rtol=1e-15)
+
+
+def test_lone_sphere_flow_amplitudes_match_the_single_layer_constants():
+    """The lone-sphere flows are fixed here by the boundary condition, not by the paper's constants.
+    Written in the paper's sigma = 0 form u = -(a^l / 8 pi eta) F^l grad^l G . Q (section III), their
+    amplitudes are the single-layer constants the paper prints: Sigma = -C_20 s for the stresslet and
+    |Q^(30)| = (C_30 / a^2) |gamma| for the septlet."""
+    rng = np.random.default_rng(31)
+    x = _rand_sep(rng, 4)
+    # stresslet: a lone sphere's flow stresslet is Sigma = -gamma s (the oracle's self term), and
+    # gamma is the single-layer C_20
+    C20 = GOLD["stresslet_single_layer_C20_over_pi_eta_a3"]["value"] * np.pi * ETA * A ** 3
+    assert abs(galerkin.constants(PRM)["gamma"] - C20) < 1e-12 * C20
+    # septlet: per unit gamma the oracle's flow is (7 a^5 / 48) F^2 grad grad G : gamma; matching
+    # -(a^2 / 8 pi eta) F^2 grad grad G : Q gives |Q| = 8 pi eta (7 a^3 / 48) |gamma|
+    C30 = GOLD["septlet_single_layer_C30_over_pi_eta_a5"]["value"] * np.pi * ETA * A ** 5
+    uG = greens.flow("SEPT", x, A, ETA)
+    uG2 = greens.flow("SEPT", 2.0 * x, A, ETA)
+    # the far field of F^2 grad grad G decays as r^-3: recover the amplitude from the r^-3 part
+    # (two radii, the r^-5 finite-size part removed) and compare with the unit-amplitude form
+    far = (uG2 * 2.0 ** 5 - uG) / (2.0 ** 2 - 1.0)          # r^-3 part at radius |x|
+    ref = np.zeros_like(uG)
+    for q in range(10):
+        T = _unit_stf3(q)
+        for p_, xx in enumerate(x):
+            r = np.linalg.norm(xx)
+            # grad grad of G_il contracted with T_ljk, leading (r^-3) part: -3 T:xx/r^5 + 15 x (T xxx)/r^7
+            Txx = np.einsum("ijk,j,k->i", T, xx, xx)
+            ref[p_, :, q] = -3 * Txx / r ** 5 + 15 * xx * (Txx @ xx) / r ** 7
+    amp = far / np.where(np.abs(ref) > 1e-12, ref, np.nan)
+    amp = amp[np.isfinite(amp)]
+    assert np.allclose(amp, amp[0], rtol=1e-9, atol=0)
+    Q_per_gamma = 8 * np.pi * ETA * amp[0] / A ** 2        # |Q| per unit gamma
+    assert abs(Q_per_gamma - C30 / A ** 2) < 1e-10 * C30 / A ** 2
