@@ -85,6 +85,12 @@ struct mbs_ctx {
   hipStream_t bstream = nullptr;
   hipGraphExec_t bgraph[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<uintptr_t> bkey;
+  // descriptors of the last batch uploaded to the workspace (offsets, item size, workspace base):
+  // an identical next batch reuses them instead of rebuilding and re-uploading
+  std::vector<int64_t> bdesc_off;
+  int bdesc_item = 0, bdesc_nitems = 0;
+  const void* bdesc_ptr[3] = {nullptr, nullptr, nullptr};  // where they were uploaded
+  uint64_t bdesc_gen = 0;  // bumped whenever a batch with other offsets or item size is uploaded
 };
 
 namespace {
@@ -1193,16 +1199,23 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   if (bad) return set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
   if (c->prm.precision != MBS_FP64)
     return set_err(c, MBS_EUNSUPPORTED, "batched solves run in binary64 only");
-  // host descriptors: configuration offsets, work items (configuration, 64-receiver tile), owner map
+  // host descriptors: configuration offsets, work items (configuration, receiver tile), owner map;
+  // built and uploaded unless the previous batch had the same offsets, item size and workspace
   const int m = c->prm.restart;
-  std::vector<int> off(nconf + 1), cid(ntot);
+  std::vector<int> off, cid;
   std::vector<int2> items;
-  for (int b = 0; b <= nconf; ++b) off[b] = (int)offsets[b];
   const int item = c->prm.batch_item ? c->prm.batch_item : c->bitem;
-  for (int b = 0; b < nconf; ++b)
-    for (int r = off[b]; r < off[b + 1]; ++r) cid[r] = b;
-  batch_items(off, nconf, item, items);
-  const int nitems = (int)items.size();
+  const bool same_desc = c->bdesc_item == item && (int64_t)c->bdesc_off.size() == (int64_t)nconf + 1 &&
+                         std::equal(c->bdesc_off.begin(), c->bdesc_off.end(), offsets);
+  if (!same_desc) {
+    off.resize(nconf + 1);
+    cid.resize(ntot);
+    for (int b = 0; b <= nconf; ++b) off[b] = (int)offsets[b];
+    for (int b = 0; b < nconf; ++b)
+      for (int r = off[b]; r < off[b + 1]; ++r) cid[r] = b;
+    batch_items(off, nconf, item, items);
+  }
+  const int nitems = same_desc ? c->bdesc_nitems : (int)items.size();
   // workspace (bytes, 256-aligned pieces)
   const int64_t len = 5 * ntot64;
   const int hs = m + 2;
@@ -1223,7 +1236,10 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   const size_t onear = pc ? reserve((size_t)ntot * (kNearCap + 1) * 4) : 0,
                ozt = pc ? reserve(len * 8) : 0, out_ = pc ? reserve(len * 8) : 0,
                ont = pc ? reserve(2 * len * 8) : 0;
+  const void* bat0 = c->bat.p;
+  const size_t batcap0 = c->bat.cap;
   CHK(ensure(c, c->bat, bytes / 8 + 64));
+  if (c->bat.p != bat0 || c->bat.cap != batcap0) c->bdesc_off.clear();  // reallocated: contents gone
   char* base = (char*)c->bat.p;
   double* Vb = (double*)(base + oV);
   double *wv = (double*)(base + ow), *xv = (double*)(base + ox), *bv = (double*)(base + ob),
@@ -1257,9 +1273,29 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   double* nt = pc ? (double*)(base + ont) : nullptr;
   double* ut = pc ? (double*)(base + out_) : nullptr;
   const double near_rc = c->prm.near_cutoff, near_rmin = 2.0 * c->prm.a;
-  HIPCHK(c, hipMemcpyAsync(doff, off.data(), (nconf + 1) * sizeof(int), hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(ditems, items.data(), nitems * sizeof(int2), hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(dcid, cid.data(), ntot * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!same_desc || c->bdesc_off.empty() || c->bdesc_ptr[0] != (void*)doff || c->bdesc_ptr[1] != (void*)ditems ||
+      c->bdesc_ptr[2] != (void*)dcid) {
+    if (same_desc) {  // same batch, moved or lost device copies: rebuild the host copies first
+      off.resize(nconf + 1);
+      cid.resize(ntot);
+      for (int b = 0; b <= nconf; ++b) off[b] = (int)offsets[b];
+      for (int b = 0; b < nconf; ++b)
+        for (int r = off[b]; r < off[b + 1]; ++r) cid[r] = b;
+      batch_items(off, nconf, item, items);
+    }
+    c->bdesc_off.clear();  // invalid until the uploads below have completed
+    HIPCHK(c, hipMemcpyAsync(doff, off.data(), (nconf + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(ditems, items.data(), nitems * sizeof(int2), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(dcid, cid.data(), ntot * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));  // the host vectors go out of scope with this call
+    if (!same_desc) ++c->bdesc_gen;
+    c->bdesc_off.assign(offsets, offsets + nconf + 1);
+    c->bdesc_item = item;
+    c->bdesc_nitems = nitems;
+    c->bdesc_ptr[0] = doff;
+    c->bdesc_ptr[1] = ditems;
+    c->bdesc_ptr[2] = dcid;
+  }
   if (!c->bstream) HIPCHK(c, hipStreamCreateWithFlags(&c->bstream, hipStreamNonBlocking));
   hipStream_t bs = c->bstream;
   // the batch stream waits for the caller's stream (uploads above, caller's producers)
@@ -1347,6 +1383,8 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
     memcpy(&tb, &rc_, sizeof tb);
     key.push_back(tb);
     key.push_back((uintptr_t)item);
+    key.push_back((uintptr_t)nitems);
+    key.push_back((uintptr_t)c->bdesc_gen);  // the captured launches depend on the batch's items
     key.push_back((uintptr_t)near_order(c));
     memcpy(&tb, &eta_, sizeof tb);
     key.push_back(tb);

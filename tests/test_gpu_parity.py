@@ -547,6 +547,35 @@ def test_batched_graph_replays_equal_direct_launches(ctx):
         assert _rel(V0[off[b]:off[b + 1]], ref["V"]) < 1e-9
 
 
+def test_batched_graphs_follow_new_offsets(ctx):
+    """Two batches with the same number of configurations and spheres but other sizes (so other
+    work items), alternated: with graphs and cached descriptors every call equals the direct
+    launches of the same batch, bit for bit."""
+    print("batched alternating offsets", flush=True)
+    ctx.set_params(batch_item=64)
+    try:
+        batches = []
+        for sizes, seed in (((64, 300), 7100), ((100, 264), 7200)):
+            ws = [_workload(n, seed=seed + n, v3t=0.0, torque=False) for n in sizes]
+            off, cat = _batch(ws)
+            batches.append((ws, (off, cat("R"), cat("v1s"), cat("v2s"), None, cat("Fe"), None)))
+        ref = []
+        ctx.set_params(graph=0)
+        for _, args in batches:
+            V, W, S, _, _ = ctx.mbs_solve_batched(*args)
+            ref.append((V.clone(), W.clone(), S.clone()))
+        ctx.set_params(graph=1)
+        for k in (0, 1, 0, 1, 1, 0):
+            V, W, S, _, _ = ctx.mbs_solve_batched(*batches[k][1])
+            assert torch.equal(V, ref[k][0]) and torch.equal(W, ref[k][1]) and torch.equal(S, ref[k][2]), k
+        for k, (ws, args) in enumerate(batches):
+            off = args[0]
+            for b, w in enumerate(ws):
+                assert _rel(ref[k][0][off[b]:off[b + 1]], galerkin.solve(w)["V"]) < 1e-9
+    finally:
+        ctx.set_params(graph=1, batch_item=0)
+
+
 # ---------------------------------------------------------------- full size, sampled
 @pytest.mark.slow
 def test_matvec_full_size_sampled_rows(ctx):
