@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--skip-stepper", action="store_true")
     ap.add_argument("--skip-kernels", action="store_true", help="skip the per-size pair-pass timings")
     ap.add_argument("--stepper-steps", type=int, default=1000)
+    ap.add_argument("--profile-passes", action="store_true",
+                    help="short run for hardware counters: one launch of every binary64 pass kernel at N")
     ap.add_argument("--profile-matvec", action="store_true",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then --steps "
                          "binary64 and --steps binary32 operator applications at the autotuned shapes")
@@ -93,6 +95,32 @@ def profile_matvec(a, w):
     ctx.close()
     print(json.dumps({"mode": "profile-matvec", "n": w.n, "tiles": [t64, t32], "ms_per_launch": times,
                       "copy_bytes": 2 * src.numel() * 8}), flush=True)
+
+
+def profile_passes(a, w):
+    """Short run for hardware-counter passes over the binary64 pass kernels at N: right-hand side,
+    outputs, flow at N field points, the higher slip modes' three passes, and one mixed-precision
+    preconditioned solve (its fused final residual + outputs pass). Default launch shapes."""
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+    d = mbstokes.to_device(w, "cuda:0")
+    g, ps, l = inputs.higher_slip_modes(w.p, 1.0, 1.0, 1.0)
+    f = lambda v: torch.as_tensor(v, dtype=torch.float64).contiguous().to("cuda:0")
+    hm = dict(gam=f(g), psi=f(ps), lam=f(l))
+    ctx = mbstokes.Context(0)
+    sig = torch.randn((w.n, 5), dtype=torch.float64, device="cuda:0")
+    gen = torch.Generator(device="cuda:0").manual_seed(5)
+    X = (torch.rand((w.n, 3), dtype=torch.float64, device="cuda:0", generator=gen) - 0.5) * a.side
+    ctx.mbs_rhs_ex(d["R"], d["v2s"], None, Fe=d["Fe"], **hm)
+    ctx.mbs_outputs_ex(d["R"], sig, d["v1s"], d["v2s"], None, Fe=d["Fe"], **hm)
+    ctx.mbs_flow_ex(X, d["R"], sig, Fe=d["Fe"], **hm)
+    ctx.set_params(precision=mbstokes.MBS_MIXED, tol=1e-10, near_cutoff=a.near_cutoff, near_order=a.near_order)
+    V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"mode": "profile-passes", "n": w.n, "solve_iters": st["iters"], "out_fused": st["out_fused"]}),
+          flush=True)
 
 
 def kernel_source_hash():
@@ -448,6 +476,9 @@ def main():
     from paper_1411_0278_amd import inputs, mbstokes
     print(f"bench: generating workload n={a.n} side={a.side} seed={a.seed}", file=sys.stderr, flush=True)
     w = inputs.trap_workload(a.n, a.side, a.seed)
+    if a.profile_passes:
+        profile_passes(a, w)
+        return
     if a.profile_matvec:
         profile_matvec(a, w)
         return
