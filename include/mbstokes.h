@@ -255,12 +255,15 @@ int mbs_step(mbs_ctx* ctx, int64_t n, double* R, double* p, double k_trap, const
              double dt, int32_t nsteps, int32_t order, double* hist, int32_t hist_valid,
              mbs_stats* per_step, double* min_dist, void* stream);
 
-/* Many independent configurations in one call (binary64, zero initial guess, near-field
-   preconditioner when params.near_cutoff > 0). Configuration b owns
+/* Many independent configurations in one call (binary64 only: params.precision must be MBS_FP64,
+   else MBS_EUNSUPPORTED; zero initial guess; near-field preconditioner of order params.near_order
+   when params.near_cutoff > 0). Configuration b owns
    rows offsets[b] .. offsets[b+1]-1 of the concatenated device arrays (same meaning as in mbs_solve).
    offsets: HOST array [nconf + 1], offsets[0] = 0, strictly increasing. All configurations advance
    together: each pass (right-hand side, operator, Gram-Schmidt, Givens, outputs) is one launch over
-   every configuration, decomposed into (configuration, 64-receiver tile) work items; converged
+   every configuration, decomposed into (configuration, receiver tile) work items, tiles of
+   params.batch_item receivers or the size mbs_autotune_batched picked (largest configurations
+   first); converged
    configurations drop out of later passes. With params.graph the phases are captured once per batch
    shape into HIP graphs on a stream owned by the context and replayed (the iteration graph holds
    four Arnoldi steps); the call synchronises with `stream` on entry and exit.
