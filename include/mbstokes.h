@@ -21,6 +21,8 @@
  *        V_n = V^a_n + F^e_n/(6 pi eta a) + sum_{m != n} U[F, T, Sigma, d],
  *        Omega_n = T^e_n/(8 pi eta a^3) + sum_{m != n} W[F, T, Sigma],
  *     with V^a_n = -V^(1s)_n, and the traction stresslet S_n = Sigma_n + (8/3) pi eta a^3 s_n.
+ *   - The _ex entry points add the septlet, vortlet and spinlet slip modes of the
+ *     minimal truncation (section IV) as further fixed sources in E, U and W.
  *
  * Conventions for every entry point below:
  *   - Arrays are caller-owned, contiguous, row-major, particle-major, IEEE
