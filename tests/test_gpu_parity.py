@@ -591,6 +591,30 @@ def test_matvec_full_size_sampled_rows(ctx):
     assert _rel(y32[rows], want) < 5e-5
 
 
+@pytest.mark.slow
+def test_operator_full_size_is_symmetric_positive_definite(ctx):
+    """Properties that hold at any size (reciprocity of the Green's function, section III): at
+    N = 10^5 the binary64 operator satisfies x.(A y) = y.(A x) to rounding and x.(A x) > 0 with
+    x.(A x) / |x|^2 inside the interval the one-body term 1/gamma and the pair coupling allow; the
+    binary32 operator is symmetric to its own accuracy."""
+    w = inputs.config2()
+    rng = np.random.default_rng(11)
+    x, y = rng.standard_normal((w.n, 5)), rng.standard_normal((w.n, 5))
+    R = _t(w.R)
+    Ax = ctx.mbs_matvec(R, _t(x)).cpu().numpy()
+    Ay = ctx.mbs_matvec(R, _t(y)).cpu().numpy()
+    xay, yax = float(np.sum(x * Ay)), float(np.sum(y * Ax))
+    scale = np.linalg.norm(x) * np.linalg.norm(Ay)
+    print(f"symmetry {abs(xay - yax) / scale:.2e}", flush=True)
+    assert abs(xay - yax) <= 1e-13 * scale
+    gam = galerkin.constants(galerkin.Params(eta=w.eta, a=w.a))["gamma"]
+    rayleigh = float(np.sum(x * Ax)) / float(np.sum(x * x))
+    assert 0.3 / gam < rayleigh < 3.0 / gam, rayleigh * gam
+    Ax32 = ctx.mbs_matvec(R, _t(x), precision=mbstokes.MBS_FP32).cpu().numpy()
+    Ay32 = ctx.mbs_matvec(R, _t(y), precision=mbstokes.MBS_FP32).cpu().numpy()
+    assert abs(float(np.sum(x * Ay32)) - float(np.sum(y * Ax32))) <= 1e-5 * scale
+
+
 # ---------------------------------------------------------------- near-field preconditioner
 @pytest.mark.parametrize("order", [2, 4, 8])
 def test_precond_apply_matches_oracle(ctx, order):
