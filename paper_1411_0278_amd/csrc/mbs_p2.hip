@@ -206,22 +206,82 @@ __global__ void __launch_bounds__(kMaxBlock)
 }
 
 // ---------------------------------------------------------------- LDS variant
+// binary32 pair arithmetic of the LDS kernel. On gfx950 a binary32 VOP2 instruction whose
+// operands are all VGPRs issues at twice the rate of one that reads an SGPR or a literal or that
+// needs the VOP3 form (a source negation, an fma whose addend is not its destination). So the
+// record carries S_zz (w = S x then needs no negation), the three constants sit in VGPRs, and the
+// raw moments accumulated are those of v/15, for which c1/15 = 1.6a^2/r^7 - 0.4/r^5 and
+// c2/15 = u - 2.8a^2 u/r^2 with u = q/r^7 are plain multiply and multiply-add chains; the factor 15
+// is restored once per receiver. The r^-5 S sums are not scaled.
+struct SrcF9 {
+  float x, y, z, sxx, syy, szz, sxy, sxz, syz;
+};
+
+struct KF32 {
+  float a16, n28, n04;  // 1.6 a^2, -2.8 a^2, -0.4
+};
+
+template <bool SELF>
+__device__ __forceinline__ void p2_pair_f32(const SrcF9& s, float xi, float yi, float zi, const KF32& k,
+                                            Mom<float>& m) {
+  const float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+  const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  const float ri = SELF ? rinv_or_zero(r2) : rsq_nr(r2);
+  const float ri2 = ri * ri;
+  const float ri5 = ri2 * ri2 * ri;
+  const float ri7 = ri5 * ri2;
+  const float wx = fmaf(s.sxx, dx, fmaf(s.sxy, dy, s.sxz * dz));
+  const float wy = fmaf(s.sxy, dx, fmaf(s.syy, dy, s.syz * dz));
+  const float wz = fmaf(s.sxz, dx, fmaf(s.syz, dy, s.szz * dz));
+  const float q = fmaf(dx, wx, fmaf(dy, wy, dz * wz));
+  const float c1 = fmaf(k.a16, ri7, k.n04 * ri5);
+  const float u = q * ri7;
+  const float c2 = fmaf(k.n28, u * ri2, u);
+  const float vx = fmaf(c1, wx, c2 * dx);
+  const float vy = fmaf(c1, wy, c2 * dy);
+  const float vz = fmaf(c1, wz, c2 * dz);
+  m.pxx = fmaf(dx, vx, m.pxx);
+  m.pyy = fmaf(dy, vy, m.pyy);
+  m.pzz = fmaf(dz, vz, m.pzz);
+  m.qxy = fmaf(dx, vy, fmaf(dy, vx, m.qxy));
+  m.qxz = fmaf(dx, vz, fmaf(dz, vx, m.qxz));
+  m.qyz = fmaf(dy, vz, fmaf(dz, vy, m.qyz));
+  m.t0 = fmaf(ri5, s.sxx, m.t0);
+  m.t1 = fmaf(ri5, s.syy, m.t1);
+  m.t2 = fmaf(ri5, s.sxy, m.t2);
+  m.t3 = fmaf(ri5, s.sxz, m.t3);
+  m.t4 = fmaf(ri5, s.syz, m.t4);
+}
+
+template <typename T>
+struct LdsRec {
+  using type = Src8<T>;
+};
+template <>
+struct LdsRec<float> {
+  using type = SrcF9;
+};
+
 template <typename T, int TJ>
 __global__ void __launch_bounds__(kMaxBlock)
     k_p2_lds(const double* __restrict__ R, const double* __restrict__ X, double* __restrict__ out,
              int n, int chunk, double P, double a2, double inv_gamma, int direct) {
-  __shared__ Src8<T> tile[TJ];
+  constexpr bool f32 = sizeof(T) == 4;
+  using Rec = typename LdsRec<T>::type;
+  __shared__ Rec tile[TJ];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int ii = i < n ? i : n - 1;
   const int b0 = blockIdx.x * blockDim.x;
   const int b1 = min(n, b0 + (int)blockDim.x);
   // binary32 re-centres on the workgroup's first receiver; binary64 keeps lab coordinates
-  const bool f32 = sizeof(T) == 4;
   const double ox = f32 ? R[3 * (int64_t)b0] : 0.0, oy = f32 ? R[3 * (int64_t)b0 + 1] : 0.0,
                oz = f32 ? R[3 * (int64_t)b0 + 2] : 0.0;
   const T xi = (T)(R[3 * (int64_t)ii] - ox), yi = (T)(R[3 * (int64_t)ii + 1] - oy),
           zi = (T)(R[3 * (int64_t)ii + 2] - oz);
   const T A24 = (T)(24.0 * a2), A42 = (T)(42.0 * a2);
+  KF32 k{(float)(1.6 * a2), (float)(-2.8 * a2), -0.4f};
+  // an empty asm with VGPR operands pins the constants to VGPRs (no SGPR or literal operand)
+  if constexpr (f32) asm volatile("" : "+v"(k.a16), "+v"(k.n28), "+v"(k.n04));
   const int j0 = blockIdx.y * chunk;
   const int j1 = min(n, j0 + chunk);
   Total<T> tot;
@@ -232,7 +292,7 @@ __global__ void __launch_bounds__(kMaxBlock)
       const int j = jt + t;
       double sxx, syy, sxy, sxz, syz;
       basis_to_cart(X + 5 * (int64_t)j, sxx, syy, sxy, sxz, syz);
-      Src8<T> r;
+      Rec r;
       r.x = (T)(R[3 * (int64_t)j] - ox);
       r.y = (T)(R[3 * (int64_t)j + 1] - oy);
       r.z = (T)(R[3 * (int64_t)j + 2] - oz);
@@ -241,23 +301,37 @@ __global__ void __launch_bounds__(kMaxBlock)
       r.sxy = (T)sxy;
       r.sxz = (T)sxz;
       r.syz = (T)syz;
+      if constexpr (f32) r.szz = (float)(-(sxx + syy));
       tile[t] = r;
     }
     __syncthreads();
     Mom<T> m;
     const bool self = jt < b1 && jt + cnt > b0;  // uniform
-    if (self) {
+    if constexpr (f32) {
+      if (self) {
 #pragma unroll 8
-      for (int jj = 0; jj < cnt; ++jj) p2_pair<T, true>(tile[jj], xi, yi, zi, A24, A42, m);
+        for (int jj = 0; jj < cnt; ++jj) p2_pair_f32<true>(tile[jj], xi, yi, zi, k, m);
+      } else {
+#pragma unroll 8
+        for (int jj = 0; jj < cnt; ++jj) p2_pair_f32<false>(tile[jj], xi, yi, zi, k, m);
+      }
     } else {
+      if (self) {
 #pragma unroll 8
-      for (int jj = 0; jj < cnt; ++jj) p2_pair<T, false>(tile[jj], xi, yi, zi, A24, A42, m);
+        for (int jj = 0; jj < cnt; ++jj) p2_pair<T, true>(tile[jj], xi, yi, zi, A24, A42, m);
+      } else {
+#pragma unroll 8
+        for (int jj = 0; jj < cnt; ++jj) p2_pair<T, false>(tile[jj], xi, yi, zi, A24, A42, m);
+      }
     }
     tot.add(m);
   }
   if (i >= n) return;
   double v[11];
   tot.get(v);
+  if constexpr (f32)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] *= 15.0;
   p2_store(v, i, n, X, out, P, a2, inv_gamma, direct);
 }
 
