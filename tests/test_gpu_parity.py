@@ -344,6 +344,44 @@ def test_errors(ctx):
     assert rc == mbstokes.MBS_EINVAL
 
 
+def test_size_limits_are_rejected_before_any_work(ctx):
+    """Every entry point refuses a size whose element count would overflow the 32-bit indexing of
+    its kernels, with MBS_EINVAL and a message, before it touches memory or launches anything (the
+    pointers passed are those of a 4-sphere buffer, valid but far too small)."""
+    import ctypes
+    lib = mbstokes.load()
+    buf = torch.zeros(4 * 80, dtype=torch.float64, device=DEV)
+    b = ctypes.c_void_p(buf.data_ptr())
+    big6, big10, big12, big80 = 2**31 // 6 + 1, 2**31 // 10 + 1, 2**31 // 12 + 1, 2**31 // 80 + 1
+    off = (ctypes.c_int64 * 2)(0, 2**31 // 20 + 1)
+    chosen = (ctypes.c_int32 * 2)()
+    coef = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    calls = {
+        "solve": lambda: lib.mbs_solve(ctx.h, big6, *[b] * 12, None, None),
+        "matvec": lambda: lib.mbs_matvec(ctx.h, big6, b, b, ctypes.c_void_p(buf.data_ptr() + 8), 0, None),
+        "rhs": lambda: lib.mbs_rhs(ctx.h, big10, *[b] * 6, None),
+        "outputs": lambda: lib.mbs_outputs(ctx.h, big10, *[b] * 10, None),
+        "flow m": lambda: lib.mbs_flow(ctx.h, big12, b, 4, *[b] * 6, None),
+        "flow n": lambda: lib.mbs_flow(ctx.h, 4, b, big10, *[b] * 6, None),
+        "step": lambda: lib.mbs_step(ctx.h, big6, b, b, 0.5, coef, 0.01, 1, 2, None, 0, None, None, None),
+        "autotune": lambda: lib.mbs_autotune(ctx.h, big6, b, None, chosen, None),
+        "precond": lambda: lib.mbs_precond_apply(ctx.h, big6, b, b, ctypes.c_void_p(buf.data_ptr() + 8), None),
+        "features": lambda: lib.mbs_features(ctx.h, big80, b, b, b, b, None),
+        "warmstart forward": lambda: lib.mbs_warmstart_forward(ctx.h, big80, b, b, None),
+        "initial guess": lambda: lib.mbs_initial_guess(ctx.h, big80, *[b] * 6, mbstokes.MBS_GUESS_DIAG, b, None),
+        "warmstart target": lambda: lib.mbs_warmstart_target(ctx.h, big80, *[b] * 7, None),
+        "batched": lambda: lib.mbs_solve_batched(ctx.h, 1, off, *[b] * 10, None, None, None),
+        "autotune batched": lambda: lib.mbs_autotune_batched(ctx.h, 1, off, b, chosen, None, None),
+    }
+    for name, call in calls.items():
+        print(f"size limit: {name}", flush=True)
+        assert call() == mbstokes.MBS_EINVAL, name
+        msg = lib.mbs_last_error(ctx.h).decode()
+        assert "too large" in msg or "too many" in msg, (name, msg)
+    torch.cuda.synchronize()
+    assert not buf.any()  # nothing was written
+
+
 # ---------------------------------------------------------------- time stepping
 def test_stepper_matches_oracle(ctx):
     w = _workload(64, seed=14, torque=False)
