@@ -91,10 +91,12 @@ typedef struct mbs_params {
   int32_t restart;       /* GMRES restart length m, 1..64 */
   int32_t precision;     /* MBS_FP64 or MBS_MIXED */
   int32_t guess;         /* MBS_GUESS_* */
-  int32_t check_overlap; /* nonzero: mbs_solve fails with MBS_EOVERLAP if some |R_n - R_m| < 2a;
+  int32_t check_overlap; /* nonzero: mbs_solve fails with MBS_EOVERLAP if some |R_n - R_m| < 2a
+                            (two distinct spheres at one centre included);
                             zero: overlapping spheres are solved as given (the pair blocks hold for
-                            any r > 0) and two coincident centres (r = 0) contribute nothing to each
-                            other, as the n == m term */
+                            any r > 0); two distinct spheres at one centre (r = 0) have infinite
+                            pair blocks, so the pair passes return non-finite values for them and
+                            mbs_solve ends with MBS_ENOCONV and a non-finite rel_resid */
   int32_t tile;          /* pair-kernel launch shape: 0 = autotuned (or default), k > 0 = entry k-1
                             of the candidate table (see mbs_autotune) */
   int32_t graph;         /* 1 (default): mbs_solve_batched captures its phases in HIP graphs and

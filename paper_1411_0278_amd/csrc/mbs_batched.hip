@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(kItemMax)
   const double A8 = 8.0 * a2, B16 = -3.2 * a2;
   Mom6 m;
 #pragma unroll 2
-  for (int j = o0; j < o1; ++j) p1_pair<HAS_T, HAS_D>(rec[j], xi, yi, zi, A8, B16, m);
+  for (int j = o0; j < o1; ++j) p1_pair<true, HAS_T, HAS_D>(rec[j], xi, yi, zi, A8, B16, m);
   if (i >= o1) return;
   double e[5];
   mom6_to_basis(m, e);
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(kItemMax)
   const double A2_2 = 2.0 * a2, A2_23 = 2.0 * a2 / 3.0, A8 = 8.0 * a2, B16 = -3.2 * a2;
   UW a;
 #pragma unroll 2
-  for (int j = o0; j < o1; ++j) p3_pair<HAS_T, HAS_D>(rec[j], xi, yi, zi, A2_2, A2_23, A8, B16, a);
+  for (int j = o0; j < o1; ++j) p3_pair<true, HAS_T, HAS_D>(rec[j], xi, yi, zi, A2_2, A2_23, A8, B16, a);
   if (i >= o1) return;
   const double u[6] = {a.ux, a.uy, a.uz, a.wx, a.wy, a.wz};
 #pragma unroll

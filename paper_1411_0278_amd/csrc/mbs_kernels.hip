@@ -52,6 +52,8 @@ __global__ void __launch_bounds__(kMaxBlock)
   __shared__ RecF tile[TJ];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int ii = i < n ? i : n - 1;
+  const int b0 = blockIdx.x * blockDim.x;
+  const int b1 = min(n, b0 + (int)blockDim.x);
   const double xi = R[3 * ii], yi = R[3 * ii + 1], zi = R[3 * ii + 2];
   const int j0 = blockIdx.y * chunk;
   const int j1 = min(n, j0 + chunk);
@@ -86,8 +88,13 @@ __global__ void __launch_bounds__(kMaxBlock)
       tile[t] = rc;
     }
     __syncthreads();
+    if (jt < b1 && jt + cnt > b0) {  // (uniform) the tile may hold a receiver of this workgroup
 #pragma unroll 2
-    for (int jj = 0; jj < cnt; ++jj) p1_pair<HAS_T, HAS_D>(tile[jj], xi, yi, zi, A8, B16, m);
+      for (int jj = 0; jj < cnt; ++jj) p1_pair<true, HAS_T, HAS_D>(tile[jj], xi, yi, zi, A8, B16, m);
+    } else {
+#pragma unroll 2
+      for (int jj = 0; jj < cnt; ++jj) p1_pair<false, HAS_T, HAS_D>(tile[jj], xi, yi, zi, A8, B16, m);
+    }
   }
   if (i >= n) return;
   double e[5];
@@ -158,6 +165,8 @@ __global__ void __launch_bounds__(kMaxBlock)
   __shared__ RecO tile[TJ];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int ii = i < n ? i : n - 1;
+  const int b0 = blockIdx.x * blockDim.x;
+  const int b1 = min(n, b0 + (int)blockDim.x);
   const double xi = R[3 * ii], yi = R[3 * ii + 1], zi = R[3 * ii + 2];
   const int j0 = blockIdx.y * chunk;
   const int j1 = min(n, j0 + chunk);
@@ -169,8 +178,15 @@ __global__ void __launch_bounds__(kMaxBlock)
     for (int t = threadIdx.x; t < cnt; t += blockDim.x)
       tile[t] = make_reco<HAS_T, HAS_D>(R, Fe, Te, Sig, D, jt + t, P, a5_10);
     __syncthreads();
+    if (jt < b1 && jt + cnt > b0) {  // (uniform) the tile may hold a receiver of this workgroup
 #pragma unroll 2
-    for (int jj = 0; jj < cnt; ++jj) p3_pair<HAS_T, HAS_D>(tile[jj], xi, yi, zi, A2_2, A2_23, A8, B16, acc);
+      for (int jj = 0; jj < cnt; ++jj)
+        p3_pair<true, HAS_T, HAS_D>(tile[jj], xi, yi, zi, A2_2, A2_23, A8, B16, acc);
+    } else {
+#pragma unroll 2
+      for (int jj = 0; jj < cnt; ++jj)
+        p3_pair<false, HAS_T, HAS_D>(tile[jj], xi, yi, zi, A2_2, A2_23, A8, B16, acc);
+    }
   }
   if (i >= n) return;
   double* o = out + (int64_t)blockIdx.y * 6 * n + 6 * (int64_t)i;

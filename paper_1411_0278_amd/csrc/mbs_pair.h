@@ -18,12 +18,13 @@ struct Mom6 {  // raw moments sum x_i v_j of the per-pair strain vector v
   double pxx = 0, pyy = 0, pzz = 0, qxy = 0, qxz = 0, qyz = 0;
 };
 
-template <bool HAS_T, bool HAS_D>
+// SELF: the source range may hold the receiver itself (r = 0 contributes nothing)
+template <bool SELF, bool HAS_T, bool HAS_D>
 __device__ __forceinline__ void p1_pair(const RecF& s, double xi, double yi, double zi, double A8,
                                         double B16, Mom6& m) {
   const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
   const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-  const double ri = rinv_or_zero(r2);
+  const double ri = SELF ? rinv_or_zero(r2) : rsq_nr(r2);
   const double ri2 = ri * ri;
   const double ri5 = ri2 * ri2 * ri;
   const double ri7 = ri5 * ri2;
@@ -133,11 +134,11 @@ __device__ __forceinline__ void p3_acc(const RecO& s, const Geo& g, double A2_2,
   }
 }
 
-template <bool HAS_T, bool HAS_D>
+template <bool SELF, bool HAS_T, bool HAS_D>
 __device__ __forceinline__ void p3_pair(const RecO& s, double xi, double yi, double zi, double A2_2,
                                         double A2_23, double A8, double B16, UW& a) {
   Geo g;
-  pair_geo<true>(s, xi, yi, zi, g);
+  pair_geo<SELF>(s, xi, yi, zi, g);
   p3_acc<HAS_T, HAS_D>(s, g, A2_2, A2_23, A8, B16, a);
 }
 

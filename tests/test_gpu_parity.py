@@ -344,6 +344,29 @@ def test_errors(ctx):
     assert rc == mbstokes.MBS_EINVAL
 
 
+def test_coincident_centres_are_rejected_or_reported(ctx):
+    """Two distinct spheres at one centre: check_overlap rejects them (distance 0 < 2a); without
+    the check their pair blocks are infinite and the solve reports it (MBS_ENOCONV, non-finite
+    residual) instead of returning a finite answer."""
+    w = _workload(600, seed=15)
+    d = mbstokes.to_device(w, DEV)
+    R = d["R"].clone()
+    R[500] = R[3]  # in different receiver blocks of every launch shape
+    ctx.set_params(check_overlap=1)
+    try:
+        with pytest.raises(mbstokes.MbsError) as e:
+            ctx.mbs_solve(R, d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+        assert e.value.code == mbstokes.MBS_EOVERLAP
+        ctx.set_params(check_overlap=0)
+        V, W, S, st = ctx.mbs_solve(R, d["p"], d["v1s"], d["v2s"], None, d["Fe"], None, allow_noconv=True)
+        assert not np.isfinite(st["rel_resid"])
+        with pytest.raises(mbstokes.MbsError) as e:
+            ctx.mbs_solve(R, d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+        assert e.value.code == mbstokes.MBS_ENOCONV
+    finally:
+        ctx.set_params(check_overlap=0)
+
+
 def test_size_limits_are_rejected_before_any_work(ctx):
     """Every entry point refuses a size whose element count would overflow the 32-bit indexing of
     its kernels, with MBS_EINVAL and a message, before it touches memory or launches anything (the
