@@ -253,6 +253,62 @@ __device__ __forceinline__ void p2_pair_f32(const SrcF9& s, float xi, float yi, 
   m.t4 = fmaf(ri5, s.syz, m.t4);
 }
 
+// K source records at once, stage by stage, so that K independent chains are in flight in each
+// wave (the reciprocal square roots and LDS reads of one step issue together); the sums take the
+// records in order, exactly as K calls of p2_pair_f32 would.
+template <bool SELF, int K>
+__device__ __forceinline__ void p2_pairs_f32(const SrcF9* s, float xi, float yi, float zi, const KF32& k,
+                                             Mom<float>& m) {
+  float dx[K], dy[K], dz[K], ri[K], ri2[K], ri5[K], ri7[K], wx[K], wy[K], wz[K], c1[K], c2[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    dx[q] = xi - s[q].x;
+    dy[q] = yi - s[q].y;
+    dz[q] = zi - s[q].z;
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const float r2 = fmaf(dx[q], dx[q], fmaf(dy[q], dy[q], dz[q] * dz[q]));
+    ri[q] = SELF ? rinv_or_zero(r2) : rsq_nr(r2);
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    wx[q] = fmaf(s[q].sxx, dx[q], fmaf(s[q].sxy, dy[q], s[q].sxz * dz[q]));
+    wy[q] = fmaf(s[q].sxy, dx[q], fmaf(s[q].syy, dy[q], s[q].syz * dz[q]));
+    wz[q] = fmaf(s[q].sxz, dx[q], fmaf(s[q].syz, dy[q], s[q].szz * dz[q]));
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    ri2[q] = ri[q] * ri[q];
+    ri5[q] = ri2[q] * ri2[q] * ri[q];
+    ri7[q] = ri5[q] * ri2[q];
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const float qv = fmaf(dx[q], wx[q], fmaf(dy[q], wy[q], dz[q] * wz[q]));
+    c1[q] = fmaf(k.a16, ri7[q], k.n04 * ri5[q]);
+    const float u = qv * ri7[q];
+    c2[q] = fmaf(k.n28, u * ri2[q], u);
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const float vx = fmaf(c1[q], wx[q], c2[q] * dx[q]);
+    const float vy = fmaf(c1[q], wy[q], c2[q] * dy[q]);
+    const float vz = fmaf(c1[q], wz[q], c2[q] * dz[q]);
+    m.pxx = fmaf(dx[q], vx, m.pxx);
+    m.pyy = fmaf(dy[q], vy, m.pyy);
+    m.pzz = fmaf(dz[q], vz, m.pzz);
+    m.qxy = fmaf(dx[q], vy, fmaf(dy[q], vx, m.qxy));
+    m.qxz = fmaf(dx[q], vz, fmaf(dz[q], vx, m.qxz));
+    m.qyz = fmaf(dy[q], vz, fmaf(dz[q], vy, m.qyz));
+    m.t0 = fmaf(ri5[q], s[q].sxx, m.t0);
+    m.t1 = fmaf(ri5[q], s[q].syy, m.t1);
+    m.t2 = fmaf(ri5[q], s[q].sxy, m.t2);
+    m.t3 = fmaf(ri5[q], s[q].sxz, m.t3);
+    m.t4 = fmaf(ri5[q], s[q].syz, m.t4);
+  }
+}
+
 template <typename T>
 struct LdsRec {
   using type = Src8<T>;
@@ -312,8 +368,10 @@ __global__ void __launch_bounds__(kMaxBlock)
 #pragma unroll 8
         for (int jj = 0; jj < cnt; ++jj) p2_pair_f32<true>(tile[jj], xi, yi, zi, k, m);
       } else {
-#pragma unroll 8
-        for (int jj = 0; jj < cnt; ++jj) p2_pair_f32<false>(tile[jj], xi, yi, zi, k, m);
+        int jj = 0;
+#pragma unroll 4
+        for (; jj + 2 <= cnt; jj += 2) p2_pairs_f32<false, 2>(tile + jj, xi, yi, zi, k, m);
+        for (; jj < cnt; ++jj) p2_pair_f32<false>(tile[jj], xi, yi, zi, k, m);
       }
     } else {
       if (self) {
