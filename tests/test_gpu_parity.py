@@ -676,6 +676,71 @@ def test_operator_full_size_is_symmetric_positive_definite(ctx):
     assert abs(float(np.sum(x * Ay32)) - float(np.sum(y * Ax32))) <= 1e-5 * scale
 
 
+@pytest.mark.slow
+def test_operator_and_preconditioner_at_ten_times_the_benchmark_size(ctx):
+    """N = 10^6 at the benchmark's density (cube side 430 * 10^(1/3)), the largest size the tests
+    drive: sampled rows of the binary64 and binary32 operator against the oracle (first row, the
+    last row of a ragged last workgroup, and random rows), symmetry x.(A y) = y.(A x), and sampled
+    rows of the near-field preconditioner (8a, order 2) against the oracle's blocks of exactly the
+    listed pairs. Binary32 bound: coordinates of this box round by up to 2^-24 * 463 = 2.8e-5,
+    1.3e-5 of the closest separation (2.2); the r^-7 factor makes that about 9e-5 of a row that its
+    nearest pair dominates, so 2e-4 (binary64 keeps the 1e-12 of the full-size test)."""
+    from scipy.spatial import cKDTree
+
+    from oracle import greens
+    n = 1_000_000
+    w = inputs.trap_workload(n, 430.0 * 10 ** (1 / 3), 77)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    rng = np.random.default_rng(12)
+    x, y = rng.standard_normal((n, 5)), rng.standard_normal((n, 5))
+    R = _t(w.R)
+    print(f"n={n}: binary64 and binary32 operator, symmetry", flush=True)
+    Ax = ctx.mbs_matvec(R, _t(x)).cpu().numpy()
+    Ay = ctx.mbs_matvec(R, _t(y)).cpu().numpy()
+    Ax32 = ctx.mbs_matvec(R, _t(x), precision=mbstokes.MBS_FP32).cpu().numpy()
+    scale = np.linalg.norm(x) * np.linalg.norm(Ay)
+    assert abs(float(np.sum(x * Ay)) - float(np.sum(y * Ax))) <= 1e-13 * scale
+    rows = np.array([0, n - 1, int(rng.integers(1, n - 1))])
+    print("oracle rows", rows, flush=True)
+    want = galerkin.matvec_rows(w.R, x, rows, prm)
+    assert _maxrel(Ax[rows], want) < 1e-12
+    assert _rel(Ax32[rows], want) < 2e-4
+
+    rc = 8.0
+    print(f"n={n}: near-field preconditioner rc={rc} order 2", flush=True)
+    ctx.set_params(near_cutoff=rc, near_order=2)
+    try:
+        Mx = ctx.mbs_precond_apply(R, _t(x)).cpu().numpy()
+    finally:
+        ctx.set_params(near_cutoff=0.0, near_order=2)
+    tree = cKDTree(w.R)
+
+    def partners(i):  # 2a <= r < rc, the 32 smallest indices
+        js = sorted(j for j in tree.query_ball_point(w.R[i], rc) if j != i)
+        return [j for j in js if 2 * w.a <= np.linalg.norm(w.R[i] - w.R[j]) < rc][:32]
+
+    def k_near(i, v):
+        js = partners(i)
+        if not js:
+            return np.zeros(5)
+        return np.einsum("kab,kb->a", greens.block("E", "S", w.R[i] - w.R[js], prm.a, prm.eta), v[js])
+
+    g = galerkin.constants(prm)["gamma"]
+    sample = rng.choice(n, 40, replace=False)
+    with_partners = 0
+    for i in sample:
+        js = partners(i)
+        kx = k_near(i, x)
+        kkx = np.zeros(5)
+        if js:
+            with_partners += 1
+            kxj = np.array([k_near(j, x) for j in js])
+            kkx = np.einsum("kab,kb->a", greens.block("E", "S", w.R[i] - w.R[js], prm.a, prm.eta), kxj)
+        ref = g * x[i] + g * g * kx + g ** 3 * kkx
+        assert np.abs(Mx[i] - ref).max() <= 1e-13 * np.abs(ref).max(), i
+    assert with_partners >= 20
+
+
 # ---------------------------------------------------------------- near-field preconditioner
 @pytest.mark.parametrize("order", [2, 4, 8])
 def test_precond_apply_matches_oracle(ctx, order):
