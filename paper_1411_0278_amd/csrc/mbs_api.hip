@@ -76,6 +76,8 @@ struct mbs_ctx {
   DevBuf mlp_w, mlp_g, mlp_m, mlp_v, mlp_wb, mlp_ws, mlp_part, mlp_loss, mlp_idx, knn_buf;
   // cell grid of the centres behind both neighbour searches (near-field lists, nearest neighbours)
   DevBuf grid;
+  // a solve in the Morton order of the centres: the permutation and the reordered inputs/outputs
+  DevBuf ord;
   // single-configuration GMRES: Arnoldi steps captured as graphs (per precision), see step_graphs
   StepGraphs sgraph[2];
   hipStream_t gstream = nullptr;
@@ -162,7 +164,8 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
     return set_err(c, MBS_EINVAL, "batch_item must be 0, 64, 128 or 256");
   if (p->near_order != 0 && (p->near_order < 2 || p->near_order > 8 || (p->near_order & 1)))
     return set_err(c, MBS_EINVAL, "near_order must be 0 (= 2), 2, 4, 6 or 8");
-  if (p->reserved != 0) return set_err(c, MBS_EINVAL, "reserved must be 0");
+  if (p->spatial_order < -1 || p->spatial_order > 1)
+    return set_err(c, MBS_EINVAL, "spatial_order must be -1, 0 or 1");
   return MBS_OK;
 }
 
@@ -663,10 +666,10 @@ int learned_guess(mbs_ctx* c, int64_t n, const double* R, const double* p, const
   return MBS_OK;
 }
 
-// The solve without argument validation; sigma0 is read for MBS_GUESS_USER.
-int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* v1s, const double* v2s,
-               const double* v3t, const double* Fe, const double* Te, const HighSlip& hi, const double* sigma0,
-               double* V, double* W, double* S, double* Sigma, mbs_stats* st, hipStream_t s) {
+// The solve without argument validation, in the order given; sigma0 is read for MBS_GUESS_USER.
+int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* v1s, const double* v2s,
+                   const double* v3t, const double* Fe, const double* Te, const HighSlip& hi, const double* sigma0,
+                   double* V, double* W, double* S, double* Sigma, mbs_stats* st, hipStream_t s) {
   CHK(ensure_ws(c, n));
   const bool high = high_mask(hi) != 0;
   const int hsplit = high_split(n, n, c->tile_pass);
@@ -820,6 +823,63 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const do
   return rc;
 }
 
+constexpr int64_t kSpatialOrderN = 65536;  // params.spatial_order = 0: reorder from this size on
+
+// The solve without argument validation. With spatial ordering the inputs are gathered into the
+// Morton order of the centres (the permutation of a cell grid with about two cells per sphere),
+// solved in that order and the outputs scattered back, so that each workgroup's receivers are
+// neighbours in space: binary32 coordinates relative to the first of them stay small and the
+// neighbour lists' gathers stay local. The solution is the same up to the order of the sums.
+int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* v1s, const double* v2s,
+               const double* v3t, const double* Fe, const double* Te, const HighSlip& hi, const double* sigma0,
+               double* V, double* W, double* S, double* Sigma, mbs_stats* st, hipStream_t s) {
+  const int mode = c->prm.spatial_order;
+  if (n < 2 || mode < 0 || (mode == 0 && n < kSpatialOrderN))
+    return solve_in_order(c, n, R, p, v1s, v2s, v3t, Fe, Te, hi, sigma0, V, W, S, Sigma, st, s);
+  const int64_t blk = (n + 63) / 64 * 64;  // doubles per row-width unit, padded
+  CHK(ensure(c, c->ord, (size_t)blk * 71 + 64));
+  double* base = c->ord.p;
+  int32_t* perm = reinterpret_cast<int32_t*>(base);
+  double* next = base + blk;  // the permutation takes n int32 <= blk doubles
+  auto take = [&](int width) {
+    double* q = next;
+    next += (int64_t)width * blk;
+    return q;
+  };
+  GridView g;
+  CHK(grid_of(c, n, R, c->prm.a, 2 * n + 64, &g, s));
+  HIPCHK(c, hipMemcpyAsync(perm, g.perm, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  auto gather = [&](const double* src, int width) -> const double* {
+    if (!src) return nullptr;
+    double* dst = take(width);
+    launch_gather_rows(src, width, perm, n, dst, s);
+    return dst;
+  };
+  const double* Ro = gather(R, 3);
+  const double* po = gather(p, 3);
+  const double* v1o = gather(v1s, 3);
+  const double* v2o = gather(v2s, 5);
+  const double* v3o = gather(v3t, 3);
+  const double* Fo = gather(Fe, 3);
+  const double* To = gather(Te, 3);
+  const HighSlip hio{gather(hi.gam, 10), gather(hi.psi, 5), gather(hi.lam, 10)};
+  const double* s0o = gather(c->prm.guess == MBS_GUESS_USER ? sigma0 : nullptr, 5);
+  double* Vo = take(3);
+  double* Wo = take(3);
+  double* So = take(5);
+  double* Sigo = Sigma ? take(5) : nullptr;
+  HIPCHK(c, hipGetLastError());
+  const int rc = solve_in_order(c, n, Ro, po, v1o, v2o, v3o, Fo, To, hio, s0o, Vo, Wo, So, Sigo, st, s);
+  if (rc != MBS_OK && rc != MBS_ENOCONV) return rc;
+  launch_scatter_rows(Vo, 3, perm, n, V, s);
+  launch_scatter_rows(Wo, 3, perm, n, W, s);
+  launch_scatter_rows(So, 5, perm, n, S, s);
+  if (Sigma) launch_scatter_rows(Sigo, 5, perm, n, Sigma, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return rc;
+}
+
 int begin_call(mbs_ctx* c) {
   if (!c) return MBS_EINVAL;
   c->err.clear();
@@ -851,7 +911,7 @@ void mbs_default_params(mbs_params* p) {
   p->batch_item = 0;
   p->superposition = 0;
   p->near_order = 2;
-  p->reserved = 0;
+  p->spatial_order = 0;
 }
 
 int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {

@@ -109,6 +109,9 @@ void launch_scale_by(const double* x, const double* alpha, int inv, double* y, i
 // y = a*x + b*y (host scalars)
 void launch_axpby(double a, const double* x, double b, double* y, int64_t len, hipStream_t s);
 void launch_copy(const double* x, double* y, int64_t len, hipStream_t s);
+// rows of `width` doubles: gather dst[k] = src[perm[k]], scatter dst[perm[k]] = src[k], k < n
+void launch_gather_rows(const double* src, int width, const int32_t* perm, int64_t n, double* dst, hipStream_t s);
+void launch_scatter_rows(const double* src, int width, const int32_t* perm, int64_t n, double* dst, hipStream_t s);
 // One Arnoldi column: H(:,k) = h1 + h2, H(k+1,k) = sqrt(nsq); Givens update; status[0] = |g_{k+1}|,
 // status[1] = H(k+1,k) (before rotation). Layout: H column-major [(m+1) x m], cs, sn, g [m+1].
 void launch_givens(double* H, int m, int k, const double* h1, const double* h2, const double* nsq,

@@ -841,6 +841,33 @@ void launch_axpby(double a, const double* x, double b, double* y, int64_t len, h
   hipLaunchKernelGGL(k_axpby, dim3(nblk(len, 256)), dim3(256), 0, s, a, x, b, y, len);
 }
 
+namespace {
+// dst[k][c] = src[perm[k]][c] and the reverse; perm is a permutation of 0..n-1
+__global__ void k_gather_rows(const double* __restrict__ src, int width, const int32_t* __restrict__ perm,
+                              int64_t n, double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * width) return;
+  const int64_t k = t / width;
+  dst[t] = src[(int64_t)perm[k] * width + (t - k * width)];
+}
+__global__ void k_scatter_rows(const double* __restrict__ src, int width, const int32_t* __restrict__ perm,
+                               int64_t n, double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * width) return;
+  const int64_t k = t / width;
+  dst[(int64_t)perm[k] * width + (t - k * width)] = src[t];
+}
+}  // namespace
+
+void launch_gather_rows(const double* src, int width, const int32_t* perm, int64_t n, double* dst, hipStream_t s) {
+  const int64_t len = n * width;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, src, width, perm, n, dst);
+}
+void launch_scatter_rows(const double* src, int width, const int32_t* perm, int64_t n, double* dst, hipStream_t s) {
+  const int64_t len = n * width;
+  hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, src, width, perm, n, dst);
+}
+
 void launch_copy(const double* x, double* y, int64_t len, hipStream_t s) {
   hipLaunchKernelGGL(k_copy, dim3(nblk(len, 256)), dim3(256), 0, s, x, y, len);
 }
