@@ -176,7 +176,10 @@ int mbs_solve(mbs_ctx* ctx, int64_t n, const double* R, const double* p, const d
 
 /* The system operator (the GMRES matvec):  y_n = x_n / gamma - sum_{m != n} E[x_m](R_n - R_m),
    x, y [n x 5]. precision: MBS_FP64 or MBS_FP32 (binary32 pair blocks, compensated
-   accumulation; x and y stay binary64). x and y must not overlap. */
+   accumulation; x and y stay binary64). x and y must not overlap. The spheres are taken in the
+   order given (no spatial reordering, see params.spatial_order): binary32 coordinates are rounded
+   relative to the first receiver of each block of 256, so the binary32 error is smallest when
+   neighbouring indices are neighbours in space. */
 int mbs_matvec(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y,
                int precision, void* stream);
 
