@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--skip-stepper", action="store_true")
     ap.add_argument("--skip-kernels", action="store_true", help="skip the per-size pair-pass timings")
     ap.add_argument("--stepper-steps", type=int, default=1000)
+    ap.add_argument("--scale-n", type=int, default=0,
+                    help="also time the preconditioned binary64 and mixed solves at this N (benchmark "
+                         "density), with and without spatial ordering; 0 (default) skips it")
     ap.add_argument("--profile-passes", action="store_true",
                     help="short run for hardware counters: one launch of every binary64 pass kernel at N")
     ap.add_argument("--profile-matvec", action="store_true",
@@ -465,6 +468,42 @@ def cpu_baseline(w, seconds):
                       f"({rows_done * (w.n - 1):.3g} pair blocks, {dt:.1f} s, numpy single thread)"}
 
 
+def bench_scale(a):
+    """Preconditioned binary64 and mixed solves of one larger trap workload (same density as the
+    benchmark), each with the solver's spatial ordering on and off: one timed solve each after the
+    context has been set up by an untimed one."""
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+    n = a.scale_n
+    side = a.side * (n / a.n) ** (1 / 3)
+    t0 = time.perf_counter()
+    w = inputs.trap_workload(n, side, a.seed)
+    print(f"bench: scale workload n={n} side={side:.1f} built in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    d = mbstokes.to_device(w, "cuda:0")
+    ctx = mbstokes.Context(0)
+    ctx.mbs_autotune(d["R"], None)
+    args = (d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+    out = {"n": n, "side": round(side, 2), "near_cutoff": a.near_cutoff, "near_order": a.near_order}
+    ctx.set_params(precision=mbstokes.MBS_MIXED, near_cutoff=a.near_cutoff, near_order=a.near_order, tol=1e-10)
+    ctx.mbs_solve(*args)  # workspace and neighbour lists set up
+    for name, prec in (("fp64_pc", mbstokes.MBS_FP64), ("mixed_pc", mbstokes.MBS_MIXED)):
+        for order_name, order in (("spatial_order", 1), ("caller_order", -1)):
+            ctx.set_params(precision=prec, near_cutoff=a.near_cutoff, near_order=a.near_order, tol=1e-10,
+                           spatial_order=order)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, _, _, st = ctx.mbs_solve(*args)
+            torch.cuda.synchronize()
+            out[f"{name}_{order_name}"] = {"s": round(time.perf_counter() - t, 3), "iters": st["iters"],
+                                           "fp64_matvecs": st["fp64_matvecs"], "fp32_matvecs": st["fp32_matvecs"],
+                                           "rel_resid": st["rel_resid"]}
+            print(f"bench: scale {name} {order_name} {out[f'{name}_{order_name}']}", file=sys.stderr, flush=True)
+    ctx.close()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -534,6 +573,8 @@ def main():
     if not a.skip_stepper:
         extra["stepper"] = bench_stepper(ctx, a)
         extra["paper_trap"] = bench_paper_trap(ctx, a)
+    if a.scale_n > 0:
+        extra["scale"] = bench_scale(a)
     head = variants[a.headline]
     out = {
         "metric": METRIC,
