@@ -154,6 +154,36 @@ def test_ordered_solve_with_higher_modes_matches_oracle(ctx):
         assert _rel(got, ref[key]) < 1e-9, key
 
 
+@pytest.mark.parametrize("shape", ["line", "plane"])
+def test_ordered_solve_on_degenerate_geometries(ctx, shape):
+    """Centres on a line or in a plane (the cell grid is flat in two or one axes), in a shuffled
+    order: the ordered solve equals the oracle and the caller-order solve."""
+    rng = np.random.default_rng(5)
+    if shape == "line":
+        R = np.stack([2.5 * np.arange(300.0), np.zeros(300), np.zeros(300)], axis=1)
+    else:
+        gx, gy = np.meshgrid(np.arange(18.0) * 2.5, np.arange(18.0) * 2.5, indexing="ij")
+        R = np.stack([gx, gy, np.zeros_like(gx)], axis=-1).reshape(-1, 3)
+    R = R[rng.permutation(len(R))]
+    n = len(R)
+    p = rng.standard_normal((n, 3))
+    p /= np.linalg.norm(p, axis=1, keepdims=True)
+    v1s, v2s, v3 = inputs.slip_modes(p, 1.0, 1.0, 0.0)
+    w = inputs.Workload(R, p, v1s, v2s, v3, -0.5 * R, np.zeros((n, 3)))
+    ref = galerkin.solve(w)
+    d = mbstokes.to_device(w, DEV)
+    out = {}
+    try:
+        for order in (1, -1):
+            ctx.set_params(spatial_order=order, tol=1e-12)
+            out[order] = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)[:3]
+    finally:
+        ctx.set_params(**RESET)
+    for k, key in enumerate(("V", "W", "S")):
+        assert _rel(out[1][k], ref[key]) < 1e-10, key
+        assert _rel(out[1][k], out[-1][k]) < 1e-11, key
+
+
 def test_spatial_order_is_validated(ctx):
     for bad in (2, -2):
         with pytest.raises(mbstokes.MbsError):
