@@ -92,8 +92,9 @@ __global__ void __launch_bounds__(kMaxBlock)
 #pragma unroll 2
       for (int jj = 0; jj < cnt; ++jj) p1_pair<true, HAS_T, HAS_D>(tile[jj], xi, yi, zi, A8, B16, m);
     } else {
-#pragma unroll 2
-      for (int jj = 0; jj < cnt; ++jj) p1_pair<false, HAS_T, HAS_D>(tile[jj], xi, yi, zi, A8, B16, m);
+      int jj = 0;
+      for (; jj + 2 <= cnt; jj += 2) p1_pairs<2, HAS_T, HAS_D>(tile + jj, xi, yi, zi, A8, B16, m);
+      for (; jj < cnt; ++jj) p1_pair<false, HAS_T, HAS_D>(tile[jj], xi, yi, zi, A8, B16, m);
     }
   }
   if (i >= n) return;

@@ -55,6 +55,55 @@ __device__ __forceinline__ void p1_pair(const RecF& s, double xi, double yi, dou
   m.qyz = fma(dy, vz, fma(dz, vy, m.qyz));
 }
 
+// K records at once, stage by stage (independent chains in flight in each wave); the moments take
+// the records in order, exactly as K calls of p1_pair<false, ...> would.
+template <int K, bool HAS_T, bool HAS_D>
+__device__ __forceinline__ void p1_pairs(const RecF* s, double xi, double yi, double zi, double A8,
+                                         double B16, Mom6& m) {
+  double dx[K], dy[K], dz[K], ri[K], vx[K], vy[K], vz[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    dx[q] = xi - s[q].x;
+    dy[q] = yi - s[q].y;
+    dz[q] = zi - s[q].z;
+    ri[q] = rsq_nr(fma(dx[q], dx[q], fma(dy[q], dy[q], dz[q] * dz[q])));
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const double ri2 = ri[q] * ri[q];
+    const double ri5 = ri2 * ri2 * ri[q];
+    const double xF = fma(dx[q], s[q].fx, fma(dy[q], s[q].fy, dz[q] * s[q].fz));
+    const double alpha = xF * ri5 * fma(A8, ri2, -3.0);
+    const double beta = B16 * ri5;
+    vx[q] = fma(beta, s[q].fx, alpha * dx[q]);
+    vy[q] = fma(beta, s[q].fy, alpha * dy[q]);
+    vz[q] = fma(beta, s[q].fz, alpha * dz[q]);
+    if (HAS_T) {
+      const double m3 = -3.0 * ri5;
+      vx[q] = fma(m3, s[q].ty * dz[q] - s[q].tz * dy[q], vx[q]);
+      vy[q] = fma(m3, s[q].tz * dx[q] - s[q].tx * dz[q], vy[q]);
+      vz[q] = fma(m3, s[q].tx * dy[q] - s[q].ty * dx[q], vz[q]);
+    }
+    if (HAS_D) {
+      const double ri7 = ri5 * ri2;
+      const double xd = -15.0 * ri7 * (dx[q] * s[q].dx + dy[q] * s[q].dy + dz[q] * s[q].dz);
+      const double six = 6.0 * ri5;
+      vx[q] = fma(six, s[q].dx, fma(xd, dx[q], vx[q]));
+      vy[q] = fma(six, s[q].dy, fma(xd, dy[q], vy[q]));
+      vz[q] = fma(six, s[q].dz, fma(xd, dz[q], vz[q]));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    m.pxx = fma(dx[q], vx[q], m.pxx);
+    m.pyy = fma(dy[q], vy[q], m.pyy);
+    m.pzz = fma(dz[q], vz[q], m.pzz);
+    m.qxy = fma(dx[q], vy[q], fma(dy[q], vx[q], m.qxy));
+    m.qxz = fma(dx[q], vz[q], fma(dz[q], vx[q], m.qxz));
+    m.qyz = fma(dy[q], vz[q], fma(dz[q], vy[q], m.qyz));
+  }
+}
+
 // traceless 5-basis projection of the moments
 __device__ __forceinline__ void mom6_to_basis(const Mom6& m, double* e) {
   e[0] = RS2 * (m.pxx - m.pyy);
