@@ -184,6 +184,28 @@ def test_ordered_solve_on_degenerate_geometries(ctx, shape):
         assert _rel(out[1][k], out[-1][k]) < 1e-11, key
 
 
+@pytest.mark.slow
+def test_stepper_at_benchmark_size_orders_by_default(ctx):
+    """N = 10^5 (the benchmark workload): the stepper's solves reorder automatically (n >= 65536);
+    two mixed preconditioned steps give the positions and orientations of the same steps in the
+    caller's order to the solve tolerance, and every step converges."""
+    w = inputs.config2()
+    out = {}
+    try:
+        for order in (0, -1):
+            ctx.set_params(spatial_order=order, precision=mbstokes.MBS_MIXED, near_cutoff=8.0, tol=1e-10)
+            R, p = _t(w.R), _t(w.p)
+            stats, _ = ctx.mbs_step(R, p, 0.5, (1.0, 1.0, 0.0), 0.01, 2, order=2)
+            assert all(st["rel_resid"] <= 1e-10 for st in stats), (order, stats)
+            out[order] = (R.cpu().numpy(), p.cpu().numpy())
+    finally:
+        ctx.set_params(**RESET)
+    disp = np.linalg.norm(out[-1][0] - w.R)
+    assert disp > 0
+    assert np.linalg.norm(out[0][0] - out[-1][0]) <= 1e-8 * disp
+    assert _rel(out[0][1], out[-1][1]) < 1e-10
+
+
 def test_spatial_order_is_validated(ctx):
     for bad in (2, -2):
         with pytest.raises(mbstokes.MbsError):
