@@ -112,7 +112,7 @@ typedef struct mbs_params {
   int32_t near_order;    /* order k of the near-field preconditioner's Neumann series: 2 (default;
                             0 means 2), 4, 6 or 8 (even orders keep M^{-1} positive definite for
                             any near block); each order is one sparse pass over the neighbour lists */
-  int32_t spatial_order; /* mbs_solve and mbs_step work internally with the spheres in the Morton
+  int32_t spatial_order; /* mbs_solve(_ex) and mbs_step work internally with the spheres in the Morton
                             order of their centres (inputs gathered into that order, outputs
                             scattered back, so the caller sees its own order): 0 = when n >= 65536
                             (default), 1 = always, -1 = never. A workgroup's receivers are then
