@@ -486,6 +486,24 @@ def bench_scale(a):
     ctx.mbs_autotune(d["R"], None)
     args = (d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
     out = {"n": n, "side": round(side, 2), "near_cutoff": a.near_cutoff, "near_order": a.near_order}
+    # binary32 operator error against binary64 with the spheres in the given order and in Morton
+    # order (mbs_matvec takes the order it is given; the solver reorders by itself)
+    import numpy as np
+    lo, hi = w.R.min(0), w.R.max(0)
+    q = ((w.R - lo) / (hi - lo + 1e-9) * 1023).astype(np.uint64)
+    code = np.zeros(n, dtype=np.uint64)
+    for b in range(10):
+        for c in range(3):
+            code |= ((q[:, c] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + c)
+    err = {}
+    x_np = np.random.default_rng(3).standard_normal((n, 5))
+    for order_name, perm in (("caller_order", np.arange(n)), ("morton_order", np.argsort(code, kind="stable"))):
+        R = torch.as_tensor(np.ascontiguousarray(w.R[perm])).to("cuda:0")
+        x = torch.as_tensor(np.ascontiguousarray(x_np[perm])).to("cuda:0")
+        y64 = ctx.mbs_matvec(R, x)
+        y32 = ctx.mbs_matvec(R, x, precision=mbstokes.MBS_FP32)
+        err[order_name] = float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64))
+    out["f32_operator_rel_err"] = err
     ctx.set_params(precision=mbstokes.MBS_MIXED, near_cutoff=a.near_cutoff, near_order=a.near_order, tol=1e-10)
     ctx.mbs_solve(*args)  # workspace and neighbour lists set up
     for name, prec in (("fp64_pc", mbstokes.MBS_FP64), ("mixed_pc", mbstokes.MBS_MIXED)):
