@@ -33,23 +33,3 @@ def from5(c):
 # only the symmetric traceless part (7 independent components) enters the flows.
 SYM3 = [(0, 0, 0), (0, 0, 1), (0, 0, 2), (0, 1, 1), (0, 1, 2), (0, 2, 2), (1, 1, 1), (1, 1, 2), (1, 2, 2),
         (2, 2, 2)]
-
-
-def sym3_full(c):
-    """[..., 10] -> [..., 3, 3, 3] symmetric tensor."""
-    c = np.asarray(c, dtype=np.float64)
-    T = np.zeros(c.shape[:-1] + (3, 3, 3))
-    import itertools
-    for q, idx in enumerate(SYM3):
-        for perm in set(itertools.permutations(idx)):
-            T[(...,) + perm] = c[..., q]
-    return T
-
-
-def stf3(T):
-    """Symmetric traceless part of a symmetric rank-3 tensor [..., 3, 3, 3]."""
-    T = np.asarray(T, dtype=np.float64)
-    t = np.einsum("...iik->...k", T)
-    d = np.eye(3)
-    return T - (np.einsum("ij,...k->...ijk", d, t) + np.einsum("ik,...j->...ijk", d, t)
-                + np.einsum("jk,...i->...ijk", d, t)) / 5.0

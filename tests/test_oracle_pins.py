@@ -360,6 +360,143 @@ def test_two_particle_trap_rotation_leading_term():
     assert rel[0] < 1e-2 and rel[1] < rel[0] / 4      # corrections fall off faster than r^-2
 
 
+def _two_particle_omega(R, p, k, s0, prm):
+    """Angular velocity of sphere 1 in the two-particle trap of section V (equations of the
+    orientational dynamics, harmonicTrap_Omega): a Stokeslet term from the trap force on sphere 2
+    and a stresslet term from sphere 2's uniaxial slip s_2 = s0 (p_2 p_2 - I/3). The paper prints
+    the second term without the 1/(8 pi eta) the first one carries (read here as a dropped
+    prefactor) and with C_20 = the single-layer stresslet constant of its table (20/3) pi eta a^3,
+    the value of the golden file."""
+    rho = R[0] - R[1]
+    r = np.linalg.norm(rho)
+    C20 = GOLD["stresslet_single_layer_C20_over_pi_eta_a3"]["value"] * np.pi * prm.eta * prm.a ** 3
+    first = -k * np.cross(R[1], R[0]) / (8 * np.pi * prm.eta * r ** 3)
+    second = 3 * C20 * s0 * (p[1] @ rho) * np.cross(p[1], rho) / (8 * np.pi * prm.eta * r ** 5)
+    return first + second
+
+
+def _two_active_trapped(scale, k, c2, theta_deg=115.0, tilt=(0.3, -0.5, 0.8)):
+    th = np.deg2rad(theta_deg)
+    R = scale * A * np.array([[0, 0, 1.0], [np.sin(th), 0, np.cos(th)]])
+    p = np.array([[0.0, 0.6, 0.8], tilt])
+    p /= np.linalg.norm(p, axis=1, keepdims=True)
+    v1s, v2s, v3t = inputs.slip_modes(p, 1.0, c2, 0.0)
+    return inputs.Workload(R, p, v1s, v2s, v3t, -k * R, np.zeros((2, 3)), ETA, A)
+
+
+def test_superposition_lone_sphere_equals_solve_and_one_body_relations():
+    """A lone sphere: the superposition approximation (section IV) is exact, and it carries the
+    one-body relations V = V^a + F^e/(6 pi eta a), Omega = T^e/(8 pi eta a^3) (appendix D) and
+    Sigma = -gamma s with gamma the single-layer constant C_20 of the section IV table."""
+    rng = np.random.default_rng(11)
+    p = rng.standard_normal((1, 3))
+    p /= np.linalg.norm(p)
+    v1s, v2s, v3t = inputs.slip_modes(p, 0.7, -1.3, 0.4)
+    w = inputs.Workload(rng.standard_normal((1, 3)), p, v1s, v2s, v3t, rng.standard_normal((1, 3)),
+                        rng.standard_normal((1, 3)), ETA, A)
+    sup = galerkin.superposition(w, PRM)
+    sol = galerkin.solve(w, PRM)
+    for key in ("V", "W", "S", "Sigma"):
+        assert np.abs(sup[key] - sol[key]).max() < 1e-14 * (1 + np.abs(sol[key]).max()), key
+    mu_t = GOLD["self_translational_mobility_8pi_eta_a"]["value"] / (8 * np.pi * ETA * A)
+    mu_r = GOLD["self_rotational_mobility_8pi_eta_a3"]["value"] / (8 * np.pi * ETA * A ** 3)
+    C20 = GOLD["stresslet_single_layer_C20_over_pi_eta_a3"]["value"] * np.pi * ETA * A ** 3
+    assert np.allclose(sup["V"], -v1s + mu_t * w.Fe, rtol=0, atol=1e-14)
+    assert np.allclose(sup["W"], mu_r * w.Te, rtol=0, atol=1e-14)
+    assert np.allclose(sup["Sigma"], -C20 * v2s, rtol=0, atol=1e-14)
+
+
+def test_superposition_two_particle_rotation_is_the_papers_formula():
+    """Two active spheres in a trap: the superposition approximation's angular velocity of sphere 1
+    equals the two-term closed form of section V exactly (the direct sum has no other term that
+    rotates sphere 1: the rank-3 mode and the mean slip give no rotation, the Faxen term of the force
+    flow is curl free, the finite-size term of the stresslet flow is a gradient). The stresslets are
+    -C_20 s_n whatever the positions."""
+    k, c2 = 0.5, -0.8
+    for scale in (4.0, 12.56):
+        w = _two_active_trapped(scale, k, c2)
+        sup = galerkin.superposition(w, PRM)
+        C20 = GOLD["stresslet_single_layer_C20_over_pi_eta_a3"]["value"] * np.pi * ETA * A ** 3
+        assert np.abs(sup["Sigma"] + C20 * w.v2s).max() < 1e-14 * np.abs(C20 * w.v2s).max()
+        want = _two_particle_omega(w.R, w.p, k, 3.0 * c2, PRM)
+        # the stresslet term must carry weight at these separations, so a sign slip shows
+        second = want - _two_particle_omega(w.R, w.p, k, 0.0, PRM)
+        assert np.linalg.norm(second) > 0.05 * np.linalg.norm(want)
+        assert np.linalg.norm(sup["W"][0] - want) < 1e-13 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("case,expo_v,expo_w", [("slip", 5, 6), ("force", 4, 7)])
+def test_superposition_departs_from_the_solve_as_a_power_of_separation(case, expo_v, expo_w):
+    """Superposition drops the coupling of the stresslets (section IV): each keeps its lone-sphere
+    value. For two spheres the many-body stresslet of one differs from it by gamma times the strain
+    of the other's flow at its centre, and that difference moves the first sphere through the
+    stresslet blocks (U ~ r^-2, W ~ r^-3).
+    * Strain slip only: the other's stresslet flow strains as r^-3, so the velocity difference falls
+      as r^-5 and the rotation difference as r^-6.
+    * Body forces only: the Stokeslet strains as r^-2, the velocity difference falls as r^-4; that
+      strain, (x.F)(I - 3 x^x^), has x^ as an eigenvector, so its rotlet part x cross (Sigma x)
+      vanishes and the rotation difference comes from the finite-size terms (a^2 r^-4), r^-7.
+    A dropped or sign-slipped coupling term in either the solve or the superposition breaks the
+    power law (the difference would then stay O(1) or fall at the rate of the direct terms)."""
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal((2, 3))
+    p /= np.linalg.norm(p, axis=1, keepdims=True)
+    v1s, v2s, v3t = inputs.slip_modes(p, 1.0, 1.0 if case == "slip" else 0.0, 0.0)
+    F = rng.standard_normal((2, 3)) if case == "force" else np.zeros((2, 3))
+    e = np.array([0.48, 0.6, 0.64])
+    dv, dw = [], []
+    for r in (20.0, 40.0, 80.0):
+        R = np.array([[0.0, 0.0, 0.0], r * A * e])
+        w = inputs.Workload(R, p, v1s, v2s, v3t, F, np.zeros((2, 3)), ETA, A)
+        sup, sol = galerkin.superposition(w, PRM), galerkin.solve(w, PRM)
+        dv.append(np.linalg.norm(sup["V"] - sol["V"]))
+        dw.append(np.linalg.norm(sup["W"] - sol["W"]))
+    for k in range(2):
+        assert abs(np.log2(dv[k] / dv[k + 1]) - expo_v) < 0.1, dv
+        assert abs(np.log2(dw[k] / dw[k + 1]) - expo_w) < 0.1, dw
+
+
+def test_stepper_orientation_update_is_omega_cross_p():
+    """Kinematics of section II, dp/dt = Omega x p, pinned through the two-particle trap of
+    section V: one short forward-Euler step of two trapped passive spheres turns p_1 at the rate
+    Omega_1 x p_1 with Omega_1 the paper's leading term -k (R_2 x R_1)/(8 pi eta rho^3); with the
+    superposition branch and active spheres the rate is the closed form of both terms exactly.
+    A p x Omega slip reverses the rate and fails both checks."""
+    k, dt = 0.5, 1e-7
+    # many-body solve, passive spheres far apart: the leading term to O(rho^-2) relative
+    for scale in (25.12, 50.24):
+        th = np.deg2rad(115.0)
+        R = scale * A * np.array([[0, 0, 1.0], [np.sin(th), 0, np.cos(th)]])
+        p = np.array([[0.0, 0.6, 0.8], [1.0, 0.0, 0.0]])
+        R1, p1, _ = stepper.run(R, p, k, (0.0, 0.0, 0.0), dt, 1, PRM, order=1)
+        rate = (p1[0] - p[0]) / dt
+        want = np.cross(_two_particle_omega(R, np.zeros((2, 3)), k, 0.0, PRM), p[0])
+        assert np.linalg.norm(rate - want) < 2e-2 * np.linalg.norm(want)
+        # the position moves with the trap velocity of the lone sphere to leading order
+        assert np.linalg.norm((R1[0] - R[0]) / dt + k * R[0] * GOLD[
+            "self_translational_mobility_8pi_eta_a"]["value"] / (8 * np.pi * ETA * A)) < 0.1 * k * scale
+    # superposition branch, active spheres: both terms of the closed form
+    c2 = 0.9
+    w = _two_active_trapped(6.0, k, c2)
+    _, p1, _ = stepper.run(w.R, w.p, k, (1.0, c2, 0.0), dt, 1, PRM, order=1, superposition=True)
+    rate = (p1[0] - w.p[0]) / dt
+    want = np.cross(_two_particle_omega(w.R, w.p, k, 3.0 * c2, PRM), w.p[0])
+    assert np.linalg.norm(rate - want) < 1e-6 * np.linalg.norm(want)
+
+
+def test_stepper_superposition_position_update_is_the_direct_sum():
+    """The superposition branch of the stepper moves each sphere by its lone-sphere motion plus the
+    pair flows of the others (section IV); a forward-Euler step of a lone trapped swimmer moves it
+    by dt (V^a - k R/(6 pi eta a)), and the p update leaves a lone sphere's orientation alone."""
+    k, dt = 0.5, 0.01
+    p = np.array([[0.0, 0.6, 0.8]])
+    R = np.array([[1.0, -2.0, 0.5]])
+    R1, p1, _ = stepper.run(R, p, k, (1.0, 0.5, 0.0), dt, 1, PRM, order=1, superposition=True)
+    mu_t = GOLD["self_translational_mobility_8pi_eta_a"]["value"] / (8 * np.pi * ETA * A)
+    assert np.allclose(R1, R + dt * (-p - k * mu_t * R), rtol=0, atol=1e-15)
+    assert np.allclose(p1, p, rtol=0, atol=1e-15)
+
+
 def test_diametrically_opposite_active_pair_does_not_rotate():
     k = 0.5
     Rs = 12.56 * A
