@@ -34,6 +34,10 @@
  *   - Optional inputs may be NULL, meaning zero.
  *   - Work is enqueued on `stream` (NULL = the default stream); every call
  *     returns after its work on that stream has completed.
+ *   - An output array must not share memory with an input or with another output
+ *     (MBS_EINVAL, checked on the address ranges before any work).
+ *   - Orientations p, wherever an entry point reads them, must be unit vectors:
+ *     | |p| - 1 | <= 1e-12 for every row (MBS_EINVAL otherwise).
  *   - Return value: MBS_OK or a negative error code; the message for the last
  *     failure on the context is available from mbs_last_error. No C++
  *     exception crosses this interface. On an error no output is written
@@ -51,7 +55,8 @@ extern "C" {
 #endif
 
 #define MBS_OK            0
-#define MBS_EINVAL       -1  /* bad argument: NULL required pointer, n < 1, bad option, non-finite value */
+#define MBS_EINVAL       -1  /* bad argument: NULL required pointer, n < 1, bad option, non-finite value,
+                                orientation p with | |p| - 1 | > 1e-12, output overlapping an input */
 #define MBS_ENOCONV      -2  /* iteration cap reached; outputs hold the last iterate, stats->rel_resid is set */
 #define MBS_EOVERLAP     -3  /* two centres closer than 2a (only when check_overlap is set) */
 #define MBS_EUNSUPPORTED -4  /* option not supported (for example lmax != 2) */
@@ -59,8 +64,11 @@ extern "C" {
 #define MBS_EHIP         -6  /* HIP runtime error; the HIP message is in mbs_last_error */
 
 #define MBS_FP64   0   /* pair blocks and Krylov arithmetic in binary64 */
-#define MBS_MIXED  1   /* binary32 pair blocks with compensated accumulation inside a binary64
-                          iterative refinement; residuals and corrections in binary64 */
+#define MBS_MIXED  1   /* binary32 pair blocks inside a binary64 iterative refinement; residuals
+                          and corrections in binary64. Accumulation of the binary32 operator: plain
+                          binary32 fused multiply-adds within a segment of sources (64 records, or
+                          one LDS tile of 64-256), Kahan-compensated binary32 sums of the segment
+                          totals, and binary64 sums of the source chunks */
 #define MBS_FP32   1   /* precision selector of mbs_matvec: binary32 pair blocks */
 
 #define MBS_GUESS_ZERO     0   /* Sigma^0 = 0 */
@@ -160,7 +168,8 @@ const char* mbs_last_error(const mbs_ctx* ctx);
 
 /* Full solve (sections II-III): Sigma from the stresslet rows, then V, Omega, S.
      R      [n x 3]  sphere centres
-     p      [n x 3]  unit orientations (read by the learned warm start; may be NULL otherwise)
+     p      [n x 3]  unit orientations (read by the learned warm start; may be NULL otherwise;
+                     checked for unit length whenever given)
      v1s    [n x 3]  mean slip mode V^(1s); V^a = -V^(1s)
      v2s    [n x 5]  symmetric traceless linear slip mode s = V^(2s)
      v3t    [n x 3]  rank-3 trace slip mode d = V^(3t) (a fixed source, exterior flow
@@ -175,8 +184,12 @@ int mbs_solve(mbs_ctx* ctx, int64_t n, const double* R, const double* p, const d
               mbs_stats* st, void* stream);
 
 /* The system operator (the GMRES matvec):  y_n = x_n / gamma - sum_{m != n} E[x_m](R_n - R_m),
-   x, y [n x 5]. precision: MBS_FP64 or MBS_FP32 (binary32 pair blocks, compensated
-   accumulation; x and y stay binary64). x and y must not overlap. The spheres are taken in the
+   x, y [n x 5]: the stresslet rows of the Galerkin system, i.e. the off-diagonal matrix elements
+   between the symmetric l = 1 modes of two spheres (section III, matrix elements as derivatives of
+   the Green's function under the finite-size operators F^1 of both spheres) and the one-body
+   diagonal 1/gamma (section IV, one-body traction-velocity relations, stresslet).
+   precision: MBS_FP64 or MBS_FP32 (binary32 pair blocks, accumulated as described at MBS_MIXED;
+   x and y stay binary64). y must not overlap x or R. The spheres are taken in the
    order given (no spatial reordering, see params.spatial_order): binary32 coordinates are rounded
    relative to the first receiver of each block of 256, so the binary32 error is smallest when
    neighbouring indices are neighbours in space. */
@@ -184,10 +197,18 @@ int mbs_matvec(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double
                int precision, void* stream);
 
 /* The near-field preconditioner on its own: y = gamma sum_{i <= k} (gamma K_near)^i x, k =
-   params.near_order (x, y [n x 5] binary64 DEVICE, params.near_cutoff > 0). */
+   params.near_order (x, y [n x 5] binary64 DEVICE, params.near_cutoff > 0; y must not overlap x or
+   R). K_near holds the blocks of mbs_matvec's sum (section III off-diagonal stresslet elements)
+   for the pairs on the neighbour lists; the series is the Neumann expansion of the inverse of the
+   near part of the system, an addition of this library (the paper names no solver). */
 int mbs_precond_apply(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y, void* stream);
 
-/* Right-hand side of the stresslet rows: b_n = sum_{m != n} E[F_m, T_m, d_m] - c s_n, b [n x 5]. */
+/* Right-hand side of the stresslet rows: b_n = sum_{m != n} E[F_m, T_m, d_m] - c s_n, b [n x 5]:
+   the known lower coefficients (force and torque, section II, overdamped Newton's equations as
+   constraints) and the fixed rank-3 trace mode moved to the right of the Schur "higher" rows
+   (section II, lower/higher partition), with the elements of section III (strain of the
+   Stokeslet with its finite-size operator F^0, of the rotlet and of the potential dipole) and the
+   self slip term of section IV. b must not overlap any input. */
 int mbs_rhs(mbs_ctx* ctx, int64_t n, const double* R, const double* v2s, const double* v3t,
             const double* Fe, const double* Te, double* b, void* stream);
 

@@ -60,7 +60,7 @@ struct mbs_ctx {
   // workspace
   DevBuf V, w, r, b, xs, dlt, part, dpart, small, H, zeros, stepbuf, srcbuf, orig, near, zt, nt, stepstate;
   bool near_ready = false;  // neighbour lists of the current solve are built
-  int* d_count = nullptr;
+  int* d_count = nullptr;  // device [2]: non-finite values, orientations off unit length
   double* h_status = nullptr;  // pinned host [4]
   hipEvent_t ev[8] = {};
   // event pairs bracketing operator applications inside a solve (harvested after each sync)
@@ -475,15 +475,72 @@ int gmres(mbs_ctx* c, int prec, int64_t n, const double* R, const double* rhs, d
   return MBS_OK;
 }
 
-int count_nonfinite(mbs_ctx* c, hipStream_t s, std::initializer_list<std::pair<const double*, int64_t>> arrs,
-                    int* bad) {
-  HIPCHK(c, hipMemsetAsync(c->d_count, 0, sizeof(int), s));
+// Orientations must be unit vectors to this tolerance wherever they are read (the slip modes and
+// the learned guess's features are built from them).
+constexpr double kUnitTol = 1e-12;
+
+// Counts, in one round trip, the non-finite values of the given arrays (*bad) and, when p is given,
+// the rows of p [n x 3] whose length is not within kUnitTol of 1 (*bad_p).
+int count_bad(mbs_ctx* c, hipStream_t s, std::initializer_list<std::pair<const double*, int64_t>> arrs,
+              int* bad, const double* p = nullptr, int64_t n = 0, int* bad_p = nullptr) {
+  HIPCHK(c, hipMemsetAsync(c->d_count, 0, 2 * sizeof(int), s));
   for (auto& a : arrs)
     if (a.first) launch_count_nonfinite(a.first, a.second, c->d_count, s);
-  int h = 0;
-  HIPCHK(c, hipMemcpyAsync(&h, c->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (p) launch_count_nonunit(p, n, kUnitTol, c->d_count + 1, s);
+  int h[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(h, c->d_count, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  *bad = h;
+  *bad = h[0];
+  if (bad_p) *bad_p = h[1];
+  return MBS_OK;
+}
+
+int count_nonfinite(mbs_ctx* c, hipStream_t s, std::initializer_list<std::pair<const double*, int64_t>> arrs,
+                    int* bad) {
+  return count_bad(c, s, arrs, bad);
+}
+
+// Non-finite inputs and orientations off unit length are argument errors.
+int check_inputs(mbs_ctx* c, hipStream_t s, std::initializer_list<std::pair<const double*, int64_t>> arrs,
+                 const double* p, int64_t n) {
+  int bad = 0, bad_p = 0;
+  CHK(count_bad(c, s, arrs, &bad, p, n, &bad_p));
+  if (bad) return set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
+  if (bad_p)
+    return set_err(c, MBS_EINVAL, "%d orientations p are not unit vectors (| |p| - 1 | > %.0e)", bad_p, kUnitTol);
+  return MBS_OK;
+}
+
+// An output array may not share memory with an input or with another output: the passes read their
+// inputs while writing their outputs. Each entry is (name, pointer, number of doubles); NULL entries
+// are skipped.
+struct Span {
+  const char* name;
+  const void* p;
+  int64_t len;
+};
+int check_aliasing(mbs_ctx* c, std::initializer_list<Span> outs, std::initializer_list<Span> ins) {
+  auto hit = [](const Span& a, const Span& b) {
+    if (!a.p || !b.p || a.len <= 0 || b.len <= 0) return false;
+    const uintptr_t a0 = (uintptr_t)a.p, a1 = a0 + (uintptr_t)a.len * sizeof(double);
+    const uintptr_t b0 = (uintptr_t)b.p, b1 = b0 + (uintptr_t)b.len * sizeof(double);
+    return a0 < b1 && b0 < a1;
+  };
+  for (auto o = outs.begin(); o != outs.end(); ++o) {
+    for (const Span& i : ins)
+      if (hit(*o, i)) return set_err(c, MBS_EINVAL, "output %s overlaps input %s", o->name, i.name);
+    for (auto q = outs.begin(); q != o; ++q)
+      if (hit(*o, *q)) return set_err(c, MBS_EINVAL, "outputs %s and %s overlap", q->name, o->name);
+  }
+  return MBS_OK;
+}
+
+// The learned guess needs a network, the orientations and at least kNeigh other spheres.
+int check_learned(mbs_ctx* c, int64_t n, const double* p) {
+  if (!c->mlp_ready)
+    return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context (mbs_warmstart_*)");
+  if (!p) return set_err(c, MBS_EINVAL, "the learned guess needs the orientations p");
+  if (n < kNeigh + 1) return set_err(c, MBS_EINVAL, "the learned guess needs n >= %d", kNeigh + 1);
   return MBS_OK;
 }
 
@@ -760,6 +817,15 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
       norm2(c, rr, len, sm.nsq, s);
       CHK(read_status(c, sm.nsq, 1, s));
       beta = sqrt(c->h_status[0]);
+      if (beta <= c->prm.tol * bnorm) {
+        // The guess may already pass (a configuration solved before): only a binary64 residual can
+        // certify it, so form that one, with the outputs of the guess in the same pass.
+        apply_op_out(c, n, R, c->xs.p, rr, op, s, cnt);
+        launch_axpby(1.0, c->b.p, -1.0, rr, len, s);
+        norm2(c, rr, len, sm.nsq, s);
+        CHK(read_status(c, sm.nsq, 1, s));
+        beta = sqrt(c->h_status[0]);
+      }
     }
     while (beta > c->prm.tol * bnorm && cnt.iters < c->prm.max_iter) {
       HIPCHK(c, hipMemsetAsync(delta, 0, len * sizeof(double), s));
@@ -936,7 +1002,7 @@ int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {
   c->ph = make_phys(prm->eta, prm->a, prm->self_slip_c);
   apply_tiles(c);
   e = hipHostMalloc((void**)&c->h_status, 8 * sizeof(double), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc((void**)&c->d_count, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->d_count, 2 * sizeof(int));
   for (int k = 0; k < 8 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
   for (int k = 0; k < 2 * mbs_ctx::kRing && e == hipSuccess; ++k) e = hipEventCreate(&c->opev[k]);
   if (e != hipSuccess) {
@@ -1016,25 +1082,22 @@ int mbs_solve_ex(mbs_ctx* c, int64_t n, const double* R, const double* p, const 
   if (!R || !V || !W || !S) return set_err(c, MBS_EINVAL, "R, V, W and S are required");
   if (c->prm.guess == MBS_GUESS_USER && !sigma0)
     return set_err(c, MBS_EINVAL, "MBS_GUESS_USER needs sigma0");
+  if (c->prm.guess == MBS_GUESS_LEARNED) CHK(check_learned(c, n, p));
+  const int64_t s0len = c->prm.guess == MBS_GUESS_USER ? 5 * n : 0;
+  CHK(check_aliasing(c, {{"V", V, 3 * n}, {"W", W, 3 * n}, {"S", S, 5 * n}, {"Sigma", Sigma, 5 * n}},
+                     {{"R", R, 3 * n}, {"p", p, 3 * n}, {"v1s", v1s, 3 * n}, {"v2s", v2s, 5 * n},
+                      {"v3t", v3t, 3 * n}, {"Fe", Fe, 3 * n}, {"Te", Te, 3 * n}, {"sigma0", sigma0, s0len},
+                      {"gam", hi.gam, 10 * n}, {"psi", hi.psi, 5 * n}, {"lam", hi.lam, 10 * n}}));
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
-  int bad = 0;
-  CHK(count_nonfinite(c, s, {{R, 3 * n}, {v1s, 3 * n}, {v2s, 5 * n}, {v3t, 3 * n}, {Fe, 3 * n},
-                             {Te, 3 * n}, {sigma0, c->prm.guess == MBS_GUESS_USER ? 5 * n : 0},
-                             {hi.gam, 10 * n}, {hi.psi, 5 * n}, {hi.lam, 10 * n}},
-                      &bad));
-  if (bad) return set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
+  CHK(check_inputs(c, s, {{R, 3 * n}, {v1s, 3 * n}, {v2s, 5 * n}, {v3t, 3 * n}, {Fe, 3 * n},
+                          {Te, 3 * n}, {sigma0, s0len}, {hi.gam, 10 * n}, {hi.psi, 5 * n}, {hi.lam, 10 * n}},
+                   p, n));
   if (c->prm.check_overlap) {
     double md = 0.0;
     CHK(check_overlap(c, n, R, s, &md));
     if (md < 2.0 * c->prm.a)
       return set_err(c, MBS_EOVERLAP, "spheres overlap: minimum centre distance %.6g < 2a", md);
-  }
-  if (c->prm.guess == MBS_GUESS_LEARNED) {
-    if (!c->mlp_ready)
-      return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context (mbs_warmstart_*)");
-    if (!p) return set_err(c, MBS_EINVAL, "the learned guess needs the orientations p");
-    if (n < kNeigh + 1) return set_err(c, MBS_EINVAL, "the learned guess needs n >= %d", kNeigh + 1);
   }
   return solve_core(c, n, R, p, v1s, v2s, v3t, Fe, Te, hi, sigma0, V, W, S, Sigma, st, s);
 }
@@ -1053,7 +1116,7 @@ int mbs_matvec(mbs_ctx* c, int64_t n, const double* R, const double* x, double* 
   if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
   if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
   if (!R || !x || !y) return set_err(c, MBS_EINVAL, "R, x and y are required");
-  if (x == y) return set_err(c, MBS_EINVAL, "x and y must not overlap");
+  CHK(check_aliasing(c, {{"y", y, 5 * n}}, {{"R", R, 3 * n}, {"x", x, 5 * n}}));
   if (precision != MBS_FP64 && precision != MBS_FP32)
     return set_err(c, MBS_EINVAL, "precision must be MBS_FP64 or MBS_FP32");
   hipStream_t s = (hipStream_t)stream;
@@ -1073,10 +1136,13 @@ int mbs_rhs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const 
   if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
   if (n > (int64_t)INT32_MAX / 10) return set_err(c, MBS_EINVAL, "n too large");
   if (!R || !b) return set_err(c, MBS_EINVAL, "R and b are required");
+  const HighSlip hi = high_of(ex);
+  CHK(check_aliasing(c, {{"b", b, 5 * n}},
+                     {{"R", R, 3 * n}, {"v2s", v2s, 5 * n}, {"v3t", v3t, 3 * n}, {"Fe", Fe, 3 * n},
+                      {"Te", Te, 3 * n}, {"gam", hi.gam, 10 * n}, {"psi", hi.psi, 5 * n}, {"lam", hi.lam, 10 * n}}));
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
   launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, c->ph, c->tile_pass, s);
-  const HighSlip hi = high_of(ex);
   if (high_mask(hi))
     launch_high(0, R, n, R, n, hi, b, nullptr, c->part.p, high_split(n, n, c->tile_pass), c->ph, c->tile_pass, s);
   HIPCHK(c, hipGetLastError());
@@ -1096,11 +1162,15 @@ int mbs_outputs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v1s, co
   if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
   if (n > (int64_t)INT32_MAX / 10) return set_err(c, MBS_EINVAL, "n too large");
   if (!R || !Sigma || !V || !W) return set_err(c, MBS_EINVAL, "R, Sigma, V and W are required");
+  const HighSlip hi = high_of(ex);
+  CHK(check_aliasing(c, {{"V", V, 3 * n}, {"W", W, 3 * n}, {"S", S, 5 * n}},
+                     {{"R", R, 3 * n}, {"v1s", v1s, 3 * n}, {"v2s", v2s, 5 * n}, {"v3t", v3t, 3 * n},
+                      {"Fe", Fe, 3 * n}, {"Te", Te, 3 * n}, {"Sigma", Sigma, 5 * n}, {"gam", hi.gam, 10 * n},
+                      {"psi", hi.psi, 5 * n}, {"lam", hi.lam, 10 * n}}));
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
   launch_p3(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, c->ph,
             c->tile_pass, s);
-  const HighSlip hi = high_of(ex);
   if (high_mask(hi))
     launch_high(1, R, n, R, n, hi, V, W, c->part.p, high_split(n, n, c->tile_pass), c->ph, c->tile_pass, s);
   HIPCHK(c, hipGetLastError());
@@ -1121,9 +1191,13 @@ int mbs_flow_ex(mbs_ctx* c, int64_t m, const double* X, int64_t n, const double*
   if (m < 1 || n < 1) return set_err(c, MBS_EINVAL, "m and n must be >= 1");
   if (m > (int64_t)INT32_MAX / 12 || n > (int64_t)INT32_MAX / 10) return set_err(c, MBS_EINVAL, "m or n too large");
   if (!X || !R || !Sigma || !U) return set_err(c, MBS_EINVAL, "X, R, Sigma and U are required");
+  const HighSlip hi = high_of(ex);
+  CHK(check_aliasing(c, {{"U", U, 3 * m}},
+                     {{"X", X, 3 * m}, {"R", R, 3 * n}, {"Fe", Fe, 3 * n}, {"Te", Te, 3 * n},
+                      {"Sigma", Sigma, 5 * n}, {"v3t", v3t, 3 * n}, {"gam", hi.gam, 10 * n},
+                      {"psi", hi.psi, 5 * n}, {"lam", hi.lam, 10 * n}}));
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));  // (zeros stand in for absent forces)
-  const HighSlip hi = high_of(ex);
   const int hsplit = high_split(m, n, c->tile_pass);
   CHK(ensure(c, c->part, (size_t)std::max(flow_split(m, n, c->tile_pass), high_mask(hi) ? hsplit : 0) * 3 * m + 64));
   launch_flow(X, m, R, Fe ? Fe : c->zeros.p, Te, Sigma, v3t, U, c->part.p, n, c->ph, c->tile_pass, s);
@@ -1149,6 +1223,8 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
   if (order != 1 && order != 2) return set_err(c, MBS_EINVAL, "order must be 1 or 2");
   if (!isfinite(dt) || !isfinite(k_trap)) return set_err(c, MBS_EINVAL, "dt and k must be finite");
   if (hist_valid && !hist) return set_err(c, MBS_EINVAL, "hist_valid needs hist");
+  if (c->prm.guess == MBS_GUESS_LEARNED) CHK(check_learned(c, n, p));
+  CHK(check_aliasing(c, {{"R", R, 3 * n}, {"p", p, 3 * n}, {"hist", hist, 11 * n}}, {}));
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
   // state: Fe, v1s, v3t, V, W, Vprev, Pdprev [3n] each; v2s, Sigma, S [5n] each. Vprev, Pdprev and
@@ -1165,9 +1241,7 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
   double* v2s = Pp + 3 * n;
   double* Sg = v2s + 5 * n;
   double* Sout = Sg + 5 * n;
-  int bad = 0;
-  int rc = count_nonfinite(c, s, {{R, 3 * n}, {p, 3 * n}}, &bad);
-  if (rc == MBS_OK && bad) rc = set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
+  int rc = check_inputs(c, s, {{R, 3 * n}, {hist_valid ? hist : nullptr, 11 * n}}, p, n);
   const int guess0 = c->prm.guess;
   bool noconv = false;
   if (rc == MBS_OK && hist_valid) {  // resume: the previous step's V, Omega x p and Sigma
@@ -1250,6 +1324,9 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   if (!R || !V || !W || !S) return set_err(c, MBS_EINVAL, "R, V, W and S are required");
   const int64_t ntot64 = offsets[nconf];
   const int ntot = (int)ntot64;
+  CHK(check_aliasing(c, {{"V", V, 3 * ntot64}, {"W", W, 3 * ntot64}, {"S", S, 5 * ntot64}, {"Sigma", Sigma, 5 * ntot64}},
+                     {{"R", R, 3 * ntot64}, {"v1s", v1s, 3 * ntot64}, {"v2s", v2s, 5 * ntot64},
+                      {"v3t", v3t, 3 * ntot64}, {"Fe", Fe, 3 * ntot64}, {"Te", Te, 3 * ntot64}}));
   hipStream_t s = (hipStream_t)stream;
   int bad = 0;
   CHK(ensure_ws(c, 16));
@@ -1704,6 +1781,7 @@ int mbs_features(mbs_ctx* c, int64_t n, const double* R, const double* p, float*
   if (n > (int64_t)INT32_MAX / kMlpIn) return set_err(c, MBS_EINVAL, "n too large");
   if (!R || !p || !feat) return set_err(c, MBS_EINVAL, "R, p and feat are required");
   hipStream_t s = (hipStream_t)stream;
+  CHK(check_inputs(c, s, {{R, 3 * n}}, p, n));
   int32_t* nb = nbr;
   if (!nb) {
     CHK(ensure(c, c->knn_buf, (size_t)n * kNeigh / 2 + 64));
@@ -1879,12 +1957,13 @@ int mbs_initial_guess(mbs_ctx* c, int64_t n, const double* R, const double* p, c
   if (n > (int64_t)INT32_MAX / kMlpIn) return set_err(c, MBS_EINVAL, "n too large");
   if (guess != MBS_GUESS_ZERO && guess != MBS_GUESS_DIAG && guess != MBS_GUESS_LEARNED)
     return set_err(c, MBS_EINVAL, "guess must be MBS_GUESS_ZERO, _DIAG or _LEARNED");
-  if (guess == MBS_GUESS_LEARNED) {
-    if (!c->mlp_ready) return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context");
-    if (!p || n < kNeigh + 1) return set_err(c, MBS_EINVAL, "the learned guess needs p and n >= %d", kNeigh + 1);
-  }
+  if (guess == MBS_GUESS_LEARNED) CHK(check_learned(c, n, p));
+  CHK(check_aliasing(c, {{"sigma0", sigma0, 5 * n}},
+                     {{"R", R, 3 * n}, {"p", p, 3 * n}, {"v2s", v2s, 5 * n}, {"v3t", v3t, 3 * n},
+                      {"Fe", Fe, 3 * n}, {"Te", Te, 3 * n}}));
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
+  if (guess == MBS_GUESS_LEARNED) CHK(check_inputs(c, s, {{R, 3 * n}}, p, n));
   launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
   if (guess == MBS_GUESS_ZERO)
     launch_axpby(0.0, c->b.p, 0.0, sigma0, 5 * n, s);
@@ -1916,7 +1995,7 @@ int mbs_precond_apply(mbs_ctx* c, int64_t n, const double* R, const double* x, d
   CHK(begin_call(c));
   if (n < 1 || !R || !x || !y) return set_err(c, MBS_EINVAL, "n >= 1, R, x and y are required");
   if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
-  if (x == y) return set_err(c, MBS_EINVAL, "x and y must not overlap");
+  CHK(check_aliasing(c, {{"y", y, 5 * n}}, {{"R", R, 3 * n}, {"x", x, 5 * n}}));
   if (!(c->prm.near_cutoff > 0.0)) return set_err(c, MBS_EINVAL, "params.near_cutoff must be > 0");
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));

@@ -77,6 +77,8 @@ void launch_min_dist2(const GridView& g, const double* R, int64_t n, double* out
                       hipStream_t s);
 // count non-finite entries of a device array -> atomically added to *cnt (device int)
 void launch_count_nonfinite(const double* a, int64_t len, int* cnt, hipStream_t s);
+// count rows of p [n x 3] with | |p| - 1 | > tol (or non-finite) -> atomically added to *cnt
+void launch_count_nonunit(const double* p, int64_t n, double tol, int* cnt, hipStream_t s);
 
 // near-field preconditioner: neighbour lists within rc (at most kNearCap per sphere) and
 // y = gamma sum_{i <= order} (gamma K_near)^i x (order >= 2 needs tmp of 10n doubles; order 1 or

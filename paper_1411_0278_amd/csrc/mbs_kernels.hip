@@ -487,6 +487,25 @@ __global__ void k_count_nonfinite(const double* __restrict__ a, int64_t len, int
   if (threadIdx.x == 0 && red[0] != 0) atomicAdd(cnt, red[0]);
 }
 
+// rows of p [n x 3] whose length is not within tol of 1 (non-finite rows included)
+__global__ void k_count_nonunit(const double* __restrict__ p, int64_t n, double tol, int* __restrict__ cnt) {
+  __shared__ int red[kMaxBlock];
+  int bad = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const double x = p[3 * k], y = p[3 * k + 1], z = p[3 * k + 2];
+    const double len = sqrt(x * x + y * y + z * z);
+    bad += fabs(len - 1.0) <= tol ? 0 : 1;
+  }
+  red[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0) atomicAdd(cnt, red[0]);
+}
+
 // ------------------------------------------------------------------ Krylov helpers
 constexpr int kDotThreads = 256;
 
@@ -812,6 +831,12 @@ void launch_count_nonfinite(const double* a, int64_t len, int* cnt, hipStream_t 
   if (len <= 0) return;
   const unsigned nb = std::min<unsigned>(nblk(len, 256), 1024u);
   hipLaunchKernelGGL(k_count_nonfinite, dim3(nb), dim3(256), 0, s, a, len, cnt);
+}
+
+void launch_count_nonunit(const double* p, int64_t n, double tol, int* cnt, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned nb = std::min<unsigned>(nblk(n, 256), 1024u);
+  hipLaunchKernelGGL(k_count_nonunit, dim3(nb), dim3(256), 0, s, p, n, tol, cnt);
 }
 
 int dot_blocks(int64_t len) {

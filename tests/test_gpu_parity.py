@@ -7,7 +7,8 @@ Tolerances:
 * binary64 solve: ||X_gpu - X_oracle||_F / ||X_oracle||_F <= 1e-10 per output X in
   {V, Omega, S, Sigma} with the GMRES tolerance 1e-12 (condition number ~1.8).
 * binary32 pair blocks: unit roundoff 6e-8; each block is a product of ~10 rounded factors
-  and the receiver sum cancels partially, so 2e-5 normwise relative is used.
+  and the receiver sum cancels partially (measured 1-4e-7 at these sizes), so 2e-6 normwise
+  relative is used.
 * mixed-precision solve: 1e-9 per output (binary64 residual 1e-11).
 """
 import numpy as np
@@ -74,7 +75,7 @@ def test_matvec_f32_matches_oracle(ctx, n):
     x = np.random.default_rng(n).standard_normal((n, 5))
     want = (galerkin.system_matrix(w.R, prm) @ x.ravel()).reshape(n, 5)
     got = ctx.mbs_matvec(_t(w.R), _t(x), precision=mbstokes.MBS_FP32)
-    assert _rel(got, want) < 2e-5
+    assert _rel(got, want) < 2e-6
 
 
 def _tiles(ctx):
@@ -101,7 +102,9 @@ def test_matvec_every_launch_shape(ctx, n):
     for k in _tiles(ctx):
         print(f"matvec n={n} tile={k}", flush=True)
         assert _maxrel(ctx.mbs_matvec(R, xt), want) < 1e-13, k
-        assert _rel(ctx.mbs_matvec(R, xt, precision=mbstokes.MBS_FP32), want) < 2e-5, k
+        e32 = _rel(ctx.mbs_matvec(R, xt, precision=mbstokes.MBS_FP32), want)
+        print(f"  binary32 error {e32:.2e}", flush=True)
+        assert e32 < 2e-6, k
         count += 1
     assert count >= 8
 
@@ -417,6 +420,128 @@ def test_stepper_matches_oracle(ctx):
     assert _maxrel(R, Rw) < 1e-12 and _maxrel(p, pw) < 1e-12
     dmin = min(np.linalg.norm(w.R[i] - w.R[j]) for i in range(w.n) for j in range(i))
     assert abs(md[0] - dmin) < 1e-12
+
+
+@pytest.mark.parametrize("prec,order", [(mbstokes.MBS_MIXED, 0), (mbstokes.MBS_FP64, 0), (mbstokes.MBS_MIXED, 1)])
+def test_stepper_as_benchmarked_matches_oracle(ctx, prec, order):
+    """The time-stepping workload exactly as the benchmark runs it, at a size the oracle solves
+    densely: the N = 10^4 workload's density (cube side 200, here 300 spheres), slip coefficients
+    (1, 1, 1) with the rank-3 mode d = p, trap k = 0.5, Adams-Bashforth dt = 0.01, near-field
+    preconditioner at 8a of order 2, the previous step's stresslet as the guess (the first step
+    from the one-body guess), mixed precision or binary64, caller's order or Morton order. Four
+    steps against the oracle's stepper (dense solves). The displacements, not the positions,
+    are compared, so the bar measures the motion: 1e-9 (mixed) and 1e-10 (binary64)."""
+    n = 300
+    side = 200.0 * (n / 10_000) ** (1 / 3)
+    w = inputs.trap_workload(n, side, seed=91, v3t=1.0)
+    print(f"stepper as benchmarked n={n} prec={prec} spatial_order={order}", flush=True)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    Rw, pw, _ = stepper.run(w.R, w.p, 0.5, (1.0, 1.0, 1.0), 0.01, 4, prm)
+    R, p = _t(w.R), _t(w.p)
+    ctx.set_params(precision=prec, guess=mbstokes.MBS_GUESS_USER, tol=1e-11, near_cutoff=8.0, near_order=2,
+                   max_iter=60, spatial_order=order)
+    try:
+        stats, md = ctx.mbs_step(R, p, 0.5, (1.0, 1.0, 1.0), 0.01, 4, order=2, want_min_dist=True)
+    finally:
+        ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-10, near_cutoff=0.0,
+                       max_iter=300, spatial_order=0)
+    bar = 1e-9 if prec == mbstokes.MBS_MIXED else 1e-10
+    dR = _rel(R.cpu().numpy() - w.R, Rw - w.R)
+    dp = _rel(p.cpu().numpy() - w.p, pw - w.p)
+    print(f"  displacement error R {dR:.2e} p {dp:.2e}; iterations {[s['iters'] for s in stats]}", flush=True)
+    assert dR < bar and dp < bar
+    assert all(s["rel_resid"] <= 1e-11 for s in stats)
+    if prec == mbstokes.MBS_MIXED:
+        assert all(s["fp32_matvecs"] > 0 for s in stats)
+    assert md[0] >= 2.2 - 1e-12
+
+
+def test_mixed_resolve_of_a_converged_guess_reports_a_binary64_residual():
+    """MBS_MIXED started from a stresslet that already meets a loose tolerance: the call returns at
+    once, and the residual it reports (and certifies against tol) is the binary64 one, equal to the
+    oracle's residual of that stresslet, not the binary32 operator's (~1e-7)."""
+    w = _workload(120, seed=61)
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    ref = galerkin.solve(w, prm)
+    c = mbstokes.Context(0, tol=1e-13)
+    try:
+        d = mbstokes.to_device(w, DEV)
+        Sigma = torch.empty((w.n, 5), dtype=torch.float64, device=DEV)
+        c.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"], Sigma=Sigma)
+        Sig_np = Sigma.cpu().numpy()
+        res_oracle = np.linalg.norm(ref["b"] - ref["A"] @ Sig_np.ravel()) / np.linalg.norm(ref["b"])
+        c.set_params(precision=mbstokes.MBS_MIXED, guess=mbstokes.MBS_GUESS_USER, tol=1e-6)
+        V, W, S, st = c.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"], sigma0=Sigma)
+    finally:
+        c.close()
+    print(f"re-solve: residual {st['rel_resid']:.3e} (oracle {res_oracle:.3e}), iterations {st['iters']}", flush=True)
+    assert st["iters"] == 0 and st["refinements"] == 0
+    assert st["out_fused"] == 1 and st["fp32_matvecs"] == 1
+    assert st["rel_resid"] < 1e-12
+    assert abs(st["rel_resid"] - res_oracle) < 2e-15
+    for name, got in (("V", V), ("W", W), ("S", S)):
+        assert _rel(got, ref[name]) < 1e-11, name
+
+
+def test_boundary_contract_rejects_non_unit_orientations_and_aliased_outputs(ctx):
+    """|p| must be 1 to 1e-12 wherever p is read; an output may not overlap an input or another
+    output. Each case returns MBS_EINVAL with a message and writes nothing."""
+    w = _workload(40, seed=17)
+    d = mbstokes.to_device(w, DEV)
+    pbad = d["p"].clone()
+    pbad[7] *= 1.0 + 1e-9
+    for name, call in (
+            ("solve", lambda: ctx.mbs_solve(d["R"], pbad, d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])),
+            ("step", lambda: ctx.mbs_step(d["R"].clone(), pbad.clone(), 0.5, (1.0, 1.0, 1.0), 0.01, 1)),
+            ("features", lambda: ctx.mbs_features(d["R"], pbad))):
+        with pytest.raises(mbstokes.MbsError) as e:
+            call()
+        assert e.value.code == mbstokes.MBS_EINVAL and "unit" in str(e.value), name
+    # a unit vector rounded to binary64 passes
+    ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
+    import ctypes
+    lib = mbstokes.load()
+    n = w.n
+    buf = torch.zeros(40 * n, dtype=torch.float64, device=DEV)
+    base = buf.data_ptr()
+    P = lambda k: ctypes.c_void_p(base + 8 * k)  # noqa: E731
+    R = P(0)
+    buf[:3 * n] = d["R"].reshape(-1)
+    x = P(3 * n)
+    cases = {
+        "matvec y overlaps x": lambda: lib.mbs_matvec(ctx.h, n, R, x, P(3 * n + 7), 0, None),
+        "matvec y overlaps R": lambda: lib.mbs_matvec(ctx.h, n, R, x, P(3 * n - 2), 0, None),
+        "rhs b overlaps Fe": lambda: lib.mbs_rhs(ctx.h, n, R, None, None, P(20 * n), None, P(20 * n + 3 * n - 1), None),
+        "outputs V overlaps W": lambda: lib.mbs_outputs(ctx.h, n, R, None, None, None, None, None, x,
+                                                        P(10 * n), P(10 * n + 2), None, None),
+        "flow U overlaps X": lambda: lib.mbs_flow(ctx.h, 4, P(30 * n), n, R, None, None, x, None, P(30 * n + 5), None),
+    }
+    snapshot = buf.clone()
+    for name, call in cases.items():
+        print(f"aliasing: {name}", flush=True)
+        assert call() == mbstokes.MBS_EINVAL, name
+        assert "overlap" in lib.mbs_last_error(ctx.h).decode(), name
+    torch.cuda.synchronize()
+    assert torch.equal(buf, snapshot)
+
+
+def test_learned_guess_checks_apply_to_the_stepper():
+    """mbs_step with the learned guess: without a network MBS_EUNSUPPORTED, with one but fewer than
+    17 spheres MBS_EINVAL; both before any launch, so R and p are untouched."""
+    c = mbstokes.Context(0, guess=mbstokes.MBS_GUESS_LEARNED)
+    try:
+        w = _workload(10, seed=19)
+        R, p = _t(w.R), _t(w.p)
+        with pytest.raises(mbstokes.MbsError) as e:
+            c.mbs_step(R, p, 0.5, (1.0, 1.0, 1.0), 0.01, 1)
+        assert e.value.code == mbstokes.MBS_EUNSUPPORTED
+        c.mbs_warmstart_init(seed=1)
+        with pytest.raises(mbstokes.MbsError) as e:
+            c.mbs_step(R, p, 0.5, (1.0, 1.0, 1.0), 0.01, 1)
+        assert e.value.code == mbstokes.MBS_EINVAL and "n >= 17" in str(e.value)
+        assert torch.equal(R, _t(w.R)) and torch.equal(p, _t(w.p))
+    finally:
+        c.close()
 
 
 @pytest.mark.parametrize("guess", [mbstokes.MBS_GUESS_USER, mbstokes.MBS_GUESS_DIAG])
