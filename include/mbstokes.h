@@ -196,6 +196,18 @@ int mbs_solve(mbs_ctx* ctx, int64_t n, const double* R, const double* p, const d
 int mbs_matvec(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y,
                int precision, void* stream);
 
+/* mbs_matvec for callers that cannot allocate device memory (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): the same operator, launch shape and results as
+   mbs_matvec, with every intermediate (chunk partial sums, packed source records, box centre) in a
+   static 56 MiB device array of the library instead of the context's workspace. It calls no
+   allocating routine. Limits: n <= 131072 (MBS_EINVAL beyond, or if the context's launch shape
+   needs more scratch than the array holds; both checked before any work). Each GPU holds one copy
+   of the array for the life of the process and every call on that GPU shares it, from any context:
+   calls that overlap in time on one GPU (other streams, other host threads) race and give wrong
+   results. Nothing from one call is read by the next. */
+int mbs_matvec_static(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y,
+                      int precision, void* stream);
+
 /* The near-field preconditioner on its own: y = gamma sum_{i <= k} (gamma K_near)^i x, k =
    params.near_order (x, y [n x 5] binary64 DEVICE, params.near_cutoff > 0; y must not overlap x or
    R). K_near holds the blocks of mbs_matvec's sum (section III off-diagonal stresslet elements)

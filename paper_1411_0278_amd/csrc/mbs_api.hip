@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
 #include <random>
 
 #include "../../include/mbstokes.h"
@@ -946,6 +947,56 @@ int solve_core(mbs_ctx* c, int64_t n, const double* R, const double* p, const do
   return rc;
 }
 
+// ---------------------------------------------------------------- static scratch (mbs_matvec_static)
+// Device memory for callers that cannot allocate: the operator's chunk partial sums, packed source
+// records and box centre of one application, for n <= kStaticMaxN. Every GPU the library runs on
+// holds its own copy of this array until the process ends. Host code never uses the array's name
+// as an address: its per-device address comes from hipGetSymbolAddress, taken once per device at
+// context creation (with that device current) and kept in g_static_ptr.
+constexpr int64_t kStaticMaxN = 131072;
+constexpr size_t kStaticDoubles = (size_t)56 << 17;  // 56 MiB
+__device__ __align__(256) double scratch[kStaticDoubles];
+
+constexpr int kMaxDevices = 64;
+double* g_static_ptr[kMaxDevices] = {};
+std::mutex g_static_mu;
+
+// Resolve this device's address of the scratch array (device current; once per device).
+int attach_static_scratch(int device, std::string* msg) {
+  if (device < 0 || device >= kMaxDevices) {
+    *msg = "device index beyond the static scratch table";
+    return MBS_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (g_static_ptr[device]) return MBS_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    *msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return MBS_EHIP;
+  }
+  g_static_ptr[device] = static_cast<double*>(ptr);
+  return MBS_OK;
+}
+
+// Scratch of one operator application at launch shape t, in doubles, each region starting on a
+// 256-byte boundary: chunk partial sums when the sources are split, packed source records for the
+// scalar-streamed variant, the box centre.
+struct OpScratch {
+  int64_t part, src, orig, total;
+};
+OpScratch op_scratch(int64_t n, Tile t) {
+  auto up = [](int64_t v) { return (v + 31) / 32 * 32; };
+  const int tj = t.variant == 0 ? ((t.tj == 64 || t.tj == 256) ? t.tj : 128) : 64;
+  const int split = split_for(n, t, tj);
+  OpScratch o;
+  o.part = 0;
+  o.src = up(split > 1 ? (int64_t)split * 5 * n : 0);
+  o.orig = o.src + up(t.variant == 1 ? 8 * n : 0);
+  o.total = o.orig + 4;
+  return o;
+}
+
 int begin_call(mbs_ctx* c) {
   if (!c) return MBS_EINVAL;
   c->err.clear();
@@ -996,6 +1047,11 @@ int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {
     return set_err(nullptr, MBS_EINVAL, "device %d out of range (%d devices)", device, ndev);
   e = hipSetDevice(device);
   if (e != hipSuccess) return set_err(nullptr, MBS_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+  {
+    std::string msg;
+    rc = attach_static_scratch(device, &msg);
+    if (rc != MBS_OK) return set_err(nullptr, rc, "%s", msg.c_str());
+  }
   mbs_ctx* c = new mbs_ctx();
   c->device = device;
   c->prm = *prm;
@@ -1127,6 +1183,34 @@ int mbs_matvec(mbs_ctx* c, int64_t n, const double* R, const double* x, double* 
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   c->npend = 0;
+  return MBS_OK;
+}
+
+int mbs_matvec_static(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, int precision,
+                      void* stream) {
+  CHK(begin_call(c));
+  if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
+  if (n > kStaticMaxN)
+    return set_err(c, MBS_EINVAL, "n = %lld exceeds the static scratch limit of %lld spheres", (long long)n,
+                   (long long)kStaticMaxN);
+  if (!R || !x || !y) return set_err(c, MBS_EINVAL, "R, x and y are required");
+  CHK(check_aliasing(c, {{"y", y, 5 * n}}, {{"R", R, 3 * n}, {"x", x, 5 * n}}));
+  if (precision != MBS_FP64 && precision != MBS_FP32)
+    return set_err(c, MBS_EINVAL, "precision must be MBS_FP64 or MBS_FP32");
+  double* base = g_static_ptr[c->device];
+  if (!base) return set_err(c, MBS_EHIP, "static scratch not attached on device %d", c->device);
+  const Tile t = precision == MBS_FP64 ? c->tile64 : c->tile32;
+  const OpScratch sc = op_scratch(n, t);
+  if (sc.total > (int64_t)kStaticDoubles)
+    return set_err(c, MBS_EINVAL, "n = %lld needs %lld doubles of scratch at this launch shape (static scratch: %zu)",
+                   (long long)n, (long long)sc.total, kStaticDoubles);
+  // every region is written before it is read within the application, so nothing needs clearing
+  double* src = base + sc.src;
+  double* orig = base + sc.orig;
+  hipStream_t s = (hipStream_t)stream;
+  launch_p2(precision == MBS_FP32, R, x, y, base, src, orig, n, c->ph, t, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;
 }
 

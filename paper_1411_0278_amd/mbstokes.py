@@ -25,7 +25,7 @@ EXPORTS = ("mbs_default_params", "mbs_create", "mbs_destroy", "mbs_set_params", 
            "mbs_autotune", "mbs_autotune_batched", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
            "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
            "mbs_warmstart_load", "mbs_warmstart_target", "mbs_initial_guess", "mbs_precond_apply",
-           "mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex")
+           "mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex", "mbs_matvec_static")
 MLP_NPARAM, MLP_NFEAT = 27525, 80
 
 
@@ -91,6 +91,8 @@ def load(path: str = LIB_PATH):
     lib.mbs_solve.restype = ctypes.c_int
     lib.mbs_matvec.argtypes = [P, I64, P, P, P, ctypes.c_int, VP]
     lib.mbs_matvec.restype = ctypes.c_int
+    lib.mbs_matvec_static.argtypes = [P, I64, P, P, P, ctypes.c_int, VP]
+    lib.mbs_matvec_static.restype = ctypes.c_int
     lib.mbs_rhs.argtypes = [P, I64, P, P, P, P, P, P, VP]
     lib.mbs_rhs.restype = ctypes.c_int
     lib.mbs_outputs.argtypes = [P, I64] + [P] * 10 + [VP]
@@ -232,6 +234,13 @@ class Context:
         y = torch.empty((n, 5), dtype=torch.float64, device=R.device) if y is None else y
         self._check(self.lib.mbs_matvec(self.h, n, _ptr(R, n, 3, "R"), _ptr(x, n, 5, "x"),
                                         _ptr(y, n, 5, "y"), precision, _stream()))
+        return y
+
+    def mbs_matvec_static(self, R, x, y, precision=MBS_FP64):
+        """The operator with the library's static scratch (no device allocation); y is required."""
+        n = R.shape[0]
+        self._check(self.lib.mbs_matvec_static(self.h, n, _ptr(R, n, 3, "R"), _ptr(x, n, 5, "x"),
+                                               _ptr(y, n, 5, "y"), precision, _stream()))
         return y
 
     def mbs_rhs(self, R, v2s=None, v3t=None, Fe=None, Te=None, b=None):
