@@ -1,7 +1,15 @@
 // Cell grid over the sphere centres (gfx950): bounding box, cell keys, stable radix sort by Morton
 // key, per-cell ranges and the centres in sorted order. Five small launches plus the sort; O(n).
+//
+// The sort is a least-significant-digit radix sort of the 30-bit keys with their sphere indices:
+// three passes of 10-bit digits. Each pass counts the digits of every tile of 1024 keys (LDS
+// histogram), scans the counts across tiles for each digit (one wavefront per digit) and across
+// digits (one workgroup), and scatters: a tile's keys are taken in order, 256 at a time; within a
+// wavefront, lanes holding the same digit find each other by ballots over the digit's bits, and a
+// key's rank among them plus the counts of the earlier wavefronts and rounds gives its place.
+// Keys therefore keep their input order among equal digits (stable), so the final order is by key
+// and then by sphere index, and every run produces the same permutation.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 #include <math.h>
 #include <stdint.h>
 
@@ -165,8 +173,131 @@ __global__ void k_cell_ranges(const uint32_t* __restrict__ key, const int32_t* _
   }
 }
 
+// ---------------------------------------------------------------- radix sort of the cell keys
+constexpr int kSortBits = 10;
+constexpr int kSortDigits = 1 << kSortBits;
+constexpr int kSortPasses = (kKeyBits + kSortBits - 1) / kSortBits;  // 3
+constexpr int kSortThreads = 256;                                      // 4 wavefronts
+constexpr int kSortRounds = 4;
+constexpr int kSortTile = kSortThreads * kSortRounds;                  // keys per tile
+static_assert(kSortPasses % 2 == 1, "an odd number of passes leaves the result in the output buffers");
+
+inline int sort_tiles(int n) { return (n + kSortTile - 1) / kSortTile; }
+
+// digit counts of one tile -> hist[digit * ntiles + tile]
+__global__ void __launch_bounds__(kSortThreads) k_sort_hist(const uint32_t* __restrict__ key, int n, int shift,
+                                                            int ntiles, int32_t* __restrict__ hist) {
+  __shared__ int32_t h[kSortDigits];
+  for (int d = threadIdx.x; d < kSortDigits; d += kSortThreads) h[d] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t k = base + r * kSortThreads + threadIdx.x;
+    if (k < n) atomicAdd(&h[(key[k] >> shift) & (kSortDigits - 1)], 1);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kSortDigits; d += kSortThreads) hist[(int64_t)d * ntiles + blockIdx.x] = h[d];
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
+// for every digit (one wavefront each): exclusive scan of its tile counts in place; total -> tot[d]
+__global__ void __launch_bounds__(kSortThreads) k_sort_scan_tiles(int32_t* __restrict__ hist, int ntiles,
+                                                                  int32_t* __restrict__ tot) {
+  const int lane = threadIdx.x & 63;
+  const int d = blockIdx.x * (kSortThreads / 64) + (threadIdx.x >> 6);
+  int32_t* row = hist + (int64_t)d * ntiles;
+  int carry = 0;
+  for (int t0 = 0; t0 < ntiles; t0 += 64) {
+    const int t = t0 + lane;
+    const int v = t < ntiles ? row[t] : 0;
+    const int s = wave_incl_scan(v, lane);
+    if (t < ntiles) row[t] = carry + s - v;
+    carry += __shfl(s, 63, 64);
+  }
+  if (lane == 0) tot[d] = carry;
+}
+
+// exclusive scan of the digit totals -> first output position of each digit (one workgroup)
+__global__ void __launch_bounds__(kSortDigits) k_sort_scan_digits(const int32_t* __restrict__ tot,
+                                                                  int32_t* __restrict__ dbase) {
+  __shared__ int32_t wsum[kSortDigits / 64];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int v = tot[t];
+  const int s = wave_incl_scan(v, lane);
+  if (lane == 63) wsum[wid] = s;
+  __syncthreads();
+  int x = 0, xs = 0;
+  if (wid == 0) {
+    x = lane < kSortDigits / 64 ? wsum[lane] : 0;
+    xs = wave_incl_scan(x, lane);
+  }
+  __syncthreads();
+  if (wid == 0 && lane < kSortDigits / 64) wsum[lane] = xs - x;
+  __syncthreads();
+  dbase[t] = wsum[wid] + s - v;
+}
+
+// stable scatter of one tile by digit
+__global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint32_t* __restrict__ kin,
+                                                               const int32_t* __restrict__ vin, int n, int shift,
+                                                               int ntiles, const int32_t* __restrict__ hist,
+                                                               const int32_t* __restrict__ dbase,
+                                                               uint32_t* __restrict__ kout, int32_t* __restrict__ vout) {
+  __shared__ int32_t base[kSortDigits];
+  __shared__ int32_t wcnt[kSortThreads / 64][kSortDigits];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int d = tid; d < kSortDigits; d += kSortThreads) {
+    base[d] = dbase[d] + hist[(int64_t)d * ntiles + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][d] = 0;
+  }
+  __syncthreads();
+  const uint64_t below = (1ull << lane) - 1ull;  // lanes before this one
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t k = (int64_t)blockIdx.x * kSortTile + r * kSortThreads + tid;
+    const bool valid = k < n;
+    const uint32_t key = valid ? kin[k] : 0u;
+    const int d = (int)((key >> shift) & (kSortDigits - 1));
+    uint64_t peers = __ballot(valid);  // valid lanes of this wavefront holding the same digit
+#pragma unroll
+    for (int b = 0; b < kSortBits; ++b) {
+      const int bit = (d >> b) & 1;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const int rank = __popcll(peers & below);
+    if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int pos = base[d] + rank;
+      for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = vin[k];
+    }
+    __syncthreads();
+    for (int dd = tid; dd < kSortDigits; dd += kSortThreads) {
+      int add = 0;
+#pragma unroll
+      for (int w = 0; w < kSortThreads / 64; ++w) {
+        add += wcnt[w][dd];
+        wcnt[w][dd] = 0;
+      }
+      base[dd] += add;
+    }
+    __syncthreads();
+  }
+}
+
 struct Layout {
-  size_t hdr, part, key_in, key, idx_in, perm, Rs, start, end, tmp, tmp_bytes, total;
+  size_t hdr, part, key_in, key, idx_in, perm, Rs, start, end, hist, tot, dbase, total;
 };
 
 Layout layout(int n, int64_t max_cells) {
@@ -190,12 +321,12 @@ Layout layout(int n, int64_t max_cells) {
   o += align256(sizeof(int32_t) * max_cells);
   L.end = o;
   o += align256(sizeof(int32_t) * max_cells);
-  size_t tb = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                           (const int32_t*)nullptr, (int32_t*)nullptr, n, 0, kKeyBits);
-  L.tmp = o;
-  L.tmp_bytes = align256(tb) + 256;
-  o += L.tmp_bytes;
+  L.hist = o;
+  o += align256(sizeof(int32_t) * (size_t)kSortDigits * sort_tiles(n));
+  L.tot = o;
+  o += align256(sizeof(int32_t) * kSortDigits);
+  L.dbase = o;
+  o += align256(sizeof(int32_t) * kSortDigits);
   L.total = o;
   return L;
 }
@@ -222,10 +353,25 @@ hipError_t grid_build(const double* R, int n, double h_min, int64_t max_cells, v
   hipLaunchKernelGGL(k_box_part, dim3(kBoxParts), dim3(256), 0, s, R, n, part);
   hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(kBoxParts), 0, s, part, n, h_min, max_cells, hdr);
   hipLaunchKernelGGL(k_cell_keys, dim3(nblk(n, 256)), dim3(256), 0, s, R, n, hdr, key_in, idx_in);
-  size_t tb = L.tmp_bytes;
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs((void*)(b + L.tmp), tb, key_in, key, idx_in, perm, n, 0,
-                                                    kKeyBits, s);
-  if (e != hipSuccess) return e;
+  {  // stable radix sort (key_in, idx_in) -> (key, perm), ping-ponging through both pairs of buffers
+    int32_t* hist = (int32_t*)(b + L.hist);
+    int32_t* tot = (int32_t*)(b + L.tot);
+    int32_t* dbase = (int32_t*)(b + L.dbase);
+    const int ntiles = sort_tiles(n);
+    uint32_t* kbuf[2] = {key_in, key};
+    int32_t* vbuf[2] = {idx_in, perm};
+    for (int p = 0; p < kSortPasses; ++p) {
+      const int shift = p * kSortBits;
+      const uint32_t* ki = kbuf[p & 1];
+      const int32_t* vi = vbuf[p & 1];
+      hipLaunchKernelGGL(k_sort_hist, dim3(ntiles), dim3(kSortThreads), 0, s, ki, n, shift, ntiles, hist);
+      hipLaunchKernelGGL(k_sort_scan_tiles, dim3(kSortDigits / (kSortThreads / 64)), dim3(kSortThreads), 0, s,
+                         hist, ntiles, tot);
+      hipLaunchKernelGGL(k_sort_scan_digits, dim3(1), dim3(kSortDigits), 0, s, tot, dbase);
+      hipLaunchKernelGGL(k_sort_scatter, dim3(ntiles), dim3(kSortThreads), 0, s, ki, vi, n, shift, ntiles, hist,
+                         dbase, kbuf[(p + 1) & 1], vbuf[(p + 1) & 1]);
+    }
+  }
   hipLaunchKernelGGL(k_clear_cells, dim3(nblk(max_cells, 256)), dim3(256), 0, s, start, end, max_cells);
   hipLaunchKernelGGL(k_cell_ranges, dim3(nblk(n, 256)), dim3(256), 0, s, key, perm, R, n, hdr, start, end, Rs);
   view->hdr = hdr;
