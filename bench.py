@@ -23,8 +23,12 @@ sys.path.insert(0, ROOT)
 METRIC = "pair-blocks/s; time to 1e-10 residual at N=1e5, plain FP64 vs mixed+warm start"
 FP64_PEAK_TF = 78.6     # MI355X vector FP64
 FP32_PEAK_TF = 157.3    # MI355X vector FP32 (published figure, counts packed FP32)
-# algorithmic FLOP per pair block of the system operator as implemented (FMA = 2, rsqrt = 1):
-# differences 3, r^2 5, 1/r 1, powers 4, Szz 1, w 15, q 5, c1 3, c2 4, v 9, moments 18, r^-5 Sigma 10
+# algorithmic FLOP per pair block of the system operator (FMA = 2, rsqrt = 1), the count the roofline's
+# `achieved` uses: differences 3, r^2 5, rsqrt 1, powers 5, w = Sigma x 15, q 5, c1 c2 c3 9, trace term 4,
+# c1 x and c2 x 6, five accumulated components 43
+P2_FLOP_PER_PAIR_ALG = 95
+# the same block as implemented (accumulating raw moments, projecting once per receiver): differences
+# 3, r^2 5, 1/r 1, powers 4, Szz 1, w 15, q 5, c1 3, c2 4, v 9, moments 18, r^-5 Sigma 10
 P2_FLOP_PER_PAIR = 78
 FLOW_FLOP_PER_PAIR = 68  # field-point flow from force and flow stresslet (no torque, no rank-3 mode)
 # the pass of the septlet, vortlet and spinlet slip modes (all three present), per pair, counted from
@@ -133,8 +137,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, n):
-    """HBM bytes per launch from committed PMC summaries, if taken on the current kernel source."""
+def measured_counters(kernel, n):
+    """The committed PMC record of a kernel at size n (HBM bytes per launch, executed FLOP per pair),
+    if the counters were taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -144,7 +149,7 @@ def measured_traffic(kernel, n):
         return None
     if not rec or rec.get("source_sha") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
 
 
 def time_variant(ctx, d, mb, name, precision, guess, steps, warmup, near_cutoff=0.0, near_order=2):
@@ -182,14 +187,22 @@ def roofline(v, n):
     if cnt == 0 or t_ms <= 0:
         return None
     per_launch_s = t_ms / cnt / 1e3
-    flop = P2_FLOP_PER_PAIR * n * (n - 1)
-    achieved = flop / per_launch_s / 1e12
+    pairs = n * (n - 1)
+    achieved = P2_FLOP_PER_PAIR_ALG * pairs / per_launch_s / 1e12
     peak = FP32_PEAK_TF if use32 else FP64_PEAK_TF
     kernel = "k_p2_f32" if use32 else "k_p2_f64"
-    return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": measured_traffic(kernel, n), "avg_launch_ms": round(per_launch_s * 1e3, 4),
-            "flop_per_pair": P2_FLOP_PER_PAIR}
+    rec = measured_counters(kernel, n) or {}
+    out = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
+           "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+           "traffic": rec.get("bytes_per_launch"), "avg_launch_ms": round(per_launch_s * 1e3, 4),
+           "frac_basis": f"algorithmic: {P2_FLOP_PER_PAIR_ALG} FLOP per pair block (the survey count) x N(N-1)",
+           "flop_per_pair": P2_FLOP_PER_PAIR_ALG,
+           "implemented_flop_per_pair": P2_FLOP_PER_PAIR,
+           "frac_implemented": round(P2_FLOP_PER_PAIR * pairs / per_launch_s / 1e12 / peak, 4)}
+    ex = rec.get("executed_flop_per_pair")
+    out["executed_flop_per_pair"] = ex
+    out["frac_executed"] = round(ex * pairs / per_launch_s / 1e12 / peak, 4) if ex else None
+    return out
 
 
 def bench_kernels(ctx, a):
@@ -227,7 +240,8 @@ def bench_kernels(ctx, a):
         for name, prec in (("p2_f64", mbstokes.MBS_FP64), ("p2_f32", mbstokes.MBS_FP32)):
             ms = median_ms(lambda: ctx.mbs_matvec(d["R"], x, y, precision=prec))
             row[name] = {"ms": round(ms, 4), "pair_blocks_per_s": n * (n - 1) / (ms * 1e-3),
-                         "tflops_algorithmic": round(P2_FLOP_PER_PAIR * n * (n - 1) / (ms * 1e-3) / 1e12, 3)}
+                         "tflops_algorithmic": round(P2_FLOP_PER_PAIR_ALG * n * (n - 1) / (ms * 1e-3) / 1e12, 3),
+                         "tflops_implemented": round(P2_FLOP_PER_PAIR * n * (n - 1) / (ms * 1e-3) / 1e12, 3)}
         if n == a.n:
             # as in the benchmark solve: no torque, no rank-3 slip
             ms = median_ms(lambda: ctx.mbs_rhs(d["R"], d["v2s"], None, d["Fe"], None))
@@ -447,25 +461,174 @@ def bench_paper_trap(ctx, a):
     return out
 
 
-def cpu_baseline(w, seconds):
-    """The oracle's system-operator rows on host cores: pair-blocks/s on a bounded row sample."""
+def _host_info():
+    """Host cores available to this process and the CPU model (from /proc/cpuinfo)."""
+    import platform
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    # one GPU's share of the host: at most 16 worker processes
+    cores = max(1, min(avail, 16, int(os.environ.get("OMP_NUM_THREADS", avail) or avail)))
+    return {"cores_available": avail, "cores_used": cores, "cpu_model": model, "nproc": os.cpu_count()}
+
+
+_CPU = {}
+
+
+def _cpu_init(R, x, eta, a):
+    _CPU.update(R=R, x=x, eta=eta, a=a)
+
+
+def _cpu_rows_for(seconds):
+    """Oracle operator rows (all sources) until the time is up; returns (rows, seconds)."""
     import numpy as np
 
     from oracle import galerkin
-    prm = galerkin.Params(eta=w.eta, a=w.a)
-    x = np.random.default_rng(0).standard_normal((w.n, 5))
-    galerkin.matvec_rows(w.R, x, np.array([0]), prm)  # builds the symbolic blocks (untimed)
-    rows_done = 0
-    rng = np.random.default_rng(1)
+    R, x = _CPU["R"], _CPU["x"]
+    prm = galerkin.Params(eta=_CPU["eta"], a=_CPU["a"])
+    galerkin.matvec_rows(R, x, np.array([0]), prm)  # builds the symbolic blocks (untimed)
+    rng = np.random.default_rng(os.getpid())
+    rows = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        rows = rng.choice(w.n, 4, replace=False)
-        galerkin.matvec_rows(w.R, x, rows, prm)
-        rows_done += len(rows)
-    dt = time.perf_counter() - t0
-    return {"value": rows_done * (w.n - 1) / dt, "unit": "pair-blocks/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rows_done} rows of the system operator against all {w.n} sources "
-                      f"({rows_done * (w.n - 1):.3g} pair blocks, {dt:.1f} s, numpy single thread)"}
+        galerkin.matvec_rows(R, x, rng.choice(len(R), 2, replace=False), prm)
+        rows += 2
+    return rows, time.perf_counter() - t0
+
+
+def _cpu_subset_rows(job):
+    """Rows of the oracle's dense system, right-hand side and outputs for a standalone workload."""
+    from oracle import galerkin
+    kind, w, rows, extra = job
+    prm = galerkin.Params(eta=w.eta, a=w.a)
+    if kind == "A":
+        return galerkin.pair_matrix(w.R, "E", "S", prm, rows), galerkin.rhs(w.R, w.v2s, w.v3t, w.Fe, w.Te, prm, rows)
+    return galerkin.outputs(w.R, w.v1s, w.v2s, w.v3t, w.Fe, w.Te, extra, prm, rows)
+
+
+def _cpu_pool(cores, initargs=None):
+    """Spawned worker processes with one BLAS thread each (they run only the oracle, never the GPU)."""
+    import multiprocessing as mp
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    for k in keys:
+        os.environ[k] = "1"
+    try:
+        if initargs is None:
+            return mp.get_context("spawn").Pool(cores)
+        return mp.get_context("spawn").Pool(cores, initializer=_cpu_init, initargs=initargs)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def cpu_baseline(w, seconds, gpu_beside):
+    """The oracle timed on the host's cores (one GPU's share, at most 16):
+    * operator rows of the benchmark workload against all its sources, in parallel worker
+      processes for about `seconds`: pair-blocks/s (the bench line's unit);
+    * the N = 256 workload end to end (dense assembly, LAPACK solve, outputs) as the oracle runs it:
+      serial assembly, LAPACK on all used cores;
+    * the 2000 spheres nearest the trap centre of the benchmark workload solved as their own system:
+      rows assembled in the worker processes, LAPACK solve on all used cores, outputs in the workers.
+    gpu_beside: the GPU's times for the same two solves, reported next to them."""
+    import numpy as np
+
+    from oracle import galerkin
+    from paper_1411_0278_amd import inputs
+    host = _host_info()
+    cores = host["cores_used"]
+    x = np.random.default_rng(0).standard_normal((w.n, 5))
+    with _cpu_pool(cores, (w.R, x, w.eta, w.a)) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_cpu_rows_for, [seconds] * cores, chunksize=1)
+        wall = time.perf_counter() - t0
+    rows = sum(r for r, _ in res)
+    span = max(s for _, s in res)
+    out = {"value": rows * (w.n - 1) / span, "unit": "pair-blocks/s", "cores": cores, "kind": "oracle",
+           "sample": f"{rows} rows of the system operator against all {w.n} sources ({rows * (w.n - 1):.3g} "
+                     f"pair blocks) in {cores} worker processes, {span:.1f} s each ({wall:.1f} s with start-up), "
+                     f"numpy one thread per process",
+           "host": host}
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    limit = threadpool_limits(limits=cores) if threadpool_limits else None
+    try:
+        w0 = inputs.config0()
+        galerkin.solve(inputs.trap_workload(8, 10.0, 0), galerkin.Params(eta=w0.eta, a=w0.a))  # symbolic set-up
+        t0 = time.perf_counter()
+        galerkin.solve(w0, galerkin.Params(eta=w0.eta, a=w0.a))
+        out["config0_end_to_end_s"] = round(time.perf_counter() - t0, 3)
+        ws = inputs.nearest_to_origin(w, 2000)
+        prm = galerkin.Params(eta=ws.eta, a=ws.a)
+        g = galerkin.constants(prm)["gamma"]
+        blocks = np.array_split(np.arange(ws.n), 4 * cores)
+        with _cpu_pool(cores) as pool:
+            t0 = time.perf_counter()
+            parts = pool.map(_cpu_subset_rows, [("A", ws, r, None) for r in blocks])
+            K = np.concatenate([p[0] for p in parts])
+            b = np.concatenate([p[1] for p in parts])
+            t_asm = time.perf_counter() - t0
+            t1 = time.perf_counter()
+            sig = np.linalg.solve(np.eye(5 * ws.n) / g - K, b).reshape(-1, 5)
+            t_lu = time.perf_counter() - t1
+            t1 = time.perf_counter()
+            pool.map(_cpu_subset_rows, [("O", ws, r, sig) for r in blocks])
+            t_out = time.perf_counter() - t1
+            out["subset2000_standalone_s"] = round(time.perf_counter() - t0, 3)
+        out["subset2000_phases_s"] = {"assembly": round(t_asm, 3), "lapack_solve": round(t_lu, 3),
+                                      "outputs": round(t_out, 3)}
+    finally:
+        if limit is not None:
+            limit.restore_original_limits()
+    out["gpu_beside"] = gpu_beside
+    return out
+
+
+def bench_small_solves(a, w):
+    """GPU time to solution of the two workloads the CPU oracle also solves end to end: N = 256
+    (density 0.004) and the 2000 spheres nearest the trap centre of the benchmark workload, binary64
+    GMRES from zero to 1e-10, plain and with the near-field preconditioner (8a, order 2). Fresh
+    context, shapes autotuned per size; median of 5 solves after 2 warm-ups (the Arnoldi steps replay
+    from graphs from the second solve on)."""
+    import statistics
+
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+    out = {}
+    for name, wl in (("config0_n256", inputs.config0()), ("subset2000", inputs.nearest_to_origin(w, 2000))):
+        ctx = mbstokes.Context(0)
+        d = mbstokes.to_device(wl, "cuda:0")
+        ctx.mbs_autotune(d["R"], None)
+        args = (d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
+        row = {"n": wl.n}
+        for label, cut in (("fp64", 0.0), ("fp64_pc", 8.0)):
+            ctx.set_params(precision=mbstokes.MBS_FP64, tol=1e-10, near_cutoff=cut, near_order=2)
+            times = []
+            for k in range(7):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, _, st = ctx.mbs_solve(*args)
+                torch.cuda.synchronize()
+                if k >= 2:
+                    times.append(1e3 * (time.perf_counter() - t0))
+            row[label] = {"ms": round(statistics.median(times), 4), "iters": st["iters"], "rel_resid": st["rel_resid"]}
+        ctx.close()
+        out[name] = row
+        print(f"bench: small solve {name} {row}", file=sys.stderr, flush=True)
+    return out
 
 
 def bench_scale(a):
@@ -618,12 +781,13 @@ def main():
         "variants": variants,
         **extra,
     }
+    ctx.close()
     if not a.skip_cpu:
+        beside = bench_small_solves(a, w)
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, beside)
     else:
         out["cpu_baseline"] = None
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 
