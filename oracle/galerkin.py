@@ -183,3 +183,93 @@ def matvec_rows(R, x, rows, prm: Params):
     x = np.asarray(x).reshape(-1, 5)
     y = x[rows] / g - (pair_matrix(R, "E", "S", prm, rows) @ np.ravel(x)).reshape(-1, 5)
     return y
+
+
+# ---------------------------------------------------------------- traction ranks <= 3
+# The quadratic-order traction modes of the minimal truncation (section IV: septlet Gamma, vortlet
+# Psi, potential dipole D) as unknowns. Each sphere's exterior flow is written through the
+# equivalent slips X^gam (7-basis), X^psi (5-basis), X^d (the slips a lone sphere would need to
+# produce the same flow of that mode) beside the flow stresslet Sigma. The Galerkin conditions of
+# the l = 2 surface modes (section III coefficients V^(3), decomposed as in section IV) read
+#     X^alpha_n + P^alpha[ sum_{m != n} u_m ](R_n) = v^alpha_n     (prescribed slip of mode alpha),
+# u_m the flow of sphere m (force, torque, Sigma, the three equivalent slips, spinlet slip), and the
+# stresslet rows keep their form with the new modes' flows among the coupled sources:
+#     Sigma_n / gamma - E[ sum_m u_m(Sigma, X) ] = E[ sum_m u_m(F, T, lambda) ] - c s_n.
+# Unknowns per sphere: [Sigma (5), X^gam (7), X^psi (5), X^d (3)] = 20.
+RANK3_BLOCKS = (("E", "S", 5), ("GAM", "SEPT7", 7), ("PSI", "VORT", 5), ("DD", "D", 3))
+RANK3_DIM = 20
+
+
+def _rank3_offsets():
+    off, o = {}, 0
+    for tgt, src, dim in RANK3_BLOCKS:
+        off[tgt] = off[src] = (o, dim)
+        o += dim
+    return off
+
+
+def system_matrix_rank3(R, prm: Params):
+    """A [20N x 20N] of the rank <= 3 system (unknowns interleaved per sphere as above)."""
+    R = np.asarray(R, dtype=np.float64)
+    n = len(R)
+    g = constants(prm)["gamma"]
+    off = _rank3_offsets()
+    A = np.zeros((n, RANK3_DIM, n, RANK3_DIM))
+    for tgt, _, _ in RANK3_BLOCKS:
+        to, td = off[tgt]
+        sign = -1.0 if tgt == "E" else 1.0
+        for _, src, _ in RANK3_BLOCKS:
+            so, sd = off[src]
+            blk = pair_matrix(R, tgt, src, prm).reshape(n, td, n, sd)
+            A[:, to:to + td, :, so:so + sd] += sign * blk
+        diag = 1.0 / g if tgt == "E" else 1.0
+        for i in range(n):
+            A[i, to:to + td, i, to:to + td] += diag * np.eye(td)
+    return A.reshape(n * RANK3_DIM, n * RANK3_DIM)
+
+
+def _prescribed_quadratic(w):
+    """The prescribed quadratic-order slips of a workload in the unknowns' coordinates."""
+    from .basis import sym3_from10, to7
+    n = len(w.R)
+    gam = getattr(w, "gam", None)
+    psi = getattr(w, "psi", None)
+    g7 = to7(sym3_from10(gam)) if gam is not None else np.zeros((n, 7))
+    p5 = np.asarray(psi, dtype=np.float64) if psi is not None else np.zeros((n, 5))
+    d3 = np.asarray(w.v3t, dtype=np.float64) if w.v3t is not None else np.zeros((n, 3))
+    return g7, p5, d3
+
+
+def rhs_rank3(w, prm: Params):
+    """b [20N]: the fixed sources (force, torque, spinlet slip) and the prescribed slips."""
+    R = np.asarray(w.R, dtype=np.float64)
+    n = len(R)
+    off = _rank3_offsets()
+    b = np.zeros((n, RANK3_DIM))
+    g7, p5, d3 = _prescribed_quadratic(w)
+    fixed = {k: v for k, v in {"F": w.Fe, "T": w.Te, "SPIN": getattr(w, "lam", None)}.items() if v is not None}
+    for tgt, _, _ in RANK3_BLOCKS:
+        to, td = off[tgt]
+        acc = np.zeros(n * td)
+        for kind, vals in fixed.items():
+            acc = acc + pair_matrix(R, tgt, kind, prm) @ np.ravel(vals)
+        b[:, to:to + td] = acc.reshape(n, td) if tgt == "E" else -acc.reshape(n, td)
+    b[:, 0:5] -= prm.self_slip_c * np.asarray(w.v2s)
+    b[:, 5:12] += g7
+    b[:, 12:17] += p5
+    b[:, 17:20] += d3
+    return b.ravel()
+
+
+def solve_rank3(w, prm: Params | None = None):
+    """Dense solve of the rank <= 3 system for a workload (fields R, v1s, v2s, v3t, Fe, Te and
+    optionally gam, psi, lam). Returns V, W, S, Sigma, the equivalent slips gam7 [N, 7], psi [N, 5],
+    d [N, 3], and b, A."""
+    prm = prm or Params(eta=getattr(w, "eta", 1.0 / (6 * np.pi)), a=getattr(w, "a", 1.0))
+    A = system_matrix_rank3(w.R, prm)
+    b = rhs_rank3(w, prm)
+    x = np.linalg.solve(A, b).reshape(-1, RANK3_DIM)
+    Sigma, g7, p5, d3 = x[:, 0:5], x[:, 5:12], x[:, 12:17], x[:, 17:20]
+    modes = {"SEPT7": g7, "VORT": p5, "SPIN": getattr(w, "lam", None)}
+    V, W, S = outputs(w.R, w.v1s, w.v2s, d3, w.Fe, w.Te, Sigma, prm, modes=modes)
+    return dict(V=V, W=W, S=S, Sigma=Sigma, gam7=g7, psi=p5, d=d3, b=b, A=A)

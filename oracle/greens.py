@@ -68,8 +68,8 @@ from . import basis
 x_, y_, z_, r_, a_, P_ = sp.symbols("x y z r a P", positive=True)
 _X = (x_, y_, z_)
 
-SOURCE_DIM = {"F": 3, "T": 3, "S": 5, "D": 3, "SEPT": 10, "VORT": 5, "SPIN": 10}
-TARGET_DIM = {"U": 3, "W": 3, "E": 5}
+SOURCE_DIM = {"F": 3, "T": 3, "S": 5, "D": 3, "SEPT": 10, "VORT": 5, "SPIN": 10, "SEPT7": 7}
+TARGET_DIM = {"U": 3, "W": 3, "E": 5, "GAM": 7, "PSI": 5, "DD": 3}
 
 
 def _canon(f):
@@ -161,6 +161,16 @@ def source_flow(kind):
                         acc += T[l][j][k] * d(d(G[i][l], j), k)
                 u.append(sp.Rational(7, 48) * a_ ** 5 * faxen(acc, 2))
             cols.append(u)
+    elif kind == "SEPT7":  # the septlet flow per unit coordinate of the 7-basis (basis.BASIS3)
+        for T in basis.BASIS3_EXACT:
+            u = []
+            for i in range(3):
+                acc = 0
+                for l, j, k in _IDX3:
+                    if T[l][j][k] != 0:
+                        acc += T[l][j][k] * d(d(G[i][l], j), k)
+                u.append(sp.Rational(7, 48) * a_ ** 5 * faxen(acc, 2))
+            cols.append(u)
     elif kind == "VORT":
         for c in range(5):
             B = [[sp.nsimplify(basis.BASIS[c][i, j], [sp.sqrt(2), sp.sqrt(6)]) for j in range(3)] for i in range(3)]
@@ -176,7 +186,42 @@ def source_flow(kind):
     return tuple(tuple(_canon(e) for e in col) for col in cols)
 
 
+def _quadratic_coefficient(u):
+    """V^(3) / a^2 of an incident flow: the l = 2 surface coefficient (5/(4 pi a^2)) int u_i Y^(2)_jk dS
+    (section III), which for a biharmonic flow is a^2 times the part of F^2 d_j d_k u_i at the
+    centre that is symmetric and traceless in (j, k)."""
+    v = [faxen(ui, 2) for ui in u]
+    H = [[[d(d(v[i], j), k) for k in range(3)] for j in range(3)] for i in range(3)]
+    S = [[[None] * 3 for _ in range(3)] for _ in range(3)]
+    for i in range(3):
+        tr = H[i][0][0] + H[i][1][1] + H[i][2][2]
+        for j in range(3):
+            for k in range(3):
+                S[i][j][k] = _canon(sp.Rational(1, 2) * (H[i][j][k] + H[i][k][j]) - int(j == k) * tr / 3)
+    return S
+
+
 def _target(kind, u):
+    if kind in ("GAM", "PSI", "DD"):
+        # irreducible parts of V^(3) = a^2 [gamma - (2/3) Delta.(eps.psi) + (3/5) Delta.delta d]
+        # (section IV, minimal truncation): gamma its symmetric traceless part, d its contraction of
+        # the velocity index with the first harmonic index, psi minus its symmetric contraction with
+        # eps over those two indices; gamma in the 7-basis, psi in the 5-basis
+        S = _quadratic_coefficient(u)
+        if kind == "GAM":
+            return [_canon(sum(B[i][j][k] * S[i][j][k] for i, j, k in _IDX3 if B[i][j][k] != 0))
+                    for B in basis.BASIS3_EXACT]
+        if kind == "DD":
+            return [_canon(S[0][0][k] + S[1][1][k] + S[2][2][k]) for k in range(3)]
+        eps = lambda p, q, s: sp.LeviCivita(p, q, s)  # noqa: E731
+        C = [[-sum(eps(l, i, j) * S[i][j][k] for i in range(3) for j in range(3)) for k in range(3)]
+             for l in range(3)]
+        out = []
+        for c in range(5):
+            B = basis.BASIS[c]
+            out.append(_canon(sum(sp.nsimplify(B[l, k], [sp.sqrt(2), sp.sqrt(6)]) * C[l][k]
+                                  for l in range(3) for k in range(3) if B[l, k] != 0.0)))
+        return out
     if kind == "U":
         return [faxen(ui, 0) for ui in u]
     if kind == "W":

@@ -4,7 +4,10 @@ The paper has no learned component; this follows the warm-start definition of th
 a 3-layer perceptron 80 -> 128 -> 128 -> 5 with ReLU, whose input is each sphere's 16 nearest
 neighbours (by centre distance, ties by index, nearest first), each contributing
 (R_j - R_i)/|R_j - R_i|, 1/|R_j - R_i| and p_j . p_i, and whose output is the correction
-Sigma - gamma b to the one-body (diagonal) guess of the stresslet rows.
+Sigma - gamma b to the one-body (diagonal) guess of the stresslet rows. An optional wider input
+(160 features, ``features_rhs``) adds each neighbour's one-body stresslet gamma b_j (5 values in
+the orthonormal 5-basis) after its five geometric features; the network then reads 160 inputs.
+The input width of a parameter vector follows from its length.
 
 The GPU network multiplies bfloat16 operands with float32 accumulation. ``forward`` mirrors the
 precision steps (round inputs, weights and hidden activations to bfloat16, round-to-nearest-even
@@ -14,15 +17,34 @@ network, whose gradient is checked against central finite differences.
 import numpy as np
 
 N_IN, N_HID, N_OUT, K_NEIGH = 80, 128, 5, 16
-SHAPES = [("W1", (N_IN, N_HID)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
-          ("W3", (N_HID, N_OUT)), ("b3", (N_OUT,))]
-N_PARAM = sum(int(np.prod(s)) for _, s in SHAPES)
+N_IN_RHS = 160  # the wider input: 16 neighbours x (5 geometric features + gamma b_j)
+
+
+def shapes(n_in=N_IN):
+    return [("W1", (n_in, N_HID)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
+            ("W3", (N_HID, N_OUT)), ("b3", (N_OUT,))]
+
+
+def n_param(n_in=N_IN):
+    return sum(int(np.prod(s)) for _, s in shapes(n_in))
+
+
+SHAPES = shapes(N_IN)
+N_PARAM = n_param(N_IN)
+
+
+def input_width(flat):
+    """Input width of a parameter vector (its length fixes the first layer)."""
+    rest = n_param(0)
+    n_in, r = divmod(len(np.ravel(flat)) - rest, N_HID)
+    assert r == 0 and n_in > 0, len(np.ravel(flat))
+    return n_in
 
 
 def unpack(flat):
     flat = np.asarray(flat, dtype=np.float64)
     out, k = {}, 0
-    for name, shp in SHAPES:
+    for name, shp in shapes(input_width(flat)):
         sz = int(np.prod(shp))
         out[name] = flat[k:k + sz].reshape(shp)
         k += sz
@@ -30,7 +52,7 @@ def unpack(flat):
 
 
 def pack(d):
-    return np.concatenate([np.ravel(d[name]) for name, _ in SHAPES])
+    return np.concatenate([np.ravel(d[name]) for name, _ in shapes(d["W1"].shape[0])])
 
 
 def bf16(x):
@@ -102,3 +124,12 @@ def features(R, p, k=K_NEIGH):
     f = np.concatenate([rel / r[..., None], (1.0 / r)[..., None],
                         np.einsum("nkc,nc->nk", p[nb], p)[..., None]], axis=2)
     return f.reshape(R.shape[0], 5 * k), nb
+
+
+def features_rhs(R, p, gb, k=K_NEIGH):
+    """[n, 10k] features: for each neighbour (order of knn()) its five geometric features followed
+    by its one-body stresslet gamma b_j [n, 5] (the diagonal solve of the stresslet rows)."""
+    f, nb = features(R, p, k)
+    gb = np.asarray(gb, dtype=np.float64)
+    f = np.concatenate([f.reshape(-1, k, 5), gb[nb]], axis=2)
+    return f.reshape(len(R), 10 * k), nb

@@ -113,7 +113,7 @@ def test_higher_slip_modes_do_not_move_a_lone_sphere(src):
         assert np.abs(mean).max() < 1e-15 and np.abs(rot).max() < 1e-15
 
 
-@pytest.mark.parametrize("src", ["F", "T", "S", "D", "SEPT", "VORT", "SPIN"])
+@pytest.mark.parametrize("src", ["F", "T", "S", "D", "SEPT", "VORT", "SPIN", "SEPT7"])
 def test_source_flows_are_stokes_flows(src):
     """Divergence free and biharmonic, exactly (symbolic)."""
     for col in greens.source_flow(src):
@@ -124,7 +124,7 @@ def test_source_flows_are_stokes_flows(src):
 
 
 # ---------------------------------------------------------------- target operators = Galerkin projections
-@pytest.mark.parametrize("src", ["F", "T", "S", "D", "SEPT", "VORT", "SPIN"])
+@pytest.mark.parametrize("src", ["F", "T", "S", "D", "SEPT", "VORT", "SPIN", "SEPT7"])
 def test_target_operators_equal_surface_integral_coefficients(src):
     rng = np.random.default_rng(7)
     nh, w = sphere_quad.sphere_rule(48, 96)
@@ -141,6 +141,47 @@ def test_target_operators_equal_surface_integral_coefficients(src):
             assert np.abs(sphere_quad.axial(V2, A) - W[:, q]).max() < 1e-12 * scale / A
             assert np.abs(basis.to5(V2 / A) - E[:, q]).max() < 1e-12 * scale / A
             assert abs(np.trace(V2)) < 1e-12 * scale * A          # no net flux
+
+
+@pytest.mark.parametrize("src", ["F", "T", "S", "D", "SEPT7", "VORT", "SPIN"])
+def test_quadratic_mode_projections_equal_surface_integral_coefficients(src):
+    """The septlet, vortlet and potential-dipole projections of an incident flow (the irreducible
+    parts of its l = 2 surface coefficient V^(3), section III definition, decomposed as in the
+    minimal truncation of section IV) equal the surface integrals by quadrature."""
+    rng = np.random.default_rng(17)
+    nh, w = sphere_quad.sphere_rule(48, 96)
+    for x in _rand_sep(rng, 2):
+        u = greens.flow(src, x[None, :] + A * nh, A, ETA)
+        G = greens.block("GAM", src, x[None], A, ETA)[0]
+        Ps = greens.block("PSI", src, x[None], A, ETA)[0]
+        D = greens.block("DD", src, x[None], A, ETA)[0]
+        for q in range(u.shape[2]):
+            gam, psi, dv = sphere_quad.quadratic_parts(sphere_quad.quadratic_coefficient(u[:, :, q], nh, w), A)
+            scale = np.abs(u[:, :, q]).max() / A ** 2
+            assert np.abs(basis.to7(gam) - G[:, q]).max() < 1e-11 * scale
+            assert np.abs(basis.to5(psi) - Ps[:, q]).max() < 1e-11 * scale
+            assert np.abs(dv - D[:, q]).max() < 1e-11 * scale
+
+
+def test_quadratic_mode_slip_fields_project_onto_themselves():
+    """Each quadratic-order slip mode's surface field (septlet (a^2/2) gamma:nn, vortlet
+    -(a^2/3) n x (psi.n), potential dipole (a^2/10)(3nn - I).d) has exactly its own coefficient in
+    the decomposition of V^(3) and none of the others; the 7-basis coordinates invert."""
+    rng = np.random.default_rng(18)
+    nh, w = sphere_quad.sphere_rule(16, 32)
+    c7 = rng.standard_normal(7)
+    g = basis.from7(c7)
+    assert np.allclose(basis.to7(g), c7, rtol=0, atol=1e-14)
+    fields = {"gam": A ** 2 / 2 * np.einsum("ijk,pj,pk->pi", g, nh, nh)}
+    psi = basis.from5(rng.standard_normal(5))
+    fields["psi"] = -A ** 2 / 3 * np.cross(nh, nh @ psi.T)
+    dv = rng.standard_normal(3)
+    fields["d"] = A ** 2 / 10 * (3 * nh * (nh @ dv)[:, None] - dv)
+    want = {"gam": (g, 0 * psi, 0 * dv), "psi": (0 * g, psi, 0 * dv), "d": (0 * g, 0 * psi, dv)}
+    for name, v in fields.items():
+        got = sphere_quad.quadratic_parts(sphere_quad.quadratic_coefficient(v, nh, w), A)
+        for x, y in zip(got, want[name]):
+            assert np.abs(x - y).max() < 1e-14, name
 
 
 # ---------------------------------------------------------------- textbook pair mobilities
@@ -265,6 +306,65 @@ def test_solution_satisfies_weak_boundary_conditions_by_quadrature(higher):
         assert np.abs(mean - (sol["V"][i] + w.v1s[i])).max() < 1e-11 * scale      # V - V^a
         assert np.abs(sphere_quad.axial(V2, A) - sol["W"][i]).max() < 1e-11 * scale / A
         assert np.abs(basis.to5(V2 / A) - w.v2s[i]).max() < 1e-11 * scale / A     # strain slip s
+
+
+def _rank3_workload(n, seed):
+    rng = np.random.default_rng(seed)
+    R = inputs.place_spheres(n, 9.0 * A, seed=seed, min_dist=2.2 * A)
+    w = inputs.Workload(R, np.zeros((n, 3)), rng.standard_normal((n, 3)), rng.standard_normal((n, 5)),
+                        rng.standard_normal((n, 3)), rng.standard_normal((n, 3)),
+                        rng.standard_normal((n, 3)), ETA, A)
+    w.gam, w.psi, w.lam = rng.standard_normal((n, 10)), rng.standard_normal((n, 5)), rng.standard_normal((n, 10))
+    return w
+
+
+def test_rank3_solution_satisfies_quadratic_boundary_conditions_by_quadrature():
+    """Traction ranks <= 3 (the quadratic-order modes of the minimal truncation, section IV, solved
+    for): on every sphere the suspension's flow has, by quadrature, the l = 0 and l = 1 surface
+    moments of the rigid motion plus the slip, and the l = 2 moments of the prescribed septlet,
+    vortlet and potential-dipole slips. The rank <= 2 solve, which keeps those modes at their
+    one-body values, misses the l = 2 conditions."""
+    n = 5
+    w = _rank3_workload(n, 8)
+    sol = galerkin.solve_rank3(w, PRM)
+    old = galerkin.solve(w, PRM)
+    nh, wq = sphere_quad.sphere_rule(48, 96)
+    g_want = basis.from7(basis.to7(basis.sym3_from10(w.gam)))
+    miss_old = 0.0
+    for i in range(n):
+        pts = w.R[i] + A * nh
+        u = galerkin.flow_field(pts, w.R, w.Fe, w.Te, sol["Sigma"], sol["d"], PRM,
+                                modes={"SEPT7": sol["gam7"], "VORT": sol["psi"], "SPIN": w.lam})
+        mean, V2 = sphere_quad.coefficients(u, nh, wq, A)
+        scale = np.abs(u).max()
+        assert np.abs(mean - (sol["V"][i] + w.v1s[i])).max() < 1e-11 * scale
+        assert np.abs(sphere_quad.axial(V2, A) - sol["W"][i]).max() < 1e-11 * scale / A
+        assert np.abs(basis.to5(V2 / A) - w.v2s[i]).max() < 1e-11 * scale / A
+        gam, psi, dv = sphere_quad.quadratic_parts(sphere_quad.quadratic_coefficient(u, nh, wq), A)
+        assert np.abs(gam - g_want[i]).max() < 1e-11 * scale / A ** 2
+        assert np.abs(basis.to5(psi) - w.psi[i]).max() < 1e-11 * scale / A ** 2
+        assert np.abs(dv - w.v3t[i]).max() < 1e-11 * scale / A ** 2
+        u_old = galerkin.flow_field(pts, w.R, w.Fe, w.Te, old["Sigma"], w.v3t, PRM, modes=galerkin.workload_modes(w))
+        g_old, _, _ = sphere_quad.quadratic_parts(sphere_quad.quadratic_coefficient(u_old, nh, wq), A)
+        miss_old = max(miss_old, np.abs(g_old - g_want[i]).max() / (np.abs(u_old).max() / A ** 2))
+    assert miss_old > 1e-4
+
+
+def test_rank3_system_reduces_and_is_consistent():
+    """A lone sphere: every equivalent slip equals its prescribed slip and the motion is the
+    one-body one; with the quadratic slips and the spinlet slip absent and the couplings of the new
+    rows removed, the rank <= 3 system's stresslet rows are the rank <= 2 system."""
+    w1 = _rank3_workload(1, 4)
+    s1 = galerkin.solve_rank3(w1, PRM)
+    g7, p5, d3 = galerkin._prescribed_quadratic(w1)
+    assert np.allclose(s1["gam7"], g7, rtol=0, atol=1e-14) and np.allclose(s1["psi"], p5, rtol=0, atol=1e-14)
+    assert np.allclose(s1["d"], d3, rtol=0, atol=1e-14)
+    ref = galerkin.solve(w1, PRM)
+    assert np.allclose(s1["V"], ref["V"], rtol=0, atol=1e-14) and np.allclose(s1["W"], ref["W"], rtol=0, atol=1e-14)
+    w = _rank3_workload(4, 6)
+    A3 = galerkin.system_matrix_rank3(w.R, PRM).reshape(4, 20, 4, 20)
+    A2 = galerkin.system_matrix(w.R, PRM).reshape(4, 5, 4, 5)
+    assert np.abs(A3[:, 0:5, :, 0:5] - A2).max() < 1e-15 * np.abs(A2).max()
 
 
 # ---------------------------------------------------------------- two-sphere mobilities (Batchelor / Jeffrey-Onishi)
@@ -522,17 +622,19 @@ def test_bf16_rounding_is_round_to_nearest_even():
     assert abs(got[5] - 3.0e-3) <= 3.0e-3 * 2 ** -8
 
 
-def test_mlp_gradient_matches_finite_differences():
+@pytest.mark.parametrize("n_in", [80, 160])
+def test_mlp_gradient_matches_finite_differences(n_in):
     from oracle import mlp
     rng = np.random.default_rng(0)
-    flat = rng.standard_normal(mlp.N_PARAM) * 0.2
-    X = rng.standard_normal((7, mlp.N_IN))
+    npar = mlp.n_param(n_in)
+    flat = rng.standard_normal(npar) * 0.2
+    X = rng.standard_normal((7, n_in))
     T = rng.standard_normal((7, mlp.N_OUT))
     loss, g = mlp.loss_grad(flat, X, T, quantize=False)
-    idx = rng.choice(mlp.N_PARAM, 60, replace=False)
+    idx = rng.choice(npar, 60, replace=False)
     h = 1e-6
     for k in idx:
-        e = np.zeros(mlp.N_PARAM)
+        e = np.zeros(npar)
         e[k] = h
         fd = (mlp.loss_grad(flat + e, X, T, quantize=False)[0] - mlp.loss_grad(flat - e, X, T, quantize=False)[0]) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])) + 1e-9, (k, fd, g[k])
@@ -541,8 +643,11 @@ def test_mlp_gradient_matches_finite_differences():
 def test_mlp_parameter_count_and_shapes():
     from oracle import mlp
     assert mlp.N_PARAM == 80 * 128 + 128 + 128 * 128 + 128 + 128 * 5 + 5 == 27525
-    flat = np.arange(mlp.N_PARAM, dtype=float)
-    assert np.array_equal(mlp.pack(mlp.unpack(flat)), flat)
+    assert mlp.n_param(160) == 160 * 128 + 128 + 128 * 128 + 128 + 128 * 5 + 5 == 37765
+    for n_in in (80, 160):
+        flat = np.arange(mlp.n_param(n_in), dtype=float)
+        assert mlp.input_width(flat) == n_in
+        assert np.array_equal(mlp.pack(mlp.unpack(flat)), flat)
 
 
 def test_knn_and_features_brute_force():
@@ -559,6 +664,14 @@ def test_knn_and_features_brute_force():
         j = nb[i, 0]
         r = np.linalg.norm(R[j] - R[i])
         assert np.allclose(f[i, :5], list((R[j] - R[i]) / r) + [1 / r, p[j] @ p[i]], rtol=1e-15)
+    gb = rng.standard_normal((40, 5))
+    f2, nb2 = mlp.features_rhs(R, p, gb)
+    assert f2.shape == (40, 160) and np.array_equal(nb2, nb)
+    for i in (0, 17, 39):
+        for q in (0, 7, 15):
+            j = nb[i, q]
+            assert np.array_equal(f2[i, 10 * q:10 * q + 5], f[i, 5 * q:5 * q + 5])
+            assert np.array_equal(f2[i, 10 * q + 5:10 * q + 10], gb[j])
 
 
 def test_lone_sphere_flow_amplitudes_match_the_single_layer_constants():
