@@ -58,7 +58,7 @@ def parse():
                     help="near-field preconditioner cutoff (centre distance) of the *_pc variants")
     ap.add_argument("--skip-warmstart", action="store_true", help="no learned warm start (no training)")
     ap.add_argument("--warmstart-configs", type=int, default=200)
-    ap.add_argument("--warmstart-epochs", type=int, default=10)
+    ap.add_argument("--warmstart-epochs", type=int, default=20)
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-stepper", action="store_true")
     ap.add_argument("--skip-kernels", action="store_true", help="skip the per-size pair-pass timings")
@@ -348,7 +348,9 @@ def bench_batched(ctx, a):
         pairs = sum(st["pair_blocks"] for st in stats)
         return {"configs": len(ws), "spheres": int(off[-1]), "near_cutoff": rc, "ms_per_batch": 1e3 * dt,
                 "configs_per_s": len(ws) / dt, "pair_blocks_per_s": pairs / dt,
-                "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+                "latency_ms_min": float(lat.min()), "latency_ms_p50": float(np.percentile(lat, 50)),
+                "latency_ms_p99": float(np.percentile(lat, 99)), "latency_ms_max": float(lat.max()),
+                "launch": "one graph launch per batch from the second call of a batch shape on",
                 "max_iters": int(max(st["iters"] for st in stats)),
                 "max_rel_resid": float(max(st["rel_resid"] for st in stats))}
 
@@ -714,35 +716,46 @@ def main():
     variants = {}
     extra = {}
     rc = a.near_cutoff
-    plan = [("plain_fp64", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_ZERO, 0.0),
-            ("fp64_diag", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_DIAG, 0.0),
-            ("mixed_zero", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_ZERO, 0.0),
-            ("mixed_diag", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG, 0.0),
-            ("fp64_pc", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_ZERO, rc),
-            ("mixed_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_ZERO, rc),
-            ("mixed_diag_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG, rc)]
+    plan = [("plain_fp64", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_ZERO, 0.0, None),
+            ("fp64_diag", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_DIAG, 0.0, None),
+            ("mixed_zero", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_ZERO, 0.0, None),
+            ("mixed_diag", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG, 0.0, None),
+            ("fp64_pc", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_ZERO, rc, None),
+            ("mixed_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_ZERO, rc, None),
+            ("mixed_diag_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_DIAG, rc, None)]
+    nets = {}
     if not a.skip_warmstart:
+        import tempfile
+
         from paper_1411_0278_amd import warmstart
-        print("bench: training the warm-start network", file=sys.stderr, flush=True)
-        rep = warmstart.train_pipeline(ctx, a.warmstart_configs, max(1, a.warmstart_configs // 20),
-                                       a.warmstart_epochs,
-                                       log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
-        plan += [("fp64_learned", mbstokes.MBS_FP64, mbstokes.MBS_GUESS_LEARNED, 0.0),
-                 ("mixed_learned", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_LEARNED, 0.0),
-                 ("mixed_learned_pc", mbstokes.MBS_MIXED, mbstokes.MBS_GUESS_LEARNED, rc)]
+        print("bench: training the warm-start networks", file=sys.stderr, flush=True)
+        wdir = tempfile.mkdtemp(prefix="mbs_bench_")
+        nets = {0: os.path.join(wdir, "geometry.bin"), 1: os.path.join(wdir, "geometry_rhs.bin")}
+        reps = warmstart.train_pipeline(ctx, a.warmstart_configs, max(1, a.warmstart_configs // 20),
+                                        a.warmstart_epochs,
+                                        log=lambda m: print("bench: " + m, file=sys.stderr, flush=True),
+                                        feature_sets=(0, 1), weights=nets)
+        L = mbstokes.MBS_GUESS_LEARNED
+        plan += [("fp64_learned", mbstokes.MBS_FP64, L, 0.0, 0), ("mixed_learned", mbstokes.MBS_MIXED, L, 0.0, 0),
+                 ("mixed_learned_pc", mbstokes.MBS_MIXED, L, rc, 0),
+                 ("fp64_learned_rhs", mbstokes.MBS_FP64, L, 0.0, 1),
+                 ("mixed_learned_rhs", mbstokes.MBS_MIXED, L, 0.0, 1),
+                 ("mixed_learned_rhs_pc", mbstokes.MBS_MIXED, L, rc, 1)]
         # surrogate error of the guesses against the converged solution of this workload
         ctx.set_params(precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-12, near_cutoff=rc,
                        near_order=a.near_order)
         sig = torch.empty((a.n, 5), dtype=torch.float64, device="cuda:0")
         ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None, Sigma=sig)
-        rep["surrogate_rel_err"] = {
-            "zero": 1.0,
-            "diag": warmstart.surrogate_error(ctx, d, sig, mbstokes.MBS_GUESS_DIAG),
-            "learned": warmstart.surrogate_error(ctx, d, sig, mbstokes.MBS_GUESS_LEARNED)}
-        extra["warmstart"] = rep
+        err = {"zero": 1.0, "diag": warmstart.surrogate_error(ctx, d, sig, mbstokes.MBS_GUESS_DIAG)}
+        for fs, key in ((0, "learned"), (1, "learned_rhs")):
+            ctx.mbs_warmstart_load(nets[fs])
+            err[key] = warmstart.surrogate_error(ctx, d, sig, L)
+        extra["warmstart"] = {"geometry_80": reps[0], "geometry_rhs_160": reps[1], "surrogate_rel_err": err}
     elif "learned" in a.headline:
         a.headline = "mixed_pc"
-    for name, prec, guess, cut in plan:
+    for name, prec, guess, cut, net in plan:
+        if net is not None:
+            ctx.mbs_warmstart_load(nets[net])
         steps = a.steps if name in (a.headline, "plain_fp64") else max(1, min(a.steps, 2))
         variants[name] = time_variant(ctx, d, mbstokes, name, prec, guess, steps, a.warmup, cut, a.near_order)
         variants[name]["near_cutoff"] = cut

@@ -342,13 +342,29 @@ int mbs_autotune_batched(mbs_ctx* ctx, int32_t nconf, const int64_t* offsets, co
                          int32_t* chosen, double* ms, void* stream);
 
 /* ---------------------------------------------------------------- learned warm start
-   A 3-layer perceptron 80 -> 128 -> 128 -> 5 (ReLU) maps the neighbourhood of each sphere to a
+   A 3-layer perceptron in -> 128 -> 128 -> 5 (ReLU) maps the neighbourhood of each sphere to a
    correction of the one-body guess: MBS_GUESS_LEARNED starts GMRES from Sigma^0 = gamma b + net(f).
    The network multiplies bfloat16 operands with float32 accumulation on the matrix cores; its
-   float32 master parameters live in the context. Parameter vector (host float32, 27525 values):
-   W1 [80 x 128] row-major (input x output), b1 [128], W2 [128 x 128], b2 [128], W3 [128 x 5], b3 [5]. */
+   float32 master parameters live in the context. Its input is one of two feature sets, chosen per
+   context with mbs_warmstart_features:
+     MBS_FEATURES_GEOMETRY (default): in = 80, the neighbourhood geometry (see mbs_features);
+     MBS_FEATURES_GEOMETRY_RHS: in = 160, each neighbour's five geometric features followed by its
+       one-body stresslet gamma b_j (the diagonal solve of its stresslet row, 5 values): the part
+       of the exact correction that the geometry alone cannot know (to first order the correction
+       is gamma^2 sum_j K(R_i - R_j) b_j).
+   Parameter vector (host float32, MBS_MLP_NPARAM or MBS_MLP_NPARAM_RHS values): W1 [in x 128]
+   row-major (input x output), b1 [128], W2 [128 x 128], b2 [128], W3 [128 x 5], b3 [5]. */
 #define MBS_MLP_NPARAM 27525
 #define MBS_MLP_NFEAT 80
+#define MBS_MLP_NPARAM_RHS 37765
+#define MBS_MLP_NFEAT_RHS 160
+#define MBS_FEATURES_GEOMETRY      0
+#define MBS_FEATURES_GEOMETRY_RHS  1
+
+/* Select the network's input feature set (MBS_FEATURES_*). The context's network is discarded
+   (MBS_GUESS_LEARNED and the mbs_warmstart_* calls that need one fail until it is initialised, set
+   or loaded again); mbs_warmstart_load selects the set the file was written with. */
+int mbs_warmstart_features(mbs_ctx* ctx, int32_t feature_set);
 
 /* Features of the warm start: for each sphere i the 16 nearest other centres j (by distance,
    ties by smaller index), nearest first, each contributing (R_j - R_i)/|R_j - R_i| (3 values),
@@ -356,16 +372,23 @@ int mbs_autotune_batched(mbs_ctx* ctx, int32_t nconf, const int64_t* offsets, co
    DEVICE receives the neighbour indices. Requires n >= 17. */
 int mbs_features(mbs_ctx* ctx, int64_t n, const double* R, const double* p, float* feat, int32_t* nbr,
                  void* stream);
+/* The features of the context's feature set: as mbs_features for MBS_FEATURES_GEOMETRY; for
+   MBS_FEATURES_GEOMETRY_RHS feat [n x 160], per neighbour the five values above and then gamma b_j,
+   where b [n x 5] binary64 DEVICE is the right-hand side of the same spheres (mbs_rhs; required for
+   that set, else ignored). */
+int mbs_features_ex(mbs_ctx* ctx, int64_t n, const double* R, const double* p, const double* b, float* feat,
+                    int32_t* nbr, void* stream);
 /* Initialise the network: He-uniform weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)) from a 64-bit
    Mersenne twister seeded with `seed`, zero biases; resets the Adam state. */
 int mbs_warmstart_init(mbs_ctx* ctx, uint64_t seed);
-/* Replace / read the parameters (host float32 [MBS_MLP_NPARAM]); set resets the Adam state. */
+/* Replace / read the parameters (host float32, MBS_MLP_NPARAM or MBS_MLP_NPARAM_RHS values as the
+   context's feature set); set resets the Adam state. */
 int mbs_warmstart_set(mbs_ctx* ctx, const float* params);
 int mbs_warmstart_get(mbs_ctx* ctx, float* params);
-/* out [m x 5] = net(feat [m x 80]); float32 DEVICE arrays. */
+/* out [m x 5] = net(feat [m x in]), in = 80 or 160 as the feature set; float32 DEVICE arrays. */
 int mbs_warmstart_forward(mbs_ctx* ctx, int64_t m, const float* feat, float* out, void* stream);
-/* Mean squared error L = sum (net(f) - t)^2 / (5 m) over m <= 65536 samples (feat [m x 80],
-   target [m x 5], float32 DEVICE) and its gradient (host float32 [MBS_MLP_NPARAM], layout as the
+/* Mean squared error L = sum (net(f) - t)^2 / (5 m) over m <= 65536 samples (feat [m x in],
+   target [m x 5], float32 DEVICE) and its gradient (host float32, one value per parameter, layout as the
    parameters); *loss (may be NULL) receives L. */
 int mbs_warmstart_grad(mbs_ctx* ctx, int64_t m, const float* feat, const float* target, float* grad,
                        double* loss, void* stream);
@@ -386,7 +409,9 @@ int mbs_warmstart_target(mbs_ctx* ctx, int64_t n, const double* R, const double*
 int mbs_initial_guess(mbs_ctx* ctx, int64_t n, const double* R, const double* p, const double* v2s,
                       const double* v3t, const double* Fe, const double* Te, int32_t guess,
                       double* sigma0, void* stream);
-/* Write / read the float32 parameters (binary: "MBSW", version 1, count, values). */
+/* Write / read the float32 parameters (binary, little-endian uint32 header "MBSW", version 2, count,
+   feature set, then the values; version 1 files (no feature set) hold 80-input networks). Loading
+   selects the file's feature set in the context. */
 int mbs_warmstart_save(mbs_ctx* ctx, const char* path);
 int mbs_warmstart_load(mbs_ctx* ctx, const char* path);
 

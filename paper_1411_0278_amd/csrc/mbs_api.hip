@@ -74,6 +74,8 @@ struct mbs_ctx {
   // activation workspace, neighbour lists and features
   bool mlp_ready = false;
   int adam_step = 0;
+  int mlp_set = MBS_FEATURES_GEOMETRY;  // input features of the network (MBS_FEATURES_*)
+  MlpLayout mlp_lay = mlp_layout(kMlpIn);
   DevBuf mlp_w, mlp_g, mlp_m, mlp_v, mlp_wb, mlp_ws, mlp_part, mlp_loss, mlp_idx, knn_buf;
   // cell grid of the centres behind both neighbour searches (near-field lists, nearest neighbours)
   DevBuf grid;
@@ -86,7 +88,10 @@ struct mbs_ctx {
   DevBuf bat, btune;
   int bitem = 64;  // receivers per batched work item (mbs_autotune_batched's choice)
   hipStream_t bstream = nullptr;
+  // graphs of the last batch shape: init, one round (Arnoldi steps + certification), outputs, and the
+  // whole solve (init, bwhole_rounds rounds, outputs) once a solve of that shape has been observed
   hipGraphExec_t bgraph[4] = {nullptr, nullptr, nullptr, nullptr};
+  int bwhole_rounds = 0;
   std::vector<uintptr_t> bkey;
   // descriptors of the last batch uploaded to the workspace (offsets, item size, workspace base):
   // an identical next batch reuses them instead of rebuilding and re-uploading
@@ -577,7 +582,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t mlp_ws_bytes(int rp) {
   size_t b = 0;
-  b += align256((size_t)rp * kMlpIn * 2);
+  b += align256((size_t)rp * kMlpInMax * 2);
   b += 2 * align256((size_t)rp * kMlpHid * 2);      // H1, H2
   b += align256((size_t)rp * 16 * 2);               // dOut
   b += 2 * align256((size_t)rp * kMlpHid * 2);      // D2, D1
@@ -589,13 +594,14 @@ size_t mlp_ws_bytes(int rp) {
 }
 
 int mlp_ensure(mbs_ctx* c, int rp) {
-  CHK(ensure(c, c->mlp_w, (kMlpParams + 1) / 2 + 8));
-  CHK(ensure(c, c->mlp_g, (kMlpParams + 1) / 2 + 8));
-  CHK(ensure(c, c->mlp_m, (kMlpParams + 1) / 2 + 8));
-  CHK(ensure(c, c->mlp_v, (kMlpParams + 1) / 2 + 8));
-  CHK(ensure(c, c->mlp_wb, (kMlpIn * kMlpHid + kMlpHid * kMlpHid + kMlpHid * 16) / 4 + 64));
+  CHK(ensure(c, c->mlp_w, (kMlpParamsMax + 1) / 2 + 8));
+  CHK(ensure(c, c->mlp_g, (kMlpParamsMax + 1) / 2 + 8));
+  CHK(ensure(c, c->mlp_m, (kMlpParamsMax + 1) / 2 + 8));
+  CHK(ensure(c, c->mlp_v, (kMlpParamsMax + 1) / 2 + 8));
+  CHK(ensure(c, c->mlp_wb, (kMlpInMax * kMlpHid + kMlpHid * kMlpHid + kMlpHid * 16) / 4 + 64));
   CHK(ensure(c, c->mlp_ws, mlp_ws_bytes(rp) / 8 + 64));
-  CHK(ensure(c, c->mlp_part, (size_t)64 * kMlpHid * kMlpHid / 2 + 64));
+  // split-K partial products of the weight gradients: up to 64 chunks of [max(in, 128) x 128] floats
+  CHK(ensure(c, c->mlp_part, (size_t)64 * std::max(kMlpInMax, kMlpHid) * kMlpHid / 2 + 64));
   CHK(ensure(c, c->mlp_loss, (size_t)mlp_mse_blocks(rp) + 64));
   return MBS_OK;
 }
@@ -608,7 +614,7 @@ MlpWs mlp_carve(mbs_ctx* c, int rp) {
     return q;
   };
   MlpWs w;
-  w.X = (uint16_t*)take((size_t)rp * kMlpIn * 2);
+  w.X = (uint16_t*)take((size_t)rp * kMlpInMax * 2);
   w.H1 = (uint16_t*)take((size_t)rp * kMlpHid * 2);
   w.H2 = (uint16_t*)take((size_t)rp * kMlpHid * 2);
   w.dOut = (uint16_t*)take((size_t)rp * 16 * 2);
@@ -633,7 +639,7 @@ MlpW mlp_weights(mbs_ctx* c) {
   MlpW o;
   o.w = (float*)c->mlp_w.p;
   o.W1 = (uint16_t*)c->mlp_wb.p;
-  o.W2 = o.W1 + kMlpIn * kMlpHid;
+  o.W2 = o.W1 + kMlpInMax * kMlpHid;
   o.W3 = o.W2 + kMlpHid * kMlpHid;
   return o;
 }
@@ -645,12 +651,13 @@ void mlp_forward_rows(mbs_ctx* c, const float* feat, const int32_t* idx, int row
                       hipStream_t s) {
   const int rp = ceil16(rows);
   MlpW W = mlp_weights(c);
+  const MlpLayout& L = c->mlp_lay;
   float* part = (float*)c->mlp_part.p;
-  mlp_gather_bf16(feat, idx, rows, rp, kMlpIn, ws.X, s);
-  mlp_gemm(ws.X, kMlpIn, false, W.W1, kMlpHid, false, ws.C1, part, rp, kMlpHid, kMlpIn, 1, s);
-  mlp_bias_relu(ws.C1, W.w + kOffB1, rp, kMlpHid, ws.H1, s);
+  mlp_gather_bf16(feat, idx, rows, rp, L.in, ws.X, s);
+  mlp_gemm(ws.X, L.in, false, W.W1, kMlpHid, false, ws.C1, part, rp, kMlpHid, L.in, 1, s);
+  mlp_bias_relu(ws.C1, W.w + L.offB1, rp, kMlpHid, ws.H1, s);
   mlp_gemm(ws.H1, kMlpHid, false, W.W2, kMlpHid, false, ws.C2, part, rp, kMlpHid, kMlpHid, 1, s);
-  mlp_bias_relu(ws.C2, W.w + kOffB2, rp, kMlpHid, ws.H2, s);
+  mlp_bias_relu(ws.C2, W.w + L.offB2, rp, kMlpHid, ws.H2, s);
   mlp_gemm(ws.H2, kMlpHid, false, W.W3, 16, false, ws.C3, part, rp, 16, kMlpHid, 1, s);
 }
 
@@ -659,26 +666,27 @@ void mlp_backward_rows(mbs_ctx* c, const float* target, const int32_t* idx, int 
                        const MlpWs& ws, double* loss_parts, hipStream_t s) {
   const int rp = ceil16(rows);
   MlpW W = mlp_weights(c);
+  const MlpLayout& L = c->mlp_lay;
   float* g = (float*)c->mlp_g.p;
   float* part = (float*)c->mlp_part.p;
   const int ks = std::max(1, std::min(64, rp / 512));
-  mlp_mse_grad(ws.C3, W.w + kOffB3, target, idx, rows, rp, 1.0 / ((double)rows * kMlpOut), ws.dOut,
+  mlp_mse_grad(ws.C3, W.w + L.offB3, target, idx, rows, rp, 1.0 / ((double)rows * kMlpOut), ws.dOut,
                ws.dOut32, loss_parts, s);
   // W3, b3
   mlp_gemm(ws.H2, kMlpHid, true, ws.dOut, 16, false, ws.G2 /*scratch [128 x 16]*/, part, kMlpHid, 16,
            rp, ks, s);
-  mlp_copy_cols(ws.G2, 16, kMlpHid, kMlpOut, g + kOffW3, s);
-  mlp_colsum(ws.dOut32, rows, kMlpOut, g + kOffB3, part, s);
+  mlp_copy_cols(ws.G2, 16, kMlpHid, kMlpOut, g + L.offW3, s);
+  mlp_colsum(ws.dOut32, rows, kMlpOut, g + L.offB3, part, s);
   // through layer 3
   mlp_gemm(ws.dOut, 16, false, W.W3, 16, true, ws.G2, part, rp, kMlpHid, 16, 1, s);
   mlp_relu_mask(ws.G2, ws.H2, (int64_t)rp * kMlpHid, ws.D2, ws.G2m, s);
-  mlp_colsum(ws.G2m, rp, kMlpHid, g + kOffB2, part, s);
-  mlp_gemm(ws.H1, kMlpHid, true, ws.D2, kMlpHid, false, g + kOffW2, part, kMlpHid, kMlpHid, rp, ks, s);
+  mlp_colsum(ws.G2m, rp, kMlpHid, g + L.offB2, part, s);
+  mlp_gemm(ws.H1, kMlpHid, true, ws.D2, kMlpHid, false, g + L.offW2, part, kMlpHid, kMlpHid, rp, ks, s);
   // through layer 2
   mlp_gemm(ws.D2, kMlpHid, false, W.W2, kMlpHid, true, ws.G1, part, rp, kMlpHid, kMlpHid, 1, s);
   mlp_relu_mask(ws.G1, ws.H1, (int64_t)rp * kMlpHid, ws.D1, ws.G1m, s);
-  mlp_colsum(ws.G1m, rp, kMlpHid, g + kOffB1, part, s);
-  mlp_gemm(ws.X, kMlpIn, true, ws.D1, kMlpHid, false, g + kOffW1, part, kMlpIn, kMlpHid, rp, ks, s);
+  mlp_colsum(ws.G1m, rp, kMlpHid, g + L.offB1, part, s);
+  mlp_gemm(ws.X, L.in, true, ws.D1, kMlpHid, false, g + L.offW1, part, L.in, kMlpHid, rp, ks, s);
 }
 
 // network output for m samples: out [m x 5] float32
@@ -689,20 +697,24 @@ int mlp_forward(mbs_ctx* c, int64_t m, const float* feat, float* out, hipStream_
   MlpW W = mlp_weights(c);
   for (int64_t r0 = 0; r0 < m; r0 += kChunkRows) {
     const int rows = (int)std::min<int64_t>(kChunkRows, m - r0);
-    mlp_forward_rows(c, feat + r0 * kMlpIn, nullptr, rows, ws, s);
-    mlp_out_bias(ws.C3, W.w + kOffB3, rows, out + r0 * kMlpOut, s);
+    mlp_forward_rows(c, feat + r0 * c->mlp_lay.in, nullptr, rows, ws, s);
+    mlp_out_bias(ws.C3, W.w + c->mlp_lay.offB3, rows, out + r0 * kMlpOut, s);
   }
   return MBS_OK;
 }
 
+// features of feature set `set` (MBS_FEATURES_GEOMETRY_RHS reads b, the right-hand side [n x 5])
 int knn_features(mbs_ctx* c, int64_t n, const double* R, const double* p, float* feat, int32_t* nbr,
-                 hipStream_t s) {
+                 hipStream_t s, int set = MBS_FEATURES_GEOMETRY, const double* b = nullptr) {
   // cells of edge >= a holding about eight centres each: the 16th neighbour is usually inside the
   // 27 cells around a sphere's own
   GridView g;
   CHK(grid_of(c, n, R, c->prm.a, std::max<int64_t>(64, n / 8), &g, s));
   launch_knn16(g, nbr, s);
-  launch_features(R, p, nbr, (int)n, feat, s);
+  if (set == MBS_FEATURES_GEOMETRY_RHS)
+    launch_features(R, p, nbr, (int)n, feat, s, b, c->ph.gamma);
+  else
+    launch_features(R, p, nbr, (int)n, feat, s);
   HIPCHK(c, hipGetLastError());
   return MBS_OK;
 }
@@ -711,14 +723,14 @@ int knn_features(mbs_ctx* c, int64_t n, const double* R, const double* p, float*
 int learned_guess(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* b, double* x,
                   hipStream_t s) {
   const size_t o_feat = align256((size_t)n * kNeigh * 4);
-  const size_t o_out = o_feat + align256((size_t)n * kMlpIn * 4);
+  const size_t o_out = o_feat + align256((size_t)n * c->mlp_lay.in * 4);
   const size_t bytes = o_out + (size_t)n * kMlpOut * 4;
   CHK(ensure(c, c->knn_buf, bytes / 8 + 64));
   char* base = (char*)c->knn_buf.p;
   int32_t* nbr = (int32_t*)base;
   float* feat = (float*)(base + o_feat);
   float* out = (float*)(base + o_out);
-  CHK(knn_features(c, n, R, p, feat, nbr, s));
+  CHK(knn_features(c, n, R, p, feat, nbr, s, c->mlp_set, b));
   CHK(mlp_forward(c, n, feat, out, s));
   launch_guess_learned(b, out, c->ph.gamma, 5 * n, x, s);
   return MBS_OK;
@@ -1442,7 +1454,10 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   const int hs = m + 2;
   size_t bytes = 0;
   auto reserve = [&](size_t b) { size_t o = bytes; bytes += align256(b); return o; };
-  const size_t oV = reserve((size_t)(m + 1) * len * 8), ow = reserve(len * 8), ox = reserve(len * 8),
+  const int C = 4;  // Arnoldi steps per round
+  // Krylov basis: m + 1 vectors and C spare ones, so that the preconditioner of the steps left in a
+  // round after every cycle has ended reads inside the basis (their results are not used)
+  const size_t oV = reserve((size_t)(m + 1 + C) * len * 8), ow = reserve(len * 8), ox = reserve(len * 8),
                ob = reserve(len * 8), orr = reserve(len * 8), orec = reserve((size_t)ntot * sizeof(RecO)),
                oH = reserve((size_t)nconf * (m + 1) * (m + 1) * 8);
   size_t osm[7];
@@ -1525,7 +1540,6 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   const Phys ph = c->ph;
   const double tol = c->prm.tol;
   const int max_iter = c->prm.max_iter;
-  const int C = 4;  // Arnoldi steps per replay of the iteration graph
   const bool has_t = Te != nullptr, has_d = v3t != nullptr;
   // the four phases
   auto phase_init = [&](hipStream_t q) {
@@ -1539,7 +1553,10 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
     batched_start(bv, st.hk1, dcid, st.status, kActive, Vb, len, q);
     batched_set_int(kdev, 0, q);
   };
-  auto phase_iter = [&](hipStream_t q) {
+  // One round: C Arnoldi steps of every active configuration, then the certification of every
+  // configuration whose cycle ended (iterate update, true residual: final, or waiting to restart),
+  // the restart gate, and the count of configurations not yet final.
+  auto phase_round = [&](hipStream_t q) {
     for (int it = 0; it < C; ++it) {
       if (pc) {  // right preconditioning: w = A M^{-1} v_k
         launch_near_apply(R, Vb, ncnt, nlist, ntot, ph, zt, q, kdev, len, nt, near_order(c));
@@ -1560,9 +1577,6 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
       batched_scale(wv, st.hk1, dcid, st.status, Vb, len, kdev, len, q);
       batched_inc(kdev, q);
     }
-    batched_count(st.status, nconf, kActive, dcnt, q);
-  };
-  auto phase_fin = [&](hipStream_t q) {
     batched_backsolve(st, nconf, m, q);
     if (pc) {  // x += M^{-1} (V y) for the configurations that ended a cycle (zero elsewhere)
       batched_fill(ut, 0.0, len, q);
@@ -1578,9 +1592,9 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
     batched_resid(bv, wv, dcid, st.status, rv, len, q);
     batched_dots(rv, 0, nullptr, 1, rv, doff, st.status, kCycleDone, st.nsq, 1, nconf, q);
     batched_check(st, nconf, m, tol, max_iter, q);
-    batched_start(rv, st.hk1, dcid, st.status, kActive, Vb, len, q);
-    batched_set_int(kdev, 0, q);
-    batched_count(st.status, nconf, kActive, dcnt, q);
+    batched_start(rv, st.hk1, dcid, st.status, kRestart, Vb, len, q);
+    batched_gate(st.status, nconf, kdev, q);
+    batched_count_not(st.status, nconf, kFinal, dcnt, q);
   };
   auto phase_out = [&](hipStream_t q) {
     batched_pack_o(R, Fe, Te, xv, v3t, ph, (RecO*)rec, ntot, q);
@@ -1589,6 +1603,19 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
   };
   // graphs: captured once per batch shape (pointers and sizes), replayed afterwards
   const bool use_graph = c->prm.graph != 0;
+  auto capture = [&](hipGraphExec_t* exec, const std::function<void(hipStream_t)>& body) -> int {
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal));
+    body(bs);
+    HIPCHK(c, hipStreamEndCapture(bs, &g));
+    hipError_t e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      *exec = nullptr;
+      return set_err(c, MBS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    return MBS_OK;
+  };
   if (use_graph) {
     std::vector<uintptr_t> key = {(uintptr_t)nconf, (uintptr_t)ntot, (uintptr_t)base, (uintptr_t)R,
                                   (uintptr_t)v1s, (uintptr_t)v2s, (uintptr_t)v3t, (uintptr_t)Fe,
@@ -1618,16 +1645,10 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
           g = nullptr;
         }
       c->bkey.clear();
-      std::function<void(hipStream_t)> phases[4] = {phase_init, phase_iter, phase_fin, phase_out};
-      for (int k = 0; k < 4; ++k) {
-        hipGraph_t g = nullptr;
-        HIPCHK(c, hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal));
-        phases[k](bs);
-        HIPCHK(c, hipStreamEndCapture(bs, &g));
-        hipError_t e = hipGraphInstantiate(&c->bgraph[k], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return set_err(c, MBS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-      }
+      c->bwhole_rounds = 0;
+      CHK(capture(&c->bgraph[0], phase_init));
+      CHK(capture(&c->bgraph[1], phase_round));
+      CHK(capture(&c->bgraph[2], phase_out));
       c->bkey = key;
     }
   }
@@ -1636,35 +1657,55 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
       HIPCHK(c, hipGraphLaunch(c->bgraph[k], bs));
     } else {
       if (k == 0) phase_init(bs);
-      if (k == 1) phase_iter(bs);
-      if (k == 2) phase_fin(bs);
-      if (k == 3) phase_out(bs);
+      if (k == 1) phase_round(bs);
+      if (k == 2) phase_out(bs);
       HIPCHK(c, hipGetLastError());
     }
     return MBS_OK;
   };
-  auto active = [&](int* out) -> int {
+  auto remaining = [&](int* out) -> int {  // configurations not yet final
     HIPCHK(c, hipMemcpyAsync(out, dcnt, sizeof(int), hipMemcpyDeviceToHost, bs));
     HIPCHK(c, hipStreamSynchronize(bs));
     return MBS_OK;
   };
+  const int max_rounds = max_iter / C + 2 * (max_iter / std::max(1, m) + 2);
   HIPCHK(c, hipEventRecord(c->ev[5], bs));
-  CHK(run(0));
-  const int max_replays = max_iter / C + 2 * (max_iter / std::max(1, m) + 2);
-  int replays = 0, nact = 1;
-  while (nact > 0 && replays < max_replays) {
-    int inner = 1;
-    while (inner > 0 && replays < max_replays) {
+  int left = 1, whole_rounds = 0;
+  if (use_graph && c->bgraph[3]) {
+    // the whole solve in one launch, sized by the rounds the last solve of this shape took; the host
+    // reads one counter at the end and continues round by round only if some configuration is left
+    HIPCHK(c, hipGraphLaunch(c->bgraph[3], bs));
+    CHK(remaining(&left));
+    if (left > 0) {
+      int rounds = c->bwhole_rounds;
+      while (left > 0 && rounds < max_rounds) {
+        CHK(run(1));
+        ++rounds;
+        CHK(remaining(&left));
+      }
+      CHK(run(2));
+    }
+  } else {
+    CHK(run(0));
+    int rounds = 0;
+    while (left > 0 && rounds < max_rounds) {
       CHK(run(1));
-      ++replays;
-      CHK(active(&inner));
+      ++rounds;
+      CHK(remaining(&left));
     }
     CHK(run(2));
-    CHK(active(&nact));
+    if (use_graph && left == 0) whole_rounds = rounds;
   }
-  CHK(run(3));
   HIPCHK(c, hipEventRecord(c->ev[6], bs));
   HIPCHK(c, hipStreamSynchronize(bs));
+  if (whole_rounds > 0) {  // later solves of this shape run as one graph of this many rounds
+    CHK(capture(&c->bgraph[3], [&](hipStream_t q) {
+      phase_init(q);
+      for (int r = 0; r < whole_rounds; ++r) phase_round(q);
+      phase_out(q);
+    }));
+    c->bwhole_rounds = whole_rounds;
+  }
   // per-configuration results
   std::vector<int> its(nconf), status(nconf);
   std::vector<double> res(nconf);
@@ -1877,17 +1918,49 @@ int mbs_features(mbs_ctx* c, int64_t n, const double* R, const double* p, float*
   return MBS_OK;
 }
 
+int mbs_features_ex(mbs_ctx* c, int64_t n, const double* R, const double* p, const double* b, float* feat,
+                    int32_t* nbr, void* stream) {
+  CHK(begin_call(c));
+  if (n < kNeigh + 1) return set_err(c, MBS_EINVAL, "features need n >= %d", kNeigh + 1);
+  if (n > (int64_t)INT32_MAX / kMlpInMax) return set_err(c, MBS_EINVAL, "n too large");
+  if (!R || !p || !feat) return set_err(c, MBS_EINVAL, "R, p and feat are required");
+  const bool rhs = c->mlp_set == MBS_FEATURES_GEOMETRY_RHS;
+  if (rhs && !b) return set_err(c, MBS_EINVAL, "this feature set needs the right-hand side b");
+  hipStream_t s = (hipStream_t)stream;
+  CHK(check_inputs(c, s, {{R, 3 * n}, {rhs ? b : nullptr, 5 * n}}, p, n));
+  int32_t* nb = nbr;
+  if (!nb) {
+    CHK(ensure(c, c->knn_buf, (size_t)n * kNeigh / 2 + 64));
+    nb = (int32_t*)c->knn_buf.p;
+  }
+  CHK(knn_features(c, n, R, p, feat, nb, s, c->mlp_set, b));
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_warmstart_features(mbs_ctx* c, int32_t feature_set) {
+  CHK(begin_call(c));
+  if (feature_set != MBS_FEATURES_GEOMETRY && feature_set != MBS_FEATURES_GEOMETRY_RHS)
+    return set_err(c, MBS_EINVAL, "unknown feature set %d", feature_set);
+  c->mlp_set = feature_set;
+  c->mlp_lay = mlp_layout(feature_set == MBS_FEATURES_GEOMETRY_RHS ? kMlpInRhs : kMlpIn);
+  c->mlp_ready = false;  // the network must be initialised, set or loaded again
+  return MBS_OK;
+}
+
 int mbs_warmstart_set(mbs_ctx* c, const float* params) {
   CHK(begin_call(c));
   if (!params) return set_err(c, MBS_EINVAL, "params is NULL");
-  for (int k = 0; k < kMlpParams; ++k)
+  const MlpLayout& L = c->mlp_lay;
+  for (int k = 0; k < L.nparam; ++k)
     if (!isfinite(params[k])) return set_err(c, MBS_EINVAL, "non-finite parameter %d", k);
   CHK(mlp_ensure(c, 16));
   MlpW W = mlp_weights(c);
-  HIPCHK(c, hipMemcpy(W.w, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemset(c->mlp_m.p, 0, kMlpParams * sizeof(float)));
-  HIPCHK(c, hipMemset(c->mlp_v.p, 0, kMlpParams * sizeof(float)));
-  mlp_weights_bf16(W.w, W.W1, W.W2, W.W3, nullptr);
+  HIPCHK(c, hipMemcpy(W.w, params, L.nparam * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemset(c->mlp_m.p, 0, L.nparam * sizeof(float)));
+  HIPCHK(c, hipMemset(c->mlp_v.p, 0, L.nparam * sizeof(float)));
+  mlp_weights_bf16(W.w, L, W.W1, W.W2, W.W3, nullptr);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipDeviceSynchronize());
   c->adam_step = 0;
@@ -1898,15 +1971,16 @@ int mbs_warmstart_set(mbs_ctx* c, const float* params) {
 int mbs_warmstart_init(mbs_ctx* c, uint64_t seed) {
   CHK(begin_call(c));
   // He-uniform weights U(-sqrt(6/fan_in), sqrt(6/fan_in)), zero biases
-  std::vector<float> w(kMlpParams, 0.f);
+  const MlpLayout& L = c->mlp_lay;
+  std::vector<float> w(L.nparam, 0.f);
   std::mt19937_64 gen(seed);
   auto fill = [&](int off, int fan_in, int count) {
     std::uniform_real_distribution<double> U(-sqrt(6.0 / fan_in), sqrt(6.0 / fan_in));
     for (int k = 0; k < count; ++k) w[off + k] = (float)U(gen);
   };
-  fill(kOffW1, kMlpIn, kMlpIn * kMlpHid);
-  fill(kOffW2, kMlpHid, kMlpHid * kMlpHid);
-  fill(kOffW3, kMlpHid, kMlpHid * kMlpOut);
+  fill(L.offW1, L.in, L.in * kMlpHid);
+  fill(L.offW2, kMlpHid, kMlpHid * kMlpHid);
+  fill(L.offW3, kMlpHid, kMlpHid * kMlpOut);
   return mbs_warmstart_set(c, w.data());
 }
 
@@ -1914,14 +1988,14 @@ int mbs_warmstart_get(mbs_ctx* c, float* params) {
   CHK(begin_call(c));
   if (!params) return set_err(c, MBS_EINVAL, "params is NULL");
   if (!c->mlp_ready) return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context");
-  HIPCHK(c, hipMemcpy(params, c->mlp_w.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(params, c->mlp_w.p, c->mlp_lay.nparam * sizeof(float), hipMemcpyDeviceToHost));
   return MBS_OK;
 }
 
 int mbs_warmstart_forward(mbs_ctx* c, int64_t m, const float* feat, float* out, void* stream) {
   CHK(begin_call(c));
   if (m < 1 || !feat || !out) return set_err(c, MBS_EINVAL, "m >= 1, feat and out are required");
-  if (m > (int64_t)INT32_MAX / kMlpIn) return set_err(c, MBS_EINVAL, "m too large");
+  if (m > (int64_t)INT32_MAX / kMlpInMax) return set_err(c, MBS_EINVAL, "m too large");
   if (!c->mlp_ready) return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context");
   hipStream_t s = (hipStream_t)stream;
   CHK(mlp_forward(c, m, feat, out, s));
@@ -1947,7 +2021,7 @@ int mbs_warmstart_grad(mbs_ctx* c, int64_t m, const float* feat, const float* ta
   const int nb = mlp_mse_blocks(rp);
   std::vector<double> parts(nb);
   HIPCHK(c, hipMemcpyAsync(parts.data(), lp, nb * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(grad, c->mlp_g.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(grad, c->mlp_g.p, c->mlp_lay.nparam * sizeof(float), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   double sum = 0.0;
   for (double v : parts) sum += v;
@@ -1959,7 +2033,7 @@ int mbs_warmstart_train(mbs_ctx* c, int64_t m, const float* feat, const float* t
                         int32_t batch, double lr, uint64_t seed, double* loss_hist, void* stream) {
   CHK(begin_call(c));
   if (m < 1 || !feat || !target) return set_err(c, MBS_EINVAL, "m >= 1, feat and target are required");
-  if (m > (int64_t)INT32_MAX / kMlpIn) return set_err(c, MBS_EINVAL, "m too large");
+  if (m > (int64_t)INT32_MAX / kMlpInMax) return set_err(c, MBS_EINVAL, "m too large");
   if (epochs < 0 || batch < 16 || batch > kChunkRows || !(lr > 0.0))
     return set_err(c, MBS_EINVAL, "need epochs >= 0, 16 <= batch <= %d, lr > 0", kChunkRows);
   if (!c->mlp_ready) return set_err(c, MBS_EUNSUPPORTED, "initialise the network first");
@@ -1989,9 +2063,9 @@ int mbs_warmstart_train(mbs_ctx* c, int64_t m, const float* feat, const float* t
       const int32_t* idx = didx + bi * batch;
       mlp_forward_rows(c, feat, idx, rows, ws, s);
       mlp_backward_rows(c, target, idx, rows, ws, (double*)c->mlp_loss.p + bi * nbl, s);
-      mlp_adam(W.w, (const float*)c->mlp_g.p, (float*)c->mlp_m.p, (float*)c->mlp_v.p, kMlpParams,
+      mlp_adam(W.w, (const float*)c->mlp_g.p, (float*)c->mlp_m.p, (float*)c->mlp_v.p, c->mlp_lay.nparam,
                (float)lr, 0.9f, 0.999f, 1e-8f, ++c->adam_step, s);
-      mlp_weights_bf16(W.w, W.W1, W.W2, W.W3, s);
+      mlp_weights_bf16(W.w, c->mlp_lay, W.W1, W.W2, W.W3, s);
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(parts.data(), c->mlp_loss.p, parts.size() * sizeof(double),
@@ -2009,12 +2083,13 @@ int mbs_warmstart_save(mbs_ctx* c, const char* path) {
   CHK(begin_call(c));
   if (!path) return set_err(c, MBS_EINVAL, "path is NULL");
   if (!c->mlp_ready) return set_err(c, MBS_EUNSUPPORTED, "no warm-start network in this context");
-  std::vector<float> w(kMlpParams);
-  HIPCHK(c, hipMemcpy(w.data(), c->mlp_w.p, kMlpParams * sizeof(float), hipMemcpyDeviceToHost));
+  const int np = c->mlp_lay.nparam;
+  std::vector<float> w(np);
+  HIPCHK(c, hipMemcpy(w.data(), c->mlp_w.p, np * sizeof(float), hipMemcpyDeviceToHost));
   FILE* f = fopen(path, "wb");
   if (!f) return set_err(c, MBS_EINVAL, "cannot write %s", path);
-  const uint32_t hdr[3] = {0x5753424Du /* "MBSW" */, 1u, (uint32_t)kMlpParams};
-  const bool ok = fwrite(hdr, sizeof hdr, 1, f) == 1 && fwrite(w.data(), sizeof(float), kMlpParams, f) == (size_t)kMlpParams;
+  const uint32_t hdr[4] = {0x5753424Du /* "MBSW" */, 2u, (uint32_t)np, (uint32_t)c->mlp_set};
+  const bool ok = fwrite(hdr, sizeof hdr, 1, f) == 1 && fwrite(w.data(), sizeof(float), np, f) == (size_t)np;
   fclose(f);
   return ok ? MBS_OK : set_err(c, MBS_EINVAL, "short write to %s", path);
 }
@@ -2025,11 +2100,16 @@ int mbs_warmstart_load(mbs_ctx* c, const char* path) {
   FILE* f = fopen(path, "rb");
   if (!f) return set_err(c, MBS_EINVAL, "cannot read %s", path);
   uint32_t hdr[3] = {0, 0, 0};
-  std::vector<float> w(kMlpParams);
-  const bool ok = fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == 0x5753424Du && hdr[1] == 1u &&
-                  hdr[2] == (uint32_t)kMlpParams && fread(w.data(), sizeof(float), kMlpParams, f) == (size_t)kMlpParams;
+  uint32_t set = MBS_FEATURES_GEOMETRY;
+  bool ok = fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == 0x5753424Du && (hdr[1] == 1u || hdr[1] == 2u);
+  if (ok && hdr[1] == 2u) ok = fread(&set, sizeof set, 1, f) == 1;  // version 1: the 80-input network
+  ok = ok && (set == (uint32_t)MBS_FEATURES_GEOMETRY || set == (uint32_t)MBS_FEATURES_GEOMETRY_RHS);
+  const MlpLayout L = mlp_layout(set == (uint32_t)MBS_FEATURES_GEOMETRY_RHS ? kMlpInRhs : kMlpIn);
+  std::vector<float> w(ok ? L.nparam : 0);
+  ok = ok && hdr[2] == (uint32_t)L.nparam && fread(w.data(), sizeof(float), L.nparam, f) == (size_t)L.nparam;
   fclose(f);
   if (!ok) return set_err(c, MBS_EINVAL, "%s is not a warm-start weight file", path);
+  CHK(mbs_warmstart_features(c, (int32_t)set));
   return mbs_warmstart_set(c, w.data());
 }
 

@@ -12,6 +12,8 @@ namespace mbs {
 constexpr int kActive = 1;     // inside an Arnoldi cycle
 constexpr int kCycleDone = 2;  // cycle ended: update the iterate and check the true residual
 constexpr int kFinal = 3;      // converged (or out of iterations)
+constexpr int kRestart = 4;    // true residual short of the tolerance: restarts (Arnoldi step 0) as soon
+                               // as no configuration is inside a cycle (the step index is shared)
 
 struct BatchState {  // device arrays indexed by configuration (stride m+2 or (m+1)^2 where noted)
   double *H, *cs, *sn, *g, *y, *h1, *h2, *nsq, *bnorm, *hk1, *resid;
@@ -59,5 +61,9 @@ void batched_init(const BatchState& b, int nconf, int m, hipStream_t s);
 void batched_start(const double* r, const double* hk1, const int* cid, const int* status, int want,
                    double* V0, int64_t len, hipStream_t s);
 void batched_count(const int* status, int nconf, int want, int* out, hipStream_t s);
+// configurations whose status is not `unwanted` -> out[0]
+void batched_count_not(const int* status, int nconf, int unwanted, int* out, hipStream_t s);
+// if no configuration is inside a cycle: waiting restarts become active and the step index is reset
+void batched_gate(int* status, int nconf, int* kdev, hipStream_t s);
 
 }  // namespace mbs

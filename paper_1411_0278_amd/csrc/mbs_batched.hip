@@ -365,7 +365,7 @@ __global__ void k_bcheck(BState st, int nconf, int m, double tol, int max_iter) 
   g[0] = beta;
   for (int i = 1; i <= m; ++i) g[i] = 0.0;
   st.hk1[b] = beta;  // V_0 = r / beta
-  st.status[b] = kActive;
+  st.status[b] = kRestart;
 }
 
 // first cycle: ||b|| known in nsq; x = 0 so r = b
@@ -401,10 +401,10 @@ __global__ void k_bstart(const double* __restrict__ r, const double* __restrict_
   V0[t] = r[t] / hk1[b];
 }
 
-__global__ void k_bcount(const int* __restrict__ status, int nconf, int want, int* __restrict__ out) {
+__global__ void k_bcount(const int* __restrict__ status, int nconf, int want, int invert, int* __restrict__ out) {
   __shared__ int red[256];
   int c = 0;
-  for (int b = threadIdx.x; b < nconf; b += blockDim.x) c += status[b] == want ? 1 : 0;
+  for (int b = threadIdx.x; b < nconf; b += blockDim.x) c += (status[b] == want) != (invert != 0) ? 1 : 0;
   red[threadIdx.x] = c;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -412,6 +412,24 @@ __global__ void k_bcount(const int* __restrict__ status, int nconf, int want, in
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// One workgroup: once no configuration is inside an Arnoldi cycle, the ones waiting to restart
+// become active and the shared step index returns to 0.
+__global__ void __launch_bounds__(256) k_bgate(int* __restrict__ status, int nconf, int* __restrict__ kdev) {
+  __shared__ int red[256];
+  int c = 0;
+  for (int b = threadIdx.x; b < nconf; b += blockDim.x) c += status[b] == kActive ? 1 : 0;
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (red[0] != 0) return;  // (uniform across the workgroup)
+  for (int b = threadIdx.x; b < nconf; b += blockDim.x)
+    if (status[b] == kRestart) status[b] = kActive;
+  if (threadIdx.x == 0) kdev[0] = 0;
 }
 
 }  // namespace
@@ -549,7 +567,15 @@ void batched_start(const double* r, const double* hk1, const int* cid, const int
 }
 
 void batched_count(const int* status, int nconf, int want, int* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_bcount, dim3(1), dim3(256), 0, s, status, nconf, want, out);
+  hipLaunchKernelGGL(k_bcount, dim3(1), dim3(256), 0, s, status, nconf, want, 0, out);
+}
+
+void batched_count_not(const int* status, int nconf, int unwanted, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_bcount, dim3(1), dim3(256), 0, s, status, nconf, unwanted, 1, out);
+}
+
+void batched_gate(int* status, int nconf, int* kdev, hipStream_t s) {
+  hipLaunchKernelGGL(k_bgate, dim3(1), dim3(256), 0, s, status, nconf, kdev);
 }
 
 }  // namespace mbs

@@ -82,7 +82,8 @@ __global__ void __launch_bounds__(256) k_knn16(GridView G, int32_t* __restrict__
 }
 
 __global__ void k_features(const double* __restrict__ R, const double* __restrict__ p,
-                           const int32_t* __restrict__ nbr, int n, float* __restrict__ feat) {
+                           const int32_t* __restrict__ nbr, int n, float* __restrict__ feat,
+                           const double* __restrict__ b, double gamma) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)n * kNeigh) return;
   const int64_t i = t / kNeigh;
@@ -92,12 +93,17 @@ __global__ void k_features(const double* __restrict__ R, const double* __restric
   const double r = sqrt(rx * rx + ry * ry + rz * rz);
   const double inv = 1.0 / r;
   const double pp = p[3 * j] * p[3 * i] + p[3 * j + 1] * p[3 * i + 1] + p[3 * j + 2] * p[3 * i + 2];
-  float* f = feat + i * kMlpIn + 5 * k;
+  const int per = b ? 10 : 5;  // features per neighbour
+  float* f = feat + i * (kNeigh * per) + per * k;
   f[0] = (float)(rx * inv);
   f[1] = (float)(ry * inv);
   f[2] = (float)(rz * inv);
   f[3] = (float)inv;
   f[4] = (float)pp;
+  if (b) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) f[5 + c] = (float)(gamma * b[5 * j + c]);
+  }
 }
 
 __global__ void k_guess_learned(const double* __restrict__ b, const float* __restrict__ out, double gamma,
@@ -127,8 +133,9 @@ void launch_knn16(const GridView& g, int32_t* nbr, hipStream_t s) {
 }
 
 void launch_features(const double* R, const double* p, const int32_t* nbr, int n, float* feat,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_features, dim3(nblk((int64_t)n * kNeigh, 256)), dim3(256), 0, s, R, p, nbr, n, feat);
+                     hipStream_t s, const double* b, double gamma) {
+  hipLaunchKernelGGL(k_features, dim3(nblk((int64_t)n * kNeigh, 256)), dim3(256), 0, s, R, p, nbr, n, feat,
+                     b, gamma);
 }
 
 void launch_guess_learned(const double* b, const float* out, double gamma, int64_t len, double* x,

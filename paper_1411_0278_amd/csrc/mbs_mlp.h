@@ -5,15 +5,27 @@
 
 namespace mbs {
 
-constexpr int kMlpIn = 80, kMlpHid = 128, kMlpOut = 5, kNeigh = 16;
-// flat float32 parameter vector: W1 [80x128], b1 [128], W2 [128x128], b2 [128], W3 [128x5], b3 [5]
-constexpr int kOffW1 = 0;
-constexpr int kOffB1 = kOffW1 + kMlpIn * kMlpHid;
-constexpr int kOffW2 = kOffB1 + kMlpHid;
-constexpr int kOffB2 = kOffW2 + kMlpHid * kMlpHid;
-constexpr int kOffW3 = kOffB2 + kMlpHid;
-constexpr int kOffB3 = kOffW3 + kMlpHid * kMlpOut;
-constexpr int kMlpParams = kOffB3 + kMlpOut;  // 27525
+constexpr int kMlpHid = 128, kMlpOut = 5, kNeigh = 16;
+// inputs: 16 neighbours x 5 geometric features (feature set 0), or x (5 geometric features + the
+// neighbour's one-body stresslet gamma b_j, 5 values) (feature set 1)
+constexpr int kMlpIn = 80, kMlpInRhs = 160, kMlpInMax = kMlpInRhs;
+// flat float32 parameter vector: W1 [in x 128], b1 [128], W2 [128x128], b2 [128], W3 [128x5], b3 [5]
+struct MlpLayout {
+  int in, offW1, offB1, offW2, offB2, offW3, offB3, nparam;
+};
+constexpr MlpLayout mlp_layout(int in) {
+  return MlpLayout{in,
+                   0,
+                   in * kMlpHid,
+                   in * kMlpHid + kMlpHid,
+                   in * kMlpHid + kMlpHid + kMlpHid * kMlpHid,
+                   in * kMlpHid + 2 * kMlpHid + kMlpHid * kMlpHid,
+                   in * kMlpHid + 2 * kMlpHid + kMlpHid * kMlpHid + kMlpHid * kMlpOut,
+                   in * kMlpHid + 2 * kMlpHid + kMlpHid * kMlpHid + kMlpHid * kMlpOut + kMlpOut};
+}
+static_assert(mlp_layout(kMlpIn).nparam == 27525, "parameter count of the 80-input network");
+static_assert(mlp_layout(kMlpInRhs).nparam == 37765, "parameter count of the 160-input network");
+constexpr int kMlpParamsMax = mlp_layout(kMlpInMax).nparam;
 
 // C[M x N] = A B (bfloat16 operands, float32 result); tA: A stored [K x M]; tB: B stored [N x K].
 // partial: float32 scratch [ksplit x M x N] when K is split (ksplit > 1).
@@ -34,15 +46,16 @@ void mlp_colsum(const float* M, int rows, int cols, float* out, float* partial, 
 void mlp_copy_cols(const float* src, int ldsrc, int rows, int cols, float* dst, hipStream_t s);
 void mlp_adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
               float eps, int step, hipStream_t s);
-void mlp_weights_bf16(const float* w, uint16_t* W1, uint16_t* W2, uint16_t* W3, hipStream_t s);
+void mlp_weights_bf16(const float* w, const MlpLayout& L, uint16_t* W1, uint16_t* W2, uint16_t* W3, hipStream_t s);
 
 // 16 nearest other centres of every sphere (ties by index), nearest first: nbr [n x 16], from a
 // cell grid of the centres
 struct GridView;
 void launch_knn16(const GridView& g, int32_t* nbr, hipStream_t s);
-// features [n x 80] float32 from the neighbour lists
+// features [n x 80] float32 from the neighbour lists; with b (binary64 [n x 5], the right-hand side)
+// the 160-feature set [n x 160]: each neighbour's five geometric features followed by gamma b_j
 void launch_features(const double* R, const double* p, const int32_t* nbr, int n, float* feat,
-                     hipStream_t s);
+                     hipStream_t s, const double* b = nullptr, double gamma = 0.0);
 // x[k] = gamma * b[k] + out[k] (binary64 guess from the network output)
 void launch_guess_learned(const double* b, const float* out, double gamma, int64_t len, double* x,
                           hipStream_t s);

@@ -1,9 +1,10 @@
-// Warm-start network on the matrix cores (gfx950): a 80 -> 128 -> 128 -> 5 perceptron with ReLU,
+// Warm-start network on the matrix cores (gfx950): an in -> 128 -> 128 -> 5 perceptron with ReLU (in = 80
+// or 160 inputs),
 // bfloat16 operands and float32 accumulation through v_mfma_f32_16x16x16_bf16, plus the
 // kernels of its training step (mean-squared-error gradient, ReLU masks, bias gradients, Adam).
 //
-// Matrices are row-major. Every GEMM is C[M x N] = A[M x K] B[K x N] with M, N, K multiples of 16;
-// one wavefront owns one 16 x 16 tile of C and walks K in steps of 16. MFMA operand layout (wave64):
+// Matrices are row-major. Every GEMM is C[M x N] = A[M x K] B[K x N] with M, N, K multiples of 16,
+// in 64 x 64 tiles of C per workgroup (see k_gemm_bf16). MFMA operand layout (wave64):
 // lane l holds A[l % 16][4(l/16) .. 4(l/16)+3], B[4(l/16) .. 4(l/16)+3][l % 16] and returns
 // C[4(l/16) .. 4(l/16)+3][l % 16]. Long K (weight gradients, K = batch) is split over grid.z into
 // partial tiles that a second kernel adds in a fixed order, so every result is reproducible.
@@ -28,28 +29,87 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
-__global__ void __launch_bounds__(64)
+// Tiled GEMM: one workgroup of 256 threads (4 wavefronts) owns a 64 x 64 tile of C; each wavefront
+// a 32 x 32 quarter (2 x 2 MFMA tiles). K is walked in panels of 32: the A panel [64 x 32] and the
+// B panel [32 x 64] are loaded with one 16-byte global load per thread each (8 consecutive bf16
+// along whichever index is contiguous in memory) and stored in LDS as As[m][k] and Bs[n][k], so
+// that every MFMA operand (4 consecutive k of one row or column) is one 8-byte LDS read. Rows and
+// columns past M or N and k past the panel's end read as zero; M, N and K are multiples of 16.
+constexpr int kGT = 64, kGK = 32, kGPad = 8;  // tile edge, K panel, LDS row padding (bank spread)
+
+__global__ void __launch_bounds__(256)
     k_gemm_bf16(const uint16_t* __restrict__ A, int lda, int transA, const uint16_t* __restrict__ B,
                 int ldb, int transB, float* __restrict__ C, int M, int N, int K, int kchunk) {
-  const int lane = threadIdx.x;
-  const int n0 = blockIdx.x * 16, m0 = blockIdx.y * 16;
+  __shared__ __align__(16) uint16_t As[kGT][kGK + kGPad];
+  __shared__ __align__(16) uint16_t Bs[kGT][kGK + kGPad];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // this wavefront's quarter
   const int r = lane & 15, kb = 4 * (lane >> 4);
   const int kbeg = blockIdx.z * kchunk;
   const int kend = min(K, kbeg + kchunk);
-  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
-    bf16x4 a, b;
+  floatx4 acc[2][2] = {};
+  // this thread's 16-byte chunk of each panel: 256 chunks of 8 elements
+  // contiguous along k (A row-major, B transposed): row = tid / 4, k offset = 8 (tid % 4)
+  // contiguous along m or n (A transposed, B row-major): k row = tid / 8, m/n offset = 8 (tid % 8)
+  for (int k0 = kbeg; k0 < kend; k0 += kGK) {
+    {  // A panel -> As[m][k]
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (!transA) {
+        const int mm = tid >> 2, kk = 8 * (tid & 3);
+        if (m0 + mm < M && k0 + kk < kend) v = *(const uint4*)(A + (int64_t)(m0 + mm) * lda + k0 + kk);
+        *(uint4*)&As[mm][kk] = v;
+      } else {
+        const int kk = tid >> 3, mm = 8 * (tid & 7);
+        if (m0 + mm < M && k0 + kk < kend) v = *(const uint4*)(A + (int64_t)(k0 + kk) * lda + m0 + mm);
+        const uint16_t* e = (const uint16_t*)&v;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int k = k0 + kb + t;
-      a[t] = (short)(transA ? A[(int64_t)k * lda + m0 + r] : A[(int64_t)(m0 + r) * lda + k]);
-      b[t] = (short)(transB ? B[(int64_t)(n0 + r) * ldb + k] : B[(int64_t)k * ldb + n0 + r]);
+        for (int q = 0; q < 8; ++q) As[mm + q][kk] = e[q];
+      }
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    {  // B panel -> Bs[n][k]
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (transB) {
+        const int nn = tid >> 2, kk = 8 * (tid & 3);
+        if (n0 + nn < N && k0 + kk < kend) v = *(const uint4*)(B + (int64_t)(n0 + nn) * ldb + k0 + kk);
+        *(uint4*)&Bs[nn][kk] = v;
+      } else {
+        const int kk = tid >> 3, nn = 8 * (tid & 7);
+        if (n0 + nn < N && k0 + kk < kend) v = *(const uint4*)(B + (int64_t)(k0 + kk) * ldb + n0 + nn);
+        const uint16_t* e = (const uint16_t*)&v;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Bs[nn + q][kk] = e[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kGK; ks += 16) {
+      bf16x4 a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = *(const bf16x4*)&As[wm + 16 * t + r][ks + kb];
+        b[t] = *(const bf16x4*)&Bs[wn + 16 * t + r][ks + kb];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
   }
   float* Cz = C + (int64_t)blockIdx.z * M * N;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) Cz[(int64_t)(m0 + kb + t) * N + n0 + r] = acc[t];
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + 16 * j + r;
+      if (col >= N) continue;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int row = m0 + wm + 16 * i + kb + t;
+        if (row < M) Cz[(int64_t)row * N + col] = acc[i][j][t];
+      }
+    }
 }
 
 __global__ void k_sum_partials(const float* __restrict__ P, int parts, int64_t len,
@@ -169,15 +229,15 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
   w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
 }
 
-// bf16 copies: W1 [80x128], W2 [128x128], W3 [128x16] (columns 5..15 zero)
-__global__ void k_weights_bf16(const float* __restrict__ w, uint16_t* __restrict__ W1,
+// bf16 copies: W1 [in x 128], W2 [128x128], W3 [128x16] (columns 5..15 zero)
+__global__ void k_weights_bf16(const float* __restrict__ w, MlpLayout L, uint16_t* __restrict__ W1,
                                uint16_t* __restrict__ W2, uint16_t* __restrict__ W3) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < kMlpIn * kMlpHid) W1[k] = f2bf(w[kOffW1 + k]);
-  if (k < kMlpHid * kMlpHid) W2[k] = f2bf(w[kOffW2 + k]);
+  if (k < L.in * kMlpHid) W1[k] = f2bf(w[L.offW1 + k]);
+  if (k < kMlpHid * kMlpHid) W2[k] = f2bf(w[L.offW2 + k]);
   if (k < kMlpHid * 16) {
     const int r = k >> 4, c = k & 15;
-    W3[k] = c < kMlpOut ? f2bf(w[kOffW3 + r * kMlpOut + c]) : (uint16_t)0;
+    W3[k] = c < kMlpOut ? f2bf(w[L.offW3 + r * kMlpOut + c]) : (uint16_t)0;
   }
 }
 
@@ -187,11 +247,12 @@ inline unsigned nblk(int64_t len, int b) { return (unsigned)((len + b - 1) / b);
 
 void mlp_gemm(const uint16_t* A, int lda, bool tA, const uint16_t* B, int ldb, bool tB, float* C,
               float* partial, int M, int N, int K, int ksplit, hipStream_t s) {
-  const int kchunk = ((K / 16 + ksplit - 1) / ksplit) * 16;
+  // K chunks of whole panels; every chunk but the last is a multiple of the panel depth
+  const int kchunk = ((K + ksplit - 1) / ksplit + kGK - 1) / kGK * kGK;
   const int parts = (K + kchunk - 1) / kchunk;
   float* out = parts > 1 ? partial : C;
-  hipLaunchKernelGGL(k_gemm_bf16, dim3(N / 16, M / 16, parts), dim3(64), 0, s, A, lda, (int)tA, B, ldb,
-                     (int)tB, out, M, N, K, kchunk);
+  hipLaunchKernelGGL(k_gemm_bf16, dim3((N + kGT - 1) / kGT, (M + kGT - 1) / kGT, parts), dim3(256), 0, s, A, lda,
+                     (int)tA, B, ldb, (int)tB, out, M, N, K, kchunk);
   if (parts > 1)
     hipLaunchKernelGGL(k_sum_partials, dim3(nblk((int64_t)M * N, 256)), dim3(256), 0, s, partial,
                        parts, (int64_t)M * N, C);
@@ -247,8 +308,9 @@ void mlp_adam(float* w, const float* g, float* m, float* v, int n, float lr, flo
   hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
 }
 
-void mlp_weights_bf16(const float* w, uint16_t* W1, uint16_t* W2, uint16_t* W3, hipStream_t s) {
-  hipLaunchKernelGGL(k_weights_bf16, dim3(nblk(kMlpHid * kMlpHid, 256)), dim3(256), 0, s, w, W1, W2, W3);
+void mlp_weights_bf16(const float* w, const MlpLayout& L, uint16_t* W1, uint16_t* W2, uint16_t* W3, hipStream_t s) {
+  const int most = std::max(L.in * kMlpHid, kMlpHid * kMlpHid);
+  hipLaunchKernelGGL(k_weights_bf16, dim3(nblk(most, 256)), dim3(256), 0, s, w, L, W1, W2, W3);
 }
 
 }  // namespace mbs

@@ -25,8 +25,12 @@ EXPORTS = ("mbs_default_params", "mbs_create", "mbs_destroy", "mbs_set_params", 
            "mbs_autotune", "mbs_autotune_batched", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
            "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
            "mbs_warmstart_load", "mbs_warmstart_target", "mbs_initial_guess", "mbs_precond_apply",
-           "mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex", "mbs_matvec_static")
+           "mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex", "mbs_matvec_static",
+           "mbs_warmstart_features", "mbs_features_ex")
 MLP_NPARAM, MLP_NFEAT = 27525, 80
+MLP_NPARAM_RHS, MLP_NFEAT_RHS = 37765, 160
+MBS_FEATURES_GEOMETRY, MBS_FEATURES_GEOMETRY_RHS = 0, 1
+_MLP_SIZES = {MBS_FEATURES_GEOMETRY: (MLP_NFEAT, MLP_NPARAM), MBS_FEATURES_GEOMETRY_RHS: (MLP_NFEAT_RHS, MLP_NPARAM_RHS)}
 
 
 class MbsError(RuntimeError):
@@ -112,6 +116,8 @@ def load(path: str = LIB_PATH):
     lib.mbs_autotune_batched.restype = ctypes.c_int
     FP = ctypes.POINTER(ctypes.c_float)
     lib.mbs_features.argtypes = [P, I64, P, P, P, P, VP]
+    lib.mbs_features_ex.argtypes = [P, I64, P, P, P, P, P, VP]
+    lib.mbs_warmstart_features.argtypes = [P, I32]
     lib.mbs_warmstart_init.argtypes = [P, ctypes.c_uint64]
     lib.mbs_warmstart_set.argtypes = [P, FP]
     lib.mbs_warmstart_get.argtypes = [P, FP]
@@ -132,7 +138,8 @@ def load(path: str = LIB_PATH):
     lib.mbs_flow_ex.argtypes = [P, I64, P, I64, P, P, P, P, P, EX, P, VP]
     for name in ("mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex"):
         getattr(lib, name).restype = ctypes.c_int
-    for name in ("mbs_warmstart_target", "mbs_initial_guess", "mbs_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
+    for name in ("mbs_warmstart_target", "mbs_initial_guess", "mbs_features", "mbs_features_ex",
+                 "mbs_warmstart_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
                  "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
                  "mbs_warmstart_load"):
         getattr(lib, name).restype = ctypes.c_int
@@ -401,6 +408,29 @@ def _features(self, R, p, want_nbr=False):
     return (feat, nbr) if want_nbr else feat
 
 
+def _mlp_sizes(self):
+    """(input width, parameter count) of the context's feature set."""
+    return _MLP_SIZES[getattr(self, "_mlp_set", MBS_FEATURES_GEOMETRY)]
+
+
+def _ws_features(self, feature_set):
+    self._check(self.lib.mbs_warmstart_features(self.h, int(feature_set)))
+    self._mlp_set = int(feature_set)
+
+
+def _features_ex(self, R, p, b=None, want_nbr=False):
+    """Features of the context's feature set (b: the right-hand side [n, 5], needed by the wider set)."""
+    import torch
+    n = R.shape[0]
+    width = _mlp_sizes(self)[0]
+    feat = torch.empty((n, width), dtype=torch.float32, device=R.device)
+    nbr = torch.empty((n, 16), dtype=torch.int32, device=R.device) if want_nbr else None
+    self._check(self.lib.mbs_features_ex(self.h, n, _ptr(R, n, 3, "R"), _ptr(p, n, 3, "p"), _ptr(b, n, 5, "b"),
+                                         _ptr(feat, n, width, "feat", torch.float32),
+                                         _ptr(nbr, n, 16, "nbr", torch.int32), _stream()))
+    return (feat, nbr) if want_nbr else feat
+
+
 def _ws_init(self, seed=0):
     self._check(self.lib.mbs_warmstart_init(self.h, int(seed)))
 
@@ -408,14 +438,15 @@ def _ws_init(self, seed=0):
 def _ws_set(self, params):
     import numpy as np
     a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
-    if a.size != MLP_NPARAM:
-        raise ValueError(f"expected {MLP_NPARAM} parameters")
+    npar = _mlp_sizes(self)[1]
+    if a.size != npar:
+        raise ValueError(f"expected {npar} parameters")
     self._check(self.lib.mbs_warmstart_set(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
 
 
 def _ws_get(self):
     import numpy as np
-    a = np.empty(MLP_NPARAM, dtype=np.float32)
+    a = np.empty(_mlp_sizes(self)[1], dtype=np.float32)
     self._check(self.lib.mbs_warmstart_get(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
     return a
 
@@ -424,7 +455,7 @@ def _ws_forward(self, feat):
     import torch
     m = feat.shape[0]
     out = torch.empty((m, 5), dtype=torch.float32, device=feat.device)
-    self._check(self.lib.mbs_warmstart_forward(self.h, m, _ptr(feat, m, MLP_NFEAT, "feat", torch.float32),
+    self._check(self.lib.mbs_warmstart_forward(self.h, m, _ptr(feat, m, _mlp_sizes(self)[0], "feat", torch.float32),
                                                _ptr(out, m, 5, "out", torch.float32), _stream()))
     return out
 
@@ -433,9 +464,9 @@ def _ws_grad(self, feat, target):
     import numpy as np
     import torch
     m = feat.shape[0]
-    g = np.empty(MLP_NPARAM, dtype=np.float32)
+    g = np.empty(_mlp_sizes(self)[1], dtype=np.float32)
     loss = ctypes.c_double()
-    self._check(self.lib.mbs_warmstart_grad(self.h, m, _ptr(feat, m, MLP_NFEAT, "feat", torch.float32),
+    self._check(self.lib.mbs_warmstart_grad(self.h, m, _ptr(feat, m, _mlp_sizes(self)[0], "feat", torch.float32),
                                             _ptr(target, m, 5, "target", torch.float32),
                                             g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                             ctypes.byref(loss), _stream()))
@@ -446,7 +477,7 @@ def _ws_train(self, feat, target, epochs, batch=4096, lr=1e-3, seed=0):
     import torch
     m = feat.shape[0]
     hist = (ctypes.c_double * max(epochs, 1))()
-    self._check(self.lib.mbs_warmstart_train(self.h, m, _ptr(feat, m, MLP_NFEAT, "feat", torch.float32),
+    self._check(self.lib.mbs_warmstart_train(self.h, m, _ptr(feat, m, _mlp_sizes(self)[0], "feat", torch.float32),
                                              _ptr(target, m, 5, "target", torch.float32), int(epochs),
                                              int(batch), float(lr), int(seed), hist, _stream()))
     return list(hist)[:epochs]
@@ -457,7 +488,11 @@ def _ws_save(self, path):
 
 
 def _ws_load(self, path):
+    import struct
     self._check(self.lib.mbs_warmstart_load(self.h, str(path).encode()))
+    with open(path, "rb") as f:  # the library selected the file's feature set: follow it
+        magic, version, _ = struct.unpack("<III", f.read(12))
+        self._mlp_set = struct.unpack("<I", f.read(4))[0] if version == 2 else MBS_FEATURES_GEOMETRY
 
 
 def _ws_target(self, R, Sigma, v2s=None, v3t=None, Fe=None, Te=None):
@@ -495,6 +530,8 @@ Context.mbs_precond_apply = _precond_apply
 Context.mbs_warmstart_target = _ws_target
 Context.mbs_initial_guess = _initial_guess
 Context.mbs_features = _features
+Context.mbs_features_ex = _features_ex
+Context.mbs_warmstart_features = _ws_features
 Context.mbs_warmstart_init = _ws_init
 Context.mbs_warmstart_set = _ws_set
 Context.mbs_warmstart_get = _ws_get

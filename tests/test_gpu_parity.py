@@ -733,6 +733,52 @@ def test_batched_graph_replays_equal_direct_launches(ctx):
         assert _rel(V0[off[b]:off[b + 1]], ref["V"]) < 1e-9
 
 
+def test_batched_single_graph_restarts_latencies_and_more_rounds(ctx):
+    """From the second call of a batch shape on, the whole batched solve is one graph launch sized
+    by the rounds the previous call took. Every call equals the direct launches bit for bit: with
+    restarts (restart length 4, so the true-residual check sends configurations back through the
+    restart gate), and after the data are overwritten in place by a denser placement that needs more
+    rounds than the graph holds (the remaining rounds then run one by one). Configurations are
+    certified in the round their iterations end: the lone sphere finishes before the largest one."""
+    print("batched single graph", flush=True)
+    sizes = (1, 2, 40, 150, 300)
+
+    def make(density, seed):
+        ws = [inputs.trap_workload(n, max(8.0, (n / density) ** (1 / 3)), seed + n) for n in sizes]
+        return ws, _batch(ws)
+
+    ws_a, (off, cat_a) = make(0.0005, 9100)
+    ws_b, (_, cat_b) = make(0.01, 9200)
+    R = cat_a("R").clone()
+    v1, v2, Fe = cat_a("v1s").clone(), cat_a("v2s").clone(), cat_a("Fe").clone()
+    ctx.set_params(tol=1e-12, restart=4, graph=0)
+    try:
+        ref_a = [t.clone() for t in ctx.mbs_solve_batched(off, R, v1, v2, None, Fe, None)[:3]]
+        ctx.set_params(graph=1)
+        lat = None
+        for rep in range(3):  # loop (observes the rounds), then the single graph twice
+            V, W, S, stats, lat = ctx.mbs_solve_batched(off, R, v1, v2, None, Fe, None)
+            assert all(torch.equal(a, b) for a, b in zip((V, W, S), ref_a)), rep
+            assert all(st["rel_resid"] <= 1e-12 for st in stats)
+        assert max(st["iters"] for st in stats) > 4          # restarts happened
+        assert lat[0] < lat[-1], lat
+        for b in (0, 2, 4):
+            assert _rel(ref_a[0][off[b]:off[b + 1]], galerkin.solve(ws_a[b])["V"]) < 1e-10
+        # same buffers, denser data: more iterations than the graph's rounds
+        for dst, name in ((R, "R"), (v1, "v1s"), (v2, "v2s"), (Fe, "Fe")):
+            dst.copy_(cat_b(name))
+        ctx.set_params(graph=0)
+        ref_b = [t.clone() for t in ctx.mbs_solve_batched(off, R, v1, v2, None, Fe, None)[:3]]
+        ctx.set_params(graph=1)
+        V, W, S, stats, _ = ctx.mbs_solve_batched(off, R, v1, v2, None, Fe, None)
+        assert all(torch.equal(a, b) for a, b in zip((V, W, S), ref_b))
+        assert all(st["rel_resid"] <= 1e-12 for st in stats)
+        for b in (1, 3, 4):
+            assert _rel(ref_b[0][off[b]:off[b + 1]], galerkin.solve(ws_b[b])["V"]) < 1e-10
+    finally:
+        ctx.set_params(tol=1e-10, restart=30, graph=1)
+
+
 def test_batched_graphs_follow_new_offsets(ctx):
     """Two batches with the same number of configurations and spheres but other sizes (so other
     work items), alternated: with graphs and cached descriptors every call equals the direct
