@@ -94,7 +94,8 @@ typedef struct mbs_params {
                             than 2a are left out); 0 = no preconditioner (default). The solution
                             is unchanged. Applies to mbs_solve, mbs_step and mbs_solve_batched
                             (there within each configuration). */
-  int32_t lmax;          /* traction truncation rank; only 2 (force, torque, stresslet) */
+  int32_t lmax;          /* traction truncation rank of these entry points: only 2 (force, torque,
+                            stresslet); rank 3 has its own entry points (mbs_solve_r3) */
   int32_t max_iter;      /* cap on GMRES iterations (all restarts, inner iterations included) */
   int32_t restart;       /* GMRES restart length m, 1..64 */
   int32_t precision;     /* MBS_FP64 or MBS_MIXED */
@@ -280,6 +281,60 @@ int mbs_outputs_ex(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, 
 int mbs_flow_ex(mbs_ctx* ctx, int64_t m, const double* X, int64_t n, const double* R, const double* Fe,
                 const double* Te, const double* Sigma, const double* v3t, const mbs_slip_ex* ex, double* U,
                 void* stream);
+
+/* Traction ranks <= 3 (section IV, minimal truncation): the septlet, vortlet and potential-dipole
+   traction modes become unknowns beside the flow stresslet. Each sphere's exterior flow is written
+   through its flow stresslet Sigma and the equivalent slips X^gam, X^psi, X^d of the three modes
+   (the slips a lone sphere would need to produce the same exterior flow of that mode; their flows
+   are those of gamma, psi and d above). The Galerkin conditions of the quadratic surface modes
+   (coefficient V^(3) of the incident flow, section III, split into its irreducible parts as in
+   section IV: gamma its symmetric traceless part, d the contraction of the velocity index with the
+   first harmonic index, psi minus the symmetric contraction with eps over those two indices) read
+       X^alpha_n + P^alpha[sum_{m != n} u_m](R_n) = v^alpha_n     (alpha = gam, psi, d)
+   with v^alpha_n the prescribed slip of that mode, and the stresslet rows keep their form with the
+   three modes' flows among the coupled sources:
+       Sigma_n / gamma - E[sum_{m != n} u_m(Sigma, X)](R_n) = E[sum_m u_m(F, T, lambda)](R_n) - c s_n.
+   The spinlet mode lambda stays a fixed source (it belongs to the cubic surface coefficient).
+   Unknowns, x [n x 20] row-major, per sphere:
+       x[0..4]   Sigma in the 5-basis
+       x[5..11]  X^gam in the 7-basis below
+       x[12..16] X^psi in the 5-basis
+       x[17..19] X^d (Cartesian)
+   7-basis of symmetric traceless rank-3 tensors: B_m = T_m / |T_m| (Frobenius norm over all 27
+   components), T_m,ijk = (1/6) d_i d_j d_k p_m for the harmonic cubics
+       p_1 = 2z^3 - 3x^2 z - 3y^2 z,  p_2 = 4xz^2 - x^3 - xy^2,  p_3 = 4yz^2 - x^2 y - y^3,
+       p_4 = x^2 z - y^2 z,  p_5 = xyz,  p_6 = x^3 - 3xy^2,  p_7 = 3x^2 y - y^3
+   (orthonormal; coordinates x_m = B_m : T of a symmetric traceless T).
+   Prescribed slips: v3t [n x 3] is v^d; ex->gam [n x 10] (symmetric components as above, traceless
+   part used) is v^gam; ex->psi [n x 5] is v^psi; ex->lam [n x 10] the spinlet slip (fixed source).
+   All arithmetic is binary64. Arrays are DEVICE, as elsewhere; NULL optional inputs are zero.
+
+   mbs_matvec_r3: y [n x 20] = A x (one all-pairs pass).
+   mbs_rhs_r3:    b [n x 20]: stresslet rows E[F, T, lambda] - c s; mode rows v^alpha - P^alpha[F, T,
+                  lambda].
+   mbs_outputs_r3: V, W [n x 3] and S [n x 5] of a solution x: V = -v1s + F/(6 pi eta a) + F^0 u,
+                  W = T/(8 pi eta a^3) + (1/2) curl u over the flows u of the other spheres' F, T,
+                  Sigma, X^gam, X^psi, X^d and lambda; S = Sigma + (8/3) pi eta a^3 v2s (NULL S: not
+                  written).
+   mbs_solve_r3:  restarted GMRES(params.restart) on A x = b to ||b - A x||_2 <= params.tol ||b||_2
+                  (binary64 operator, no preconditioner, at most params.max_iter Arnoldi steps),
+                  starting from x0 [n x 20] (NULL: zero), then the outputs. x [n x 20] (or NULL)
+                  receives the solution. params.precision, guess, near_cutoff and the learned guess
+                  do not apply; params.check_overlap does. stats: iters, fp64_matvecs, rel_resid and
+                  the timings (refinements and fp32_matvecs are 0). Returns MBS_ENOCONV (outputs of
+                  the last iterate written) when the tolerance is not reached.
+   Errors: MBS_EINVAL for n < 1, a missing required pointer, an output overlapping an input or
+   another output, non-finite inputs (solve); MBS_EOVERLAP as mbs_solve. */
+int mbs_matvec_r3(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y, void* stream);
+int mbs_rhs_r3(mbs_ctx* ctx, int64_t n, const double* R, const double* v2s, const double* v3t,
+               const mbs_slip_ex* ex, const double* Fe, const double* Te, double* b, void* stream);
+int mbs_outputs_r3(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, const double* v2s,
+                   const mbs_slip_ex* ex, const double* Fe, const double* Te, const double* x, double* V,
+                   double* W, double* S, void* stream);
+int mbs_solve_r3(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, const double* v2s,
+                 const double* v3t, const mbs_slip_ex* ex, const double* Fe, const double* Te,
+                 const double* x0, double* V, double* W, double* S, double* x, mbs_stats* st,
+                 void* stream);
 
 /* Time integration in a harmonic trap (section V set-up; kinematics of section II):
    every step rebuilds F^e = -k_trap R, T^e = 0, V^(1s) = c0 p, V^(2s) = c1 * 3(pp - I/3),

@@ -228,6 +228,27 @@ def system_matrix_rank3(R, prm: Params):
     return A.reshape(n * RANK3_DIM, n * RANK3_DIM)
 
 
+def matvec_rows_rank3(R, x, rows, prm: Params):
+    """(A x) of the rank <= 3 system restricted to the given spheres, without forming A:
+    [len(rows), 20] (x [N, 20] in the unknowns' layout above)."""
+    R = np.asarray(R, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64).reshape(len(R), RANK3_DIM)
+    rows = np.asarray(rows)
+    g = constants(prm)["gamma"]
+    off = _rank3_offsets()
+    y = np.zeros((len(rows), RANK3_DIM))
+    for tgt, _, _ in RANK3_BLOCKS:
+        to, td = off[tgt]
+        sign = -1.0 if tgt == "E" else 1.0
+        acc = np.zeros(len(rows) * td)
+        for _, src, _ in RANK3_BLOCKS:
+            so, sd = off[src]
+            acc = acc + pair_matrix(R, tgt, src, prm, rows) @ np.ravel(x[:, so:so + sd])
+        diag = 1.0 / g if tgt == "E" else 1.0
+        y[:, to:to + td] = diag * x[rows, to:to + td] + sign * acc.reshape(len(rows), td)
+    return y
+
+
 def _prescribed_quadratic(w):
     """The prescribed quadratic-order slips of a workload in the unknowns' coordinates."""
     from .basis import sym3_from10, to7

@@ -79,6 +79,8 @@ struct mbs_ctx {
   DevBuf mlp_w, mlp_g, mlp_m, mlp_v, mlp_wb, mlp_ws, mlp_part, mlp_loss, mlp_idx, knn_buf;
   // cell grid of the centres behind both neighbour searches (near-field lists, nearest neighbours)
   DevBuf grid;
+  // traction ranks <= 3: Krylov basis, residual and solution vectors, pass partial sums
+  DevBuf r3;
   // a solve in the Morton order of the centres: the permutation and the reordered inputs/outputs
   DevBuf ord;
   // single-configuration GMRES: Arnoldi steps captured as graphs (per precision), see step_graphs
@@ -152,7 +154,9 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
   if (!(p->tol > 0.0) || !(p->tol < 1.0)) return set_err(c, MBS_EINVAL, "tol must be in (0, 1)");
   if (!isfinite(p->self_slip_c)) return set_err(c, MBS_EINVAL, "self_slip_c must be finite");
   if (p->lmax != 2)
-    return set_err(c, MBS_EUNSUPPORTED, "lmax = %d: only traction rank 2 (force, torque, stresslet)",
+    return set_err(c, MBS_EUNSUPPORTED,
+                   "lmax = %d: these entry points solve traction rank 2 (force, torque, stresslet); rank 3 "
+                   "is solved by mbs_solve_r3",
                    p->lmax);
   if (p->max_iter < 1) return set_err(c, MBS_EINVAL, "max_iter must be >= 1");
   if (p->restart < 1 || p->restart > 64) return set_err(c, MBS_EINVAL, "restart must be in 1..64");
@@ -1018,6 +1022,116 @@ int begin_call(mbs_ctx* c) {
 
 }  // namespace
 
+
+// ---------------------------------------------------------------- traction ranks <= 3
+// Unknowns x [n x 20] per sphere: [Sigma (5-basis), X^gam (7-basis), X^psi (5-basis), X^d (3)] (the
+// flow stresslet and the equivalent slips of the septlet, vortlet and potential-dipole traction modes,
+// section IV). The system is solved in binary64 by restarted GMRES without preconditioner; every
+// operator application is one all-pairs pass of the rank-3 kernel.
+namespace {
+
+struct R3Ws {
+  double *V, *w, *r, *b, *x, *part;
+};
+
+int r3_workspace(mbs_ctx* c, int64_t n, R3Ws* o) {
+  CHK(ensure_ws(c, n));  // dot partials, Hessenberg matrix, small vectors, zeros
+  const int m = c->prm.restart;
+  const int64_t len = 20 * n;
+  const size_t total = (size_t)(m + 5) * len + (size_t)rank3_part_elems(n) + 64;
+  CHK(ensure(c, c->r3, total));
+  double* q = c->r3.p;
+  o->V = q;
+  q += (int64_t)(m + 1) * len;
+  o->w = q;
+  q += len;
+  o->r = q;
+  q += len;
+  o->b = q;
+  q += len;
+  o->x = q;
+  q += len;
+  o->part = q;
+  return MBS_OK;
+}
+
+// y = A x (one pass), timed through the context's event ring like the rank-2 operator
+void r3_apply(mbs_ctx* c, int64_t n, const double* R, const R3Ws& ws, const double* x, double* y, hipStream_t s,
+              Counters& cnt) {
+  if (c->npend == mbs_ctx::kRing) {
+    (void)hipStreamSynchronize(s);
+    harvest_ops(c);
+  }
+  const int slot = c->npend++;
+  c->op_prec[slot] = MBS_FP64;
+  (void)hipEventRecord(c->opev[2 * slot], s);
+  launch_rank3(0, R, x, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, y, nullptr,
+               nullptr, ws.part, n, c->ph, s);
+  (void)hipEventRecord(c->opev[2 * slot + 1], s);
+  cnt.f64++;
+  cnt.pairs += (double)n * (double)(n - 1);
+}
+
+// Restarted GMRES(m) on the rank-3 system: classical Gram-Schmidt applied twice, Givens rotations on
+// the device; the residual of every restart is recomputed with the operator. *resid: final ||b - A x||.
+int r3_gmres(mbs_ctx* c, int64_t n, const double* R, const R3Ws& ws, bool x_zero, double tol_abs, int max_iters,
+             double* resid, Counters& cnt, hipStream_t s) {
+  const int m = c->prm.restart;
+  const int64_t len = 20 * n;
+  Small sm = small_of(c);
+  if (x_zero) {
+    launch_copy(ws.b, ws.r, len, s);
+  } else {
+    r3_apply(c, n, R, ws, ws.x, ws.r, s, cnt);
+    launch_axpby(1.0, ws.b, -1.0, ws.r, len, s);
+  }
+  norm2(c, ws.r, len, sm.nsq, s);
+  launch_init_g(sm.nsq, sm.g, m, sm.status, s);
+  CHK(read_status(c, sm.status, 1, s));
+  double beta = c->h_status[0];
+  int used = 0;
+  while (beta > tol_abs && used < max_iters) {
+    launch_scale_by(ws.r, sm.status, 1, ws.V, len, s);
+    int k = 0;
+    bool breakdown = false;
+    while (k < m && used < max_iters) {
+      r3_apply(c, n, R, ws, ws.V + (int64_t)k * len, ws.w, s, cnt);
+      launch_dots(ws.V, len, k + 1, ws.w, len, c->dpart.p, sm.h1, s);
+      launch_axpy_multi(ws.V, len, k + 1, sm.h1, -1.0, ws.w, len, s);
+      launch_dots(ws.V, len, k + 1, ws.w, len, c->dpart.p, sm.h2, s);
+      launch_axpy_multi(ws.V, len, k + 1, sm.h2, -1.0, ws.w, len, s);
+      norm2(c, ws.w, len, sm.nsq, s);
+      launch_givens(c->H.p, m, k, sm.h1, sm.h2, sm.nsq, sm.cs, sm.sn, sm.g, sm.status, s);
+      launch_scale_by(ws.w, sm.status + 1, 1, ws.V + (int64_t)(k + 1) * len, len, s);
+      CHK(read_status(c, sm.status, 2, s));
+      ++k;
+      ++used;
+      cnt.iters++;
+      if (!(c->h_status[1] > 1e-300 * beta)) breakdown = true;
+      if (c->h_status[0] <= tol_abs || breakdown) break;
+    }
+    launch_backsolve(c->H.p, m, k, sm.g, sm.y, s);
+    launch_axpy_multi(ws.V, len, k, sm.y, 1.0, ws.x, len, s);
+    r3_apply(c, n, R, ws, ws.x, ws.r, s, cnt);
+    launch_axpby(1.0, ws.b, -1.0, ws.r, len, s);
+    norm2(c, ws.r, len, sm.nsq, s);
+    launch_init_g(sm.nsq, sm.g, m, sm.status, s);
+    CHK(read_status(c, sm.status, 1, s));
+    beta = c->h_status[0];
+    if (breakdown) break;
+  }
+  *resid = beta;
+  return MBS_OK;
+}
+
+int r3_check_n(mbs_ctx* c, int64_t n) {
+  if (n < 1) return set_err(c, MBS_EINVAL, "n = %lld must be >= 1", (long long)n);
+  if (n > (int64_t)INT32_MAX / 20) return set_err(c, MBS_EINVAL, "n too large");
+  return MBS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void mbs_default_params(mbs_params* p) {
@@ -1089,7 +1203,8 @@ void mbs_destroy(mbs_ctx* c) {
                     &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig, &c->near, &c->zt,
                     &c->nt, &c->stepstate,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
-                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->bat, &c->btune};
+                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->ord, &c->r3,
+                    &c->bat, &c->btune};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& g : c->bgraph)
@@ -2169,6 +2284,134 @@ int mbs_precond_apply(mbs_ctx* c, int64_t n, const double* R, const double* x, d
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;
+}
+
+
+int mbs_matvec_r3(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, void* stream) {
+  CHK(begin_call(c));
+  CHK(r3_check_n(c, n));
+  if (!R || !x || !y) return set_err(c, MBS_EINVAL, "R, x and y are required");
+  CHK(check_aliasing(c, {{"y", y, 20 * n}}, {{"R", R, 3 * n}, {"x", x, 20 * n}}));
+  hipStream_t s = (hipStream_t)stream;
+  R3Ws ws;
+  CHK(r3_workspace(c, n, &ws));
+  launch_rank3(0, R, x, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, y, nullptr, nullptr,
+               ws.part, n, c->ph, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_rhs_r3(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const double* v3t, const mbs_slip_ex* ex,
+               const double* Fe, const double* Te, double* b, void* stream) {
+  CHK(begin_call(c));
+  CHK(r3_check_n(c, n));
+  if (!R || !b) return set_err(c, MBS_EINVAL, "R and b are required");
+  const HighSlip hi = high_of(ex);
+  CHK(check_aliasing(c, {{"b", b, 20 * n}},
+                     {{"R", R, 3 * n}, {"v2s", v2s, 5 * n}, {"v3t", v3t, 3 * n}, {"Fe", Fe, 3 * n},
+                      {"Te", Te, 3 * n}, {"gam", hi.gam, 10 * n}, {"psi", hi.psi, 5 * n}, {"lam", hi.lam, 10 * n}}));
+  hipStream_t s = (hipStream_t)stream;
+  R3Ws ws;
+  CHK(r3_workspace(c, n, &ws));
+  launch_rank3(1, R, nullptr, nullptr, v2s, v3t, hi.gam, hi.psi, hi.lam, Fe, Te, b, nullptr, nullptr, ws.part, n,
+               c->ph, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_outputs_r3(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const double* v2s,
+                   const mbs_slip_ex* ex, const double* Fe, const double* Te, const double* x, double* V, double* W,
+                   double* S, void* stream) {
+  CHK(begin_call(c));
+  CHK(r3_check_n(c, n));
+  if (!R || !x || !V || !W) return set_err(c, MBS_EINVAL, "R, x, V and W are required");
+  const HighSlip hi = high_of(ex);
+  CHK(check_aliasing(c, {{"V", V, 3 * n}, {"W", W, 3 * n}, {"S", S, 5 * n}},
+                     {{"R", R, 3 * n}, {"v1s", v1s, 3 * n}, {"v2s", v2s, 5 * n}, {"Fe", Fe, 3 * n},
+                      {"Te", Te, 3 * n}, {"x", x, 20 * n}, {"lam", hi.lam, 10 * n}}));
+  hipStream_t s = (hipStream_t)stream;
+  R3Ws ws;
+  CHK(r3_workspace(c, n, &ws));
+  launch_rank3(2, R, x, v1s, v2s, nullptr, nullptr, nullptr, hi.lam, Fe, Te, V, W, S, ws.part, n, c->ph, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
+int mbs_solve_r3(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const double* v2s, const double* v3t,
+                 const mbs_slip_ex* ex, const double* Fe, const double* Te, const double* x0, double* V, double* W,
+                 double* S, double* x, mbs_stats* st, void* stream) {
+  CHK(begin_call(c));
+  CHK(r3_check_n(c, n));
+  if (!R || !V || !W || !S) return set_err(c, MBS_EINVAL, "R, V, W and S are required");
+  const HighSlip hi = high_of(ex);
+  CHK(check_aliasing(c, {{"V", V, 3 * n}, {"W", W, 3 * n}, {"S", S, 5 * n}, {"x", x, 20 * n}},
+                     {{"R", R, 3 * n}, {"v1s", v1s, 3 * n}, {"v2s", v2s, 5 * n}, {"v3t", v3t, 3 * n},
+                      {"Fe", Fe, 3 * n}, {"Te", Te, 3 * n}, {"x0", x0, 20 * n}, {"gam", hi.gam, 10 * n},
+                      {"psi", hi.psi, 5 * n}, {"lam", hi.lam, 10 * n}}));
+  hipStream_t s = (hipStream_t)stream;
+  R3Ws ws;
+  CHK(r3_workspace(c, n, &ws));
+  CHK(check_inputs(c, s, {{R, 3 * n}, {v1s, 3 * n}, {v2s, 5 * n}, {v3t, 3 * n}, {Fe, 3 * n}, {Te, 3 * n},
+                          {x0, 20 * n}, {hi.gam, 10 * n}, {hi.psi, 5 * n}, {hi.lam, 10 * n}},
+                   nullptr, n));
+  if (c->prm.check_overlap) {
+    double md = 0.0;
+    CHK(check_overlap(c, n, R, s, &md));
+    if (md < 2.0 * c->prm.a)
+      return set_err(c, MBS_EOVERLAP, "spheres overlap: minimum centre distance %.6g < 2a", md);
+  }
+  const int64_t len = 20 * n;
+  Counters cnt;
+  Small sm = small_of(c);
+  c->npend = 0;
+  c->t_op[0] = c->t_op[1] = 0.0;
+  HIPCHK(c, hipEventRecord(c->ev[0], s));
+  launch_rank3(1, R, nullptr, nullptr, v2s, v3t, hi.gam, hi.psi, hi.lam, Fe, Te, ws.b, nullptr, nullptr, ws.part, n,
+               c->ph, s);
+  cnt.pairs += (double)n * (double)(n - 1);
+  HIPCHK(c, hipEventRecord(c->ev[1], s));
+  norm2(c, ws.b, len, sm.bnorm2, s);
+  CHK(read_status(c, sm.bnorm2, 1, s));
+  const double bnorm = sqrt(c->h_status[0]);
+  if (x0)
+    launch_copy(x0, ws.x, len, s);
+  else
+    launch_axpby(0.0, ws.b, 0.0, ws.x, len, s);
+  double resid = 0.0, rel = 0.0;
+  int rc = MBS_OK;
+  if (bnorm == 0.0 && !x0) {
+    rel = 0.0;  // x = 0 solves the system exactly
+  } else {
+    CHK(r3_gmres(c, n, R, ws, x0 == nullptr, c->prm.tol * bnorm, c->prm.max_iter, &resid, cnt, s));
+    rel = bnorm > 0.0 ? resid / bnorm : resid;
+    if (!(rel <= c->prm.tol)) rc = MBS_ENOCONV;
+  }
+  HIPCHK(c, hipEventRecord(c->ev[2], s));
+  launch_rank3(2, R, ws.x, v1s, v2s, nullptr, nullptr, nullptr, hi.lam, Fe, Te, V, W, S, ws.part, n, c->ph, s);
+  cnt.pairs += (double)n * (double)(n - 1);
+  if (x) launch_copy(ws.x, x, len, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipEventRecord(c->ev[3], s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  harvest_ops(c);
+  if (st) {
+    memset(st, 0, sizeof(*st));
+    st->iters = cnt.iters;
+    st->fp64_matvecs = cnt.f64;
+    st->rel_resid = rel;
+    st->t_rhs_ms = ev_ms(c->ev[0], c->ev[1]);
+    st->t_iter_ms = ev_ms(c->ev[1], c->ev[2]);
+    st->t_out_ms = ev_ms(c->ev[2], c->ev[3]);
+    st->t_total_ms = ev_ms(c->ev[0], c->ev[3]);
+    st->t_op64_ms = c->t_op[0];
+    st->pair_blocks = cnt.pairs;
+  }
+  if (rc == MBS_ENOCONV)
+    set_err(c, MBS_ENOCONV, "no convergence: relative residual %.3e after %d iterations", rel, cnt.iters);
+  return rc;
 }
 
 }  // extern "C"

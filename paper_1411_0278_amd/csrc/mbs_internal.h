@@ -70,6 +70,17 @@ int high_mask(const HighSlip& h);  // bit 0 gam, bit 1 psi, bit 2 lam
 int high_split(int64_t m, int64_t n, Tile t);
 void launch_high(int target, const double* X, int64_t m, const double* R, int64_t n, const HighSlip& h,
                  double* a, double* b, double* part, int split, const Phys& ph, Tile t, hipStream_t s);
+// Traction ranks <= 3: one all-pairs pass over the 20 unknowns per sphere x [n x 20] = [Sigma (5-basis),
+// X^gam (7-basis), X^psi (5-basis), X^d (3)]. mode 0: out = A x (out [n x 20]); mode 1: out = b from
+// the fixed sources (Fe, Te, lam; NULL = absent) and the prescribed slips (v2s, gam [n x 10], psi
+// [n x 5], v3t); mode 2: out = V, out2 = W [n x 3] of the solution x with the fixed sources, and
+// out3 = S [n x 5] (Sigma + slip_S v2s; skipped when NULL). part: scratch of rank3_part_elems(n) doubles.
+int rank3_split(int64_t n);
+int64_t rank3_part_elems(int64_t n);
+void launch_rank3(int mode, const double* R, const double* X20, const double* v1s, const double* v2s,
+                  const double* v3t, const double* gam, const double* psi, const double* lam, const double* Fe,
+                  const double* Te, double* out, double* out2, double* out3, double* part, int64_t n,
+                  const Phys& ph, hipStream_t s);
 // min over pairs of |R_n - R_m|^2 -> out[0] (device), from the cell grid g of R (exact: an
 // all-pairs scan takes over when no pair is closer than one cell edge); scratch: ceil(n/256) doubles
 struct GridView;

@@ -26,7 +26,9 @@ EXPORTS = ("mbs_default_params", "mbs_create", "mbs_destroy", "mbs_set_params", 
            "mbs_warmstart_forward", "mbs_warmstart_grad", "mbs_warmstart_train", "mbs_warmstart_save",
            "mbs_warmstart_load", "mbs_warmstart_target", "mbs_initial_guess", "mbs_precond_apply",
            "mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex", "mbs_matvec_static",
-           "mbs_warmstart_features", "mbs_features_ex")
+           "mbs_warmstart_features", "mbs_features_ex", "mbs_matvec_r3", "mbs_rhs_r3", "mbs_outputs_r3",
+           "mbs_solve_r3")
+R3_DIM = 20  # unknowns per sphere at traction ranks <= 3: Sigma (5), X^gam (7), X^psi (5), X^d (3)
 MLP_NPARAM, MLP_NFEAT = 27525, 80
 MLP_NPARAM_RHS, MLP_NFEAT_RHS = 37765, 160
 MBS_FEATURES_GEOMETRY, MBS_FEATURES_GEOMETRY_RHS = 0, 1
@@ -136,7 +138,12 @@ def load(path: str = LIB_PATH):
     lib.mbs_rhs_ex.argtypes = [P, I64, P, P, P, EX, P, P, P, VP]
     lib.mbs_outputs_ex.argtypes = [P, I64, P, P, P, P, EX] + [P] * 6 + [VP]
     lib.mbs_flow_ex.argtypes = [P, I64, P, I64, P, P, P, P, P, EX, P, VP]
-    for name in ("mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex"):
+    lib.mbs_matvec_r3.argtypes = [P, I64, P, P, P, VP]
+    lib.mbs_rhs_r3.argtypes = [P, I64, P, P, P, EX, P, P, P, VP]
+    lib.mbs_outputs_r3.argtypes = [P, I64, P, P, P, EX] + [P] * 6 + [VP]
+    lib.mbs_solve_r3.argtypes = [P, I64] + [P] * 4 + [EX] + [P] * 7 + [ctypes.POINTER(Stats), VP]
+    for name in ("mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex", "mbs_matvec_r3", "mbs_rhs_r3",
+                 "mbs_outputs_r3", "mbs_solve_r3"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mbs_warmstart_target", "mbs_initial_guess", "mbs_features", "mbs_features_ex",
                  "mbs_warmstart_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
@@ -339,6 +346,57 @@ class Context:
                                          _ptr(Te, n, 3, "Te"), _ptr(Sigma, n, 5, "Sigma"), _ptr(v3t, n, 3, "v3t"),
                                          ctypes.byref(ex), _ptr(U, m, 3, "U"), _stream()))
         return U
+
+    # ---- traction ranks <= 3: unknowns x [n, 20] = [Sigma (5-basis), X^gam (7-basis), X^psi, X^d]
+    def mbs_matvec_r3(self, R, x, y=None):
+        import torch
+        n = R.shape[0]
+        y = torch.empty((n, R3_DIM), dtype=torch.float64, device=R.device) if y is None else y
+        self._check(self.lib.mbs_matvec_r3(self.h, n, _ptr(R, n, 3, "R"), _ptr(x, n, R3_DIM, "x"),
+                                           _ptr(y, n, R3_DIM, "y"), _stream()))
+        return y
+
+    def mbs_rhs_r3(self, R, v2s=None, v3t=None, gam=None, psi=None, lam=None, Fe=None, Te=None, b=None):
+        import torch
+        n = R.shape[0]
+        b = torch.empty((n, R3_DIM), dtype=torch.float64, device=R.device) if b is None else b
+        ex = self._slip_ex(n, gam, psi, lam)
+        self._check(self.lib.mbs_rhs_r3(self.h, n, _ptr(R, n, 3, "R"), _ptr(v2s, n, 5, "v2s"), _ptr(v3t, n, 3, "v3t"),
+                                        ctypes.byref(ex), _ptr(Fe, n, 3, "Fe"), _ptr(Te, n, 3, "Te"),
+                                        _ptr(b, n, R3_DIM, "b"), _stream()))
+        return b
+
+    def mbs_outputs_r3(self, R, x, v1s=None, v2s=None, lam=None, Fe=None, Te=None, V=None, W=None, S=None):
+        import torch
+        n = R.shape[0]
+        V = torch.empty((n, 3), dtype=torch.float64, device=R.device) if V is None else V
+        W = torch.empty((n, 3), dtype=torch.float64, device=R.device) if W is None else W
+        S = torch.empty((n, 5), dtype=torch.float64, device=R.device) if S is None else S
+        ex = self._slip_ex(n, None, None, lam)
+        self._check(self.lib.mbs_outputs_r3(self.h, n, _ptr(R, n, 3, "R"), _ptr(v1s, n, 3, "v1s"),
+                                            _ptr(v2s, n, 5, "v2s"), ctypes.byref(ex), _ptr(Fe, n, 3, "Fe"),
+                                            _ptr(Te, n, 3, "Te"), _ptr(x, n, R3_DIM, "x"), _ptr(V, n, 3, "V"),
+                                            _ptr(W, n, 3, "W"), _ptr(S, n, 5, "S"), _stream()))
+        return V, W, S
+
+    def mbs_solve_r3(self, R, v1s=None, v2s=None, v3t=None, gam=None, psi=None, lam=None, Fe=None, Te=None,
+                     x0=None, V=None, W=None, S=None, x=None, allow_noconv=False):
+        """Returns V, W, S, x [n, 20] and the stats."""
+        import torch
+        n = R.shape[0]
+        V = torch.empty((n, 3), dtype=torch.float64, device=R.device) if V is None else V
+        W = torch.empty((n, 3), dtype=torch.float64, device=R.device) if W is None else W
+        S = torch.empty((n, 5), dtype=torch.float64, device=R.device) if S is None else S
+        x = torch.empty((n, R3_DIM), dtype=torch.float64, device=R.device) if x is None else x
+        ex = self._slip_ex(n, gam, psi, lam)
+        st = Stats()
+        rc = self.lib.mbs_solve_r3(self.h, n, _ptr(R, n, 3, "R"), _ptr(v1s, n, 3, "v1s"), _ptr(v2s, n, 5, "v2s"),
+                                   _ptr(v3t, n, 3, "v3t"), ctypes.byref(ex), _ptr(Fe, n, 3, "Fe"),
+                                   _ptr(Te, n, 3, "Te"), _ptr(x0, n, R3_DIM, "x0"), _ptr(V, n, 3, "V"),
+                                   _ptr(W, n, 3, "W"), _ptr(S, n, 5, "S"), _ptr(x, n, R3_DIM, "x"),
+                                   ctypes.byref(st), _stream())
+        self._check(rc, (MBS_ENOCONV,) if allow_noconv else ())
+        return V, W, S, x, st.as_dict()
 
     def mbs_step(self, R, p, k_trap, slip_coef, dt, nsteps, order=2, want_min_dist=False,
                  allow_noconv=False, hist=None, hist_valid=False):

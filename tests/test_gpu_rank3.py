@@ -1,0 +1,172 @@
+"""Traction ranks <= 3 on the GPU (section IV, minimal truncation with the septlet, vortlet and
+potential-dipole traction modes solved for): operator, right-hand side, outputs and solve against
+the oracle's dense rank <= 3 system, element by element, at sizes that span several workgroups and
+source tiles with ragged tails, and on sampled rows at 10^4 spheres."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+from oracle import basis, galerkin  # noqa: E402
+from paper_1411_0278_amd import inputs, mbstokes  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to(DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _maxrel(got, want):
+    got = _np(got) if hasattr(got, "detach") else np.asarray(got)
+    return np.abs(got - want).max() / max(np.abs(want).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mbstokes.Context(0)
+    yield c
+    c.close()
+
+
+def _workload(n, seed, side=None):
+    """Trap-like spheres at the benchmark density with every source and slip mode present."""
+    side = side or max(8.0, (n / 0.004) ** (1 / 3))
+    w = inputs.trap_workload(n, side, seed, v3t=1.0)
+    rng = np.random.default_rng(seed + 7)
+    w.Te = rng.standard_normal((n, 3))
+    w.gam, w.psi, w.lam = rng.standard_normal((n, 10)), rng.standard_normal((n, 5)), rng.standard_normal((n, 10))
+    return w
+
+
+def _prm(w):
+    return galerkin.Params(eta=w.eta, a=w.a)
+
+
+@pytest.mark.parametrize("n", [1, 2, 97, 257])
+def test_rank3_operator_matches_oracle(ctx, n):
+    print(f"rank3 matvec n={n}", flush=True)
+    w = _workload(n, 500 + n)
+    x = np.random.default_rng(n).standard_normal((n, 20))
+    want = (galerkin.system_matrix_rank3(w.R, _prm(w)) @ x.ravel()).reshape(n, 20)
+    got = ctx.mbs_matvec_r3(_t(w.R), _t(x))
+    assert _maxrel(got, want) < 1e-12
+    for lo, hi in ((0, 5), (5, 12), (12, 17), (17, 20)):  # every block of rows on its own scale
+        assert _maxrel(got[:, lo:hi], want[:, lo:hi]) < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 97, 257])
+def test_rank3_rhs_matches_oracle(ctx, n):
+    print(f"rank3 rhs n={n}", flush=True)
+    w = _workload(n, 600 + n)
+    want = galerkin.rhs_rank3(w, _prm(w)).reshape(n, 20)
+    got = ctx.mbs_rhs_r3(_t(w.R), _t(w.v2s), _t(w.v3t), _t(w.gam), _t(w.psi), _t(w.lam), _t(w.Fe), _t(w.Te))
+    for lo, hi in ((0, 5), (5, 12), (12, 17), (17, 20)):
+        assert _maxrel(got[:, lo:hi], want[:, lo:hi]) < 1e-12
+
+
+def test_rank3_null_inputs_mean_zero(ctx):
+    n = 97
+    w = _workload(n, 650)
+    z3, z5, z10 = np.zeros((n, 3)), np.zeros((n, 5)), np.zeros((n, 10))
+    R = _t(w.R)
+    b0 = ctx.mbs_rhs_r3(R, _t(w.v2s), None, None, None, None, _t(w.Fe), None)
+    bz = ctx.mbs_rhs_r3(R, _t(w.v2s), _t(z3), _t(z10), _t(z5), _t(z10), _t(w.Fe), _t(z3))
+    assert torch.equal(b0, bz)
+
+
+@pytest.mark.parametrize("n", [1, 2, 97, 257])
+def test_rank3_outputs_match_oracle(ctx, n):
+    print(f"rank3 outputs n={n}", flush=True)
+    w = _workload(n, 700 + n)
+    prm = _prm(w)
+    x = np.random.default_rng(n + 1).standard_normal((n, 20))
+    modes = {"SEPT7": x[:, 5:12], "VORT": x[:, 12:17], "SPIN": w.lam}
+    V, W, S = galerkin.outputs(w.R, w.v1s, w.v2s, x[:, 17:20], w.Fe, w.Te, x[:, 0:5], prm, modes=modes)
+    gV, gW, gS = ctx.mbs_outputs_r3(_t(w.R), _t(x), _t(w.v1s), _t(w.v2s), _t(w.lam), _t(w.Fe), _t(w.Te))
+    assert _maxrel(gV, V) < 1e-12
+    assert _maxrel(gW, W) < 1e-12
+    assert _maxrel(gS, S) < 1e-14
+
+
+@pytest.mark.parametrize("n", [1, 2, 60, 257])
+def test_rank3_solve_matches_oracle(ctx, n):
+    """The GMRES solution against the dense LU solution of the same system; the binary64 residual of
+    the GPU solution, evaluated with the oracle's matrix, meets the tolerance."""
+    print(f"rank3 solve n={n}", flush=True)
+    w = _workload(n, 800 + n)
+    prm = _prm(w)
+    sol = galerkin.solve_rank3(w, prm)
+    ctx.set_params(tol=1e-12)
+    try:
+        V, W, S, x, st = ctx.mbs_solve_r3(_t(w.R), _t(w.v1s), _t(w.v2s), _t(w.v3t), _t(w.gam), _t(w.psi),
+                                          _t(w.lam), _t(w.Fe), _t(w.Te))
+    finally:
+        ctx.set_params(tol=1e-10)
+    xs = np.concatenate([sol["Sigma"], sol["gam7"], sol["psi"], sol["d"]], axis=1)
+    b = sol["b"]
+    r = b - sol["A"] @ _np(x).ravel()
+    assert np.linalg.norm(r) <= 1.01e-12 * np.linalg.norm(b)
+    assert st["rel_resid"] <= 1e-12
+    assert abs(st["rel_resid"] - np.linalg.norm(r) / np.linalg.norm(b)) < 1e-13
+    assert _maxrel(x, xs) < 1e-9
+    assert _maxrel(V, sol["V"]) < 1e-9
+    assert _maxrel(W, sol["W"]) < 1e-9
+    assert _maxrel(S, sol["S"]) < 1e-9
+    if n == 1:  # a lone sphere: every equivalent slip is its prescribed slip
+        g7 = basis.to7(basis.sym3_from10(w.gam))
+        assert np.abs(_np(x)[:, 5:12] - g7).max() < 1e-14 * max(1.0, np.abs(g7).max())
+        assert np.abs(_np(x)[:, 12:17] - w.psi).max() < 1e-14 * max(1.0, np.abs(w.psi).max())
+        assert np.abs(_np(x)[:, 17:20] - w.v3t).max() < 1e-14 * max(1.0, np.abs(w.v3t).max())
+
+
+def test_rank3_solve_from_its_solution_takes_no_step_and_user_guess(ctx):
+    n = 97
+    w = _workload(n, 900)
+    args = [_t(a) for a in (w.R, w.v1s, w.v2s, w.v3t, w.gam, w.psi, w.lam, w.Fe, w.Te)]
+    V, W, S, x, st = ctx.mbs_solve_r3(*args)
+    V2, W2, S2, x2, st2 = ctx.mbs_solve_r3(*args, x0=x.clone())
+    assert st2["iters"] == 0 and st2["rel_resid"] <= ctx.params.tol
+    assert torch.equal(x2, x) and torch.equal(V2, V)
+
+
+def test_rank3_operator_at_ten_thousand_spheres_sampled_rows(ctx):
+    """The benchmarked size (10^4 spheres in the trap box at the benchmark density): sampled
+    receivers against all sources."""
+    n = 10_000
+    w = _workload(n, 1001, side=200.0)
+    x = np.random.default_rng(5).standard_normal((n, 20))
+    got = _np(ctx.mbs_matvec_r3(_t(w.R), _t(x)))
+    rows = np.random.default_rng(6).choice(n, 12, replace=False)
+    want = galerkin.matvec_rows_rank3(w.R, x, rows, _prm(w))
+    for lo, hi in ((0, 5), (5, 12), (12, 17), (17, 20)):
+        assert _maxrel(got[rows, lo:hi], want[:, lo:hi]) < 1e-11
+
+
+def test_rank3_errors(ctx):
+    n = 8
+    w = _workload(n, 950)
+    R, x = _t(w.R), _t(np.ones((n, 20)))
+    with pytest.raises(mbstokes.MbsError):
+        ctx.mbs_matvec_r3(R, x, y=x)  # output overlaps the input
+    bad = w.Fe.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(mbstokes.MbsError):
+        ctx.mbs_solve_r3(R, Fe=_t(bad))
+    ctx.set_params(max_iter=1, tol=1e-14)
+    try:
+        _, _, _, _, st = ctx.mbs_solve_r3(R, _t(w.v1s), _t(w.v2s), _t(w.v3t), Fe=_t(w.Fe), allow_noconv=True)
+        assert st["iters"] == 1 and st["rel_resid"] > 1e-14
+        with pytest.raises(mbstokes.MbsError):
+            ctx.mbs_solve_r3(R, _t(w.v1s), _t(w.v2s), _t(w.v3t), Fe=_t(w.Fe))
+    finally:
+        ctx.set_params(max_iter=300, tol=1e-10)

@@ -365,6 +365,11 @@ def test_rank3_system_reduces_and_is_consistent():
     A3 = galerkin.system_matrix_rank3(w.R, PRM).reshape(4, 20, 4, 20)
     A2 = galerkin.system_matrix(w.R, PRM).reshape(4, 5, 4, 5)
     assert np.abs(A3[:, 0:5, :, 0:5] - A2).max() < 1e-15 * np.abs(A2).max()
+    # the operator restricted to rows (used at sizes where A is not formed) is the same operator
+    x = np.random.default_rng(2).standard_normal((4, 20))
+    rows = np.array([3, 0])
+    y = (A3.reshape(80, 80) @ x.ravel()).reshape(4, 20)[rows]
+    assert np.abs(galerkin.matvec_rows_rank3(w.R, x, rows, PRM) - y).max() < 1e-14 * np.abs(y).max()
 
 
 # ---------------------------------------------------------------- two-sphere mobilities (Batchelor / Jeffrey-Onishi)
