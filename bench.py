@@ -68,6 +68,10 @@ def parse():
                          "density), with and without spatial ordering; 0 (default) skips it")
     ap.add_argument("--profile-passes", action="store_true",
                     help="short run for hardware counters: one launch of every binary64 pass kernel at N")
+    ap.add_argument("--skip-rank3", action="store_true", help="skip the traction rank <= 3 timings")
+    ap.add_argument("--profile-rank3", action="store_true",
+                    help="profiling mode: a 256 MiB device copy (counter calibration), then --steps "
+                         "rank <= 3 operator applications at N = 10^4")
     ap.add_argument("--profile-matvec", action="store_true",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then --steps "
                          "binary64 and --steps binary32 operator applications at the autotuned shapes")
@@ -130,16 +134,124 @@ def profile_passes(a, w):
           flush=True)
 
 
-def kernel_source_hash():
+P2_SOURCES = ("mbs_p2.hip", "mbs_pair.h", "mbs_device.h")
+RANK3_SOURCES = ("mbs_rank3.hip", "mbs_device.h")
+
+
+def profile_rank3(a):
+    """Short run for hardware-counter passes: calibration copy, then the rank <= 3 operator at 10^4."""
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+    src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)  # 256 MiB read + 256 MiB written
+    w = inputs.config1()
+    R = torch.as_tensor(w.R, dtype=torch.float64).to("cuda:0")
+    gen = torch.Generator(device="cuda:0").manual_seed(3)
+    x = torch.randn((w.n, 20), dtype=torch.float64, device="cuda:0", generator=gen)
+    ctx = mbstokes.Context(0)
+    y = ctx.mbs_matvec_r3(R, x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.steps):
+        ctx.mbs_matvec_r3(R, x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"mode": "profile-rank3", "n": w.n, "ms_per_launch": e0.elapsed_time(e1) / a.steps,
+                      "copy_bytes": 2 * src.numel() * 8}), flush=True)
+
+
+def bench_rank3(ctx, a):
+    """Traction ranks <= 3 (septlet, vortlet and potential-dipole traction modes solved for beside the
+    stresslet; 20 unknowns per sphere, binary64). The operator pass at 10^4 spheres (the trap box of
+    side 200) and at the benchmark N; at 10^4 also the right-hand-side and output passes and the
+    solve to 1e-10 with every slip mode present (uniaxial modes from the orientations: s = 3(pp - I/3),
+    d = p, gamma, psi, lambda of the orientations, F = -0.5 R). Median of 5 launches after 2 warm-ups
+    (3 solves after 1), HIP events on the launch stream; the roofline is the executed FLOP per pair
+    from the committed counters against the binary64 vector peak."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+
+    def median_ms(fn, warm=2, reps=5):
+        for _ in range(warm):
+            fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return statistics.median(ts)
+
+    out = {"unknowns_per_sphere": 20, "dtype": "f64", "peak_tflops_f64_vector": 78.6}
+    for label, w in (("n10000", inputs.trap_workload(10_000, 200.0, 1, v3t=1.0)),
+                     ("n%d" % a.n, inputs.trap_workload(a.n, a.side, a.seed, v3t=1.0))):
+        n = w.n
+        f = lambda v: torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64).to("cuda:0")
+        R = f(w.R)
+        gen = torch.Generator(device="cuda:0").manual_seed(3)
+        x = torch.randn((n, 20), dtype=torch.float64, device="cuda:0", generator=gen)
+        y = torch.empty_like(x)
+        ms = median_ms(lambda: ctx.mbs_matvec_r3(R, x, y), reps=5 if n <= 20_000 else 3)
+        pairs = n * (n - 1)
+        row = {"n": n, "matvec": {"ms": round(ms, 4), "pair_blocks_per_s": pairs / (ms * 1e-3)}}
+        rec = measured_counters("k_rank3_op", n, RANK3_SOURCES)
+        ex = rec.get("executed_flop_per_pair") if rec else None
+        row["matvec"]["executed_flop_per_pair"] = ex
+        row["matvec"]["executed_tflops"] = round(ex * pairs / (ms * 1e-3) / 1e12, 3) if ex else None
+        row["matvec"]["frac_executed"] = round(ex * pairs / (ms * 1e-3) / 1e12 / 78.6, 4) if ex else None
+        if n <= 20_000:
+            g, ps, l = inputs.higher_slip_modes(w.p, 1.0, 1.0, 1.0)
+            hm = dict(gam=f(g), psi=f(ps), lam=f(l))
+            d = mbstokes.to_device(w, "cuda:0")
+            ms = median_ms(lambda: ctx.mbs_rhs_r3(d["R"], d["v2s"], d["v3t"], Fe=d["Fe"], **hm))
+            row["rhs"] = {"ms": round(ms, 4)}
+            ms = median_ms(lambda: ctx.mbs_outputs_r3(d["R"], x, d["v1s"], d["v2s"], hm["lam"], Fe=d["Fe"]))
+            row["outputs"] = {"ms": round(ms, 4)}
+            ctx.set_params(tol=1e-10, max_iter=300, precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO,
+                           near_cutoff=0.0, superposition=0)
+            sts = []
+            for k in range(4):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                V, W, S, xs, st = ctx.mbs_solve_r3(d["R"], d["v1s"], d["v2s"], d["v3t"], Fe=d["Fe"], **hm)
+                torch.cuda.synchronize()
+                if k:
+                    st["wall_ms"] = 1e3 * (time.perf_counter() - t0)
+                    sts.append(st)
+            med = sorted(sts, key=lambda t: t["wall_ms"])[len(sts) // 2]
+            row["solve"] = {"ms": round(med["wall_ms"], 3), "device_ms": round(med["t_total_ms"], 3),
+                            "iters": med["iters"], "fp64_matvecs": med["fp64_matvecs"],
+                            "rel_resid": med["rel_resid"], "t_op64_ms": round(med["t_op64_ms"], 3)}
+            # how far the rank <= 2 truncation is from it on the same spheres (the modes' one-body
+            # closure against solving for them): relative change of V and Omega
+            V2, W2, S2, _ = ctx.mbs_solve_ex(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], Fe=d["Fe"], **hm)
+            row["vs_rank2"] = {"rel_change_V": float((V - V2).norm() / V.norm()),
+                               "rel_change_Omega": float((W - W2).norm() / W.norm())}
+        out[label] = row
+        print(f"bench: rank-3 {label} matvec {row['matvec']['ms']} ms", file=sys.stderr, flush=True)
+    return out
+
+
+def kernel_source_hash(files=P2_SOURCES):
     h = hashlib.sha256()
-    for f in ("mbs_p2.hip", "mbs_pair.h", "mbs_device.h"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_1411_0278_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_counters(kernel, n):
+def measured_counters(kernel, n, files=P2_SOURCES):
     """The committed PMC record of a kernel at size n (HBM bytes per launch, executed FLOP per pair),
-    if the counters were taken on the current kernel source; else None."""
+    if the counters were taken on the current source of the files it is built from; else None."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -147,7 +259,7 @@ def measured_counters(kernel, n):
         rec = json.load(open(path)).get(f"{kernel}@n{n}")
     except Exception:
         return None
-    if not rec or rec.get("source_sha") != kernel_source_hash():
+    if not rec or rec.get("source_sha") != kernel_source_hash(files):
         return None
     return rec
 
@@ -463,6 +575,80 @@ def bench_paper_trap(ctx, a):
     return out
 
 
+def bench_two_particle_orbits(ctx, horizon_tau=100, snap_tau=10):
+    """Two active spheres in the trap of section V at R* = 12.56a (the two-particle figure): sphere 1
+    at the pole, sphere 2 at the angle theta0 from it in the x-z plane, both pointing outward, mean
+    slip only (V^a = p, as the 10^4-sphere run; the figure's stresslet and potential-dipole strengths
+    are not given). AB2 with dt = 0.1 (tau_r / 167) for up to horizon_tau rotation times, stopped at
+    the first step whose centre distance falls below 2a (the model has no contact force, so the motion
+    past contact means nothing). A snapshot every snap_tau: polar angles of both centres in the x-z
+    plane (from +z towards -x, degrees), |R|/R*, the centre distance and p.R/|R|. Superposition for
+    every theta0, the many-body solve for three of them."""
+    import numpy as np
+    import torch
+
+    from paper_1411_0278_amd import mbstokes
+    rstar, eta, a = 12.56, ctx.params.eta, ctx.params.a
+    k = 6.0 * np.pi * eta * a / (rstar * a)
+    tau_r = 8.0 * np.pi * eta * a / k
+    dt = 0.1
+    per = int(round(tau_r / dt))
+    out = {"Rstar_over_a": rstar, "k": k, "tau_r": tau_r, "dt": dt, "steps_per_tau_r": per,
+           "slip": "V^a = p (mean slip only)", "plane": "x-z", "stop": "first centre distance < 2a",
+           "orbits": []}
+
+    def snap(R, p, t):
+        Rn, pn = R.cpu().numpy(), p.cpu().numpy()
+        r = np.linalg.norm(Rn, axis=1)
+        ang = np.degrees(np.arctan2(-Rn[:, 0], Rn[:, 2])) % 360.0
+        return {"t_over_tau_r": round(t / tau_r, 2), "polar_deg": [round(float(v), 2) for v in ang],
+                "radius_over_Rstar": [round(float(v), 5) for v in r / rstar],
+                "distance_over_a": round(float(np.linalg.norm(Rn[0] - Rn[1]) / a), 4),
+                "p_dot_rhat": [round(float(v), 6) for v in (pn * Rn).sum(1) / r],
+                "out_of_plane": float(np.abs(Rn[:, 1]).max() + np.abs(pn[:, 1]).max())}
+
+    for theta0, modes in ((180, (1, 0)), (115, (1, 0)), (190, (1, 0)), (260, (1, 0))):
+        th = np.radians(theta0)
+        R0 = rstar * a * np.array([[0.0, 0.0, 1.0], [-np.sin(th), 0.0, np.cos(th)]])
+        p0 = R0 / np.linalg.norm(R0, axis=1, keepdims=True)
+        for sup in modes:
+            R = torch.as_tensor(R0).to("cuda:0")
+            p = torch.as_tensor(p0).to("cuda:0")
+            hist = torch.zeros(22, dtype=torch.float64, device="cuda:0")
+            ctx.set_params(superposition=sup, precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO,
+                           tol=1e-12, near_cutoff=0.0, max_iter=60)
+            snaps, mind, done, contact = [snap(R, p, 0.0)], float("inf"), 0, None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for blk in range(horizon_tau):
+                _, md = ctx.mbs_step(R, p, k, (-1.0, 0.0, 0.0), dt, per, order=2, want_min_dist=True,
+                                     hist=hist, hist_valid=done > 0)
+                hit = [i for i, v in enumerate(md) if v < 2.0 * a]
+                if hit:  # the configuration after step done + hit[0] + 1 overlaps
+                    contact = (done + hit[0] + 1) * dt / tau_r
+                    mind = min(mind, min(md[:hit[0]]) if hit[0] else mind)
+                    done += per
+                    break
+                mind = min(mind, min(md))
+                done += per
+                if (blk + 1) % snap_tau == 0:
+                    snaps.append(snap(R, p, done * dt))
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            rad = [v for s_ in snaps for v in s_["radius_over_Rstar"]]
+            out["orbits"].append({
+                "theta0": theta0, "mode": "superposition" if sup else "many_body", "steps": done,
+                "ms_per_step": 1e3 * secs / done, "contact_at_t_over_tau_r": round(contact, 3) if contact else None,
+                "min_distance_before_contact_over_a": round(mind / a, 4),
+                "radius_over_Rstar_range": [min(rad), max(rad)],
+                "min_p_dot_rhat": min(v for s_ in snaps for v in s_["p_dot_rhat"]), "snapshots": snaps})
+            print(f"bench: two-particle orbit theta0={theta0} {'superposition' if sup else 'many-body'} "
+                  f"{done} steps in {secs:.1f} s, contact at {contact}", file=sys.stderr, flush=True)
+    ctx.set_params(superposition=0, precision=mbstokes.MBS_FP64, guess=mbstokes.MBS_GUESS_ZERO, tol=1e-10,
+                   max_iter=300)
+    return out
+
+
 def _host_info():
     """Host cores available to this process and the CPU model (from /proc/cpuinfo)."""
     import platform
@@ -704,6 +890,9 @@ def main():
     if a.profile_matvec:
         profile_matvec(a, w)
         return
+    if a.profile_rank3:
+        profile_rank3(a)
+        return
     d = mbstokes.to_device(w, "cuda:0")
     # the workload has no external torque and no rank-3 trace slip: pass NULL (= zero)
     d.pop("Te")
@@ -767,6 +956,9 @@ def main():
     if not a.skip_stepper:
         extra["stepper"] = bench_stepper(ctx, a)
         extra["paper_trap"] = bench_paper_trap(ctx, a)
+        extra["paper_trap"]["two_particle"] = bench_two_particle_orbits(ctx)
+    if not a.skip_rank3:
+        extra["rank3"] = bench_rank3(ctx, a)
     if a.scale_n > 0:
         extra["scale"] = bench_scale(a)
     head = variants[a.headline]

@@ -104,6 +104,20 @@ __device__ __forceinline__ void jaxpyL(double s, const J2& A, const LW& w, J2& a
   acc.czz = fma(s2, A.czz, acc.czz);
 }
 
+// A *= s
+__device__ __forceinline__ void jscale(double s, J2& A) {
+  A.c0 *= s;
+  A.cx *= s;
+  A.cy *= s;
+  A.cz *= s;
+  A.cxx *= s;
+  A.cxy *= s;
+  A.cxz *= s;
+  A.cyy *= s;
+  A.cyz *= s;
+  A.czz *= s;
+}
+
 __device__ __forceinline__ J2 jlin(double c0, double cx, double cy, double cz) {
   J2 A;
   A.c0 = c0;
@@ -262,15 +276,23 @@ struct alignas(16) Rec3 {
 constexpr int kR3TJ = 32;   // source records per LDS tile
 constexpr int kR3Blk = 128;  // receivers per workgroup
 enum { kR3Op = 0, kR3Rhs = 1, kR3Out = 2 };
+// Source groups, each swept by its own workgroups (grid.y = groups x source chunks) so that each
+// sweep's registers are those of its own sources: the fixed sources (force, torque, spinlet slip),
+// the flow stresslet with X^d, and X^g with X^p.
+enum { kGFix = 1, kGSig = 2, kGQuad = 4 };
+constexpr int r3_ngroups(int mode) { return mode == kR3Op ? 2 : (mode == kR3Rhs ? 1 : 3); }
+constexpr int r3_group(int mode, int g) {
+  return mode == kR3Op ? (g == 0 ? kGSig : kGQuad) : (mode == kR3Rhs ? kGFix : (g == 0 ? kGFix : (g == 1 ? kGSig : kGQuad)));
+}
 
 struct R3C {  // per-problem constants
   double a2, a5, a7;
   LW w;
 };
 
-// add the flow of source record s at x = receiver - source, with its Laplacian weighted as in
-// jaxpyL, to A[3]
-template <int MODE>
+// add the flow of the sources of group(s) GRP in record s at x = receiver - source, with its
+// Laplacian weighted as in jaxpyL, to A[3]
+template <int GRP>
 __device__ __forceinline__ void r3_pair(const Rec3& s, double x, double y, double z, const R3C& k, J2 A[3]) {
   const double r2 = fma(x, x, fma(y, y, z * z));
   const double ri = rsq_nr(r2);
@@ -280,7 +302,7 @@ __device__ __forceinline__ void r3_pair(const Rec3& s, double x, double y, doubl
   const J2 R5 = jradial(5.0, p5, p7, p9, x, y, z);
   const J2 R7 = jradial(7.0, p7, p9, p11, x, y, z);
   const J2 X[3] = {jlin(x, 1.0, 0.0, 0.0), jlin(y, 0.0, 1.0, 0.0), jlin(z, 0.0, 0.0, 1.0)};
-  if (MODE != kR3Op) {  // force and torque
+  if (GRP & kGFix) {  // force, torque, spinlet slip
     const J2 R1 = jradial(1.0, ri, p3, p5, x, y, z);
     J2 c1 = R1;
     jaxpy(k.a2 / 3.0, R3, c1);
@@ -318,9 +340,7 @@ __device__ __forceinline__ void r3_pair(const Rec3& s, double x, double y, doubl
     jaxpy(cl, jmul(wy, R7), A[1]);
     jaxpy(cl, jmul(wz, R7), A[2]);
   }
-  if (MODE != kR3Rhs) {  // flow stresslet, X^d, X^g, X^p
-    const J2 R9 = jradial(9.0, p9, p11, p13, x, y, z);
-    // Sigma (Cartesian xx yy xy xz yz zz)
+  if (GRP & kGSig) {  // flow stresslet and X^d
     const double* S = s.s;
     const J2 w[3] = {jlin(fma(S[0], x, fma(S[2], y, S[3] * z)), S[0], S[2], S[3]),
                      jlin(fma(S[2], x, fma(S[1], y, S[4] * z)), S[2], S[1], S[4]),
@@ -329,55 +349,34 @@ __device__ __forceinline__ void r3_pair(const Rec3& s, double x, double y, doubl
     jaxpy(1.0, jmul(X[1], w[1]), q);
     jaxpy(1.0, jmul(X[2], w[2]), q);
     J2 cq = R7;  // 3a^2/r^7 - 3/r^5
-    cq.c0 *= 3.0 * k.a2;
-    cq.cx *= 3.0 * k.a2;
-    cq.cy *= 3.0 * k.a2;
-    cq.cz *= 3.0 * k.a2;
-    cq.cxx *= 3.0 * k.a2;
-    cq.cxy *= 3.0 * k.a2;
-    cq.cxz *= 3.0 * k.a2;
-    cq.cyy *= 3.0 * k.a2;
-    cq.cyz *= 3.0 * k.a2;
-    cq.czz *= 3.0 * k.a2;
+    jscale(3.0 * k.a2, cq);
     jaxpy(-3.0, R5, cq);
     const J2 tq = jmul(q, cq);
     const J2 tl = jmul(q, R7);
     // X^d ((a^5/10)-scaled): 3 (x.d) x/r^5 - d/r^3
     const J2 xd = jlin(fma(x, s.d[0], fma(y, s.d[1], z * s.d[2])), s.d[0], s.d[1], s.d[2]);
     const J2 td = jmul(xd, R5);
-    // X^g: g = X^g:xx, Q = g.x
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const J2 r5w = jmul(R5, w[i]);
+      jaxpy(1.0, jmul(tq, X[i]), A[i]);
+      jaxpy(-1.2 * k.a2, r5w, A[i]);
+      jaxpyL(30.0, jmul(tl, X[i]), k.w, A[i]);
+      jaxpyL(-12.0, r5w, k.w, A[i]);
+      jaxpy(3.0, jmul(td, X[i]), A[i]);
+      jaxpy(-s.d[i], R3, A[i]);
+    }
+  }
+  if (GRP & kGQuad) {  // X^g and X^p
+    const J2 R9 = jradial(9.0, p9, p11, p13, x, y, z);
     J2 g[3], Q;
     quad_jets(sym3_of(s.g), x, y, z, g, Q);
     J2 ca = R5;  // -7a^5/(16 r^5) + 15a^7/(16 r^7)
-    {
-      const double s5 = -7.0 / 16.0 * k.a5;
-      ca.c0 *= s5;
-      ca.cx *= s5;
-      ca.cy *= s5;
-      ca.cz *= s5;
-      ca.cxx *= s5;
-      ca.cxy *= s5;
-      ca.cxz *= s5;
-      ca.cyy *= s5;
-      ca.cyz *= s5;
-      ca.czz *= s5;
-      jaxpy(15.0 / 16.0 * k.a7, R7, ca);
-    }
+    jscale(-7.0 / 16.0 * k.a5, ca);
+    jaxpy(15.0 / 16.0 * k.a7, R7, ca);
     J2 cb = R7;  // 35a^5/(16 r^7) - 35a^7/(16 r^9)
-    {
-      const double s7 = 35.0 / 16.0 * k.a5;
-      cb.c0 *= s7;
-      cb.cx *= s7;
-      cb.cy *= s7;
-      cb.cz *= s7;
-      cb.cxx *= s7;
-      cb.cxy *= s7;
-      cb.cxz *= s7;
-      cb.cyy *= s7;
-      cb.cyz *= s7;
-      cb.czz *= s7;
-      jaxpy(-35.0 / 16.0 * k.a7, R9, cb);
-    }
+    jscale(35.0 / 16.0 * k.a5, cb);
+    jaxpy(-35.0 / 16.0 * k.a7, R9, cb);
     const J2 Qb = jmul(Q, cb);
     const J2 Q9 = jmul(Q, R9);
     const double lg = 7.0 / 24.0 * k.a5;
@@ -396,27 +395,16 @@ __device__ __forceinline__ void r3_pair(const Rec3& s, double x, double y, doubl
     const double cp = -k.a5 / 3.0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      // Sigma
-      const J2 r5w = jmul(R5, w[i]);
-      jaxpy(1.0, jmul(tq, X[i]), A[i]);
-      jaxpy(-1.2 * k.a2, r5w, A[i]);
-      jaxpyL(30.0, jmul(tl, X[i]), k.w, A[i]);
-      jaxpyL(-12.0, r5w, k.w, A[i]);
-      // X^d
-      jaxpy(3.0, jmul(td, X[i]), A[i]);
-      jaxpy(-s.d[i], R3, A[i]);
-      // X^g
       jaxpy(1.0, jmul(g[i], ca), A[i]);
       jaxpy(1.0, jmul(Qb, X[i]), A[i]);
       jaxpyL(45.0 * lg, jmul(g[i], R7), k.w, A[i]);
       jaxpyL(-105.0 * lg, jmul(Q9, X[i]), k.w, A[i]);
-      // X^p
       jaxpy(cp, jmul(xw[i], R5), A[i]);
     }
   }
 }
 
-template <int MODE>
+template <int GRP>
 __device__ __forceinline__ Rec3 make_rec3(int j, const double* __restrict__ R, const double* __restrict__ X20,
                                           const double* __restrict__ Fe, const double* __restrict__ Te,
                                           const double* __restrict__ lam, double P, double a5_10) {
@@ -424,15 +412,15 @@ __device__ __forceinline__ Rec3 make_rec3(int j, const double* __restrict__ R, c
   r.x = R[3 * (int64_t)j];
   r.y = R[3 * (int64_t)j + 1];
   r.z = R[3 * (int64_t)j + 2];
-  if (MODE != kR3Op) {
+  if (GRP & kGFix) {
     for (int c = 0; c < 3; ++c) {
       r.f[c] = Fe ? P * Fe[3 * (int64_t)j + c] : 0.0;
       r.t[c] = Te ? P * Te[3 * (int64_t)j + c] : 0.0;
     }
     if (lam) stf10(lam + 10 * (int64_t)j, r.l);
   }
-  if (MODE != kR3Rhs) {
-    const double* x = X20 + 20 * (int64_t)j;
+  const double* x = X20 + 20 * (int64_t)j;
+  if (GRP & kGSig) {
     double sxx, syy, sxy, sxz, syz;
     basis_to_cart(x, sxx, syy, sxy, sxz, syz);
     r.s[0] = P * sxx;
@@ -441,6 +429,9 @@ __device__ __forceinline__ Rec3 make_rec3(int j, const double* __restrict__ R, c
     r.s[3] = P * sxz;
     r.s[4] = P * syz;
     r.s[5] = -P * (sxx + syy);
+    for (int c = 0; c < 3; ++c) r.d[c] = a5_10 * x[17 + c];
+  }
+  if (GRP & kGQuad) {
     from7(x + 5, r.g);
     double pxx, pyy, pxy, pxz, pyz;
     basis_to_cart(x + 12, pxx, pyy, pxy, pxz, pyz);
@@ -450,7 +441,6 @@ __device__ __forceinline__ Rec3 make_rec3(int j, const double* __restrict__ R, c
     r.p[3] = pxz;
     r.p[4] = pyz;
     r.p[5] = -(pxx + pyy);
-    for (int c = 0; c < 3; ++c) r.d[c] = a5_10 * x[17 + c];
   }
   return r;
 }
@@ -458,31 +448,48 @@ __device__ __forceinline__ Rec3 make_rec3(int j, const double* __restrict__ R, c
 // width of the per-receiver partial sums: 20 projections (E, septlet, vortlet, potential dipole) or 6 (U, W)
 constexpr int r3_width(int mode) { return mode == kR3Out ? 6 : 20; }
 
+// Sum over the sources j0 <= j < j1 of group(s) GRP at receiver (xi, yi, zi) (index ii: skipped)
+template <int GRP>
+__device__ __forceinline__ void r3_sweep(Rec3* tile, int ii, double xi, double yi, double zi, int j0, int j1,
+                                         const double* __restrict__ R, const double* __restrict__ X20,
+                                         const double* __restrict__ Fe, const double* __restrict__ Te,
+                                         const double* __restrict__ lam, double P, const R3C& k, J2 A[3]) {
+  for (int jt = j0; jt < j1; jt += kR3TJ) {
+    const int cnt = min(kR3TJ, j1 - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x)
+      tile[t] = make_rec3<GRP>(jt + t, R, X20, Fe, Te, lam, P, 0.1 * k.a5);
+    __syncthreads();
+    for (int jj = 0; jj < cnt; ++jj) {
+      if (jt + jj == ii) continue;  // a sphere does not act on itself
+      const Rec3& s = tile[jj];
+      r3_pair<GRP>(s, xi - s.x, yi - s.y, zi - s.z, k, A);
+    }
+  }
+}
+
+// grid: (receiver blocks, groups x chunks); workgroup y sweeps source chunk y % split of group
+// y / split and writes partial slice y
 template <int MODE>
 __global__ void __launch_bounds__(kR3Blk)
     k_rank3(const double* __restrict__ R, const double* __restrict__ X20, const double* __restrict__ Fe,
-            const double* __restrict__ Te, const double* __restrict__ lam, int n, int chunk, double P, double a2,
-            double a5, double a7, double* __restrict__ part) {
+            const double* __restrict__ Te, const double* __restrict__ lam, int n, int chunk, int split, double P,
+            double a2, double a5, double a7, double* __restrict__ part) {
   __shared__ Rec3 tile[kR3TJ];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int ii = i < n ? i : n - 1;
   const double xi = R[3 * (int64_t)ii], yi = R[3 * (int64_t)ii + 1], zi = R[3 * (int64_t)ii + 2];
   const R3C k{a2, a5, a7, LW{a2 / 6.0, a2 / 10.0, a2 / 14.0}};
-  const int j0 = blockIdx.y * chunk;
+  const int grp = blockIdx.y / split;  // uniform
+  const int j0 = (blockIdx.y % split) * chunk;
   const int j1 = min(n, j0 + chunk);
   J2 A[3];
-  for (int jt = j0; jt < j1; jt += kR3TJ) {
-    const int cnt = min(kR3TJ, j1 - jt);
-    __syncthreads();
-    for (int t = threadIdx.x; t < cnt; t += blockDim.x)
-      tile[t] = make_rec3<MODE>(jt + t, R, X20, Fe, Te, lam, P, 0.1 * a5);
-    __syncthreads();
-    for (int jj = 0; jj < cnt; ++jj) {
-      if (jt + jj == ii) continue;  // a sphere does not act on itself
-      const Rec3& s = tile[jj];
-      r3_pair<MODE>(s, xi - s.x, yi - s.y, zi - s.z, k, A);
-    }
-  }
+  if (grp == 0)
+    r3_sweep<r3_group(MODE, 0)>(tile, ii, xi, yi, zi, j0, j1, R, X20, Fe, Te, lam, P, k, A);
+  else if (grp == 1)
+    r3_sweep<r3_group(MODE, 1)>(tile, ii, xi, yi, zi, j0, j1, R, X20, Fe, Te, lam, P, k, A);
+  else
+    r3_sweep<r3_group(MODE, 2)>(tile, ii, xi, yi, zi, j0, j1, R, X20, Fe, Te, lam, P, k, A);
   if (i >= n) return;
   double* o = part + ((int64_t)blockIdx.y * n + i) * r3_width(MODE);
   if (MODE == kR3Out) {  // U = F^0 u, W = curl u / 2
@@ -591,7 +598,8 @@ int rank3_split(int64_t n) {
   return (int)s;
 }
 
-int64_t rank3_part_elems(int64_t n) { return (int64_t)rank3_split(n) * 20 * n; }
+// the largest of groups x split x width over the three modes (the operator: 2 x split x 20)
+int64_t rank3_part_elems(int64_t n) { return (int64_t)rank3_split(n) * 40 * n; }
 
 namespace {
 template <int M>
@@ -602,9 +610,10 @@ void launch_rank3_mode(const double* R, const double* X20, const double* v1s, co
   const int split = rank3_split(n);
   const int chunk = (int)((n + split - 1) / split);
   const double a2 = ph.a2, a5 = a2 * a2 * ph.a, a7 = a5 * a2;
-  hipLaunchKernelGGL(k_rank3<M>, dim3(nblk3(n, kR3Blk), split), dim3(kR3Blk), 0, s, R, X20, Fe, Te, lam, (int)n,
-                     chunk, ph.P, a2, a5, a7, part);
-  hipLaunchKernelGGL(k_rank3_finish<M>, dim3(nblk3(n, 256)), dim3(256), 0, s, part, split, (int)n, X20, v1s, v2s,
+  const int slices = r3_ngroups(M) * split;
+  hipLaunchKernelGGL(k_rank3<M>, dim3(nblk3(n, kR3Blk), slices), dim3(kR3Blk), 0, s, R, X20, Fe, Te, lam, (int)n,
+                     chunk, split, ph.P, a2, a5, a7, part);
+  hipLaunchKernelGGL(k_rank3_finish<M>, dim3(nblk3(n, 256)), dim3(256), 0, s, part, slices, (int)n, X20, v1s, v2s,
                      v3t, gam, psi, Fe, Te, ph.inv_gamma, ph.c_slip, ph.mu_t, ph.mu_r, ph.slip_S, out, out2,
                      out3);
 }

@@ -636,6 +636,31 @@ def test_antipodal_active_pair_keeps_its_orientation(ctx, superposition):
     assert np.abs(R.cpu().numpy()[:, :2]).max() < 1e-12
 
 
+@pytest.mark.parametrize("theta0", [115, 260])
+@pytest.mark.parametrize("superposition", [1, 0])
+def test_two_particle_trap_orbit_matches_oracle(ctx, theta0, superposition):
+    """The two-particle trap of section V (R* = 12.56a, sphere 2 at theta0 from sphere 1 in the x-z
+    plane, both pointing outward, mean slip only): 200 AB2 steps of dt = 0.5 (six rotation times)
+    against the oracle's stepper; the motion stays in the plane of the initial condition."""
+    print(f"two-particle orbit theta0={theta0} superposition={superposition}", flush=True)
+    rs = 12.56
+    th = np.radians(theta0)
+    Rn = rs * np.array([[0.0, 0.0, 1.0], [-np.sin(th), 0.0, np.cos(th)]])
+    pn = Rn / rs
+    k = 1.0 / rs  # 6 pi eta a v_s / R* with eta = 1/(6 pi), a = 1, v_s = 1
+    prm = galerkin.Params(eta=1.0 / (6.0 * np.pi), a=1.0)
+    Rw, pw, _ = stepper.run(Rn, pn, k, (-1.0, 0.0, 0.0), 0.5, 200, prm, order=2, superposition=bool(superposition))
+    R, p = _t(Rn), _t(pn)
+    ctx.set_params(superposition=superposition, tol=1e-13)
+    try:
+        ctx.mbs_step(R, p, k, (-1.0, 0.0, 0.0), 0.5, 200, order=2)
+    finally:
+        ctx.set_params(superposition=0, tol=1e-10)
+    assert _maxrel(R, Rw) < 1e-9 and _maxrel(p, pw) < 1e-9
+    assert np.abs(R.cpu().numpy()[:, 1]).max() < 1e-12 and np.abs(p.cpu().numpy()[:, 1]).max() < 1e-12
+    assert np.linalg.norm(Rw[0] - Rn[0]) > 0.1  # the pair has started to move round the trap
+
+
 # ---------------------------------------------------------------- batched
 def _batch(ws):
     off = np.cumsum([0] + [w.n for w in ws])
