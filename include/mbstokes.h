@@ -366,9 +366,13 @@ int mbs_step(mbs_ctx* ctx, int64_t n, double* R, double* p, double k_trap, const
    every configuration, decomposed into (configuration, receiver tile) work items, tiles of
    params.batch_item receivers or the size mbs_autotune_batched picked (largest configurations
    first); converged
-   configurations drop out of later passes. With params.graph the phases are captured once per batch
-   shape into HIP graphs on a stream owned by the context and replayed (the iteration graph holds
-   four Arnoldi steps); the call synchronises with `stream` on entry and exit.
+   configurations drop out of later passes. A configuration is certified (binary64 residual) in the
+   round of four Arnoldi steps in which its own cycle ends and then leaves the sweeps. With
+   params.graph the phases are captured once per batch shape into HIP graphs on a stream owned by
+   the context and replayed; from the second call of a batch shape on, the whole solve (init, the
+   number of rounds the first call took, outputs) is one graph launch, followed by one read of the
+   count of active configurations and more rounds only if one is still active. The call
+   synchronises with `stream` on entry and exit.
    per_conf: host [nconf] or NULL (iters, rel_resid, pair_blocks, t_total_ms of the whole batch).
    latency_ms: host [nconf] or NULL: time from the start of the batch to the device clock reading
    taken when the configuration's true residual met the tolerance. Returns MBS_ENOCONV if some
