@@ -204,9 +204,12 @@ def bench_rank3(ctx, a):
         ms = median_ms(lambda: ctx.mbs_matvec_r3(R, x, y), reps=5 if n <= 20_000 else 3)
         pairs = n * (n - 1)
         row = {"n": n, "matvec": {"ms": round(ms, 4), "pair_blocks_per_s": pairs / (ms * 1e-3)}}
-        rec = measured_counters("k_rank3_op", n, RANK3_SOURCES)
+        # executed FLOP per pair is a property of the pair arithmetic: the counters taken at 10^4
+        # apply at every size
+        rec = measured_counters("k_rank3_op", 10_000, RANK3_SOURCES)
         ex = rec.get("executed_flop_per_pair") if rec else None
         row["matvec"]["executed_flop_per_pair"] = ex
+        row["matvec"]["counters_taken_at_n"] = 10_000 if ex else None
         row["matvec"]["executed_tflops"] = round(ex * pairs / (ms * 1e-3) / 1e12, 3) if ex else None
         row["matvec"]["frac_executed"] = round(ex * pairs / (ms * 1e-3) / 1e12 / 78.6, 4) if ex else None
         if n <= 20_000:
@@ -708,6 +711,13 @@ def _cpu_subset_rows(job):
     return galerkin.outputs(w.R, w.v1s, w.v2s, w.v3t, w.Fe, w.Te, extra, prm, rows)
 
 
+def _cpu_matvec_rows(job):
+    """Rows of the oracle's operator y = A x for one block of receivers (all sources)."""
+    from oracle import galerkin
+    R, x, rows, eta, a = job
+    return galerkin.matvec_rows(R, x, rows, galerkin.Params(eta=eta, a=a))
+
+
 def _cpu_pool(cores, initargs=None):
     """Spawned worker processes with one BLAS thread each (they run only the oracle, never the GPU)."""
     import multiprocessing as mp
@@ -735,6 +745,7 @@ def cpu_baseline(w, seconds, gpu_beside):
       serial assembly, LAPACK on all used cores;
     * the 2000 spheres nearest the trap centre of the benchmark workload solved as their own system:
       rows assembled in the worker processes, LAPACK solve on all used cores, outputs in the workers.
+    * the oracle's whole operator y = A x at 2000 and 10^4 spheres, rows split over the workers.
     gpu_beside: the GPU's times for the same two solves, reported next to them."""
     import numpy as np
 
@@ -784,6 +795,21 @@ def cpu_baseline(w, seconds, gpu_beside):
             out["subset2000_standalone_s"] = round(time.perf_counter() - t0, 3)
         out["subset2000_phases_s"] = {"assembly": round(t_asm, 3), "lapack_solve": round(t_lu, 3),
                                       "outputs": round(t_out, 3)}
+        # the oracle's whole operator y = A x (every row against every source) at 2000 spheres (the
+        # standalone subset) and at 10^4 (the trap box of side 200), rows split over the workers
+        out["p2_matvec"] = {}
+        for label, wm in (("n2000", ws), ("n10000", inputs.config1())):
+            xm = np.random.default_rng(1).standard_normal((wm.n, 5))
+            blocks = np.array_split(np.arange(wm.n), 8 * cores)
+            with _cpu_pool(cores) as pool:
+                # every worker builds its symbolic blocks first (each warm-up task takes seconds, so
+                # the pool hands one to every idle worker)
+                pool.map(_cpu_matvec_rows, [(wm.R[:8], xm[:8], np.arange(2), wm.eta, wm.a)] * cores, chunksize=1)
+                t0 = time.perf_counter()
+                ym = np.concatenate(pool.map(_cpu_matvec_rows, [(wm.R, xm, r, wm.eta, wm.a) for r in blocks]))
+                t_mv = time.perf_counter() - t0
+            assert ym.shape == (wm.n, 5)
+            out["p2_matvec"][label] = {"s": round(t_mv, 3), "pair_blocks_per_s": wm.n * (wm.n - 1) / t_mv}
     finally:
         if limit is not None:
             limit.restore_original_limits()

@@ -379,6 +379,7 @@ def test_size_limits_are_rejected_before_any_work(ctx):
     buf = torch.zeros(4 * 80, dtype=torch.float64, device=DEV)
     b = ctypes.c_void_p(buf.data_ptr())
     big6, big10, big12, big80 = 2**31 // 6 + 1, 2**31 // 10 + 1, 2**31 // 12 + 1, 2**31 // 80 + 1
+    big20 = 2**31 // 20 + 1
     off = (ctypes.c_int64 * 2)(0, 2**31 // 20 + 1)
     chosen = (ctypes.c_int32 * 2)()
     coef = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
@@ -398,6 +399,10 @@ def test_size_limits_are_rejected_before_any_work(ctx):
         "warmstart target": lambda: lib.mbs_warmstart_target(ctx.h, big80, *[b] * 7, None),
         "batched": lambda: lib.mbs_solve_batched(ctx.h, 1, off, *[b] * 10, None, None, None),
         "autotune batched": lambda: lib.mbs_autotune_batched(ctx.h, 1, off, b, chosen, None, None),
+        "matvec r3": lambda: lib.mbs_matvec_r3(ctx.h, big20, b, b, b, None),
+        "rhs r3": lambda: lib.mbs_rhs_r3(ctx.h, big20, b, b, b, None, b, b, b, None),
+        "outputs r3": lambda: lib.mbs_outputs_r3(ctx.h, big20, b, b, b, None, b, b, b, b, b, b, None),
+        "solve r3": lambda: lib.mbs_solve_r3(ctx.h, big20, b, b, b, b, None, b, b, None, b, b, b, b, None, None),
     }
     for name, call in calls.items():
         print(f"size limit: {name}", flush=True)

@@ -139,11 +139,13 @@ def test_rank3_solve_from_its_solution_takes_no_step_and_user_guess(ctx):
     assert torch.equal(x2, x) and torch.equal(V2, V)
 
 
-def test_rank3_operator_at_ten_thousand_spheres_sampled_rows(ctx):
-    """The benchmarked size (10^4 spheres in the trap box at the benchmark density): sampled
-    receivers against all sources."""
-    n = 10_000
-    w = _workload(n, 1001, side=200.0)
+@pytest.mark.parametrize("n,side,seed", [(10_000, 200.0, 1), (100_000, 430.0, 1000)])
+def test_rank3_operator_at_the_benchmarked_sizes_sampled_rows(ctx, n, side, seed):
+    """The two sizes the bench times the pass at (10^4 spheres in the box of side 200, and the
+    benchmark's 10^5 spheres in the box of side 430, the same centres): sampled receivers against
+    all sources."""
+    print(f"rank3 sampled rows n={n}", flush=True)
+    w = _workload(n, seed, side=side)
     x = np.random.default_rng(5).standard_normal((n, 20))
     got = _np(ctx.mbs_matvec_r3(_t(w.R), _t(x)))
     rows = np.random.default_rng(6).choice(n, 12, replace=False)
@@ -156,6 +158,12 @@ def test_rank3_errors(ctx):
     n = 8
     w = _workload(n, 950)
     R, x = _t(w.R), _t(np.ones((n, 20)))
+    R0, x0 = _t(np.zeros((0, 3))), _t(np.zeros((0, 20)))
+    for call in (lambda: ctx.mbs_matvec_r3(R0, x0), lambda: ctx.mbs_rhs_r3(R0),
+                 lambda: ctx.mbs_outputs_r3(R0, x0), lambda: ctx.mbs_solve_r3(R0)):
+        with pytest.raises(mbstokes.MbsError) as e:  # n = 0
+            call()
+        assert e.value.code == mbstokes.MBS_EINVAL
     with pytest.raises(mbstokes.MbsError):
         ctx.mbs_matvec_r3(R, x, y=x)  # output overlaps the input
     bad = w.Fe.copy()
