@@ -235,6 +235,24 @@ def bench_rank3(ctx, a):
             row["solve"] = {"ms": round(med["wall_ms"], 3), "device_ms": round(med["t_total_ms"], 3),
                             "iters": med["iters"], "fp64_matvecs": med["fp64_matvecs"],
                             "rel_resid": med["rel_resid"], "t_op64_ms": round(med["t_op64_ms"], 3)}
+            # right-preconditioned by the near-field series over the pairs within the cutoff
+            row["solve_pc"] = {}
+            for cut, order in ((8.0, 2), (12.0, 4)):
+                ctx.set_params(near_cutoff=cut, near_order=order)
+                sts = []
+                for k in range(4):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, _, _, _, st = ctx.mbs_solve_r3(d["R"], d["v1s"], d["v2s"], d["v3t"], Fe=d["Fe"], **hm)
+                    torch.cuda.synchronize()
+                    if k:
+                        st["wall_ms"] = 1e3 * (time.perf_counter() - t0)
+                        sts.append(st)
+                med = sorted(sts, key=lambda t: t["wall_ms"])[len(sts) // 2]
+                row["solve_pc"][f"{cut:g}a_order{order}"] = {
+                    "ms": round(med["wall_ms"], 3), "device_ms": round(med["t_total_ms"], 3), "iters": med["iters"],
+                    "fp64_matvecs": med["fp64_matvecs"], "rel_resid": med["rel_resid"]}
+            ctx.set_params(near_cutoff=0.0, near_order=0)
             # how far the rank <= 2 truncation is from it on the same spheres (the modes' one-body
             # closure against solving for them): relative change of V and Omega
             V2, W2, S2, _ = ctx.mbs_solve_ex(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], Fe=d["Fe"], **hm)

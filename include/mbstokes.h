@@ -317,10 +317,18 @@ int mbs_flow_ex(mbs_ctx* ctx, int64_t m, const double* X, int64_t n, const doubl
                   Sigma, X^gam, X^psi, X^d and lambda; S = Sigma + (8/3) pi eta a^3 v2s (NULL S: not
                   written).
    mbs_solve_r3:  restarted GMRES(params.restart) on A x = b to ||b - A x||_2 <= params.tol ||b||_2
-                  (binary64 operator, no preconditioner, at most params.max_iter Arnoldi steps),
-                  starting from x0 [n x 20] (NULL: zero), then the outputs. x [n x 20] (or NULL)
-                  receives the solution. params.precision, guess, near_cutoff and the learned guess
-                  do not apply; params.check_overlap does. stats: iters, fp64_matvecs, rel_resid and
+                  (binary64 operator, at most params.max_iter Arnoldi steps), starting from x0
+                  [n x 20] (NULL: zero), then the outputs. x [n x 20] (or NULL) receives the
+                  solution. With params.near_cutoff > 0 GMRES is right-preconditioned by the
+                  near-field series of mbs_precond_apply_r3 (order params.near_order); the solution
+                  is the same. params.precision, guess and the learned guess do not apply;
+                  params.check_overlap does.
+   mbs_precond_apply_r3: y [n x 20] = sum_{i <= k} (-D^{-1} B_near)^i D^{-1} x, k = params.near_order,
+                  with A = D + B (D = diag(I/gamma, I) per sphere, B the couplings of mbs_matvec_r3)
+                  and B_near B restricted to the pairs of the near-field neighbour lists (2a <= r <
+                  params.near_cutoff, at most 32 partners per sphere, the smallest indices): the
+                  Neumann expansion of the inverse of the near part of the system, an addition of
+                  this library (the paper names no solver). params.near_cutoff must be > 0. stats: iters, fp64_matvecs, rel_resid and
                   the timings (refinements and fp32_matvecs are 0). Returns MBS_ENOCONV (outputs of
                   the last iterate written) when the tolerance is not reached.
    Errors: MBS_EINVAL for n < 1, a missing required pointer, an output overlapping an input or
@@ -331,6 +339,8 @@ int mbs_rhs_r3(mbs_ctx* ctx, int64_t n, const double* R, const double* v2s, cons
 int mbs_outputs_r3(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, const double* v2s,
                    const mbs_slip_ex* ex, const double* Fe, const double* Te, const double* x, double* V,
                    double* W, double* S, void* stream);
+int mbs_precond_apply_r3(mbs_ctx* ctx, int64_t n, const double* R, const double* x, double* y,
+                         void* stream);
 int mbs_solve_r3(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, const double* v2s,
                  const double* v3t, const mbs_slip_ex* ex, const double* Fe, const double* Te,
                  const double* x0, double* V, double* W, double* S, double* x, mbs_stats* st,

@@ -1031,14 +1031,14 @@ int begin_call(mbs_ctx* c) {
 namespace {
 
 struct R3Ws {
-  double *V, *w, *r, *b, *x, *part;
+  double *V, *w, *r, *b, *x, *zt, *na, *nb, *part;
 };
 
 int r3_workspace(mbs_ctx* c, int64_t n, R3Ws* o) {
   CHK(ensure_ws(c, n));  // dot partials, Hessenberg matrix, small vectors, zeros
   const int m = c->prm.restart;
   const int64_t len = 20 * n;
-  const size_t total = (size_t)(m + 5) * len + (size_t)rank3_part_elems(n) + 64;
+  const size_t total = (size_t)(m + 8) * len + (size_t)rank3_part_elems(n) + 64;
   CHK(ensure(c, c->r3, total));
   double* q = c->r3.p;
   o->V = q;
@@ -1051,8 +1051,38 @@ int r3_workspace(mbs_ctx* c, int64_t n, R3Ws* o) {
   q += len;
   o->x = q;
   q += len;
+  o->zt = q;
+  q += len;
+  o->na = q;
+  q += len;
+  o->nb = q;
+  q += len;
   o->part = q;
   return MBS_OK;
+}
+
+// Right preconditioner of the rank <= 3 system: the near-field Neumann series of order k =
+// params.near_order over the context's neighbour lists (near_prepare),
+// y = sum_{i <= k} (-D^{-1} B_near)^i D^{-1} v, as t_1 = D^{-1}(v - B_near D^{-1} v),
+// t_j = D^{-1}(v - B_near t_{j-1}), y = t_k (k passes; y must not overlap v)
+void r3_precond(mbs_ctx* c, int64_t n, const double* R, const double* v, double* y, const R3Ws& ws,
+                hipStream_t s) {
+  const int* cntp = (const int*)c->near.p;
+  const int order = near_order(c);
+  if (order < 2) {
+    launch_rank3_near(R, v, nullptr, cntp, cntp + n, n, c->ph, y, s);
+    return;
+  }
+  double* ta = ws.na;
+  double* tb = ws.nb;
+  launch_rank3_near(R, v, nullptr, cntp, cntp + n, n, c->ph, ta, s);
+  for (int j = 2; j < order; ++j) {
+    launch_rank3_near(R, v, ta, cntp, cntp + n, n, c->ph, tb, s);
+    double* t = ta;
+    ta = tb;
+    tb = t;
+  }
+  launch_rank3_near(R, v, ta, cntp, cntp + n, n, c->ph, y, s);
 }
 
 // y = A x (one pass), timed through the context's event ring like the rank-2 operator
@@ -1073,9 +1103,10 @@ void r3_apply(mbs_ctx* c, int64_t n, const double* R, const R3Ws& ws, const doub
 }
 
 // Restarted GMRES(m) on the rank-3 system: classical Gram-Schmidt applied twice, Givens rotations on
-// the device; the residual of every restart is recomputed with the operator. *resid: final ||b - A x||.
-int r3_gmres(mbs_ctx* c, int64_t n, const double* R, const R3Ws& ws, bool x_zero, double tol_abs, int max_iters,
-             double* resid, Counters& cnt, hipStream_t s) {
+// the device; with pc, right-preconditioned by r3_precond (A M^{-1} u = b, x = M^{-1} u); the
+// residual of every restart is recomputed with the operator. *resid: final ||b - A x||.
+int r3_gmres(mbs_ctx* c, int64_t n, const double* R, const R3Ws& ws, bool x_zero, bool pc, double tol_abs,
+             int max_iters, double* resid, Counters& cnt, hipStream_t s) {
   const int m = c->prm.restart;
   const int64_t len = 20 * n;
   Small sm = small_of(c);
@@ -1095,7 +1126,12 @@ int r3_gmres(mbs_ctx* c, int64_t n, const double* R, const R3Ws& ws, bool x_zero
     int k = 0;
     bool breakdown = false;
     while (k < m && used < max_iters) {
-      r3_apply(c, n, R, ws, ws.V + (int64_t)k * len, ws.w, s, cnt);
+      if (pc) {
+        r3_precond(c, n, R, ws.V + (int64_t)k * len, ws.zt, ws, s);
+        r3_apply(c, n, R, ws, ws.zt, ws.w, s, cnt);
+      } else {
+        r3_apply(c, n, R, ws, ws.V + (int64_t)k * len, ws.w, s, cnt);
+      }
       launch_dots(ws.V, len, k + 1, ws.w, len, c->dpart.p, sm.h1, s);
       launch_axpy_multi(ws.V, len, k + 1, sm.h1, -1.0, ws.w, len, s);
       launch_dots(ws.V, len, k + 1, ws.w, len, c->dpart.p, sm.h2, s);
@@ -1111,7 +1147,14 @@ int r3_gmres(mbs_ctx* c, int64_t n, const double* R, const R3Ws& ws, bool x_zero
       if (c->h_status[0] <= tol_abs || breakdown) break;
     }
     launch_backsolve(c->H.p, m, k, sm.g, sm.y, s);
-    launch_axpy_multi(ws.V, len, k, sm.y, 1.0, ws.x, len, s);
+    if (pc) {  // x += M^{-1} (V y)
+      launch_axpby(0.0, ws.w, 0.0, ws.zt, len, s);
+      launch_axpy_multi(ws.V, len, k, sm.y, 1.0, ws.zt, len, s);
+      r3_precond(c, n, R, ws.zt, ws.w, ws, s);
+      launch_axpby(1.0, ws.w, 1.0, ws.x, len, s);
+    } else {
+      launch_axpy_multi(ws.V, len, k, sm.y, 1.0, ws.x, len, s);
+    }
     r3_apply(c, n, R, ws, ws.x, ws.r, s, cnt);
     launch_axpby(1.0, ws.b, -1.0, ws.r, len, s);
     norm2(c, ws.r, len, sm.nsq, s);
@@ -2340,6 +2383,23 @@ int mbs_outputs_r3(mbs_ctx* c, int64_t n, const double* R, const double* v1s, co
   return MBS_OK;
 }
 
+int mbs_precond_apply_r3(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, void* stream) {
+  CHK(begin_call(c));
+  CHK(r3_check_n(c, n));
+  if (!R || !x || !y) return set_err(c, MBS_EINVAL, "R, x and y are required");
+  CHK(check_aliasing(c, {{"y", y, 20 * n}}, {{"R", R, 3 * n}, {"x", x, 20 * n}}));
+  if (!(c->prm.near_cutoff > 0.0)) return set_err(c, MBS_EINVAL, "params.near_cutoff must be > 0");
+  hipStream_t s = (hipStream_t)stream;
+  R3Ws ws;
+  CHK(r3_workspace(c, n, &ws));
+  CHK(near_prepare(c, n, R, s));
+  r3_precond(c, n, R, x, y, ws, s);
+  c->near_ready = false;
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  return MBS_OK;
+}
+
 int mbs_solve_r3(mbs_ctx* c, int64_t n, const double* R, const double* v1s, const double* v2s, const double* v3t,
                  const mbs_slip_ex* ex, const double* Fe, const double* Te, const double* x0, double* V, double* W,
                  double* S, double* x, mbs_stats* st, void* stream) {
@@ -2382,10 +2442,13 @@ int mbs_solve_r3(mbs_ctx* c, int64_t n, const double* R, const double* v1s, cons
     launch_axpby(0.0, ws.b, 0.0, ws.x, len, s);
   double resid = 0.0, rel = 0.0;
   int rc = MBS_OK;
+  const bool pc = c->prm.near_cutoff > 0.0 && n > 1;
   if (bnorm == 0.0 && !x0) {
     rel = 0.0;  // x = 0 solves the system exactly
   } else {
-    CHK(r3_gmres(c, n, R, ws, x0 == nullptr, c->prm.tol * bnorm, c->prm.max_iter, &resid, cnt, s));
+    if (pc) CHK(near_prepare(c, n, R, s));
+    CHK(r3_gmres(c, n, R, ws, x0 == nullptr, pc, c->prm.tol * bnorm, c->prm.max_iter, &resid, cnt, s));
+    c->near_ready = false;
     rel = bnorm > 0.0 ? resid / bnorm : resid;
     if (!(rel <= c->prm.tol)) rc = MBS_ENOCONV;
   }

@@ -81,6 +81,11 @@ void launch_rank3(int mode, const double* R, const double* X20, const double* v1
                   const double* v3t, const double* gam, const double* psi, const double* lam, const double* Fe,
                   const double* Te, double* out, double* out2, double* out3, double* part, int64_t n,
                   const Phys& ph, hipStream_t s);
+// One term of the rank <= 3 near-field Neumann series: y = D^{-1} (v - B_near z), D = diag(I/gamma,
+// I), B_near the couplings of the listed pairs (launch_near_build); z == NULL stands for D^{-1} v.
+// v, z, y [n x 20]; y must not overlap v or z.
+void launch_rank3_near(const double* R, const double* v, const double* z, const int* cnt, const int* list,
+                       int64_t n, const Phys& ph, double* y, hipStream_t s);
 // min over pairs of |R_n - R_m|^2 -> out[0] (device), from the cell grid g of R (exact: an
 // all-pairs scan takes over when no pair is closer than one cell edge); scratch: ceil(n/256) doubles
 struct GridView;

@@ -448,6 +448,46 @@ __device__ __forceinline__ Rec3 make_rec3(int j, const double* __restrict__ R, c
 // width of the per-receiver partial sums: 20 projections (E, septlet, vortlet, potential dipole) or 6 (U, W)
 constexpr int r3_width(int mode) { return mode == kR3Out ? 6 : 20; }
 
+// The receiver's 20 projections from the summed Taylor data: E (5-basis), then V^(3)/a^2 split into
+// its septlet (7-basis), vortlet (5-basis) and potential-dipole (3) parts
+__device__ __forceinline__ void r3_project(const J2 A[3], double* o) {
+  // E = sym grad F^1 u, 5-basis
+  o[0] = kRs2 * (A[0].cx - A[1].cy);
+  o[1] = kRs6 * (2.0 * A[2].cz - A[0].cx - A[1].cy);
+  o[2] = kRs2 * (A[0].cy + A[1].cx);
+  o[3] = kRs2 * (A[0].cz + A[2].cx);
+  o[4] = kRs2 * (A[1].cz + A[2].cy);
+  // S_ijk = part of d_j d_k F^2 u_i symmetric traceless in (j, k)
+  double S[3][3][3];
+  for (int c = 0; c < 3; ++c) {
+    double H[3][3];
+    H[0][0] = 2.0 * A[c].cxx;
+    H[1][1] = 2.0 * A[c].cyy;
+    H[2][2] = 2.0 * A[c].czz;
+    H[0][1] = H[1][0] = A[c].cxy;
+    H[0][2] = H[2][0] = A[c].cxz;
+    H[1][2] = H[2][1] = A[c].cyz;
+    const double tr = (H[0][0] + H[1][1] + H[2][2]) / 3.0;
+    for (int j = 0; j < 3; ++j)
+      for (int kk = 0; kk < 3; ++kk) S[c][j][kk] = H[j][kk] - (j == kk ? tr : 0.0);
+  }
+  to7(S, o + 5);
+  // vortlet: C_lk = -eps_lij S_ijk, symmetric part in the 5-basis
+  double C[3][3];
+  for (int kk = 0; kk < 3; ++kk) {
+    C[0][kk] = S[2][1][kk] - S[1][2][kk];
+    C[1][kk] = S[0][2][kk] - S[2][0][kk];
+    C[2][kk] = S[1][0][kk] - S[0][1][kk];
+  }
+  o[12] = kRs2 * (C[0][0] - C[1][1]);
+  o[13] = kRs6 * (2.0 * C[2][2] - C[0][0] - C[1][1]);
+  o[14] = kRs2 * (C[0][1] + C[1][0]);
+  o[15] = kRs2 * (C[0][2] + C[2][0]);
+  o[16] = kRs2 * (C[1][2] + C[2][1]);
+  // potential dipole: S_iik
+  for (int kk = 0; kk < 3; ++kk) o[17 + kk] = S[0][0][kk] + S[1][1][kk] + S[2][2][kk];
+}
+
 // Sum over the sources j0 <= j < j1 of group(s) GRP at receiver (xi, yi, zi) (index ii: skipped)
 template <int GRP>
 __device__ __forceinline__ void r3_sweep(Rec3* tile, int ii, double xi, double yi, double zi, int j0, int j1,
@@ -499,41 +539,7 @@ __global__ void __launch_bounds__(kR3Blk)
     o[5] = 0.5 * (A[1].cx - A[0].cy);
     return;
   }
-  // E = sym grad F^1 u, 5-basis
-  o[0] = kRs2 * (A[0].cx - A[1].cy);
-  o[1] = kRs6 * (2.0 * A[2].cz - A[0].cx - A[1].cy);
-  o[2] = kRs2 * (A[0].cy + A[1].cx);
-  o[3] = kRs2 * (A[0].cz + A[2].cx);
-  o[4] = kRs2 * (A[1].cz + A[2].cy);
-  // S_ijk = part of d_j d_k F^2 u_i symmetric traceless in (j, k)
-  double S[3][3][3];
-  for (int c = 0; c < 3; ++c) {
-    double H[3][3];
-    H[0][0] = 2.0 * A[c].cxx;
-    H[1][1] = 2.0 * A[c].cyy;
-    H[2][2] = 2.0 * A[c].czz;
-    H[0][1] = H[1][0] = A[c].cxy;
-    H[0][2] = H[2][0] = A[c].cxz;
-    H[1][2] = H[2][1] = A[c].cyz;
-    const double tr = (H[0][0] + H[1][1] + H[2][2]) / 3.0;
-    for (int j = 0; j < 3; ++j)
-      for (int kk = 0; kk < 3; ++kk) S[c][j][kk] = H[j][kk] - (j == kk ? tr : 0.0);
-  }
-  to7(S, o + 5);
-  // vortlet: C_lk = -eps_lij S_ijk, symmetric part in the 5-basis
-  double C[3][3];
-  for (int kk = 0; kk < 3; ++kk) {
-    C[0][kk] = S[2][1][kk] - S[1][2][kk];
-    C[1][kk] = S[0][2][kk] - S[2][0][kk];
-    C[2][kk] = S[1][0][kk] - S[0][1][kk];
-  }
-  o[12] = kRs2 * (C[0][0] - C[1][1]);
-  o[13] = kRs6 * (2.0 * C[2][2] - C[0][0] - C[1][1]);
-  o[14] = kRs2 * (C[0][1] + C[1][0]);
-  o[15] = kRs2 * (C[0][2] + C[2][0]);
-  o[16] = kRs2 * (C[1][2] + C[2][1]);
-  // potential dipole: S_iik
-  for (int kk = 0; kk < 3; ++kk) o[17 + kk] = S[0][0][kk] + S[1][1][kk] + S[2][2][kk];
+  r3_project(A, o);
 }
 
 // y = [x_Sigma/gamma - E, x_alpha + P_alpha] (operator), b = [E - c s, v_alpha - P_alpha] (right-hand
@@ -587,6 +593,35 @@ __global__ void k_rank3_finish(const double* __restrict__ part, int split, int n
   }
 }
 
+// One term of the near-field Neumann series of the rank <= 3 system A = D + B (D = diag(I/gamma, I)
+// per sphere, B the couplings): y = D^{-1} (v - B_near z) over the pairs on the neighbour lists,
+// z = Z, or D^{-1} v when Z is NULL. B's stresslet rows are -E and its mode rows +P^alpha.
+constexpr int kR3NearBlk = 64;
+__global__ void __launch_bounds__(kR3NearBlk)
+    k_rank3_near(const double* __restrict__ R, const double* __restrict__ V, const double* __restrict__ Z,
+                 const int* __restrict__ cnt, const int* __restrict__ list, int n, double P, double a2, double a5,
+                 double a7, double gamma, double* __restrict__ Y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const R3C k{a2, a5, a7, LW{a2 / 6.0, a2 / 10.0, a2 / 14.0}};
+  const double xi = R[3 * (int64_t)i], yi = R[3 * (int64_t)i + 1], zi = R[3 * (int64_t)i + 2];
+  const double* src = Z ? Z : V;
+  const double ps = Z ? P : P * gamma;  // D^{-1} v scales the stresslet part by gamma
+  J2 A[3];
+  const int c = cnt[i];
+  for (int q = 0; q < c; ++q) {
+    const int j = list[(int64_t)i * kNearCap + q];
+    const Rec3 s = make_rec3<kGSig | kGQuad>(j, R, src, nullptr, nullptr, nullptr, ps, 0.1 * a5);
+    r3_pair<kGSig | kGQuad>(s, xi - s.x, yi - s.y, zi - s.z, k, A);
+  }
+  double o[20];
+  r3_project(A, o);
+  const double* v = V + 20 * (int64_t)i;
+  double* y = Y + 20 * (int64_t)i;
+  for (int q = 0; q < 5; ++q) y[q] = gamma * (v[q] + o[q]);
+  for (int q = 5; q < 20; ++q) y[q] = v[q] - o[q];
+}
+
 inline unsigned nblk3(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
 
 }  // namespace
@@ -630,6 +665,14 @@ void launch_rank3(int mode, const double* R, const double* X20, const double* v1
     launch_rank3_mode<kR3Rhs>(R, X20, v1s, v2s, v3t, gam, psi, lam, Fe, Te, out, out2, out3, part, n, ph, s);
   else
     launch_rank3_mode<kR3Out>(R, X20, v1s, v2s, v3t, gam, psi, lam, Fe, Te, out, out2, out3, part, n, ph, s);
+}
+
+void launch_rank3_near(const double* R, const double* v, const double* z, const int* cnt, const int* list,
+                       int64_t n, const Phys& ph, double* y, hipStream_t s) {
+  if (n <= 0) return;
+  const double a2 = ph.a2, a5 = a2 * a2 * ph.a, a7 = a5 * a2;
+  hipLaunchKernelGGL(k_rank3_near, dim3(nblk3(n, kR3NearBlk)), dim3(kR3NearBlk), 0, s, R, v, z, cnt, list, (int)n,
+                     ph.P, a2, a5, a7, ph.gamma, y);
 }
 
 }  // namespace mbs

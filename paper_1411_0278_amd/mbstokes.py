@@ -27,7 +27,7 @@ EXPORTS = ("mbs_default_params", "mbs_create", "mbs_destroy", "mbs_set_params", 
            "mbs_warmstart_load", "mbs_warmstart_target", "mbs_initial_guess", "mbs_precond_apply",
            "mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex", "mbs_matvec_static",
            "mbs_warmstart_features", "mbs_features_ex", "mbs_matvec_r3", "mbs_rhs_r3", "mbs_outputs_r3",
-           "mbs_solve_r3")
+           "mbs_solve_r3", "mbs_precond_apply_r3")
 R3_DIM = 20  # unknowns per sphere at traction ranks <= 3: Sigma (5), X^gam (7), X^psi (5), X^d (3)
 MLP_NPARAM, MLP_NFEAT = 27525, 80
 MLP_NPARAM_RHS, MLP_NFEAT_RHS = 37765, 160
@@ -142,8 +142,9 @@ def load(path: str = LIB_PATH):
     lib.mbs_rhs_r3.argtypes = [P, I64, P, P, P, EX, P, P, P, VP]
     lib.mbs_outputs_r3.argtypes = [P, I64, P, P, P, EX] + [P] * 6 + [VP]
     lib.mbs_solve_r3.argtypes = [P, I64] + [P] * 4 + [EX] + [P] * 7 + [ctypes.POINTER(Stats), VP]
+    lib.mbs_precond_apply_r3.argtypes = [P, I64, P, P, P, VP]
     for name in ("mbs_solve_ex", "mbs_rhs_ex", "mbs_outputs_ex", "mbs_flow_ex", "mbs_matvec_r3", "mbs_rhs_r3",
-                 "mbs_outputs_r3", "mbs_solve_r3"):
+                 "mbs_outputs_r3", "mbs_solve_r3", "mbs_precond_apply_r3"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mbs_warmstart_target", "mbs_initial_guess", "mbs_features", "mbs_features_ex",
                  "mbs_warmstart_features", "mbs_warmstart_init", "mbs_warmstart_set", "mbs_warmstart_get",
@@ -378,6 +379,14 @@ class Context:
                                             _ptr(Te, n, 3, "Te"), _ptr(x, n, R3_DIM, "x"), _ptr(V, n, 3, "V"),
                                             _ptr(W, n, 3, "W"), _ptr(S, n, 5, "S"), _stream()))
         return V, W, S
+
+    def mbs_precond_apply_r3(self, R, x, y=None):
+        import torch
+        n = R.shape[0]
+        y = torch.empty((n, R3_DIM), dtype=torch.float64, device=R.device) if y is None else y
+        self._check(self.lib.mbs_precond_apply_r3(self.h, n, _ptr(R, n, 3, "R"), _ptr(x, n, R3_DIM, "x"),
+                                                  _ptr(y, n, R3_DIM, "y"), _stream()))
+        return y
 
     def mbs_solve_r3(self, R, v1s=None, v2s=None, v3t=None, gam=None, psi=None, lam=None, Fe=None, Te=None,
                      x0=None, V=None, W=None, S=None, x=None, allow_noconv=False):

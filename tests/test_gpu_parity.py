@@ -403,6 +403,7 @@ def test_size_limits_are_rejected_before_any_work(ctx):
         "rhs r3": lambda: lib.mbs_rhs_r3(ctx.h, big20, b, b, b, None, b, b, b, None),
         "outputs r3": lambda: lib.mbs_outputs_r3(ctx.h, big20, b, b, b, None, b, b, b, b, b, b, None),
         "solve r3": lambda: lib.mbs_solve_r3(ctx.h, big20, b, b, b, b, None, b, b, None, b, b, b, b, None, None),
+        "precond r3": lambda: lib.mbs_precond_apply_r3(ctx.h, big20, b, b, b, None),
     }
     for name, call in calls.items():
         print(f"size limit: {name}", flush=True)
