@@ -278,11 +278,13 @@ constexpr int kR3Blk = 128;  // receivers per workgroup
 enum { kR3Op = 0, kR3Rhs = 1, kR3Out = 2 };
 // Source groups, each swept by its own workgroups (grid.y = groups x source chunks) so that each
 // sweep's registers are those of its own sources: the fixed sources (force, torque, spinlet slip),
-// the flow stresslet with X^d, and X^g with X^p.
-enum { kGFix = 1, kGSig = 2, kGQuad = 4 };
-constexpr int r3_ngroups(int mode) { return mode == kR3Op ? 2 : (mode == kR3Rhs ? 1 : 3); }
+// the flow stresslet with X^d, X^g, X^p. The operator sweeps the last three separately (then every
+// sweep fits two waves per SIMD), the outputs the fixed sources, the stresslet with X^d, and X^g
+// with X^p.
+enum { kGFix = 1, kGSig = 2, kGSept = 4, kGVort = 8, kGQuad = kGSept | kGVort };
+constexpr int r3_ngroups(int mode) { return mode == kR3Op ? 3 : (mode == kR3Rhs ? 1 : 3); }
 constexpr int r3_group(int mode, int g) {
-  return mode == kR3Op ? (g == 0 ? kGSig : kGQuad) : (mode == kR3Rhs ? kGFix : (g == 0 ? kGFix : (g == 1 ? kGSig : kGQuad)));
+  return mode == kR3Op ? (g == 0 ? kGSig : (g == 1 ? kGSept : kGVort)) : (mode == kR3Rhs ? kGFix : (g == 0 ? kGFix : (g == 1 ? kGSig : kGQuad)));
 }
 
 struct R3C {  // per-problem constants
@@ -367,7 +369,7 @@ __device__ __forceinline__ void r3_pair(const Rec3& s, double x, double y, doubl
       jaxpy(-s.d[i], R3, A[i]);
     }
   }
-  if (GRP & kGQuad) {  // X^g and X^p
+  if (GRP & kGSept) {  // X^g
     const J2 R9 = jradial(9.0, p9, p11, p13, x, y, z);
     J2 g[3], Q;
     quad_jets(sym3_of(s.g), x, y, z, g, Q);
@@ -380,7 +382,15 @@ __device__ __forceinline__ void r3_pair(const Rec3& s, double x, double y, doubl
     const J2 Qb = jmul(Q, cb);
     const J2 Q9 = jmul(Q, R9);
     const double lg = 7.0 / 24.0 * k.a5;
-    // X^p: -(a^5/3) (x cross (X^p.x))/r^5
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      jaxpy(1.0, jmul(g[i], ca), A[i]);
+      jaxpy(1.0, jmul(Qb, X[i]), A[i]);
+      jaxpyL(45.0 * lg, jmul(g[i], R7), k.w, A[i]);
+      jaxpyL(-105.0 * lg, jmul(Q9, X[i]), k.w, A[i]);
+    }
+  }
+  if (GRP & kGVort) {  // X^p: -(a^5/3) (x cross (X^p.x))/r^5
     const double* Pp = s.p;
     const J2 pw[3] = {jlin(fma(Pp[0], x, fma(Pp[2], y, Pp[3] * z)), Pp[0], Pp[2], Pp[3]),
                       jlin(fma(Pp[2], x, fma(Pp[1], y, Pp[4] * z)), Pp[2], Pp[1], Pp[4]),
@@ -394,13 +404,7 @@ __device__ __forceinline__ void r3_pair(const Rec3& s, double x, double y, doubl
     jaxpy(-1.0, jmul(X[1], pw[0]), xw[2]);
     const double cp = -k.a5 / 3.0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      jaxpy(1.0, jmul(g[i], ca), A[i]);
-      jaxpy(1.0, jmul(Qb, X[i]), A[i]);
-      jaxpyL(45.0 * lg, jmul(g[i], R7), k.w, A[i]);
-      jaxpyL(-105.0 * lg, jmul(Q9, X[i]), k.w, A[i]);
-      jaxpy(cp, jmul(xw[i], R5), A[i]);
-    }
+    for (int i = 0; i < 3; ++i) jaxpy(cp, jmul(xw[i], R5), A[i]);
   }
 }
 
@@ -431,8 +435,8 @@ __device__ __forceinline__ Rec3 make_rec3(int j, const double* __restrict__ R, c
     r.s[5] = -P * (sxx + syy);
     for (int c = 0; c < 3; ++c) r.d[c] = a5_10 * x[17 + c];
   }
-  if (GRP & kGQuad) {
-    from7(x + 5, r.g);
+  if (GRP & kGSept) from7(x + 5, r.g);
+  if (GRP & kGVort) {
     double pxx, pyy, pxy, pxz, pyz;
     basis_to_cart(x + 12, pxx, pyy, pxy, pxz, pyz);
     r.p[0] = pxx;
@@ -509,9 +513,10 @@ __device__ __forceinline__ void r3_sweep(Rec3* tile, int ii, double xi, double y
 }
 
 // grid: (receiver blocks, groups x chunks); workgroup y sweeps source chunk y % split of group
-// y / split and writes partial slice y
+// y / split and writes partial slice y. Two waves per SIMD: the largest sweep (X^g) then keeps its
+// Taylor data in 256 registers with a few bytes spilled, faster than one wave with more registers.
 template <int MODE>
-__global__ void __launch_bounds__(kR3Blk)
+__global__ void __launch_bounds__(kR3Blk, 2)
     k_rank3(const double* __restrict__ R, const double* __restrict__ X20, const double* __restrict__ Fe,
             const double* __restrict__ Te, const double* __restrict__ lam, int n, int chunk, int split, double P,
             double a2, double a5, double a7, double* __restrict__ part) {
@@ -633,8 +638,8 @@ int rank3_split(int64_t n) {
   return (int)s;
 }
 
-// the largest of groups x split x width over the three modes (the operator: 2 x split x 20)
-int64_t rank3_part_elems(int64_t n) { return (int64_t)rank3_split(n) * 40 * n; }
+// the largest of groups x split x width over the three modes (the operator: 3 x split x 20)
+int64_t rank3_part_elems(int64_t n) { return (int64_t)rank3_split(n) * 60 * n; }
 
 namespace {
 template <int M>
