@@ -23,6 +23,10 @@
  *     with V^a_n = -V^(1s)_n, and the traction stresslet S_n = Sigma_n + (8/3) pi eta a^3 s_n.
  *   - The _ex entry points add the septlet, vortlet and spinlet slip modes of the
  *     minimal truncation (section IV) as further fixed sources in E, U and W.
+ *   - The _r3 entry points solve the traction rank <= 3 system of the minimal
+ *     truncation instead: the septlet, vortlet and potential-dipole traction modes
+ *     are unknowns beside the stresslet, with the quadratic (l = 2) surface
+ *     conditions as their rows (20 unknowns per sphere; declared below).
  *
  * Conventions for every entry point below:
  *   - Arrays are caller-owned, contiguous, row-major, particle-major, IEEE
