@@ -322,11 +322,12 @@ int mbs_flow_ex(mbs_ctx* ctx, int64_t m, const double* X, int64_t n, const doubl
                   written).
    mbs_solve_r3:  restarted GMRES(params.restart) on A x = b to ||b - A x||_2 <= params.tol ||b||_2
                   (binary64 operator, at most params.max_iter Arnoldi steps), starting from x0
-                  [n x 20] (NULL: zero), then the outputs. x [n x 20] (or NULL) receives the
-                  solution. With params.near_cutoff > 0 GMRES is right-preconditioned by the
-                  near-field series of mbs_precond_apply_r3 (order params.near_order); the solution
-                  is the same. params.precision, guess and the learned guess do not apply;
-                  params.check_overlap does.
+                  [n x 20], or when x0 is NULL from the one-body guess D^{-1} b (params.guess =
+                  MBS_GUESS_DIAG; D as below) or zero (any other guess), then the outputs. x [n x 20]
+                  (or NULL) receives the solution. With params.near_cutoff > 0 GMRES is
+                  right-preconditioned by the near-field series of mbs_precond_apply_r3 (order
+                  params.near_order); the solution is the same. params.precision does not apply
+                  (binary64 throughout); params.check_overlap does.
    mbs_precond_apply_r3: y [n x 20] = sum_{i <= k} (-D^{-1} B_near)^i D^{-1} x, k = params.near_order,
                   with A = D + B (D = diag(I/gamma, I) per sphere, B the couplings of mbs_matvec_r3)
                   and B_near B restricted to the pairs of the near-field neighbour lists (2a <= r <

@@ -2436,18 +2436,23 @@ int mbs_solve_r3(mbs_ctx* c, int64_t n, const double* R, const double* v1s, cons
   norm2(c, ws.b, len, sm.bnorm2, s);
   CHK(read_status(c, sm.bnorm2, 1, s));
   const double bnorm = sqrt(c->h_status[0]);
+  // start: x0 if given, else the one-body guess D^{-1} b (params.guess = MBS_GUESS_DIAG) or zero
+  const bool diag = !x0 && c->prm.guess == MBS_GUESS_DIAG;
   if (x0)
     launch_copy(x0, ws.x, len, s);
+  else if (diag)
+    launch_rank3_diag(ws.b, n, c->ph.gamma, ws.x, s);
   else
     launch_axpby(0.0, ws.b, 0.0, ws.x, len, s);
+  const bool x_zero = !x0 && !diag;
   double resid = 0.0, rel = 0.0;
   int rc = MBS_OK;
   const bool pc = c->prm.near_cutoff > 0.0 && n > 1;
-  if (bnorm == 0.0 && !x0) {
+  if (bnorm == 0.0 && x_zero) {
     rel = 0.0;  // x = 0 solves the system exactly
   } else {
     if (pc) CHK(near_prepare(c, n, R, s));
-    CHK(r3_gmres(c, n, R, ws, x0 == nullptr, pc, c->prm.tol * bnorm, c->prm.max_iter, &resid, cnt, s));
+    CHK(r3_gmres(c, n, R, ws, x_zero, pc, c->prm.tol * bnorm, c->prm.max_iter, &resid, cnt, s));
     c->near_ready = false;
     rel = bnorm > 0.0 ? resid / bnorm : resid;
     if (!(rel <= c->prm.tol)) rc = MBS_ENOCONV;

@@ -81,6 +81,8 @@ void launch_rank3(int mode, const double* R, const double* X20, const double* v1
                   const double* v3t, const double* gam, const double* psi, const double* lam, const double* Fe,
                   const double* Te, double* out, double* out2, double* out3, double* part, int64_t n,
                   const Phys& ph, hipStream_t s);
+// x [n x 20] = D^{-1} b, D = diag(I/gamma, I) per sphere (the one-body guess of the rank <= 3 system)
+void launch_rank3_diag(const double* b, int64_t n, double gamma, double* x, hipStream_t s);
 // One term of the rank <= 3 near-field Neumann series: y = D^{-1} (v - B_near z), D = diag(I/gamma,
 // I), B_near the couplings of the listed pairs (launch_near_build); z == NULL stands for D^{-1} v.
 // v, z, y [n x 20]; y must not overlap v or z.

@@ -827,6 +827,20 @@ void launch_min_dist2(const GridView& g, const double* R, int64_t n, double* out
   hipLaunchKernelGGL(k_min_finish, dim3(1), dim3(256), 0, s, scratch, (int)nb, out, g.hdr);
 }
 
+namespace {
+// x = D^{-1} b for the rank <= 3 unknowns (20 per sphere): the stresslet rows scaled by gamma
+__global__ void k_rank3_diag(const double* __restrict__ b, int64_t len, double gamma, double* __restrict__ x) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  x[k] = (k % 20) < 5 ? gamma * b[k] : b[k];
+}
+}  // namespace
+
+void launch_rank3_diag(const double* b, int64_t n, double gamma, double* x, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_rank3_diag, dim3(nblk(20 * n, 256)), dim3(256), 0, s, b, 20 * n, gamma, x);
+}
+
 void launch_count_nonfinite(const double* a, int64_t len, int* cnt, hipStream_t s) {
   if (len <= 0) return;
   const unsigned nb = std::min<unsigned>(nblk(len, 256), 1024u);

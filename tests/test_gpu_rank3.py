@@ -197,6 +197,28 @@ def test_rank3_preconditioned_solve_matches_oracle(ctx, order):
     assert st["iters"] < st0["iters"]
 
 
+@pytest.mark.parametrize("n", [1, 97])
+def test_rank3_one_body_guess(ctx, n):
+    """params.guess = MBS_GUESS_DIAG starts from D^{-1} b: for a lone sphere that is the solution
+    (no Arnoldi step); otherwise the same answer as from zero."""
+    w = _workload(n, 1300 + n)
+    sol = galerkin.solve_rank3(w, _prm(w))
+    args = [_t(a) for a in (w.R, w.v1s, w.v2s, w.v3t, w.gam, w.psi, w.lam, w.Fe, w.Te)]
+    ctx.set_params(tol=1e-12)
+    try:
+        _, _, _, x0, st0 = ctx.mbs_solve_r3(*args)
+        ctx.set_params(guess=mbstokes.MBS_GUESS_DIAG)
+        V, W, S, x, st = ctx.mbs_solve_r3(*args)
+    finally:
+        ctx.set_params(tol=1e-10, guess=mbstokes.MBS_GUESS_ZERO)
+    xs = np.concatenate([sol["Sigma"], sol["gam7"], sol["psi"], sol["d"]], axis=1)
+    assert _maxrel(x, xs) < 1e-9 and _maxrel(V, sol["V"]) < 1e-9 and _maxrel(W, sol["W"]) < 1e-9
+    if n == 1:
+        assert st["iters"] == 0 and st["rel_resid"] < 1e-15
+    else:
+        assert st["iters"] <= st0["iters"]
+
+
 def test_rank3_solve_from_its_solution_takes_no_step_and_user_guess(ctx):
     n = 97
     w = _workload(n, 900)
