@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import sympy as sp
 
-from oracle import basis, galerkin, greens, krylov, stepper
+from oracle import basis, galerkin, greens, krylov, plane, stepper
 from paper_1411_0278_amd import inputs
 from tests import sphere_quad
 
@@ -711,3 +711,82 @@ def test_lone_sphere_flow_amplitudes_match_the_single_layer_constants():
     assert np.allclose(amp, amp[0], rtol=1e-9, atol=0)
     Q_per_gamma = 8 * np.pi * ETA * amp[0] / A ** 2        # |Q| per unit gamma
     assert abs(Q_per_gamma - C30 / A ** 2) < 1e-10 * C30 / A ** 2
+
+
+# ---------------------------------------------------------------- a free-slip plane (other geometry)
+def _plane_flow_of(kind, c, y, X, z_w):
+    args = {"Fe": None, "Te": None, "Sigma": None, "v3t": None}
+    args[{"F": "Fe", "T": "Te", "S": "Sigma", "D": "v3t"}[kind]] = np.asarray(c)[None]
+    return plane.flow_field(X, y, args["Fe"], args["Te"], args["Sigma"], args["v3t"], PRM, z_w)
+
+
+def _plane_violation(kind, c, y, X, z_w, dz=1e-4):
+    """Largest normal velocity and normal derivative of the tangential velocity on the plane,
+    relative to the flow's size there."""
+    e = np.array([0.0, 0.0, 1.0])
+    u0 = _plane_flow_of(kind, c, y, X, z_w)
+    dudz = (_plane_flow_of(kind, c, y, X + dz * e, z_w) - _plane_flow_of(kind, c, y, X - dz * e, z_w)) / (2 * dz)
+    scale = np.abs(u0).max()
+    return np.abs(u0[:, 2]).max() / scale, np.abs(dudz[:, :2]).max() / scale
+
+
+def test_free_slip_plane_images_meet_the_plane_conditions(monkeypatch):
+    """Half space bounded by a stress-free plane (the paper's remark on other geometries: the
+    Green's function of that geometry): each source kind with its mirror image has zero normal
+    velocity and zero normal derivative of the tangential velocity on the plane. A wrong
+    transformation law of an image (a torque reflected as a polar vector, a stresslet whose xz, yz
+    parts keep their sign) breaks them."""
+    rng = np.random.default_rng(21)
+    z_w = -0.7
+    y = np.array([[0.3, -0.4, z_w + 1.9 * A]])
+    X = np.column_stack([rng.uniform(-4, 4, 30), rng.uniform(-4, 4, 30), np.full(30, z_w)])
+    for kind, dim in (("F", 3), ("T", 3), ("S", 5), ("D", 3)):
+        c = rng.standard_normal(dim)
+        normal, shear = _plane_violation(kind, c, y, X, z_w)
+        assert normal < 1e-12 and shear < 1e-6, kind
+    monkeypatch.setitem(plane.IMAGE_MAP, "T", plane.M3)
+    assert max(_plane_violation("T", rng.standard_normal(3), y, X, z_w)) > 1e-2
+    monkeypatch.setitem(plane.IMAGE_MAP, "S", np.eye(5))
+    assert max(_plane_violation("S", rng.standard_normal(5), y, X, z_w)) > 1e-2
+
+
+def _lone_near_plane(h, z_w, F=None, T=None):
+    R = np.array([[0.2, 0.1, z_w + h]])
+    z3, z5 = np.zeros((1, 3)), np.zeros((1, 5))
+    return plane.solve(inputs.Workload(R, z3, z3, z5, None, F, T, ETA, A), z_w, PRM)
+
+
+def test_lone_sphere_near_a_free_slip_plane_moves_as_its_images_predict():
+    """A lone sphere at height h: under a force parallel / normal to the plane it moves with
+    mu0 (1 + (3/8)(a/h) + (1/16)(a/h)^3) / mu0 (1 - (3/4)(a/h) + (1/8)(a/h)^3) (the image Stokeslet
+    and its two finite-size terms), under a torque parallel / normal to it it turns with
+    (1 + (1/16)(a/h)^3) / (1 + (1/8)(a/h)^3) (the image rotlet) times the free rate; what remains
+    falls off faster than (a/h)^3 (the normal translation as (a/h)^4)."""
+    z_w = -0.4
+    mu0, om0 = 1 / (6 * np.pi * ETA * A), 1 / (8 * np.pi * ETA * A ** 3)
+    ex, ez = np.array([[1.0, 0.0, 0.0]]), np.array([[0.0, 0.0, 1.0]])
+    rem = {}
+    for ha in (8, 16, 32):
+        e = 1.0 / ha
+        h = ha * A
+        rem[ha] = (
+            _lone_near_plane(h, z_w, F=ex)["V"][0, 0] / mu0 - (1 + 3 / 8 * e + e ** 3 / 16),
+            _lone_near_plane(h, z_w, F=ez)["V"][0, 2] / mu0 - (1 - 3 / 4 * e + e ** 3 / 8),
+            _lone_near_plane(h, z_w, T=ex)["W"][0, 0] / om0 - (1 + e ** 3 / 16),
+            _lone_near_plane(h, z_w, T=ez)["W"][0, 2] / om0 - (1 + e ** 3 / 8))
+        assert max(abs(r) for r in rem[ha]) < 0.05 * e ** 3
+    assert 10.0 < rem[16][1] / rem[32][1] < 24.0  # the normal translation's remainder is O((a/h)^4)
+
+
+def test_free_slip_plane_system_is_the_free_one_far_from_the_plane_and_symmetric():
+    """The half-space system tends to the free-space one as the plane recedes (image blocks decay
+    as h^-3), and stays symmetric positive definite (the images keep reciprocity)."""
+    w = inputs.trap_workload(12, 10.0, 3)
+    A0 = galerkin.system_matrix(w.R, PRM)
+    for z_w, bar in ((w.R[:, 2].min() - 3 * A, 1e-1), (w.R[:, 2].min() - 300 * A, 1e-5)):
+        Ap = plane.system_matrix(w.R, PRM, z_w)
+        assert np.abs(Ap - Ap.T).max() < 1e-14 * np.abs(Ap).max()
+        assert np.linalg.eigvalsh(Ap).min() > 0
+        assert np.abs(Ap - A0).max() / np.abs(A0).max() < bar
+    with pytest.raises(ValueError):
+        plane.system_matrix(w.R, PRM, w.R[:, 2].min() - 0.5 * A)
