@@ -133,6 +133,21 @@ typedef struct mbs_params {
                             them stay small (N = 10^6: binary32 operator error 8.6e-7 -> 1.1e-7, one
                             binary32 iteration fewer); otherwise only the order of the sums, and so
                             the rounding, changes */
+  int32_t plane;         /* nonzero: the fluid fills the half space z > plane_z above a flat plane on
+                            which it slips freely (zero normal velocity and tangential stress: a flat
+                            free surface). Its Green's function is the free-space one plus its mirror
+                            image, so every sphere also acts through its mirror image in the plane
+                            (on every sphere, itself included), with F* = M F, T* = -M T,
+                            Sigma* = M Sigma M, d* = M d, M = diag(1, 1, -1) (the paper's remark that
+                            other geometries follow from their Green's function, Discussion). Every
+                            sphere must lie at least a above the plane (MBS_EINVAL otherwise). Applies
+                            to mbs_solve(_ex), mbs_matvec, mbs_rhs(_ex), mbs_outputs(_ex), mbs_flow(_ex)
+                            (field points must lie in the fluid too); the higher slip modes, the
+                            stepper, the batched solver, the rank <= 3 entry points and
+                            mbs_matvec_static refuse it (MBS_EUNSUPPORTED). The near-field
+                            preconditioner keeps the free-space pairs. 0 = unbounded fluid (default) */
+  int32_t reserved0;
+  double  plane_z;       /* height of the plane (plane != 0) */
 } mbs_params;
 
 typedef struct mbs_stats {
@@ -158,7 +173,7 @@ typedef struct mbs_ctx mbs_ctx;
 
 /* Fill *prm with the defaults: eta = 1/(6 pi), a = 1, tol = 1e-10, c = 1, inner_tol = 1e-5,
    lmax = 2, max_iter = 300, restart = 30, MBS_FP64, MBS_GUESS_ZERO, no overlap check, tile 0,
-   graph 1, near_order 2. */
+   graph 1, near_order 2, spatial_order 0, no plane. */
 void mbs_default_params(mbs_params* prm);
 
 /* Create a context on HIP device `device`. *ctx receives the handle (NULL on failure).

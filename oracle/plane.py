@@ -112,3 +112,10 @@ def flow_field(X, R, Fe, Te, Sigma, v3t, prm: galerkin.Params, z_w):
         for m in range(Rs.shape[0]):
             u += greens.flow(kind, X - Rs[m], prm.a, prm.eta) @ (IMAGE_MAP[kind] @ vals[m])
     return u
+
+
+def matvec_rows(R, x, rows, prm: galerkin.Params, z_w):
+    """(A x) of the half-space system restricted to the given spheres, without forming A."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1, 5)
+    img = image_matrix(R, "E", "S", prm, z_w, rows) @ np.ravel(x)
+    return galerkin.matvec_rows(R, x, rows, prm) - img.reshape(-1, 5)

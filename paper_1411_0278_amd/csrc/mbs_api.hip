@@ -176,6 +176,8 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
     return set_err(c, MBS_EINVAL, "near_order must be 0 (= 2), 2, 4, 6 or 8");
   if (p->spatial_order < -1 || p->spatial_order > 1)
     return set_err(c, MBS_EINVAL, "spatial_order must be -1, 0 or 1");
+  if (p->plane != 0 && p->plane != 1) return set_err(c, MBS_EINVAL, "plane must be 0 or 1");
+  if (p->plane && !isfinite(p->plane_z)) return set_err(c, MBS_EINVAL, "plane_z must be finite");
   return MBS_OK;
 }
 
@@ -198,7 +200,7 @@ int ensure_ws(mbs_ctx* c, int64_t n) {
   CHK(ensure(c, c->b, len));
   CHK(ensure(c, c->xs, len));
   CHK(ensure(c, c->dlt, len));
-  const int64_t pe = part_elems_max(n);
+  const int64_t pe = std::max<int64_t>(part_elems_max(n), c->prm.plane ? image_part_elems(n, n) : 0);
   CHK(ensure(c, c->part, (size_t)pe));
   CHK(ensure(c, c->srcbuf, (size_t)8 * n));
   CHK(ensure(c, c->orig, 4));
@@ -287,6 +289,10 @@ void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x,
     launch_p2(true, R, x, y, c->part.p, c->srcbuf.p, c->orig.p, n, c->ph, c->tile32, s);
     cnt.f32++;
   }
+  if (c->prm.plane) {  // the images' part of the operator (binary64 in either precision)
+    launch_image_op(R, x, y, c->part.p, n, c->ph, c->prm.plane_z, s);
+    cnt.pairs += (double)n * (double)n;
+  }
   if (timed) (void)hipEventRecord(c->opev[2 * slot + 1], s);
   cnt.pairs += (double)n * (double)(n - 1);
 }
@@ -297,6 +303,11 @@ void apply_op_out(mbs_ctx* c, int64_t n, const double* R, const double* x, doubl
                   hipStream_t s, Counters& cnt) {
   (void)hipEventRecord(c->ev[4], s);
   launch_p23(R, o.v1s, o.v2s, o.v3t, o.Fe, o.Te, x, y, o.V, o.W, o.S, c->part.p, n, c->ph, c->tile_pass, s);
+  if (c->prm.plane) {
+    launch_image_op(R, x, y, c->part.p, n, c->ph, c->prm.plane_z, s);
+    launch_image_out(R, o.Fe, o.Te, x, o.v3t, o.V, o.W, c->part.p, n, c->ph, c->prm.plane_z, s);
+    cnt.pairs += 2.0 * (double)n * (double)n;
+  }
   (void)hipEventRecord(c->ev[5], s);
   cnt.pairs += 2.0 * (double)n * (double)(n - 1);
   o.valid = true;
@@ -359,7 +370,7 @@ StepGraphs* step_graphs(mbs_ctx* c, int prec, int64_t n, const double* R, bool p
       (uintptr_t)c->H.p, (uintptr_t)c->small.p, (uintptr_t)c->dpart.p, (uintptr_t)c->part.p,
       (uintptr_t)c->srcbuf.p, (uintptr_t)c->orig.p, (uintptr_t)c->near.p, (uintptr_t)near_order(c),
       dbits(c->ph.P), dbits(c->ph.a2),
-      dbits(c->ph.gamma), dbits(c->ph.inv_gamma)};
+      dbits(c->ph.gamma), dbits(c->ph.inv_gamma), (uintptr_t)c->prm.plane, dbits(c->prm.plane_z)};
   StepGraphs& G = c->sgraph[prec == MBS_FP64 ? 0 : 1];
   if (key == G.key) return &G;
   G.reset();
@@ -518,6 +529,28 @@ int check_inputs(mbs_ctx* c, hipStream_t s, std::initializer_list<std::pair<cons
   if (bad) return set_err(c, MBS_EINVAL, "%d non-finite input values", bad);
   if (bad_p)
     return set_err(c, MBS_EINVAL, "%d orientations p are not unit vectors (| |p| - 1 | > %.0e)", bad_p, kUnitTol);
+  return MBS_OK;
+}
+
+// With params.plane, the points X [m x 3] must lie at or above zmin (non-finite ones count as below).
+int check_above(mbs_ctx* c, hipStream_t s, const double* X, int64_t m, double zmin, const char* what) {
+  HIPCHK(c, hipMemsetAsync(c->d_count, 0, sizeof(int), s));
+  launch_count_below(X, m, zmin, c->d_count, s);
+  int h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, c->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (h) return set_err(c, MBS_EINVAL, "%d %s", h, what);
+  return MBS_OK;
+}
+// every sphere at least a above the plane (a no-op without params.plane)
+int check_plane(mbs_ctx* c, hipStream_t s, const double* R, int64_t n) {
+  if (!c->prm.plane) return MBS_OK;
+  return check_above(c, s, R, n, c->prm.plane_z + c->prm.a,
+                     "sphere centres lie less than a above the plane (params.plane_z + a)");
+}
+// entry points that do not take the plane
+int refuse_plane(mbs_ctx* c, const char* what) {
+  if (c->prm.plane) return set_err(c, MBS_EUNSUPPORTED, "%s does not support params.plane", what);
   return MBS_OK;
 }
 
@@ -763,6 +796,7 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
     HIPCHK(c, hipEventRecord(c->ev[2], s));
     launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
     if (high) launch_high(1, R, n, R, n, hi, V, W, c->part.p, hsplit, c->ph, c->tile_pass, s);
+    if (c->prm.plane) launch_image_out(R, Fe, Te, c->xs.p, v3t, V, W, c->part.p, n, c->ph, c->prm.plane_z, s);
     if (Sigma) launch_copy(c->xs.p, Sigma, len, s);
     HIPCHK(c, hipEventRecord(c->ev[3], s));
     HIPCHK(c, hipStreamSynchronize(s));
@@ -777,6 +811,10 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
   // right-hand side
   launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
   cnt.pairs += (double)n * (double)(n - 1);
+  if (c->prm.plane) {
+    launch_image_rhs(R, Fe, Te, v3t, c->b.p, c->part.p, n, c->ph, c->prm.plane_z, s);
+    cnt.pairs += (double)n * (double)n;
+  }
   if (high) {  // strain of the septlet, vortlet and spinlet flows
     launch_high(0, R, n, R, n, hi, c->b.p, nullptr, c->part.p, hsplit, c->ph, c->tile_pass, s);
     cnt.pairs += (double)n * (double)(n - 1);
@@ -875,6 +913,10 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
   if (!fused) {
     launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
     cnt.pairs += (double)n * (double)(n - 1);
+    if (c->prm.plane) {
+      launch_image_out(R, Fe, Te, c->xs.p, v3t, V, W, c->part.p, n, c->ph, c->prm.plane_z, s);
+      cnt.pairs += (double)n * (double)n;
+    }
   }
   if (high) {  // velocities and rotations from the septlet, vortlet and spinlet flows
     launch_high(1, R, n, R, n, hi, V, W, c->part.p, hsplit, c->ph, c->tile_pass, s);
@@ -1198,6 +1240,8 @@ void mbs_default_params(mbs_params* p) {
   p->superposition = 0;
   p->near_order = 2;
   p->spatial_order = 0;
+  p->plane = 0;
+  p->plane_z = 0.0;
 }
 
 int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {
@@ -1319,6 +1363,9 @@ int mbs_solve_ex(mbs_ctx* c, int64_t n, const double* R, const double* p, const 
   CHK(check_inputs(c, s, {{R, 3 * n}, {v1s, 3 * n}, {v2s, 5 * n}, {v3t, 3 * n}, {Fe, 3 * n},
                           {Te, 3 * n}, {sigma0, s0len}, {hi.gam, 10 * n}, {hi.psi, 5 * n}, {hi.lam, 10 * n}},
                    p, n));
+  if (c->prm.plane && high_mask(hi))
+    return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane");
+  CHK(check_plane(c, s, R, n));
   if (c->prm.check_overlap) {
     double md = 0.0;
     CHK(check_overlap(c, n, R, s, &md));
@@ -1347,6 +1394,7 @@ int mbs_matvec(mbs_ctx* c, int64_t n, const double* R, const double* x, double* 
     return set_err(c, MBS_EINVAL, "precision must be MBS_FP64 or MBS_FP32");
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
+  CHK(check_plane(c, s, R, n));
   Counters cnt;
   c->npend = 0;
   apply_op(c, precision, n, R, x, y, s, cnt);
@@ -1359,6 +1407,7 @@ int mbs_matvec(mbs_ctx* c, int64_t n, const double* R, const double* x, double* 
 int mbs_matvec_static(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, int precision,
                       void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_plane(c, "mbs_matvec_static"));
   if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
   if (n > kStaticMaxN)
     return set_err(c, MBS_EINVAL, "n = %lld exceeds the static scratch limit of %lld spheres", (long long)n,
@@ -1396,9 +1445,13 @@ int mbs_rhs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const 
                       {"Te", Te, 3 * n}, {"gam", hi.gam, 10 * n}, {"psi", hi.psi, 5 * n}, {"lam", hi.lam, 10 * n}}));
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
+  if (c->prm.plane && high_mask(hi))
+    return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane");
+  CHK(check_plane(c, s, R, n));
   launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, c->ph, c->tile_pass, s);
   if (high_mask(hi))
     launch_high(0, R, n, R, n, hi, b, nullptr, c->part.p, high_split(n, n, c->tile_pass), c->ph, c->tile_pass, s);
+  if (c->prm.plane) launch_image_rhs(R, Fe, Te, v3t, b, c->part.p, n, c->ph, c->prm.plane_z, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;
@@ -1423,10 +1476,14 @@ int mbs_outputs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v1s, co
                       {"psi", hi.psi, 5 * n}, {"lam", hi.lam, 10 * n}}));
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
+  if (c->prm.plane && high_mask(hi))
+    return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane");
+  CHK(check_plane(c, s, R, n));
   launch_p3(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, c->ph,
             c->tile_pass, s);
   if (high_mask(hi))
     launch_high(1, R, n, R, n, hi, V, W, c->part.p, high_split(n, n, c->tile_pass), c->ph, c->tile_pass, s);
+  if (c->prm.plane) launch_image_out(R, Fe, Te, Sigma, v3t, V, W, c->part.p, n, c->ph, c->prm.plane_z, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;
@@ -1453,9 +1510,17 @@ int mbs_flow_ex(mbs_ctx* c, int64_t m, const double* X, int64_t n, const double*
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));  // (zeros stand in for absent forces)
   const int hsplit = high_split(m, n, c->tile_pass);
-  CHK(ensure(c, c->part, (size_t)std::max(flow_split(m, n, c->tile_pass), high_mask(hi) ? hsplit : 0) * 3 * m + 64));
+  CHK(ensure(c, c->part, (size_t)std::max<int64_t>((int64_t)std::max(flow_split(m, n, c->tile_pass), high_mask(hi) ? hsplit : 0) * 3 * m,
+                                                 c->prm.plane ? image_part_elems(m, n) : 0) + 64));
+  if (c->prm.plane) {
+    if (high_mask(hi))
+      return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane");
+    CHK(check_plane(c, s, R, n));
+    CHK(check_above(c, s, X, m, c->prm.plane_z, "field points lie below the plane"));
+  }
   launch_flow(X, m, R, Fe ? Fe : c->zeros.p, Te, Sigma, v3t, U, c->part.p, n, c->ph, c->tile_pass, s);
   if (high_mask(hi)) launch_high(2, X, m, R, n, hi, U, nullptr, c->part.p, hsplit, c->ph, c->tile_pass, s);
+  if (c->prm.plane) launch_image_flow(X, m, R, n, Fe, Te, Sigma, v3t, U, c->part.p, c->ph, c->prm.plane_z, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;
@@ -1470,6 +1535,7 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
              double dt, int32_t nsteps, int32_t order, double* hist, int32_t hist_valid,
              mbs_stats* per_step, double* min_dist, void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_plane(c, "mbs_step"));
   if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
   if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
   if (!R || !p || !slip_coef) return set_err(c, MBS_EINVAL, "R, p and slip_coef are required");
@@ -1574,6 +1640,7 @@ int mbs_solve_batched(mbs_ctx* c, int32_t nconf, const int64_t* offsets, const d
                       const double* Te, double* V, double* W, double* S, double* Sigma,
                       mbs_stats* per_conf, double* latency_ms, void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_plane(c, "mbs_solve_batched"));
   CHK(check_offsets(c, nconf, offsets));
   if (!R || !V || !W || !S) return set_err(c, MBS_EINVAL, "R, V, W and S are required");
   const int64_t ntot64 = offsets[nconf];
@@ -2275,6 +2342,7 @@ int mbs_initial_guess(mbs_ctx* c, int64_t n, const double* R, const double* p, c
                       const double* v3t, const double* Fe, const double* Te, int32_t guess,
                       double* sigma0, void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_plane(c, "mbs_initial_guess"));
   if (n < 1 || !R || !sigma0) return set_err(c, MBS_EINVAL, "n >= 1, R and sigma0 are required");
   if (n > (int64_t)INT32_MAX / kMlpIn) return set_err(c, MBS_EINVAL, "n too large");
   if (guess != MBS_GUESS_ZERO && guess != MBS_GUESS_DIAG && guess != MBS_GUESS_LEARNED)
@@ -2302,6 +2370,7 @@ int mbs_warmstart_target(mbs_ctx* c, int64_t n, const double* R, const double* v
                          const double* Fe, const double* Te, const double* Sigma, float* target,
                          void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_plane(c, "mbs_warmstart_target"));
   if (n < 1 || !R || !Sigma || !target) return set_err(c, MBS_EINVAL, "n >= 1, R, Sigma, target required");
   if (n > (int64_t)INT32_MAX / kMlpIn) return set_err(c, MBS_EINVAL, "n too large");
   hipStream_t s = (hipStream_t)stream;
@@ -2332,6 +2401,7 @@ int mbs_precond_apply(mbs_ctx* c, int64_t n, const double* R, const double* x, d
 
 int mbs_matvec_r3(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_plane(c, "the rank-3 entry points"));
   CHK(r3_check_n(c, n));
   if (!R || !x || !y) return set_err(c, MBS_EINVAL, "R, x and y are required");
   CHK(check_aliasing(c, {{"y", y, 20 * n}}, {{"R", R, 3 * n}, {"x", x, 20 * n}}));
@@ -2348,6 +2418,7 @@ int mbs_matvec_r3(mbs_ctx* c, int64_t n, const double* R, const double* x, doubl
 int mbs_rhs_r3(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const double* v3t, const mbs_slip_ex* ex,
                const double* Fe, const double* Te, double* b, void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_plane(c, "the rank-3 entry points"));
   CHK(r3_check_n(c, n));
   if (!R || !b) return set_err(c, MBS_EINVAL, "R and b are required");
   const HighSlip hi = high_of(ex);
@@ -2368,6 +2439,7 @@ int mbs_outputs_r3(mbs_ctx* c, int64_t n, const double* R, const double* v1s, co
                    const mbs_slip_ex* ex, const double* Fe, const double* Te, const double* x, double* V, double* W,
                    double* S, void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_plane(c, "the rank-3 entry points"));
   CHK(r3_check_n(c, n));
   if (!R || !x || !V || !W) return set_err(c, MBS_EINVAL, "R, x, V and W are required");
   const HighSlip hi = high_of(ex);
@@ -2385,6 +2457,7 @@ int mbs_outputs_r3(mbs_ctx* c, int64_t n, const double* R, const double* v1s, co
 
 int mbs_precond_apply_r3(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_plane(c, "the rank-3 entry points"));
   CHK(r3_check_n(c, n));
   if (!R || !x || !y) return set_err(c, MBS_EINVAL, "R, x and y are required");
   CHK(check_aliasing(c, {{"y", y, 20 * n}}, {{"R", R, 3 * n}, {"x", x, 20 * n}}));
@@ -2404,6 +2477,7 @@ int mbs_solve_r3(mbs_ctx* c, int64_t n, const double* R, const double* v1s, cons
                  const mbs_slip_ex* ex, const double* Fe, const double* Te, const double* x0, double* V, double* W,
                  double* S, double* x, mbs_stats* st, void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_plane(c, "the rank-3 entry points"));
   CHK(r3_check_n(c, n));
   if (!R || !V || !W || !S) return set_err(c, MBS_EINVAL, "R, V, W and S are required");
   const HighSlip hi = high_of(ex);

@@ -790,3 +790,9 @@ def test_free_slip_plane_system_is_the_free_one_far_from_the_plane_and_symmetric
         assert np.abs(Ap - A0).max() / np.abs(A0).max() < bar
     with pytest.raises(ValueError):
         plane.system_matrix(w.R, PRM, w.R[:, 2].min() - 0.5 * A)
+    # the operator restricted to rows (used where A is not formed) is the same operator
+    z_w = w.R[:, 2].min() - 2 * A
+    x = np.random.default_rng(4).standard_normal((12, 5))
+    rows = np.array([7, 0, 11])
+    y = (plane.system_matrix(w.R, PRM, z_w) @ x.ravel()).reshape(12, 5)[rows]
+    assert np.abs(plane.matvec_rows(w.R, x, rows, PRM, z_w) - y).max() < 1e-14 * np.abs(y).max()
