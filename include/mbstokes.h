@@ -144,8 +144,11 @@ typedef struct mbs_params {
                             to mbs_solve(_ex), mbs_matvec, mbs_rhs(_ex), mbs_outputs(_ex), mbs_flow(_ex)
                             (field points must lie in the fluid too); the higher slip modes, the
                             stepper, the batched solver, the rank <= 3 entry points and
-                            mbs_matvec_static refuse it (MBS_EUNSUPPORTED). The near-field
-                            preconditioner keeps the free-space pairs. 0 = unbounded fluid (default) */
+                            mbs_matvec_static refuse it (MBS_EUNSUPPORTED). The images' part of the
+                            operator runs in the pass's precision (binary32 in the inner passes of
+                            MBS_MIXED); the right-hand side, outputs and flow add theirs in binary64.
+                            The near-field preconditioner keeps the free-space pairs.
+                            0 = unbounded fluid (default) */
   int32_t reserved0;
   double  plane_z;       /* height of the plane (plane != 0) */
 } mbs_params;

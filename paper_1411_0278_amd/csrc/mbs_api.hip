@@ -289,8 +289,9 @@ void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x,
     launch_p2(true, R, x, y, c->part.p, c->srcbuf.p, c->orig.p, n, c->ph, c->tile32, s);
     cnt.f32++;
   }
-  if (c->prm.plane) {  // the images' part of the operator (binary64 in either precision)
-    launch_image_op(R, x, y, c->part.p, n, c->ph, c->prm.plane_z, s);
+  if (c->prm.plane) {  // the images' part of the operator, in the same precision
+    launch_p2_image(prec != MBS_FP64, R, x, y, c->part.p, n, c->ph, c->prm.plane_z,
+                    prec == MBS_FP64 ? c->tile64 : c->tile32, s);
     cnt.pairs += (double)n * (double)n;
   }
   if (timed) (void)hipEventRecord(c->opev[2 * slot + 1], s);
@@ -304,7 +305,7 @@ void apply_op_out(mbs_ctx* c, int64_t n, const double* R, const double* x, doubl
   (void)hipEventRecord(c->ev[4], s);
   launch_p23(R, o.v1s, o.v2s, o.v3t, o.Fe, o.Te, x, y, o.V, o.W, o.S, c->part.p, n, c->ph, c->tile_pass, s);
   if (c->prm.plane) {
-    launch_image_op(R, x, y, c->part.p, n, c->ph, c->prm.plane_z, s);
+    launch_p2_image(false, R, x, y, c->part.p, n, c->ph, c->prm.plane_z, c->tile64, s);
     launch_image_out(R, o.Fe, o.Te, x, o.v3t, o.V, o.W, c->part.p, n, c->ph, c->prm.plane_z, s);
     cnt.pairs += 2.0 * (double)n * (double)n;
   }

@@ -37,6 +37,11 @@ extern const int kTileCount;
 // src: scratch of 8n doubles (packed source records, variant 1); orig: 4 doubles of scratch.
 void launch_p2(bool f32, const double* R, const double* x, double* y, double* part, double* src,
                double* orig, int64_t n, const Phys& ph, Tile t, hipStream_t s);
+// y -= E* [x]: the strain of the spheres' mirror images in the plane z = plane_z (stresslet M x M,
+// M = diag(1, 1, -1)) at every sphere, own image included, with the LDS kernel of tile t (the streamed
+// variant falls back to 128-record tiles). part: scratch [split x 5n] as for launch_p2.
+void launch_p2_image(bool f32, const double* R, const double* x, double* y, double* part, int64_t n,
+                     const Phys& ph, double plane_z, Tile t, hipStream_t s);
 // b = E[F, T, d] - c s
 void launch_p1(const double* R, const double* v2s, const double* v3t, const double* Fe,
                const double* Te, double* b, double* part, int64_t n, const Phys& ph, Tile t,
@@ -89,12 +94,10 @@ void launch_rank3_diag(const double* b, int64_t n, double gamma, double* x, hipS
 void launch_rank3_near(const double* R, const double* v, const double* z, const int* cnt, const int* list,
                        int64_t n, const Phys& ph, double* y, hipStream_t s);
 // Spheres above a stress-free plane z = plane_z: the passes of the spheres' mirror images (every
-// sphere's own image included). part: scratch of image_part_elems(m, n) doubles.
+// sphere's own image included; the operator's image part is launch_p2_image). part: scratch of
+// image_part_elems(m, n) doubles.
 int image_split(int64_t m, int64_t n);
 int64_t image_part_elems(int64_t m, int64_t n);
-// y -= E[images of the stresslets x] (the operator's image part)
-void launch_image_op(const double* R, const double* x, double* y, double* part, int64_t n, const Phys& ph,
-                     double plane_z, hipStream_t s);
 // b += E[images of F, T, d] (NULL = absent)
 void launch_image_rhs(const double* R, const double* Fe, const double* Te, const double* v3t, double* b, double* part,
                       int64_t n, const Phys& ph, double plane_z, hipStream_t s);

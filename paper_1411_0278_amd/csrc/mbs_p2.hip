@@ -318,10 +318,13 @@ struct LdsRec<float> {
   using type = SrcF9;
 };
 
-template <typename T, int TJ>
+// IMG: the sources are the mirror images of the spheres in the plane z = zw2/2 (centre z -> zw2 - z,
+// stresslet M Sigma M with M = diag(1, 1, -1): the xz and yz components change sign); no image
+// coincides with a receiver, and the sums always go to the chunk partials.
+template <typename T, int TJ, bool IMG>
 __global__ void __launch_bounds__(kMaxBlock)
     k_p2_lds(const double* __restrict__ R, const double* __restrict__ X, double* __restrict__ out,
-             int n, int chunk, double P, double a2, double inv_gamma, int direct) {
+             int n, int chunk, double P, double a2, double inv_gamma, int direct, double zw2) {
   constexpr bool f32 = sizeof(T) == 4;
   using Rec = typename LdsRec<T>::type;
   __shared__ Rec tile[TJ];
@@ -351,18 +354,18 @@ __global__ void __launch_bounds__(kMaxBlock)
       Rec r;
       r.x = (T)(R[3 * (int64_t)j] - ox);
       r.y = (T)(R[3 * (int64_t)j + 1] - oy);
-      r.z = (T)(R[3 * (int64_t)j + 2] - oz);
+      r.z = (T)((IMG ? zw2 - R[3 * (int64_t)j + 2] : R[3 * (int64_t)j + 2]) - oz);
       r.sxx = (T)sxx;
       r.syy = (T)syy;
       r.sxy = (T)sxy;
-      r.sxz = (T)sxz;
-      r.syz = (T)syz;
+      r.sxz = (T)(IMG ? -sxz : sxz);
+      r.syz = (T)(IMG ? -syz : syz);
       if constexpr (f32) r.szz = (float)(-(sxx + syy));
       tile[t] = r;
     }
     __syncthreads();
     Mom<T> m;
-    const bool self = jt < b1 && jt + cnt > b0;  // uniform
+    const bool self = !IMG && jt < b1 && jt + cnt > b0;  // uniform
     if constexpr (f32) {
       if (self) {
 #pragma unroll 8
@@ -403,6 +406,15 @@ __global__ void k_p2_finish(const double* __restrict__ X, const double* __restri
   y[k] = X[k] * inv_gamma - acc;
 }
 
+// y -= sum_s part[s] (the images' part of the operator)
+__global__ void k_p2_finish_sub(const double* __restrict__ part, double* __restrict__ y, int64_t len, int split) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  double acc = 0.0;
+  for (int s = 0; s < split; ++s) acc += part[s * len + k];
+  y[k] -= acc;
+}
+
 inline unsigned nblk(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
 
 template <typename T>
@@ -424,18 +436,42 @@ void p2_launch(const double* R, const double* x, double* y, double* part, double
     hipLaunchKernelGGL(k_p2_stream<T>, grid, dim3(b), 0, s, src, R, x, out, (int)n, chunk, o, ph.P,
                        ph.a2, ph.inv_gamma, direct);
   } else if (tj == 64) {
-    hipLaunchKernelGGL((k_p2_lds<T, 64>), grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P, ph.a2,
-                       ph.inv_gamma, direct);
+    hipLaunchKernelGGL((k_p2_lds<T, 64, false>), grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P, ph.a2,
+                       ph.inv_gamma, direct, 0.0);
   } else if (tj == 256) {
-    hipLaunchKernelGGL((k_p2_lds<T, 256>), grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P,
-                       ph.a2, ph.inv_gamma, direct);
+    hipLaunchKernelGGL((k_p2_lds<T, 256, false>), grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P,
+                       ph.a2, ph.inv_gamma, direct, 0.0);
   } else {
-    hipLaunchKernelGGL((k_p2_lds<T, 128>), grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P,
-                       ph.a2, ph.inv_gamma, direct);
+    hipLaunchKernelGGL((k_p2_lds<T, 128, false>), grid, dim3(b), 0, s, R, x, out, (int)n, chunk, ph.P,
+                       ph.a2, ph.inv_gamma, direct, 0.0);
   }
   if (split > 1)
     hipLaunchKernelGGL(k_p2_finish, dim3(nblk(5 * n, 256)), dim3(256), 0, s, x, part, y, 5 * n,
                        split, ph.inv_gamma);
+}
+
+// y -= (the images' strain E) with the LDS kernel of tile t (the scalar-streamed variant, which packs
+// records once per call, falls back to 128-record tiles of 256 receivers)
+template <typename T>
+void p2_image_launch(const double* R, const double* x, double* y, double* part, int64_t n, const Phys& ph,
+                     double plane_z, Tile t, hipStream_t s) {
+  if (t.variant != 0) t = Tile{0, 256, 128, 2048};
+  const int b = tile_block(t);
+  const int tj = (t.tj == 64 || t.tj == 256) ? t.tj : 128;
+  const int split = split_for(n, t, tj);
+  const int chunk = (int)((n + split - 1) / split);
+  dim3 grid(nblk(n, b), split);
+  const double zw2 = 2.0 * plane_z;
+  if (tj == 64)
+    hipLaunchKernelGGL((k_p2_lds<T, 64, true>), grid, dim3(b), 0, s, R, x, part, (int)n, chunk, ph.P, ph.a2,
+                       ph.inv_gamma, 0, zw2);
+  else if (tj == 256)
+    hipLaunchKernelGGL((k_p2_lds<T, 256, true>), grid, dim3(b), 0, s, R, x, part, (int)n, chunk, ph.P, ph.a2,
+                       ph.inv_gamma, 0, zw2);
+  else
+    hipLaunchKernelGGL((k_p2_lds<T, 128, true>), grid, dim3(b), 0, s, R, x, part, (int)n, chunk, ph.P, ph.a2,
+                       ph.inv_gamma, 0, zw2);
+  hipLaunchKernelGGL(k_p2_finish_sub, dim3(nblk(5 * n, 256)), dim3(256), 0, s, part, y, 5 * n, split);
 }
 
 }  // namespace
@@ -471,6 +507,15 @@ void launch_p2(bool f32, const double* R, const double* x, double* y, double* pa
     p2_launch<float>(R, x, y, part, src, orig, n, ph, t, s);
   else
     p2_launch<double>(R, x, y, part, src, orig, n, ph, t, s);
+}
+
+void launch_p2_image(bool f32, const double* R, const double* x, double* y, double* part, int64_t n,
+                     const Phys& ph, double plane_z, Tile t, hipStream_t s) {
+  if (n <= 0) return;
+  if (f32)
+    p2_image_launch<float>(R, x, y, part, n, ph, plane_z, t, s);
+  else
+    p2_image_launch<double>(R, x, y, part, n, ph, plane_z, t, s);
 }
 
 }  // namespace mbs

@@ -8,9 +8,9 @@
 //     force F* = M F,   torque T* = -M T (axial),   stresslet Sigma* = M Sigma M,   d* = M d,
 // and the receiver's Galerkin projections (the finite-size operators included) act on the image
 // flows as on any incident Stokes flow. The free-space passes are unchanged; these passes add the
-// images: the strain E of the images' stresslets (the operator), of their forces, torques and rank-3
-// trace modes (the right-hand side), their velocity and rotation U, W (the outputs) and their flow
-// at field points. Every sphere lies at least a above the plane (checked by the caller), so no image
+// images: the strain E of their forces, torques and rank-3 trace modes (the right-hand side), their
+// velocity and rotation U, W (the outputs) and their flow at field points. The strain of the images'
+// stresslets (the operator's image part, in the solve's precision) is a mode of the operator kernel. Every sphere lies at least a above the plane (checked by the caller), so no image
 // comes closer than 2a to a receiver.
 //
 // Layout: one receiver per thread, image records built from the caller's arrays into LDS tiles, the
@@ -114,7 +114,7 @@ __device__ __forceinline__ void image_flow(const RecO& s, const Geo& g, double a
   uz = fma(g.ri3, s.tx * g.dy - s.ty * g.dx, fma(-g.ri3, s.dz, uz));
 }
 
-enum { kImOp = 0, kImRhs = 1, kImOut = 2, kImFlow = 3 };
+enum { kImRhs = 1, kImOut = 2, kImFlow = 3 };
 constexpr int im_width(int t) { return t == kImOut ? 6 : (t == kImFlow ? 3 : 5); }
 
 // receivers X [m x 3] (the spheres, or field points for kImFlow) against the images of the n spheres
@@ -129,7 +129,6 @@ __global__ void __launch_bounds__(kImBlk)
   const double xi = X[3 * (int64_t)ii], yi = X[3 * (int64_t)ii + 1], zi = X[3 * (int64_t)ii + 2];
   const int j0 = blockIdx.y * chunk;
   const int j1 = min(n, j0 + chunk);
-  Mom<double> ms;
   Mom6 mf;
   UW uw;
   double ux = 0.0, uy = 0.0, uz = 0.0;
@@ -137,14 +136,12 @@ __global__ void __launch_bounds__(kImBlk)
     const int cnt = min(kImTJ, j1 - jt);
     __syncthreads();
     for (int t = threadIdx.x; t < cnt; t += blockDim.x)
-      tile[t] = make_image(R, TGT == kImOp ? nullptr : Fe, TGT == kImOp ? nullptr : Te,
-                           TGT == kImRhs ? nullptr : Sig, D, jt + t, P, a5_10, zw2);
+      tile[t] = make_image(R, Fe, Te, TGT == kImRhs ? nullptr : Sig, D, jt + t, P, a5_10, zw2);
     __syncthreads();
     for (int jj = 0; jj < cnt; ++jj) {
       const RecO& s = tile[jj];
       Geo g;
       pair_geo<false>(s, xi, yi, zi, g);  // an image is never closer than 2a to a sphere
-      if (TGT == kImOp) p2_acc(s, g, 24.0 * a2, 42.0 * a2, ms);
       if (TGT == kImRhs) image_fixed_strain(s, g, 8.0 * a2, -3.2 * a2, mf);
       if (TGT == kImOut) p3_acc<true, true>(s, g, 2.0 * a2, 2.0 * a2 / 3.0, 8.0 * a2, -3.2 * a2, uw);
       if (TGT == kImFlow) image_flow(s, g, a2, ux, uy, uz);
@@ -152,7 +149,6 @@ __global__ void __launch_bounds__(kImBlk)
   }
   if (i >= m) return;
   double* o = part + ((int64_t)blockIdx.y * m + i) * im_width(TGT);
-  if (TGT == kImOp) p2_strain(&ms.pxx, 1.0, a2, o);  // the records carry P
   if (TGT == kImRhs) mom6_to_basis(mf, o);
   if (TGT == kImOut) {
     o[0] = uw.ux;
@@ -225,12 +221,6 @@ int image_split(int64_t m, int64_t n) {
 }
 
 int64_t image_part_elems(int64_t m, int64_t n) { return (int64_t)image_split(m, n) * 6 * m; }
-
-void launch_image_op(const double* R, const double* x, double* y, double* part, int64_t n, const Phys& ph,
-                     double plane_z, hipStream_t s) {
-  if (n <= 0) return;
-  image_launch<kImOp>(R, n, R, n, nullptr, nullptr, x, nullptr, -1.0, y, nullptr, part, ph, plane_z, s);
-}
 
 void launch_image_rhs(const double* R, const double* Fe, const double* Te, const double* v3t, double* b, double* part,
                       int64_t n, const Phys& ph, double plane_z, hipStream_t s) {

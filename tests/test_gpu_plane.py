@@ -73,7 +73,7 @@ def test_plane_operator_matches_oracle(ctx, n):
         got = ctx.mbs_matvec(_t(w.R), _t(x))
         got32 = ctx.mbs_matvec(_t(w.R), _t(x), precision=mbstokes.MBS_FP32)
     assert _maxrel(got, want) < 1e-13
-    assert _maxrel(got32, want) < 2e-6  # binary32 free-space part, binary64 image part
+    assert _maxrel(got32, want) < 2e-6  # binary32 free-space and image parts
 
 
 @pytest.mark.parametrize("n", [1, 2, 97, 257])
@@ -147,9 +147,37 @@ def test_plane_operator_at_ten_thousand_spheres_sampled_rows(ctx):
     x = np.random.default_rng(5).standard_normal((n, 5))
     with _Plane(ctx, z_w):
         got = _np(ctx.mbs_matvec(_t(w.R), _t(x)))
+        got32 = _np(ctx.mbs_matvec(_t(w.R), _t(x), precision=mbstokes.MBS_FP32))
     rows = np.concatenate([np.argsort(w.R[:, 2])[:4], np.random.default_rng(6).choice(n, 12, replace=False)])
     want = plane.matvec_rows(w.R, x, rows, _prm(w), z_w)
     assert _maxrel(got[rows], want) < 1e-12
+    assert _maxrel(got32[rows], want) < 2e-6
+
+
+@pytest.mark.parametrize("n", [257, 1300])
+def test_plane_operator_every_launch_shape(ctx, n):
+    """The images' part runs in the operator kernel's LDS variant with the context's launch shape
+    (64, 128 or 256 records per tile; the streamed shapes fall back to 128): every candidate shape
+    agrees with the oracle in both precisions."""
+    w, z_w = _workload(n, 2100 + n)
+    x = np.random.default_rng(n + 1).standard_normal((n, 5))
+    want = (plane.system_matrix(w.R, _prm(w), z_w) @ x.ravel()).reshape(n, 5)
+    R, xt = _t(w.R), _t(x)
+    count = 0
+    with _Plane(ctx, z_w):
+        k = 1
+        while True:
+            try:
+                ctx.set_params(tile=k)
+            except mbstokes.MbsError:
+                break
+            print(f"plane matvec n={n} tile={k}", flush=True)
+            assert _maxrel(ctx.mbs_matvec(R, xt), want) < 1e-13, k
+            assert _maxrel(ctx.mbs_matvec(R, xt, precision=mbstokes.MBS_FP32), want) < 2e-6, k
+            count += 1
+            k += 1
+        ctx.set_params(tile=0)
+    assert count >= 8
 
 
 def test_plane_errors(ctx):
