@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import sympy as sp
 
-from oracle import basis, galerkin, greens, krylov, plane, stepper
+from oracle import basis, galerkin, greens, krylov, plane, stepper, wall
 from paper_1411_0278_amd import inputs
 from tests import sphere_quad
 
@@ -796,3 +796,157 @@ def test_free_slip_plane_system_is_the_free_one_far_from_the_plane_and_symmetric
     rows = np.array([7, 0, 11])
     y = (plane.system_matrix(w.R, PRM, z_w) @ x.ravel()).reshape(12, 5)[rows]
     assert np.abs(plane.matvec_rows(w.R, x, rows, PRM, z_w) - y).max() < 1e-14 * np.abs(y).max()
+
+
+# ---------------------------------------------------------------- a no-slip plane wall (other geometry)
+def test_wall_two_point_form_reproduces_the_free_space_blocks():
+    """The wall blocks take each source's surface moments against a kernel K(x, y) in its source
+    argument (finite-size operators and derivatives in y) rather than as derivatives of G(x - y) in
+    the field point; with K = G(x - y) that form is the free-space block of every target and source
+    kind, and the free-space flow."""
+    rng = np.random.default_rng(31)
+    dx = rng.standard_normal((12, 3)) * 3.0 + np.array([0.0, 0.0, 0.4])
+    for tgt in ("E", "U", "W"):
+        for src in ("F", "T", "S", "D"):
+            want = greens.block(tgt, src, dx, A, ETA)
+            got = wall.block("free", tgt, src, dx, 0.0, A, ETA)
+            assert np.abs(got - want).max() <= 1e-13 * max(np.abs(want).max(), 1e-300), (tgt, src)
+    for src in ("F", "T", "S", "D"):
+        want = greens.flow(src, dx, A, ETA)
+        assert np.abs(wall.flow("free", src, dx, 0.0, A, ETA) - want).max() < 1e-13 * np.abs(want).max()
+
+
+def _wall_caches_clear():
+    for f in (wall.kernel_expr, wall.source_flow, wall.block_expr, wall._block_fn, wall._flow_fn):
+        f.cache_clear()
+
+
+def _wall_slip(kind, c, y, X, z_w):
+    """Largest velocity on the wall of one source with its image part, relative to its free flow."""
+    uf = greens.flow(kind, X - y, A, ETA) @ c
+    ui = wall.flow("wall", kind, X - wall.mirror(y, z_w), y[0, 2] - z_w, A, ETA) @ c
+    return np.abs(uf + ui).max() / np.abs(uf).max()
+
+
+def test_wall_image_flows_vanish_on_the_wall(monkeypatch):
+    """Blake's image system: each source kind (force, torque, stresslet, rank-3 mode, each with its
+    finite-size operator acting on the source point) together with its image part has zero
+    velocity on the wall. The image kernel is divergence free and biharmonic in the field point and
+    in the source point. Reflecting the doublets with the identity instead of M = diag(1, 1, -1)
+    breaks the no-slip condition."""
+    K = wall.kernel_expr("wall")
+    for j in range(3):
+        assert wall._canon(sum(wall._dx("wall", K[i][j], i) for i in range(3))) == 0
+        assert wall._canon(sum(wall._dy("wall", K[j][i], i) for i in range(3))) == 0
+    for i, j in ((0, 0), (0, 2), (2, 1)):
+        assert wall._lap("wall", wall._lap("wall", K[i][j], "x"), "x") == 0
+        assert wall._lap("wall", wall._lap("wall", K[i][j], "y"), "y") == 0
+    rng = np.random.default_rng(32)
+    z_w = 0.6
+    y = np.array([[0.3, -0.4, z_w + 1.7 * A]])
+    X = np.column_stack([rng.uniform(-5, 5, 30), rng.uniform(-5, 5, 30), np.full(30, z_w)])
+    for kind, dim in (("F", 3), ("T", 3), ("S", 5), ("D", 3)):
+        assert _wall_slip(kind, rng.standard_normal(dim), y, X, z_w) < 1e-13, kind
+    try:
+        monkeypatch.setattr(wall, "_M", (1, 1, 1))
+        _wall_caches_clear()
+        assert _wall_slip("F", rng.standard_normal(3), y, X, z_w) > 1e-2
+    finally:
+        monkeypatch.undo()
+        _wall_caches_clear()
+
+
+def test_wall_kernel_is_reciprocal_and_the_system_symmetric():
+    """Lorentz reciprocity of the wall's Green's function, K_ij(x, y) = K_ji(y, x) (here its image
+    part), makes the half-space system symmetric; it stays positive definite."""
+    rng = np.random.default_rng(33)
+    z_w = -1.0
+    x = np.column_stack([rng.uniform(-3, 3, 8), rng.uniform(-3, 3, 8), z_w + rng.uniform(1, 4, 8)])
+    y = np.column_stack([rng.uniform(-3, 3, 8), rng.uniform(-3, 3, 8), z_w + rng.uniform(1, 4, 8)])
+    Kxy = np.array([wall.flow("wall", "F", x[p] - wall.mirror(y[p], z_w), y[p, 2] - z_w, A, ETA)[0]
+                    for p in range(8)])
+    Kyx = np.array([wall.flow("wall", "F", y[p] - wall.mirror(x[p], z_w), x[p, 2] - z_w, A, ETA)[0]
+                    for p in range(8)])
+    # with the finite-size operator F^0 on both points the image tensor is symmetric under the swap
+    Uxy = np.array([wall.block("wall", "U", "F", x[p] - wall.mirror(y[p], z_w), y[p, 2] - z_w, A, ETA)[0]
+                    for p in range(8)])
+    Uyx = np.array([wall.block("wall", "U", "F", y[p] - wall.mirror(x[p], z_w), x[p, 2] - z_w, A, ETA)[0]
+                    for p in range(8)])
+    assert np.abs(Uxy - Uyx.transpose(0, 2, 1)).max() < 1e-14 * np.abs(Uxy).max()
+    assert np.abs(Kxy - Kyx.transpose(0, 2, 1)).max() > 1e-6 * np.abs(Kxy).max()  # F^0 on one side only
+    w = inputs.trap_workload(10, 9.0, 4)
+    Aw = wall.system_matrix(w.R, PRM, w.R[:, 2].min() - 1.5 * A)
+    assert np.abs(Aw - Aw.T).max() < 1e-14 * np.abs(Aw).max()
+    assert np.linalg.eigvalsh(Aw).min() > 0
+
+
+def _lone_near_wall(h, z_w, F=None, T=None):
+    R = np.array([[0.2, 0.1, z_w + h]])
+    z3, z5 = np.zeros((1, 3)), np.zeros((1, 5))
+    return wall.solve(inputs.Workload(R, z3, z3, z5, None, F, T, ETA, A), z_w, PRM)
+
+
+def test_lone_sphere_near_a_no_slip_wall_follows_the_reflection_series():
+    """A lone sphere at height h above a no-slip wall, e = a/h: under a force parallel / normal to
+    the wall it moves with mu0 (1 - (9/16)e + (1/8)e^3) / mu0 (1 - (9/8)e + (1/2)e^3) up to terms of
+    order e^4 (the method of reflections, Faxen and Lorentz), under a torque about an axis parallel /
+    normal to it it turns with (1 - (5/16)e^3) / (1 - (1/8)e^3) times the free rate up to order e^6,
+    and a force parallel to the wall turns it at (3/32) e^4 F / (6 pi eta a^2) at leading order."""
+    z_w = 0.3
+    mu0, om0 = 1 / (6 * np.pi * ETA * A), 1 / (8 * np.pi * ETA * A ** 3)
+    ex, ez = np.array([[1.0, 0.0, 0.0]]), np.array([[0.0, 0.0, 1.0]])
+    for ha in (8, 16, 32):
+        e = 1.0 / ha
+        h = ha * A
+        sF = _lone_near_wall(h, z_w, F=ex)
+        par = sF["V"][0, 0] / mu0 - (1 - 9 / 16 * e + e ** 3 / 8)
+        per = _lone_near_wall(h, z_w, F=ez)["V"][0, 2] / mu0 - (1 - 9 / 8 * e + e ** 3 / 2)
+        rpar = _lone_near_wall(h, z_w, T=ex)["W"][0, 0] / om0 - (1 - 5 / 16 * e ** 3)
+        rper = _lone_near_wall(h, z_w, T=ez)["W"][0, 2] / om0 - (1 - e ** 3 / 8)
+        assert abs(par) < 0.2 * e ** 4 and abs(per) < 0.6 * e ** 4, ha
+        assert abs(rpar) < 0.1 * e ** 6 and abs(rper) < 0.1 * e ** 6, ha
+        coupling = abs(sF["W"][0, 1]) / (1 / (6 * np.pi * ETA * A ** 2))
+        assert abs(coupling / e ** 4 - 3 / 32) < 0.2 * e, ha
+
+
+def test_wall_solution_satisfies_weak_boundary_conditions_by_quadrature():
+    """A suspension solved above the wall (force, torque, slip modes, spheres 1.2a to 4a above it)
+    has, on every sphere, the l = 0 and l = 1 surface moments of its rigid motion plus the slip, in
+    the flow of all spheres and their image parts; the flow vanishes on the wall."""
+    rng = np.random.default_rng(34)
+    n, z_w = 4, -2.0
+    R = np.array([[0.0, 0.0, 1.2], [2.6, 0.3, 2.0], [-0.4, 2.5, 4.0], [2.2, 2.9, 1.5]]) * A
+    R[:, 2] += z_w
+    w = inputs.Workload(R, np.zeros((n, 3)), rng.standard_normal((n, 3)), rng.standard_normal((n, 5)),
+                        rng.standard_normal((n, 3)), rng.standard_normal((n, 3)),
+                        rng.standard_normal((n, 3)), ETA, A)
+    sol = wall.solve(w, z_w, PRM)
+    nh, wq = sphere_quad.sphere_rule(48, 96)
+    for i in range(n):
+        pts = R[i] + A * nh
+        u = wall.flow_field(pts, R, w.Fe, w.Te, sol["Sigma"], w.v3t, PRM, z_w)
+        mean, V2 = sphere_quad.coefficients(u, nh, wq, A)
+        scale = np.abs(u).max()
+        assert np.abs(mean - (sol["V"][i] + w.v1s[i])).max() < 1e-11 * scale
+        assert np.abs(sphere_quad.axial(V2, A) - sol["W"][i]).max() < 1e-11 * scale / A
+        assert np.abs(basis.to5(V2 / A) - w.v2s[i]).max() < 1e-11 * scale / A
+    X = np.column_stack([rng.uniform(-4, 6, 20), rng.uniform(-4, 6, 20), np.full(20, z_w)])
+    uw = wall.flow_field(X, R, w.Fe, w.Te, sol["Sigma"], w.v3t, PRM, z_w)
+    assert np.abs(uw).max() < 1e-12 * np.abs(sol["V"]).max()
+
+
+def test_wall_system_is_the_free_one_far_from_the_wall():
+    """The image blocks decay as the wall recedes; the operator restricted to rows is the same
+    operator; a sphere reaching through the wall is refused."""
+    w = inputs.trap_workload(12, 10.0, 3)
+    A0 = galerkin.system_matrix(w.R, PRM)
+    for z_w, bar in ((w.R[:, 2].min() - 3 * A, 2e-1), (w.R[:, 2].min() - 300 * A, 1e-5)):
+        assert np.abs(wall.system_matrix(w.R, PRM, z_w) - A0).max() / np.abs(A0).max() < bar
+    with pytest.raises(ValueError):
+        wall.system_matrix(w.R, PRM, w.R[:, 2].min() - 0.5 * A)
+    z_w = w.R[:, 2].min() - 2 * A
+    x = np.random.default_rng(4).standard_normal((12, 5))
+    rows = np.array([7, 0, 11])
+    y = (wall.system_matrix(w.R, PRM, z_w) @ x.ravel()).reshape(12, 5)[rows]
+    assert np.abs(wall.matvec_rows(w.R, x, rows, PRM, z_w) - y).max() < 1e-14 * np.abs(y).max()
+
