@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--profile-passes", action="store_true",
                     help="short run for hardware counters: one launch of every binary64 pass kernel at N")
     ap.add_argument("--skip-rank3", action="store_true", help="skip the traction rank <= 3 timings")
-    ap.add_argument("--skip-plane", action="store_true", help="skip the stress-free plane timings")
+    ap.add_argument("--skip-plane", action="store_true", help="skip the plane (stress-free, no-slip) timings")
     ap.add_argument("--profile-rank3", action="store_true",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then --steps "
                          "rank <= 3 operator applications at N = 10^4")
@@ -679,10 +679,11 @@ def bench_two_particle_orbits(ctx, horizon_tau=100, snap_tau=10):
 
 
 def bench_plane(ctx, a):
-    """Spheres above a stress-free plane (params.plane: every sphere also acts through its mirror
-    image): the trap spheres of the box of side 200 (10^4) and of the benchmark (10^5) with the plane
-    1.5a below the lowest one. The operator with and without the plane (binary64; binary32 with the
-    image part in binary64), and at 10^4 the solve to 1e-10 (binary64; mixed and binary64 with the
+    """Spheres above a plane (params.plane: 1 stress-free, every sphere also acting through its
+    mirror image; 2 no-slip wall, Blake's image system): the trap spheres of the box of side 200
+    (10^4) and of the benchmark (10^5) with the plane 1.5a below the lowest one. The operator with
+    and without the plane (binary64; binary32, whose image part is binary32 for the stress-free plane
+    and binary64 for the wall), and at 10^4 the solve to 1e-10 (binary64; binary64 and mixed with the
     near-field preconditioner at 12a, order 4). Median of 5 launches after 2 warm-ups, HIP events."""
     import statistics
 
@@ -703,40 +704,44 @@ def bench_plane(ctx, a):
             ts.append(e0.elapsed_time(e1))
         return statistics.median(ts)
 
-    out = {"plane": "stress-free, 1.5a below the lowest sphere"}
-    for label, w in (("n10000", inputs.trap_workload(10_000, 200.0, 1)),
-                     ("n%d" % a.n, inputs.trap_workload(a.n, a.side, a.seed))):
-        n = w.n
-        z_w = float(w.R[:, 2].min() - 1.5 * w.a)
-        d = mbstokes.to_device(w, "cuda:0")
-        x = d["v2s"].contiguous()
-        y = torch.empty_like(x)
-        row = {"n": n, "plane_z": z_w}
-        for name, prec in (("f64", mbstokes.MBS_FP64), ("f32", mbstokes.MBS_FP32)):
-            ctx.set_params(plane=0)
-            free = median_ms(lambda: ctx.mbs_matvec(d["R"], x, y, precision=prec))
-            ctx.set_params(plane=1, plane_z=z_w)
-            withp = median_ms(lambda: ctx.mbs_matvec(d["R"], x, y, precision=prec))
-            row["matvec_" + name] = {"free_ms": round(free, 4), "plane_ms": round(withp, 4),
-                                    "image_pass_ms": round(withp - free, 4)}
-        if n <= 20_000:
-            row["solve"] = {}
-            for vname, prec, cut, order in (("fp64", mbstokes.MBS_FP64, 0.0, 2), ("fp64_pc", mbstokes.MBS_FP64, 12.0, 4),
-                                            ("mixed_pc", mbstokes.MBS_MIXED, 12.0, 4)):
-                ctx.set_params(plane=1, plane_z=z_w, precision=prec, near_cutoff=cut, near_order=order, tol=1e-10,
-                               guess=mbstokes.MBS_GUESS_ZERO)
-                sts = []
-                for k in range(3):
-                    V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
-                    if k:
-                        sts.append(st)
-                med = sorted(sts, key=lambda t: t["t_total_ms"])[len(sts) // 2]
-                row["solve"][vname] = {"ms": round(med["t_total_ms"], 3), "iters": med["iters"],
-                                       "fp64_matvecs": med["fp64_matvecs"], "fp32_matvecs": med["fp32_matvecs"],
-                                       "rel_resid": med["rel_resid"]}
-        ctx.set_params(plane=0, plane_z=0.0, precision=mbstokes.MBS_FP64, near_cutoff=0.0, near_order=2)
-        out[label] = row
-        print(f"bench: plane {label} {row['matvec_f64']}", file=sys.stderr, flush=True)
+    out = {"plane": "1.5a below the lowest sphere"}
+    for kind, kname in ((1, "free_slip"), (2, "no_slip")):
+        rows = {}
+        for label, w in (("n10000", inputs.trap_workload(10_000, 200.0, 1)),
+                         ("n%d" % a.n, inputs.trap_workload(a.n, a.side, a.seed))):
+            n = w.n
+            z_w = float(w.R[:, 2].min() - 1.5 * w.a)
+            d = mbstokes.to_device(w, "cuda:0")
+            x = d["v2s"].contiguous()
+            y = torch.empty_like(x)
+            row = {"n": n, "plane_z": z_w}
+            for name, prec in (("f64", mbstokes.MBS_FP64), ("f32", mbstokes.MBS_FP32)):
+                ctx.set_params(plane=0)
+                free = median_ms(lambda: ctx.mbs_matvec(d["R"], x, y, precision=prec))
+                ctx.set_params(plane=kind, plane_z=z_w)
+                withp = median_ms(lambda: ctx.mbs_matvec(d["R"], x, y, precision=prec))
+                row["matvec_" + name] = {"free_ms": round(free, 4), "plane_ms": round(withp, 4),
+                                        "image_pass_ms": round(withp - free, 4)}
+            if n <= 20_000:
+                row["solve"] = {}
+                for vname, prec, cut, order in (("fp64", mbstokes.MBS_FP64, 0.0, 2),
+                                                ("fp64_pc", mbstokes.MBS_FP64, 12.0, 4),
+                                                ("mixed_pc", mbstokes.MBS_MIXED, 12.0, 4)):
+                    ctx.set_params(plane=kind, plane_z=z_w, precision=prec, near_cutoff=cut, near_order=order,
+                                   tol=1e-10, guess=mbstokes.MBS_GUESS_ZERO)
+                    sts = []
+                    for k in range(3):
+                        V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+                        if k:
+                            sts.append(st)
+                    med = sorted(sts, key=lambda t: t["t_total_ms"])[len(sts) // 2]
+                    row["solve"][vname] = {"ms": round(med["t_total_ms"], 3), "iters": med["iters"],
+                                           "fp64_matvecs": med["fp64_matvecs"],
+                                           "fp32_matvecs": med["fp32_matvecs"], "rel_resid": med["rel_resid"]}
+            ctx.set_params(plane=0, plane_z=0.0, precision=mbstokes.MBS_FP64, near_cutoff=0.0, near_order=2)
+            rows[label] = row
+            print(f"bench: plane {kname} {label} {row['matvec_f64']}", file=sys.stderr, flush=True)
+        out[kname] = rows
     return out
 
 

@@ -133,22 +133,29 @@ typedef struct mbs_params {
                             them stay small (N = 10^6: binary32 operator error 8.6e-7 -> 1.1e-7, one
                             binary32 iteration fewer); otherwise only the order of the sums, and so
                             the rounding, changes */
-  int32_t plane;         /* nonzero: the fluid fills the half space z > plane_z above a flat plane on
-                            which it slips freely (zero normal velocity and tangential stress: a flat
-                            free surface). Its Green's function is the free-space one plus its mirror
+  int32_t plane;         /* 1: the fluid fills the half space z > plane_z above a flat plane on which it
+                            slips freely (zero normal velocity and tangential stress: a flat free
+                            surface). Its Green's function is the free-space one plus its mirror
                             image, so every sphere also acts through its mirror image in the plane
                             (on every sphere, itself included), with F* = M F, T* = -M T,
-                            Sigma* = M Sigma M, d* = M d, M = diag(1, 1, -1) (the paper's remark that
-                            other geometries follow from their Green's function, Discussion). Every
-                            sphere must lie at least a above the plane (MBS_EINVAL otherwise). Applies
-                            to mbs_solve(_ex), mbs_matvec, mbs_rhs(_ex), mbs_outputs(_ex), mbs_flow(_ex)
-                            (field points must lie in the fluid too); the higher slip modes, the
-                            stepper, the batched solver, the rank <= 3 entry points and
-                            mbs_matvec_static refuse it (MBS_EUNSUPPORTED). The images' part of the
+                            Sigma* = M Sigma M, d* = M d, M = diag(1, 1, -1). The images' part of the
                             operator runs in the pass's precision (binary32 in the inner passes of
                             MBS_MIXED); the right-hand side, outputs and flow add theirs in binary64.
-                            The near-field preconditioner keeps the free-space pairs.
-                            0 = unbounded fluid (default) */
+                            2: the plane is a no-slip wall (zero velocity on it). Its Green's
+                            function is Blake's: the free-space one plus an image system at the
+                            mirror point (a Stokeslet, a Stokes doublet and a source doublet whose
+                            strengths depend on the source's height); every sphere acts through it
+                            on every sphere, itself included, with each source's finite-size operator
+                            taken in the source point. Its image part runs in binary64 in every pass.
+                            Both follow the paper's remark that other geometries, plane walls among
+                            them, follow from their Green's function (Discussion). Every sphere must
+                            lie at least a above the plane (MBS_EINVAL otherwise). Applies to
+                            mbs_solve(_ex), mbs_matvec, mbs_rhs(_ex), mbs_outputs(_ex), mbs_flow(_ex)
+                            (field points must lie in the fluid too); the higher slip modes, the
+                            stepper, the batched solver, the rank <= 3 entry points and
+                            mbs_matvec_static refuse it (MBS_EUNSUPPORTED). The near-field
+                            preconditioner keeps the free-space pairs. 0 = unbounded fluid (default);
+                            other values are MBS_EINVAL */
   int32_t reserved0;
   double  plane_z;       /* height of the plane (plane != 0) */
 } mbs_params;

@@ -176,7 +176,7 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
     return set_err(c, MBS_EINVAL, "near_order must be 0 (= 2), 2, 4, 6 or 8");
   if (p->spatial_order < -1 || p->spatial_order > 1)
     return set_err(c, MBS_EINVAL, "spatial_order must be -1, 0 or 1");
-  if (p->plane != 0 && p->plane != 1) return set_err(c, MBS_EINVAL, "plane must be 0 or 1");
+  if (p->plane < 0 || p->plane > 2) return set_err(c, MBS_EINVAL, "plane must be 0, 1 or 2");
   if (p->plane && !isfinite(p->plane_z)) return set_err(c, MBS_EINVAL, "plane_z must be finite");
   return MBS_OK;
 }
@@ -289,9 +289,12 @@ void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x,
     launch_p2(true, R, x, y, c->part.p, c->srcbuf.p, c->orig.p, n, c->ph, c->tile32, s);
     cnt.f32++;
   }
-  if (c->prm.plane) {  // the images' part of the operator, in the same precision
+  if (c->prm.plane == 1) {  // the mirror images' part of the operator, in the same precision
     launch_p2_image(prec != MBS_FP64, R, x, y, c->part.p, n, c->ph, c->prm.plane_z,
                     prec == MBS_FP64 ? c->tile64 : c->tile32, s);
+    cnt.pairs += (double)n * (double)n;
+  } else if (c->prm.plane == 2) {  // the wall images' part (binary64 in either precision)
+    launch_wall_op(R, x, y, c->part.p, n, c->ph, c->prm.plane_z, s);
     cnt.pairs += (double)n * (double)n;
   }
   if (timed) (void)hipEventRecord(c->opev[2 * slot + 1], s);
@@ -305,8 +308,11 @@ void apply_op_out(mbs_ctx* c, int64_t n, const double* R, const double* x, doubl
   (void)hipEventRecord(c->ev[4], s);
   launch_p23(R, o.v1s, o.v2s, o.v3t, o.Fe, o.Te, x, y, o.V, o.W, o.S, c->part.p, n, c->ph, c->tile_pass, s);
   if (c->prm.plane) {
-    launch_p2_image(false, R, x, y, c->part.p, n, c->ph, c->prm.plane_z, c->tile64, s);
-    launch_image_out(R, o.Fe, o.Te, x, o.v3t, o.V, o.W, c->part.p, n, c->ph, c->prm.plane_z, s);
+    if (c->prm.plane == 1)
+      launch_p2_image(false, R, x, y, c->part.p, n, c->ph, c->prm.plane_z, c->tile64, s);
+    else
+      launch_wall_op(R, x, y, c->part.p, n, c->ph, c->prm.plane_z, s);
+    launch_image_out(c->prm.plane, R, o.Fe, o.Te, x, o.v3t, o.V, o.W, c->part.p, n, c->ph, c->prm.plane_z, s);
     cnt.pairs += 2.0 * (double)n * (double)n;
   }
   (void)hipEventRecord(c->ev[5], s);
@@ -797,7 +803,8 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
     HIPCHK(c, hipEventRecord(c->ev[2], s));
     launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
     if (high) launch_high(1, R, n, R, n, hi, V, W, c->part.p, hsplit, c->ph, c->tile_pass, s);
-    if (c->prm.plane) launch_image_out(R, Fe, Te, c->xs.p, v3t, V, W, c->part.p, n, c->ph, c->prm.plane_z, s);
+    if (c->prm.plane)
+      launch_image_out(c->prm.plane, R, Fe, Te, c->xs.p, v3t, V, W, c->part.p, n, c->ph, c->prm.plane_z, s);
     if (Sigma) launch_copy(c->xs.p, Sigma, len, s);
     HIPCHK(c, hipEventRecord(c->ev[3], s));
     HIPCHK(c, hipStreamSynchronize(s));
@@ -813,7 +820,7 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
   launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
   cnt.pairs += (double)n * (double)(n - 1);
   if (c->prm.plane) {
-    launch_image_rhs(R, Fe, Te, v3t, c->b.p, c->part.p, n, c->ph, c->prm.plane_z, s);
+    launch_image_rhs(c->prm.plane, R, Fe, Te, v3t, c->b.p, c->part.p, n, c->ph, c->prm.plane_z, s);
     cnt.pairs += (double)n * (double)n;
   }
   if (high) {  // strain of the septlet, vortlet and spinlet flows
@@ -915,7 +922,7 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
     launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
     cnt.pairs += (double)n * (double)(n - 1);
     if (c->prm.plane) {
-      launch_image_out(R, Fe, Te, c->xs.p, v3t, V, W, c->part.p, n, c->ph, c->prm.plane_z, s);
+      launch_image_out(c->prm.plane, R, Fe, Te, c->xs.p, v3t, V, W, c->part.p, n, c->ph, c->prm.plane_z, s);
       cnt.pairs += (double)n * (double)n;
     }
   }
@@ -1452,7 +1459,7 @@ int mbs_rhs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const 
   launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, c->ph, c->tile_pass, s);
   if (high_mask(hi))
     launch_high(0, R, n, R, n, hi, b, nullptr, c->part.p, high_split(n, n, c->tile_pass), c->ph, c->tile_pass, s);
-  if (c->prm.plane) launch_image_rhs(R, Fe, Te, v3t, b, c->part.p, n, c->ph, c->prm.plane_z, s);
+  if (c->prm.plane) launch_image_rhs(c->prm.plane, R, Fe, Te, v3t, b, c->part.p, n, c->ph, c->prm.plane_z, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;
@@ -1484,7 +1491,8 @@ int mbs_outputs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v1s, co
             c->tile_pass, s);
   if (high_mask(hi))
     launch_high(1, R, n, R, n, hi, V, W, c->part.p, high_split(n, n, c->tile_pass), c->ph, c->tile_pass, s);
-  if (c->prm.plane) launch_image_out(R, Fe, Te, Sigma, v3t, V, W, c->part.p, n, c->ph, c->prm.plane_z, s);
+  if (c->prm.plane)
+    launch_image_out(c->prm.plane, R, Fe, Te, Sigma, v3t, V, W, c->part.p, n, c->ph, c->prm.plane_z, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;
@@ -1521,7 +1529,8 @@ int mbs_flow_ex(mbs_ctx* c, int64_t m, const double* X, int64_t n, const double*
   }
   launch_flow(X, m, R, Fe ? Fe : c->zeros.p, Te, Sigma, v3t, U, c->part.p, n, c->ph, c->tile_pass, s);
   if (high_mask(hi)) launch_high(2, X, m, R, n, hi, U, nullptr, c->part.p, hsplit, c->ph, c->tile_pass, s);
-  if (c->prm.plane) launch_image_flow(X, m, R, n, Fe, Te, Sigma, v3t, U, c->part.p, c->ph, c->prm.plane_z, s);
+  if (c->prm.plane)
+    launch_image_flow(c->prm.plane, X, m, R, n, Fe, Te, Sigma, v3t, U, c->part.p, c->ph, c->prm.plane_z, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   return MBS_OK;

@@ -93,21 +93,25 @@ void launch_rank3_diag(const double* b, int64_t n, double gamma, double* x, hipS
 // v, z, y [n x 20]; y must not overlap v or z.
 void launch_rank3_near(const double* R, const double* v, const double* z, const int* cnt, const int* list,
                        int64_t n, const Phys& ph, double* y, hipStream_t s);
-// Spheres above a stress-free plane z = plane_z: the passes of the spheres' mirror images (every
-// sphere's own image included; the operator's image part is launch_p2_image). part: scratch of
-// image_part_elems(m, n) doubles.
+// Spheres above a plane z = plane_z, kind 1 stress-free (mirror images; the operator's image part
+// is launch_p2_image) or kind 2 no-slip (Blake's image system, binary64): the image passes (every
+// sphere's own image included). part: scratch of image_part_elems(m, n) doubles.
 int image_split(int64_t m, int64_t n);
 int64_t image_part_elems(int64_t m, int64_t n);
+// y -= E[wall images of the stresslets x] (kind 2: the operator's image part)
+void launch_wall_op(const double* R, const double* x, double* y, double* part, int64_t n, const Phys& ph,
+                    double plane_z, hipStream_t s);
 // b += E[images of F, T, d] (NULL = absent)
-void launch_image_rhs(const double* R, const double* Fe, const double* Te, const double* v3t, double* b, double* part,
-                      int64_t n, const Phys& ph, double plane_z, hipStream_t s);
+void launch_image_rhs(int kind, const double* R, const double* Fe, const double* Te, const double* v3t, double* b,
+                      double* part, int64_t n, const Phys& ph, double plane_z, hipStream_t s);
 // V += U, W += W of the images of F, T, Sigma, d
-void launch_image_out(const double* R, const double* Fe, const double* Te, const double* Sig, const double* v3t,
-                      double* V, double* W, double* part, int64_t n, const Phys& ph, double plane_z, hipStream_t s);
+void launch_image_out(int kind, const double* R, const double* Fe, const double* Te, const double* Sig,
+                      const double* v3t, double* V, double* W, double* part, int64_t n, const Phys& ph, double plane_z,
+                      hipStream_t s);
 // U [m x 3] += flow of the images at field points X [m x 3]
-void launch_image_flow(const double* X, int64_t m, const double* R, int64_t n, const double* Fe, const double* Te,
-                       const double* Sig, const double* v3t, double* U, double* part, const Phys& ph, double plane_z,
-                       hipStream_t s);
+void launch_image_flow(int kind, const double* X, int64_t m, const double* R, int64_t n, const double* Fe,
+                       const double* Te, const double* Sig, const double* v3t, double* U, double* part, const Phys& ph,
+                       double plane_z, hipStream_t s);
 // rows of R [n x 3] with z < zmin (or non-finite) -> atomically added to *cnt
 void launch_count_below(const double* R, int64_t n, double zmin, int* cnt, hipStream_t s);
 // min over pairs of |R_n - R_m|^2 -> out[0] (device), from the cell grid g of R (exact: an

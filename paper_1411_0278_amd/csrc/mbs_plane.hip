@@ -13,6 +13,13 @@
 // stresslets (the operator's image part, in the solve's precision) is a mode of the operator kernel. Every sphere lies at least a above the plane (checked by the caller), so no image
 // comes closer than 2a to a receiver.
 //
+// A plane no-slip wall (zero velocity on z = z_w) has Blake's Green's function instead: the
+// free-space one plus an image part at the mirror point that depends on the source's height as well
+// as on the separation (a Stokeslet, a Stokes doublet and a source doublet there). Its blocks take
+// each source sphere's surface moments against that image part in the source point; the per-pair
+// arithmetic of every target (operator, right-hand side, outputs, flow) is generated from the
+// image system into mbs_wall_gen.h and evaluated here in binary64.
+//
 // Layout: one receiver per thread, image records built from the caller's arrays into LDS tiles, the
 // sources split into grid.y chunks whose partial sums a finishing kernel adds into the caller's
 // output in a fixed order.
@@ -25,6 +32,7 @@
 #include "mbs_device.h"
 #include "mbs_internal.h"
 #include "mbs_pair.h"
+#include "mbs_wall_gen.h"
 
 namespace mbs {
 namespace {
@@ -114,7 +122,7 @@ __device__ __forceinline__ void image_flow(const RecO& s, const Geo& g, double a
   uz = fma(g.ri3, s.tx * g.dy - s.ty * g.dx, fma(-g.ri3, s.dz, uz));
 }
 
-enum { kImRhs = 1, kImOut = 2, kImFlow = 3 };
+enum { kImOp = 0, kImRhs = 1, kImOut = 2, kImFlow = 3 };
 constexpr int im_width(int t) { return t == kImOut ? 6 : (t == kImFlow ? 3 : 5); }
 
 // receivers X [m x 3] (the spheres, or field points for kImFlow) against the images of the n spheres
@@ -165,6 +173,73 @@ __global__ void __launch_bounds__(kImBlk)
   }
 }
 
+// source record of the no-slip wall: centre, and the coefficients pre-scaled as the generated
+// arithmetic takes them (f = P F, t = P T, s = P Sigma in the 5-basis, q = (a^5/20) d; absent = 0)
+struct alignas(16) RecW {
+  double x, y, z, f[3], t[3], s[5], q[3], pad;
+};
+
+__device__ __forceinline__ RecW make_wall(const double* __restrict__ R, const double* __restrict__ Fe,
+                                          const double* __restrict__ Te, const double* __restrict__ Sig,
+                                          const double* __restrict__ D, int j, double P, double a5_20) {
+  RecW r;
+  r.x = R[3 * (int64_t)j];
+  r.y = R[3 * (int64_t)j + 1];
+  r.z = R[3 * (int64_t)j + 2];
+  for (int c = 0; c < 3; ++c) {
+    r.f[c] = Fe ? P * Fe[3 * (int64_t)j + c] : 0.0;
+    r.t[c] = Te ? P * Te[3 * (int64_t)j + c] : 0.0;
+    r.q[c] = D ? a5_20 * D[3 * (int64_t)j + c] : 0.0;
+  }
+  for (int c = 0; c < 5; ++c) r.s[c] = Sig ? P * Sig[5 * (int64_t)j + c] : 0.0;
+  r.pad = 0.0;
+  return r;
+}
+
+// receivers X [m x 3] against the wall images of the n spheres: kImOp the strain of the stresslets
+// Sig (the operator), kImRhs the strain of Fe, Te, D, kImOut U and W of all four, kImFlow the flow
+// of all four at field points
+template <int TGT>
+__global__ void __launch_bounds__(kImBlk)
+    k_wall(const double* __restrict__ X, int m, const double* __restrict__ R, int n, const double* __restrict__ Fe,
+           const double* __restrict__ Te, const double* __restrict__ Sig, const double* __restrict__ D, int chunk,
+           double P, double a2, double a5_20, double zw, double* __restrict__ part) {
+  __shared__ RecW tile[kImTJ];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < m ? i : m - 1;
+  const double xi = X[3 * (int64_t)ii], yi = X[3 * (int64_t)ii + 1], zi = X[3 * (int64_t)ii + 2];
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  constexpr int W = im_width(TGT);
+  double acc[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) acc[c] = 0.0;
+  for (int jt = j0; jt < j1; jt += kImTJ) {
+    const int cnt = min(kImTJ, j1 - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x)
+      tile[t] = make_wall(R, TGT == kImOp ? nullptr : Fe, TGT == kImOp ? nullptr : Te,
+                          TGT == kImRhs ? nullptr : Sig, TGT == kImOp ? nullptr : D, jt + t, P, a5_20);
+    __syncthreads();
+    for (int jj = 0; jj < cnt; ++jj) {
+      const RecW& s = tile[jj];
+      // separation from the mirror point and the source's height (at least a above the wall, so
+      // |R| >= 2a for a sphere and every image)
+      const double h = s.z - zw;
+      const double R1 = xi - s.x, R2 = yi - s.y, R3 = zi - zw + h;
+      const double ri = 1.0 / sqrt(fma(R1, R1, fma(R2, R2, R3 * R3)));
+      if (TGT == kImOp) wall_strain_s(R1, R2, R3, h, ri, a2, s.s, acc);
+      if (TGT == kImRhs) wall_strain_ftq(R1, R2, R3, h, ri, a2, s.f, s.t, s.q, acc);
+      if (TGT == kImOut) wall_motion_ftsq(R1, R2, R3, h, ri, a2, s.f, s.t, s.s, s.q, acc, acc + 3);
+      if (TGT == kImFlow) wall_flow_ftsq(R1, R2, R3, h, ri, a2, s.f, s.t, s.s, s.q, acc);
+    }
+  }
+  if (i >= m) return;
+  double* o = part + ((int64_t)blockIdx.y * m + i) * W;
+#pragma unroll
+  for (int c = 0; c < W; ++c) o[c] = acc[c];
+}
+
 // out += sign * (sum of the split partials, in order); widths 3 and 5 go to `out` [m x w], width 6 to
 // out [m x 3] (velocity) and out2 [m x 3] (rotation)
 template <int TGT>
@@ -201,13 +276,18 @@ __global__ void k_count_below(const double* __restrict__ R, int64_t n, double zm
 inline unsigned nblk_im(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
 
 template <int TGT>
-void image_launch(const double* X, int64_t m, const double* R, int64_t n, const double* Fe, const double* Te,
-                  const double* Sig, const double* D, double sign, double* out, double* out2, double* part,
-                  const Phys& ph, double plane_z, hipStream_t s) {
+void image_launch(int kind, const double* X, int64_t m, const double* R, int64_t n, const double* Fe,
+                  const double* Te, const double* Sig, const double* D, double sign, double* out, double* out2,
+                  double* part, const Phys& ph, double plane_z, hipStream_t s) {
   const int split = image_split(m, n);
   const int chunk = (int)((n + split - 1) / split);
-  hipLaunchKernelGGL(k_image<TGT>, dim3(nblk_im(m, kImBlk), split), dim3(kImBlk), 0, s, X, (int)m, R, (int)n, Fe, Te,
-                     Sig, D, chunk, ph.P, ph.a2, ph.a5_10, 2.0 * plane_z, part);
+  const dim3 grid(nblk_im(m, kImBlk), split);
+  if (kind == 2)
+    hipLaunchKernelGGL(k_wall<TGT>, grid, dim3(kImBlk), 0, s, X, (int)m, R, (int)n, Fe, Te, Sig, D, chunk, ph.P,
+                       ph.a2, 0.5 * ph.a5_10, plane_z, part);
+  else if constexpr (TGT != kImOp)
+    hipLaunchKernelGGL(k_image<TGT>, grid, dim3(kImBlk), 0, s, X, (int)m, R, (int)n, Fe, Te, Sig, D, chunk, ph.P,
+                       ph.a2, ph.a5_10, 2.0 * plane_z, part);
   hipLaunchKernelGGL(k_image_finish<TGT>, dim3(nblk_im(m, 256)), dim3(256), 0, s, part, split, (int)m, sign, out,
                      out2);
 }
@@ -222,23 +302,30 @@ int image_split(int64_t m, int64_t n) {
 
 int64_t image_part_elems(int64_t m, int64_t n) { return (int64_t)image_split(m, n) * 6 * m; }
 
-void launch_image_rhs(const double* R, const double* Fe, const double* Te, const double* v3t, double* b, double* part,
-                      int64_t n, const Phys& ph, double plane_z, hipStream_t s) {
-  if (n <= 0 || (!Fe && !Te && !v3t)) return;
-  image_launch<kImRhs>(R, n, R, n, Fe, Te, nullptr, v3t, 1.0, b, nullptr, part, ph, plane_z, s);
-}
-
-void launch_image_out(const double* R, const double* Fe, const double* Te, const double* Sig, const double* v3t,
-                      double* V, double* W, double* part, int64_t n, const Phys& ph, double plane_z, hipStream_t s) {
+void launch_wall_op(const double* R, const double* x, double* y, double* part, int64_t n, const Phys& ph,
+                    double plane_z, hipStream_t s) {
   if (n <= 0) return;
-  image_launch<kImOut>(R, n, R, n, Fe, Te, Sig, v3t, 1.0, V, W, part, ph, plane_z, s);
+  image_launch<kImOp>(2, R, n, R, n, nullptr, nullptr, x, nullptr, -1.0, y, nullptr, part, ph, plane_z, s);
 }
 
-void launch_image_flow(const double* X, int64_t m, const double* R, int64_t n, const double* Fe, const double* Te,
-                       const double* Sig, const double* v3t, double* U, double* part, const Phys& ph, double plane_z,
-                       hipStream_t s) {
+void launch_image_rhs(int kind, const double* R, const double* Fe, const double* Te, const double* v3t, double* b,
+                      double* part, int64_t n, const Phys& ph, double plane_z, hipStream_t s) {
+  if (n <= 0 || (!Fe && !Te && !v3t)) return;
+  image_launch<kImRhs>(kind, R, n, R, n, Fe, Te, nullptr, v3t, 1.0, b, nullptr, part, ph, plane_z, s);
+}
+
+void launch_image_out(int kind, const double* R, const double* Fe, const double* Te, const double* Sig,
+                      const double* v3t, double* V, double* W, double* part, int64_t n, const Phys& ph, double plane_z,
+                      hipStream_t s) {
+  if (n <= 0) return;
+  image_launch<kImOut>(kind, R, n, R, n, Fe, Te, Sig, v3t, 1.0, V, W, part, ph, plane_z, s);
+}
+
+void launch_image_flow(int kind, const double* X, int64_t m, const double* R, int64_t n, const double* Fe,
+                       const double* Te, const double* Sig, const double* v3t, double* U, double* part, const Phys& ph,
+                       double plane_z, hipStream_t s) {
   if (m <= 0 || n <= 0) return;
-  image_launch<kImFlow>(X, m, R, n, Fe, Te, Sig, v3t, 1.0, U, nullptr, part, ph, plane_z, s);
+  image_launch<kImFlow>(kind, X, m, R, n, Fe, Te, Sig, v3t, 1.0, U, nullptr, part, ph, plane_z, s);
 }
 
 void launch_count_below(const double* R, int64_t n, double zmin, int* cnt, hipStream_t s) {
