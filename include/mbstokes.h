@@ -151,9 +151,10 @@ typedef struct mbs_params {
                             them, follow from their Green's function (Discussion). Every sphere must
                             lie at least a above the plane (MBS_EINVAL otherwise). Applies to
                             mbs_solve(_ex), mbs_matvec, mbs_rhs(_ex), mbs_outputs(_ex), mbs_flow(_ex)
-                            (field points must lie in the fluid too); the higher slip modes, the
-                            stepper, the batched solver, the rank <= 3 entry points and
-                            mbs_matvec_static refuse it (MBS_EUNSUPPORTED). The near-field
+                            (field points must lie in the fluid too) and mbs_step (which monitors
+                            the heights, see there); the higher slip modes, the batched solver, the
+                            rank <= 3 entry points and mbs_matvec_static refuse it
+                            (MBS_EUNSUPPORTED). The near-field
                             preconditioner keeps the free-space pairs. 0 = unbounded fluid (default);
                             other values are MBS_EINVAL */
   int32_t reserved0;
@@ -384,6 +385,11 @@ int mbs_solve_r3(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, co
    forward Euler throughout). R, p [n x 3] are updated in place. slip_coef: host array [3].
    per_step: host array [nsteps] or NULL. min_dist: host array [nsteps] or NULL, receives the
    minimum centre distance of each step's configuration (overlaps are reported, not fatal).
+   With params.plane the spheres must start at least a above the plane (MBS_EINVAL); each sphere's
+   own image then counts as a neighbour at distance 2h (h its centre's height above the plane), so
+   min_dist < 2a also reports contact with the plane; the run goes on while every centre lies
+   above the plane and stops with MBS_EINVAL at the first step that finds one on or below it (R, p
+   hold the state before that step).
    With params.guess = MBS_GUESS_USER every step after the first starts from the previous step's
    Sigma (the first from the one-body guess). A step whose solve stops short of params.tol still
    advances and the call returns MBS_ENOCONV at the end; a non-finite residual stops the run

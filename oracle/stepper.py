@@ -24,9 +24,10 @@ def slip_from_orientation(p, coef):
     return coef[0] * p, coef[1] * to5(3.0 * (pp - np.eye(3) / 3.0)), coef[2] * p
 
 
-def run(R, p, k_trap, coef, dt, nsteps, prm: galerkin.Params, order=2, superposition=False):
+def run(R, p, k_trap, coef, dt, nsteps, prm: galerkin.Params, order=2, superposition=False, solve=None):
     """Integrate nsteps; returns (R, p, history of per-step dicts). With superposition the motion
-    comes from the superposition approximation (section IV) instead of the many-body solve."""
+    comes from the superposition approximation (section IV) instead of the many-body solve; `solve`
+    (state, prm) -> dict with V, W replaces the unbounded-fluid solve (a bounded geometry)."""
     R = np.array(R, dtype=np.float64)
     p = np.array(p, dtype=np.float64)
     prev = None
@@ -34,7 +35,10 @@ def run(R, p, k_trap, coef, dt, nsteps, prm: galerkin.Params, order=2, superposi
     for _ in range(nsteps):
         v1s, v2s, v3t = slip_from_orientation(p, coef)
         st = _State(R, p, v1s, v2s, v3t, -k_trap * R, np.zeros_like(R), prm.eta, prm.a)
-        sol = galerkin.superposition(st, prm) if superposition else galerkin.solve(st, prm)
+        if solve is not None:
+            sol = solve(st, prm)
+        else:
+            sol = galerkin.superposition(st, prm) if superposition else galerkin.solve(st, prm)
         V, W = sol["V"], sol["W"]
         pdot = np.cross(W, p)
         if order == 1 or prev is None:

@@ -608,6 +608,15 @@ int check_overlap(mbs_ctx* c, int64_t n, const double* R, hipStream_t s, double*
   return MBS_OK;
 }
 
+// lowest centre's height above the plane (params.plane)
+int min_height(mbs_ctx* c, int64_t n, const double* R, hipStream_t s, double* h) {
+  double* out = c->small.p + c->small.cap - 1;
+  launch_min_height(R, n, c->prm.plane_z, out, s);
+  CHK(read_status(c, out, 1, s));
+  *h = c->h_status[0];
+  return MBS_OK;
+}
+
 float ev_ms(hipEvent_t a, hipEvent_t b) {
   float t = 0.f;
   if (hipEventElapsedTime(&t, a, b) != hipSuccess) return 0.f;
@@ -1545,7 +1554,6 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
              double dt, int32_t nsteps, int32_t order, double* hist, int32_t hist_valid,
              mbs_stats* per_step, double* min_dist, void* stream) {
   CHK(begin_call(c));
-  CHK(refuse_plane(c, "mbs_step"));
   if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
   if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
   if (!R || !p || !slip_coef) return set_err(c, MBS_EINVAL, "R, p and slip_coef are required");
@@ -1572,6 +1580,7 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
   double* Sg = v2s + 5 * n;
   double* Sout = Sg + 5 * n;
   int rc = check_inputs(c, s, {{R, 3 * n}, {hist_valid ? hist : nullptr, 11 * n}}, p, n);
+  if (rc == MBS_OK) rc = check_plane(c, s, R, n);
   const int guess0 = c->prm.guess;
   bool noconv = false;
   if (rc == MBS_OK && hist_valid) {  // resume: the previous step's V, Omega x p and Sigma
@@ -1582,11 +1591,23 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
   for (int k = 0; k < nsteps && rc == MBS_OK; ++k) {
     launch_trap_modes(R, p, k_trap, slip_coef[0], slip_coef[1], slip_coef[2], Fe, v1s, v2s, v3t, n,
                       s);
+    // above a plane the run goes on while every centre is above it (closer than a is contact with
+    // it, as a pair closer than 2a is, and the model has no steric force); each sphere's own image
+    // counts as a neighbour at distance 2h in min_dist
+    double hmin = INFINITY;
+    if (c->prm.plane) {
+      rc = min_height(c, n, R, s, &hmin);
+      if (rc != MBS_OK) break;
+      if (!(hmin > 0.0)) {
+        rc = set_err(c, MBS_EINVAL, "step %d: a sphere centre reached the plane", k);
+        break;
+      }
+    }
     if (min_dist) {
       double md = 0.0;
       rc = check_overlap(c, n, R, s, &md);
       if (rc != MBS_OK) break;
-      min_dist[k] = md;
+      min_dist[k] = fmin(md, 2.0 * hmin);
     }
     mbs_stats one{};
     const bool first = k == 0 && !hist_valid;  // no history yet: one-body guess, Euler step

@@ -112,6 +112,8 @@ void launch_image_out(int kind, const double* R, const double* Fe, const double*
 void launch_image_flow(int kind, const double* X, int64_t m, const double* R, int64_t n, const double* Fe,
                        const double* Te, const double* Sig, const double* v3t, double* U, double* part, const Phys& ph,
                        double plane_z, hipStream_t s);
+// out[0] = min over the n centres of z - plane_z (non-finite heights give -infinity)
+void launch_min_height(const double* R, int64_t n, double plane_z, double* out, hipStream_t s);
 // rows of R [n x 3] with z < zmin (or non-finite) -> atomically added to *cnt
 void launch_count_below(const double* R, int64_t n, double zmin, int* cnt, hipStream_t s);
 // min over pairs of |R_n - R_m|^2 -> out[0] (device), from the cell grid g of R (exact: an

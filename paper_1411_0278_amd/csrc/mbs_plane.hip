@@ -273,6 +273,24 @@ __global__ void k_count_below(const double* __restrict__ R, int64_t n, double zm
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
 }
 
+// out[0] = min over the spheres of (z - zw); a non-finite height counts as -infinity (one workgroup)
+__global__ void __launch_bounds__(256) k_min_height(const double* __restrict__ R, int64_t n, double zw,
+                                                    double* __restrict__ out) {
+  __shared__ double lo[256];
+  double m = INFINITY;
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const double h = R[3 * k + 2] - zw;
+    m = isfinite(h) ? fmin(m, h) : -INFINITY;
+  }
+  lo[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = lo[0];
+}
+
 inline unsigned nblk_im(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
 
 template <int TGT>
@@ -326,6 +344,10 @@ void launch_image_flow(int kind, const double* X, int64_t m, const double* R, in
                        double plane_z, hipStream_t s) {
   if (m <= 0 || n <= 0) return;
   image_launch<kImFlow>(kind, X, m, R, n, Fe, Te, Sig, v3t, 1.0, U, nullptr, part, ph, plane_z, s);
+}
+
+void launch_min_height(const double* R, int64_t n, double plane_z, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_min_height, dim3(1), dim3(256), 0, s, R, n, plane_z, out);
 }
 
 void launch_count_below(const double* R, int64_t n, double zmin, int* cnt, hipStream_t s) {

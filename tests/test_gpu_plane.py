@@ -197,7 +197,8 @@ def test_plane_errors(ctx, kind):
     w, z_w = _workload(n, 1900)
     R, x = _t(w.R), _t(np.ones((n, 5)))
     with _Plane(ctx, w.R[:, 2].min() - 0.5, kind):  # the lowest sphere reaches through the plane
-        for call in (lambda: ctx.mbs_matvec(R, x), lambda: ctx.mbs_solve(R, None, _t(w.v1s), _t(w.v2s))):
+        for call in (lambda: ctx.mbs_matvec(R, x), lambda: ctx.mbs_solve(R, None, _t(w.v1s), _t(w.v2s)),
+                     lambda: ctx.mbs_step(R.clone(), _t(w.p), 0.5, (1.0, 1.0, 1.0), 0.01, 1)):
             with pytest.raises(mbstokes.MbsError) as e:
                 call()
             assert e.value.code == mbstokes.MBS_EINVAL
@@ -206,8 +207,7 @@ def test_plane_errors(ctx, kind):
         with pytest.raises(mbstokes.MbsError) as e:  # a field point below the plane
             ctx.mbs_flow(X, R, x)
         assert e.value.code == mbstokes.MBS_EINVAL
-        refused = [lambda: ctx.mbs_step(R.clone(), _t(w.p), 0.5, (1.0, 1.0, 1.0), 0.01, 1),
-                   lambda: ctx.mbs_matvec_r3(R, _t(np.ones((n, 20)))),
+        refused = [lambda: ctx.mbs_matvec_r3(R, _t(np.ones((n, 20)))),
                    lambda: ctx.mbs_matvec_static(R, x, torch.empty_like(x)),
                    lambda: ctx.mbs_solve_ex(R, None, _t(w.v1s), _t(w.v2s), gam=_t(np.ones((n, 10))))]
         for call in refused:
@@ -218,3 +218,43 @@ def test_plane_errors(ctx, kind):
         with pytest.raises(mbstokes.MbsError):
             ctx.set_params(plane=bad)
     ctx.set_params(plane=0)
+
+
+@KINDS
+def test_plane_stepper_matches_oracle(ctx, kind):
+    """Three Adams-Bashforth steps of trapped swimmers above the plane against the oracle's stepper
+    with the half-space solve; min_dist counts each sphere's own image at twice its height."""
+    from oracle import stepper
+    n = 64
+    w, z_w = _workload(n, 2300, lift=1.2)
+    prm = _prm(w)
+    Rw, pw, _ = stepper.run(w.R, w.p, 0.5, (1.0, 1.0, 1.0), 0.01, 3, prm,
+                            solve=lambda st, pr: ORACLE[kind].solve(st, z_w, pr))
+    R, p = _t(w.R), _t(w.p)
+    with _Plane(ctx, z_w, kind, tol=1e-13):
+        stats, md = ctx.mbs_step(R, p, 0.5, (1.0, 1.0, 1.0), 0.01, 3, order=2, want_min_dist=True)
+    assert _maxrel(R, Rw) < 1e-12 and _maxrel(p, pw) < 1e-12
+    dmin = min(np.linalg.norm(w.R[i] - w.R[j]) for i in range(n) for j in range(i))
+    assert abs(md[0] - min(dmin, 2 * (w.R[:, 2].min() - z_w))) < 1e-12
+
+
+@KINDS
+def test_plane_stepper_stops_when_a_sphere_reaches_the_plane(ctx, kind):
+    """A lone swimmer heading into the plane with a step long enough to carry its centre through it:
+    the first step runs, the second finds the centre below the plane and ends the run with
+    MBS_EINVAL; R holds the state after the first step."""
+    z_w = -3.0
+    R = _t(np.array([[0.0, 0.0, z_w + 1.5]]))
+    p = _t(np.array([[0.0, 0.0, -1.0]]))
+    with _Plane(ctx, z_w, kind):
+        for coef in ((1.0, 0.0, 0.0), (-1.0, 0.0, 0.0)):  # one of the two swims towards the plane
+            R1, p1 = R.clone(), p.clone()
+            try:
+                ctx.mbs_step(R1, p1, 0.0, coef, 20.0, 3, order=1)
+            except mbstokes.MbsError as e:
+                assert e.code == mbstokes.MBS_EINVAL and "reached the plane" in str(e)
+                assert float(R1[0, 2]) <= z_w  # the first step was taken and carried it through
+                break
+        else:
+            raise AssertionError("neither direction reached the plane")
+
