@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import sympy as sp
 
-from oracle import basis, galerkin, greens, krylov, plane, stepper, wall
+from oracle import basis, galerkin, greens, krylov, periodic, plane, stepper, wall
 from paper_1411_0278_amd import inputs
 from tests import sphere_quad
 
@@ -949,4 +949,95 @@ def test_wall_system_is_the_free_one_far_from_the_wall():
     rows = np.array([7, 0, 11])
     y = (wall.system_matrix(w.R, PRM, z_w) @ x.ravel()).reshape(12, 5)[rows]
     assert np.abs(wall.matvec_rows(w.R, x, rows, PRM, z_w) - y).max() < 1e-14 * np.abs(y).max()
+
+
+# ---------------------------------------------------------------- a periodic box (other geometry)
+def test_periodic_operator_chain_reproduces_the_free_space_blocks():
+    """The periodic blocks apply the free-space operator chain to the periodic kernel; written for
+    any kernel, the chain applied to G itself is the free-space block of every target and source."""
+    rng = np.random.default_rng(41)
+    dx = rng.standard_normal((8, 3)) * 2.0 + 0.3
+    r = np.sqrt((dx ** 2).sum(1))
+    for tgt in ("E", "U", "W"):
+        for src in ("F", "T", "S", "D"):
+            M = periodic._block(periodic.kernel("free"), tgt, src, periodic._Rules(False))
+            f = sp.lambdify((greens.x_, greens.y_, greens.z_, greens.r_, greens.a_, greens.P_), M.tolist(), "numpy")
+            raw = f(dx[:, 0], dx[:, 1], dx[:, 2], r, A, 1 / (8 * np.pi * ETA))
+            got = np.array([[np.broadcast_to(np.asarray(v, float), (8,)) for v in row] for row in raw]).transpose(2, 0, 1)
+            want = greens.block(tgt, src, dx, A, ETA)
+            assert np.abs(got - want).max() <= 1e-13 * max(np.abs(want).max(), 1e-300), (tgt, src)
+
+
+def test_ewald_split_sums_back_to_the_oseen_tensor():
+    """G^R(x) + G^K(x) = G(x): the screened real-space tensor plus the inverse transform of the
+    Fourier part (by quadrature in k) is the Oseen tensor."""
+    xi = 0.7
+    kr, wr = np.polynomial.legendre.leggauss(200)
+    kr, wr = 7 * xi * (kr + 1), 7 * xi * wr
+    ct, wt = np.polynomial.legendre.leggauss(60)
+    ph = np.arange(120) * (2 * np.pi / 120)
+    st = np.sqrt(1 - ct ** 2)
+    d = np.stack([np.outer(st, np.cos(ph)), np.outer(st, np.sin(ph)), np.outer(ct, np.ones(120))], -1).reshape(-1, 3)
+    wd = np.outer(wt, np.full(120, 2 * np.pi / 120)).reshape(-1)
+    G0 = periodic.kernel("real")
+    f = sp.lambdify((greens.x_, greens.y_, greens.z_, greens.r_, periodic.ec_, periodic.ex_, periodic.xi_),
+                    [list(row) for row in G0], "numpy")
+    from scipy.special import erfc
+    for x in (np.array([0.3, 0.2, -0.5]), np.array([1.5, -0.7, 0.9]), np.array([0.0, 3.1, 0.4])):
+        GK = np.zeros((3, 3))
+        for k0, w0 in zip(kr, wr):
+            k = k0 * d
+            q = k0 * k0 / (4 * xi * xi)
+            Gh = 8 * np.pi / k0 ** 2 * (np.eye(3)[None] - k[:, :, None] * k[:, None, :] / k0 ** 2) * (1 + q) * np.exp(-q)
+            GK += w0 * k0 ** 2 * np.einsum("p,pij->ij", wd * np.cos(k @ x), Gh)
+        GK /= (2 * np.pi) ** 3
+        r = np.linalg.norm(x)
+        GR = np.array(f(x[0], x[1], x[2], r, erfc(xi * r), np.exp(-(xi * r) ** 2), xi), dtype=float)
+        G = np.eye(3) / r + np.outer(x, x) / r ** 3
+        assert np.abs(GR + GK - G).max() < 1e-12 * np.abs(G).max()
+
+
+def test_periodic_blocks_do_not_depend_on_the_splitting():
+    """The periodic blocks (pairs with all their images, each sphere with its own) are the same for
+    two splitting parameters: what the real-space sum leaves out the Fourier sum supplies."""
+    L = 10.0
+    R = np.random.default_rng(42).uniform(0, L, (4, 3))
+    for tgt, src in (("E", "S"), ("U", "F"), ("W", "T"), ("E", "F"), ("U", "D"), ("W", "S")):
+        A1 = periodic.periodic_blocks(tgt, src, R, periodic.Ewald(L, xi=0.7), A, ETA)
+        A2 = periodic.periodic_blocks(tgt, src, R, periodic.Ewald(L, xi=1.0), A, ETA)
+        assert np.abs(A1 - A2).max() < 2e-9 * np.abs(A1).max(), (tgt, src)
+
+
+def test_lone_sphere_in_a_periodic_box_moves_as_hasimoto_found():
+    """A simple cubic array of spheres (one per box of side L) under a force: V = mu0 F (1 - 2.8372974795 e
+    + (4 pi/3) e^3), e = a/L (Hasimoto, J. Fluid Mech. 5, 317 (1959)); at the l <= 2 truncation
+    nothing else enters (by the lattice's symmetry the force induces no stresslet), so the
+    remainder is rounding. A torque turns it at the rate of the array's own rotlet sum."""
+    mu0 = 1 / (6 * np.pi * ETA * A)
+    for Lb in (10.0, 20.0):
+        e = A / Lb
+        w = inputs.Workload(np.array([[1.0, 2.0, 3.0]]), np.zeros((1, 3)), np.zeros((1, 3)), np.zeros((1, 5)),
+                            None, np.array([[0.0, 1.0, 0.0]]), None, ETA, A)
+        sol = periodic.solve(w, periodic.Ewald(Lb), PRM)
+        assert abs(sol["V"][0, 1] / mu0 - (1 - 2.8372974795 * e + 4 * np.pi / 3 * e ** 3)) < 1e-9
+        assert np.abs(sol["V"][0, [0, 2]]).max() < 1e-13 and np.abs(sol["Sigma"]).max() < 1e-13 * mu0
+
+
+def test_periodic_system_is_symmetric_and_tends_to_the_free_one():
+    """The periodic system is symmetric positive definite; two spheres 3a apart in ever larger
+    boxes approach the free-space pair (their coupling through the images falls off as L^-3)."""
+    L = 12.0
+    R = np.random.default_rng(43).uniform(0, L, (6, 3))
+    Ap = periodic.system_matrix(R, PRM, periodic.Ewald(L))
+    assert np.abs(Ap - Ap.T).max() < 1e-12 * np.abs(Ap).max()
+    assert np.linalg.eigvalsh(0.5 * (Ap + Ap.T)).min() > 0
+    R2 = np.array([[0.0, 0.0, 0.0], [3.0 * A, 0.0, 0.0]])
+    A0 = galerkin.system_matrix(R2, PRM)
+    dev = [np.abs(periodic.system_matrix(R2, PRM, periodic.Ewald(Lb)) - A0).max() / np.abs(A0).max()
+           for Lb in (20.0, 40.0)]
+    assert 6.0 < dev[0] / dev[1] < 10.0  # L^-3
+    x = np.random.default_rng(44).standard_normal((6, 5))
+    rows = np.array([4, 1])
+    y = (Ap @ x.ravel()).reshape(6, 5)[rows]
+    assert np.abs(periodic.matvec_rows(R, x, rows, PRM, periodic.Ewald(L)) - y).max() < 1e-13 * np.abs(y).max()
 
