@@ -1,0 +1,92 @@
+"""The generated periodic arithmetic (csrc/mbs_periodic_gen.h, written by
+paper_1411_0278_amd/periodic_codegen.py from its own form of the Ewald split) against the oracle's
+periodic blocks, on the CPU: the header is built for the host with g++ and evaluated."""
+import ctypes
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+from oracle import periodic  # noqa: E402
+
+ETA, A, XI = 1.0 / (6.0 * np.pi), 1.3, 0.45
+P = 1.0 / (8.0 * np.pi * ETA)
+
+
+@pytest.fixture(scope="module")
+def lib(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("pergen") / "periodic_gen_host.so")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-o", out,
+                    os.path.join(ROOT, "tests", "host", "periodic_gen_host.cpp"),
+                    "-I", os.path.join(ROOT, "paper_1411_0278_amd", "csrc")], check=True)
+    return ctypes.CDLL(out)
+
+
+def _p(a):
+    return np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(ctypes.c_void_p)
+
+
+def _close(got, want, tol=1e-12):
+    return np.abs(got - want).max() <= tol * np.abs(want).max()
+
+
+def test_generated_real_space_matches_oracle(lib):
+    rng = np.random.default_rng(1)
+    n = 50
+    x = rng.standard_normal((n, 3)) * 4.0
+    F, T, S, d = rng.standard_normal((n, 3)), rng.standard_normal((n, 3)), rng.standard_normal((n, 5)), rng.standard_normal((n, 3))
+    args = [_p(P * F), _p(P * T), _p(P * S), _p(A ** 5 / 20 * d)]
+    e, u, w = np.zeros((n, 5)), np.zeros((n, 3)), np.zeros((n, 3))
+    pe, pu, pw = (v.ctypes.data_as(ctypes.c_void_p) for v in (e, u, w))
+    blk = lambda T_, S_: periodic.real_block(T_, S_, x, XI, A, ETA)  # noqa: E731
+    lib.ev_real(0, n, _p(x), ctypes.c_double(XI), ctypes.c_double(A * A), *args, pe, None)
+    assert _close(e, np.einsum("pij,pj->pi", blk("E", "S"), S))
+    lib.ev_real(1, n, _p(x), ctypes.c_double(XI), ctypes.c_double(A * A), *args, pe, None)
+    assert _close(e, sum(np.einsum("pij,pj->pi", blk("E", k), v) for k, v in (("F", F), ("T", T), ("D", d))))
+    lib.ev_real(2, n, _p(x), ctypes.c_double(XI), ctypes.c_double(A * A), *args, pu, pw)
+    src = (("F", F), ("T", T), ("S", S), ("D", d))
+    assert _close(u, sum(np.einsum("pij,pj->pi", blk("U", k), v) for k, v in src))
+    assert _close(w, sum(np.einsum("pij,pj->pi", blk("W", k), v) for k, v in src))
+
+
+def test_generated_fourier_multipliers_match_oracle(lib):
+    rng = np.random.default_rng(2)
+    n = 40
+    k = rng.standard_normal((n, 3)) * 0.8
+    cplx = lambda m: rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))  # noqa: E731
+    F, T, S, d = cplx(3), cplx(3), cplx(5), cplx(3)
+    pre = {"F": P * F, "T": P * T, "S": P * S, "D": A ** 5 / 20 * d}
+    q = np.einsum("pi,pi->p", k, k) / (4 * XI * XI)
+    phi = ((1 + q) * np.exp(-q))[:, None]
+
+    def run(which, width):
+        outr, outi = np.zeros((n, width)), np.zeros((n, width))
+        parts = []
+        for kind in ("F", "T", "S", "D"):
+            parts += [_p(pre[kind].real), _p(pre[kind].imag)]
+        lib.ev_hat(which, n, _p(k), ctypes.c_double(A * A), *parts, outr.ctypes.data_as(ctypes.c_void_p),
+                   outi.ctypes.data_as(ctypes.c_void_p))
+        return (outr + 1j * outi) * phi
+
+    blk = lambda T_, S_: periodic.fourier_block(T_, S_, k, XI, A, ETA)  # noqa: E731
+    want = np.einsum("pij,pj->pi", blk("E", "S"), S)
+    assert _close(run(0, 5), want)
+    want = sum(np.einsum("pij,pj->pi", blk("E", kk), v) for kk, v in (("F", F), ("T", T), ("D", d)))
+    assert _close(run(1, 5), want)
+    src = (("F", F), ("T", T), ("S", S), ("D", d))
+    U = sum(np.einsum("pij,pj->pi", blk("U", kk), v) for kk, v in src)
+    W = sum(np.einsum("pij,pj->pi", blk("W", kk), v) for kk, v in src)
+    assert _close(run(2, 6), np.concatenate([U, W], 1))
+
+
+def test_generated_self_constants_match_oracle(lib):
+    out = np.zeros(4)
+    lib.ev_self(ctypes.c_double(XI), ctypes.c_double(A * A), out.ctypes.data_as(ctypes.c_void_p))
+    for c, (tgt, src, dim) in zip(out, (("E", "S", 5), ("U", "F", 3), ("U", "D", 3), ("W", "T", 3))):
+        want = periodic._smooth_self(tgt, src, XI, A, ETA)
+        scale = A ** 5 / 20 if src == "D" else P
+        assert np.abs(want - c * scale * np.eye(dim)).max() < 1e-12 * abs(c * scale), (tgt, src)
