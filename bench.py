@@ -70,6 +70,7 @@ def parse():
                     help="short run for hardware counters: one launch of every binary64 pass kernel at N")
     ap.add_argument("--skip-rank3", action="store_true", help="skip the traction rank <= 3 timings")
     ap.add_argument("--skip-plane", action="store_true", help="skip the plane (stress-free, no-slip) timings")
+    ap.add_argument("--skip-periodic", action="store_true", help="skip the periodic box timings")
     ap.add_argument("--profile-rank3", action="store_true",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then --steps "
                          "rank <= 3 operator applications at N = 10^4")
@@ -745,6 +746,81 @@ def bench_plane(ctx, a):
     return out
 
 
+def bench_periodic(ctx, a):
+    """Spheres in a periodic cubic box (params.box, Ewald summation) at the benchmark density
+    (0.004 spheres per a^3 on jittered lattice sites): the operator
+    at 10^4 and 10^5 spheres against the unbounded operator of the same spheres, and at 10^4 the
+    right-hand side, outputs and the solve to 1e-10 (binary64, and with the near-field preconditioner
+    at 8a). Default splitting xi = 13/L. Median of 5 launches after 2 warm-ups, HIP events."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+
+    def median_ms(fn, warm=2, reps=5):
+        for _ in range(warm):
+            fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return statistics.median(ts)
+
+    def lattice_positions(n, L, seed):
+        """n sites of a cubic lattice filling the box, chosen at random and jittered so that every
+        minimum-image distance stays >= 2.2a (the lattice is periodic, so across faces too)."""
+        rng = np.random.default_rng(seed)
+        m = int(np.ceil(n ** (1.0 / 3.0) - 1e-9))
+        h = L / m
+        g = (np.arange(m) + 0.5) * h
+        sites = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+        sites = sites[rng.choice(len(sites), n, replace=False)]
+        return sites + rng.uniform(-1.0, 1.0, (n, 3)) * max(0.0, (h - 2.2) / 2)
+
+    out = {"density": 0.004, "splitting": "xi = 13/L, rc = L/2, kmax = 13 xi",
+           "positions": "jittered cubic lattice sites, minimum-image distance >= 2.2a; orientations, slip and "
+                        "forces of the trap workload"}
+    for n, seed in ((10_000, 1), (a.n, a.seed)):
+        L = (n / 0.004) ** (1.0 / 3.0)
+        w = inputs.trap_workload(n, L, seed)
+        w.R = lattice_positions(n, L, seed)
+        d = mbstokes.to_device(w, "cuda:0")
+        x = d["v2s"].contiguous()
+        y = torch.empty_like(x)
+        row = {"n": n, "box": L}
+        ctx.set_params(box=0.0)
+        row["matvec_unbounded_ms"] = round(median_ms(lambda: ctx.mbs_matvec(d["R"], x, y)), 4)
+        ctx.set_params(box=L)
+        row["matvec_ms"] = round(median_ms(lambda: ctx.mbs_matvec(d["R"], x, y)), 4)
+        if n <= 20_000:
+            row["rhs_ms"] = round(median_ms(lambda: ctx.mbs_rhs(d["R"], d["v2s"], None, d["Fe"], None, b=y)), 4)
+            V, W, S = (torch.empty((n, k), dtype=torch.float64, device="cuda:0") for k in (3, 3, 5))
+            row["outputs_ms"] = round(median_ms(lambda: ctx.mbs_outputs(d["R"], x, d["v1s"], d["v2s"], None, d["Fe"], None,
+                                                                          V=V, W=W, S=S)), 4)
+            row["solve"] = {}
+            for vname, cut in (("fp64", 0.0), ("fp64_pc", 8.0)):
+                ctx.set_params(box=L, precision=mbstokes.MBS_FP64, near_cutoff=cut, near_order=2, tol=1e-10,
+                               guess=mbstokes.MBS_GUESS_ZERO)
+                sts = []
+                for k in range(3):
+                    _, _, _, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+                    if k:
+                        sts.append(st)
+                med = sorted(sts, key=lambda t: t["t_total_ms"])[len(sts) // 2]
+                row["solve"][vname] = {"ms": round(med["t_total_ms"], 3), "iters": med["iters"],
+                                       "rel_resid": med["rel_resid"]}
+        ctx.set_params(box=0.0, near_cutoff=0.0, precision=mbstokes.MBS_FP64)
+        out["n%d" % n] = row
+        print(f"bench: periodic n={n} {row.get('matvec_ms')} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def _host_info():
     """Host cores available to this process and the CPU model (from /proc/cpuinfo)."""
     import platform
@@ -1080,6 +1156,8 @@ def main():
         extra["rank3"] = bench_rank3(ctx, a)
     if not a.skip_plane:
         extra["plane"] = bench_plane(ctx, a)
+    if not a.skip_periodic:
+        extra["periodic"] = bench_periodic(ctx, a)
     if a.scale_n > 0:
         extra["scale"] = bench_scale(a)
     head = variants[a.headline]

@@ -159,6 +159,26 @@ typedef struct mbs_params {
                             other values are MBS_EINVAL */
   int32_t reserved0;
   double  plane_z;       /* height of the plane (plane != 0) */
+  double  box;           /* > 0: the spheres fill a periodic cubic box of this side (the paper's remark
+                            that periodic domains follow from the periodic Green's function, whose
+                            direct sum converges only conditionally, Discussion). Hasimoto's
+                            procedure: the fluid's mean velocity over the box is zero (the k = 0
+                            Fourier mode is left out; a net force on the spheres is balanced by a
+                            mean pressure gradient), and the periodic Oseen tensor is summed by
+                            Ewald's method: a screened real-space part over the minimum image within
+                            rc = 6.5/xi <= box/2 and a Fourier part over the reciprocal lattice up to
+                            |k| = 13 xi, each sphere's own images through the Fourier sum less its
+                            smooth self part; binary64 in every pass (truncation below 1e-13 of the
+                            blocks). Positions may lie anywhere (they are taken modulo the box).
+                            Applies to mbs_solve(_ex), mbs_matvec, mbs_rhs(_ex), mbs_outputs(_ex)
+                            without higher slip modes; the flow at field points, the stepper, the
+                            batched solver, the rank <= 3 entry points, the warm-start calls and
+                            mbs_matvec_static refuse it (MBS_EUNSUPPORTED); exclusive with plane
+                            (MBS_EINVAL). The near-field preconditioner keeps its unwrapped
+                            neighbour lists. 0 = unbounded fluid (default) */
+  double  ewald_xi;      /* Ewald splitting parameter xi (box > 0): 0 = 13/box (the real-space cutoff
+                            then reaches box/2); larger values move work to the Fourier sum (more
+                            wave vectors, fewer real-space pairs); xi * box < 13 is MBS_EINVAL */
 } mbs_params;
 
 typedef struct mbs_stats {
@@ -184,7 +204,7 @@ typedef struct mbs_ctx mbs_ctx;
 
 /* Fill *prm with the defaults: eta = 1/(6 pi), a = 1, tol = 1e-10, c = 1, inner_tol = 1e-5,
    lmax = 2, max_iter = 300, restart = 30, MBS_FP64, MBS_GUESS_ZERO, no overlap check, tile 0,
-   graph 1, near_order 2, spatial_order 0, no plane. */
+   graph 1, near_order 2, spatial_order 0, no plane, no box. */
 void mbs_default_params(mbs_params* prm);
 
 /* Create a context on HIP device `device`. *ctx receives the handle (NULL on failure).

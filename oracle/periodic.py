@@ -264,6 +264,9 @@ def periodic_blocks(target, source, R, ew: Ewald, a, eta, rows=None):
     kv = ew.kvecs()
     Mk = fourier_block(target, source, kv, ew.xi, a, eta)  # [nk, dT, dX]
     V = ew.L ** 3
+    Mf = Mk.reshape(len(kv), dT * dX)
+    Ep = np.exp(1j * (R @ kv.T))   # [n, nk]
+    Em = np.conj(Ep)
     chunk = max(1, 200000 // max(1, n * len(nvec)))
     for c0 in range(0, len(rows), chunk):
         rr = rows[c0:c0 + chunk]
@@ -276,10 +279,11 @@ def periodic_blocks(target, source, R, ew: Ewald, a, eta, rows=None):
         if ia.size:
             blk = real_block(target, source, s[sel], ew.xi, a, eta)
             np.add.at(out, (c0 + ia, ib), blk)
-        # Fourier space: every sphere, the receiver itself included
+        # Fourier space: every sphere, the receiver itself included; exp(i k.(R_i - R_m)) =
+        # exp(i k.R_i) exp(-i k.R_m) on the reciprocal lattice (a wrap by L changes no phase)
+        for d in range(dT * dX):
+            out[c0:c0 + len(rr), :, d // dX, d % dX] += (((Ep[rr] * Mf[None, :, d]) @ Em.T) / V).real
         for q, i in enumerate(rr):
-            ph = np.exp(1j * (dx[q] @ kv.T))  # [n, nk]
-            out[c0 + q] += (np.einsum("mk,kij->mij", ph, Mk) / V).real
             out[c0 + q, i] -= _smooth_self(target, source, ew.xi, a, eta)
     return out.transpose(0, 2, 1, 3).reshape(len(rows) * dT, n * dX)
 

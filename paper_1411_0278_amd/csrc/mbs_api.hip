@@ -81,6 +81,9 @@ struct mbs_ctx {
   DevBuf grid;
   // traction ranks <= 3: Krylov basis, residual and solution vectors, pass partial sums
   DevBuf r3;
+  DevBuf per_kv;  // the periodic box's half-lattice wave vectors [per_K x 3]
+  int per_K = 0;
+  double per_L = 0.0, per_kmax = 0.0;
   // a solve in the Morton order of the centres: the permutation and the reordered inputs/outputs
   DevBuf ord;
   // single-configuration GMRES: Arnoldi steps captured as graphs (per precision), see step_graphs
@@ -178,6 +181,11 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
     return set_err(c, MBS_EINVAL, "spatial_order must be -1, 0 or 1");
   if (p->plane < 0 || p->plane > 2) return set_err(c, MBS_EINVAL, "plane must be 0, 1 or 2");
   if (p->plane && !isfinite(p->plane_z)) return set_err(c, MBS_EINVAL, "plane_z must be finite");
+  if (!(p->box >= 0.0) || !isfinite(p->box)) return set_err(c, MBS_EINVAL, "box must be finite and >= 0");
+  if (!(p->ewald_xi >= 0.0) || !isfinite(p->ewald_xi)) return set_err(c, MBS_EINVAL, "ewald_xi must be finite and >= 0");
+  if (p->box > 0.0 && p->ewald_xi > 0.0 && p->ewald_xi * p->box < 13.0)
+    return set_err(c, MBS_EINVAL, "ewald_xi * box must be at least 13 (real-space cutoff within box/2)");
+  if (p->box > 0.0 && p->plane) return set_err(c, MBS_EINVAL, "box and plane exclude each other");
   return MBS_OK;
 }
 
@@ -191,6 +199,28 @@ void apply_tiles(mbs_ctx* c) {
 }
 
 // Workspace for n spheres and restart m.
+// the periodic box (params.box): splitting parameter, cutoffs and the wave vectors on the device
+bool periodic(const mbs_ctx* c) { return c->prm.box > 0.0; }
+double per_xi(const mbs_ctx* c) { return c->prm.ewald_xi > 0.0 ? c->prm.ewald_xi : 13.0 / c->prm.box; }
+PerBox per_box(const mbs_ctx* c) {
+  const double xi = per_xi(c);
+  return PerBox{c->prm.box, xi, std::min(6.5 / xi, 0.5 * c->prm.box), c->per_K, c->per_kv.p};
+}
+// (re)builds the wave-vector list when the box or the splitting changed (outside any graph capture)
+int per_prepare(mbs_ctx* c) {
+  const double kmax = 13.0 * per_xi(c);
+  if (c->per_kv.p && c->per_L == c->prm.box && c->per_kmax == kmax) return MBS_OK;
+  const std::vector<double> kv = per_kvecs(c->prm.box, kmax);
+  const int K = (int)(kv.size() / 3);
+  if (K < 1) return set_err(c, MBS_EINVAL, "no wave vector below the Fourier cutoff");
+  CHK(ensure(c, c->per_kv, kv.size()));
+  HIPCHK(c, hipMemcpy(c->per_kv.p, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice));
+  c->per_K = K;
+  c->per_L = c->prm.box;
+  c->per_kmax = kmax;
+  return MBS_OK;
+}
+
 int ensure_ws(mbs_ctx* c, int64_t n) {
   const int m = c->prm.restart;
   const int64_t len = 5 * n;
@@ -200,7 +230,11 @@ int ensure_ws(mbs_ctx* c, int64_t n) {
   CHK(ensure(c, c->b, len));
   CHK(ensure(c, c->xs, len));
   CHK(ensure(c, c->dlt, len));
-  const int64_t pe = std::max<int64_t>(part_elems_max(n), c->prm.plane ? image_part_elems(n, n) : 0);
+  int64_t pe = std::max<int64_t>(part_elems_max(n), c->prm.plane ? image_part_elems(n, n) : 0);
+  if (periodic(c)) {
+    CHK(per_prepare(c));
+    pe = std::max<int64_t>(pe, per_part_elems(n, c->per_K));
+  }
   CHK(ensure(c, c->part, (size_t)pe));
   CHK(ensure(c, c->srcbuf, (size_t)8 * n));
   CHK(ensure(c, c->orig, 4));
@@ -282,7 +316,10 @@ void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x,
     c->op_prec[slot] = prec;
     (void)hipEventRecord(c->opev[2 * slot], s);
   }
-  if (prec == MBS_FP64) {
+  if (periodic(c)) {  // the Ewald sums (binary64 in either precision)
+    launch_per_op(R, x, y, c->part.p, n, per_box(c), c->ph, s);
+    (prec == MBS_FP64 ? cnt.f64 : cnt.f32)++;
+  } else if (prec == MBS_FP64) {
     launch_p2(false, R, x, y, c->part.p, c->srcbuf.p, c->orig.p, n, c->ph, c->tile64, s);
     cnt.f64++;
   } else {
@@ -306,6 +343,14 @@ void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x,
 void apply_op_out(mbs_ctx* c, int64_t n, const double* R, const double* x, double* y, OutPass& o,
                   hipStream_t s, Counters& cnt) {
   (void)hipEventRecord(c->ev[4], s);
+  if (periodic(c)) {  // operator and outputs as two Ewald passes
+    launch_per_op(R, x, y, c->part.p, n, per_box(c), c->ph, s);
+    launch_per_out(R, o.v1s, o.v2s, o.v3t, o.Fe, o.Te, x, o.V, o.W, o.S, c->part.p, n, per_box(c), c->ph, s);
+    (void)hipEventRecord(c->ev[5], s);
+    cnt.pairs += 2.0 * (double)n * (double)(n - 1);
+    o.valid = true;
+    return;
+  }
   launch_p23(R, o.v1s, o.v2s, o.v3t, o.Fe, o.Te, x, y, o.V, o.W, o.S, c->part.p, n, c->ph, c->tile_pass, s);
   if (c->prm.plane) {
     if (c->prm.plane == 1)
@@ -377,7 +422,8 @@ StepGraphs* step_graphs(mbs_ctx* c, int prec, int64_t n, const double* R, bool p
       (uintptr_t)c->H.p, (uintptr_t)c->small.p, (uintptr_t)c->dpart.p, (uintptr_t)c->part.p,
       (uintptr_t)c->srcbuf.p, (uintptr_t)c->orig.p, (uintptr_t)c->near.p, (uintptr_t)near_order(c),
       dbits(c->ph.P), dbits(c->ph.a2),
-      dbits(c->ph.gamma), dbits(c->ph.inv_gamma), (uintptr_t)c->prm.plane, dbits(c->prm.plane_z)};
+      dbits(c->ph.gamma), dbits(c->ph.inv_gamma), (uintptr_t)c->prm.plane, dbits(c->prm.plane_z),
+      dbits(c->prm.box), dbits(c->prm.ewald_xi), (uintptr_t)c->per_kv.p, (uintptr_t)c->per_K};
   StepGraphs& G = c->sgraph[prec == MBS_FP64 ? 0 : 1];
   if (key == G.key) return &G;
   G.reset();
@@ -558,6 +604,12 @@ int check_plane(mbs_ctx* c, hipStream_t s, const double* R, int64_t n) {
 // entry points that do not take the plane
 int refuse_plane(mbs_ctx* c, const char* what) {
   if (c->prm.plane) return set_err(c, MBS_EUNSUPPORTED, "%s does not support params.plane", what);
+  if (c->prm.box > 0.0) return set_err(c, MBS_EUNSUPPORTED, "%s does not support params.box", what);
+  return MBS_OK;
+}
+// entry points that take the plane but not the periodic box
+int refuse_box(mbs_ctx* c, const char* what) {
+  if (c->prm.box > 0.0) return set_err(c, MBS_EUNSUPPORTED, "%s does not support params.box", what);
   return MBS_OK;
 }
 
@@ -810,7 +862,10 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
     launch_axpby(-c->ph.c_slip * c->ph.gamma, v2s ? v2s : c->zeros.p, 0.0, c->xs.p, len, s);
     HIPCHK(c, hipEventRecord(c->ev[1], s));
     HIPCHK(c, hipEventRecord(c->ev[2], s));
-    launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
+    if (periodic(c))
+      launch_per_out(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, per_box(c), c->ph, s);
+    else
+      launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
     if (high) launch_high(1, R, n, R, n, hi, V, W, c->part.p, hsplit, c->ph, c->tile_pass, s);
     if (c->prm.plane)
       launch_image_out(c->prm.plane, R, Fe, Te, c->xs.p, v3t, V, W, c->part.p, n, c->ph, c->prm.plane_z, s);
@@ -826,7 +881,10 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
   }
   if (c->prm.near_cutoff > 0.0) CHK(near_prepare(c, n, R, s));
   // right-hand side
-  launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
+  if (periodic(c))
+    launch_per_rhs(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, per_box(c), c->ph, s);
+  else
+    launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
   cnt.pairs += (double)n * (double)(n - 1);
   if (c->prm.plane) {
     launch_image_rhs(c->prm.plane, R, Fe, Te, v3t, c->b.p, c->part.p, n, c->ph, c->prm.plane_z, s);
@@ -928,7 +986,10 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
   HIPCHK(c, hipEventRecord(c->ev[2], s));
   const bool fused = op.valid;  // outputs already formed with the final residual
   if (!fused) {
-    launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
+    if (periodic(c))
+      launch_per_out(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, per_box(c), c->ph, s);
+    else
+      launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
     cnt.pairs += (double)n * (double)(n - 1);
     if (c->prm.plane) {
       launch_image_out(c->prm.plane, R, Fe, Te, c->xs.p, v3t, V, W, c->part.p, n, c->ph, c->prm.plane_z, s);
@@ -1259,6 +1320,8 @@ void mbs_default_params(mbs_params* p) {
   p->spatial_order = 0;
   p->plane = 0;
   p->plane_z = 0.0;
+  p->box = 0.0;
+  p->ewald_xi = 0.0;
 }
 
 int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {
@@ -1307,7 +1370,7 @@ void mbs_destroy(mbs_ctx* c) {
                     &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig, &c->near, &c->zt,
                     &c->nt, &c->stepstate,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
-                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->ord, &c->r3,
+                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->ord, &c->r3, &c->per_kv,
                     &c->bat, &c->btune};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
@@ -1380,8 +1443,10 @@ int mbs_solve_ex(mbs_ctx* c, int64_t n, const double* R, const double* p, const 
   CHK(check_inputs(c, s, {{R, 3 * n}, {v1s, 3 * n}, {v2s, 5 * n}, {v3t, 3 * n}, {Fe, 3 * n},
                           {Te, 3 * n}, {sigma0, s0len}, {hi.gam, 10 * n}, {hi.psi, 5 * n}, {hi.lam, 10 * n}},
                    p, n));
-  if (c->prm.plane && high_mask(hi))
-    return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane");
+  if ((c->prm.plane || periodic(c)) && high_mask(hi))
+    return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane or params.box");
+  if (periodic(c) && c->prm.guess == MBS_GUESS_LEARNED)
+    return set_err(c, MBS_EUNSUPPORTED, "the learned guess does not support params.box");
   CHK(check_plane(c, s, R, n));
   if (c->prm.check_overlap) {
     double md = 0.0;
@@ -1462,10 +1527,13 @@ int mbs_rhs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const 
                       {"Te", Te, 3 * n}, {"gam", hi.gam, 10 * n}, {"psi", hi.psi, 5 * n}, {"lam", hi.lam, 10 * n}}));
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
-  if (c->prm.plane && high_mask(hi))
-    return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane");
+  if ((c->prm.plane || periodic(c)) && high_mask(hi))
+    return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane or params.box");
   CHK(check_plane(c, s, R, n));
-  launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, c->ph, c->tile_pass, s);
+  if (periodic(c))
+    launch_per_rhs(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, per_box(c), c->ph, s);
+  else
+    launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, c->ph, c->tile_pass, s);
   if (high_mask(hi))
     launch_high(0, R, n, R, n, hi, b, nullptr, c->part.p, high_split(n, n, c->tile_pass), c->ph, c->tile_pass, s);
   if (c->prm.plane) launch_image_rhs(c->prm.plane, R, Fe, Te, v3t, b, c->part.p, n, c->ph, c->prm.plane_z, s);
@@ -1493,11 +1561,13 @@ int mbs_outputs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v1s, co
                       {"psi", hi.psi, 5 * n}, {"lam", hi.lam, 10 * n}}));
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));
-  if (c->prm.plane && high_mask(hi))
-    return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane");
+  if ((c->prm.plane || periodic(c)) && high_mask(hi))
+    return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane or params.box");
   CHK(check_plane(c, s, R, n));
-  launch_p3(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, c->ph,
-            c->tile_pass, s);
+  if (periodic(c))
+    launch_per_out(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, per_box(c), c->ph, s);
+  else
+    launch_p3(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
   if (high_mask(hi))
     launch_high(1, R, n, R, n, hi, V, W, c->part.p, high_split(n, n, c->tile_pass), c->ph, c->tile_pass, s);
   if (c->prm.plane)
@@ -1517,6 +1587,7 @@ int mbs_flow_ex(mbs_ctx* c, int64_t m, const double* X, int64_t n, const double*
                 const double* Te, const double* Sigma, const double* v3t, const mbs_slip_ex* ex, double* U,
                 void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_box(c, "the flow at field points"));
   if (m < 1 || n < 1) return set_err(c, MBS_EINVAL, "m and n must be >= 1");
   if (m > (int64_t)INT32_MAX / 12 || n > (int64_t)INT32_MAX / 10) return set_err(c, MBS_EINVAL, "m or n too large");
   if (!X || !R || !Sigma || !U) return set_err(c, MBS_EINVAL, "X, R, Sigma and U are required");
@@ -1554,6 +1625,7 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
              double dt, int32_t nsteps, int32_t order, double* hist, int32_t hist_valid,
              mbs_stats* per_step, double* min_dist, void* stream) {
   CHK(begin_call(c));
+  CHK(refuse_box(c, "mbs_step"));
   if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
   if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
   if (!R || !p || !slip_coef) return set_err(c, MBS_EINVAL, "R, p and slip_coef are required");

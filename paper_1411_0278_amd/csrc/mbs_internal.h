@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace mbs {
 
 // Physical constants of one problem, derived once on the host.
@@ -112,6 +114,24 @@ void launch_image_out(int kind, const double* R, const double* Fe, const double*
 void launch_image_flow(int kind, const double* X, int64_t m, const double* R, int64_t n, const double* Fe,
                        const double* Te, const double* Sig, const double* v3t, double* U, double* part, const Phys& ph,
                        double plane_z, hipStream_t s);
+// Spheres in a periodic cubic box of side L: Ewald summation (real space within rc <= L/2, the K
+// half-lattice wave vectors kv [K x 3] on the device, 0 < |k| <= kmax). part: scratch of
+// per_part_elems(n, K) doubles. Each pass writes its output completely: the operator
+// y = x/gamma - E_per[x], the right-hand side b = E_per[F, T, d] - c s, the outputs V, W, S.
+struct PerBox {
+  double L, xi, rc;
+  int K;
+  const double* kv;
+};
+std::vector<double> per_kvecs(double L, double kmax);
+int64_t per_part_elems(int64_t n, int K);
+void launch_per_op(const double* R, const double* x, double* y, double* part, int64_t n, const PerBox& g,
+                   const Phys& ph, hipStream_t s);
+void launch_per_rhs(const double* R, const double* v2s, const double* v3t, const double* Fe, const double* Te,
+                    double* b, double* part, int64_t n, const PerBox& g, const Phys& ph, hipStream_t s);
+void launch_per_out(const double* R, const double* v1s, const double* v2s, const double* v3t, const double* Fe,
+                    const double* Te, const double* Sig, double* V, double* W, double* S, double* part, int64_t n,
+                    const PerBox& g, const Phys& ph, hipStream_t s);
 // out[0] = min over the n centres of z - plane_z (non-finite heights give -infinity)
 void launch_min_height(const double* R, int64_t n, double plane_z, double* out, hipStream_t s);
 // rows of R [n x 3] with z < zmin (or non-finite) -> atomically added to *cnt

@@ -1,0 +1,380 @@
+// Spheres in a periodic cubic box (gfx950): Ewald summation of the periodic Oseen tensor.
+//
+// The paper notes that periodic domains follow from the periodic Green's function, whose direct
+// sum converges only conditionally. Hasimoto's procedure fixes it: zero mean velocity over the box
+// (the k = 0 Fourier mode left out, a net force balanced by a mean pressure gradient), the tensor
+// split with a parameter xi into a screened real-space part, summed over the images within a
+// cutoff rc <= L/2 (so the minimum image is the only one), and a smooth Fourier part summed over the
+// reciprocal lattice k = 2 pi n / L, 0 < |k| <= kmax. A sphere's own images enter through the
+// Fourier sum (which runs over every sphere, the receiver included) minus the smooth part of its own
+// flow at its centre, a constant per block (a multiple of the identity, or zero by parity).
+//
+// One pass (operator, right-hand side or outputs) is five launches:
+//   k_per_real    receiver per thread, source records staged through LDS tiles, the minimum-image
+//                 separation inside rc evaluated with the generated screened blocks; grid.y chunks
+//                 of the sources, partial sums per chunk;
+//   k_per_sf      wave vector per thread: structure factors sum_m c_m exp(-i k.R_m) of the source
+//                 coefficients (5, 9 or 14 of them), grid.y chunks of the sources;
+//   k_per_mult    wave vector per thread: the chunks added in order, the generated Fourier
+//                 multiplier applied, times 2/L^3 (k and -k together) and the splitting factor;
+//   k_per_recip   receiver per thread, wave vectors and their complex targets staged through LDS:
+//                 Re sum_k exp(i k.R_n) T(k); grid.y chunks of the wave vectors;
+//   k_per_finish  the chunks added in order, the self constants and the one-body terms.
+// Every sum runs in a fixed order (bitwise reproducible). The arithmetic is binary64 throughout.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "mbs_device.h"
+#include "mbs_internal.h"
+#include "mbs_periodic_gen.h"
+
+namespace mbs {
+namespace {
+
+constexpr int kPBlk = 128;   // receivers per workgroup (real space, reciprocal sum)
+constexpr int kPTJ = 64;     // source records per LDS tile
+constexpr int kPKBlk = 64;   // wave vectors per workgroup (structure factors, multipliers)
+constexpr int kPKT = 64;     // wave vectors per LDS tile of the reciprocal sum
+
+enum { kPOp = 0, kPRhs = 1, kPOut = 2 };
+constexpr int pw(int t) { return t == kPOut ? 6 : 5; }   // target width
+constexpr int pnc(int t) { return t == kPOp ? 5 : (t == kPRhs ? 9 : 14); }  // source coefficients
+
+// source record: centre and pre-scaled coefficients (f = P F, t = P T, s = P Sigma, q = (a^5/20) d)
+struct alignas(16) RecP {
+  double x, y, z, f[3], t[3], s[5], q[3], pad;
+};
+
+template <int TGT>
+__device__ __forceinline__ RecP make_rec(const double* __restrict__ R, const double* __restrict__ Fe,
+                                         const double* __restrict__ Te, const double* __restrict__ Sig,
+                                         const double* __restrict__ D, int j, double P, double a5_20) {
+  RecP r;
+  r.x = R[3 * (int64_t)j];
+  r.y = R[3 * (int64_t)j + 1];
+  r.z = R[3 * (int64_t)j + 2];
+  for (int c = 0; c < 3; ++c) {
+    r.f[c] = (TGT != kPOp && Fe) ? P * Fe[3 * (int64_t)j + c] : 0.0;
+    r.t[c] = (TGT != kPOp && Te) ? P * Te[3 * (int64_t)j + c] : 0.0;
+    r.q[c] = (TGT != kPOp && D) ? a5_20 * D[3 * (int64_t)j + c] : 0.0;
+  }
+  for (int c = 0; c < 5; ++c) r.s[c] = (TGT != kPRhs && Sig) ? P * Sig[5 * (int64_t)j + c] : 0.0;
+  r.pad = 0.0;
+  return r;
+}
+
+// the source coefficients of a record in the order the structure factors hold them
+template <int TGT>
+__device__ __forceinline__ void coeffs(const RecP& r, double* v) {
+  if (TGT == kPOp) {
+    for (int c = 0; c < 5; ++c) v[c] = r.s[c];
+  } else if (TGT == kPRhs) {
+    for (int c = 0; c < 3; ++c) {
+      v[c] = r.f[c];
+      v[3 + c] = r.t[c];
+      v[6 + c] = r.q[c];
+    }
+  } else {
+    for (int c = 0; c < 3; ++c) {
+      v[c] = r.f[c];
+      v[3 + c] = r.t[c];
+      v[11 + c] = r.q[c];
+    }
+    for (int c = 0; c < 5; ++c) v[6 + c] = r.s[c];
+  }
+}
+
+__device__ __forceinline__ double wrap(double d, double L, double invL) { return d - L * rint(d * invL); }
+
+template <int TGT>
+__global__ void __launch_bounds__(kPBlk)
+    k_per_real(const double* __restrict__ R, int n, const double* __restrict__ Fe, const double* __restrict__ Te,
+               const double* __restrict__ Sig, const double* __restrict__ D, int chunk, double L, double invL,
+               double rc2, double xi, double a2, double P, double a5_20, double* __restrict__ part) {
+  __shared__ RecP tile[kPTJ];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const double xi0 = R[3 * (int64_t)ii], yi0 = R[3 * (int64_t)ii + 1], zi0 = R[3 * (int64_t)ii + 2];
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  constexpr int W = pw(TGT);
+  double acc[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) acc[c] = 0.0;
+  for (int jt = j0; jt < j1; jt += kPTJ) {
+    const int cnt = min(kPTJ, j1 - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) tile[t] = make_rec<TGT>(R, Fe, Te, Sig, D, jt + t, P, a5_20);
+    __syncthreads();
+    for (int jj = 0; jj < cnt; ++jj) {
+      const RecP& s = tile[jj];
+      const double dx = wrap(xi0 - s.x, L, invL), dy = wrap(yi0 - s.y, L, invL), dz = wrap(zi0 - s.z, L, invL);
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      if (r2 < rc2 && r2 > 0.0) {  // the receiver itself (and its images, beyond rc) excluded
+        const double r = sqrt(r2);
+        const double ri = 1.0 / r, ec = erfc(xi * r), ex = exp(-xi * xi * r2);
+        if (TGT == kPOp) per_real_strain_s(dx, dy, dz, ri, ec, ex, xi, a2, s.s, acc);
+        if (TGT == kPRhs) per_real_strain_ftq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.q, acc);
+        if (TGT == kPOut) per_real_motion_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc, acc + 3);
+      }
+    }
+  }
+  if (i >= n) return;
+  double* o = part + ((int64_t)blockIdx.y * n + i) * W;
+#pragma unroll
+  for (int c = 0; c < W; ++c) o[c] = acc[c];
+}
+
+// structure factors of one source chunk: sf[(chunk * K + k) * 2NC] = (re[NC], im[NC])
+template <int TGT>
+__global__ void __launch_bounds__(kPKBlk)
+    k_per_sf(const double* __restrict__ R, int n, const double* __restrict__ Fe, const double* __restrict__ Te,
+             const double* __restrict__ Sig, const double* __restrict__ D, const double* __restrict__ kv, int K,
+             int chunk, double P, double a5_20, double* __restrict__ sf) {
+  __shared__ RecP tile[kPTJ];
+  constexpr int NC = pnc(TGT);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int kk = k < K ? k : K - 1;
+  const double k1 = kv[3 * (int64_t)kk], k2 = kv[3 * (int64_t)kk + 1], k3 = kv[3 * (int64_t)kk + 2];
+  const int j0 = blockIdx.y * chunk;
+  const int j1 = min(n, j0 + chunk);
+  double re[NC], im[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) re[c] = im[c] = 0.0;
+  for (int jt = j0; jt < j1; jt += kPTJ) {
+    const int cnt = min(kPTJ, j1 - jt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) tile[t] = make_rec<TGT>(R, Fe, Te, Sig, D, jt + t, P, a5_20);
+    __syncthreads();
+    for (int jj = 0; jj < cnt; ++jj) {
+      const RecP& s = tile[jj];
+      double sn, cs;
+      sincos(fma(k1, s.x, fma(k2, s.y, k3 * s.z)), &sn, &cs);
+      double v[NC];
+      coeffs<TGT>(s, v);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {  // exp(-i theta) = cos - i sin
+        re[c] = fma(v[c], cs, re[c]);
+        im[c] = fma(-v[c], sn, im[c]);
+      }
+    }
+  }
+  if (k >= K) return;
+  double* o = sf + ((int64_t)blockIdx.y * K + k) * (2 * NC);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    o[c] = re[c];
+    o[NC + c] = im[c];
+  }
+}
+
+// T[k * 2W] = (2 / L^3) phi(k) M(k) S(k): the chunks' structure factors added in order, the
+// generated multiplier applied
+template <int TGT>
+__global__ void __launch_bounds__(kPKBlk)
+    k_per_mult(const double* __restrict__ sf, int nchunk, const double* __restrict__ kv, int K, double xi, double a2,
+               double scale, double* __restrict__ T) {
+  constexpr int NC = pnc(TGT), W = pw(TGT);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double v[2 * NC];
+#pragma unroll
+  for (int c = 0; c < 2 * NC; ++c) v[c] = 0.0;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const double* p = sf + ((int64_t)ch * K + k) * (2 * NC);
+#pragma unroll
+    for (int c = 0; c < 2 * NC; ++c) v[c] += p[c];
+  }
+  const double k1 = kv[3 * (int64_t)k], k2 = kv[3 * (int64_t)k + 1], k3 = kv[3 * (int64_t)k + 2];
+  const double ksq = fma(k1, k1, fma(k2, k2, k3 * k3));
+  const double ik2 = 1.0 / ksq;
+  const double q = ksq / (4.0 * xi * xi);
+  const double g = scale * (1.0 + q) * exp(-q);
+  double tr[W], ti[W];
+  const double* re = v;
+  const double* im = v + NC;
+  if (TGT == kPOp) per_hat_strain_s(k1, k2, k3, ik2, a2, re, im, tr, ti);
+  if (TGT == kPRhs) per_hat_strain_ftq(k1, k2, k3, ik2, a2, re, im, re + 3, im + 3, re + 6, im + 6, tr, ti);
+  if (TGT == kPOut)
+    per_hat_motion_ftsq(k1, k2, k3, ik2, a2, re, im, re + 3, im + 3, re + 6, im + 6, re + 11, im + 11, tr, ti);
+  double* o = T + (int64_t)k * (2 * W);
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    o[c] = g * tr[c];
+    o[W + c] = g * ti[c];
+  }
+}
+
+// part[(chunk * n + i) * W] = Re sum_{k in chunk} exp(i k.R_i) T(k)
+template <int TGT>
+__global__ void __launch_bounds__(kPBlk)
+    k_per_recip(const double* __restrict__ R, int n, const double* __restrict__ kv, const double* __restrict__ T,
+                int K, int chunk, double* __restrict__ part) {
+  constexpr int W = pw(TGT);
+  __shared__ double tk[kPKT][3 + 2 * W];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const double x = R[3 * (int64_t)ii], y = R[3 * (int64_t)ii + 1], z = R[3 * (int64_t)ii + 2];
+  const int k0 = blockIdx.y * chunk;
+  const int k1e = min(K, k0 + chunk);
+  double acc[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) acc[c] = 0.0;
+  for (int kt = k0; kt < k1e; kt += kPKT) {
+    const int cnt = min(kPKT, k1e - kt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt * (3 + 2 * W); t += blockDim.x) {
+      const int q = t / (3 + 2 * W), c = t % (3 + 2 * W);
+      tk[q][c] = c < 3 ? kv[3 * (int64_t)(kt + q) + c] : T[(int64_t)(kt + q) * (2 * W) + (c - 3)];
+    }
+    __syncthreads();
+    for (int q = 0; q < cnt; ++q) {
+      double sn, cs;
+      sincos(fma(tk[q][0], x, fma(tk[q][1], y, tk[q][2] * z)), &sn, &cs);
+#pragma unroll
+      for (int c = 0; c < W; ++c) acc[c] = fma(tk[q][3 + c], cs, fma(-tk[q][3 + W + c], sn, acc[c]));
+    }
+  }
+  if (i >= n) return;
+  double* o = part + ((int64_t)blockIdx.y * n + i) * W;
+#pragma unroll
+  for (int c = 0; c < W; ++c) o[c] = acc[c];
+}
+
+// the chunks added in order, then
+//   operator:  y = x (1/gamma + P c_es) - real - recip                  (out = y)
+//   rhs:       b = real + recip - c_slip v2s                             (out = b)
+//   outputs:   V = real + recip + mu_t F - P c_uf F - (a^5/20) c_ud d - v1s, W = real + recip + mu_r T
+//              - P c_wt T, S = Sigma + slip_S v2s                        (out = V, out2 = W, out3 = S)
+template <int TGT>
+__global__ void k_per_finish(const double* __restrict__ preal, int nreal, const double* __restrict__ precip,
+                             int nrecip, int n, const double* __restrict__ X, const double* __restrict__ Fe,
+                             const double* __restrict__ Te, const double* __restrict__ D,
+                             const double* __restrict__ v1s, const double* __restrict__ v2s, double self0,
+                             double self1, double self2, const Phys ph, double* __restrict__ out,
+                             double* __restrict__ out2, double* __restrict__ out3) {
+  constexpr int W = pw(TGT);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc[W];
+  for (int c = 0; c < W; ++c) acc[c] = 0.0;
+  for (int ch = 0; ch < nreal; ++ch)
+    for (int c = 0; c < W; ++c) acc[c] += preal[((int64_t)ch * n + i) * W + c];
+  for (int ch = 0; ch < nrecip; ++ch)
+    for (int c = 0; c < W; ++c) acc[c] += precip[((int64_t)ch * n + i) * W + c];
+  if (TGT == kPOp) {
+    for (int c = 0; c < 5; ++c) out[5 * (int64_t)i + c] = X[5 * (int64_t)i + c] * (ph.inv_gamma + self0) - acc[c];
+  } else if (TGT == kPRhs) {
+    for (int c = 0; c < 5; ++c) out[5 * (int64_t)i + c] = acc[c] - (v2s ? ph.c_slip * v2s[5 * (int64_t)i + c] : 0.0);
+  } else {
+    for (int c = 0; c < 3; ++c) {
+      const double F = Fe ? Fe[3 * (int64_t)i + c] : 0.0, Tq = Te ? Te[3 * (int64_t)i + c] : 0.0;
+      const double d = D ? D[3 * (int64_t)i + c] : 0.0;
+      out[3 * (int64_t)i + c] = acc[c] + (ph.mu_t - self0) * F - self1 * d - (v1s ? v1s[3 * (int64_t)i + c] : 0.0);
+      out2[3 * (int64_t)i + c] = acc[3 + c] + (ph.mu_r - self2) * Tq;
+    }
+    for (int c = 0; c < 5; ++c)
+      out3[5 * (int64_t)i + c] = X[5 * (int64_t)i + c] + (v2s ? ph.slip_S * v2s[5 * (int64_t)i + c] : 0.0);
+  }
+}
+
+inline unsigned nblk_p(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
+
+// launch shapes: source chunks of the real-space pass, source chunks of the structure factors,
+// wave-vector chunks of the reciprocal sum (each aiming at about 2048 workgroups)
+struct PerShape {
+  int nreal, creal, nsf, csf, nrec, crec;
+};
+
+PerShape per_shape(int64_t n, int K) {
+  PerShape p;
+  const int64_t rb = (n + kPBlk - 1) / kPBlk, kb = (K + kPKBlk - 1) / kPKBlk;
+  p.nreal = (int)std::min<int64_t>(std::max<int64_t>((2048 + rb - 1) / rb, 1), (n + kPTJ - 1) / kPTJ);
+  p.creal = (int)((n + p.nreal - 1) / p.nreal);
+  p.nsf = (int)std::min<int64_t>(std::max<int64_t>((2048 + kb - 1) / kb, 1), std::min<int64_t>(16, (n + kPTJ - 1) / kPTJ));
+  p.csf = (int)((n + p.nsf - 1) / p.nsf);
+  p.nrec = (int)std::min<int64_t>(std::max<int64_t>((2048 + rb - 1) / rb, 1), (K + kPKT - 1) / kPKT);
+  p.crec = (int)((K + p.nrec - 1) / p.nrec);
+  return p;
+}
+
+template <int TGT>
+void per_launch(const double* R, int64_t n, const double* Fe, const double* Te, const double* Sig, const double* D,
+                const double* v1s, const double* v2s, double* out, double* out2, double* out3, double* part,
+                const PerBox& g, const Phys& ph, hipStream_t s) {
+  constexpr int W = pw(TGT), NC = pnc(TGT);
+  const PerShape sh = per_shape(n, g.K);
+  double* preal = part;
+  double* precip = preal + (int64_t)sh.nreal * W * n;
+  double* sf = precip + (int64_t)sh.nrec * W * n;
+  double* T = sf + (int64_t)sh.nsf * 2 * NC * g.K;
+  const double a5_20 = 0.5 * ph.a5_10;
+  hipLaunchKernelGGL(k_per_real<TGT>, dim3(nblk_p(n, kPBlk), sh.nreal), dim3(kPBlk), 0, s, R, (int)n, Fe, Te, Sig, D,
+                     sh.creal, g.L, 1.0 / g.L, g.rc * g.rc, g.xi, ph.a2, ph.P, a5_20, preal);
+  hipLaunchKernelGGL(k_per_sf<TGT>, dim3(nblk_p(g.K, kPKBlk), sh.nsf), dim3(kPKBlk), 0, s, R, (int)n, Fe, Te, Sig, D,
+                     g.kv, g.K, sh.csf, ph.P, a5_20, sf);
+  hipLaunchKernelGGL(k_per_mult<TGT>, dim3(nblk_p(g.K, kPKBlk)), dim3(kPKBlk), 0, s, sf, sh.nsf, g.kv, g.K, g.xi,
+                     ph.a2, 2.0 / (g.L * g.L * g.L), T);
+  hipLaunchKernelGGL(k_per_recip<TGT>, dim3(nblk_p(n, kPBlk), sh.nrec), dim3(kPBlk), 0, s, R, (int)n, g.kv, T, g.K,
+                     sh.crec, precip);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (TGT == kPOp) s0 = ph.P * per_self_es(g.xi, ph.a2);
+  if (TGT == kPOut) {
+    s0 = ph.P * per_self_uf(g.xi, ph.a2);
+    s1 = a5_20 * per_self_ud(g.xi, ph.a2);
+    s2 = ph.P * per_self_wt(g.xi, ph.a2);
+  }
+  hipLaunchKernelGGL(k_per_finish<TGT>, dim3(nblk_p(n, 256)), dim3(256), 0, s, preal, sh.nreal, precip, sh.nrec,
+                     (int)n, Sig, Fe, Te, D, v1s, v2s, s0, s1, s2, ph, out, out2, out3);
+}
+
+}  // namespace
+
+std::vector<double> per_kvecs(double L, double kmax) {
+  // half of the reciprocal lattice (k and -k give complex conjugate terms): the first nonzero
+  // component of the integer vector positive
+  std::vector<double> kv;
+  const double dk = 2.0 * M_PI / L;
+  const int m = (int)floor(kmax / dk);
+  for (int a = 0; a <= m; ++a)
+    for (int b = -m; b <= m; ++b)
+      for (int c = -m; c <= m; ++c) {
+        if (a == 0 && (b < 0 || (b == 0 && c <= 0))) continue;
+        const double k1 = a * dk, k2 = b * dk, k3 = c * dk;
+        if (k1 * k1 + k2 * k2 + k3 * k3 > kmax * kmax) continue;
+        kv.push_back(k1);
+        kv.push_back(k2);
+        kv.push_back(k3);
+      }
+  return kv;
+}
+
+int64_t per_part_elems(int64_t n, int K) {
+  const PerShape sh = per_shape(n, K);
+  return (int64_t)sh.nreal * 6 * n + (int64_t)sh.nrec * 6 * n + (int64_t)sh.nsf * 28 * K + (int64_t)12 * K + 64;
+}
+
+void launch_per_op(const double* R, const double* x, double* y, double* part, int64_t n, const PerBox& g,
+                   const Phys& ph, hipStream_t s) {
+  if (n <= 0) return;
+  per_launch<kPOp>(R, n, nullptr, nullptr, x, nullptr, nullptr, nullptr, y, nullptr, nullptr, part, g, ph, s);
+}
+
+void launch_per_rhs(const double* R, const double* v2s, const double* v3t, const double* Fe, const double* Te,
+                    double* b, double* part, int64_t n, const PerBox& g, const Phys& ph, hipStream_t s) {
+  if (n <= 0) return;
+  per_launch<kPRhs>(R, n, Fe, Te, nullptr, v3t, nullptr, v2s, b, nullptr, nullptr, part, g, ph, s);
+}
+
+void launch_per_out(const double* R, const double* v1s, const double* v2s, const double* v3t, const double* Fe,
+                    const double* Te, const double* Sig, double* V, double* W, double* S, double* part, int64_t n,
+                    const PerBox& g, const Phys& ph, hipStream_t s) {
+  if (n <= 0) return;
+  per_launch<kPOut>(R, n, Fe, Te, Sig, v3t, v1s, v2s, V, W, S, part, g, ph, s);
+}
+
+}  // namespace mbs

@@ -40,8 +40,8 @@ def test_default_params_and_struct_layout():
     p = mbstokes.default_params()
     assert p.lmax == 2 and p.restart == 30 and abs(p.tol - 1e-10) < 1e-25
     assert abs(p.eta * 6 * 3.141592653589793 - 1) < 1e-15 and p.a == 1.0
-    assert p.plane == 0 and p.plane_z == 0.0
-    assert ctypes.sizeof(mbstokes.Params) == 7 * 8 + 14 * 4
+    assert p.plane == 0 and p.plane_z == 0.0 and p.box == 0.0 and p.ewald_xi == 0.0
+    assert ctypes.sizeof(mbstokes.Params) == 9 * 8 + 14 * 4
     assert ctypes.sizeof(mbstokes.Stats) == 4 * 4 + 8 * 8 + 2 * 4
     assert ctypes.sizeof(mbstokes.SlipEx) == 3 * 8
 
