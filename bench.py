@@ -751,7 +751,7 @@ def bench_periodic(ctx, a):
     (0.004 spheres per a^3 on jittered lattice sites): the operator
     at 10^4 and 10^5 spheres against the unbounded operator of the same spheres, and at 10^4 the
     right-hand side, outputs and the solve to 1e-10 (binary64, and with the near-field preconditioner
-    at 8a). Default splitting xi = 13/L. Median of 5 launches after 2 warm-ups, HIP events."""
+    at 8a). Default splitting. Median of 5 launches after 2 warm-ups, HIP events."""
     import statistics
 
     import numpy as np
@@ -783,7 +783,7 @@ def bench_periodic(ctx, a):
         sites = sites[rng.choice(len(sites), n, replace=False)]
         return sites + rng.uniform(-1.0, 1.0, (n, 3)) * max(0.0, (h - 2.2) / 2)
 
-    out = {"density": 0.004, "splitting": "xi = 13/L, rc = L/2, kmax = 13 xi",
+    out = {"density": 0.004, "splitting": "default: xi L = max(13, 16 (n/1e4)^0.2), rc = 6.5/xi, kmax = 13 xi",
            "positions": "jittered cubic lattice sites, minimum-image distance >= 2.2a; orientations, slip and "
                         "forces of the trap workload"}
     for n, seed in ((10_000, 1), (a.n, a.seed)):

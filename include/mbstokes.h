@@ -176,9 +176,11 @@ typedef struct mbs_params {
                             mbs_matvec_static refuse it (MBS_EUNSUPPORTED); exclusive with plane
                             (MBS_EINVAL). The near-field preconditioner keeps its unwrapped
                             neighbour lists. 0 = unbounded fluid (default) */
-  double  ewald_xi;      /* Ewald splitting parameter xi (box > 0): 0 = 13/box (the real-space cutoff
-                            then reaches box/2); larger values move work to the Fourier sum (more
-                            wave vectors, fewer real-space pairs); xi * box < 13 is MBS_EINVAL */
+  double  ewald_xi;      /* Ewald splitting parameter xi (box > 0): 0 = max(13, 16 (n/10^4)^0.2)/box
+                            (balances the real-space pairs, which fall as (xi box)^-3, against the
+                            wave vectors, which grow as (xi box)^3); larger values move work to the
+                            Fourier sum; xi * box < 13 is MBS_EINVAL (the real-space cutoff 6.5/xi
+                            must stay within box/2) */
 } mbs_params;
 
 typedef struct mbs_stats {

@@ -82,7 +82,8 @@ struct mbs_ctx {
   // traction ranks <= 3: Krylov basis, residual and solution vectors, pass partial sums
   DevBuf r3;
   DevBuf per_kv;  // the periodic box's half-lattice wave vectors [per_K x 3]
-  int per_K = 0;
+  DevBuf per_seg;  // their row segments: 8-long then 4-long, (first, count) pairs
+  int per_K = 0, per_nseg8 = 0, per_nseg4 = 0;
   double per_L = 0.0, per_kmax = 0.0;
   // a solve in the Morton order of the centres: the permutation and the reordered inputs/outputs
   DevBuf ord;
@@ -201,20 +202,34 @@ void apply_tiles(mbs_ctx* c) {
 // Workspace for n spheres and restart m.
 // the periodic box (params.box): splitting parameter, cutoffs and the wave vectors on the device
 bool periodic(const mbs_ctx* c) { return c->prm.box > 0.0; }
-double per_xi(const mbs_ctx* c) { return c->prm.ewald_xi > 0.0 ? c->prm.ewald_xi : 13.0 / c->prm.box; }
-PerBox per_box(const mbs_ctx* c) {
-  const double xi = per_xi(c);
-  return PerBox{c->prm.box, xi, std::min(6.5 / xi, 0.5 * c->prm.box), c->per_K, c->per_kv.p};
+// default splitting: xi L = max(13, 16 (n/10^4)^0.2), measured to balance the real-space pass (whose
+// pairs within rc fall as (xi L)^-3) against the Fourier passes (whose wave vectors grow as (xi L)^3)
+double per_xi(const mbs_ctx* c, int64_t n) {
+  if (c->prm.ewald_xi > 0.0) return c->prm.ewald_xi;
+  return std::max(13.0, 16.0 * pow((double)n / 1e4, 0.2)) / c->prm.box;
+}
+PerBox per_box(const mbs_ctx* c, int64_t n) {
+  const double xi = per_xi(c, n);
+  const int2* seg = reinterpret_cast<const int2*>(c->per_seg.p);
+  return PerBox{c->prm.box, xi, std::min(6.5 / xi, 0.5 * c->prm.box), c->per_K, c->per_kv.p,
+                seg, c->per_nseg8, seg + c->per_nseg8, c->per_nseg4};
 }
 // (re)builds the wave-vector list when the box or the splitting changed (outside any graph capture)
-int per_prepare(mbs_ctx* c) {
-  const double kmax = 13.0 * per_xi(c);
+int per_prepare(mbs_ctx* c, int64_t n) {
+  const double kmax = 13.0 * per_xi(c, n);
   if (c->per_kv.p && c->per_L == c->prm.box && c->per_kmax == kmax) return MBS_OK;
   const std::vector<double> kv = per_kvecs(c->prm.box, kmax);
   const int K = (int)(kv.size() / 3);
   if (K < 1) return set_err(c, MBS_EINVAL, "no wave vector below the Fourier cutoff");
   CHK(ensure(c, c->per_kv, kv.size()));
   HIPCHK(c, hipMemcpy(c->per_kv.p, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<int> seg = per_segments(kv, c->prm.box, 8);
+  const std::vector<int> seg4 = per_segments(kv, c->prm.box, 4);
+  c->per_nseg8 = (int)(seg.size() / 2);
+  c->per_nseg4 = (int)(seg4.size() / 2);
+  seg.insert(seg.end(), seg4.begin(), seg4.end());
+  CHK(ensure(c, c->per_seg, (seg.size() + 1) / 2));  // (ints stored in a double buffer)
+  HIPCHK(c, hipMemcpy(c->per_seg.p, seg.data(), seg.size() * sizeof(int), hipMemcpyHostToDevice));
   c->per_K = K;
   c->per_L = c->prm.box;
   c->per_kmax = kmax;
@@ -232,8 +247,8 @@ int ensure_ws(mbs_ctx* c, int64_t n) {
   CHK(ensure(c, c->dlt, len));
   int64_t pe = std::max<int64_t>(part_elems_max(n), c->prm.plane ? image_part_elems(n, n) : 0);
   if (periodic(c)) {
-    CHK(per_prepare(c));
-    pe = std::max<int64_t>(pe, per_part_elems(n, c->per_K));
+    CHK(per_prepare(c, n));
+    pe = std::max<int64_t>(pe, per_part_elems(n, c->per_K, c->per_nseg8));
   }
   CHK(ensure(c, c->part, (size_t)pe));
   CHK(ensure(c, c->srcbuf, (size_t)8 * n));
@@ -317,7 +332,7 @@ void apply_op(mbs_ctx* c, int prec, int64_t n, const double* R, const double* x,
     (void)hipEventRecord(c->opev[2 * slot], s);
   }
   if (periodic(c)) {  // the Ewald sums (binary64 in either precision)
-    launch_per_op(R, x, y, c->part.p, n, per_box(c), c->ph, s);
+    launch_per_op(R, x, y, c->part.p, n, per_box(c, n), c->ph, s);
     (prec == MBS_FP64 ? cnt.f64 : cnt.f32)++;
   } else if (prec == MBS_FP64) {
     launch_p2(false, R, x, y, c->part.p, c->srcbuf.p, c->orig.p, n, c->ph, c->tile64, s);
@@ -344,8 +359,8 @@ void apply_op_out(mbs_ctx* c, int64_t n, const double* R, const double* x, doubl
                   hipStream_t s, Counters& cnt) {
   (void)hipEventRecord(c->ev[4], s);
   if (periodic(c)) {  // operator and outputs as two Ewald passes
-    launch_per_op(R, x, y, c->part.p, n, per_box(c), c->ph, s);
-    launch_per_out(R, o.v1s, o.v2s, o.v3t, o.Fe, o.Te, x, o.V, o.W, o.S, c->part.p, n, per_box(c), c->ph, s);
+    launch_per_op(R, x, y, c->part.p, n, per_box(c, n), c->ph, s);
+    launch_per_out(R, o.v1s, o.v2s, o.v3t, o.Fe, o.Te, x, o.V, o.W, o.S, c->part.p, n, per_box(c, n), c->ph, s);
     (void)hipEventRecord(c->ev[5], s);
     cnt.pairs += 2.0 * (double)n * (double)(n - 1);
     o.valid = true;
@@ -863,7 +878,7 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
     HIPCHK(c, hipEventRecord(c->ev[1], s));
     HIPCHK(c, hipEventRecord(c->ev[2], s));
     if (periodic(c))
-      launch_per_out(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, per_box(c), c->ph, s);
+      launch_per_out(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, per_box(c, n), c->ph, s);
     else
       launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
     if (high) launch_high(1, R, n, R, n, hi, V, W, c->part.p, hsplit, c->ph, c->tile_pass, s);
@@ -882,7 +897,7 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
   if (c->prm.near_cutoff > 0.0) CHK(near_prepare(c, n, R, s));
   // right-hand side
   if (periodic(c))
-    launch_per_rhs(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, per_box(c), c->ph, s);
+    launch_per_rhs(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, per_box(c, n), c->ph, s);
   else
     launch_p1(R, v2s, v3t, Fz, Te, c->b.p, c->part.p, n, c->ph, c->tile_pass, s);
   cnt.pairs += (double)n * (double)(n - 1);
@@ -987,7 +1002,7 @@ int solve_in_order(mbs_ctx* c, int64_t n, const double* R, const double* p, cons
   const bool fused = op.valid;  // outputs already formed with the final residual
   if (!fused) {
     if (periodic(c))
-      launch_per_out(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, per_box(c), c->ph, s);
+      launch_per_out(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, per_box(c, n), c->ph, s);
     else
       launch_p3(R, v1s, v2s, v3t, Fz, Te, c->xs.p, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
     cnt.pairs += (double)n * (double)(n - 1);
@@ -1370,7 +1385,7 @@ void mbs_destroy(mbs_ctx* c) {
                     &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig, &c->near, &c->zt,
                     &c->nt, &c->stepstate,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
-                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->ord, &c->r3, &c->per_kv,
+                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->ord, &c->r3, &c->per_kv, &c->per_seg,
                     &c->bat, &c->btune};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
@@ -1531,7 +1546,7 @@ int mbs_rhs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v2s, const 
     return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane or params.box");
   CHK(check_plane(c, s, R, n));
   if (periodic(c))
-    launch_per_rhs(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, per_box(c), c->ph, s);
+    launch_per_rhs(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, per_box(c, n), c->ph, s);
   else
     launch_p1(R, v2s, v3t, Fe ? Fe : c->zeros.p, Te, b, c->part.p, n, c->ph, c->tile_pass, s);
   if (high_mask(hi))
@@ -1565,7 +1580,7 @@ int mbs_outputs_ex(mbs_ctx* c, int64_t n, const double* R, const double* v1s, co
     return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.plane or params.box");
   CHK(check_plane(c, s, R, n));
   if (periodic(c))
-    launch_per_out(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, per_box(c), c->ph, s);
+    launch_per_out(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, per_box(c, n), c->ph, s);
   else
     launch_p3(R, v1s, v2s, v3t, Fe ? Fe : c->zeros.p, Te, Sigma, V, W, S, c->part.p, n, c->ph, c->tile_pass, s);
   if (high_mask(hi))

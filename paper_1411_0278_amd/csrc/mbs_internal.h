@@ -122,9 +122,16 @@ struct PerBox {
   double L, xi, rc;
   int K;
   const double* kv;
+  const int2* seg8;  // row segments of at most 8 (operator) and 4 (other passes) wave vectors
+  int nseg8;
+  const int2* seg4;
+  int nseg4;
 };
 std::vector<double> per_kvecs(double L, double kmax);
-int64_t per_part_elems(int64_t n, int K);
+// (first wave vector, count) pairs: runs of consecutive k3 within one (k1, k2) row, at most maxlen
+std::vector<int> per_segments(const std::vector<double>& kv, double L, int maxlen);
+// scratch doubles of one pass with nseg structure-factor segments (the larger segment count)
+int64_t per_part_elems(int64_t n, int K, int nseg);
 void launch_per_op(const double* R, const double* x, double* y, double* part, int64_t n, const PerBox& g,
                    const Phys& ph, hipStream_t s);
 void launch_per_rhs(const double* R, const double* v2s, const double* v3t, const double* Fe, const double* Te,

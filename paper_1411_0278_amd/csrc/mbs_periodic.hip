@@ -10,15 +10,20 @@
 // flow at its centre, a constant per block (a multiple of the identity, or zero by parity).
 //
 // One pass (operator, right-hand side or outputs) is five launches:
-//   k_per_real    receiver per thread, source records staged through LDS tiles, the minimum-image
-//                 separation inside rc evaluated with the generated screened blocks; grid.y chunks
-//                 of the sources, partial sums per chunk;
-//   k_per_sf      wave vector per thread: structure factors sum_m c_m exp(-i k.R_m) of the source
-//                 coefficients (5, 9 or 14 of them), grid.y chunks of the sources;
+//   k_per_real    receiver per thread, source records staged through LDS tiles of 64, each lane
+//                 marking the records within rc (minimum image) in a bit mask and then evaluating
+//                 its own hits with the generated screened blocks; grid.y chunks of the sources,
+//                 partial sums per chunk;
+//   k_per_sf      segment of up to kseg consecutive wave vectors of one lattice row per thread:
+//                 structure factors sum_m c_m exp(-i k.R_m) of the source coefficients (5, 9 or 14
+//                 of them), one sincos per (segment, source) and the row's step exp(-i dk z_m) for
+//                 the rest; grid.y chunks of the sources;
 //   k_per_mult    wave vector per thread: the chunks added in order, the generated Fourier
 //                 multiplier applied, times 2/L^3 (k and -k together) and the splitting factor;
 //   k_per_recip   receiver per thread, wave vectors and their complex targets staged through LDS:
-//                 Re sum_k exp(i k.R_n) T(k); grid.y chunks of the wave vectors;
+//                 Re sum_k exp(i k.R_n) T(k), the phase carried along each lattice row by one complex
+//                 factor exp(i dk z_n) (a sincos where a row starts and every 16 steps); grid.y
+//                 chunks of the wave vectors;
 //   k_per_finish  the chunks added in order, the self constants and the one-body terms.
 // Every sum runs in a fixed order (bitwise reproducible). The arithmetic is binary64 throughout.
 #include <hip/hip_runtime.h>
@@ -39,6 +44,8 @@ constexpr int kPBlk = 128;   // receivers per workgroup (real space, reciprocal 
 constexpr int kPTJ = 64;     // source records per LDS tile
 constexpr int kPKBlk = 64;   // wave vectors per workgroup (structure factors, multipliers)
 constexpr int kPKT = 64;     // wave vectors per LDS tile of the reciprocal sum
+// wave vectors per structure-factor thread (consecutive along a lattice row), by target
+constexpr int kseg(int t) { return t == 0 ? 8 : 4; }
 
 enum { kPOp = 0, kPRhs = 1, kPOut = 2 };
 constexpr int pw(int t) { return t == kPOut ? 6 : 5; }   // target width
@@ -110,17 +117,28 @@ __global__ void __launch_bounds__(kPBlk)
     __syncthreads();
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) tile[t] = make_rec<TGT>(R, Fe, Te, Sig, D, jt + t, P, a5_20);
     __syncthreads();
+    // which records of the tile lie within rc of this receiver (the receiver itself, and its images
+    // beyond rc, excluded): a cheap pass over the tile, then each lane evaluates only its own hits,
+    // so a wavefront pays for its busiest lane rather than for every record any lane needs
+    uint64_t hits = 0;
+#pragma unroll 8
     for (int jj = 0; jj < cnt; ++jj) {
+      const double dx = wrap(xi0 - tile[jj].x, L, invL), dy = wrap(yi0 - tile[jj].y, L, invL),
+                   dz = wrap(zi0 - tile[jj].z, L, invL);
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      hits |= (uint64_t)(r2 < rc2 && r2 > 0.0) << jj;
+    }
+    while (hits) {
+      const int jj = __ffsll((unsigned long long)hits) - 1;
+      hits &= hits - 1;
       const RecP& s = tile[jj];
       const double dx = wrap(xi0 - s.x, L, invL), dy = wrap(yi0 - s.y, L, invL), dz = wrap(zi0 - s.z, L, invL);
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      if (r2 < rc2 && r2 > 0.0) {  // the receiver itself (and its images, beyond rc) excluded
-        const double r = sqrt(r2);
-        const double ri = 1.0 / r, ec = erfc(xi * r), ex = exp(-xi * xi * r2);
-        if (TGT == kPOp) per_real_strain_s(dx, dy, dz, ri, ec, ex, xi, a2, s.s, acc);
-        if (TGT == kPRhs) per_real_strain_ftq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.q, acc);
-        if (TGT == kPOut) per_real_motion_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc, acc + 3);
-      }
+      const double r = sqrt(r2);
+      const double ri = 1.0 / r, ec = erfc(xi * r), ex = exp(-xi * xi * r2);
+      if (TGT == kPOp) per_real_strain_s(dx, dy, dz, ri, ec, ex, xi, a2, s.s, acc);
+      if (TGT == kPRhs) per_real_strain_ftq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.q, acc);
+      if (TGT == kPOut) per_real_motion_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc, acc + 3);
     }
   }
   if (i >= n) return;
@@ -129,46 +147,70 @@ __global__ void __launch_bounds__(kPBlk)
   for (int c = 0; c < W; ++c) o[c] = acc[c];
 }
 
-// structure factors of one source chunk: sf[(chunk * K + k) * 2NC] = (re[NC], im[NC])
+// structure factors of one source chunk over the segments (first wave vector, count <= kseg) of
+// the half lattice: sf[(chunk * K + k) * 2NC] = (re[NC], im[NC])
 template <int TGT>
 __global__ void __launch_bounds__(kPKBlk)
     k_per_sf(const double* __restrict__ R, int n, const double* __restrict__ Fe, const double* __restrict__ Te,
-             const double* __restrict__ Sig, const double* __restrict__ D, const double* __restrict__ kv, int K,
-             int chunk, double P, double a5_20, double* __restrict__ sf) {
+             const double* __restrict__ Sig, const double* __restrict__ D, const double* __restrict__ kv,
+             const int2* __restrict__ seg, int nseg, int K, double dk, int chunk, double P, double a5_20,
+             double* __restrict__ sf) {
   __shared__ RecP tile[kPTJ];
-  constexpr int NC = pnc(TGT);
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int kk = k < K ? k : K - 1;
-  const double k1 = kv[3 * (int64_t)kk], k2 = kv[3 * (int64_t)kk + 1], k3 = kv[3 * (int64_t)kk + 2];
+  __shared__ double wre[kPTJ], wim[kPTJ];  // exp(-i dk z_m): one step along a row
+  constexpr int NC = pnc(TGT), S = kseg(TGT);
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int2 sg = seg[g < nseg ? g : nseg - 1];
+  const double k1 = kv[3 * (int64_t)sg.x], k2 = kv[3 * (int64_t)sg.x + 1], k3 = kv[3 * (int64_t)sg.x + 2];
   const int j0 = blockIdx.y * chunk;
   const int j1 = min(n, j0 + chunk);
-  double re[NC], im[NC];
+  double re[S][NC], im[S][NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) re[c] = im[c] = 0.0;
+  for (int q = 0; q < S; ++q)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) re[q][c] = im[q][c] = 0.0;
   for (int jt = j0; jt < j1; jt += kPTJ) {
     const int cnt = min(kPTJ, j1 - jt);
     __syncthreads();
-    for (int t = threadIdx.x; t < cnt; t += blockDim.x) tile[t] = make_rec<TGT>(R, Fe, Te, Sig, D, jt + t, P, a5_20);
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      tile[t] = make_rec<TGT>(R, Fe, Te, Sig, D, jt + t, P, a5_20);
+      double sn, cs;
+      sincos(dk * tile[t].z, &sn, &cs);
+      wre[t] = cs;
+      wim[t] = -sn;
+    }
     __syncthreads();
     for (int jj = 0; jj < cnt; ++jj) {
       const RecP& s = tile[jj];
       double sn, cs;
       sincos(fma(k1, s.x, fma(k2, s.y, k3 * s.z)), &sn, &cs);
+      double pr = cs, pi = -sn;  // exp(-i k.R_m) at the segment's first wave vector
+      const double wr = wre[jj], wi = wim[jj];
       double v[NC];
       coeffs<TGT>(s, v);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {  // exp(-i theta) = cos - i sin
-        re[c] = fma(v[c], cs, re[c]);
-        im[c] = fma(-v[c], sn, im[c]);
+      for (int q = 0; q < S; ++q) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          re[q][c] = fma(v[c], pr, re[q][c]);
+          im[q][c] = fma(v[c], pi, im[q][c]);
+        }
+        const double t = pr * wr - pi * wi;
+        pi = fma(pr, wi, pi * wr);
+        pr = t;
       }
     }
   }
-  if (k >= K) return;
-  double* o = sf + ((int64_t)blockIdx.y * K + k) * (2 * NC);
+  if (g >= nseg) return;
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    o[c] = re[c];
-    o[NC + c] = im[c];
+  for (int q = 0; q < S; ++q) {
+    if (q < sg.y) {
+      double* o = sf + ((int64_t)blockIdx.y * K + sg.x + q) * (2 * NC);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        o[c] = re[q][c];
+        o[NC + c] = im[q][c];
+      }
+    }
   }
 }
 
@@ -213,17 +255,22 @@ __global__ void __launch_bounds__(kPKBlk)
 template <int TGT>
 __global__ void __launch_bounds__(kPBlk)
     k_per_recip(const double* __restrict__ R, int n, const double* __restrict__ kv, const double* __restrict__ T,
-                int K, int chunk, double* __restrict__ part) {
+                int K, double dk, int chunk, double* __restrict__ part) {
   constexpr int W = pw(TGT);
   __shared__ double tk[kPKT][3 + 2 * W];
+  __shared__ int step[kPKT];  // 1: same lattice row as the previous wave vector, next k3
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int ii = i < n ? i : n - 1;
   const double x = R[3 * (int64_t)ii], y = R[3 * (int64_t)ii + 1], z = R[3 * (int64_t)ii + 2];
+  double wr, wi;  // exp(i dk z): one step along a row
+  sincos(dk * z, &wi, &wr);
   const int k0 = blockIdx.y * chunk;
   const int k1e = min(K, k0 + chunk);
   double acc[W];
 #pragma unroll
   for (int c = 0; c < W; ++c) acc[c] = 0.0;
+  double cs = 1.0, sn = 0.0;
+  int run = 0;  // steps since the last sincos (a fresh one every 16 bounds the rounding carried along)
   for (int kt = k0; kt < k1e; kt += kPKT) {
     const int cnt = min(kPKT, k1e - kt);
     __syncthreads();
@@ -231,10 +278,23 @@ __global__ void __launch_bounds__(kPBlk)
       const int q = t / (3 + 2 * W), c = t % (3 + 2 * W);
       tk[q][c] = c < 3 ? kv[3 * (int64_t)(kt + q) + c] : T[(int64_t)(kt + q) * (2 * W) + (c - 3)];
     }
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+      const int k = kt + q;  // the chunk's first wave vector always starts afresh
+      step[q] = (k > k0 && kv[3 * (int64_t)k] == kv[3 * (int64_t)(k - 1)] &&
+                 kv[3 * (int64_t)k + 1] == kv[3 * (int64_t)(k - 1) + 1] &&
+                 fabs(kv[3 * (int64_t)k + 2] - kv[3 * (int64_t)(k - 1) + 2] - dk) < 0.5 * dk) ? 1 : 0;
+    }
     __syncthreads();
     for (int q = 0; q < cnt; ++q) {
-      double sn, cs;
-      sincos(fma(tk[q][0], x, fma(tk[q][1], y, tk[q][2] * z)), &sn, &cs);
+      if (step[q] && run < 16) {  // uniform across the workgroup
+        const double t = cs * wr - sn * wi;
+        sn = fma(cs, wi, sn * wr);
+        cs = t;
+        ++run;
+      } else {
+        sincos(fma(tk[q][0], x, fma(tk[q][1], y, tk[q][2] * z)), &sn, &cs);
+        run = 0;
+      }
 #pragma unroll
       for (int c = 0; c < W; ++c) acc[c] = fma(tk[q][3 + c], cs, fma(-tk[q][3 + W + c], sn, acc[c]));
     }
@@ -290,9 +350,9 @@ struct PerShape {
   int nreal, creal, nsf, csf, nrec, crec;
 };
 
-PerShape per_shape(int64_t n, int K) {
+PerShape per_shape(int64_t n, int K, int nseg) {
   PerShape p;
-  const int64_t rb = (n + kPBlk - 1) / kPBlk, kb = (K + kPKBlk - 1) / kPKBlk;
+  const int64_t rb = (n + kPBlk - 1) / kPBlk, kb = (nseg + kPKBlk - 1) / kPKBlk;
   p.nreal = (int)std::min<int64_t>(std::max<int64_t>((2048 + rb - 1) / rb, 1), (n + kPTJ - 1) / kPTJ);
   p.creal = (int)((n + p.nreal - 1) / p.nreal);
   p.nsf = (int)std::min<int64_t>(std::max<int64_t>((2048 + kb - 1) / kb, 1), std::min<int64_t>(16, (n + kPTJ - 1) / kPTJ));
@@ -307,7 +367,7 @@ void per_launch(const double* R, int64_t n, const double* Fe, const double* Te, 
                 const double* v1s, const double* v2s, double* out, double* out2, double* out3, double* part,
                 const PerBox& g, const Phys& ph, hipStream_t s) {
   constexpr int W = pw(TGT), NC = pnc(TGT);
-  const PerShape sh = per_shape(n, g.K);
+  const PerShape sh = per_shape(n, g.K, TGT == kPOp ? g.nseg8 : g.nseg4);
   double* preal = part;
   double* precip = preal + (int64_t)sh.nreal * W * n;
   double* sf = precip + (int64_t)sh.nrec * W * n;
@@ -315,12 +375,14 @@ void per_launch(const double* R, int64_t n, const double* Fe, const double* Te, 
   const double a5_20 = 0.5 * ph.a5_10;
   hipLaunchKernelGGL(k_per_real<TGT>, dim3(nblk_p(n, kPBlk), sh.nreal), dim3(kPBlk), 0, s, R, (int)n, Fe, Te, Sig, D,
                      sh.creal, g.L, 1.0 / g.L, g.rc * g.rc, g.xi, ph.a2, ph.P, a5_20, preal);
-  hipLaunchKernelGGL(k_per_sf<TGT>, dim3(nblk_p(g.K, kPKBlk), sh.nsf), dim3(kPKBlk), 0, s, R, (int)n, Fe, Te, Sig, D,
-                     g.kv, g.K, sh.csf, ph.P, a5_20, sf);
+  const int nseg = TGT == kPOp ? g.nseg8 : g.nseg4;
+  const double dk = 2.0 * M_PI / g.L;
+  hipLaunchKernelGGL(k_per_sf<TGT>, dim3(nblk_p(nseg, kPKBlk), sh.nsf), dim3(kPKBlk), 0, s, R, (int)n, Fe, Te, Sig, D,
+                     g.kv, TGT == kPOp ? g.seg8 : g.seg4, nseg, g.K, dk, sh.csf, ph.P, a5_20, sf);
   hipLaunchKernelGGL(k_per_mult<TGT>, dim3(nblk_p(g.K, kPKBlk)), dim3(kPKBlk), 0, s, sf, sh.nsf, g.kv, g.K, g.xi,
                      ph.a2, 2.0 / (g.L * g.L * g.L), T);
   hipLaunchKernelGGL(k_per_recip<TGT>, dim3(nblk_p(n, kPBlk), sh.nrec), dim3(kPBlk), 0, s, R, (int)n, g.kv, T, g.K,
-                     sh.crec, precip);
+                     dk, sh.crec, precip);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   if (TGT == kPOp) s0 = ph.P * per_self_es(g.xi, ph.a2);
   if (TGT == kPOut) {
@@ -353,8 +415,26 @@ std::vector<double> per_kvecs(double L, double kmax) {
   return kv;
 }
 
-int64_t per_part_elems(int64_t n, int K) {
-  const PerShape sh = per_shape(n, K);
+std::vector<int> per_segments(const std::vector<double>& kv, double L, int maxlen) {
+  // runs of consecutive k3 within one (k1, k2) row, cut into pieces of at most maxlen
+  std::vector<int> seg;
+  const int K = (int)(kv.size() / 3);
+  const double dk = 2.0 * M_PI / L;
+  int k = 0;
+  while (k < K) {
+    int e = k + 1;
+    while (e < K && e - k < maxlen && kv[3 * e] == kv[3 * k] && kv[3 * e + 1] == kv[3 * k + 1] &&
+           fabs(kv[3 * e + 2] - kv[3 * (e - 1) + 2] - dk) < 0.5 * dk)
+      ++e;
+    seg.push_back(k);
+    seg.push_back(e - k);
+    k = e;
+  }
+  return seg;
+}
+
+int64_t per_part_elems(int64_t n, int K, int nseg) {
+  const PerShape sh = per_shape(n, K, nseg);
   return (int64_t)sh.nreal * 6 * n + (int64_t)sh.nrec * 6 * n + (int64_t)sh.nsf * 28 * K + (int64_t)12 * K + 64;
 }
 

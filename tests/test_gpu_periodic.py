@@ -99,8 +99,10 @@ def test_periodic_operator_matches_oracle(ctx, n):
     with _Box(ctx, L):
         got = ctx.mbs_matvec(_t(w.R), _t(x))
         got32 = ctx.mbs_matvec(_t(w.R), _t(x), precision=mbstokes.MBS_FP32)  # binary64 Ewald sums too
-    assert _maxrel(got, want) < 1e-12
-    assert _maxrel(got32, want) < 1e-12
+    # a sphere's Fourier self sum and its smooth self constant cancel to about an eighth of their size
+    # in the smallest box (8a, default splitting), which multiplies their rounding accordingly
+    assert _maxrel(got, want) < 2e-12
+    assert _maxrel(got32, want) < 2e-12
 
 
 @pytest.mark.parametrize("n", [1, 2, 97])
