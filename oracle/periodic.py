@@ -331,6 +331,54 @@ def solve(w, ew: Ewald, prm: galerkin.Params | None = None):
     return dict(V=V, W=W, S=S, Sigma=Sigma, b=b, A=A)
 
 
+@functools.lru_cache(maxsize=None)
+def _flow_fn(which, source):
+    cols = _flows(kernel(which), source, _Rules(which == "fourier"))
+    mat = [[cols[q][i] for q in range(len(cols))] for i in range(3)]
+    args = (kx_, ky_, kz_, xi_, a_, P_) if which == "fourier" else (x_, y_, z_, r_, ec_, ex_, xi_, a_, P_)
+    return sp.lambdify(args, mat, "numpy", cse=True)
+
+
+def flow_field(X, R, Fe, Te, Sigma, v3t, prm: galerkin.Params, ew: Ewald):
+    """Flow of the periodic suspension at field points X [m, 3] (no finite-size operator at the field
+    point): every sphere with all its images, real-space part within rc plus the Fourier sum."""
+    from scipy.special import erfc
+    X = np.asarray(X, dtype=np.float64).reshape(-1, 3)
+    R = np.asarray(R, dtype=np.float64).reshape(-1, 3)
+    P = 1.0 / (8 * np.pi * prm.eta)
+    nvec = ew.images()
+    kv = ew.kvecs()
+    q = np.einsum("pi,pi->p", kv, kv) / (4.0 * ew.xi * ew.xi)
+    phi = (1.0 + q) * np.exp(-q)
+    Ex = np.exp(1j * (X @ kv.T))        # [m, nk]
+    Er = np.exp(-1j * (R @ kv.T))       # [n, nk]
+    u = np.zeros((X.shape[0], 3))
+    for kind, vals in (("F", Fe), ("T", Te), ("S", Sigma), ("D", v3t)):
+        if vals is None:
+            continue
+        vals = np.asarray(vals, dtype=np.float64)
+        fr = _flow_fn("real", kind)
+        for m in range(R.shape[0]):
+            s = _wrap(X - R[m], ew.L)[:, None, :] + nvec[None, :, :]
+            r = np.sqrt(np.einsum("abi,abi->ab", s, s))
+            sel = (r <= ew.rc) & (r > 0)
+            if np.any(sel):
+                pts, rr = s[sel], r[sel]
+                raw = fr(pts[:, 0], pts[:, 1], pts[:, 2], rr, erfc(ew.xi * rr), np.exp(-(ew.xi * rr) ** 2), ew.xi,
+                         prm.a, P)
+                blk = np.stack([np.stack([np.broadcast_to(np.asarray(raw[i][j], dtype=float), (len(rr),))
+                                          for j in range(len(raw[0]))], -1) for i in range(3)], 1)
+                ia = np.nonzero(sel)[0]
+                np.add.at(u, ia, np.einsum("pij,j->pi", blk, vals[m]))
+        raw = _flow_fn("fourier", kind)(kv[:, 0], kv[:, 1], kv[:, 2], ew.xi, prm.a, P)
+        Mk = np.stack([np.stack([np.broadcast_to(np.asarray(raw[i][j], dtype=complex), (len(kv),))
+                                 for j in range(len(raw[0]))], -1) for i in range(3)], 1) * phi[:, None, None]
+        Sk = Er.T @ vals                   # [nk, dX]: sum_m exp(-i k.R_m) c_m
+        Tk = np.einsum("kij,kj->ki", Mk, Sk)  # [nk, 3]
+        u += ((Ex @ Tk) / ew.L ** 3).real
+    return u
+
+
 def matvec_rows(R, x, rows, prm: galerkin.Params, ew: Ewald):
     """(A x) restricted to the given spheres, without forming A."""
     x = np.asarray(x, dtype=np.float64).reshape(-1, 5)

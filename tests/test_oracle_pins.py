@@ -1041,3 +1041,31 @@ def test_periodic_system_is_symmetric_and_tends_to_the_free_one():
     y = (Ap @ x.ravel()).reshape(6, 5)[rows]
     assert np.abs(periodic.matvec_rows(R, x, rows, PRM, periodic.Ewald(L)) - y).max() < 1e-13 * np.abs(y).max()
 
+
+def test_periodic_suspension_satisfies_weak_boundary_conditions_by_quadrature():
+    """A suspension solved in a periodic box (force, torque, slip modes; two spheres close to
+    opposite faces, so that they interact through the box) has, on every sphere, the l = 0 and l = 1
+    surface moments of its rigid motion plus the slip in the periodic flow of all spheres (the first two
+    are 2.65a apart through a face of the box); the flow does not depend on the splitting."""
+    rng = np.random.default_rng(45)
+    n, L = 4, 9.0 * A
+    R = np.array([[1.2, 4.0, 4.5], [7.6, 4.3, 4.1], [4.4, 1.2, 6.9], [5.0, 7.0, 2.0]]) * A  # >= 2.6a apart
+    w = inputs.Workload(R, np.zeros((n, 3)), rng.standard_normal((n, 3)), rng.standard_normal((n, 5)),
+                        rng.standard_normal((n, 3)), rng.standard_normal((n, 3)),
+                        rng.standard_normal((n, 3)), ETA, A)
+    ew = periodic.Ewald(L, xi=7.0 / L)
+    sol = periodic.solve(w, ew, PRM)
+    nh, wq = sphere_quad.sphere_rule(32, 64)
+    for i in range(n):
+        pts = R[i] + A * nh
+        u = periodic.flow_field(pts, R, w.Fe, w.Te, sol["Sigma"], w.v3t, PRM, ew)
+        mean, V2 = sphere_quad.coefficients(u, nh, wq, A)
+        scale = np.abs(u).max()
+        assert np.abs(mean - (sol["V"][i] + w.v1s[i])).max() < 1e-10 * scale
+        assert np.abs(sphere_quad.axial(V2, A) - sol["W"][i]).max() < 1e-10 * scale / A
+        assert np.abs(basis.to5(V2 / A) - w.v2s[i]).max() < 1e-10 * scale / A
+    X = rng.uniform(0, L, (6, 3))
+    u1 = periodic.flow_field(X, R, w.Fe, w.Te, sol["Sigma"], w.v3t, PRM, ew)
+    u2 = periodic.flow_field(X, R, w.Fe, w.Te, sol["Sigma"], w.v3t, PRM, periodic.Ewald(L, xi=10.0 / L))
+    assert np.abs(u1 - u2).max() < 1e-10 * np.abs(u1).max()
+
