@@ -170,9 +170,10 @@ typedef struct mbs_params {
                             |k| = 13 xi, each sphere's own images through the Fourier sum less its
                             smooth self part; binary64 in every pass (truncation below 1e-13 of the
                             blocks). Positions may lie anywhere (they are taken modulo the box).
-                            Applies to mbs_solve(_ex), mbs_matvec, mbs_rhs(_ex), mbs_outputs(_ex)
-                            without higher slip modes; the flow at field points, the stepper, the
-                            batched solver, the rank <= 3 entry points, the warm-start calls and
+                            Applies to mbs_solve(_ex), mbs_matvec, mbs_rhs(_ex), mbs_outputs(_ex),
+                            mbs_flow(_ex) without higher slip modes, and mbs_step (which leaves the
+                            positions unwrapped and reports minimum-image distances in min_dist);
+                            the batched solver, the rank <= 3 entry points, the warm-start calls and
                             mbs_matvec_static refuse it (MBS_EUNSUPPORTED); exclusive with plane
                             (MBS_EINVAL). The near-field preconditioner keeps its unwrapped
                             neighbour lists. 0 = unbounded fluid (default) */

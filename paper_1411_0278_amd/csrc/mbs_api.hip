@@ -248,7 +248,7 @@ int ensure_ws(mbs_ctx* c, int64_t n) {
   int64_t pe = std::max<int64_t>(part_elems_max(n), c->prm.plane ? image_part_elems(n, n) : 0);
   if (periodic(c)) {
     CHK(per_prepare(c, n));
-    pe = std::max<int64_t>(pe, per_part_elems(n, c->per_K, c->per_nseg8));
+    pe = std::max<int64_t>(pe, per_part_elems(n, n, c->per_K, c->per_nseg8));
   }
   CHK(ensure(c, c->part, (size_t)pe));
   CHK(ensure(c, c->srcbuf, (size_t)8 * n));
@@ -672,6 +672,20 @@ int check_overlap(mbs_ctx* c, int64_t n, const double* R, hipStream_t s, double*
   launch_min_dist2(g, R, n, out, c->dpart.p + 1024, s);
   CHK(read_status(c, out, 1, s));
   *min_d = sqrt(c->h_status[0]);
+  return MBS_OK;
+}
+
+// smallest minimum-image centre distance in the periodic box (params.box; infinity for one sphere)
+int per_min_dist(mbs_ctx* c, int64_t n, const double* R, hipStream_t s, double* md) {
+  if (n < 2) {
+    *md = INFINITY;
+    return MBS_OK;
+  }
+  // (the tail of dpart holds at least (n + 255)/256 + 64 doubles beyond offset 1024, as for check_overlap)
+  double* out = c->small.p + c->small.cap - 1;
+  launch_per_min_dist(R, n, c->prm.box, c->dpart.p + 1024, out, s);
+  CHK(read_status(c, out, 1, s));
+  *md = c->h_status[0];
   return MBS_OK;
 }
 
@@ -1602,7 +1616,6 @@ int mbs_flow_ex(mbs_ctx* c, int64_t m, const double* X, int64_t n, const double*
                 const double* Te, const double* Sigma, const double* v3t, const mbs_slip_ex* ex, double* U,
                 void* stream) {
   CHK(begin_call(c));
-  CHK(refuse_box(c, "the flow at field points"));
   if (m < 1 || n < 1) return set_err(c, MBS_EINVAL, "m and n must be >= 1");
   if (m > (int64_t)INT32_MAX / 12 || n > (int64_t)INT32_MAX / 10) return set_err(c, MBS_EINVAL, "m or n too large");
   if (!X || !R || !Sigma || !U) return set_err(c, MBS_EINVAL, "X, R, Sigma and U are required");
@@ -1613,6 +1626,14 @@ int mbs_flow_ex(mbs_ctx* c, int64_t m, const double* X, int64_t n, const double*
                       {"psi", hi.psi, 5 * n}, {"lam", hi.lam, 10 * n}}));
   hipStream_t s = (hipStream_t)stream;
   CHK(ensure_ws(c, n));  // (zeros stand in for absent forces)
+  if (periodic(c)) {  // the periodic suspension's flow (Ewald sums)
+    if (high_mask(hi)) return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.box");
+    CHK(ensure(c, c->part, (size_t)per_part_elems(m, n, c->per_K, c->per_nseg8)));
+    launch_per_flow(X, m, R, n, Fe, Te, Sigma, v3t, U, c->part.p, per_box(c, n), c->ph, s);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(s));
+    return MBS_OK;
+  }
   const int hsplit = high_split(m, n, c->tile_pass);
   CHK(ensure(c, c->part, (size_t)std::max<int64_t>((int64_t)std::max(flow_split(m, n, c->tile_pass), high_mask(hi) ? hsplit : 0) * 3 * m,
                                                  c->prm.plane ? image_part_elems(m, n) : 0) + 64));
@@ -1640,7 +1661,6 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
              double dt, int32_t nsteps, int32_t order, double* hist, int32_t hist_valid,
              mbs_stats* per_step, double* min_dist, void* stream) {
   CHK(begin_call(c));
-  CHK(refuse_box(c, "mbs_step"));
   if (n < 1) return set_err(c, MBS_EINVAL, "n must be >= 1");
   if (n > (int64_t)INT32_MAX / 6) return set_err(c, MBS_EINVAL, "n too large");
   if (!R || !p || !slip_coef) return set_err(c, MBS_EINVAL, "R, p and slip_coef are required");
@@ -1692,7 +1712,7 @@ int mbs_step(mbs_ctx* c, int64_t n, double* R, double* p, double k_trap, const d
     }
     if (min_dist) {
       double md = 0.0;
-      rc = check_overlap(c, n, R, s, &md);
+      rc = periodic(c) ? per_min_dist(c, n, R, s, &md) : check_overlap(c, n, R, s, &md);
       if (rc != MBS_OK) break;
       min_dist[k] = fmin(md, 2.0 * hmin);
     }

@@ -130,8 +130,17 @@ struct PerBox {
 std::vector<double> per_kvecs(double L, double kmax);
 // (first wave vector, count) pairs: runs of consecutive k3 within one (k1, k2) row, at most maxlen
 std::vector<int> per_segments(const std::vector<double>& kv, double L, int maxlen);
-// scratch doubles of one pass with nseg structure-factor segments (the larger segment count)
-int64_t per_part_elems(int64_t n, int K, int nseg);
+// scratch doubles of one pass for m receivers and n sources with nseg structure-factor segments
+// (the larger segment count)
+int64_t per_part_elems(int64_t m, int64_t n, int K, int nseg);
+// out[0] = the smallest minimum-image centre distance of the n >= 2 spheres; part: per_min_dist_part(n)
+// doubles of scratch
+int per_min_dist_part(int64_t n);
+void launch_per_min_dist(const double* R, int64_t n, double L, double* part, double* out, hipStream_t s);
+// U [m x 3] = flow of the periodic suspension at field points X [m x 3]
+void launch_per_flow(const double* X, int64_t m, const double* R, int64_t n, const double* Fe, const double* Te,
+                     const double* Sig, const double* v3t, double* U, double* part, const PerBox& g, const Phys& ph,
+                     hipStream_t s);
 void launch_per_op(const double* R, const double* x, double* y, double* part, int64_t n, const PerBox& g,
                    const Phys& ph, hipStream_t s);
 void launch_per_rhs(const double* R, const double* v2s, const double* v3t, const double* Fe, const double* Te,

@@ -44,12 +44,13 @@ constexpr int kPBlk = 128;   // receivers per workgroup (real space, reciprocal 
 constexpr int kPTJ = 64;     // source records per LDS tile
 constexpr int kPKBlk = 64;   // wave vectors per workgroup (structure factors, multipliers)
 constexpr int kPKT = 64;     // wave vectors per LDS tile of the reciprocal sum
-// wave vectors per structure-factor thread (consecutive along a lattice row), by target
-constexpr int kseg(int t) { return t == 0 ? 8 : 4; }
 
-enum { kPOp = 0, kPRhs = 1, kPOut = 2 };
-constexpr int pw(int t) { return t == kPOut ? 6 : 5; }   // target width
+enum { kPOp = 0, kPRhs = 1, kPOut = 2, kPFlow = 3 };
+constexpr int pw(int t) { return t == kPOut ? 6 : (t == kPFlow ? 3 : 5); }  // target width
 constexpr int pnc(int t) { return t == kPOp ? 5 : (t == kPRhs ? 9 : 14); }  // source coefficients
+constexpr int sft(int t) { return t == kPFlow ? kPOut : t; }  // the structure factors a target uses
+// wave vectors per structure-factor thread (consecutive along a lattice row), by target
+constexpr int kseg(int t) { return t == kPOp ? 8 : 4; }
 
 // source record: centre and pre-scaled coefficients (f = P F, t = P T, s = P Sigma, q = (a^5/20) d)
 struct alignas(16) RecP {
@@ -99,13 +100,14 @@ __device__ __forceinline__ double wrap(double d, double L, double invL) { return
 
 template <int TGT>
 __global__ void __launch_bounds__(kPBlk)
-    k_per_real(const double* __restrict__ R, int n, const double* __restrict__ Fe, const double* __restrict__ Te,
-               const double* __restrict__ Sig, const double* __restrict__ D, int chunk, double L, double invL,
-               double rc2, double xi, double a2, double P, double a5_20, double* __restrict__ part) {
+    k_per_real(const double* __restrict__ X, int m, const double* __restrict__ R, int n,
+               const double* __restrict__ Fe, const double* __restrict__ Te, const double* __restrict__ Sig,
+               const double* __restrict__ D, int chunk, double L, double invL, double rc2, double xi, double a2,
+               double P, double a5_20, double* __restrict__ part) {
   __shared__ RecP tile[kPTJ];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ii = i < n ? i : n - 1;
-  const double xi0 = R[3 * (int64_t)ii], yi0 = R[3 * (int64_t)ii + 1], zi0 = R[3 * (int64_t)ii + 2];
+  const int ii = i < m ? i : m - 1;
+  const double xi0 = X[3 * (int64_t)ii], yi0 = X[3 * (int64_t)ii + 1], zi0 = X[3 * (int64_t)ii + 2];
   const int j0 = blockIdx.y * chunk;
   const int j1 = min(n, j0 + chunk);
   constexpr int W = pw(TGT);
@@ -139,10 +141,11 @@ __global__ void __launch_bounds__(kPBlk)
       if (TGT == kPOp) per_real_strain_s(dx, dy, dz, ri, ec, ex, xi, a2, s.s, acc);
       if (TGT == kPRhs) per_real_strain_ftq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.q, acc);
       if (TGT == kPOut) per_real_motion_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc, acc + 3);
+      if (TGT == kPFlow) per_real_flow_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc);
     }
   }
-  if (i >= n) return;
-  double* o = part + ((int64_t)blockIdx.y * n + i) * W;
+  if (i >= m) return;
+  double* o = part + ((int64_t)blockIdx.y * m + i) * W;
 #pragma unroll
   for (int c = 0; c < W; ++c) o[c] = acc[c];
 }
@@ -243,6 +246,8 @@ __global__ void __launch_bounds__(kPKBlk)
   if (TGT == kPRhs) per_hat_strain_ftq(k1, k2, k3, ik2, a2, re, im, re + 3, im + 3, re + 6, im + 6, tr, ti);
   if (TGT == kPOut)
     per_hat_motion_ftsq(k1, k2, k3, ik2, a2, re, im, re + 3, im + 3, re + 6, im + 6, re + 11, im + 11, tr, ti);
+  if (TGT == kPFlow)
+    per_hat_flow_ftsq(k1, k2, k3, ik2, a2, re, im, re + 3, im + 3, re + 6, im + 6, re + 11, im + 11, tr, ti);
   double* o = T + (int64_t)k * (2 * W);
 #pragma unroll
   for (int c = 0; c < W; ++c) {
@@ -326,7 +331,9 @@ __global__ void k_per_finish(const double* __restrict__ preal, int nreal, const 
     for (int c = 0; c < W; ++c) acc[c] += preal[((int64_t)ch * n + i) * W + c];
   for (int ch = 0; ch < nrecip; ++ch)
     for (int c = 0; c < W; ++c) acc[c] += precip[((int64_t)ch * n + i) * W + c];
-  if (TGT == kPOp) {
+  if (TGT == kPFlow) {
+    for (int c = 0; c < 3; ++c) out[3 * (int64_t)i + c] = acc[c];
+  } else if (TGT == kPOp) {
     for (int c = 0; c < 5; ++c) out[5 * (int64_t)i + c] = X[5 * (int64_t)i + c] * (ph.inv_gamma + self0) - acc[c];
   } else if (TGT == kPRhs) {
     for (int c = 0; c < 5; ++c) out[5 * (int64_t)i + c] = acc[c] - (v2s ? ph.c_slip * v2s[5 * (int64_t)i + c] : 0.0);
@@ -340,6 +347,53 @@ __global__ void k_per_finish(const double* __restrict__ preal, int nreal, const 
     for (int c = 0; c < 5; ++c)
       out3[5 * (int64_t)i + c] = X[5 * (int64_t)i + c] + (v2s ? ph.slip_S * v2s[5 * (int64_t)i + c] : 0.0);
   }
+}
+
+// the smallest minimum-image distance squared of each workgroup's receivers to every other sphere:
+// part[block] (all pairs, positions staged through LDS)
+__global__ void __launch_bounds__(256) k_per_min_d2(const double* __restrict__ R, int n, double L, double invL,
+                                                    double* __restrict__ part) {
+  __shared__ double tx[256], ty[256], tz[256], red[256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const double x = R[3 * (int64_t)ii], y = R[3 * (int64_t)ii + 1], z = R[3 * (int64_t)ii + 2];
+  double best = INFINITY;
+  for (int jt = 0; jt < n; jt += 256) {
+    const int cnt = min(256, n - jt);
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+      tx[threadIdx.x] = R[3 * (int64_t)(jt + threadIdx.x)];
+      ty[threadIdx.x] = R[3 * (int64_t)(jt + threadIdx.x) + 1];
+      tz[threadIdx.x] = R[3 * (int64_t)(jt + threadIdx.x) + 2];
+    }
+    __syncthreads();
+    for (int jj = 0; jj < cnt; ++jj) {
+      if (jt + jj == ii) continue;
+      const double dx = wrap(x - tx[jj], L, invL), dy = wrap(y - ty[jj], L, invL), dz = wrap(z - tz[jj], L, invL);
+      best = fmin(best, fma(dx, dx, fma(dy, dy, dz * dz)));
+    }
+  }
+  red[threadIdx.x] = i < n ? best : INFINITY;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out[0] = sqrt(min over the nb partial minima)
+__global__ void __launch_bounds__(256) k_min_finish(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double red[256];
+  double m = INFINITY;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) m = fmin(m, part[k]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(red[0]);
 }
 
 inline unsigned nblk_p(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
@@ -363,25 +417,28 @@ PerShape per_shape(int64_t n, int K, int nseg) {
 }
 
 template <int TGT>
-void per_launch(const double* R, int64_t n, const double* Fe, const double* Te, const double* Sig, const double* D,
-                const double* v1s, const double* v2s, double* out, double* out2, double* out3, double* part,
-                const PerBox& g, const Phys& ph, hipStream_t s) {
+void per_launch(const double* X, int64_t m, const double* R, int64_t n, const double* Fe, const double* Te,
+                const double* Sig, const double* D, const double* v1s, const double* v2s, double* out, double* out2,
+                double* out3, double* part, const PerBox& g, const Phys& ph, hipStream_t s) {
   constexpr int W = pw(TGT), NC = pnc(TGT);
-  const PerShape sh = per_shape(n, g.K, TGT == kPOp ? g.nseg8 : g.nseg4);
+  // receivers m for the real-space and reciprocal passes, sources n for the structure factors
+  const PerShape sh = per_shape(m, g.K, TGT == kPOp ? g.nseg8 : g.nseg4);
+  const PerShape shs = per_shape(n, g.K, TGT == kPOp ? g.nseg8 : g.nseg4);
   double* preal = part;
-  double* precip = preal + (int64_t)sh.nreal * W * n;
-  double* sf = precip + (int64_t)sh.nrec * W * n;
-  double* T = sf + (int64_t)sh.nsf * 2 * NC * g.K;
+  double* precip = preal + (int64_t)sh.nreal * W * m;
+  double* sf = precip + (int64_t)sh.nrec * W * m;
+  double* T = sf + (int64_t)shs.nsf * 2 * NC * g.K;
   const double a5_20 = 0.5 * ph.a5_10;
-  hipLaunchKernelGGL(k_per_real<TGT>, dim3(nblk_p(n, kPBlk), sh.nreal), dim3(kPBlk), 0, s, R, (int)n, Fe, Te, Sig, D,
-                     sh.creal, g.L, 1.0 / g.L, g.rc * g.rc, g.xi, ph.a2, ph.P, a5_20, preal);
+  const int creal = (int)((n + sh.nreal - 1) / sh.nreal);  // sources per real-space chunk
+  hipLaunchKernelGGL(k_per_real<TGT>, dim3(nblk_p(m, kPBlk), sh.nreal), dim3(kPBlk), 0, s, X, (int)m, R, (int)n, Fe,
+                     Te, Sig, D, creal, g.L, 1.0 / g.L, g.rc * g.rc, g.xi, ph.a2, ph.P, a5_20, preal);
   const int nseg = TGT == kPOp ? g.nseg8 : g.nseg4;
   const double dk = 2.0 * M_PI / g.L;
-  hipLaunchKernelGGL(k_per_sf<TGT>, dim3(nblk_p(nseg, kPKBlk), sh.nsf), dim3(kPKBlk), 0, s, R, (int)n, Fe, Te, Sig, D,
-                     g.kv, TGT == kPOp ? g.seg8 : g.seg4, nseg, g.K, dk, sh.csf, ph.P, a5_20, sf);
-  hipLaunchKernelGGL(k_per_mult<TGT>, dim3(nblk_p(g.K, kPKBlk)), dim3(kPKBlk), 0, s, sf, sh.nsf, g.kv, g.K, g.xi,
+  hipLaunchKernelGGL(k_per_sf<sft(TGT)>, dim3(nblk_p(nseg, kPKBlk), shs.nsf), dim3(kPKBlk), 0, s, R, (int)n, Fe, Te,
+                     Sig, D, g.kv, TGT == kPOp ? g.seg8 : g.seg4, nseg, g.K, dk, shs.csf, ph.P, a5_20, sf);
+  hipLaunchKernelGGL(k_per_mult<TGT>, dim3(nblk_p(g.K, kPKBlk)), dim3(kPKBlk), 0, s, sf, shs.nsf, g.kv, g.K, g.xi,
                      ph.a2, 2.0 / (g.L * g.L * g.L), T);
-  hipLaunchKernelGGL(k_per_recip<TGT>, dim3(nblk_p(n, kPBlk), sh.nrec), dim3(kPBlk), 0, s, R, (int)n, g.kv, T, g.K,
+  hipLaunchKernelGGL(k_per_recip<TGT>, dim3(nblk_p(m, kPBlk), sh.nrec), dim3(kPBlk), 0, s, X, (int)m, g.kv, T, g.K,
                      dk, sh.crec, precip);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   if (TGT == kPOp) s0 = ph.P * per_self_es(g.xi, ph.a2);
@@ -390,8 +447,8 @@ void per_launch(const double* R, int64_t n, const double* Fe, const double* Te, 
     s1 = a5_20 * per_self_ud(g.xi, ph.a2);
     s2 = ph.P * per_self_wt(g.xi, ph.a2);
   }
-  hipLaunchKernelGGL(k_per_finish<TGT>, dim3(nblk_p(n, 256)), dim3(256), 0, s, preal, sh.nreal, precip, sh.nrec,
-                     (int)n, Sig, Fe, Te, D, v1s, v2s, s0, s1, s2, ph, out, out2, out3);
+  hipLaunchKernelGGL(k_per_finish<TGT>, dim3(nblk_p(m, 256)), dim3(256), 0, s, preal, sh.nreal, precip, sh.nrec,
+                     (int)m, Sig, Fe, Te, D, v1s, v2s, s0, s1, s2, ph, out, out2, out3);
 }
 
 }  // namespace
@@ -433,28 +490,43 @@ std::vector<int> per_segments(const std::vector<double>& kv, double L, int maxle
   return seg;
 }
 
-int64_t per_part_elems(int64_t n, int K, int nseg) {
-  const PerShape sh = per_shape(n, K, nseg);
-  return (int64_t)sh.nreal * 6 * n + (int64_t)sh.nrec * 6 * n + (int64_t)sh.nsf * 28 * K + (int64_t)12 * K + 64;
+int64_t per_part_elems(int64_t m, int64_t n, int K, int nseg) {
+  const PerShape sh = per_shape(m, K, nseg), shs = per_shape(n, K, nseg);  // receivers m, sources n
+  return (int64_t)sh.nreal * 6 * m + (int64_t)sh.nrec * 6 * m + (int64_t)shs.nsf * 28 * K + (int64_t)12 * K + 64;
 }
 
 void launch_per_op(const double* R, const double* x, double* y, double* part, int64_t n, const PerBox& g,
                    const Phys& ph, hipStream_t s) {
   if (n <= 0) return;
-  per_launch<kPOp>(R, n, nullptr, nullptr, x, nullptr, nullptr, nullptr, y, nullptr, nullptr, part, g, ph, s);
+  per_launch<kPOp>(R, n, R, n, nullptr, nullptr, x, nullptr, nullptr, nullptr, y, nullptr, nullptr, part, g, ph, s);
 }
 
 void launch_per_rhs(const double* R, const double* v2s, const double* v3t, const double* Fe, const double* Te,
                     double* b, double* part, int64_t n, const PerBox& g, const Phys& ph, hipStream_t s) {
   if (n <= 0) return;
-  per_launch<kPRhs>(R, n, Fe, Te, nullptr, v3t, nullptr, v2s, b, nullptr, nullptr, part, g, ph, s);
+  per_launch<kPRhs>(R, n, R, n, Fe, Te, nullptr, v3t, nullptr, v2s, b, nullptr, nullptr, part, g, ph, s);
 }
 
 void launch_per_out(const double* R, const double* v1s, const double* v2s, const double* v3t, const double* Fe,
                     const double* Te, const double* Sig, double* V, double* W, double* S, double* part, int64_t n,
                     const PerBox& g, const Phys& ph, hipStream_t s) {
   if (n <= 0) return;
-  per_launch<kPOut>(R, n, Fe, Te, Sig, v3t, v1s, v2s, V, W, S, part, g, ph, s);
+  per_launch<kPOut>(R, n, R, n, Fe, Te, Sig, v3t, v1s, v2s, V, W, S, part, g, ph, s);
+}
+
+int per_min_dist_part(int64_t n) { return (int)((n + 255) / 256); }
+
+void launch_per_min_dist(const double* R, int64_t n, double L, double* part, double* out, hipStream_t s) {
+  const int nb = per_min_dist_part(n);
+  hipLaunchKernelGGL(k_per_min_d2, dim3(nb), dim3(256), 0, s, R, (int)n, L, 1.0 / L, part);
+  hipLaunchKernelGGL(k_min_finish, dim3(1), dim3(256), 0, s, part, nb, out);
+}
+
+void launch_per_flow(const double* X, int64_t m, const double* R, int64_t n, const double* Fe, const double* Te,
+                     const double* Sig, const double* v3t, double* U, double* part, const PerBox& g, const Phys& ph,
+                     hipStream_t s) {
+  if (m <= 0 || n <= 0) return;
+  per_launch<kPFlow>(X, m, R, n, Fe, Te, Sig, v3t, nullptr, nullptr, U, nullptr, nullptr, part, g, ph, s);
 }
 
 }  // namespace mbs

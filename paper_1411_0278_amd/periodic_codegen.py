@@ -22,10 +22,12 @@ the pre-scaled source coefficients f = P F, t = P T, s = P Sigma (5-basis), q = 
 P = 1/(8 pi eta):
 
     real space (x the separation, r = |x|, ri = 1/r, ec = erfc(xi r), ex = exp(-xi^2 r^2)):
-        per_real_strain_s, per_real_strain_ftq, per_real_motion_ftsq   (accumulate e[5] / u[3], w[3])
+        per_real_strain_s, per_real_strain_ftq, per_real_motion_ftsq   (accumulate e[5] / u[3], w[3]),
+        per_real_flow_ftsq (the flow itself at a field point, accumulate u[3])
     Fourier space (k, ik2 = 1/k^2, the complex structure factors of the coefficients split into real
     and imaginary parts; the splitting factor and 1/L^3 applied by the caller):
-        per_hat_strain_s, per_hat_strain_ftq, per_hat_motion_ftsq      (write the complex targets)
+        per_hat_strain_s, per_hat_strain_ftq, per_hat_motion_ftsq, per_hat_flow_ftsq
+                                                                       (write the complex targets)
     a sphere's smooth part at its own centre, (1/(2 pi)^3) integral of the multiplier over all k
     (isotropic: a multiple of the identity for the blocks that do not vanish by parity):
         per_self_es, per_self_uf, per_self_ud, per_self_wt
@@ -261,6 +263,10 @@ def generate():
     parts.append(_emit("per_real_motion_ftsq", geo + ", const double* f, const double* t, const double* s, "
                        "const double* q, double* u, double* w", [("u", c, "+=") for c in range(3)] +
                        [("w", c, "+=") for c in range(3)], U + W, list(f) + list(t) + list(s) + list(q), sub))
+    ff = source_flow(rl, Kr, f, t, s, q)
+    parts.append(_emit("per_real_flow_ftsq", geo + ", const double* f, const double* t, const double* s, "
+                       "const double* q, double* u", [("u", c, "+=") for c in range(3)], ff,
+                       list(f) + list(t) + list(s) + list(q), sub))
     # Fourier space: complex structure factors in, complex targets out
     fo = _Fourier()
     Kf = fo.kernel()
@@ -287,6 +293,13 @@ def generate():
                        "const double* ti, const double* sr, const double* si, const double* qr, const double* qi, "
                        "double* ur, double* ui", [("ur", c, "=") for c in range(6)] + [("ui", c, "=") for c in range(6)],
                        re_ + im_, list(fr) + list(fi) + list(tr) + list(ti) + list(sr) + list(si) + list(qr) + list(qi)))
+    hf3 = source_flow(fo, Kf, f, t, s, q)
+    re_, im_ = _complex_parts(hf3, list(f) + list(t) + list(s) + list(q), list(fr) + list(tr) + list(sr) + list(qr),
+                              list(fi) + list(ti) + list(si) + list(qi))
+    parts.append(_emit("per_hat_flow_ftsq", kgeo + ", const double* fr, const double* fi, const double* tr, "
+                       "const double* ti, const double* sr, const double* si, const double* qr, const double* qi, "
+                       "double* ur, double* ui", [("ur", c, "=") for c in range(3)] + [("ui", c, "=") for c in range(3)],
+                       re_ + im_, list(fr) + list(fi) + list(tr) + list(ti) + list(sr) + list(si) + list(qr) + list(qi)))
     # self constants: the diagonal of the isotropic blocks, per unit P (E from s, U from f, U from q, W from t)
     consts = {}
     unit = lambda syms, k: [sp.Integer(int(i == k)) for i in range(len(syms))]  # noqa: E731
@@ -310,8 +323,8 @@ def generate():
             nm = str(sym)
             m = re.match(r"([a-z]+)(\d+)$", nm)
             sym_map[nm] = "%s[%s]" % (m.group(1), m.group(2))
-    names = ("per_real_strain_s", "per_real_strain_ftq", "per_real_motion_ftsq", "per_hat_strain_s",
-             "per_hat_strain_ftq", "per_hat_motion_ftsq")
+    names = ("per_real_strain_s", "per_real_strain_ftq", "per_real_motion_ftsq", "per_real_flow_ftsq",
+             "per_hat_strain_s", "per_hat_strain_ftq", "per_hat_motion_ftsq", "per_hat_flow_ftsq")
     body, counts = [], []
     for (code, nops), nm in zip(parts, names):
         for k, v in sym_map.items():

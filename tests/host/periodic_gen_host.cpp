@@ -20,10 +20,14 @@ void ev_real(int which, int n, const double* x, double xi, double a2, const doub
     } else if (which == 1) {
       for (int c = 0; c < 5; ++c) o1[5 * p + c] = 0.0;
       mbs::per_real_strain_ftq(d[0], d[1], d[2], ri, ec, ex, xi, a2, f + 3 * p, t + 3 * p, q + 3 * p, o1 + 5 * p);
-    } else {
+    } else if (which == 2) {
       for (int c = 0; c < 3; ++c) o1[3 * p + c] = o2[3 * p + c] = 0.0;
       mbs::per_real_motion_ftsq(d[0], d[1], d[2], ri, ec, ex, xi, a2, f + 3 * p, t + 3 * p, s + 5 * p, q + 3 * p,
                                 o1 + 3 * p, o2 + 3 * p);
+    } else {
+      for (int c = 0; c < 3; ++c) o1[3 * p + c] = 0.0;
+      mbs::per_real_flow_ftsq(d[0], d[1], d[2], ri, ec, ex, xi, a2, f + 3 * p, t + 3 * p, s + 5 * p, q + 3 * p,
+                              o1 + 3 * p);
     }
   }
 }
@@ -40,9 +44,12 @@ void ev_hat(int which, int n, const double* k, double a2, const double* fr, cons
     else if (which == 1)
       mbs::per_hat_strain_ftq(kv[0], kv[1], kv[2], ik2, a2, fr + 3 * p, fi + 3 * p, tr + 3 * p, ti + 3 * p, qr + 3 * p,
                               qi + 3 * p, outr + 5 * p, outi + 5 * p);
-    else
+    else if (which == 2)
       mbs::per_hat_motion_ftsq(kv[0], kv[1], kv[2], ik2, a2, fr + 3 * p, fi + 3 * p, tr + 3 * p, ti + 3 * p,
                                sr + 5 * p, si + 5 * p, qr + 3 * p, qi + 3 * p, outr + 6 * p, outi + 6 * p);
+    else
+      mbs::per_hat_flow_ftsq(kv[0], kv[1], kv[2], ik2, a2, fr + 3 * p, fi + 3 * p, tr + 3 * p, ti + 3 * p,
+                             sr + 5 * p, si + 5 * p, qr + 3 * p, qi + 3 * p, outr + 3 * p, outi + 3 * p);
   }
 }
 void ev_self(double xi, double a2, double* out) {

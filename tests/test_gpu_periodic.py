@@ -1,7 +1,7 @@
 """Spheres in a periodic cubic box on the GPU (params.box, Ewald summation): every pass and the solve
 against the oracle's periodic system (summed with its own splitting parameter, which the pinned
-result does not depend on), Hasimoto's simple cubic mobility, invariance under shifts by box
-vectors, and the entry points that refuse the box."""
+result does not depend on), the flow at field points, the stepper, Hasimoto's simple cubic
+mobility, invariance under shifts by box vectors, and the entry points that refuse the box."""
 import functools
 import os
 import sys
@@ -187,6 +187,36 @@ def test_periodic_operator_sampled_rows_at_a_thousand_spheres(ctx):
     assert _maxrel(got[rows], want) < 1e-12
 
 
+def test_periodic_flow_field_matches_oracle(ctx):
+    n, m = 97, 240
+    w, L = _workload(n, 3600)
+    Sig = np.random.default_rng(21).standard_normal((n, 5))
+    X = np.random.default_rng(22).uniform(-0.5 * L, 1.5 * L, (m, 3))  # anywhere: taken modulo the box
+    want = periodic.flow_field(X, w.R, w.Fe, w.Te, Sig, w.v3t, PRM, _ew(L))
+    with _Box(ctx, L):
+        got = ctx.mbs_flow(_t(X), _t(w.R), _t(Sig), _t(w.Fe), _t(w.Te), _t(w.v3t))
+    assert _maxrel(got, want) < 1e-12
+
+
+def test_periodic_stepper_matches_oracle(ctx):
+    """Force-free swimmers (no trap, slip modes 1, 1, 1 along p) stepped three times in the box
+    against the oracle's stepper on the periodic solve; min_dist is the smallest minimum-image
+    distance."""
+    from oracle import stepper
+    n = 24
+    w, L = _workload(n, 3700, L=14.0)
+    Rw, pw, _ = stepper.run(w.R, w.p, 0.0, (1.0, 1.0, 1.0), 0.05, 3, PRM,
+                            solve=lambda st, pr: periodic.solve(st, _ew(L), pr))
+    R, p = _t(w.R), _t(w.p)
+    with _Box(ctx, L, tol=1e-13):
+        stats, md = ctx.mbs_step(R, p, 0.0, (1.0, 1.0, 1.0), 0.05, 3, order=2, want_min_dist=True)
+    assert _maxrel(R, Rw) < 1e-11 and _maxrel(p, pw) < 1e-11
+    d = w.R[:, None, :] - w.R[None, :, :]
+    d -= L * np.round(d / L)
+    dist = np.sqrt((d ** 2).sum(-1)) + np.eye(n) * 1e9
+    assert abs(md[0] - dist.min()) < 1e-12
+
+
 def test_periodic_errors(ctx):
     n = 8
     w, L = _workload(n, 3500)
@@ -199,9 +229,7 @@ def test_periodic_errors(ctx):
     assert e.value.code == mbstokes.MBS_EINVAL
     ctx.set_params(box=0.0, plane=0, ewald_xi=0.0)
     with _Box(ctx, L):
-        refused = [lambda: ctx.mbs_step(R.clone(), _t(w.p), 0.5, (1.0, 1.0, 1.0), 0.01, 1),
-                   lambda: ctx.mbs_flow(_t(np.zeros((2, 3))), R, x),
-                   lambda: ctx.mbs_matvec_r3(R, _t(np.ones((n, 20)))),
+        refused = [lambda: ctx.mbs_matvec_r3(R, _t(np.ones((n, 20)))),
                    lambda: ctx.mbs_matvec_static(R, x, torch.empty_like(x)),
                    lambda: ctx.mbs_solve_ex(R, None, _t(w.v1s), _t(w.v2s), gam=_t(np.ones((n, 10))))]
         for call in refused:

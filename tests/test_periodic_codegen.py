@@ -51,6 +51,16 @@ def test_generated_real_space_matches_oracle(lib):
     src = (("F", F), ("T", T), ("S", S), ("D", d))
     assert _close(u, sum(np.einsum("pij,pj->pi", blk("U", k), v) for k, v in src))
     assert _close(w, sum(np.einsum("pij,pj->pi", blk("W", k), v) for k, v in src))
+    lib.ev_real(3, n, _p(x), ctypes.c_double(XI), ctypes.c_double(A * A), *args, pu, None)
+    from scipy.special import erfc
+    r = np.sqrt((x ** 2).sum(1))
+    want = np.zeros((n, 3))
+    for k, v in src:
+        raw = periodic._flow_fn("real", k)(x[:, 0], x[:, 1], x[:, 2], r, erfc(XI * r), np.exp(-(XI * r) ** 2), XI, A, P)
+        M = np.stack([np.stack([np.broadcast_to(np.asarray(raw[i][j], float), (n,)) for j in range(v.shape[1])], -1)
+                      for i in range(3)], 1)
+        want += np.einsum("pij,pj->pi", M, v)
+    assert _close(u, want)
 
 
 def test_generated_fourier_multipliers_match_oracle(lib):
@@ -81,6 +91,13 @@ def test_generated_fourier_multipliers_match_oracle(lib):
     U = sum(np.einsum("pij,pj->pi", blk("U", kk), v) for kk, v in src)
     W = sum(np.einsum("pij,pj->pi", blk("W", kk), v) for kk, v in src)
     assert _close(run(2, 6), np.concatenate([U, W], 1))
+    want = 0
+    for kk, v in src:
+        raw = periodic._flow_fn("fourier", kk)(k[:, 0], k[:, 1], k[:, 2], XI, A, P)
+        M = np.stack([np.stack([np.broadcast_to(np.asarray(raw[i][j], complex), (n,)) for j in range(v.shape[1])], -1)
+                      for i in range(3)], 1)
+        want = want + np.einsum("pij,pj->pi", M, v) * phi
+    assert _close(run(3, 3), want)
 
 
 def test_generated_self_constants_match_oracle(lib):
