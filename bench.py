@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--profile-rank3", action="store_true",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then --steps "
                          "rank <= 3 operator applications at N = 10^4")
+    ap.add_argument("--profile-geometries", action="store_true",
+                    help="profiling mode: the plane, wall and periodic-box sections of the bench line alone "
+                         "(their passes at 10^4 and --n spheres and the solves at 10^4), printed as JSON")
     ap.add_argument("--profile-matvec", action="store_true",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then --steps "
                          "binary64 and --steps binary32 operator applications at the autotuned shapes")
@@ -1087,6 +1090,12 @@ def main():
         return
     if a.profile_rank3:
         profile_rank3(a)
+        return
+    if a.profile_geometries:
+        ctx = mbstokes.Context(0)
+        print(json.dumps({"mode": "profile-geometries", "plane": bench_plane(ctx, a),
+                          "periodic": bench_periodic(ctx, a)}), flush=True)
+        ctx.close()
         return
     d = mbstokes.to_device(w, "cuda:0")
     # the workload has no external torque and no rank-3 trace slip: pass NULL (= zero)
