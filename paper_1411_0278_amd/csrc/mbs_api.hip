@@ -438,7 +438,8 @@ StepGraphs* step_graphs(mbs_ctx* c, int prec, int64_t n, const double* R, bool p
       (uintptr_t)c->srcbuf.p, (uintptr_t)c->orig.p, (uintptr_t)c->near.p, (uintptr_t)near_order(c),
       dbits(c->ph.P), dbits(c->ph.a2),
       dbits(c->ph.gamma), dbits(c->ph.inv_gamma), (uintptr_t)c->prm.plane, dbits(c->prm.plane_z),
-      dbits(c->prm.box), dbits(c->prm.ewald_xi), (uintptr_t)c->per_kv.p, (uintptr_t)c->per_K};
+      dbits(c->prm.box), dbits(c->prm.ewald_xi), (uintptr_t)c->per_kv.p, (uintptr_t)c->per_K,
+      (uintptr_t)c->per_seg.p, (uintptr_t)c->per_nseg8};
   StepGraphs& G = c->sgraph[prec == MBS_FP64 ? 0 : 1];
   if (key == G.key) return &G;
   G.reset();
