@@ -786,7 +786,7 @@ def bench_periodic(ctx, a):
         sites = sites[rng.choice(len(sites), n, replace=False)]
         return sites + rng.uniform(-1.0, 1.0, (n, 3)) * max(0.0, (h - 2.2) / 2)
 
-    out = {"density": 0.004, "splitting": "default: xi L = max(13, 16 (n/1e4)^0.2), rc = 6.5/xi, kmax = 13 xi",
+    out = {"density": 0.004, "splitting": "default: xi L = max(13, 13 (n/1e4)^0.15), rc = 6.5/xi, kmax = 13 xi",
            "positions": "jittered cubic lattice sites, minimum-image distance >= 2.2a; orientations, slip and "
                         "forces of the trap workload"}
     for n, seed in ((10_000, 1), (a.n, a.seed)):

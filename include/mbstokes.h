@@ -177,7 +177,7 @@ typedef struct mbs_params {
                             mbs_matvec_static refuse it (MBS_EUNSUPPORTED); exclusive with plane
                             (MBS_EINVAL). The near-field preconditioner keeps its unwrapped
                             neighbour lists. 0 = unbounded fluid (default) */
-  double  ewald_xi;      /* Ewald splitting parameter xi (box > 0): 0 = max(13, 16 (n/10^4)^0.2)/box
+  double  ewald_xi;      /* Ewald splitting parameter xi (box > 0): 0 = max(13, 13 (n/10^4)^0.15)/box
                             (balances the real-space pairs, which fall as (xi box)^-3, against the
                             wave vectors, which grow as (xi box)^3); larger values move work to the
                             Fourier sum; xi * box < 13 is MBS_EINVAL (the real-space cutoff 6.5/xi

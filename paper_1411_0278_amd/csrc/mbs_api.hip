@@ -202,11 +202,11 @@ void apply_tiles(mbs_ctx* c) {
 // Workspace for n spheres and restart m.
 // the periodic box (params.box): splitting parameter, cutoffs and the wave vectors on the device
 bool periodic(const mbs_ctx* c) { return c->prm.box > 0.0; }
-// default splitting: xi L = max(13, 16 (n/10^4)^0.2), measured to balance the real-space pass (whose
+// default splitting: xi L = max(13, 13 (n/10^4)^0.15), measured to balance the real-space pass (whose
 // pairs within rc fall as (xi L)^-3) against the Fourier passes (whose wave vectors grow as (xi L)^3)
 double per_xi(const mbs_ctx* c, int64_t n) {
   if (c->prm.ewald_xi > 0.0) return c->prm.ewald_xi;
-  return std::max(13.0, 16.0 * pow((double)n / 1e4, 0.2)) / c->prm.box;
+  return std::max(13.0, 13.0 * pow((double)n / 1e4, 0.15)) / c->prm.box;
 }
 PerBox per_box(const mbs_ctx* c, int64_t n) {
   const double xi = per_xi(c, n);

@@ -12,8 +12,10 @@
 // One pass (operator, right-hand side or outputs) is five launches:
 //   k_per_real    receiver per thread, source records staged through LDS tiles of 64, each lane
 //                 marking the records within rc (minimum image) in a bit mask and then evaluating
-//                 its own hits with the generated screened blocks; grid.y chunks of the sources,
-//                 partial sums per chunk;
+//                 its own hits with the generated screened blocks (the operator through the
+//                 isotropic form of the screened stresslet strain: three generated radial
+//                 functions and the contraction here); grid.y chunks of the sources, partial sums
+//                 per chunk;
 //   k_per_sf      segment of up to kseg consecutive wave vectors of one lattice row per thread:
 //                 structure factors sum_m c_m exp(-i k.R_m) of the source coefficients (5, 9 or 14
 //                 of them), one sincos per (segment, source) and the row's step exp(-i dk z_m) for
@@ -138,7 +140,30 @@ __global__ void __launch_bounds__(kPBlk)
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
       const double r = sqrt(r2);
       const double ri = 1.0 / r, ec = erfc(xi * r), ex = exp(-xi * xi * r2);
-      if (TGT == kPOp) per_real_strain_s(dx, dy, dz, ri, ec, ex, xi, a2, s.s, acc);
+      if (TGT == kPOp) {
+        // E = al Sigma + be (x w + w x) + ga q x x (+ a trace the 5-basis drops), w = Sigma x, q = x.w
+        double abg[3];
+        per_real_es_radial(ri, ec, ex, xi, a2, abg);
+        double sxx, syy, sxy, sxz, syz;
+        basis_to_cart(s.s, sxx, syy, sxy, sxz, syz);
+        const double szz = -(sxx + syy);
+        const double wx = fma(sxx, dx, fma(sxy, dy, sxz * dz));
+        const double wy = fma(sxy, dx, fma(syy, dy, syz * dz));
+        const double wz = fma(sxz, dx, fma(syz, dy, szz * dz));
+        const double q = fma(dx, wx, fma(dy, wy, dz * wz));
+        const double b2 = 2.0 * abg[1], gq = abg[2] * q;
+        // M = be (x w + w x) + ga q x x: diagonal M_ii and doubled off-diagonals 2 M_ij
+        const double mxx = fma(b2 * dx, wx, gq * dx * dx), myy = fma(b2 * dy, wy, gq * dy * dy),
+                     mzz = fma(b2 * dz, wz, gq * dz * dz);
+        const double mxy = fma(b2, fma(dx, wy, dy * wx), 2.0 * gq * dx * dy);
+        const double mxz = fma(b2, fma(dx, wz, dz * wx), 2.0 * gq * dx * dz);
+        const double myz = fma(b2, fma(dy, wz, dz * wy), 2.0 * gq * dy * dz);
+        acc[0] = fma(abg[0], s.s[0], fma(RS2, mxx - myy, acc[0]));
+        acc[1] = fma(abg[0], s.s[1], fma(RS6, 2.0 * mzz - mxx - myy, acc[1]));
+        acc[2] = fma(abg[0], s.s[2], fma(RS2, mxy, acc[2]));
+        acc[3] = fma(abg[0], s.s[3], fma(RS2, mxz, acc[3]));
+        acc[4] = fma(abg[0], s.s[4], fma(RS2, myz, acc[4]));
+      }
       if (TGT == kPRhs) per_real_strain_ftq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.q, acc);
       if (TGT == kPOut) per_real_motion_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc, acc + 3);
       if (TGT == kPFlow) per_real_flow_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc);

@@ -23,7 +23,10 @@ P = 1/(8 pi eta):
 
     real space (x the separation, r = |x|, ri = 1/r, ec = erfc(xi r), ex = exp(-xi^2 r^2)):
         per_real_strain_s, per_real_strain_ftq, per_real_motion_ftsq   (accumulate e[5] / u[3], w[3]),
-        per_real_flow_ftsq (the flow itself at a field point, accumulate u[3])
+        per_real_flow_ftsq (the flow itself at a field point, accumulate u[3]),
+        per_real_es_radial (the radial functions al, be, ga of the stresslet strain's isotropic form
+        E = al Sigma + be (x (Sigma x) + (Sigma x) x) + ga (x.Sigma x) x x + (trace), which the operator
+        pass contracts itself: about a tenth of the operations of per_real_strain_s)
     Fourier space (k, ik2 = 1/k^2, the complex structure factors of the coefficients split into real
     and imaginary parts; the splitting factor and 1/L^3 applied by the caller):
         per_hat_strain_s, per_hat_strain_ftq, per_hat_motion_ftsq, per_hat_flow_ftsq
@@ -242,6 +245,33 @@ def _complex_parts(exprs, coeffs, re_syms, im_syms):
     return out_re, out_im
 
 
+def stresslet_radial():
+    """The real-space strain of a stresslet through the screened kernel in its isotropic form,
+    E = al Sigma + be (x (Sigma x) + (Sigma x) x) + ga (x.Sigma x) x x + de (x.Sigma x) I: the radial
+    functions read off along the z axis and the form then checked for a general separation."""
+    rl = _Real()
+    K = rl.kernel()
+    sxx, syy, sxy, sxz, syz = sp.symbols("sxx syy sxy sxz syz", real=True)
+    S = [[sxx, sxy, sxz], [sxy, syy, syz], [sxz, syz, -sxx - syy]]
+    u = [_faxen(rl, sum(rl.d(K[i][j], k) * S[j][k] for j in range(3) for k in range(3)), 1) for i in range(3)]
+    v = [_faxen(rl, ui, 1) for ui in u]
+    E = [[rl.red(sp.Rational(1, 2) * (rl.d(v[i], j) + rl.d(v[j], i))) for j in range(3)] for i in range(3)]
+    z = {X1: 0, X2: 0, X3: RR}
+    Ez = [[sp.expand(E[i][j].subs(z)) for j in range(3)] for i in range(3)]
+    al = sp.expand(Ez[0][1].coeff(sxy))
+    be = sp.expand((Ez[0][2].coeff(sxz) - al) / RR ** 2)
+    de = sp.expand(-(Ez[0][0] - al * sxx).coeff(syy) / RR ** 2)
+    ga = sp.expand((-Ez[2][2].coeff(syy) - al - 2 * be * RR ** 2 - de * RR ** 2) / RR ** 4)
+    w = [sum(S[i][j] * _XV[j] for j in range(3)) for i in range(3)]
+    q = sum(_XV[i] * w[i] for i in range(3))
+    for i in range(3):
+        for j in range(i, 3):
+            form = al * S[i][j] + be * (_XV[i] * w[j] + w[i] * _XV[j]) + ga * q * _XV[i] * _XV[j] + de * q * int(i == j)
+            if rl.red(E[i][j] - form) != 0:
+                raise AssertionError("the screened stresslet strain is not of the isotropic form")
+    return al, be, ga
+
+
 def generate():
     f = sp.symbols("f0:3")
     t = sp.symbols("t0:3")
@@ -263,6 +293,9 @@ def generate():
     parts.append(_emit("per_real_motion_ftsq", geo + ", const double* f, const double* t, const double* s, "
                        "const double* q, double* u, double* w", [("u", c, "+=") for c in range(3)] +
                        [("w", c, "+=") for c in range(3)], U + W, list(f) + list(t) + list(s) + list(q), sub))
+    al, be, ga = stresslet_radial()
+    parts.append(_emit("per_real_es_radial", "double ri, double ec, double ex, double xi, double a2, double* abg",
+                       [("abg", 0, "="), ("abg", 1, "="), ("abg", 2, "=")], [al, be, ga], [EC, EX], sub))
     ff = source_flow(rl, Kr, f, t, s, q)
     parts.append(_emit("per_real_flow_ftsq", geo + ", const double* f, const double* t, const double* s, "
                        "const double* q, double* u", [("u", c, "+=") for c in range(3)], ff,
@@ -323,7 +356,7 @@ def generate():
             nm = str(sym)
             m = re.match(r"([a-z]+)(\d+)$", nm)
             sym_map[nm] = "%s[%s]" % (m.group(1), m.group(2))
-    names = ("per_real_strain_s", "per_real_strain_ftq", "per_real_motion_ftsq", "per_real_flow_ftsq",
+    names = ("per_real_strain_s", "per_real_strain_ftq", "per_real_motion_ftsq", "per_real_es_radial", "per_real_flow_ftsq",
              "per_hat_strain_s", "per_hat_strain_ftq", "per_hat_motion_ftsq", "per_hat_flow_ftsq")
     body, counts = [], []
     for (code, nops), nm in zip(parts, names):

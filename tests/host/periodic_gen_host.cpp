@@ -52,6 +52,11 @@ void ev_hat(int which, int n, const double* k, double a2, const double* fr, cons
                              sr + 5 * p, si + 5 * p, qr + 3 * p, qi + 3 * p, outr + 3 * p, outi + 3 * p);
   }
 }
+// radial functions (al, be, ga) of the screened stresslet strain at distances r [n]
+void ev_es_radial(int n, const double* r, double xi, double a2, double* abg) {
+  for (int p = 0; p < n; ++p)
+    mbs::per_real_es_radial(1.0 / r[p], std::erfc(xi * r[p]), std::exp(-xi * xi * r[p] * r[p]), xi, a2, abg + 3 * p);
+}
 void ev_self(double xi, double a2, double* out) {
   out[0] = mbs::per_self_es(xi, a2);
   out[1] = mbs::per_self_uf(xi, a2);

@@ -107,3 +107,26 @@ def test_generated_self_constants_match_oracle(lib):
         want = periodic._smooth_self(tgt, src, XI, A, ETA)
         scale = A ** 5 / 20 if src == "D" else P
         assert np.abs(want - c * scale * np.eye(dim)).max() < 1e-12 * abs(c * scale), (tgt, src)
+
+
+def test_generated_radial_stresslet_strain_matches_oracle(lib):
+    """The operator pass contracts the screened stresslet strain from three radial functions,
+    E = al Sigma + be (x (Sigma x) + (Sigma x) x) + ga (x.Sigma x) x x (+ a trace): with the generated
+    al, be, ga that form is the oracle's real-space block."""
+    from oracle import basis
+    rng = np.random.default_rng(4)
+    n = 40
+    x = rng.standard_normal((n, 3)) * 4.0
+    r = np.sqrt((x ** 2).sum(1))
+    abg = np.zeros((n, 3))
+    lib.ev_es_radial(n, _p(r), ctypes.c_double(XI), ctypes.c_double(A * A), abg.ctypes.data_as(ctypes.c_void_p))
+    S5 = rng.standard_normal((n, 5))
+    S = np.stack([basis.from5(v) for v in S5])
+    w = np.einsum("pij,pj->pi", S, x)
+    q = np.einsum("pi,pi->p", x, w)
+    E = (abg[:, 0, None, None] * S + abg[:, 1, None, None] * (x[:, :, None] * w[:, None, :] + w[:, :, None] * x[:, None, :])
+         + (abg[:, 2] * q)[:, None, None] * x[:, :, None] * x[:, None, :])
+    got = P * np.stack([basis.to5(e) for e in E])
+    want = np.einsum("pij,pj->pi", periodic.real_block("E", "S", x, XI, A, ETA), S5)
+    assert _close(got, want)
+
