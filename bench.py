@@ -754,7 +754,10 @@ def bench_periodic(ctx, a):
     (0.004 spheres per a^3 on jittered lattice sites): the operator
     at 10^4 and 10^5 spheres against the unbounded operator of the same spheres, and at 10^4 the
     right-hand side, outputs and the solve to 1e-10 (binary64, and with the near-field preconditioner
-    at 8a). Default splitting. Median of 5 launches after 2 warm-ups, HIP events."""
+    at 8a). Default splitting. The same with smooth particle-mesh Ewald (params.ewald_mesh, mesh spacing
+    at most 1.25a, default splitting for the mesh), with the largest relative difference of its
+    operator from the direct sums', and the mesh operator alone at 10^6 spheres beside one direct
+    pass. Median of 5 launches after 2 warm-ups, HIP events."""
     import statistics
 
     import numpy as np
@@ -786,7 +789,14 @@ def bench_periodic(ctx, a):
         sites = sites[rng.choice(len(sites), n, replace=False)]
         return sites + rng.uniform(-1.0, 1.0, (n, 3)) * max(0.0, (h - 2.2) / 2)
 
+    def mesh_for(L):
+        M = 16
+        while L / M > 1.25:
+            M *= 2
+        return M
+
     out = {"density": 0.004, "splitting": "default: xi L = max(13, 13 (n/1e4)^0.15), rc = 6.5/xi, kmax = 13 xi",
+           "mesh_splitting": "default: xi = min(pi M / (14 L), 0.5/a), rc = 5/xi, B-splines of order 8",
            "positions": "jittered cubic lattice sites, minimum-image distance >= 2.2a; orientations, slip and "
                         "forces of the trap workload"}
     for n, seed in ((10_000, 1), (a.n, a.seed)):
@@ -818,9 +828,48 @@ def bench_periodic(ctx, a):
                 med = sorted(sts, key=lambda t: t["t_total_ms"])[len(sts) // 2]
                 row["solve"][vname] = {"ms": round(med["t_total_ms"], 3), "iters": med["iters"],
                                        "rel_resid": med["rel_resid"]}
-        ctx.set_params(box=0.0, near_cutoff=0.0, precision=mbstokes.MBS_FP64)
+        ctx.set_params(box=L, near_cutoff=0.0, precision=mbstokes.MBS_FP64)
+        ctx.mbs_matvec(d["R"], x, y)  # the direct sums' operator, kept for the comparison
+        M = mesh_for(L)
+        ctx.set_params(box=L, ewald_mesh=M)
+        ym = torch.empty_like(x)
+        mesh = {"M": M, "matvec_ms": round(median_ms(lambda: ctx.mbs_matvec(d["R"], x, ym)), 4)}
+        mesh["vs_direct_maxrel"] = float((ym - y).abs().max() / y.abs().max())
+        if n <= 20_000:
+            mesh["rhs_ms"] = round(median_ms(lambda: ctx.mbs_rhs(d["R"], d["v2s"], None, d["Fe"], None, b=y)), 4)
+            mesh["outputs_ms"] = round(median_ms(lambda: ctx.mbs_outputs(d["R"], x, d["v1s"], d["v2s"], None, d["Fe"],
+                                                                           None, V=V, W=W, S=S)), 4)
+            ctx.set_params(box=L, ewald_mesh=M, tol=1e-10, guess=mbstokes.MBS_GUESS_ZERO)
+            sts = []
+            for k in range(3):
+                _, _, _, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+                if k:
+                    sts.append(st)
+            med = sorted(sts, key=lambda t: t["t_total_ms"])[len(sts) // 2]
+            mesh["solve_fp64"] = {"ms": round(med["t_total_ms"], 3), "iters": med["iters"],
+                                  "rel_resid": med["rel_resid"]}
+        row["mesh"] = mesh
+        ctx.set_params(box=0.0, ewald_mesh=0, near_cutoff=0.0, precision=mbstokes.MBS_FP64)
         out["n%d" % n] = row
-        print(f"bench: periodic n={n} {row.get('matvec_ms')} ms", file=sys.stderr, flush=True)
+        print(f"bench: periodic n={n} {row.get('matvec_ms')} ms, mesh {mesh['matvec_ms']} ms", file=sys.stderr,
+              flush=True)
+    n = 1_000_000
+    L = (n / 0.004) ** (1.0 / 3.0)
+    w = inputs.trap_workload(n, L, 3)
+    w.R = lattice_positions(n, L, 3)
+    d = mbstokes.to_device(w, "cuda:0")
+    x = d["v2s"].contiguous()
+    y, ym = torch.empty_like(x), torch.empty_like(x)
+    M = mesh_for(L)
+    ctx.set_params(box=L, ewald_mesh=M)
+    row = {"n": n, "box": L, "M": M, "mesh_matvec_ms": round(median_ms(lambda: ctx.mbs_matvec(d["R"], x, ym)), 4)}
+    print(f"bench: periodic n={n} mesh {row['mesh_matvec_ms']} ms", file=sys.stderr, flush=True)
+    ctx.set_params(box=L, ewald_mesh=0)
+    row["direct_matvec_ms_one_pass"] = round(median_ms(lambda: ctx.mbs_matvec(d["R"], x, y), warm=0, reps=1), 1)
+    row["mesh_vs_direct_maxrel"] = float((ym - y).abs().max() / y.abs().max())
+    ctx.set_params(box=0.0, ewald_mesh=0)
+    out["n%d" % n] = row
+    print(f"bench: periodic n={n} direct {row['direct_matvec_ms_one_pass']} ms", file=sys.stderr, flush=True)
     return out
 
 

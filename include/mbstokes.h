@@ -157,7 +157,22 @@ typedef struct mbs_params {
                             (MBS_EUNSUPPORTED). The near-field
                             preconditioner keeps the free-space pairs. 0 = unbounded fluid (default);
                             other values are MBS_EINVAL */
-  int32_t reserved0;
+  int32_t ewald_mesh;    /* box > 0: 0 = the Fourier part of the Ewald sums directly over the wave
+                            vectors (O(N K), the default); M = a power of 2 from 16 to 512: smooth
+                            particle-mesh Ewald on an M^3 mesh of spacing box/M, the fast
+                            matrix-vector product that the paper leaves to future work (SIV): every
+                            sphere's coefficients spread onto the mesh by cardinal B-splines of
+                            order 8, one 3D FFT, the same Fourier multipliers per mesh wave vector
+                            (|m| < M/2 per axis), the inverse FFT interpolated back with the same
+                            weights, so a pass costs O(N + M^3 log M) with the real-space part kept
+                            within rc = 5/xi; ewald_xi defaults to pi M/(14 box), kept at most
+                            0.5/a and at least 10/box, and an explicit xi * box must be at least 10.
+                            The result carries the mesh's interpolation error, about 1e-6 of the
+                            Fourier part at the default xi (smaller xi or larger M: smaller), instead
+                            of the direct sums' 1e-13; it grows roughly as (xi a)^7 once xi a exceeds
+                            about 0.5 (boxes under 20a). Device memory: 160 M^3
+                            bytes of mesh fields plus about 270 bytes per sphere. Other values are
+                            MBS_EINVAL, as is a mesh without a box */
   double  plane_z;       /* height of the plane (plane != 0) */
   double  box;           /* > 0: the spheres fill a periodic cubic box of this side (the paper's remark
                             that periodic domains follow from the periodic Green's function, whose

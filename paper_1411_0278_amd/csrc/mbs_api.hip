@@ -85,6 +85,9 @@ struct mbs_ctx {
   DevBuf per_seg;  // their row segments: 8-long then 4-long, (first, count) pairs
   int per_K = 0, per_nseg8 = 0, per_nseg4 = 0;
   double per_L = 0.0, per_kmax = 0.0;
+  DevBuf per_tab;  // particle-mesh Ewald: the mesh's twiddles and B-spline factors
+  DevBuf per_mws;  // particle-mesh Ewald: mesh fields, weights and the sources' box grid
+  int per_tabM = 0;
   // a solve in the Morton order of the centres: the permutation and the reordered inputs/outputs
   DevBuf ord;
   // single-configuration GMRES: Arnoldi steps captured as graphs (per precision), see step_graphs
@@ -184,8 +187,13 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
   if (p->plane && !isfinite(p->plane_z)) return set_err(c, MBS_EINVAL, "plane_z must be finite");
   if (!(p->box >= 0.0) || !isfinite(p->box)) return set_err(c, MBS_EINVAL, "box must be finite and >= 0");
   if (!(p->ewald_xi >= 0.0) || !isfinite(p->ewald_xi)) return set_err(c, MBS_EINVAL, "ewald_xi must be finite and >= 0");
-  if (p->box > 0.0 && p->ewald_xi > 0.0 && p->ewald_xi * p->box < 13.0)
+  if (p->ewald_mesh != 0 && (p->ewald_mesh < 16 || p->ewald_mesh > 512 || (p->ewald_mesh & (p->ewald_mesh - 1))))
+    return set_err(c, MBS_EINVAL, "ewald_mesh must be 0 or a power of 2 from 16 to 512");
+  if (p->ewald_mesh && !(p->box > 0.0)) return set_err(c, MBS_EINVAL, "ewald_mesh needs a periodic box");
+  if (p->box > 0.0 && p->ewald_xi > 0.0 && !p->ewald_mesh && p->ewald_xi * p->box < 13.0)
     return set_err(c, MBS_EINVAL, "ewald_xi * box must be at least 13 (real-space cutoff within box/2)");
+  if (p->box > 0.0 && p->ewald_mesh && p->ewald_xi > 0.0 && p->ewald_xi * p->box < 10.0)
+    return set_err(c, MBS_EINVAL, "ewald_xi * box must be at least 10 with a mesh (real-space cutoff within box/2)");
   if (p->box > 0.0 && p->plane) return set_err(c, MBS_EINVAL, "box and plane exclude each other");
   return MBS_OK;
 }
@@ -204,18 +212,49 @@ void apply_tiles(mbs_ctx* c) {
 bool periodic(const mbs_ctx* c) { return c->prm.box > 0.0; }
 // default splitting: xi L = max(13, 13 (n/10^4)^0.15), measured to balance the real-space pass (whose
 // pairs within rc fall as (xi L)^-3) against the Fourier passes (whose wave vectors grow as (xi L)^3)
+// With a mesh of M points per axis the default is xi = pi M / (14 box): the splitting factor
+// exp(-k^2 / 4 xi^2) at the mesh's Nyquist wave number pi M / box is then exp(-49/4) ~ 5e-6, which
+// with B-splines of order 8 keeps the mesh error near 1e-6 of the Fourier part. The finite-size
+// factors of the multipliers grow as (a k)^4, so on meshes finer than the spheres (spacing below
+// about a/2) the error grows roughly as (xi a)^7: xi is kept at most 0.5/a there, and at least 10/box
+// (the real-space cutoff within box/2).
 double per_xi(const mbs_ctx* c, int64_t n) {
   if (c->prm.ewald_xi > 0.0) return c->prm.ewald_xi;
+  if (c->prm.ewald_mesh)
+    return std::max(10.0 / c->prm.box, std::min(M_PI * c->prm.ewald_mesh / (14.0 * c->prm.box), 0.5 / c->prm.a));
   return std::max(13.0, 13.0 * pow((double)n / 1e4, 0.15)) / c->prm.box;
+}
+// the real-space cutoff: 6.5/xi for the direct sums (below 1e-13 of the blocks), 5/xi with a mesh
+// (below 1e-9, well under the mesh's own error); the cells of the sources' box grid at least rc
+double per_rc(const mbs_ctx* c, double xi) {
+  return std::min((c->prm.ewald_mesh ? 5.0 : 6.5) / xi, 0.5 * c->prm.box);
+}
+int per_nc(const mbs_ctx* c, double xi) {
+  return std::max(1, std::min(256, (int)floor(c->prm.box / per_rc(c, xi))));
 }
 PerBox per_box(const mbs_ctx* c, int64_t n) {
   const double xi = per_xi(c, n);
   const int2* seg = reinterpret_cast<const int2*>(c->per_seg.p);
-  return PerBox{c->prm.box, xi, std::min(6.5 / xi, 0.5 * c->prm.box), c->per_K, c->per_kv.p,
-                seg, c->per_nseg8, seg + c->per_nseg8, c->per_nseg4};
+  return PerBox{c->prm.box, xi, per_rc(c, xi), c->per_K, c->per_kv.p, seg, c->per_nseg8,
+                seg ? seg + c->per_nseg8 : nullptr, c->per_nseg4, c->prm.ewald_mesh, per_nc(c, xi),
+                c->per_tab.p, c->per_mws.p};
+}
+// the mesh's tables and workspace for n sources (particle-mesh Ewald)
+int pm_prepare(mbs_ctx* c, int64_t n) {
+  const int M = c->prm.ewald_mesh;
+  if (c->per_tabM != M || !c->per_tab.p) {
+    const std::vector<double> t = pm_tables(M);
+    CHK(ensure(c, c->per_tab, t.size()));
+    HIPCHK(c, hipMemcpy(c->per_tab.p, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->per_tabM = M;
+  }
+  const size_t bytes = pm_ws_bytes(M, n, per_nc(c, per_xi(c, n)));
+  CHK(ensure(c, c->per_mws, (bytes + 7) / 8));
+  return MBS_OK;
 }
 // (re)builds the wave-vector list when the box or the splitting changed (outside any graph capture)
 int per_prepare(mbs_ctx* c, int64_t n) {
+  if (c->prm.ewald_mesh) return pm_prepare(c, n);
   const double kmax = 13.0 * per_xi(c, n);
   if (c->per_kv.p && c->per_L == c->prm.box && c->per_kmax == kmax) return MBS_OK;
   const std::vector<double> kv = per_kvecs(c->prm.box, kmax);
@@ -439,7 +478,8 @@ StepGraphs* step_graphs(mbs_ctx* c, int prec, int64_t n, const double* R, bool p
       dbits(c->ph.P), dbits(c->ph.a2),
       dbits(c->ph.gamma), dbits(c->ph.inv_gamma), (uintptr_t)c->prm.plane, dbits(c->prm.plane_z),
       dbits(c->prm.box), dbits(c->prm.ewald_xi), (uintptr_t)c->per_kv.p, (uintptr_t)c->per_K,
-      (uintptr_t)c->per_seg.p, (uintptr_t)c->per_nseg8};
+      (uintptr_t)c->per_seg.p, (uintptr_t)c->per_nseg8, (uintptr_t)c->prm.ewald_mesh, (uintptr_t)c->per_tab.p,
+      (uintptr_t)c->per_mws.p};
   StepGraphs& G = c->sgraph[prec == MBS_FP64 ? 0 : 1];
   if (key == G.key) return &G;
   G.reset();
@@ -1352,6 +1392,7 @@ void mbs_default_params(mbs_params* p) {
   p->plane_z = 0.0;
   p->box = 0.0;
   p->ewald_xi = 0.0;
+  p->ewald_mesh = 0;
 }
 
 int mbs_create(mbs_ctx** out, int device, const mbs_params* prm) {
@@ -1400,7 +1441,7 @@ void mbs_destroy(mbs_ctx* c) {
                     &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig, &c->near, &c->zt,
                     &c->nt, &c->stepstate,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
-                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->ord, &c->r3, &c->per_kv, &c->per_seg,
+                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->ord, &c->r3, &c->per_kv, &c->per_seg, &c->per_tab, &c->per_mws,
                     &c->bat, &c->btune};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);

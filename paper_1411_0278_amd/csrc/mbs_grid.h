@@ -58,5 +58,10 @@ size_t grid_ws_bytes(int n, int64_t max_cells);
 // memory of grid_ws_bytes(n, max_cells) bytes (256-byte aligned). Returns a HIP error code.
 hipError_t grid_build(const double* R, int n, double h_min, int64_t max_cells, void* ws,
                       size_t ws_bytes, GridView* view, hipStream_t s);
+// The same for the centres of a periodic cubic box of side L: nc cells of edge L / nc per axis from
+// the origin (nc <= 1024), every centre wrapped into [0, L) first (Rs holds the wrapped centres);
+// ws: grid_ws_bytes(n, nc^3) bytes.
+hipError_t grid_build_box(const double* R, int n, double L, int nc, void* ws, size_t ws_bytes,
+                          GridView* view, hipStream_t s);
 
 }  // namespace mbs

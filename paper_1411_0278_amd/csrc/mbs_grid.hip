@@ -126,14 +126,39 @@ __global__ void __launch_bounds__(256) k_grid_params(const double* __restrict__ 
   *hdr = H;
 }
 
-__global__ void k_cell_keys(const double* __restrict__ R, int n, const GridHdr* __restrict__ hdr,
+// a periodic box of side L > 0: the centre wrapped into [0, L); L = 0: unchanged
+__device__ __forceinline__ double box_wrap(double x, double L) {
+  if (!(L > 0.0)) return x;
+  double w = x - L * floor(x / L);
+  if (w >= L) w -= L;
+  if (w < 0.0) w += L;
+  return w;
+}
+
+// a periodic box: nc cells of edge L / nc along each axis, from the origin
+__global__ void k_grid_params_box(int n, double L, int nc, GridHdr* __restrict__ hdr) {
+  if (threadIdx.x != 0) return;
+  GridHdr H;
+  for (int d = 0; d < 3; ++d) {
+    H.lo[d] = 0.0;
+    H.g[d] = nc;
+  }
+  H.h = L / nc;
+  H.inv_h = nc / L;
+  H.maxocc = 0;
+  H.n = n;
+  H.pad = 0;
+  *hdr = H;
+}
+
+__global__ void k_cell_keys(const double* __restrict__ R, int n, double L, const GridHdr* __restrict__ hdr,
                             uint32_t* __restrict__ key, int32_t* __restrict__ idx) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const GridHdr H = *hdr;
-  const int cx = grid_cell1(R[3 * (int64_t)i], H.lo[0], H.inv_h, H.g[0]);
-  const int cy = grid_cell1(R[3 * (int64_t)i + 1], H.lo[1], H.inv_h, H.g[1]);
-  const int cz = grid_cell1(R[3 * (int64_t)i + 2], H.lo[2], H.inv_h, H.g[2]);
+  const int cx = grid_cell1(box_wrap(R[3 * (int64_t)i], L), H.lo[0], H.inv_h, H.g[0]);
+  const int cy = grid_cell1(box_wrap(R[3 * (int64_t)i + 1], L), H.lo[1], H.inv_h, H.g[1]);
+  const int cz = grid_cell1(box_wrap(R[3 * (int64_t)i + 2], L), H.lo[2], H.inv_h, H.g[2]);
   key[i] = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
   idx[i] = i;
 }
@@ -146,16 +171,16 @@ __global__ void k_clear_cells(int32_t* __restrict__ start, int32_t* __restrict__
 }
 
 __global__ void k_cell_ranges(const uint32_t* __restrict__ key, const int32_t* __restrict__ perm,
-                              const double* __restrict__ R, int n, GridHdr* __restrict__ hdr,
+                              const double* __restrict__ R, int n, double L, GridHdr* __restrict__ hdr,
                               int32_t* __restrict__ start, int32_t* __restrict__ end, double* __restrict__ Rs) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const GridHdr H = *hdr;
   const uint32_t kk = key[k];
   const int64_t i = perm[k];
-  Rs[4 * (int64_t)k] = R[3 * i];
-  Rs[4 * (int64_t)k + 1] = R[3 * i + 1];
-  Rs[4 * (int64_t)k + 2] = R[3 * i + 2];
+  Rs[4 * (int64_t)k] = box_wrap(R[3 * i], L);
+  Rs[4 * (int64_t)k + 1] = box_wrap(R[3 * i + 1], L);
+  Rs[4 * (int64_t)k + 2] = box_wrap(R[3 * i + 2], L);
   Rs[4 * (int64_t)k + 3] = 0.0;
   const int c = grid_linear(H, (int)compact3(kk), (int)compact3(kk >> 1), (int)compact3(kk >> 2));
   if (k == 0 || key[k - 1] != kk) start[c] = k;
@@ -335,14 +360,46 @@ Layout layout(int n, int64_t max_cells) {
 
 size_t grid_ws_bytes(int n, int64_t max_cells) { return layout(n, max_cells).total; }
 
+namespace {
+
+// the sort, the cell ranges and the sorted centres, once the header is in place (box > 0: a
+// periodic box of that side, centres wrapped into it)
+hipError_t grid_finish(const double* R, int n, double box, int64_t max_cells, void* ws, GridView* view,
+                       hipStream_t s);
+
+}  // namespace
+
+hipError_t grid_build_box(const double* R, int n, double L, int nc, void* ws, size_t ws_bytes, GridView* view,
+                          hipStream_t s) {
+  if (n < 1 || nc < 1 || nc > (1 << kGridAxisBits) || !(L > 0.0)) return hipErrorInvalidValue;
+  const int64_t cells = (int64_t)nc * nc * nc;
+  const Layout Ly = layout(n, cells);
+  if (ws_bytes < Ly.total) return hipErrorInvalidValue;
+  GridHdr* hdr = (GridHdr*)((char*)ws + Ly.hdr);
+  hipLaunchKernelGGL(k_grid_params_box, dim3(1), dim3(64), 0, s, n, L, nc, hdr);
+  return grid_finish(R, n, L, cells, ws, view, s);
+}
+
 hipError_t grid_build(const double* R, int n, double h_min, int64_t max_cells, void* ws, size_t ws_bytes,
                       GridView* view, hipStream_t s) {
   if (n < 1 || max_cells < 1 || !(h_min > 0.0)) return hipErrorInvalidValue;
+  const Layout Ly = layout(n, max_cells);
+  if (ws_bytes < Ly.total) return hipErrorInvalidValue;
+  char* b = (char*)ws;
+  GridHdr* hdr = (GridHdr*)(b + Ly.hdr);
+  double* part = (double*)(b + Ly.part);
+  hipLaunchKernelGGL(k_box_part, dim3(kBoxParts), dim3(256), 0, s, R, n, part);
+  hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(kBoxParts), 0, s, part, n, h_min, max_cells, hdr);
+  return grid_finish(R, n, 0.0, max_cells, ws, view, s);
+}
+
+namespace {
+
+hipError_t grid_finish(const double* R, int n, double box, int64_t max_cells, void* ws, GridView* view,
+                       hipStream_t s) {
   const Layout L = layout(n, max_cells);
-  if (ws_bytes < L.total) return hipErrorInvalidValue;
   char* b = (char*)ws;
   GridHdr* hdr = (GridHdr*)(b + L.hdr);
-  double* part = (double*)(b + L.part);
   uint32_t* key_in = (uint32_t*)(b + L.key_in);
   uint32_t* key = (uint32_t*)(b + L.key);
   int32_t* idx_in = (int32_t*)(b + L.idx_in);
@@ -350,9 +407,7 @@ hipError_t grid_build(const double* R, int n, double h_min, int64_t max_cells, v
   double* Rs = (double*)(b + L.Rs);
   int32_t* start = (int32_t*)(b + L.start);
   int32_t* end = (int32_t*)(b + L.end);
-  hipLaunchKernelGGL(k_box_part, dim3(kBoxParts), dim3(256), 0, s, R, n, part);
-  hipLaunchKernelGGL(k_grid_params, dim3(1), dim3(kBoxParts), 0, s, part, n, h_min, max_cells, hdr);
-  hipLaunchKernelGGL(k_cell_keys, dim3(nblk(n, 256)), dim3(256), 0, s, R, n, hdr, key_in, idx_in);
+  hipLaunchKernelGGL(k_cell_keys, dim3(nblk(n, 256)), dim3(256), 0, s, R, n, box, hdr, key_in, idx_in);
   {  // stable radix sort (key_in, idx_in) -> (key, perm), ping-ponging through both pairs of buffers
     int32_t* hist = (int32_t*)(b + L.hist);
     int32_t* tot = (int32_t*)(b + L.tot);
@@ -373,7 +428,8 @@ hipError_t grid_build(const double* R, int n, double h_min, int64_t max_cells, v
     }
   }
   hipLaunchKernelGGL(k_clear_cells, dim3(nblk(max_cells, 256)), dim3(256), 0, s, start, end, max_cells);
-  hipLaunchKernelGGL(k_cell_ranges, dim3(nblk(n, 256)), dim3(256), 0, s, key, perm, R, n, hdr, start, end, Rs);
+  hipLaunchKernelGGL(k_cell_ranges, dim3(nblk(n, 256)), dim3(256), 0, s, key, perm, R, n, box, hdr, start, end,
+                     Rs);
   view->hdr = hdr;
   view->Rs = Rs;
   view->perm = perm;
@@ -382,5 +438,7 @@ hipError_t grid_build(const double* R, int n, double h_min, int64_t max_cells, v
   view->n = n;
   return hipGetLastError();
 }
+
+}  // namespace
 
 }  // namespace mbs

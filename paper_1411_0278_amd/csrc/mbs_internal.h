@@ -126,7 +126,15 @@ struct PerBox {
   int nseg8;
   const int2* seg4;
   int nseg4;
+  // smooth particle-mesh Ewald when M > 0: the Fourier part on an M^3 mesh (M a power of 2)
+  int M;
+  int nc;             // cells per axis of the sources' box grid
+  const double* tab;  // pm_tables(M) on the device
+  void* mws;          // pm_ws_bytes(M, n, nc) bytes of device workspace (256-byte aligned)
 };
+// mesh workspace bytes for n sources; the mesh's twiddles and B-spline factors (2M doubles)
+size_t pm_ws_bytes(int M, int64_t n, int nc);
+std::vector<double> pm_tables(int M);
 std::vector<double> per_kvecs(double L, double kmax);
 // (first wave vector, count) pairs: runs of consecutive k3 within one (k1, k2) row, at most maxlen
 std::vector<int> per_segments(const std::vector<double>& kv, double L, int maxlen);

@@ -27,6 +27,9 @@
 //                 factor exp(i dk z_n) (a sincos where a row starts and every 16 steps); grid.y
 //                 chunks of the wave vectors;
 //   k_per_finish  the chunks added in order, the self constants and the one-body terms.
+// With a mesh (smooth particle-mesh Ewald, below) the structure factors and reciprocal sums give way
+// to spreading, a 3D FFT, the multipliers per mesh wave vector, the inverse FFT and interpolation,
+// and the real-space pass walks the neighbouring cells of the sources' box grid.
 // Every sum runs in a fixed order (bitwise reproducible). The arithmetic is binary64 throughout.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -36,6 +39,7 @@
 #include <vector>
 
 #include "mbs_device.h"
+#include "mbs_grid.h"
 #include "mbs_internal.h"
 #include "mbs_periodic_gen.h"
 
@@ -100,6 +104,43 @@ __device__ __forceinline__ void coeffs(const RecP& r, double* v) {
 
 __device__ __forceinline__ double wrap(double d, double L, double invL) { return d - L * rint(d * invL); }
 
+// one source record's screened real-space term at a receiver (the pair within rc, not coincident)
+template <int TGT>
+__device__ __forceinline__ void real_pair(const RecP& s, double xi0, double yi0, double zi0, double L, double invL,
+                                          double xi, double a2, double* acc) {
+  const double dx = wrap(xi0 - s.x, L, invL), dy = wrap(yi0 - s.y, L, invL), dz = wrap(zi0 - s.z, L, invL);
+  const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  const double r = sqrt(r2);
+  const double ri = 1.0 / r, ec = erfc(xi * r), ex = exp(-xi * xi * r2);
+  if (TGT == kPOp) {
+    // E = al Sigma + be (x w + w x) + ga q x x (+ a trace the 5-basis drops), w = Sigma x, q = x.w
+    double abg[3];
+    per_real_es_radial(ri, ec, ex, xi, a2, abg);
+    double sxx, syy, sxy, sxz, syz;
+    basis_to_cart(s.s, sxx, syy, sxy, sxz, syz);
+    const double szz = -(sxx + syy);
+    const double wx = fma(sxx, dx, fma(sxy, dy, sxz * dz));
+    const double wy = fma(sxy, dx, fma(syy, dy, syz * dz));
+    const double wz = fma(sxz, dx, fma(syz, dy, szz * dz));
+    const double q = fma(dx, wx, fma(dy, wy, dz * wz));
+    const double b2 = 2.0 * abg[1], gq = abg[2] * q;
+    // M = be (x w + w x) + ga q x x: diagonal M_ii and doubled off-diagonals 2 M_ij
+    const double mxx = fma(b2 * dx, wx, gq * dx * dx), myy = fma(b2 * dy, wy, gq * dy * dy),
+                 mzz = fma(b2 * dz, wz, gq * dz * dz);
+    const double mxy = fma(b2, fma(dx, wy, dy * wx), 2.0 * gq * dx * dy);
+    const double mxz = fma(b2, fma(dx, wz, dz * wx), 2.0 * gq * dx * dz);
+    const double myz = fma(b2, fma(dy, wz, dz * wy), 2.0 * gq * dy * dz);
+    acc[0] = fma(abg[0], s.s[0], fma(RS2, mxx - myy, acc[0]));
+    acc[1] = fma(abg[0], s.s[1], fma(RS6, 2.0 * mzz - mxx - myy, acc[1]));
+    acc[2] = fma(abg[0], s.s[2], fma(RS2, mxy, acc[2]));
+    acc[3] = fma(abg[0], s.s[3], fma(RS2, mxz, acc[3]));
+    acc[4] = fma(abg[0], s.s[4], fma(RS2, myz, acc[4]));
+  }
+  if (TGT == kPRhs) per_real_strain_ftq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.q, acc);
+  if (TGT == kPOut) per_real_motion_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc, acc + 3);
+  if (TGT == kPFlow) per_real_flow_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc);
+}
+
 template <int TGT>
 __global__ void __launch_bounds__(kPBlk)
     k_per_real(const double* __restrict__ X, int m, const double* __restrict__ R, int n,
@@ -135,38 +176,7 @@ __global__ void __launch_bounds__(kPBlk)
     while (hits) {
       const int jj = __ffsll((unsigned long long)hits) - 1;
       hits &= hits - 1;
-      const RecP& s = tile[jj];
-      const double dx = wrap(xi0 - s.x, L, invL), dy = wrap(yi0 - s.y, L, invL), dz = wrap(zi0 - s.z, L, invL);
-      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      const double r = sqrt(r2);
-      const double ri = 1.0 / r, ec = erfc(xi * r), ex = exp(-xi * xi * r2);
-      if (TGT == kPOp) {
-        // E = al Sigma + be (x w + w x) + ga q x x (+ a trace the 5-basis drops), w = Sigma x, q = x.w
-        double abg[3];
-        per_real_es_radial(ri, ec, ex, xi, a2, abg);
-        double sxx, syy, sxy, sxz, syz;
-        basis_to_cart(s.s, sxx, syy, sxy, sxz, syz);
-        const double szz = -(sxx + syy);
-        const double wx = fma(sxx, dx, fma(sxy, dy, sxz * dz));
-        const double wy = fma(sxy, dx, fma(syy, dy, syz * dz));
-        const double wz = fma(sxz, dx, fma(syz, dy, szz * dz));
-        const double q = fma(dx, wx, fma(dy, wy, dz * wz));
-        const double b2 = 2.0 * abg[1], gq = abg[2] * q;
-        // M = be (x w + w x) + ga q x x: diagonal M_ii and doubled off-diagonals 2 M_ij
-        const double mxx = fma(b2 * dx, wx, gq * dx * dx), myy = fma(b2 * dy, wy, gq * dy * dy),
-                     mzz = fma(b2 * dz, wz, gq * dz * dz);
-        const double mxy = fma(b2, fma(dx, wy, dy * wx), 2.0 * gq * dx * dy);
-        const double mxz = fma(b2, fma(dx, wz, dz * wx), 2.0 * gq * dx * dz);
-        const double myz = fma(b2, fma(dy, wz, dz * wy), 2.0 * gq * dy * dz);
-        acc[0] = fma(abg[0], s.s[0], fma(RS2, mxx - myy, acc[0]));
-        acc[1] = fma(abg[0], s.s[1], fma(RS6, 2.0 * mzz - mxx - myy, acc[1]));
-        acc[2] = fma(abg[0], s.s[2], fma(RS2, mxy, acc[2]));
-        acc[3] = fma(abg[0], s.s[3], fma(RS2, mxz, acc[3]));
-        acc[4] = fma(abg[0], s.s[4], fma(RS2, myz, acc[4]));
-      }
-      if (TGT == kPRhs) per_real_strain_ftq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.q, acc);
-      if (TGT == kPOut) per_real_motion_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc, acc + 3);
-      if (TGT == kPFlow) per_real_flow_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc);
+      real_pair<TGT>(tile[jj], xi0, yi0, zi0, L, invL, xi, a2, acc);
     }
   }
   if (i >= m) return;
@@ -421,6 +431,344 @@ __global__ void __launch_bounds__(256) k_min_finish(const double* __restrict__ p
   if (threadIdx.x == 0) out[0] = sqrt(red[0]);
 }
 
+// ---------------------------------------------------------------- smooth particle-mesh Ewald
+// With a mesh of M^3 points (spacing h = L / M) the Fourier sum runs on the mesh instead of over the
+// spheres: exp(-i k.R) is interpolated by cardinal B-splines of order kPmP on the mesh points around
+// R (Euler exponential splines, the interpolation's error corrected in Fourier space by |b(m)|^2),
+// so the structure factors become one discrete Fourier transform of the source coefficients spread
+// onto the mesh, the multiplier is applied per mesh wave vector, and the inverse transform is
+// interpolated back at the receivers with the same weights: O(N P^3 + M^3 log M) instead of O(N K).
+constexpr int kPmP = 8;    // B-spline order (support of P mesh points per axis)
+constexpr int kPmB = 8;    // mesh block edge of the spreading kernel
+constexpr int kPmT = 64;   // candidate sources per LDS tile of the spreading kernel
+
+// the weights of mesh points b0 + o, o = 0..P-1, for a scaled coordinate u = floor(u) + t with
+// b0 = floor(u) - P + 1: w[o] = M_P(t + P - 1 - o), the B-spline built up from order 2 by its
+// two-term recursion M_n(x) = (x M_{n-1}(x) + (n - x) M_{n-1}(x - 1)) / (n - 1)
+__host__ __device__ inline void bspline_w(double t, double* w) {
+  double v[kPmP];  // v[o] = M_n(t + o), o < n
+  v[0] = t;
+  v[1] = 1.0 - t;
+  for (int n = 3; n <= kPmP; ++n) {
+    const double inv = 1.0 / (n - 1);
+    v[n - 1] = (1.0 - t) * v[n - 2] * inv;
+    for (int o = n - 2; o >= 1; --o) v[o] = ((t + o) * v[o] + (n - t - o) * v[o - 1]) * inv;
+    v[0] = t * v[0] * inv;
+  }
+  for (int o = 0; o < kPmP; ++o) w[o] = v[kPmP - 1 - o];
+}
+
+// the c-th source coefficient of sphere j, in the order the structure factors hold them
+template <int TGT>
+__device__ __forceinline__ double pm_coef(int c, int64_t j, const double* __restrict__ Fe,
+                                          const double* __restrict__ Te, const double* __restrict__ Sig,
+                                          const double* __restrict__ D, double P, double a5_20) {
+  if (TGT == kPOp) return Sig ? P * Sig[5 * j + c] : 0.0;
+  if (TGT == kPRhs) {
+    if (c < 3) return Fe ? P * Fe[3 * j + c] : 0.0;
+    if (c < 6) return Te ? P * Te[3 * j + c - 3] : 0.0;
+    return D ? a5_20 * D[3 * j + c - 6] : 0.0;
+  }
+  if (c < 3) return Fe ? P * Fe[3 * j + c] : 0.0;
+  if (c < 6) return Te ? P * Te[3 * j + c - 3] : 0.0;
+  if (c < 11) return Sig ? P * Sig[5 * j + c - 6] : 0.0;
+  return D ? a5_20 * D[3 * j + c - 11] : 0.0;
+}
+
+// per sphere in the box grid's order (wrapped centres Rs): first mesh point and weights per axis
+__global__ void __launch_bounds__(256) k_pm_prep(const double* __restrict__ Rs, int n, int M, double inv_h,
+                                                 int* __restrict__ b0, double* __restrict__ wts) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  for (int d = 0; d < 3; ++d) {
+    const double u = Rs[4 * (int64_t)k + d] * inv_h;
+    const double fu = floor(u);
+    double w[kPmP];
+    bspline_w(u - fu, w);
+    b0[4 * (int64_t)k + d] = ((int)fu - (kPmP - 1)) & (M - 1);
+    for (int o = 0; o < kPmP; ++o) wts[(3 * (int64_t)k + d) * kPmP + o] = w[o];
+  }
+  b0[4 * (int64_t)k + 3] = 0;
+}
+
+// the real-space pass over the sources' box grid (cells of edge >= rc, at least 3 per axis, so a
+// receiver's partners within rc lie in its own and the 26 neighbouring cells, each met once): a
+// workgroup per (cell, layer of neighbouring cells along z), its receivers 64 at a time, the 9 cells
+// of the layer staged through LDS with the same bit-mask evaluation as k_per_real; partial sums
+// part[(layer * m + i) * W] at the receivers' own indices
+template <int TGT>
+__global__ void __launch_bounds__(64)
+    k_pm_real(const double* __restrict__ Rs, const int32_t* __restrict__ perm, const int32_t* __restrict__ cstart,
+              const int32_t* __restrict__ cend, int nc, int m, const double* __restrict__ Fe,
+              const double* __restrict__ Te, const double* __restrict__ Sig, const double* __restrict__ D, double L,
+              double invL, double rc2, double xi, double a2, double P, double a5_20, double* __restrict__ part) {
+  __shared__ RecP tile[kPTJ];
+  constexpr int W = pw(TGT);
+  const int cell = blockIdx.x;
+  const int ix = cell % nc, iy = (cell / nc) % nc, iz = cell / (nc * nc);
+  const int jz = (iz + (int)blockIdx.y - 1 + nc) % nc;
+  const int r0 = cstart[cell], r1 = cend[cell];
+  for (int rb = r0; rb < r1; rb += 64) {
+    const int k = rb + threadIdx.x;
+    const int kk = k < r1 ? k : r1 - 1;
+    const double xi0 = Rs[4 * (int64_t)kk], yi0 = Rs[4 * (int64_t)kk + 1], zi0 = Rs[4 * (int64_t)kk + 2];
+    double acc[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) acc[c] = 0.0;
+    for (int nb = 0; nb < 9; ++nb) {
+      const int jx = (ix + nb % 3 - 1 + nc) % nc, jy = (iy + nb / 3 - 1 + nc) % nc;
+      const int sc = (jz * nc + jy) * nc + jx;
+      const int s0 = cstart[sc], s1 = cend[sc];
+      for (int jt = s0; jt < s1; jt += kPTJ) {
+        const int cnt = min(kPTJ, s1 - jt);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+          const int64_t j = perm[jt + t];
+          RecP r;
+          r.pad = 0.0;
+          r.x = Rs[4 * (int64_t)(jt + t)];
+          r.y = Rs[4 * (int64_t)(jt + t) + 1];
+          r.z = Rs[4 * (int64_t)(jt + t) + 2];
+          for (int c = 0; c < 3; ++c) {
+            r.f[c] = (TGT != kPOp && Fe) ? P * Fe[3 * j + c] : 0.0;
+            r.t[c] = (TGT != kPOp && Te) ? P * Te[3 * j + c] : 0.0;
+            r.q[c] = (TGT != kPOp && D) ? a5_20 * D[3 * j + c] : 0.0;
+          }
+          for (int c = 0; c < 5; ++c) r.s[c] = (TGT != kPRhs && Sig) ? P * Sig[5 * j + c] : 0.0;
+          tile[t] = r;
+        }
+        __syncthreads();
+        uint64_t hits = 0;
+#pragma unroll 8
+        for (int q = 0; q < cnt; ++q) {
+          const double dx = wrap(xi0 - tile[q].x, L, invL), dy = wrap(yi0 - tile[q].y, L, invL),
+                       dz = wrap(zi0 - tile[q].z, L, invL);
+          const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          hits |= (uint64_t)(r2 < rc2 && r2 > 0.0) << q;
+        }
+        while (hits) {
+          const int q = __ffsll((unsigned long long)hits) - 1;
+          hits &= hits - 1;
+          real_pair<TGT>(tile[q], xi0, yi0, zi0, L, invL, xi, a2, acc);
+        }
+      }
+    }
+    if (k < r1) {
+      double* o = part + ((int64_t)blockIdx.y * m + perm[k]) * W;
+#pragma unroll
+      for (int c = 0; c < W; ++c) o[c] = acc[c];
+    }
+  }
+}
+
+// Q_c(g) = sum_j c_j W_j(g) on one 8^3 block of the mesh, coefficients [C0, C0 + CN) (C0 even),
+// written in pairs as complex fields (Q_{C0}, Q_{C0+1}), ... from field C0/2 on. A thread holds one
+// line of 8 points along x; the candidate spheres (those binned in the cells that reach the block)
+// pass through LDS in the grid's order, so every point adds its terms in one fixed order.
+template <int TGT, int C0, int CN>
+__global__ void __launch_bounds__(64)
+    k_pm_spread(const int32_t* __restrict__ perm, const int32_t* __restrict__ cstart,
+                const int32_t* __restrict__ cend, const int* __restrict__ b0, const double* __restrict__ wts,
+                const double* __restrict__ Fe, const double* __restrict__ Te, const double* __restrict__ Sig,
+                const double* __restrict__ D, double P, double a5_20, int M, int nc, double2* __restrict__ fld) {
+  __shared__ int tb[kPmT][4];
+  __shared__ double tw[kPmT][3 * kPmP];
+  __shared__ double tc[kPmT][CN];
+  const int nb = M / kPmB;
+  const int bx = blockIdx.x % nb, by = (blockIdx.x / nb) % nb, bz = blockIdx.x / (nb * nb);
+  const int G0[3] = {bx * kPmB, by * kPmB, bz * kPmB};
+  const int gy = G0[1] + (threadIdx.x & 7), gz = G0[2] + (threadIdx.x >> 3);
+  double acc[kPmB][CN];
+#pragma unroll
+  for (int x = 0; x < kPmB; ++x)
+#pragma unroll
+    for (int c = 0; c < CN; ++c) acc[x][c] = 0.0;
+  // cells holding centres with floor(u) in [G0, G0 + B + P - 1) per axis, with a margin for rounding
+  int lo[3], cnt[3];
+  const double cpm = (double)nc / M;  // cells per mesh spacing
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (int)floor((G0[d] - 1e-6) * cpm);
+    const int hi = (int)floor((G0[d] + kPmB + kPmP - 1 + 1e-6) * cpm);
+    cnt[d] = min(hi - lo[d] + 1, nc);
+  }
+  for (int cz = 0; cz < cnt[2]; ++cz)
+    for (int cy = 0; cy < cnt[1]; ++cy)
+      for (int cx = 0; cx < cnt[0]; ++cx) {
+        const int ix = ((lo[0] + cx) % nc + nc) % nc, iy = ((lo[1] + cy) % nc + nc) % nc,
+                  iz = ((lo[2] + cz) % nc + nc) % nc;
+        const int cell = (iz * nc + iy) * nc + ix;
+        const int s0 = cstart[cell], s1 = cend[cell];
+        for (int st = s0; st < s1; st += kPmT) {
+          const int m = min(kPmT, s1 - st);
+          __syncthreads();
+          if ((int)threadIdx.x < m) {
+            const int k = st + threadIdx.x;
+            const int64_t j = perm[k];
+            for (int d = 0; d < 3; ++d) tb[threadIdx.x][d] = b0[4 * (int64_t)k + d];
+            for (int o = 0; o < 3 * kPmP; ++o) tw[threadIdx.x][o] = wts[3 * kPmP * (int64_t)k + o];
+#pragma unroll
+            for (int c = 0; c < CN; ++c) tc[threadIdx.x][c] = pm_coef<TGT>(C0 + c, j, Fe, Te, Sig, D, P, a5_20);
+          }
+          __syncthreads();
+          for (int q = 0; q < m; ++q) {
+            const int oy = (gy - tb[q][1]) & (M - 1), oz = (gz - tb[q][2]) & (M - 1);
+            if (oy >= kPmP || oz >= kPmP) continue;
+            const double wyz = tw[q][kPmP + oy] * tw[q][2 * kPmP + oz];
+#pragma unroll
+            for (int x = 0; x < kPmB; ++x) {
+              const int ox = (G0[0] + x - tb[q][0]) & (M - 1);
+              if (ox < kPmP) {
+                const double w = wyz * tw[q][ox];
+#pragma unroll
+                for (int c = 0; c < CN; ++c) acc[x][c] = fma(w, tc[q][c], acc[x][c]);
+              }
+            }
+          }
+        }
+      }
+  const int64_t M3 = (int64_t)M * M * M;
+#pragma unroll
+  for (int x = 0; x < kPmB; ++x) {
+    const int64_t idx = ((int64_t)gz * M + gy) * M + G0[0] + x;
+#pragma unroll
+    for (int f = 0; f < (CN + 1) / 2; ++f)
+      fld[(int64_t)f * M3 + idx] = make_double2(acc[x][2 * f], 2 * f + 1 < CN ? acc[x][2 * f + 1] : 0.0);
+  }
+}
+
+// One radix-2 pass of the 3D transform: every line of M points along one axis (element k of line l
+// of a bundle at base + l sb + k sk) transformed in LDS, B lines per workgroup (consecutive in
+// memory for the strided axes, so loads and stores move B contiguous points). Decimation in time:
+// loaded in bit-reversed order, log2 M butterfly stages in place, stored in natural order. Forward:
+// X(m) = sum_g x(g) exp(-2 pi i m g / M); INV: the conjugate exponent, no normalisation.
+template <bool INV>
+__global__ void __launch_bounds__(256)
+    k_fft_lines(double2* __restrict__ a, int M, int logM, int B, int64_t sk, int64_t sb, int nbu, int64_t su,
+                int64_t sv, int64_t sf, const double2* __restrict__ tw) {
+  extern __shared__ double2 xs[];
+  const int bu = blockIdx.x % nbu, bv = blockIdx.x / nbu;
+  double2* base = a + (int64_t)blockIdx.y * sf + (int64_t)bu * su + (int64_t)bv * sv;
+  const int E = B * M;
+  for (int e = threadIdx.x; e < E; e += blockDim.x) {
+    const int l = sk == 1 ? e / M : e % B, k = sk == 1 ? e % M : e / B;
+    xs[l * M + (int)(__brev((unsigned)k) >> (32 - logM))] = base[(int64_t)l * sb + (int64_t)k * sk];
+  }
+  __syncthreads();
+  const int hM = M >> 1;
+  for (int st = 0; st < logM; ++st) {
+    const int half = 1 << st;
+    for (int j = threadIdx.x; j < B * hM; j += blockDim.x) {
+      const int l = j / hM, jj = j % hM;
+      const int pos = jj & (half - 1);
+      const int i0 = l * M + ((jj >> st) << (st + 1)) + pos, i1 = i0 + half;
+      double2 w = tw[pos << (logM - 1 - st)];
+      if (INV) w.y = -w.y;
+      const double2 x0 = xs[i0], x1 = xs[i1];
+      const double tr = w.x * x1.x - w.y * x1.y, ti = fma(w.x, x1.y, w.y * x1.x);
+      xs[i0] = make_double2(x0.x + tr, x0.y + ti);
+      xs[i1] = make_double2(x0.x - tr, x0.y - ti);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < E; e += blockDim.x) {
+    const int l = sk == 1 ? e / M : e % B, k = sk == 1 ? e % M : e / B;
+    base[(int64_t)l * sb + (int64_t)k * sk] = xs[l * M + k];
+  }
+}
+
+// per mesh wave vector m (k = 2 pi m / L, |m_d| < M/2, m != 0): the coefficients' transforms
+// separated from the packed fields (Z = Q_{2a} + i Q_{2a+1}: Q_{2a}(m) = (Z(m) + conj Z(-m)) / 2,
+// Q_{2a+1}(m) = (Z(m) - conj Z(-m)) / 2i), the generated multiplier applied with the splitting
+// factor, |b(m)|^2 and 1 / L^3, the targets packed again in pairs (T_{2b} + i T_{2b+1})
+template <int TGT>
+__global__ void __launch_bounds__(256)
+    k_pm_mult(const double2* __restrict__ fin, int M, double dk, double xi, double a2, double invL3,
+              const double* __restrict__ bmod, double2* __restrict__ fout) {
+  constexpr int NC = pnc(sft(TGT)), W = pw(TGT), NI = (NC + 1) / 2, NO = (W + 1) / 2;
+  const int64_t M3 = (int64_t)M * M * M;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M3) return;
+  const int x = (int)(idx % M), y = (int)((idx / M) % M), z = (int)(idx / ((int64_t)M * M));
+  const int h = M >> 1;
+  if ((x == 0 && y == 0 && z == 0) || x == h || y == h || z == h) {
+    for (int b = 0; b < NO; ++b) fout[(int64_t)b * M3 + idx] = make_double2(0.0, 0.0);
+    return;
+  }
+  const int64_t nidx = ((int64_t)((M - z) & (M - 1)) * M + ((M - y) & (M - 1))) * M + ((M - x) & (M - 1));
+  double re[2 * NI], im[2 * NI];
+#pragma unroll
+  for (int a = 0; a < NI; ++a) {
+    const double2 zp = fin[(int64_t)a * M3 + idx], zm = fin[(int64_t)a * M3 + nidx];
+    re[2 * a] = 0.5 * (zp.x + zm.x);
+    im[2 * a] = 0.5 * (zp.y - zm.y);
+    re[2 * a + 1] = 0.5 * (zp.y + zm.y);
+    im[2 * a + 1] = 0.5 * (zm.x - zp.x);
+  }
+  const double k1 = dk * (x < h ? x : x - M), k2 = dk * (y < h ? y : y - M), k3 = dk * (z < h ? z : z - M);
+  const double ksq = fma(k1, k1, fma(k2, k2, k3 * k3));
+  const double ik2 = 1.0 / ksq;
+  const double q = ksq / (4.0 * xi * xi);
+  const double g = invL3 * (1.0 + q) * exp(-q) * bmod[x] * bmod[y] * bmod[z];
+  double tr[2 * NO], ti[2 * NO];
+  tr[2 * NO - 1] = ti[2 * NO - 1] = 0.0;
+  if (TGT == kPOp) per_hat_strain_s(k1, k2, k3, ik2, a2, re, im, tr, ti);
+  if (TGT == kPRhs) per_hat_strain_ftq(k1, k2, k3, ik2, a2, re, im, re + 3, im + 3, re + 6, im + 6, tr, ti);
+  if (TGT == kPOut)
+    per_hat_motion_ftsq(k1, k2, k3, ik2, a2, re, im, re + 3, im + 3, re + 6, im + 6, re + 11, im + 11, tr, ti);
+  if (TGT == kPFlow)
+    per_hat_flow_ftsq(k1, k2, k3, ik2, a2, re, im, re + 3, im + 3, re + 6, im + 6, re + 11, im + 11, tr, ti);
+#pragma unroll
+  for (int b = 0; b < NO; ++b)
+    fout[(int64_t)b * M3 + idx] =
+        make_double2(g * (tr[2 * b] - ti[2 * b + 1]), g * (ti[2 * b] + tr[2 * b + 1]));
+}
+
+// part[out(k) * W] = sum over the P^3 mesh points around receiver k of its weights times the
+// inverse transform (out(k) = perm[k] when perm is given, else k; receivers at Xr with a stride)
+template <int TGT>
+__global__ void __launch_bounds__(256)
+    k_pm_gather(const double* __restrict__ Xr, int stride, const int32_t* __restrict__ perm, int m, double L,
+                int M, const double2* __restrict__ fout, double* __restrict__ part) {
+  constexpr int W = pw(TGT), NO = (W + 1) / 2;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int64_t M3 = (int64_t)M * M * M;
+  int b[3];
+  double w[3][kPmP];
+  for (int d = 0; d < 3; ++d) {
+    double xw = Xr[(int64_t)stride * k + d];
+    xw -= L * floor(xw / L);
+    const double u = xw * (M / L);
+    const double fu = floor(u);
+    bspline_w(u - fu, w[d]);
+    b[d] = ((int)fu - (kPmP - 1)) & (M - 1);
+  }
+  double acc[2 * NO];
+#pragma unroll
+  for (int c = 0; c < 2 * NO; ++c) acc[c] = 0.0;
+  for (int oz = 0; oz < kPmP; ++oz) {
+    const int64_t pz = (int64_t)((b[2] + oz) & (M - 1)) * M;
+    for (int oy = 0; oy < kPmP; ++oy) {
+      const int64_t py = (pz + ((b[1] + oy) & (M - 1))) * M;
+      const double wyz = w[2][oz] * w[1][oy];
+#pragma unroll
+      for (int ox = 0; ox < kPmP; ++ox) {
+        const int64_t p = py + ((b[0] + ox) & (M - 1));
+        const double ww = wyz * w[0][ox];
+#pragma unroll
+        for (int f = 0; f < NO; ++f) {
+          const double2 v = fout[(int64_t)f * M3 + p];
+          acc[2 * f] = fma(ww, v.x, acc[2 * f]);
+          acc[2 * f + 1] = fma(ww, v.y, acc[2 * f + 1]);
+        }
+      }
+    }
+  }
+  const int64_t o = perm ? perm[k] : k;
+#pragma unroll
+  for (int c = 0; c < W; ++c) part[o * W + c] = acc[c];
+}
+
 inline unsigned nblk_p(int64_t len, int b) { return (unsigned)((len + b - 1) / b); }
 
 // launch shapes: source chunks of the real-space pass, source chunks of the structure factors,
@@ -431,7 +779,7 @@ struct PerShape {
 
 PerShape per_shape(int64_t n, int K, int nseg) {
   PerShape p;
-  const int64_t rb = (n + kPBlk - 1) / kPBlk, kb = (nseg + kPKBlk - 1) / kPKBlk;
+  const int64_t rb = std::max<int64_t>((n + kPBlk - 1) / kPBlk, 1), kb = std::max((nseg + kPKBlk - 1) / kPKBlk, 1);
   p.nreal = (int)std::min<int64_t>(std::max<int64_t>((2048 + rb - 1) / rb, 1), (n + kPTJ - 1) / kPTJ);
   p.creal = (int)((n + p.nreal - 1) / p.nreal);
   p.nsf = (int)std::min<int64_t>(std::max<int64_t>((2048 + kb - 1) / kb, 1), std::min<int64_t>(16, (n + kPTJ - 1) / kPTJ));
@@ -441,10 +789,132 @@ PerShape per_shape(int64_t n, int K, int nseg) {
   return p;
 }
 
+inline size_t align256p(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct PmLayout {
+  size_t fin, fout, b0, wts, grid, total;
+};
+
+// mesh workspace: 7 complex input fields and 3 output fields of M^3 points, per-sphere first mesh
+// points and weights, the box grid of the sources
+PmLayout pm_layout(int M, int64_t n, int nc) {
+  const int64_t M3 = (int64_t)M * M * M;
+  PmLayout y{};
+  size_t o = 0;
+  y.fin = o;
+  o += align256p(sizeof(double2) * 7 * (size_t)M3);
+  y.fout = o;
+  o += align256p(sizeof(double2) * 3 * (size_t)M3);
+  y.b0 = o;
+  o += align256p(sizeof(int) * 4 * (size_t)n);
+  y.wts = o;
+  o += align256p(sizeof(double) * 3 * kPmP * (size_t)n);
+  y.grid = o;
+  o += align256p(grid_ws_bytes((int)n, (int64_t)nc * nc * nc));
+  y.total = o;
+  return y;
+}
+
+// the 3D transform of nf complex fields of M^3 points (x fastest), in place
+void pm_fft(double2* a, int nf, int M, bool inv, const double2* tw, hipStream_t s) {
+  int logM = 0;
+  while ((1 << logM) < M) ++logM;
+  const int B = std::max(1, std::min(16, 4096 / M));
+  const int64_t M2 = (int64_t)M * M, M3 = M2 * M;
+  const size_t lds = (size_t)B * M * sizeof(double2);
+  const dim3 grid((unsigned)(M2 / B), (unsigned)nf);
+  auto go = [&](int64_t sk, int64_t sb, int64_t su, int64_t sv) {
+    if (inv)
+      hipLaunchKernelGGL(k_fft_lines<true>, grid, dim3(256), lds, s, a, M, logM, B, sk, sb, M / B, su, sv, M3, tw);
+    else
+      hipLaunchKernelGGL(k_fft_lines<false>, grid, dim3(256), lds, s, a, M, logM, B, sk, sb, M / B, su, sv, M3, tw);
+  };
+  go(1, M, (int64_t)B * M, M2);  // along x: a workgroup's lines consecutive in y
+  go(M, 1, B, M2);               // along y: lines consecutive in x
+  go(M2, 1, B, M);               // along z: lines consecutive in x
+}
+
+template <int TGT>
+void pm_launch(const double* X, int64_t m, const double* R, int64_t n, const double* Fe, const double* Te,
+               const double* Sig, const double* D, const double* v1s, const double* v2s, double* out, double* out2,
+               double* out3, double* part, const PerBox& g, const Phys& ph, hipStream_t s) {
+  constexpr int W = pw(TGT), NC = pnc(sft(TGT)), NI = (NC + 1) / 2, NO = (W + 1) / 2;
+  const int M = g.M;
+  const int64_t M3 = (int64_t)M * M * M;
+  const PmLayout Ly = pm_layout(M, n, g.nc);
+  char* wb = (char*)g.mws;
+  double2* fin = (double2*)(wb + Ly.fin);
+  double2* fout = (double2*)(wb + Ly.fout);
+  int* b0 = (int*)(wb + Ly.b0);
+  double* wts = (double*)(wb + Ly.wts);
+  const double2* tw = (const double2*)g.tab;
+  const double* bmod = g.tab + M;
+  const double a5_20 = 0.5 * ph.a5_10;
+  GridView gv;
+  (void)grid_build_box(R, (int)n, g.L, g.nc, wb + Ly.grid, Ly.total - Ly.grid, &gv, s);
+  hipLaunchKernelGGL(k_pm_prep, dim3(nblk_p(n, 256)), dim3(256), 0, s, gv.Rs, (int)n, M, M / g.L, b0, wts);
+  const dim3 sg((unsigned)(M3 / (kPmB * kPmB * kPmB)));
+  if (sft(TGT) == kPOp) {
+    hipLaunchKernelGGL((k_pm_spread<kPOp, 0, 5>), sg, dim3(64), 0, s, gv.perm, gv.start, gv.end, b0, wts, Fe, Te, Sig,
+                       D, ph.P, a5_20, M, g.nc, fin);
+  } else if (sft(TGT) == kPRhs) {
+    hipLaunchKernelGGL((k_pm_spread<kPRhs, 0, 6>), sg, dim3(64), 0, s, gv.perm, gv.start, gv.end, b0, wts, Fe, Te,
+                       Sig, D, ph.P, a5_20, M, g.nc, fin);
+    hipLaunchKernelGGL((k_pm_spread<kPRhs, 6, 3>), sg, dim3(64), 0, s, gv.perm, gv.start, gv.end, b0, wts, Fe, Te,
+                       Sig, D, ph.P, a5_20, M, g.nc, fin + 3 * M3);
+  } else {
+    hipLaunchKernelGGL((k_pm_spread<kPOut, 0, 6>), sg, dim3(64), 0, s, gv.perm, gv.start, gv.end, b0, wts, Fe, Te,
+                       Sig, D, ph.P, a5_20, M, g.nc, fin);
+    hipLaunchKernelGGL((k_pm_spread<kPOut, 6, 6>), sg, dim3(64), 0, s, gv.perm, gv.start, gv.end, b0, wts, Fe, Te,
+                       Sig, D, ph.P, a5_20, M, g.nc, fin + 3 * M3);
+    hipLaunchKernelGGL((k_pm_spread<kPOut, 12, 2>), sg, dim3(64), 0, s, gv.perm, gv.start, gv.end, b0, wts, Fe, Te,
+                       Sig, D, ph.P, a5_20, M, g.nc, fin + 6 * M3);
+  }
+  pm_fft(fin, NI, M, false, tw, s);
+  hipLaunchKernelGGL(k_pm_mult<TGT>, dim3(nblk_p(M3, 256)), dim3(256), 0, s, fin, M, 2.0 * M_PI / g.L, g.xi, ph.a2,
+                     1.0 / (g.L * g.L * g.L), bmod, fout);
+  pm_fft(fout, NO, M, true, tw, s);
+  // real space: over the box grid's neighbouring cells when it has at least 3 cells per axis (the
+  // spheres as receivers), else over all pairs; the mesh part interpolated at the receivers
+  const bool cells = TGT != kPFlow && g.nc >= 3;
+  const PerShape sh = per_shape(m, 0, 0);
+  const int nreal = cells ? 3 : sh.nreal;
+  double* preal = part;
+  double* precip = preal + (int64_t)nreal * W * m;
+  if (cells) {
+    hipLaunchKernelGGL(k_pm_real<TGT>, dim3((unsigned)g.nc * g.nc * g.nc, 3), dim3(64), 0, s, gv.Rs, gv.perm,
+                       gv.start, gv.end, g.nc, (int)m, Fe, Te, Sig, D, g.L, 1.0 / g.L, g.rc * g.rc, g.xi, ph.a2,
+                       ph.P, a5_20, preal);
+  } else {
+    const int creal = (int)((n + sh.nreal - 1) / sh.nreal);
+    hipLaunchKernelGGL(k_per_real<TGT>, dim3(nblk_p(m, kPBlk), sh.nreal), dim3(kPBlk), 0, s, X, (int)m, R, (int)n,
+                       Fe, Te, Sig, D, creal, g.L, 1.0 / g.L, g.rc * g.rc, g.xi, ph.a2, ph.P, a5_20, preal);
+  }
+  if (TGT == kPFlow)
+    hipLaunchKernelGGL(k_pm_gather<TGT>, dim3(nblk_p(m, 256)), dim3(256), 0, s, X, 3, (const int32_t*)nullptr,
+                       (int)m, g.L, M, fout, precip);
+  else
+    hipLaunchKernelGGL(k_pm_gather<TGT>, dim3(nblk_p(m, 256)), dim3(256), 0, s, gv.Rs, 4, gv.perm, (int)m, g.L, M,
+                       fout, precip);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (TGT == kPOp) s0 = ph.P * per_self_es(g.xi, ph.a2);
+  if (TGT == kPOut) {
+    s0 = ph.P * per_self_uf(g.xi, ph.a2);
+    s1 = a5_20 * per_self_ud(g.xi, ph.a2);
+    s2 = ph.P * per_self_wt(g.xi, ph.a2);
+  }
+  hipLaunchKernelGGL(k_per_finish<TGT>, dim3(nblk_p(m, 256)), dim3(256), 0, s, preal, nreal, precip, 1, (int)m,
+                     Sig, Fe, Te, D, v1s, v2s, s0, s1, s2, ph, out, out2, out3);
+}
+
 template <int TGT>
 void per_launch(const double* X, int64_t m, const double* R, int64_t n, const double* Fe, const double* Te,
                 const double* Sig, const double* D, const double* v1s, const double* v2s, double* out, double* out2,
                 double* out3, double* part, const PerBox& g, const Phys& ph, hipStream_t s) {
+  if (g.M > 0) {
+    pm_launch<TGT>(X, m, R, n, Fe, Te, Sig, D, v1s, v2s, out, out2, out3, part, g, ph, s);
+    return;
+  }
   constexpr int W = pw(TGT), NC = pnc(TGT);
   // receivers m for the real-space and reciprocal passes, sources n for the structure factors
   const PerShape sh = per_shape(m, g.K, TGT == kPOp ? g.nseg8 : g.nseg4);
@@ -517,7 +987,33 @@ std::vector<int> per_segments(const std::vector<double>& kv, double L, int maxle
 
 int64_t per_part_elems(int64_t m, int64_t n, int K, int nseg) {
   const PerShape sh = per_shape(m, K, nseg), shs = per_shape(n, K, nseg);  // receivers m, sources n
-  return (int64_t)sh.nreal * 6 * m + (int64_t)sh.nrec * 6 * m + (int64_t)shs.nsf * 28 * K + (int64_t)12 * K + 64;
+  return (int64_t)(std::max(sh.nreal, 3) + sh.nrec + 1) * 6 * m + (int64_t)shs.nsf * 28 * K + (int64_t)12 * K + 64;
+}
+
+size_t pm_ws_bytes(int M, int64_t n, int nc) { return pm_layout(M, n, nc).total; }
+
+std::vector<double> pm_tables(int M) {
+  // twiddles exp(-2 pi i k / M), k < M/2, then |b(m)|^2 = 1 / |sum_{k <= P-2} M_P(k + 1) exp(2 pi i m k / M)|^2
+  std::vector<double> t(2 * (size_t)M);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int k = 0; k < M / 2; ++k) {
+    const long double ang = 2.0L * pi * k / M;
+    t[2 * k] = (double)cosl(ang);
+    t[2 * k + 1] = (double)-sinl(ang);
+  }
+  double w[kPmP];
+  bspline_w(0.0, w);  // w[o] = M_P(P - 1 - o)
+  for (int mm = 0; mm < M; ++mm) {
+    const int f = mm < M / 2 ? mm : mm - M;
+    long double re = 0.0L, im = 0.0L;
+    for (int k = 0; k <= kPmP - 2; ++k) {
+      const long double v = w[kPmP - 2 - k], ang = 2.0L * pi * f * k / M;
+      re += v * cosl(ang);
+      im += v * sinl(ang);
+    }
+    t[M + mm] = (double)(1.0L / (re * re + im * im));
+  }
+  return t;
 }
 
 void launch_per_op(const double* R, const double* x, double* y, double* part, int64_t n, const PerBox& g,

@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
                 ("check_overlap", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("batch_item", ctypes.c_int32), ("superposition", ctypes.c_int32),
                 ("near_order", ctypes.c_int32), ("spatial_order", ctypes.c_int32),
-                ("plane", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("plane_z", ctypes.c_double),
+                ("plane", ctypes.c_int32), ("ewald_mesh", ctypes.c_int32), ("plane_z", ctypes.c_double),
                 ("box", ctypes.c_double), ("ewald_xi", ctypes.c_double)]
 
 
