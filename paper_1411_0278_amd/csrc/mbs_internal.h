@@ -132,7 +132,7 @@ struct PerBox {
   const double* tab;  // pm_tables(M) on the device
   void* mws;          // pm_ws_bytes(M, n, nc) bytes of device workspace (256-byte aligned)
 };
-// mesh workspace bytes for n sources; the mesh's twiddles and B-spline factors (2M doubles)
+// mesh workspace bytes for n sources; the mesh's twiddles and B-spline factors (3M doubles)
 size_t pm_ws_bytes(int M, int64_t n, int nc);
 std::vector<double> pm_tables(int M);
 std::vector<double> per_kvecs(double L, double kmax);

@@ -493,11 +493,13 @@ __global__ void __launch_bounds__(256) k_pm_prep(const double* __restrict__ Rs, 
 
 // the real-space pass over the sources' box grid (cells of edge >= rc, at least 3 per axis, so a
 // receiver's partners within rc lie in its own and the 26 neighbouring cells, each met once): a
-// workgroup per (cell, layer of neighbouring cells along z), its receivers 64 at a time, the 9 cells
+// workgroup per (cell, layer of neighbouring cells along z), its receivers 128 at a time, the 9 cells
 // of the layer staged through LDS with the same bit-mask evaluation as k_per_real; partial sums
 // part[(layer * m + i) * W] at the receivers' own indices
+constexpr int kPmRT = 128;  // threads of the cell real-space kernel (receivers per round)
+
 template <int TGT>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(kPmRT)
     k_pm_real(const double* __restrict__ Rs, const int32_t* __restrict__ perm, const int32_t* __restrict__ cstart,
               const int32_t* __restrict__ cend, int nc, int m, const double* __restrict__ Fe,
               const double* __restrict__ Te, const double* __restrict__ Sig, const double* __restrict__ D, double L,
@@ -508,7 +510,7 @@ __global__ void __launch_bounds__(64)
   const int ix = cell % nc, iy = (cell / nc) % nc, iz = cell / (nc * nc);
   const int jz = (iz + (int)blockIdx.y - 1 + nc) % nc;
   const int r0 = cstart[cell], r1 = cend[cell];
-  for (int rb = r0; rb < r1; rb += 64) {
+  for (int rb = r0; rb < r1; rb += kPmRT) {
     const int k = rb + threadIdx.x;
     const int kk = k < r1 ? k : r1 - 1;
     const double xi0 = Rs[4 * (int64_t)kk], yi0 = Rs[4 * (int64_t)kk + 1], zi0 = Rs[4 * (int64_t)kk + 2];
@@ -563,8 +565,10 @@ __global__ void __launch_bounds__(64)
 
 // Q_c(g) = sum_j c_j W_j(g) on one 8^3 block of the mesh, coefficients [C0, C0 + CN) (C0 even),
 // written in pairs as complex fields (Q_{C0}, Q_{C0+1}), ... from field C0/2 on. A thread holds one
-// line of 8 points along x; the candidate spheres (those binned in the cells that reach the block)
-// pass through LDS in the grid's order, so every point adds its terms in one fixed order.
+// line of 8 points along x. The candidate spheres (those binned in the cells that reach the block)
+// are taken 64 at a time in the grid's order; those whose P^3 points overlap the block (a few
+// percent of them) are compacted by a ballot, in order, and only their weights and coefficients go
+// through LDS, so every point adds its terms in one fixed order.
 template <int TGT, int C0, int CN>
 __global__ void __launch_bounds__(64)
     k_pm_spread(const int32_t* __restrict__ perm, const int32_t* __restrict__ cstart,
@@ -599,15 +603,27 @@ __global__ void __launch_bounds__(64)
         const int cell = (iz * nc + iy) * nc + ix;
         const int s0 = cstart[cell], s1 = cend[cell];
         for (int st = s0; st < s1; st += kPmT) {
-          const int m = min(kPmT, s1 - st);
-          __syncthreads();
-          if ((int)threadIdx.x < m) {
-            const int k = st + threadIdx.x;
-            const int64_t j = perm[k];
-            for (int d = 0; d < 3; ++d) tb[threadIdx.x][d] = b0[4 * (int64_t)k + d];
-            for (int o = 0; o < 3 * kPmP; ++o) tw[threadIdx.x][o] = wts[3 * kPmP * (int64_t)k + o];
+          const int k = st + threadIdx.x;
+          int bq[3] = {0, 0, 0};
+          bool in = k < s1;
+          if (in) {
 #pragma unroll
-            for (int c = 0; c < CN; ++c) tc[threadIdx.x][c] = pm_coef<TGT>(C0 + c, j, Fe, Te, Sig, D, P, a5_20);
+            for (int d = 0; d < 3; ++d) {
+              bq[d] = b0[4 * (int64_t)k + d];
+              in = in && (((G0[d] - bq[d]) & (M - 1)) < kPmP || ((bq[d] - G0[d]) & (M - 1)) < kPmB);
+            }
+          }
+          const uint64_t mask = __ballot(in);
+          const int m = __popcll(mask);
+          if (m == 0) continue;  // (uniform: one wavefront per workgroup)
+          __syncthreads();
+          if (in) {
+            const int pos = __popcll(mask & ((1ull << threadIdx.x) - 1ull));
+            const int64_t j = perm[k];
+            for (int d = 0; d < 3; ++d) tb[pos][d] = bq[d];
+            for (int o = 0; o < 3 * kPmP; ++o) tw[pos][o] = wts[3 * kPmP * (int64_t)k + o];
+#pragma unroll
+            for (int c = 0; c < CN; ++c) tc[pos][c] = pm_coef<TGT>(C0 + c, j, Fe, Te, Sig, D, P, a5_20);
           }
           __syncthreads();
           for (int q = 0; q < m; ++q) {
@@ -636,43 +652,122 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// One radix-2 pass of the 3D transform: every line of M points along one axis (element k of line l
-// of a bundle at base + l sb + k sk) transformed in LDS, B lines per workgroup (consecutive in
-// memory for the strided axes, so loads and stores move B contiguous points). Decimation in time:
-// loaded in bit-reversed order, log2 M butterfly stages in place, stored in natural order. Forward:
-// X(m) = sum_g x(g) exp(-2 pi i m g / M); INV: the conjugate exponent, no normalisation.
+// Radix-4 and radix-8 DFTs in registers: forward exp(-2 pi i q r / R), INV the conjugate.
+template <bool INV>
+__device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, double2& a3) {
+  const double2 t0 = make_double2(a0.x + a2.x, a0.y + a2.y), t1 = make_double2(a0.x - a2.x, a0.y - a2.y);
+  const double2 t2 = make_double2(a1.x + a3.x, a1.y + a3.y);
+  const double2 d = make_double2(a1.x - a3.x, a1.y - a3.y);
+  const double2 t3 = INV ? make_double2(-d.y, d.x) : make_double2(d.y, -d.x);  // (a1 - a3) times -i (i: INV)
+  a0 = make_double2(t0.x + t2.x, t0.y + t2.y);
+  a2 = make_double2(t0.x - t2.x, t0.y - t2.y);
+  a1 = make_double2(t1.x + t3.x, t1.y + t3.y);
+  a3 = make_double2(t1.x - t3.x, t1.y - t3.y);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft_small(double2* v) {
+  if (R == 4) {
+    dft4<INV>(v[0], v[1], v[2], v[3]);
+  } else {  // 8: the even and odd halves, then exp(-/+ 2 pi i k / 8) on the odd ones
+    double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<INV>(e0, e1, e2, e3);
+    dft4<INV>(o0, o1, o2, o3);
+    const double c = 0.70710678118654752440;
+    o1 = INV ? make_double2(c * (o1.x - o1.y), c * (o1.x + o1.y)) : make_double2(c * (o1.x + o1.y), c * (o1.y - o1.x));
+    o2 = INV ? make_double2(-o2.y, o2.x) : make_double2(o2.y, -o2.x);
+    o3 = INV ? make_double2(-c * (o3.x + o3.y), c * (o3.x - o3.y)) : make_double2(c * (o3.y - o3.x), -c * (o3.x + o3.y));
+    v[0] = make_double2(e0.x + o0.x, e0.y + o0.y);
+    v[4] = make_double2(e0.x - o0.x, e0.y - o0.y);
+    v[1] = make_double2(e1.x + o1.x, e1.y + o1.y);
+    v[5] = make_double2(e1.x - o1.x, e1.y - o1.y);
+    v[2] = make_double2(e2.x + o2.x, e2.y + o2.y);
+    v[6] = make_double2(e2.x - o2.x, e2.y - o2.y);
+    v[3] = make_double2(e3.x + o3.x, e3.y + o3.y);
+    v[7] = make_double2(e3.x - o3.x, e3.y - o3.y);
+  }
+}
+
+// LDS slot of point idx of line l: rows of M points, the low 4 bits of idx swizzled by the line so
+// that lanes reading the same point of consecutive lines meet different banks
+__device__ __forceinline__ int fft_slot(int l, int idx, int M) { return l * M + (idx ^ (l & 15)); }
+
+struct FftPlan {
+  int nst;
+  int r[6];  // radix of each stage (8 or 4), product M
+};
+
+// One radix-R Stockham stage over the B lines of a bundle: butterfly j (< M/R) of line l takes the
+// points j + r M/R, multiplies them by exp(-/+ 2 pi i r k / (Ns R)) (k = j mod Ns, Ns the product of
+// the earlier radices), transforms them and puts them at (j - k) R + k + r Ns: natural order in and
+// out. The first stage reads the line from memory and the last one writes it back; the others work
+// in LDS, every thread reading all its points before the barrier and writing after it.
+template <int R, bool INV>
+__device__ __forceinline__ void fft_stage(double2* xs, double2* g, bool from_g, bool to_g, int M, int B, int Ns,
+                                          int64_t sk, int64_t sb, const double2* __restrict__ tw) {
+  constexpr int NB = 4096 / R / 256;  // butterflies per thread (B M <= 4096, 256 threads)
+  const int MR = M / R, nbf = B * MR;
+  double2 v[NB][R];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int e = threadIdx.x + q * 256;
+    if (e < nbf) {
+      const int l = sk == 1 ? e / MR : e % B, j = sk == 1 ? e % MR : e / B;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int idx = j + r * MR;
+        v[q][r] = from_g ? g[(int64_t)l * sb + (int64_t)idx * sk] : xs[fft_slot(l, idx, M)];
+      }
+      const int k = j & (Ns - 1), step = M / (Ns * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        double2 w = tw[r * k * step];
+        if (INV) w.y = -w.y;
+        const double2 x = v[q][r];
+        v[q][r] = make_double2(w.x * x.x - w.y * x.y, fma(w.x, x.y, w.y * x.x));
+      }
+      dft_small<R, INV>(v[q]);
+    }
+  }
+  if (!from_g) __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int e = threadIdx.x + q * 256;
+    if (e < nbf) {
+      const int l = sk == 1 ? e / MR : e % B, j = sk == 1 ? e % MR : e / B;
+      const int k = j & (Ns - 1), o = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int idx = o + r * Ns;
+        if (to_g)
+          g[(int64_t)l * sb + (int64_t)idx * sk] = v[q][r];
+        else
+          xs[fft_slot(l, idx, M)] = v[q][r];
+      }
+    }
+  }
+  if (!to_g) __syncthreads();
+}
+
+// One pass of the 3D transform: every line of M points along one axis (point idx of line l of a
+// bundle at base + l sb + idx sk), B lines per workgroup (consecutive in memory for the strided axes,
+// so that B contiguous points move together). Forward: X(m) = sum_g x(g) exp(-2 pi i m g / M); INV:
+// the conjugate exponent, no normalisation.
 template <bool INV>
 __global__ void __launch_bounds__(256)
-    k_fft_lines(double2* __restrict__ a, int M, int logM, int B, int64_t sk, int64_t sb, int nbu, int64_t su,
-                int64_t sv, int64_t sf, const double2* __restrict__ tw) {
+    k_fft_lines(double2* __restrict__ a, int M, int B, int64_t sk, int64_t sb, int nbu, int64_t su, int64_t sv,
+                int64_t sf, const double2* __restrict__ tw, FftPlan pl) {
   extern __shared__ double2 xs[];
   const int bu = blockIdx.x % nbu, bv = blockIdx.x / nbu;
   double2* base = a + (int64_t)blockIdx.y * sf + (int64_t)bu * su + (int64_t)bv * sv;
-  const int E = B * M;
-  for (int e = threadIdx.x; e < E; e += blockDim.x) {
-    const int l = sk == 1 ? e / M : e % B, k = sk == 1 ? e % M : e / B;
-    xs[l * M + (int)(__brev((unsigned)k) >> (32 - logM))] = base[(int64_t)l * sb + (int64_t)k * sk];
-  }
-  __syncthreads();
-  const int hM = M >> 1;
-  for (int st = 0; st < logM; ++st) {
-    const int half = 1 << st;
-    for (int j = threadIdx.x; j < B * hM; j += blockDim.x) {
-      const int l = j / hM, jj = j % hM;
-      const int pos = jj & (half - 1);
-      const int i0 = l * M + ((jj >> st) << (st + 1)) + pos, i1 = i0 + half;
-      double2 w = tw[pos << (logM - 1 - st)];
-      if (INV) w.y = -w.y;
-      const double2 x0 = xs[i0], x1 = xs[i1];
-      const double tr = w.x * x1.x - w.y * x1.y, ti = fma(w.x, x1.y, w.y * x1.x);
-      xs[i0] = make_double2(x0.x + tr, x0.y + ti);
-      xs[i1] = make_double2(x0.x - tr, x0.y - ti);
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < E; e += blockDim.x) {
-    const int l = sk == 1 ? e / M : e % B, k = sk == 1 ? e % M : e / B;
-    base[(int64_t)l * sb + (int64_t)k * sk] = xs[l * M + k];
+  int Ns = 1;
+  for (int st = 0; st < pl.nst; ++st) {
+    const bool first = st == 0, last = st == pl.nst - 1;
+    if (pl.r[st] == 8)
+      fft_stage<8, INV>(xs, base, first, last, M, B, Ns, sk, sb, tw);
+    else
+      fft_stage<4, INV>(xs, base, first, last, M, B, Ns, sk, sb, tw);
+    Ns *= pl.r[st];
   }
 }
 
@@ -724,46 +819,56 @@ __global__ void __launch_bounds__(256)
 }
 
 // part[out(k) * W] = sum over the P^3 mesh points around receiver k of its weights times the
-// inverse transform (out(k) = perm[k] when perm is given, else k; receivers at Xr with a stride)
+// inverse transform (out(k) = perm[k] when perm is given, else k; receivers at Xr with a stride).
+// Eight lanes per receiver, one per x offset, so that each load moves eight consecutive mesh points;
+// the lanes' sums are combined by shuffles in a fixed order.
 template <int TGT>
 __global__ void __launch_bounds__(256)
     k_pm_gather(const double* __restrict__ Xr, int stride, const int32_t* __restrict__ perm, int m, double L,
                 int M, const double2* __restrict__ fout, double* __restrict__ part) {
   constexpr int W = pw(TGT), NO = (W + 1) / 2;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= m) return;
+  const int k = blockIdx.x * (blockDim.x / kPmP) + threadIdx.x / kPmP;
+  const int ox = threadIdx.x % kPmP;
+  const int kk = k < m ? k : m - 1;
   const int64_t M3 = (int64_t)M * M * M;
   int b[3];
   double w[3][kPmP];
   for (int d = 0; d < 3; ++d) {
-    double xw = Xr[(int64_t)stride * k + d];
+    double xw = Xr[(int64_t)stride * kk + d];
     xw -= L * floor(xw / L);
     const double u = xw * (M / L);
     const double fu = floor(u);
     bspline_w(u - fu, w[d]);
     b[d] = ((int)fu - (kPmP - 1)) & (M - 1);
   }
+  double wx = w[0][0];
+#pragma unroll
+  for (int o = 1; o < kPmP; ++o)
+    if (ox == o) wx = w[0][o];
+  const int px = (b[0] + ox) & (M - 1);
   double acc[2 * NO];
 #pragma unroll
   for (int c = 0; c < 2 * NO; ++c) acc[c] = 0.0;
   for (int oz = 0; oz < kPmP; ++oz) {
     const int64_t pz = (int64_t)((b[2] + oz) & (M - 1)) * M;
+    const double wz = w[2][oz] * wx;
+#pragma unroll
     for (int oy = 0; oy < kPmP; ++oy) {
-      const int64_t py = (pz + ((b[1] + oy) & (M - 1))) * M;
-      const double wyz = w[2][oz] * w[1][oy];
+      const int64_t p = (pz + ((b[1] + oy) & (M - 1))) * M + px;
+      const double ww = wz * w[1][oy];
 #pragma unroll
-      for (int ox = 0; ox < kPmP; ++ox) {
-        const int64_t p = py + ((b[0] + ox) & (M - 1));
-        const double ww = wyz * w[0][ox];
-#pragma unroll
-        for (int f = 0; f < NO; ++f) {
-          const double2 v = fout[(int64_t)f * M3 + p];
-          acc[2 * f] = fma(ww, v.x, acc[2 * f]);
-          acc[2 * f + 1] = fma(ww, v.y, acc[2 * f + 1]);
-        }
+      for (int f = 0; f < NO; ++f) {
+        const double2 v = fout[(int64_t)f * M3 + p];
+        acc[2 * f] = fma(ww, v.x, acc[2 * f]);
+        acc[2 * f + 1] = fma(ww, v.y, acc[2 * f + 1]);
       }
     }
   }
+#pragma unroll
+  for (int c = 0; c < 2 * NO; ++c)
+#pragma unroll
+    for (int sh = kPmP / 2; sh > 0; sh >>= 1) acc[c] += __shfl_xor(acc[c], sh, kPmP);
+  if (ox != 0 || k >= m) return;
   const int64_t o = perm ? perm[k] : k;
 #pragma unroll
   for (int c = 0; c < W; ++c) part[o * W + c] = acc[c];
@@ -815,19 +920,34 @@ PmLayout pm_layout(int M, int64_t n, int nc) {
   return y;
 }
 
+// radices of the transform of length M (a power of 2, 16 or more): eights, then one or two fours
+FftPlan fft_plan(int M) {
+  int lg = 0;
+  while ((1 << lg) < M) ++lg;
+  FftPlan p{};
+  while (lg >= 3 && lg != 4 && lg - 3 != 1) {
+    p.r[p.nst++] = 8;
+    lg -= 3;
+  }
+  while (lg >= 2) {
+    p.r[p.nst++] = 4;
+    lg -= 2;
+  }
+  return p;
+}
+
 // the 3D transform of nf complex fields of M^3 points (x fastest), in place
 void pm_fft(double2* a, int nf, int M, bool inv, const double2* tw, hipStream_t s) {
-  int logM = 0;
-  while ((1 << logM) < M) ++logM;
+  const FftPlan pl = fft_plan(M);
   const int B = std::max(1, std::min(16, 4096 / M));
   const int64_t M2 = (int64_t)M * M, M3 = M2 * M;
   const size_t lds = (size_t)B * M * sizeof(double2);
   const dim3 grid((unsigned)(M2 / B), (unsigned)nf);
   auto go = [&](int64_t sk, int64_t sb, int64_t su, int64_t sv) {
     if (inv)
-      hipLaunchKernelGGL(k_fft_lines<true>, grid, dim3(256), lds, s, a, M, logM, B, sk, sb, M / B, su, sv, M3, tw);
+      hipLaunchKernelGGL(k_fft_lines<true>, grid, dim3(256), lds, s, a, M, B, sk, sb, M / B, su, sv, M3, tw, pl);
     else
-      hipLaunchKernelGGL(k_fft_lines<false>, grid, dim3(256), lds, s, a, M, logM, B, sk, sb, M / B, su, sv, M3, tw);
+      hipLaunchKernelGGL(k_fft_lines<false>, grid, dim3(256), lds, s, a, M, B, sk, sb, M / B, su, sv, M3, tw, pl);
   };
   go(1, M, (int64_t)B * M, M2);  // along x: a workgroup's lines consecutive in y
   go(M, 1, B, M2);               // along y: lines consecutive in x
@@ -848,7 +968,7 @@ void pm_launch(const double* X, int64_t m, const double* R, int64_t n, const dou
   int* b0 = (int*)(wb + Ly.b0);
   double* wts = (double*)(wb + Ly.wts);
   const double2* tw = (const double2*)g.tab;
-  const double* bmod = g.tab + M;
+  const double* bmod = g.tab + 2 * M;
   const double a5_20 = 0.5 * ph.a5_10;
   GridView gv;
   (void)grid_build_box(R, (int)n, g.L, g.nc, wb + Ly.grid, Ly.total - Ly.grid, &gv, s);
@@ -882,7 +1002,7 @@ void pm_launch(const double* X, int64_t m, const double* R, int64_t n, const dou
   double* preal = part;
   double* precip = preal + (int64_t)nreal * W * m;
   if (cells) {
-    hipLaunchKernelGGL(k_pm_real<TGT>, dim3((unsigned)g.nc * g.nc * g.nc, 3), dim3(64), 0, s, gv.Rs, gv.perm,
+    hipLaunchKernelGGL(k_pm_real<TGT>, dim3((unsigned)g.nc * g.nc * g.nc, 3), dim3(kPmRT), 0, s, gv.Rs, gv.perm,
                        gv.start, gv.end, g.nc, (int)m, Fe, Te, Sig, D, g.L, 1.0 / g.L, g.rc * g.rc, g.xi, ph.a2,
                        ph.P, a5_20, preal);
   } else {
@@ -891,11 +1011,11 @@ void pm_launch(const double* X, int64_t m, const double* R, int64_t n, const dou
                        Fe, Te, Sig, D, creal, g.L, 1.0 / g.L, g.rc * g.rc, g.xi, ph.a2, ph.P, a5_20, preal);
   }
   if (TGT == kPFlow)
-    hipLaunchKernelGGL(k_pm_gather<TGT>, dim3(nblk_p(m, 256)), dim3(256), 0, s, X, 3, (const int32_t*)nullptr,
-                       (int)m, g.L, M, fout, precip);
+    hipLaunchKernelGGL(k_pm_gather<TGT>, dim3(nblk_p(m, 256 / kPmP)), dim3(256), 0, s, X, 3,
+                       (const int32_t*)nullptr, (int)m, g.L, M, fout, precip);
   else
-    hipLaunchKernelGGL(k_pm_gather<TGT>, dim3(nblk_p(m, 256)), dim3(256), 0, s, gv.Rs, 4, gv.perm, (int)m, g.L, M,
-                       fout, precip);
+    hipLaunchKernelGGL(k_pm_gather<TGT>, dim3(nblk_p(m, 256 / kPmP)), dim3(256), 0, s, gv.Rs, 4, gv.perm, (int)m, g.L,
+                       M, fout, precip);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   if (TGT == kPOp) s0 = ph.P * per_self_es(g.xi, ph.a2);
   if (TGT == kPOut) {
@@ -993,10 +1113,10 @@ int64_t per_part_elems(int64_t m, int64_t n, int K, int nseg) {
 size_t pm_ws_bytes(int M, int64_t n, int nc) { return pm_layout(M, n, nc).total; }
 
 std::vector<double> pm_tables(int M) {
-  // twiddles exp(-2 pi i k / M), k < M/2, then |b(m)|^2 = 1 / |sum_{k <= P-2} M_P(k + 1) exp(2 pi i m k / M)|^2
-  std::vector<double> t(2 * (size_t)M);
+  // twiddles exp(-2 pi i k / M), k < M, then |b(m)|^2 = 1 / |sum_{k <= P-2} M_P(k + 1) exp(2 pi i m k / M)|^2
+  std::vector<double> t(3 * (size_t)M);
   const long double pi = 3.141592653589793238462643383279502884L;
-  for (int k = 0; k < M / 2; ++k) {
+  for (int k = 0; k < M; ++k) {
     const long double ang = 2.0L * pi * k / M;
     t[2 * k] = (double)cosl(ang);
     t[2 * k + 1] = (double)-sinl(ang);
@@ -1011,7 +1131,7 @@ std::vector<double> pm_tables(int M) {
       re += v * cosl(ang);
       im += v * sinl(ang);
     }
-    t[M + mm] = (double)(1.0L / (re * re + im * im));
+    t[2 * M + mm] = (double)(1.0L / (re * re + im * im));
   }
   return t;
 }
