@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--profile-geometries", action="store_true",
                     help="profiling mode: the plane, wall and periodic-box sections of the bench line alone "
                          "(their passes at 10^4 and --n spheres and the solves at 10^4), printed as JSON")
+    ap.add_argument("--profile-mesh", action="store_true",
+                    help="profiling mode: the particle-mesh Ewald operator in the periodic box, 10^5 spheres "
+                         "on a 256^3 mesh and 10^6 on a 512^3 mesh, 6 untimed and 5 timed passes each")
     ap.add_argument("--profile-matvec", action="store_true",
                     help="profiling mode: a 256 MiB device copy (counter calibration), then --steps "
                          "binary64 and --steps binary32 operator applications at the autotuned shapes")
@@ -749,6 +752,51 @@ def bench_plane(ctx, a):
     return out
 
 
+def _lattice_positions(n, L, seed):
+    """n sites of a cubic lattice filling the box, chosen at random and jittered so that every
+    minimum-image distance stays >= 2.2a (the lattice is periodic, so across faces too)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    m = int(np.ceil(n ** (1.0 / 3.0) - 1e-9))
+    h = L / m
+    g = (np.arange(m) + 0.5) * h
+    sites = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    sites = sites[rng.choice(len(sites), n, replace=False)]
+    return sites + rng.uniform(-1.0, 1.0, (n, 3)) * max(0.0, (h - 2.2) / 2)
+
+
+def profile_mesh():
+    """Profiling mode: the particle-mesh Ewald operator in the periodic box at density 0.004, 10^5
+    spheres on a 256^3 mesh and 10^6 on a 512^3 mesh, 6 untimed and 5 timed passes each."""
+    import time
+
+    import torch
+
+    from paper_1411_0278_amd import inputs, mbstokes
+    ctx = mbstokes.Context(0)
+    out = {"mode": "profile-mesh"}
+    for n, M in ((100_000, 256), (1_000_000, 512)):
+        L = (n / 0.004) ** (1.0 / 3.0)
+        w = inputs.trap_workload(n, L, 3)
+        w.R = _lattice_positions(n, L, 3)
+        d = mbstokes.to_device(w, "cuda:0")
+        x = d["v2s"].contiguous()
+        y = torch.empty_like(x)
+        ctx.set_params(box=L, ewald_mesh=M)
+        for _ in range(6):
+            ctx.mbs_matvec(d["R"], x, y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ctx.mbs_matvec(d["R"], x, y)
+        torch.cuda.synchronize()
+        out["n%d_M%d_ms" % (n, M)] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
+        print(f"profile-mesh: n={n} M={M} {out['n%d_M%d_ms' % (n, M)]} ms per pass", file=sys.stderr, flush=True)
+        ctx.set_params(box=0.0, ewald_mesh=0)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_periodic(ctx, a):
     """Spheres in a periodic cubic box (params.box, Ewald summation) at the benchmark density
     (0.004 spheres per a^3 on jittered lattice sites): the operator
@@ -778,16 +826,7 @@ def bench_periodic(ctx, a):
             ts.append(e0.elapsed_time(e1))
         return statistics.median(ts)
 
-    def lattice_positions(n, L, seed):
-        """n sites of a cubic lattice filling the box, chosen at random and jittered so that every
-        minimum-image distance stays >= 2.2a (the lattice is periodic, so across faces too)."""
-        rng = np.random.default_rng(seed)
-        m = int(np.ceil(n ** (1.0 / 3.0) - 1e-9))
-        h = L / m
-        g = (np.arange(m) + 0.5) * h
-        sites = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
-        sites = sites[rng.choice(len(sites), n, replace=False)]
-        return sites + rng.uniform(-1.0, 1.0, (n, 3)) * max(0.0, (h - 2.2) / 2)
+    lattice_positions = _lattice_positions
 
     def mesh_for(L):
         M = 16
@@ -1139,6 +1178,9 @@ def main():
         return
     if a.profile_rank3:
         profile_rank3(a)
+        return
+    if a.profile_mesh:
+        profile_mesh()
         return
     if a.profile_geometries:
         ctx = mbstokes.Context(0)
