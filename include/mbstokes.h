@@ -428,6 +428,9 @@ int mbs_solve_r3(mbs_ctx* ctx, int64_t n, const double* R, const double* v1s, co
    min_dist < 2a also reports contact with the plane; the run goes on while every centre lies
    above the plane and stops with MBS_EINVAL at the first step that finds one on or below it (R, p
    hold the state before that step).
+   With params.box the distances are minimum-image ones; with params.ewald_mesh as well they come
+   from the 27 neighbouring cells of a box grid (O(n); all pairs only when no pair is closer than a
+   cell edge), otherwise from all pairs.
    With params.guess = MBS_GUESS_USER every step after the first starts from the previous step's
    Sigma (the first from the one-body guess). A step whose solve stops short of params.tol still
    advances and the call returns MBS_ENOCONV at the end; a non-finite residual stops the run

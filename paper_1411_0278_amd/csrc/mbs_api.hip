@@ -297,7 +297,7 @@ int ensure_ws(mbs_ctx* c, int64_t n) {
     CHK(ensure(c, c->near, (size_t)(kNearCap + 1) * n / 2 + 64));
     CHK(ensure(c, c->nt, 2 * len));  // the preconditioner's two partial sums
   }
-  CHK(ensure(c, c->dpart, (size_t)std::max<int64_t>((int64_t)(m + 2) * 256, 1024 + (n + 255) / 256) + 64));
+  CHK(ensure(c, c->dpart, (size_t)std::max<int64_t>((int64_t)(m + 2) * 256, 1024 + 2 * ((n + 255) / 256)) + 64));
   CHK(ensure(c, c->small, (size_t)8 * (m + 2) + 64));
   CHK(ensure(c, c->H, (size_t)(m + 1) * (m + 1)));
   if (c->zeros.cap < (size_t)len) {
@@ -722,9 +722,13 @@ int per_min_dist(mbs_ctx* c, int64_t n, const double* R, hipStream_t s, double* 
     *md = INFINITY;
     return MBS_OK;
   }
-  // (the tail of dpart holds at least (n + 255)/256 + 64 doubles beyond offset 1024, as for check_overlap)
+  // (the tail of dpart holds at least 2 (n + 255)/256 + 64 doubles beyond offset 1024)
   double* out = c->small.p + c->small.cap - 1;
-  launch_per_min_dist(R, n, c->prm.box, c->dpart.p + 1024, out, s);
+  const PerBox g = per_box(c, n);
+  if (g.M > 0 && g.nc >= 3)
+    launch_pm_min_dist(R, n, g, c->dpart.p + 1024, out, s);
+  else
+    launch_per_min_dist(R, n, c->prm.box, c->dpart.p + 1024, out, s);
   CHK(read_status(c, out, 1, s));
   *md = c->h_status[0];
   return MBS_OK;

@@ -145,6 +145,9 @@ int64_t per_part_elems(int64_t m, int64_t n, int K, int nseg);
 // doubles of scratch
 int per_min_dist_part(int64_t n);
 void launch_per_min_dist(const double* R, int64_t n, double L, double* part, double* out, hipStream_t s);
+// the same from the box grid of a mesh box (g.M > 0, g.nc >= 3), all pairs only when no pair is closer
+// than a cell edge; part: 2 per_min_dist_part(n) doubles of scratch
+void launch_pm_min_dist(const double* R, int64_t n, const PerBox& g, double* part, double* out, hipStream_t s);
 // U [m x 3] = flow of the periodic suspension at field points X [m x 3]
 void launch_per_flow(const double* X, int64_t m, const double* R, int64_t n, const double* Fe, const double* Te,
                      const double* Sig, const double* v3t, double* U, double* part, const PerBox& g, const Phys& ph,

@@ -386,8 +386,11 @@ __global__ void k_per_finish(const double* __restrict__ preal, int nreal, const 
 
 // the smallest minimum-image distance squared of each workgroup's receivers to every other sphere:
 // part[block] (all pairs, positions staged through LDS)
+// (skip: when given and *skip < edge, the cell search already found the minimum: nothing to do)
 __global__ void __launch_bounds__(256) k_per_min_d2(const double* __restrict__ R, int n, double L, double invL,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part, const double* __restrict__ skip,
+                                                    double edge) {
+  if (skip && *skip < edge) return;
   __shared__ double tx[256], ty[256], tz[256], red[256];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int ii = i < n ? i : n - 1;
@@ -417,8 +420,44 @@ __global__ void __launch_bounds__(256) k_per_min_d2(const double* __restrict__ R
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// out[0] = sqrt(min over the nb partial minima)
-__global__ void __launch_bounds__(256) k_min_finish(const double* __restrict__ part, int nb, double* __restrict__ out) {
+// the smallest minimum-image distance squared from each sphere (box grid order, at least 3 cells per
+// axis) to the others in its 27 neighbouring cells: part[block]
+__global__ void __launch_bounds__(256) k_pm_min_d2(const GridHdr* __restrict__ hdr, const double* __restrict__ Rs,
+                                                   const int32_t* __restrict__ cstart, const int32_t* __restrict__ cend,
+                                                   int nc, int n, double L, double invL, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  double best = INFINITY;
+  if (k < n) {
+    const GridHdr H = *hdr;
+    const double x = Rs[4 * (int64_t)k], y = Rs[4 * (int64_t)k + 1], z = Rs[4 * (int64_t)k + 2];
+    const int cx = grid_cell1(x, 0.0, H.inv_h, nc), cy = grid_cell1(y, 0.0, H.inv_h, nc),
+              cz = grid_cell1(z, 0.0, H.inv_h, nc);
+    for (int nb = 0; nb < 27; ++nb) {
+      const int jx = (cx + nb % 3 - 1 + nc) % nc, jy = (cy + (nb / 3) % 3 - 1 + nc) % nc,
+                jz = (cz + nb / 9 - 1 + nc) % nc;
+      const int c = (jz * nc + jy) * nc + jx;
+      for (int j = cstart[c]; j < cend[c]; ++j) {
+        if (j == k) continue;
+        const double dx = wrap(x - Rs[4 * (int64_t)j], L, invL), dy = wrap(y - Rs[4 * (int64_t)j + 1], L, invL),
+                     dz = wrap(z - Rs[4 * (int64_t)j + 2], L, invL);
+        best = fmin(best, fma(dx, dx, fma(dy, dy, dz * dz)));
+      }
+    }
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out[0] = sqrt(min over the nb partial minima) (unless skip is given and out[0] < edge already)
+__global__ void __launch_bounds__(256) k_min_finish(const double* __restrict__ part, int nb, double* __restrict__ out,
+                                                    bool skip, double edge) {
+  if (skip && out[0] < edge) return;
   __shared__ double red[256];
   double m = INFINITY;
   for (int k = threadIdx.x; k < nb; k += blockDim.x) m = fmin(m, part[k]);
@@ -702,7 +741,7 @@ struct FftPlan {
 // the earlier radices), transforms them and puts them at (j - k) R + k + r Ns: natural order in and
 // out. The first stage reads the line from memory and the last one writes it back; the others work
 // in LDS, every thread reading all its points before the barrier and writing after it.
-template <int R, bool INV>
+template <int R, bool INV, bool CONTIG>
 __device__ __forceinline__ void fft_stage(double2* xs, double2* g, bool from_g, bool to_g, int M, int B, int Ns,
                                           int64_t sk, int64_t sb, const double2* __restrict__ tw) {
   constexpr int NB = 4096 / R / 256;  // butterflies per thread (B M <= 4096, 256 threads)
@@ -712,11 +751,11 @@ __device__ __forceinline__ void fft_stage(double2* xs, double2* g, bool from_g, 
   for (int q = 0; q < NB; ++q) {
     const int e = threadIdx.x + q * 256;
     if (e < nbf) {
-      const int l = sk == 1 ? e / MR : e % B, j = sk == 1 ? e % MR : e / B;
+      const int l = CONTIG ? e / MR : e % B, j = CONTIG ? e % MR : e / B;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = j + r * MR;
-        v[q][r] = from_g ? g[(int64_t)l * sb + (int64_t)idx * sk] : xs[fft_slot(l, idx, M)];
+        v[q][r] = from_g ? g[(int64_t)l * sb + (CONTIG ? (int64_t)idx : (int64_t)idx * sk)] : xs[fft_slot(l, idx, M)];
       }
       const int k = j & (Ns - 1), step = M / (Ns * R);
 #pragma unroll
@@ -734,13 +773,13 @@ __device__ __forceinline__ void fft_stage(double2* xs, double2* g, bool from_g, 
   for (int q = 0; q < NB; ++q) {
     const int e = threadIdx.x + q * 256;
     if (e < nbf) {
-      const int l = sk == 1 ? e / MR : e % B, j = sk == 1 ? e % MR : e / B;
+      const int l = CONTIG ? e / MR : e % B, j = CONTIG ? e % MR : e / B;
       const int k = j & (Ns - 1), o = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = o + r * Ns;
         if (to_g)
-          g[(int64_t)l * sb + (int64_t)idx * sk] = v[q][r];
+          g[(int64_t)l * sb + (CONTIG ? (int64_t)idx : (int64_t)idx * sk)] = v[q][r];
         else
           xs[fft_slot(l, idx, M)] = v[q][r];
       }
@@ -752,8 +791,8 @@ __device__ __forceinline__ void fft_stage(double2* xs, double2* g, bool from_g, 
 // One pass of the 3D transform: every line of M points along one axis (point idx of line l of a
 // bundle at base + l sb + idx sk), B lines per workgroup (consecutive in memory for the strided axes,
 // so that B contiguous points move together). Forward: X(m) = sum_g x(g) exp(-2 pi i m g / M); INV:
-// the conjugate exponent, no normalisation.
-template <bool INV>
+// the conjugate exponent, no normalisation. AXIS 0 is the contiguous one (sk = 1).
+template <bool INV, int AXIS>
 __global__ void __launch_bounds__(256)
     k_fft_lines(double2* __restrict__ a, int M, int B, int64_t sk, int64_t sb, int nbu, int64_t su, int64_t sv,
                 int64_t sf, const double2* __restrict__ tw, FftPlan pl) {
@@ -764,9 +803,9 @@ __global__ void __launch_bounds__(256)
   for (int st = 0; st < pl.nst; ++st) {
     const bool first = st == 0, last = st == pl.nst - 1;
     if (pl.r[st] == 8)
-      fft_stage<8, INV>(xs, base, first, last, M, B, Ns, sk, sb, tw);
+      fft_stage<8, INV, AXIS == 0>(xs, base, first, last, M, B, Ns, sk, sb, tw);
     else
-      fft_stage<4, INV>(xs, base, first, last, M, B, Ns, sk, sb, tw);
+      fft_stage<4, INV, AXIS == 0>(xs, base, first, last, M, B, Ns, sk, sb, tw);
     Ns *= pl.r[st];
   }
 }
@@ -943,15 +982,19 @@ void pm_fft(double2* a, int nf, int M, bool inv, const double2* tw, hipStream_t 
   const int64_t M2 = (int64_t)M * M, M3 = M2 * M;
   const size_t lds = (size_t)B * M * sizeof(double2);
   const dim3 grid((unsigned)(M2 / B), (unsigned)nf);
-  auto go = [&](int64_t sk, int64_t sb, int64_t su, int64_t sv) {
-    if (inv)
-      hipLaunchKernelGGL(k_fft_lines<true>, grid, dim3(256), lds, s, a, M, B, sk, sb, M / B, su, sv, M3, tw, pl);
-    else
-      hipLaunchKernelGGL(k_fft_lines<false>, grid, dim3(256), lds, s, a, M, B, sk, sb, M / B, su, sv, M3, tw, pl);
-  };
-  go(1, M, (int64_t)B * M, M2);  // along x: a workgroup's lines consecutive in y
-  go(M, 1, B, M2);               // along y: lines consecutive in x
-  go(M2, 1, B, M);               // along z: lines consecutive in x
+#define MBS_FFT_PASS(AX, SK, SB, SU, SV)                                                                        \
+  do {                                                                                                          \
+    if (inv)                                                                                                    \
+      hipLaunchKernelGGL((k_fft_lines<true, AX>), grid, dim3(256), lds, s, a, M, B, SK, SB, M / B, SU, SV, M3, \
+                         tw, pl);                                                                               \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_fft_lines<false, AX>), grid, dim3(256), lds, s, a, M, B, SK, SB, M / B, SU, SV,    \
+                         M3, tw, pl);                                                                           \
+  } while (0)
+  MBS_FFT_PASS(0, (int64_t)1, (int64_t)M, (int64_t)B * M, M2);  // along x: a workgroup's lines consecutive in y
+  MBS_FFT_PASS(1, (int64_t)M, (int64_t)1, (int64_t)B, M2);      // along y: lines consecutive in x
+  MBS_FFT_PASS(2, M2, (int64_t)1, (int64_t)B, (int64_t)M);      // along z: lines consecutive in x
+#undef MBS_FFT_PASS
 }
 
 template <int TGT>
@@ -1159,8 +1202,25 @@ int per_min_dist_part(int64_t n) { return (int)((n + 255) / 256); }
 
 void launch_per_min_dist(const double* R, int64_t n, double L, double* part, double* out, hipStream_t s) {
   const int nb = per_min_dist_part(n);
-  hipLaunchKernelGGL(k_per_min_d2, dim3(nb), dim3(256), 0, s, R, (int)n, L, 1.0 / L, part);
-  hipLaunchKernelGGL(k_min_finish, dim3(1), dim3(256), 0, s, part, nb, out);
+  hipLaunchKernelGGL(k_per_min_d2, dim3(nb), dim3(256), 0, s, R, (int)n, L, 1.0 / L, part, (const double*)nullptr,
+                     0.0);
+  hipLaunchKernelGGL(k_min_finish, dim3(1), dim3(256), 0, s, part, nb, out, false, 0.0);
+}
+
+void launch_pm_min_dist(const double* R, int64_t n, const PerBox& g, double* part, double* out, hipStream_t s) {
+  // the box grid's 27 neighbouring cells find every pair closer than a cell edge; only when none is
+  // (a sparse box) does the all-pairs scan run, decided on the device
+  const int nb = per_min_dist_part(n);
+  const PmLayout Ly = pm_layout(g.M, n, g.nc);
+  char* wb = (char*)g.mws;
+  GridView gv;
+  (void)grid_build_box(R, (int)n, g.L, g.nc, wb + Ly.grid, Ly.total - Ly.grid, &gv, s);
+  const double edge = g.L / g.nc;
+  hipLaunchKernelGGL(k_pm_min_d2, dim3(nb), dim3(256), 0, s, gv.hdr, gv.Rs, gv.start, gv.end, g.nc, (int)n, g.L,
+                     1.0 / g.L, part);
+  hipLaunchKernelGGL(k_min_finish, dim3(1), dim3(256), 0, s, part, nb, out, false, 0.0);
+  hipLaunchKernelGGL(k_per_min_d2, dim3(nb), dim3(256), 0, s, R, (int)n, g.L, 1.0 / g.L, part + nb, out, edge);
+  hipLaunchKernelGGL(k_min_finish, dim3(1), dim3(256), 0, s, part + nb, nb, out, true, edge);
 }
 
 void launch_per_flow(const double* X, int64_t m, const double* R, int64_t n, const double* Fe, const double* Te,

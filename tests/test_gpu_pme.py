@@ -191,3 +191,42 @@ def test_pme_parameter_checks(ctx):
         ctx.set_params(box=0.0, ewald_mesh=64)  # a mesh needs a box
     assert e.value.code == mbstokes.MBS_EINVAL
     ctx.set_params(box=0.0, ewald_mesh=0, ewald_xi=0.0)
+
+
+def test_pme_stepper_matches_oracle(ctx):
+    """Force-free swimmers (slip modes 1, 1, 1 along p, no trap) stepped three times in the box on the
+    mesh against the oracle's stepper on the exact periodic solve."""
+    from oracle import stepper
+    n = 24
+    w, L = _workload(n, 4500, L=20.0)
+    Rw, pw, _ = stepper.run(w.R, w.p, 0.0, (1.0, 1.0, 1.0), 0.05, 3, PRM,
+                            solve=lambda st, pr: periodic.solve(st, _ew(L), pr))
+    R, p = _t(w.R), _t(w.p)
+    with _Mesh(ctx, L, 64, tol=1e-13):
+        stats, md = ctx.mbs_step(R, p, 0.0, (1.0, 1.0, 1.0), 0.05, 3, order=2, want_min_dist=True)
+    errs = (_maxrel(R, Rw), _maxrel(p, pw))
+    print(f"  stepper errors R {errs[0]:.3e} p {errs[1]:.3e}", flush=True)
+    assert max(errs) < 1e-8
+
+
+@pytest.mark.parametrize("layout", ["random", "sparse"])
+def test_pme_stepper_min_dist_from_the_box_grid(ctx, layout):
+    """With a mesh and at least 3 cells per axis the stepper's smallest minimum-image distance comes
+    from the box grid's neighbouring cells (300 spheres placed at random), or from all pairs when no
+    pair is closer than a cell edge (8 spheres near the sites of a 2 x 2 x 2 lattice): exact either way."""
+    print(f"pme min_dist {layout}", flush=True)
+    L = 42.0  # M = 128: xi = 0.5/a, rc = 10a, 4 cells of 10.5a per axis
+    if layout == "random":
+        w, _ = _workload(300, 4600, L=L)
+    else:
+        w, _ = _workload(8, 4601, L=L)
+        g = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], float) * (L / 2) + 5.0
+        w.R = g + np.random.default_rng(3).uniform(-1.0, 1.0, g.shape)
+    n = len(w.R)
+    d = w.R[:, None, :] - w.R[None, :, :]
+    d -= L * np.round(d / L)
+    want = (np.sqrt((d ** 2).sum(-1)) + np.eye(n) * 1e9).min()
+    with _Mesh(ctx, L, 128, tol=1e-8):
+        stats, md = ctx.mbs_step(_t(w.R), _t(w.p), 0.0, (1.0, 1.0, 1.0), 0.01, 1, order=1, want_min_dist=True)
+    assert (want < 10.5) == (layout == "random")
+    assert abs(md[0] - want) < 1e-12 * L
