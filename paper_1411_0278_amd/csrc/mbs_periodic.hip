@@ -104,11 +104,11 @@ __device__ __forceinline__ void coeffs(const RecP& r, double* v) {
 
 __device__ __forceinline__ double wrap(double d, double L, double invL) { return d - L * rint(d * invL); }
 
-// one source record's screened real-space term at a receiver (the pair within rc, not coincident)
+// one source record's screened real-space term at a receiver, the separation (dx, dy, dz) already
+// the minimum image (the pair within rc, not coincident)
 template <int TGT>
-__device__ __forceinline__ void real_pair(const RecP& s, double xi0, double yi0, double zi0, double L, double invL,
-                                          double xi, double a2, double* acc) {
-  const double dx = wrap(xi0 - s.x, L, invL), dy = wrap(yi0 - s.y, L, invL), dz = wrap(zi0 - s.z, L, invL);
+__device__ __forceinline__ void real_pair_d(const RecP& s, double dx, double dy, double dz, double xi, double a2,
+                                            double* acc) {
   const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
   const double r = sqrt(r2);
   const double ri = 1.0 / r, ec = erfc(xi * r), ex = exp(-xi * xi * r2);
@@ -139,6 +139,12 @@ __device__ __forceinline__ void real_pair(const RecP& s, double xi0, double yi0,
   if (TGT == kPRhs) per_real_strain_ftq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.q, acc);
   if (TGT == kPOut) per_real_motion_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc, acc + 3);
   if (TGT == kPFlow) per_real_flow_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc);
+}
+
+template <int TGT>
+__device__ __forceinline__ void real_pair(const RecP& s, double xi0, double yi0, double zi0, double L, double invL,
+                                          double xi, double a2, double* acc) {
+  real_pair_d<TGT>(s, wrap(xi0 - s.x, L, invL), wrap(yi0 - s.y, L, invL), wrap(zi0 - s.z, L, invL), xi, a2, acc);
 }
 
 template <int TGT>
@@ -547,7 +553,9 @@ __global__ void __launch_bounds__(kPmRT)
   constexpr int W = pw(TGT);
   const int cell = blockIdx.x;
   const int ix = cell % nc, iy = (cell / nc) % nc, iz = cell / (nc * nc);
-  const int jz = (iz + (int)blockIdx.y - 1 + nc) % nc;
+  const int jzr = iz + (int)blockIdx.y - 1;
+  const int jz = (jzr + nc) % nc;
+  const double shz = jzr < 0 ? -L : (jzr >= nc ? L : 0.0);
   const int r0 = cstart[cell], r1 = cend[cell];
   for (int rb = r0; rb < r1; rb += kPmRT) {
     const int k = rb + threadIdx.x;
@@ -557,8 +565,12 @@ __global__ void __launch_bounds__(kPmRT)
 #pragma unroll
     for (int c = 0; c < W; ++c) acc[c] = 0.0;
     for (int nb = 0; nb < 9; ++nb) {
-      const int jx = (ix + nb % 3 - 1 + nc) % nc, jy = (iy + nb / 3 - 1 + nc) % nc;
+      const int jxr = ix + nb % 3 - 1, jyr = iy + nb / 3 - 1;  // neighbour cell before wrapping
+      const int jx = (jxr + nc) % nc, jy = (jyr + nc) % nc;
       const int sc = (jz * nc + jy) * nc + jx;
+      // the neighbour's spheres moved by whole boxes to the cell's side of the receiver's: with cells
+      // of at least rc and 3 or more per axis this is the minimum image of every pair within rc
+      const double shx = jxr < 0 ? -L : (jxr >= nc ? L : 0.0), shy = jyr < 0 ? -L : (jyr >= nc ? L : 0.0);
       const int s0 = cstart[sc], s1 = cend[sc];
       for (int jt = s0; jt < s1; jt += kPTJ) {
         const int cnt = min(kPTJ, s1 - jt);
@@ -567,9 +579,9 @@ __global__ void __launch_bounds__(kPmRT)
           const int64_t j = perm[jt + t];
           RecP r;
           r.pad = 0.0;
-          r.x = Rs[4 * (int64_t)(jt + t)];
-          r.y = Rs[4 * (int64_t)(jt + t) + 1];
-          r.z = Rs[4 * (int64_t)(jt + t) + 2];
+          r.x = Rs[4 * (int64_t)(jt + t)] + shx;
+          r.y = Rs[4 * (int64_t)(jt + t) + 1] + shy;
+          r.z = Rs[4 * (int64_t)(jt + t) + 2] + shz;
           for (int c = 0; c < 3; ++c) {
             r.f[c] = (TGT != kPOp && Fe) ? P * Fe[3 * j + c] : 0.0;
             r.t[c] = (TGT != kPOp && Te) ? P * Te[3 * j + c] : 0.0;
@@ -582,15 +594,14 @@ __global__ void __launch_bounds__(kPmRT)
         uint64_t hits = 0;
 #pragma unroll 8
         for (int q = 0; q < cnt; ++q) {
-          const double dx = wrap(xi0 - tile[q].x, L, invL), dy = wrap(yi0 - tile[q].y, L, invL),
-                       dz = wrap(zi0 - tile[q].z, L, invL);
+          const double dx = xi0 - tile[q].x, dy = yi0 - tile[q].y, dz = zi0 - tile[q].z;
           const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
           hits |= (uint64_t)(r2 < rc2 && r2 > 0.0) << q;
         }
         while (hits) {
           const int q = __ffsll((unsigned long long)hits) - 1;
           hits &= hits - 1;
-          real_pair<TGT>(tile[q], xi0, yi0, zi0, L, invL, xi, a2, acc);
+          real_pair_d<TGT>(tile[q], xi0 - tile[q].x, yi0 - tile[q].y, zi0 - tile[q].z, xi, a2, acc);
         }
       }
     }
@@ -810,33 +821,29 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// per mesh wave vector m (k = 2 pi m / L, |m_d| < M/2, m != 0): the coefficients' transforms
-// separated from the packed fields (Z = Q_{2a} + i Q_{2a+1}: Q_{2a}(m) = (Z(m) + conj Z(-m)) / 2,
-// Q_{2a+1}(m) = (Z(m) - conj Z(-m)) / 2i), the generated multiplier applied with the splitting
-// factor, |b(m)|^2 and 1 / L^3, the targets packed again in pairs (T_{2b} + i T_{2b+1})
+// At mesh wave vector m = (x, y, z) (k = 2 pi m / L, |m_d| < M/2, m != 0): the coefficients'
+// transforms separated from the packed fields at m (zp) and -m (zm) (Z = Q_{2a} + i Q_{2a+1}:
+// Q_{2a}(m) = (Z(m) + conj Z(-m)) / 2, Q_{2a+1}(m) = (Z(m) - conj Z(-m)) / 2i), the generated
+// multiplier applied with the splitting factor, |b(m)|^2 and 1 / L^3, the targets packed again in
+// pairs (T_{2b} + i T_{2b+1}) into Y; zero at m = 0 and on the Nyquist planes.
 template <int TGT>
-__global__ void __launch_bounds__(256)
-    k_pm_mult(const double2* __restrict__ fin, int M, double dk, double xi, double a2, double invL3,
-              const double* __restrict__ bmod, double2* __restrict__ fout) {
+__device__ __forceinline__ void pm_point(const double2* zp, const double2* zm, int x, int y, int z, int M, double dk,
+                                         double xi, double a2, double invL3, const double* __restrict__ bmod,
+                                         double2* Y) {
   constexpr int NC = pnc(sft(TGT)), W = pw(TGT), NI = (NC + 1) / 2, NO = (W + 1) / 2;
-  const int64_t M3 = (int64_t)M * M * M;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= M3) return;
-  const int x = (int)(idx % M), y = (int)((idx / M) % M), z = (int)(idx / ((int64_t)M * M));
   const int h = M >> 1;
   if ((x == 0 && y == 0 && z == 0) || x == h || y == h || z == h) {
-    for (int b = 0; b < NO; ++b) fout[(int64_t)b * M3 + idx] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int b = 0; b < NO; ++b) Y[b] = make_double2(0.0, 0.0);
     return;
   }
-  const int64_t nidx = ((int64_t)((M - z) & (M - 1)) * M + ((M - y) & (M - 1))) * M + ((M - x) & (M - 1));
   double re[2 * NI], im[2 * NI];
 #pragma unroll
   for (int a = 0; a < NI; ++a) {
-    const double2 zp = fin[(int64_t)a * M3 + idx], zm = fin[(int64_t)a * M3 + nidx];
-    re[2 * a] = 0.5 * (zp.x + zm.x);
-    im[2 * a] = 0.5 * (zp.y - zm.y);
-    re[2 * a + 1] = 0.5 * (zp.y + zm.y);
-    im[2 * a + 1] = 0.5 * (zm.x - zp.x);
+    re[2 * a] = 0.5 * (zp[a].x + zm[a].x);
+    im[2 * a] = 0.5 * (zp[a].y - zm[a].y);
+    re[2 * a + 1] = 0.5 * (zp[a].y + zm[a].y);
+    im[2 * a + 1] = 0.5 * (zm[a].x - zp[a].x);
   }
   const double k1 = dk * (x < h ? x : x - M), k2 = dk * (y < h ? y : y - M), k3 = dk * (z < h ? z : z - M);
   const double ksq = fma(k1, k1, fma(k2, k2, k3 * k3));
@@ -852,9 +859,112 @@ __global__ void __launch_bounds__(256)
   if (TGT == kPFlow)
     per_hat_flow_ftsq(k1, k2, k3, ik2, a2, re, im, re + 3, im + 3, re + 6, im + 6, re + 11, im + 11, tr, ti);
 #pragma unroll
-  for (int b = 0; b < NO; ++b)
-    fout[(int64_t)b * M3 + idx] =
-        make_double2(g * (tr[2 * b] - ti[2 * b + 1]), g * (ti[2 * b] + tr[2 * b + 1]));
+  for (int b = 0; b < NO; ++b) Y[b] = make_double2(g * (tr[2 * b] - ti[2 * b + 1]), g * (ti[2 * b] + tr[2 * b + 1]));
+}
+
+// the multiplier at every mesh point, from the transformed packed fields (all three axes)
+template <int TGT>
+__global__ void __launch_bounds__(256)
+    k_pm_mult(const double2* __restrict__ fin, int M, double dk, double xi, double a2, double invL3,
+              const double* __restrict__ bmod, double2* __restrict__ fout) {
+  constexpr int NC = pnc(sft(TGT)), W = pw(TGT), NI = (NC + 1) / 2, NO = (W + 1) / 2;
+  const int64_t M3 = (int64_t)M * M * M;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M3) return;
+  const int x = (int)(idx % M), y = (int)((idx / M) % M), z = (int)(idx / ((int64_t)M * M));
+  const int64_t nidx = ((int64_t)((M - z) & (M - 1)) * M + ((M - y) & (M - 1))) * M + ((M - x) & (M - 1));
+  double2 zp[NI], zm[NI], Y[NO];
+#pragma unroll
+  for (int a = 0; a < NI; ++a) {
+    zp[a] = fin[(int64_t)a * M3 + idx];
+    zm[a] = fin[(int64_t)a * M3 + nidx];
+  }
+  pm_point<TGT>(zp, zm, x, y, z, M, dk, xi, a2, invL3, bmod, Y);
+#pragma unroll
+  for (int b = 0; b < NO; ++b) fout[(int64_t)b * M3 + idx] = Y[b];
+}
+
+// The x transforms fused with the multiplier: one x line (y, z) of the packed fields and its mirror
+// line (-y, -z) (the multiplier at m needs the packed inputs at -m, which lie on the mirror line)
+// read once into LDS after the y and z transforms, transformed along x, multiplied point pair by
+// point pair (m on this line with -m on the mirror line, each thread reading its pairs before the
+// barrier and writing after it), transformed back along x and written to the output fields, which
+// then take the inverse y and z transforms. The workgroup of the lower of the two lines does both
+// (a line that is its own mirror, y and z each 0 or M/2, alone). Needs 2 NI M <= 4096 (LDS).
+template <int TGT>
+__global__ void __launch_bounds__(256)
+    k_pm_xmult(const double2* __restrict__ fin, int M, double dk, double xi, double a2, double invL3,
+               const double* __restrict__ bmod, const double2* __restrict__ tw, FftPlan pl,
+               double2* __restrict__ fout) {
+  constexpr int NC = pnc(sft(TGT)), W = pw(TGT), NI = (NC + 1) / 2, NO = (W + 1) / 2;
+  constexpr int PPT = 2;  // point pairs per thread (M <= 512)
+  extern __shared__ double2 xs[];
+  const int y = blockIdx.x % M, z = blockIdx.x / M;
+  const int yp = (M - y) & (M - 1), zp = (M - z) & (M - 1);
+  if (z * M + y > zp * M + yp) return;  // (uniform) the mirror line's workgroup does both
+  const bool self = y == yp && z == zp;
+  const int nl = self ? NI : 2 * NI;
+  const int64_t M3 = (int64_t)M * M * M;
+  const int64_t row = ((int64_t)z * M + y) * M, rowp = ((int64_t)zp * M + yp) * M;
+  for (int e = threadIdx.x; e < nl * M; e += blockDim.x) {
+    const int l = e / M, x = e % M;
+    xs[fft_slot(l, x, M)] = fin[(l < NI ? row : rowp) + (int64_t)(l % NI) * M3 + x];
+  }
+  __syncthreads();
+  int Ns = 1;
+  for (int st = 0; st < pl.nst; ++st) {
+    if (pl.r[st] == 8)
+      fft_stage<8, false, true>(xs, nullptr, false, false, M, nl, Ns, 1, M, tw);
+    else
+      fft_stage<4, false, true>(xs, nullptr, false, false, M, nl, Ns, 1, M, tw);
+    Ns *= pl.r[st];
+  }
+  const int npair = self ? M / 2 + 1 : M;  // (self: x = 0..M/2 with -x on the same line)
+  const int lm = self ? 0 : NI;            // first input line of the mirror
+  const int lo = self ? 0 : NO;            // first output line of the mirror
+  double2 yo[PPT][NO], ym[PPT][NO];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int x = threadIdx.x + q * 256;
+    if (x < npair) {
+      const int xm = (M - x) & (M - 1);
+      double2 zo[NI], zr[NI];
+#pragma unroll
+      for (int a = 0; a < NI; ++a) {
+        zo[a] = xs[fft_slot(a, x, M)];
+        zr[a] = xs[fft_slot(lm + a, xm, M)];
+      }
+      pm_point<TGT>(zo, zr, x, y, z, M, dk, xi, a2, invL3, bmod, yo[q]);
+      pm_point<TGT>(zr, zo, xm, yp, zp, M, dk, xi, a2, invL3, bmod, ym[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int x = threadIdx.x + q * 256;
+    if (x < npair) {
+      const int xm = (M - x) & (M - 1);
+#pragma unroll
+      for (int b = 0; b < NO; ++b) {
+        xs[fft_slot(b, x, M)] = yo[q][b];
+        xs[fft_slot(lo + b, xm, M)] = ym[q][b];
+      }
+    }
+  }
+  __syncthreads();
+  const int nlo = self ? NO : 2 * NO;
+  Ns = 1;
+  for (int st = 0; st < pl.nst; ++st) {
+    if (pl.r[st] == 8)
+      fft_stage<8, true, true>(xs, nullptr, false, false, M, nlo, Ns, 1, M, tw);
+    else
+      fft_stage<4, true, true>(xs, nullptr, false, false, M, nlo, Ns, 1, M, tw);
+    Ns *= pl.r[st];
+  }
+  for (int e = threadIdx.x; e < nlo * M; e += blockDim.x) {
+    const int l = e / M, x = e % M;
+    fout[(l < NO ? row : rowp) + (int64_t)(l % NO) * M3 + x] = xs[fft_slot(l, x, M)];
+  }
 }
 
 // part[out(k) * W] = sum over the P^3 mesh points around receiver k of its weights times the
@@ -975,8 +1085,9 @@ FftPlan fft_plan(int M) {
   return p;
 }
 
-// the 3D transform of nf complex fields of M^3 points (x fastest), in place
-void pm_fft(double2* a, int nf, int M, bool inv, const double2* tw, hipStream_t s) {
+// the transform of nf complex fields of M^3 points (x fastest) along the axes in mask (1 x, 2 y,
+// 4 z), in place
+void pm_fft(double2* a, int nf, int M, bool inv, const double2* tw, hipStream_t s, int mask = 7) {
   const FftPlan pl = fft_plan(M);
   const int B = std::max(1, std::min(16, 4096 / M));
   const int64_t M2 = (int64_t)M * M, M3 = M2 * M;
@@ -991,9 +1102,9 @@ void pm_fft(double2* a, int nf, int M, bool inv, const double2* tw, hipStream_t 
       hipLaunchKernelGGL((k_fft_lines<false, AX>), grid, dim3(256), lds, s, a, M, B, SK, SB, M / B, SU, SV,    \
                          M3, tw, pl);                                                                           \
   } while (0)
-  MBS_FFT_PASS(0, (int64_t)1, (int64_t)M, (int64_t)B * M, M2);  // along x: a workgroup's lines consecutive in y
-  MBS_FFT_PASS(1, (int64_t)M, (int64_t)1, (int64_t)B, M2);      // along y: lines consecutive in x
-  MBS_FFT_PASS(2, M2, (int64_t)1, (int64_t)B, (int64_t)M);      // along z: lines consecutive in x
+  if (mask & 1) MBS_FFT_PASS(0, (int64_t)1, (int64_t)M, (int64_t)B * M, M2);  // x: lines consecutive in y
+  if (mask & 2) MBS_FFT_PASS(1, (int64_t)M, (int64_t)1, (int64_t)B, M2);      // y: lines consecutive in x
+  if (mask & 4) MBS_FFT_PASS(2, M2, (int64_t)1, (int64_t)B, (int64_t)M);      // z: lines consecutive in x
 #undef MBS_FFT_PASS
 }
 
@@ -1033,10 +1144,17 @@ void pm_launch(const double* X, int64_t m, const double* R, int64_t n, const dou
     hipLaunchKernelGGL((k_pm_spread<kPOut, 12, 2>), sg, dim3(64), 0, s, gv.perm, gv.start, gv.end, b0, wts, Fe, Te,
                        Sig, D, ph.P, a5_20, M, g.nc, fin + 6 * M3);
   }
-  pm_fft(fin, NI, M, false, tw, s);
-  hipLaunchKernelGGL(k_pm_mult<TGT>, dim3(nblk_p(M3, 256)), dim3(256), 0, s, fin, M, 2.0 * M_PI / g.L, g.xi, ph.a2,
-                     1.0 / (g.L * g.L * g.L), bmod, fout);
-  pm_fft(fout, NO, M, true, tw, s);
+  if (2 * NI * M <= 4096) {  // the x transforms fused with the multiplier
+    pm_fft(fin, NI, M, false, tw, s, 6);
+    hipLaunchKernelGGL(k_pm_xmult<TGT>, dim3((unsigned)(M * M)), dim3(256), (size_t)2 * NI * M * sizeof(double2), s,
+                       fin, M, 2.0 * M_PI / g.L, g.xi, ph.a2, 1.0 / (g.L * g.L * g.L), bmod, tw, fft_plan(M), fout);
+    pm_fft(fout, NO, M, true, tw, s, 6);
+  } else {
+    pm_fft(fin, NI, M, false, tw, s);
+    hipLaunchKernelGGL(k_pm_mult<TGT>, dim3(nblk_p(M3, 256)), dim3(256), 0, s, fin, M, 2.0 * M_PI / g.L, g.xi, ph.a2,
+                       1.0 / (g.L * g.L * g.L), bmod, fout);
+    pm_fft(fout, NO, M, true, tw, s);
+  }
   // real space: over the box grid's neighbouring cells when it has at least 3 cells per axis (the
   // spheres as receivers), else over all pairs; the mesh part interpolated at the receivers
   const bool cells = TGT != kPFlow && g.nc >= 3;

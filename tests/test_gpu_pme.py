@@ -109,9 +109,11 @@ def test_pme_operator_matches_oracle(ctx, n, M):
     assert torch.equal(got, again)  # every sum in a fixed order: bitwise reproducible
 
 
-@pytest.mark.parametrize("n,M", [(97, 64), (300, 128)])
+@pytest.mark.parametrize("n,M", [(97, 64), (300, 128), (97, 512)])
 def test_pme_rhs_and_outputs_match_oracle(ctx, n, M):
-    print(f"pme rhs/outputs n={n} M={M}", flush=True)  # 300 spheres: the real space over the box grid's cells
+    # 300 spheres: the real space over the box grid's cells; M = 512: the multiplier in its own pass
+    # (the x transforms fused with it need 2 NI M <= 4096 points of LDS)
+    print(f"pme rhs/outputs n={n} M={M}", flush=True)
     w, L = _workload(n, 4100 + n)
     Sig = np.random.default_rng(5).standard_normal((n, 5))
     b = periodic.rhs(w.R, w.v2s, w.v3t, w.Fe, w.Te, PRM, _ew(L)).reshape(n, 5)
