@@ -88,6 +88,9 @@ struct mbs_ctx {
   DevBuf per_tab;  // particle-mesh Ewald: the mesh's twiddles and B-spline factors
   DevBuf per_mws;  // particle-mesh Ewald: mesh fields, weights and the sources' box grid
   int per_tabM = 0;
+  DevBuf per_rtab;  // particle-mesh Ewald: the operator's radial table for the real-space pass
+  int per_rt_np = 0;
+  double per_rt_xi = 0.0, per_rt_a2 = 0.0, per_rt_rc = 0.0;
   // a solve in the Morton order of the centres: the permutation and the reordered inputs/outputs
   DevBuf ord;
   // single-configuration GMRES: Arnoldi steps captured as graphs (per precision), see step_graphs
@@ -237,7 +240,7 @@ PerBox per_box(const mbs_ctx* c, int64_t n) {
   const int2* seg = reinterpret_cast<const int2*>(c->per_seg.p);
   return PerBox{c->prm.box, xi, per_rc(c, xi), c->per_K, c->per_kv.p, seg, c->per_nseg8,
                 seg ? seg + c->per_nseg8 : nullptr, c->per_nseg4, c->prm.ewald_mesh, per_nc(c, xi),
-                c->per_tab.p, c->per_mws.p};
+                c->per_tab.p, c->per_mws.p, c->per_rtab.p, c->prm.ewald_mesh ? c->per_rt_np : 0};
 }
 // the mesh's tables and workspace for n sources (particle-mesh Ewald)
 int pm_prepare(mbs_ctx* c, int64_t n) {
@@ -250,6 +253,16 @@ int pm_prepare(mbs_ctx* c, int64_t n) {
   }
   const size_t bytes = pm_ws_bytes(M, n, per_nc(c, per_xi(c, n)));
   CHK(ensure(c, c->per_mws, (bytes + 7) / 8));
+  const double xi = per_xi(c, n), rc = per_rc(c, xi);
+  if (!c->per_rtab.p || c->per_rt_xi != xi || c->per_rt_a2 != c->ph.a2 || c->per_rt_rc != rc) {
+    CHK(ensure(c, c->per_rtab, pm_radial_doubles()));
+    HIPCHK(c, pm_radial_table(xi, c->ph.a2, rc, c->per_rtab.p, nullptr));
+    HIPCHK(c, hipDeviceSynchronize());
+    c->per_rt_np = pm_radial_pieces(c->ph.a2, rc);
+    c->per_rt_xi = xi;
+    c->per_rt_a2 = c->ph.a2;
+    c->per_rt_rc = rc;
+  }
   return MBS_OK;
 }
 // (re)builds the wave-vector list when the box or the splitting changed (outside any graph capture)
@@ -1445,7 +1458,7 @@ void mbs_destroy(mbs_ctx* c) {
                     &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig, &c->near, &c->zt,
                     &c->nt, &c->stepstate,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
-                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->ord, &c->r3, &c->per_kv, &c->per_seg, &c->per_tab, &c->per_mws,
+                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->ord, &c->r3, &c->per_kv, &c->per_seg, &c->per_tab, &c->per_mws, &c->per_rtab,
                     &c->bat, &c->btune};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);

@@ -131,7 +131,14 @@ struct PerBox {
   int nc;             // cells per axis of the sources' box grid
   const double* tab;  // pm_tables(M) on the device
   void* mws;          // pm_ws_bytes(M, n, nc) bytes of device workspace (256-byte aligned)
+  const double* rtab; // the operator's radial functions tabulated for the real-space pass (npiece > 0)
+  int npiece;
 };
+// pieces of the radial table for spheres of radius^2 a2 and cutoff rc (0: no table); device doubles
+// to hold any table; the table of splitting xi built on stream s
+int pm_radial_pieces(double a2, double rc);
+size_t pm_radial_doubles();
+hipError_t pm_radial_table(double xi, double a2, double rc, double* tab, hipStream_t s);
 // mesh workspace bytes for n sources; the mesh's twiddles and B-spline factors (3M doubles)
 size_t pm_ws_bytes(int M, int64_t n, int nc);
 std::vector<double> pm_tables(int M);

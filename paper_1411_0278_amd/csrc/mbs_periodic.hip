@@ -104,18 +104,85 @@ __device__ __forceinline__ void coeffs(const RecP& r, double* v) {
 
 __device__ __forceinline__ double wrap(double d, double L, double invL) { return d - L * rint(d * invL); }
 
+// The operator's three radial functions (al, be, ga of the screened stresslet strain's isotropic
+// form) tabulated in s = r^2 for the mesh's real-space pass, whose result carries the mesh's own
+// error of order 1e-8: Chebyshev series of degree kRtD on kRtK pieces per octave of s / a^2 from
+// s = a^2 up (a piece spans 1/8 of its octave, so the powers of 1/r and the splitting's exponentials
+// are resolved to about 1e-13 of their values), evaluated by Clenshaw's recurrence; pairs closer
+// than a, or beyond the table, take the exact form. No erfc, exp, square root or division per pair.
+constexpr int kRtD = 10;                       // degree
+constexpr int kRtK = 8;                        // pieces per octave
+constexpr int kRtOct = 20;                     // octaves at most (rc up to 1024 a)
+constexpr int kRtC = 3 * (kRtD + 1);           // coefficients per piece
+constexpr int kRtMax = kRtOct * kRtK * kRtC;   // doubles
+
+// piece (oct, sub) covers s in s_lo 2^oct [1 + sub/K, 1 + (sub + 1)/K): its coefficients from the
+// exact radial functions at the D + 1 Chebyshev points (c_0 stored halved)
+__global__ void __launch_bounds__(64) k_pm_rtab(int npiece, double s_lo, double xi, double a2,
+                                                double* __restrict__ tab) {
+  const int iv = blockIdx.x * blockDim.x + threadIdx.x;
+  if (iv >= npiece) return;
+  const int oct = iv / kRtK, sub = iv % kRtK;
+  const double base = ldexp(s_lo, oct);
+  const double s0 = base * (1.0 + (double)sub / kRtK), s1 = base * (1.0 + (double)(sub + 1) / kRtK);
+  const double mid = 0.5 * (s0 + s1), half = 0.5 * (s1 - s0);
+  double v[kRtD + 1][3];
+  for (int j = 0; j <= kRtD; ++j) {
+    const double th = M_PI * (j + 0.5) / (kRtD + 1);
+    const double sj = fma(half, cos(th), mid);
+    const double r = sqrt(sj);
+    per_real_es_radial(1.0 / r, erfc(xi * r), exp(-xi * xi * sj), xi, a2, v[j]);
+  }
+  for (int f = 0; f < 3; ++f)
+    for (int k = 0; k <= kRtD; ++k) {
+      double c = 0.0;
+      for (int j = 0; j <= kRtD; ++j) c = fma(v[j][f], cos(M_PI * k * (j + 0.5) / (kRtD + 1)), c);
+      c *= 2.0 / (kRtD + 1);
+      tab[(int64_t)iv * kRtC + f * (kRtD + 1) + k] = k == 0 ? 0.5 * c : c;
+    }
+}
+
+// abg from the table in LDS (npiece pieces); false when s lies outside it
+__device__ __forceinline__ bool rtab_eval(const double* rt, int npiece, double s, double inv_slo, double* abg) {
+  int e;
+  const double m = frexp(s * inv_slo, &e);  // s / s_lo = m 2^e, m in [1/2, 1)
+  const int oct = e - 1;
+  if (oct < 0) return false;
+  const double fk = (2.0 * m - 1.0) * kRtK;  // position within the octave, in pieces
+  const int sub = min((int)fk, kRtK - 1);
+  const int iv = oct * kRtK + sub;
+  if (iv >= npiece) return false;
+  const double t = 2.0 * (fk - sub) - 1.0, t2 = 2.0 * t;
+  const double* c = rt + iv * kRtC;
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int k = kRtD; k >= 1; --k) {
+      const double b0 = fma(t2, b1, c[f * (kRtD + 1) + k] - b2);
+      b2 = b1;
+      b1 = b0;
+    }
+    abg[f] = fma(t, b1, c[f * (kRtD + 1)] - b2);
+  }
+  return true;
+}
+
 // one source record's screened real-space term at a receiver, the separation (dx, dy, dz) already
-// the minimum image (the pair within rc, not coincident)
+// the minimum image (the pair within rc, not coincident); the operator's radial functions from the
+// table rt when one is given and covers the pair
 template <int TGT>
 __device__ __forceinline__ void real_pair_d(const RecP& s, double dx, double dy, double dz, double xi, double a2,
-                                            double* acc) {
+                                            double* acc, const double* rt = nullptr, int npiece = 0,
+                                            double inv_slo = 0.0) {
   const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-  const double r = sqrt(r2);
-  const double ri = 1.0 / r, ec = erfc(xi * r), ex = exp(-xi * xi * r2);
   if (TGT == kPOp) {
     // E = al Sigma + be (x w + w x) + ga q x x (+ a trace the 5-basis drops), w = Sigma x, q = x.w
     double abg[3];
-    per_real_es_radial(ri, ec, ex, xi, a2, abg);
+    if (!rt || !rtab_eval(rt, npiece, r2, inv_slo, abg)) {
+      const double r = sqrt(r2);
+      per_real_es_radial(1.0 / r, erfc(xi * r), exp(-xi * xi * r2), xi, a2, abg);
+    }
     double sxx, syy, sxy, sxz, syz;
     basis_to_cart(s.s, sxx, syy, sxy, sxz, syz);
     const double szz = -(sxx + syy);
@@ -135,7 +202,10 @@ __device__ __forceinline__ void real_pair_d(const RecP& s, double dx, double dy,
     acc[2] = fma(abg[0], s.s[2], fma(RS2, mxy, acc[2]));
     acc[3] = fma(abg[0], s.s[3], fma(RS2, mxz, acc[3]));
     acc[4] = fma(abg[0], s.s[4], fma(RS2, myz, acc[4]));
+    return;
   }
+  const double r = sqrt(r2);
+  const double ri = 1.0 / r, ec = erfc(xi * r), ex = exp(-xi * xi * r2);
   if (TGT == kPRhs) per_real_strain_ftq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.q, acc);
   if (TGT == kPOut) per_real_motion_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc, acc + 3);
   if (TGT == kPFlow) per_real_flow_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc);
@@ -543,14 +613,21 @@ __global__ void __launch_bounds__(256) k_pm_prep(const double* __restrict__ Rs, 
 // part[(layer * m + i) * W] at the receivers' own indices
 constexpr int kPmRT = 128;  // threads of the cell real-space kernel (receivers per round)
 
+
 template <int TGT>
 __global__ void __launch_bounds__(kPmRT)
     k_pm_real(const double* __restrict__ Rs, const int32_t* __restrict__ perm, const int32_t* __restrict__ cstart,
               const int32_t* __restrict__ cend, int nc, int m, const double* __restrict__ Fe,
               const double* __restrict__ Te, const double* __restrict__ Sig, const double* __restrict__ D, double L,
-              double invL, double rc2, double xi, double a2, double P, double a5_20, double* __restrict__ part) {
+              double invL, double rc2, double xi, double a2, double P, double a5_20, const double* __restrict__ rtab,
+              int npiece, double inv_slo, double* __restrict__ part) {
   __shared__ RecP tile[kPTJ];
+  extern __shared__ double rt[];  // the operator's radial table (npiece pieces), when given
   constexpr int W = pw(TGT);
+  if (rtab) {
+    for (int i = threadIdx.x; i < npiece * kRtC; i += blockDim.x) rt[i] = rtab[i];
+    __syncthreads();
+  }
   const int cell = blockIdx.x;
   const int ix = cell % nc, iy = (cell / nc) % nc, iz = cell / (nc * nc);
   const int jzr = iz + (int)blockIdx.y - 1;
@@ -601,7 +678,8 @@ __global__ void __launch_bounds__(kPmRT)
         while (hits) {
           const int q = __ffsll((unsigned long long)hits) - 1;
           hits &= hits - 1;
-          real_pair_d<TGT>(tile[q], xi0 - tile[q].x, yi0 - tile[q].y, zi0 - tile[q].z, xi, a2, acc);
+          real_pair_d<TGT>(tile[q], xi0 - tile[q].x, yi0 - tile[q].y, zi0 - tile[q].z, xi, a2, acc,
+                           rtab ? rt : nullptr, npiece, inv_slo);
         }
       }
     }
@@ -1163,9 +1241,11 @@ void pm_launch(const double* X, int64_t m, const double* R, int64_t n, const dou
   double* preal = part;
   double* precip = preal + (int64_t)nreal * W * m;
   if (cells) {
-    hipLaunchKernelGGL(k_pm_real<TGT>, dim3((unsigned)g.nc * g.nc * g.nc, 3), dim3(kPmRT), 0, s, gv.Rs, gv.perm,
-                       gv.start, gv.end, g.nc, (int)m, Fe, Te, Sig, D, g.L, 1.0 / g.L, g.rc * g.rc, g.xi, ph.a2,
-                       ph.P, a5_20, preal);
+    const double* rtab = TGT == kPOp && g.npiece > 0 ? g.rtab : nullptr;
+    hipLaunchKernelGGL(k_pm_real<TGT>, dim3((unsigned)g.nc * g.nc * g.nc, 3), dim3(kPmRT),
+                       rtab ? (size_t)g.npiece * kRtC * sizeof(double) : 0, s, gv.Rs, gv.perm, gv.start, gv.end, g.nc,
+                       (int)m, Fe, Te, Sig, D, g.L, 1.0 / g.L, g.rc * g.rc, g.xi, ph.a2, ph.P, a5_20, rtab, g.npiece,
+                       1.0 / ph.a2, preal);
   } else {
     const int creal = (int)((n + sh.nreal - 1) / sh.nreal);
     hipLaunchKernelGGL(k_per_real<TGT>, dim3(nblk_p(m, kPBlk), sh.nreal), dim3(kPBlk), 0, s, X, (int)m, R, (int)n,
@@ -1272,6 +1352,22 @@ int64_t per_part_elems(int64_t m, int64_t n, int K, int nseg) {
 }
 
 size_t pm_ws_bytes(int M, int64_t n, int nc) { return pm_layout(M, n, nc).total; }
+
+int pm_radial_pieces(double a2, double rc) {
+  const double ratio = rc * rc / a2;
+  if (!(ratio > 1.0)) return 0;
+  const int noct = (int)ceil(log2(ratio)) + 1;
+  return noct > kRtOct ? 0 : noct * kRtK;
+}
+
+size_t pm_radial_doubles() { return (size_t)kRtMax; }
+
+hipError_t pm_radial_table(double xi, double a2, double rc, double* tab, hipStream_t s) {
+  const int np = pm_radial_pieces(a2, rc);
+  if (np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pm_rtab, dim3((unsigned)((np + 63) / 64)), dim3(64), 0, s, np, a2, xi, a2, tab);
+  return hipGetLastError();
+}
 
 std::vector<double> pm_tables(int M) {
   // twiddles exp(-2 pi i k / M), k < M, then |b(m)|^2 = 1 / |sum_{k <= P-2} M_P(k + 1) exp(2 pi i m k / M)|^2
