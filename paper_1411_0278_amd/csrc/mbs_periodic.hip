@@ -206,8 +206,57 @@ __device__ __forceinline__ void real_pair_d(const RecP& s, double dx, double dy,
   }
   const double r = sqrt(r2);
   const double ri = 1.0 / r, ec = erfc(xi * r), ex = exp(-xi * xi * r2);
-  if (TGT == kPRhs) per_real_strain_ftq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.q, acc);
-  if (TGT == kPOut) per_real_motion_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc, acc + 3);
+  if (TGT == kPRhs) {
+    // E = x a + a x + b x x (+ a trace), a = Af f + Aq q + Dt (x cross t), b = Bf (x.f) + Bq (x.q)
+    double rf[5];
+    per_real_ftq_radial(ri, ec, ex, xi, a2, rf);
+    const double xt0 = dy * s.t[2] - dz * s.t[1], xt1 = dz * s.t[0] - dx * s.t[2], xt2 = dx * s.t[1] - dy * s.t[0];
+    const double ax = fma(rf[0], s.f[0], fma(rf[2], s.q[0], rf[4] * xt0));
+    const double ay = fma(rf[0], s.f[1], fma(rf[2], s.q[1], rf[4] * xt1));
+    const double az = fma(rf[0], s.f[2], fma(rf[2], s.q[2], rf[4] * xt2));
+    const double xf = fma(dx, s.f[0], fma(dy, s.f[1], dz * s.f[2]));
+    const double xq = fma(dx, s.q[0], fma(dy, s.q[1], dz * s.q[2]));
+    const double b = fma(rf[1], xf, rf[3] * xq);
+    // diagonal M_ii and doubled off-diagonals 2 M_ij
+    const double mxx = dx * fma(b, dx, 2.0 * ax), myy = dy * fma(b, dy, 2.0 * ay), mzz = dz * fma(b, dz, 2.0 * az);
+    const double mxy = 2.0 * fma(b * dx, dy, fma(dx, ay, dy * ax));
+    const double mxz = 2.0 * fma(b * dx, dz, fma(dx, az, dz * ax));
+    const double myz = 2.0 * fma(b * dy, dz, fma(dy, az, dz * ay));
+    acc[0] = fma(RS2, mxx - myy, acc[0]);
+    acc[1] = fma(RS6, 2.0 * mzz - mxx - myy, acc[1]);
+    acc[2] = fma(RS2, mxy, acc[2]);
+    acc[3] = fma(RS2, mxz, acc[3]);
+    acc[4] = fma(RS2, myz, acc[4]);
+  }
+  if (TGT == kPOut) {
+    // U = F1 f + Q1 q + S1 w + T1 (t cross x) + (F2 (x.f) + Q2 (x.q) + S2 (x.w)) x,
+    // W = G1 (f cross x) + Gq (q cross x) + J1 (x cross w) + H1 t + H2 (x.t) x,  w = Sigma x
+    double rm[12];
+    per_real_motion_radial(ri, ec, ex, xi, a2, rm);
+    double sxx, syy, sxy, sxz, syz;
+    basis_to_cart(s.s, sxx, syy, sxy, sxz, syz);
+    const double szz = -(sxx + syy);
+    const double wx = fma(sxx, dx, fma(sxy, dy, sxz * dz));
+    const double wy = fma(sxy, dx, fma(syy, dy, syz * dz));
+    const double wz = fma(sxz, dx, fma(syz, dy, szz * dz));
+    const double xf = fma(dx, s.f[0], fma(dy, s.f[1], dz * s.f[2]));
+    const double xq = fma(dx, s.q[0], fma(dy, s.q[1], dz * s.q[2]));
+    const double xw = fma(dx, wx, fma(dy, wy, dz * wz));
+    const double xt = fma(dx, s.t[0], fma(dy, s.t[1], dz * s.t[2]));
+    const double c = fma(rm[1], xf, fma(rm[3], xq, rm[6] * xw));
+    const double tx0 = s.t[1] * dz - s.t[2] * dy, tx1 = s.t[2] * dx - s.t[0] * dz, tx2 = s.t[0] * dy - s.t[1] * dx;
+    acc[0] += fma(rm[0], s.f[0], fma(rm[2], s.q[0], fma(rm[5], wx, fma(rm[4], tx0, c * dx))));
+    acc[1] += fma(rm[0], s.f[1], fma(rm[2], s.q[1], fma(rm[5], wy, fma(rm[4], tx1, c * dy))));
+    acc[2] += fma(rm[0], s.f[2], fma(rm[2], s.q[2], fma(rm[5], wz, fma(rm[4], tx2, c * dz))));
+    // v = G1 f + Gq q - J1 w gives G1 (f cross x) + Gq (q cross x) + J1 (x cross w) = v cross x
+    const double v0 = fma(rm[7], s.f[0], fma(rm[8], s.q[0], -rm[11] * wx));
+    const double v1 = fma(rm[7], s.f[1], fma(rm[8], s.q[1], -rm[11] * wy));
+    const double v2 = fma(rm[7], s.f[2], fma(rm[8], s.q[2], -rm[11] * wz));
+    const double h = rm[10] * xt;
+    acc[3] += fma(v1, dz, fma(-v2, dy, fma(rm[9], s.t[0], h * dx)));
+    acc[4] += fma(v2, dx, fma(-v0, dz, fma(rm[9], s.t[1], h * dy)));
+    acc[5] += fma(v0, dy, fma(-v1, dx, fma(rm[9], s.t[2], h * dz)));
+  }
   if (TGT == kPFlow) per_real_flow_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc);
 }
 

@@ -26,7 +26,12 @@ P = 1/(8 pi eta):
         per_real_flow_ftsq (the flow itself at a field point, accumulate u[3]),
         per_real_es_radial (the radial functions al, be, ga of the stresslet strain's isotropic form
         E = al Sigma + be (x (Sigma x) + (Sigma x) x) + ga (x.Sigma x) x x + (trace), which the operator
-        pass contracts itself: about a tenth of the operations of per_real_strain_s)
+        pass contracts itself: about a tenth of the operations of per_real_strain_s),
+        per_real_ftq_radial (the five radial functions of the strain of a force, a torque and the
+        rank-3 mode, E = x a + a x + b x x, a = Af f + Aq q + Dt (x cross t), b = Bf (x.f) + Bq (x.q)),
+        per_real_motion_radial (the twelve of the rigid-body motion, U = F1 f + Q1 q + S1 w + T1 (t cross x)
+        + (F2 (x.f) + Q2 (x.q) + S2 (x.w)) x, W = G1 (f cross x) + Gq (q cross x) + J1 (x cross w) + H1 t
+        + H2 (x.t) x, w = Sigma x), contracted by the right-hand side and output passes
     Fourier space (k, ik2 = 1/k^2, the complex structure factors of the coefficients split into real
     and imaginary parts; the splitting factor and 1/L^3 applied by the caller):
         per_hat_strain_s, per_hat_strain_ftq, per_hat_motion_ftsq, per_hat_flow_ftsq
@@ -272,6 +277,110 @@ def stresslet_radial():
     return al, be, ga
 
 
+def _cart_strain(rl, u):
+    """Cartesian strain sym grad F^1 u of a flow (the receiver's Faxen operator applied first)."""
+    v = [_faxen(rl, ui, 1) for ui in u]
+    return [[rl.red(sp.Rational(1, 2) * (rl.d(v[i], j) + rl.d(v[j], i))) for j in range(3)] for i in range(3)]
+
+
+def _cross(a, b):
+    return [a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]]
+
+
+def _check_form(rl, exact, form, what):
+    for e, g in zip(exact, form):
+        if rl.red(e - g) != 0:
+            raise AssertionError("the screened %s is not of the isotropic form" % what)
+
+
+def rhs_radial():
+    """The real-space strain of a force, a torque and the rank-3 trace mode through the screened
+    kernel in isotropic form: E = x a + a x + b x x (+ a trace the 5-basis drops) with
+    a = Af f + Aq q + Dt (x cross t) and b = Bf (x.f) + Bq (x.q); the five radial functions read off along the z axis
+    and the form checked for a general separation."""
+    rl = _Real()
+    K = rl.kernel()
+    f = sp.symbols("f0:3", real=True)
+    t = sp.symbols("t0:3", real=True)
+    q = sp.symbols("q0:3", real=True)
+    z = {X1: 0, X2: 0, X3: RR}
+    out = {}
+    for name, vec in (("f", f), ("q", q)):
+        E = _cart_strain(rl, source_flow(rl, K, f if name == "f" else None, None, None, q if name == "q" else None))
+        Ez = [[sp.expand(E[i][j].subs(z)) for j in range(3)] for i in range(3)]
+        A = sp.expand(Ez[0][2].coeff(vec[0]) / RR)
+        C = sp.expand(Ez[0][0].coeff(vec[2]) / RR)
+        B = sp.expand((Ez[2][2].coeff(vec[2]) - 2 * A * RR - C * RR) / RR ** 3)
+        xv = sum(_XV[i] * vec[i] for i in range(3))
+        _check_form(rl, [E[i][j] for i in range(3) for j in range(i, 3)],
+                    [A * (_XV[i] * vec[j] + vec[i] * _XV[j]) + B * xv * _XV[i] * _XV[j] + C * xv * int(i == j)
+                     for i in range(3) for j in range(i, 3)], "strain of a vector source")
+        out["A" + name], out["B" + name] = A, B
+    E = _cart_strain(rl, source_flow(rl, K, None, t, None, None))
+    Ez = [[sp.expand(E[i][j].subs(z)) for j in range(3)] for i in range(3)]
+    D = sp.expand(-Ez[0][2].coeff(t[1]) / RR ** 2)
+    xt = _cross(_XV, t)
+    _check_form(rl, [E[i][j] for i in range(3) for j in range(i, 3)],
+                [D * (xt[i] * _XV[j] + _XV[i] * xt[j]) for i in range(3) for j in range(i, 3)], "strain of a torque")
+    return [out["Af"], out["Bf"], out["Aq"], out["Bq"], D]
+
+
+def motion_radial():
+    """The real-space rigid-body motion of a sphere (U = F^0 u, W = (1/2) curl u) driven by a force,
+    a torque, a stresslet and the rank-3 trace mode through the screened kernel in isotropic form:
+        U = F1 f + Q1 q + S1 w + T1 (t cross x) + (F2 (x.f) + Q2 (x.q) + S2 (x.w)) x,   w = Sigma x,
+        W = G1 (f cross x) + Gq (q cross x) + J1 (x cross w) + H1 t + H2 (x.t) x;
+    the twelve radial functions [F1, F2, Q1, Q2, T1, S1, S2, G1, Gq, H1, H2, J1] read off along the z
+    axis and the forms checked for a general separation."""
+    rl = _Real()
+    K = rl.kernel()
+    f = sp.symbols("f0:3", real=True)
+    t = sp.symbols("t0:3", real=True)
+    q = sp.symbols("q0:3", real=True)
+    sxx, syy, sxy, sxz, syz = sp.symbols("sxx syy sxy sxz syz", real=True)
+    S = [[sxx, sxy, sxz], [sxy, syy, syz], [sxz, syz, -sxx - syy]]
+    # the stresslet through Cartesian components (the 5-basis maps onto them linearly)
+    uS = [_faxen(rl, sum(rl.d(K[i][j], k) * S[j][k] for j in range(3) for k in range(3)), 1) for i in range(3)]
+    z = {X1: 0, X2: 0, X3: RR}
+    r = {}
+    for name, vec in (("F", f), ("Q", q)):
+        U, W = motion(rl, source_flow(rl, K, f if name == "F" else None, None, None, q if name == "Q" else None))
+        Uz = [sp.expand(c.subs(z)) for c in U]
+        Wz = [sp.expand(c.subs(z)) for c in W]
+        c1 = sp.expand(Uz[0].coeff(vec[0]))
+        c2 = sp.expand((Uz[2].coeff(vec[2]) - c1) / RR ** 2)
+        g = sp.expand(Wz[0].coeff(vec[1]) / RR)  # W = g (v cross x): along z, W_x = g r v_y
+        xv = sum(_XV[i] * vec[i] for i in range(3))
+        vx = _cross(vec, _XV)
+        _check_form(rl, U, [c1 * vec[i] + c2 * xv * _XV[i] for i in range(3)], "motion of a vector source")
+        _check_form(rl, W, [g * vx[i] for i in range(3)], "rotation of a vector source")
+        r[name + "1"], r[name + "2"], r["G" + name] = c1, c2, g
+    U, W = motion(rl, source_flow(rl, K, None, t, None, None))
+    Uz = [sp.expand(c.subs(z)) for c in U]
+    Wz = [sp.expand(c.subs(z)) for c in W]
+    T1 = sp.expand(Uz[0].coeff(t[1]) / RR)
+    H1 = sp.expand(Wz[0].coeff(t[0]))
+    H2 = sp.expand((Wz[2].coeff(t[2]) - H1) / RR ** 2)
+    tx = _cross(t, _XV)
+    xt = sum(_XV[i] * t[i] for i in range(3))
+    _check_form(rl, U, [T1 * tx[i] for i in range(3)], "motion of a torque")
+    _check_form(rl, W, [H1 * t[i] + H2 * xt * _XV[i] for i in range(3)], "rotation of a torque")
+    U = [_faxen(rl, ui, 0) for ui in uS]
+    W = [rl.red(sp.Rational(1, 2) * (rl.d(uS[(i + 2) % 3], (i + 1) % 3) - rl.d(uS[(i + 1) % 3], (i + 2) % 3)))
+         for i in range(3)]
+    Uz = [sp.expand(c.subs(z)) for c in U]
+    Wz = [sp.expand(c.subs(z)) for c in W]
+    S1 = sp.expand(Uz[0].coeff(sxz) / RR)
+    S2 = sp.expand((-Uz[2].coeff(sxx) - S1 * RR) / RR ** 3)  # S_zz = -sxx - syy
+    J1 = sp.expand(-Wz[0].coeff(syz) / RR ** 2)
+    w = [sum(S[i][j] * _XV[j] for j in range(3)) for i in range(3)]
+    xw = sum(_XV[i] * w[i] for i in range(3))
+    xcw = _cross(_XV, w)
+    _check_form(rl, U, [S1 * w[i] + S2 * xw * _XV[i] for i in range(3)], "motion of a stresslet")
+    _check_form(rl, W, [J1 * xcw[i] for i in range(3)], "rotation of a stresslet")
+    return [r["F1"], r["F2"], r["Q1"], r["Q2"], T1, S1, S2, r["GF"], r["GQ"], H1, H2, J1]
+
+
 def generate():
     f = sp.symbols("f0:3")
     t = sp.symbols("t0:3")
@@ -296,6 +405,10 @@ def generate():
     al, be, ga = stresslet_radial()
     parts.append(_emit("per_real_es_radial", "double ri, double ec, double ex, double xi, double a2, double* abg",
                        [("abg", 0, "="), ("abg", 1, "="), ("abg", 2, "=")], [al, be, ga], [EC, EX], sub))
+    parts.append(_emit("per_real_ftq_radial", "double ri, double ec, double ex, double xi, double a2, double* rf",
+                       [("rf", c, "=") for c in range(5)], rhs_radial(), [EC, EX], sub))
+    parts.append(_emit("per_real_motion_radial", "double ri, double ec, double ex, double xi, double a2, double* rm",
+                       [("rm", c, "=") for c in range(12)], motion_radial(), [EC, EX], sub))
     ff = source_flow(rl, Kr, f, t, s, q)
     parts.append(_emit("per_real_flow_ftsq", geo + ", const double* f, const double* t, const double* s, "
                        "const double* q, double* u", [("u", c, "+=") for c in range(3)], ff,
@@ -356,7 +469,8 @@ def generate():
             nm = str(sym)
             m = re.match(r"([a-z]+)(\d+)$", nm)
             sym_map[nm] = "%s[%s]" % (m.group(1), m.group(2))
-    names = ("per_real_strain_s", "per_real_strain_ftq", "per_real_motion_ftsq", "per_real_es_radial", "per_real_flow_ftsq",
+    names = ("per_real_strain_s", "per_real_strain_ftq", "per_real_motion_ftsq", "per_real_es_radial",
+             "per_real_ftq_radial", "per_real_motion_radial", "per_real_flow_ftsq",
              "per_hat_strain_s", "per_hat_strain_ftq", "per_hat_motion_ftsq", "per_hat_flow_ftsq")
     body, counts = [], []
     for (code, nops), nm in zip(parts, names):

@@ -57,6 +57,16 @@ void ev_es_radial(int n, const double* r, double xi, double a2, double* abg) {
   for (int p = 0; p < n; ++p)
     mbs::per_real_es_radial(1.0 / r[p], std::erfc(xi * r[p]), std::exp(-xi * xi * r[p] * r[p]), xi, a2, abg + 3 * p);
 }
+// radial functions of the right-hand side's strain (5) and of the outputs' motion (12) at distances r [n]
+void ev_ftq_radial(int n, const double* r, double xi, double a2, double* rf) {
+  for (int p = 0; p < n; ++p)
+    mbs::per_real_ftq_radial(1.0 / r[p], std::erfc(xi * r[p]), std::exp(-xi * xi * r[p] * r[p]), xi, a2, rf + 5 * p);
+}
+void ev_motion_radial(int n, const double* r, double xi, double a2, double* rm) {
+  for (int p = 0; p < n; ++p)
+    mbs::per_real_motion_radial(1.0 / r[p], std::erfc(xi * r[p]), std::exp(-xi * xi * r[p] * r[p]), xi, a2,
+                                rm + 12 * p);
+}
 void ev_self(double xi, double a2, double* out) {
   out[0] = mbs::per_self_es(xi, a2);
   out[1] = mbs::per_self_uf(xi, a2);

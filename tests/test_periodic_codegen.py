@@ -130,3 +130,37 @@ def test_generated_radial_stresslet_strain_matches_oracle(lib):
     want = np.einsum("pij,pj->pi", periodic.real_block("E", "S", x, XI, A, ETA), S5)
     assert _close(got, want)
 
+
+
+def test_generated_radial_forms_of_the_other_passes_match_oracle(lib):
+    """The right-hand side and output passes contract the screened strain of a force, a torque and the
+    rank-3 mode, and the screened rigid-body motion of every source, from radial functions: with the
+    generated ones those isotropic forms are the oracle's real-space blocks."""
+    from oracle import basis
+    rng = np.random.default_rng(5)
+    n = 40
+    x = rng.standard_normal((n, 3)) * 4.0
+    r = np.sqrt((x ** 2).sum(1))
+    rf, rm = np.zeros((n, 5)), np.zeros((n, 12))
+    lib.ev_ftq_radial(n, _p(r), ctypes.c_double(XI), ctypes.c_double(A * A), rf.ctypes.data_as(ctypes.c_void_p))
+    lib.ev_motion_radial(n, _p(r), ctypes.c_double(XI), ctypes.c_double(A * A), rm.ctypes.data_as(ctypes.c_void_p))
+    F, T, d = rng.standard_normal((n, 3)), rng.standard_normal((n, 3)), rng.standard_normal((n, 3))
+    S5 = rng.standard_normal((n, 5))
+    f, t, q = P * F, P * T, A ** 5 / 20 * d
+    S = P * np.stack([basis.from5(v) for v in S5])
+    dot = lambda a, b: np.einsum("pi,pi->p", a, b)  # noqa: E731
+    blk = lambda T_, S_: periodic.real_block(T_, S_, x, XI, A, ETA)  # noqa: E731
+    a = rf[:, 0, None] * f + rf[:, 2, None] * q + rf[:, 4, None] * np.cross(x, t)
+    b = rf[:, 1] * dot(x, f) + rf[:, 3] * dot(x, q)
+    E = x[:, :, None] * a[:, None, :] + a[:, :, None] * x[:, None, :] + b[:, None, None] * x[:, :, None] * x[:, None, :]
+    got = np.stack([basis.to5(e) for e in E])
+    want = sum(np.einsum("pij,pj->pi", blk("E", k), v) for k, v in (("F", F), ("T", T), ("D", d)))
+    assert _close(got, want)
+    w = np.einsum("pij,pj->pi", S, x)
+    U = (rm[:, 0, None] * f + rm[:, 2, None] * q + rm[:, 5, None] * w + rm[:, 4, None] * np.cross(t, x)
+         + (rm[:, 1] * dot(x, f) + rm[:, 3] * dot(x, q) + rm[:, 6] * dot(x, w))[:, None] * x)
+    W = (rm[:, 7, None] * np.cross(f, x) + rm[:, 8, None] * np.cross(q, x) + rm[:, 11, None] * np.cross(x, w)
+         + rm[:, 9, None] * t + (rm[:, 10] * dot(x, t))[:, None] * x)
+    src = (("F", F), ("T", T), ("S", S5), ("D", d))
+    assert _close(U, sum(np.einsum("pij,pj->pi", blk("U", k), v) for k, v in src))
+    assert _close(W, sum(np.einsum("pij,pj->pi", blk("W", k), v) for k, v in src))
