@@ -935,7 +935,11 @@ __global__ void __launch_bounds__(256)
     k_fft_lines(double2* __restrict__ a, int M, int B, int64_t sk, int64_t sb, int nbu, int64_t su, int64_t sv,
                 int64_t sf, const double2* __restrict__ tw, FftPlan pl) {
   extern __shared__ double2 xs[];
-  const int bu = blockIdx.x % nbu, bv = blockIdx.x / nbu;
+  // workgroups are dealt round-robin over the 8 XCDs: renumber them so that each XCD takes a
+  // contiguous run of bundles (neighbouring lines share pages and its L2)
+  const int nwg = gridDim.x;
+  const int id = (nwg & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (nwg >> 3) + (int)(blockIdx.x >> 3);
+  const int bu = id % nbu, bv = id / nbu;
   double2* base = a + (int64_t)blockIdx.y * sf + (int64_t)bu * su + (int64_t)bv * sv;
   int Ns = 1;
   for (int st = 0; st < pl.nst; ++st) {
