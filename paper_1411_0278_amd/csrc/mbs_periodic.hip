@@ -257,7 +257,25 @@ __device__ __forceinline__ void real_pair_d(const RecP& s, double dx, double dy,
     acc[4] += fma(v2, dx, fma(-v0, dz, fma(rm[9], s.t[1], h * dy)));
     acc[5] += fma(v0, dy, fma(-v1, dx, fma(rm[9], s.t[2], h * dz)));
   }
-  if (TGT == kPFlow) per_real_flow_ftsq(dx, dy, dz, ri, ec, ex, xi, a2, s.f, s.t, s.s, s.q, acc);
+  if (TGT == kPFlow) {
+    // u = F1 f + Q1 q + S1 w + T1 (t cross x) + (F2 (x.f) + Q2 (x.q) + S2 (x.w)) x,  w = Sigma x
+    double rw[7];
+    per_real_flow_radial(ri, ec, ex, xi, a2, rw);
+    double sxx, syy, sxy, sxz, syz;
+    basis_to_cart(s.s, sxx, syy, sxy, sxz, syz);
+    const double szz = -(sxx + syy);
+    const double wx = fma(sxx, dx, fma(sxy, dy, sxz * dz));
+    const double wy = fma(sxy, dx, fma(syy, dy, syz * dz));
+    const double wz = fma(sxz, dx, fma(syz, dy, szz * dz));
+    const double xf = fma(dx, s.f[0], fma(dy, s.f[1], dz * s.f[2]));
+    const double xq = fma(dx, s.q[0], fma(dy, s.q[1], dz * s.q[2]));
+    const double xw = fma(dx, wx, fma(dy, wy, dz * wz));
+    const double c = fma(rw[1], xf, fma(rw[3], xq, rw[6] * xw));
+    const double tx0 = s.t[1] * dz - s.t[2] * dy, tx1 = s.t[2] * dx - s.t[0] * dz, tx2 = s.t[0] * dy - s.t[1] * dx;
+    acc[0] += fma(rw[0], s.f[0], fma(rw[2], s.q[0], fma(rw[5], wx, fma(rw[4], tx0, c * dx))));
+    acc[1] += fma(rw[0], s.f[1], fma(rw[2], s.q[1], fma(rw[5], wy, fma(rw[4], tx1, c * dy))));
+    acc[2] += fma(rw[0], s.f[2], fma(rw[2], s.q[2], fma(rw[5], wz, fma(rw[4], tx2, c * dz))));
+  }
 }
 
 template <int TGT>

@@ -31,7 +31,9 @@ P = 1/(8 pi eta):
         rank-3 mode, E = x a + a x + b x x, a = Af f + Aq q + Dt (x cross t), b = Bf (x.f) + Bq (x.q)),
         per_real_motion_radial (the twelve of the rigid-body motion, U = F1 f + Q1 q + S1 w + T1 (t cross x)
         + (F2 (x.f) + Q2 (x.q) + S2 (x.w)) x, W = G1 (f cross x) + Gq (q cross x) + J1 (x cross w) + H1 t
-        + H2 (x.t) x, w = Sigma x), contracted by the right-hand side and output passes
+        + H2 (x.t) x, w = Sigma x), contracted by the right-hand side and output passes,
+        per_real_flow_radial (the seven of the flow at a field point, the U form without the receiver's
+        operator), contracted by the flow pass
     Fourier space (k, ik2 = 1/k^2, the complex structure factors of the coefficients split into real
     and imaginary parts; the splitting factor and 1/L^3 applied by the caller):
         per_hat_strain_s, per_hat_strain_ftq, per_hat_motion_ftsq, per_hat_flow_ftsq
@@ -381,6 +383,44 @@ def motion_radial():
     return [r["F1"], r["F2"], r["Q1"], r["Q2"], T1, S1, S2, r["GF"], r["GQ"], H1, H2, J1]
 
 
+def flow_radial():
+    """The real-space flow itself at a field point (no receiver operator) of a force, a torque, a
+    stresslet and the rank-3 trace mode through the screened kernel in isotropic form,
+        u = F1 f + Q1 q + S1 w + T1 (t cross x) + (F2 (x.f) + Q2 (x.q) + S2 (x.w)) x,   w = Sigma x;
+    the seven radial functions [F1, F2, Q1, Q2, T1, S1, S2] read off along the z axis and the form
+    checked for a general separation."""
+    rl = _Real()
+    K = rl.kernel()
+    f = sp.symbols("f0:3", real=True)
+    t = sp.symbols("t0:3", real=True)
+    q = sp.symbols("q0:3", real=True)
+    sxx, syy, sxy, sxz, syz = sp.symbols("sxx syy sxy sxz syz", real=True)
+    S = [[sxx, sxy, sxz], [sxy, syy, syz], [sxz, syz, -sxx - syy]]
+    z = {X1: 0, X2: 0, X3: RR}
+    r = {}
+    for name, vec in (("F", f), ("Q", q)):
+        u = source_flow(rl, K, f if name == "F" else None, None, None, q if name == "Q" else None)
+        uz = [sp.expand(c.subs(z)) for c in u]
+        c1 = sp.expand(uz[0].coeff(vec[0]))
+        c2 = sp.expand((uz[2].coeff(vec[2]) - c1) / RR ** 2)
+        xv = sum(_XV[i] * vec[i] for i in range(3))
+        _check_form(rl, u, [c1 * vec[i] + c2 * xv * _XV[i] for i in range(3)], "flow of a vector source")
+        r[name + "1"], r[name + "2"] = c1, c2
+    u = source_flow(rl, K, None, t, None, None)
+    uz = [sp.expand(c.subs(z)) for c in u]
+    T1 = sp.expand(uz[0].coeff(t[1]) / RR)
+    tx = _cross(t, _XV)
+    _check_form(rl, u, [T1 * tx[i] for i in range(3)], "flow of a torque")
+    u = [_faxen(rl, sum(rl.d(K[i][j], k) * S[j][k] for j in range(3) for k in range(3)), 1) for i in range(3)]
+    uz = [sp.expand(c.subs(z)) for c in u]
+    S1 = sp.expand(uz[0].coeff(sxz) / RR)
+    S2 = sp.expand((-uz[2].coeff(sxx) - S1 * RR) / RR ** 3)
+    w = [sum(S[i][j] * _XV[j] for j in range(3)) for i in range(3)]
+    xw = sum(_XV[i] * w[i] for i in range(3))
+    _check_form(rl, u, [S1 * w[i] + S2 * xw * _XV[i] for i in range(3)], "flow of a stresslet")
+    return [r["F1"], r["F2"], r["Q1"], r["Q2"], T1, S1, S2]
+
+
 def generate():
     f = sp.symbols("f0:3")
     t = sp.symbols("t0:3")
@@ -409,6 +449,8 @@ def generate():
                        [("rf", c, "=") for c in range(5)], rhs_radial(), [EC, EX], sub))
     parts.append(_emit("per_real_motion_radial", "double ri, double ec, double ex, double xi, double a2, double* rm",
                        [("rm", c, "=") for c in range(12)], motion_radial(), [EC, EX], sub))
+    parts.append(_emit("per_real_flow_radial", "double ri, double ec, double ex, double xi, double a2, double* rw",
+                       [("rw", c, "=") for c in range(7)], flow_radial(), [EC, EX], sub))
     ff = source_flow(rl, Kr, f, t, s, q)
     parts.append(_emit("per_real_flow_ftsq", geo + ", const double* f, const double* t, const double* s, "
                        "const double* q, double* u", [("u", c, "+=") for c in range(3)], ff,
@@ -470,7 +512,7 @@ def generate():
             m = re.match(r"([a-z]+)(\d+)$", nm)
             sym_map[nm] = "%s[%s]" % (m.group(1), m.group(2))
     names = ("per_real_strain_s", "per_real_strain_ftq", "per_real_motion_ftsq", "per_real_es_radial",
-             "per_real_ftq_radial", "per_real_motion_radial", "per_real_flow_ftsq",
+             "per_real_ftq_radial", "per_real_motion_radial", "per_real_flow_radial", "per_real_flow_ftsq",
              "per_hat_strain_s", "per_hat_strain_ftq", "per_hat_motion_ftsq", "per_hat_flow_ftsq")
     body, counts = [], []
     for (code, nops), nm in zip(parts, names):

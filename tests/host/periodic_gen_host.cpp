@@ -67,6 +67,10 @@ void ev_motion_radial(int n, const double* r, double xi, double a2, double* rm) 
     mbs::per_real_motion_radial(1.0 / r[p], std::erfc(xi * r[p]), std::exp(-xi * xi * r[p] * r[p]), xi, a2,
                                 rm + 12 * p);
 }
+void ev_flow_radial(int n, const double* r, double xi, double a2, double* rw) {
+  for (int p = 0; p < n; ++p)
+    mbs::per_real_flow_radial(1.0 / r[p], std::erfc(xi * r[p]), std::exp(-xi * xi * r[p] * r[p]), xi, a2, rw + 7 * p);
+}
 void ev_self(double xi, double a2, double* out) {
   out[0] = mbs::per_self_es(xi, a2);
   out[1] = mbs::per_self_uf(xi, a2);

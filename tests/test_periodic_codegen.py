@@ -164,3 +164,30 @@ def test_generated_radial_forms_of_the_other_passes_match_oracle(lib):
     src = (("F", F), ("T", T), ("S", S5), ("D", d))
     assert _close(U, sum(np.einsum("pij,pj->pi", blk("U", k), v) for k, v in src))
     assert _close(W, sum(np.einsum("pij,pj->pi", blk("W", k), v) for k, v in src))
+
+
+def test_generated_radial_flow_matches_oracle(lib):
+    """The flow pass contracts the screened flow at a field point from seven radial functions: with
+    the generated ones that form is the oracle's real-space flow."""
+    from oracle import basis
+    from scipy.special import erfc
+    rng = np.random.default_rng(6)
+    n = 40
+    x = rng.standard_normal((n, 3)) * 4.0
+    r = np.sqrt((x ** 2).sum(1))
+    rw = np.zeros((n, 7))
+    lib.ev_flow_radial(n, _p(r), ctypes.c_double(XI), ctypes.c_double(A * A), rw.ctypes.data_as(ctypes.c_void_p))
+    F, T, d = rng.standard_normal((n, 3)), rng.standard_normal((n, 3)), rng.standard_normal((n, 3))
+    S5 = rng.standard_normal((n, 5))
+    f, t, q = P * F, P * T, A ** 5 / 20 * d
+    w = np.einsum("pij,pj->pi", P * np.stack([basis.from5(v) for v in S5]), x)
+    dot = lambda a, b: np.einsum("pi,pi->p", a, b)  # noqa: E731
+    got = (rw[:, 0, None] * f + rw[:, 2, None] * q + rw[:, 5, None] * w + rw[:, 4, None] * np.cross(t, x)
+           + (rw[:, 1] * dot(x, f) + rw[:, 3] * dot(x, q) + rw[:, 6] * dot(x, w))[:, None] * x)
+    want = np.zeros((n, 3))
+    for k, v in (("F", F), ("T", T), ("S", S5), ("D", d)):
+        raw = periodic._flow_fn("real", k)(x[:, 0], x[:, 1], x[:, 2], r, erfc(XI * r), np.exp(-(XI * r) ** 2), XI, A, P)
+        M = np.stack([np.stack([np.broadcast_to(np.asarray(raw[i][j], float), (n,)) for j in range(v.shape[1])], -1)
+                      for i in range(3)], 1)
+        want += np.einsum("pij,pj->pi", M, v)
+    assert _close(got, want)
