@@ -614,6 +614,8 @@ __global__ void __launch_bounds__(256) k_min_finish(const double* __restrict__ p
 }
 
 // ---------------------------------------------------------------- smooth particle-mesh Ewald
+// The smooth particle-mesh Ewald method (Essmann, Perera, Berkowitz, Darden, Lee and Pedersen,
+// J. Chem. Phys. 103, 8577, 1995), applied here to the Stokes blocks of every pass.
 // With a mesh of M^3 points (spacing h = L / M) the Fourier sum runs on the mesh instead of over the
 // spheres: exp(-i k.R) is interpolated by cardinal B-splines of order kPmP on the mesh points around
 // R (Euler exponential splines, the interpolation's error corrected in Fourier space by |b(m)|^2),
@@ -686,7 +688,7 @@ __global__ void __launch_bounds__(kPmRT)
     k_pm_real(const double* __restrict__ Rs, const int32_t* __restrict__ perm, const int32_t* __restrict__ cstart,
               const int32_t* __restrict__ cend, int nc, int m, const double* __restrict__ Fe,
               const double* __restrict__ Te, const double* __restrict__ Sig, const double* __restrict__ D, double L,
-              double invL, double rc2, double xi, double a2, double P, double a5_20, const double* __restrict__ rtab,
+              double rc2, double xi, double a2, double P, double a5_20, const double* __restrict__ rtab,
               int npiece, double inv_slo, double* __restrict__ part) {
   __shared__ RecP tile[kPTJ];
   extern __shared__ double rt[];  // the operator's radial table (npiece pieces), when given
@@ -1315,7 +1317,7 @@ void pm_launch(const double* X, int64_t m, const double* R, int64_t n, const dou
     const double* rtab = TGT == kPOp && g.npiece > 0 ? g.rtab : nullptr;
     hipLaunchKernelGGL(k_pm_real<TGT>, dim3((unsigned)g.nc * g.nc * g.nc, 3), dim3(kPmRT),
                        rtab ? (size_t)g.npiece * kRtC * sizeof(double) : 0, s, gv.Rs, gv.perm, gv.start, gv.end, g.nc,
-                       (int)m, Fe, Te, Sig, D, g.L, 1.0 / g.L, g.rc * g.rc, g.xi, ph.a2, ph.P, a5_20, rtab, g.npiece,
+                       (int)m, Fe, Te, Sig, D, g.L, g.rc * g.rc, g.xi, ph.a2, ph.P, a5_20, rtab, g.npiece,
                        1.0 / ph.a2, preal);
   } else {
     const int creal = (int)((n + sh.nreal - 1) / sh.nreal);
