@@ -146,12 +146,15 @@ def test_pme_solve_matches_oracle(ctx):
     sol = periodic.solve(w, _ew(L), PRM)
     d = mbstokes.to_device(w, DEV)
     Sig = torch.empty((n, 5), dtype=torch.float64, device=DEV)
-    for prec, near in ((mbstokes.MBS_FP64, 0.0), (mbstokes.MBS_MIXED, 8.0)):
-        with _Mesh(ctx, L, M, tol=1e-12, precision=prec, near_cutoff=near):
+    for prec, near, spatial in ((mbstokes.MBS_FP64, 0.0, 0), (mbstokes.MBS_MIXED, 8.0, 0), (mbstokes.MBS_FP64, 8.0, 1)):
+        with _Mesh(ctx, L, M, tol=1e-12, precision=prec, near_cutoff=near, spatial_order=spatial):
             V, W, S, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"], Sigma=Sig)
+            V2, W2, S2, st2 = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], d["v3t"], d["Fe"], d["Te"])
         errs = [_maxrel(V, sol["V"]), _maxrel(W, sol["W"]), _maxrel(S, sol["S"]), _maxrel(Sig, sol["Sigma"])]
-        print(f"  solve precision={prec}: " + " ".join(f"{e:.3e}" for e in errs), flush=True)
+        print(f"  solve precision={prec} near={near} spatial={spatial}: " + " ".join(f"{e:.3e}" for e in errs),
+              flush=True)
         assert max(errs) < 10 * BAR
+        assert torch.equal(V, V2) and torch.equal(W, W2)  # the second solve replays the captured steps
 
 
 def test_pme_flow_field_matches_oracle(ctx):
