@@ -902,12 +902,12 @@ struct FftPlan {
 template <int R, bool INV, bool CONTIG>
 __device__ __forceinline__ void fft_stage(double2* xs, double2* g, bool from_g, bool to_g, int M, int B, int Ns,
                                           int64_t sk, int64_t sb, const double2* __restrict__ tw) {
-  constexpr int NB = 4096 / R / 256;  // butterflies per thread (B M <= 4096, 256 threads)
+  constexpr int NB = 16 / R;  // butterflies per thread (B M <= 16 threads)
   const int MR = M / R, nbf = B * MR;
   double2 v[NB][R];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int e = threadIdx.x + q * 256;
+    const int e = threadIdx.x + q * blockDim.x;
     if (e < nbf) {
       const int l = CONTIG ? e / MR : e % B, j = CONTIG ? e % MR : e / B;
 #pragma unroll
@@ -929,7 +929,7 @@ __device__ __forceinline__ void fft_stage(double2* xs, double2* g, bool from_g, 
   if (!from_g) __syncthreads();
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int e = threadIdx.x + q * 256;
+    const int e = threadIdx.x + q * blockDim.x;
     if (e < nbf) {
       const int l = CONTIG ? e / MR : e % B, j = CONTIG ? e % MR : e / B;
       const int k = j & (Ns - 1), o = (j - k) * R + k;
@@ -949,9 +949,9 @@ __device__ __forceinline__ void fft_stage(double2* xs, double2* g, bool from_g, 
 // One pass of the 3D transform: every line of M points along one axis (point idx of line l of a
 // bundle at base + l sb + idx sk), B lines per workgroup (consecutive in memory for the strided axes,
 // so that B contiguous points move together). Forward: X(m) = sum_g x(g) exp(-2 pi i m g / M); INV:
-// the conjugate exponent, no normalisation. AXIS 0 is the contiguous one (sk = 1).
+// the conjugate exponent, no normalisation. AXIS 0 is the contiguous one (sk = 1). B M / 16 threads.
 template <bool INV, int AXIS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
     k_fft_lines(double2* __restrict__ a, int M, int B, int64_t sk, int64_t sb, int nbu, int64_t su, int64_t sv,
                 int64_t sf, const double2* __restrict__ tw, FftPlan pl) {
   extern __shared__ double2 xs[];
@@ -1238,24 +1238,41 @@ FftPlan fft_plan(int M) {
 
 // the transform of nf complex fields of M^3 points (x fastest) along the axes in mask (1 x, 2 y,
 // 4 z), in place
+// the per-workgroup LDS the device allows (gfx950: 160 KB per CU), once
+size_t fft_lds_limit() {
+  static size_t lim = 0;
+  if (!lim) {
+    int dev = 0, v = 0;
+    lim = 65536;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 65536)
+      lim = (size_t)v;
+  }
+  return lim;
+}
+
 void pm_fft(double2* a, int nf, int M, bool inv, const double2* tw, hipStream_t s, int mask = 7) {
   const FftPlan pl = fft_plan(M);
+  // lines per workgroup: B M = 4096 points (64 KB) in general; 16 lines (256-byte runs) along z on
+  // the 512-point mesh, whose lines stride 4 MB, where the device allows 128 KB of LDS per workgroup
+  // (measured: z 4.0 -> 3.35 ms per pass at 512^3 x 3 fields; y, striding 8 KB, gains nothing)
   const int B = std::max(1, std::min(16, 4096 / M));
+  const int Bs = (M * 16 * (int)sizeof(double2) <= (int)fft_lds_limit() && 16 * M <= 8192) ? 16 : B;
   const int64_t M2 = (int64_t)M * M, M3 = M2 * M;
-  const size_t lds = (size_t)B * M * sizeof(double2);
-  const dim3 grid((unsigned)(M2 / B), (unsigned)nf);
-#define MBS_FFT_PASS(AX, SK, SB, SU, SV)                                                                        \
+#define MBS_FFT_PASS(AX, BB, SK, SB, SU, SV)                                                                    \
   do {                                                                                                          \
+    const size_t lds = (size_t)(BB) * M * sizeof(double2);                                                      \
+    const dim3 grid((unsigned)(M2 / (BB)), (unsigned)nf), blk((unsigned)((BB) * M / 16));                      \
     if (inv)                                                                                                    \
-      hipLaunchKernelGGL((k_fft_lines<true, AX>), grid, dim3(256), lds, s, a, M, B, SK, SB, M / B, SU, SV, M3, \
-                         tw, pl);                                                                               \
+      hipLaunchKernelGGL((k_fft_lines<true, AX>), grid, blk, lds, s, a, M, BB, SK, SB, M / (BB), SU, SV, M3, tw, \
+                         pl);                                                                                   \
     else                                                                                                        \
-      hipLaunchKernelGGL((k_fft_lines<false, AX>), grid, dim3(256), lds, s, a, M, B, SK, SB, M / B, SU, SV,    \
-                         M3, tw, pl);                                                                           \
+      hipLaunchKernelGGL((k_fft_lines<false, AX>), grid, blk, lds, s, a, M, BB, SK, SB, M / (BB), SU, SV, M3,  \
+                         tw, pl);                                                                               \
   } while (0)
-  if (mask & 1) MBS_FFT_PASS(0, (int64_t)1, (int64_t)M, (int64_t)B * M, M2);  // x: lines consecutive in y
-  if (mask & 2) MBS_FFT_PASS(1, (int64_t)M, (int64_t)1, (int64_t)B, M2);      // y: lines consecutive in x
-  if (mask & 4) MBS_FFT_PASS(2, M2, (int64_t)1, (int64_t)B, (int64_t)M);      // z: lines consecutive in x
+  if (mask & 1) MBS_FFT_PASS(0, B, (int64_t)1, (int64_t)M, (int64_t)B * M, M2);  // x: lines consecutive in y
+  if (mask & 2) MBS_FFT_PASS(1, B, (int64_t)M, (int64_t)1, (int64_t)B, M2);       // y: lines consecutive in x
+  if (mask & 4) MBS_FFT_PASS(2, Bs, M2, (int64_t)1, (int64_t)Bs, (int64_t)M);     // z: lines consecutive in x
 #undef MBS_FFT_PASS
 }
 
