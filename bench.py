@@ -804,8 +804,9 @@ def bench_periodic(ctx, a):
     right-hand side, outputs and the solve to 1e-10 (binary64, and with the near-field preconditioner
     at 8a). Default splitting. The same with smooth particle-mesh Ewald (params.ewald_mesh, mesh spacing
     at most 1.25a, default splitting for the mesh): operator (with the largest relative difference of
-    its result from the direct sums), right-hand side, outputs and the binary64 solve to 1e-10 at 10^4
-    and 10^5 spheres, and at 10^6 the mesh operator and solve beside one direct pass. Median of 5
+    its result from the direct sums), right-hand side, outputs and the binary64 solve to 1e-10 (also with
+    the near-field preconditioner at 12a, order 4) at 10^4 and 10^5 spheres, and at 10^6 the mesh
+    operator and solves beside one direct pass. Median of 5
     launches after 2 warm-ups, HIP events (solves: the device time in their stats)."""
     import statistics
 
@@ -879,16 +880,18 @@ def bench_periodic(ctx, a):
         mesh["rhs_ms"] = round(median_ms(lambda: ctx.mbs_rhs(d["R"], d["v2s"], None, d["Fe"], None, b=y)), 4)
         mesh["outputs_ms"] = round(median_ms(lambda: ctx.mbs_outputs(d["R"], x, d["v1s"], d["v2s"], None, d["Fe"],
                                                                        None, V=V, W=W, S=S)), 4)
-        ctx.set_params(box=L, ewald_mesh=M, tol=1e-10, guess=mbstokes.MBS_GUESS_ZERO)
-        sts = []
-        for k in range(3):
-            _, _, _, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
-            if k:
-                sts.append(st)
-        med = sorted(sts, key=lambda t: t["t_total_ms"])[len(sts) // 2]
-        mesh["solve_fp64"] = {"ms": round(med["t_total_ms"], 3), "iters": med["iters"], "rel_resid": med["rel_resid"]}
+        for vname, cut, order in (("solve_fp64", 0.0, 2), ("solve_fp64_pc", 12.0, 4)):
+            ctx.set_params(box=L, ewald_mesh=M, tol=1e-10, guess=mbstokes.MBS_GUESS_ZERO, near_cutoff=cut,
+                           near_order=order)
+            sts = []
+            for k in range(3):
+                _, _, _, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+                if k:
+                    sts.append(st)
+            med = sorted(sts, key=lambda t: t["t_total_ms"])[len(sts) // 2]
+            mesh[vname] = {"ms": round(med["t_total_ms"], 3), "iters": med["iters"], "rel_resid": med["rel_resid"]}
         row["mesh"] = mesh
-        ctx.set_params(box=0.0, ewald_mesh=0, near_cutoff=0.0, precision=mbstokes.MBS_FP64)
+        ctx.set_params(box=0.0, ewald_mesh=0, near_cutoff=0.0, near_order=2, precision=mbstokes.MBS_FP64)
         out["n%d" % n] = row
         print(f"bench: periodic n={n} {row.get('matvec_ms')} ms, mesh {mesh['matvec_ms']} ms", file=sys.stderr,
               flush=True)
@@ -903,15 +906,16 @@ def bench_periodic(ctx, a):
     ctx.set_params(box=L, ewald_mesh=M)
     row = {"n": n, "box": L, "M": M, "mesh_matvec_ms": round(median_ms(lambda: ctx.mbs_matvec(d["R"], x, ym)), 4)}
     print(f"bench: periodic n={n} mesh {row['mesh_matvec_ms']} ms", file=sys.stderr, flush=True)
-    ctx.set_params(box=L, ewald_mesh=M, tol=1e-10, guess=mbstokes.MBS_GUESS_ZERO)
-    sts = []
-    for k in range(2):
-        _, _, _, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
-        if k:
-            sts.append(st)
-    row["mesh_solve_fp64"] = {"ms": round(sts[0]["t_total_ms"], 3), "iters": sts[0]["iters"],
-                              "rel_resid": sts[0]["rel_resid"]}
-    print(f"bench: periodic n={n} mesh solve {row['mesh_solve_fp64']}", file=sys.stderr, flush=True)
+    for vname, cut, order in (("mesh_solve_fp64", 0.0, 2), ("mesh_solve_fp64_pc", 12.0, 4)):
+        ctx.set_params(box=L, ewald_mesh=M, tol=1e-10, guess=mbstokes.MBS_GUESS_ZERO, near_cutoff=cut, near_order=order)
+        sts = []
+        for k in range(2):
+            _, _, _, st = ctx.mbs_solve(d["R"], d["p"], d["v1s"], d["v2s"], None, d["Fe"], None)
+            if k:
+                sts.append(st)
+        row[vname] = {"ms": round(sts[0]["t_total_ms"], 3), "iters": sts[0]["iters"], "rel_resid": sts[0]["rel_resid"]}
+        print(f"bench: periodic n={n} {vname} {row[vname]}", file=sys.stderr, flush=True)
+    ctx.set_params(near_cutoff=0.0, near_order=2)
     ctx.set_params(box=L, ewald_mesh=0)
     row["direct_matvec_ms_one_pass"] = round(median_ms(lambda: ctx.mbs_matvec(d["R"], x, y), warm=0, reps=1), 1)
     row["mesh_vs_direct_maxrel"] = float((ym - y).abs().max() / y.abs().max())
