@@ -336,7 +336,7 @@ def roofline(v, n):
     out = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
            "traffic": rec.get("bytes_per_launch"), "avg_launch_ms": round(per_launch_s * 1e3, 4),
-           "frac_basis": f"algorithmic: {P2_FLOP_PER_PAIR_ALG} FLOP per pair block (the survey count) x N(N-1)",
+           "frac_basis": f"algorithmic: {P2_FLOP_PER_PAIR_ALG} FLOP per pair block (the closed-form block's count) x N(N-1)",
            "flop_per_pair": P2_FLOP_PER_PAIR_ALG,
            "implemented_flop_per_pair": P2_FLOP_PER_PAIR,
            "frac_implemented": round(P2_FLOP_PER_PAIR * pairs / per_launch_s / 1e12 / peak, 4)}
