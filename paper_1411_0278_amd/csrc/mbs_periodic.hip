@@ -626,6 +626,14 @@ constexpr int kPmP = 8;    // B-spline order (support of P mesh points per axis)
 constexpr int kPmB = 8;    // mesh block edge of the spreading kernel
 constexpr int kPmT = 64;   // candidate sources per LDS tile of the spreading kernel
 
+// Workgroups are dealt round-robin over the 8 XCDs, each with its own L2: renumber the first 8 floor(n/8)
+// of n so that every XCD takes a contiguous run (neighbouring cells or receivers, which share sources
+// and mesh points), the rest unchanged
+__device__ __forceinline__ int xcd_order(int b, int n) {
+  const int q = n >> 3;
+  return b >= 8 * q ? b : (b & 7) * q + (b >> 3);
+}
+
 // the weights of mesh points b0 + o, o = 0..P-1, for a scaled coordinate u = floor(u) + t with
 // b0 = floor(u) - P + 1: w[o] = M_P(t + P - 1 - o), the B-spline built up from order 2 by its
 // two-term recursion M_n(x) = (x M_{n-1}(x) + (n - x) M_{n-1}(x - 1)) / (n - 1)
@@ -697,7 +705,7 @@ __global__ void __launch_bounds__(kPmRT)
     for (int i = threadIdx.x; i < npiece * kRtC; i += blockDim.x) rt[i] = rtab[i];
     __syncthreads();
   }
-  const int cell = blockIdx.x;
+  const int cell = (gridDim.x & 7) ? (int)blockIdx.x : xcd_order(blockIdx.x, gridDim.x);
   const int ix = cell % nc, iy = (cell / nc) % nc, iz = cell / (nc * nc);
   const int jzr = iz + (int)blockIdx.y - 1;
   const int jz = (jzr + nc) % nc;
@@ -1127,7 +1135,7 @@ __global__ void __launch_bounds__(256)
     k_pm_gather(const double* __restrict__ Xr, int stride, const int32_t* __restrict__ perm, int m, double L,
                 int M, const double2* __restrict__ fout, double* __restrict__ part) {
   constexpr int W = pw(TGT), NO = (W + 1) / 2;
-  const int k = blockIdx.x * (blockDim.x / kPmP) + threadIdx.x / kPmP;
+  const int k = xcd_order(blockIdx.x, gridDim.x) * (blockDim.x / kPmP) + threadIdx.x / kPmP;
   const int ox = threadIdx.x % kPmP;
   const int kk = k < m ? k : m - 1;
   const int64_t M3 = (int64_t)M * M * M;
