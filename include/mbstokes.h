@@ -158,7 +158,8 @@ typedef struct mbs_params {
                             preconditioner keeps the free-space pairs. 0 = unbounded fluid (default);
                             other values are MBS_EINVAL */
   int32_t ewald_mesh;    /* box > 0: 0 = the Fourier part of the Ewald sums directly over the wave
-                            vectors (O(N K), the default); M = a power of 2 from 16 to 512: smooth
+                            vectors (O(N K), the default); -1: M chosen as the smallest power of 2
+                            from 16 to 512 with box/M <= 1.25 a; M = a power of 2 from 16 to 512: smooth
                             particle-mesh Ewald on an M^3 mesh of spacing box/M, the fast
                             matrix-vector product that the paper leaves to future work (SIV): every
                             sphere's coefficients spread onto the mesh by cardinal B-splines of

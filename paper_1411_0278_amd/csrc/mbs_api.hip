@@ -190,8 +190,9 @@ int validate_params(mbs_ctx* c, const mbs_params* p) {
   if (p->plane && !isfinite(p->plane_z)) return set_err(c, MBS_EINVAL, "plane_z must be finite");
   if (!(p->box >= 0.0) || !isfinite(p->box)) return set_err(c, MBS_EINVAL, "box must be finite and >= 0");
   if (!(p->ewald_xi >= 0.0) || !isfinite(p->ewald_xi)) return set_err(c, MBS_EINVAL, "ewald_xi must be finite and >= 0");
-  if (p->ewald_mesh != 0 && (p->ewald_mesh < 16 || p->ewald_mesh > 512 || (p->ewald_mesh & (p->ewald_mesh - 1))))
-    return set_err(c, MBS_EINVAL, "ewald_mesh must be 0 or a power of 2 from 16 to 512");
+  if (p->ewald_mesh != 0 && p->ewald_mesh != -1 &&
+      (p->ewald_mesh < 16 || p->ewald_mesh > 512 || (p->ewald_mesh & (p->ewald_mesh - 1))))
+    return set_err(c, MBS_EINVAL, "ewald_mesh must be 0, -1 or a power of 2 from 16 to 512");
   if (p->ewald_mesh && !(p->box > 0.0)) return set_err(c, MBS_EINVAL, "ewald_mesh needs a periodic box");
   if (p->box > 0.0 && p->ewald_xi > 0.0 && !p->ewald_mesh && p->ewald_xi * p->box < 13.0)
     return set_err(c, MBS_EINVAL, "ewald_xi * box must be at least 13 (real-space cutoff within box/2)");
@@ -213,6 +214,15 @@ void apply_tiles(mbs_ctx* c) {
 // Workspace for n spheres and restart m.
 // the periodic box (params.box): splitting parameter, cutoffs and the wave vectors on the device
 bool periodic(const mbs_ctx* c) { return c->prm.box > 0.0; }
+// the mesh of params.ewald_mesh (-1: the smallest power of 2 from 16 to 512 whose spacing is at most
+// 1.25 a), 0 for the direct sums
+int mesh_M(const mbs_ctx* c) {
+  const int m = c->prm.ewald_mesh;
+  if (m != -1) return m;
+  int M = 16;
+  while (M < 512 && c->prm.box / M > 1.25 * c->prm.a) M *= 2;
+  return M;
+}
 // default splitting: xi L = max(13, 13 (n/10^4)^0.15), measured to balance the real-space pass (whose
 // pairs within rc fall as (xi L)^-3) against the Fourier passes (whose wave vectors grow as (xi L)^3)
 // With a mesh of M points per axis the default is xi = pi M / (14 box): the splitting factor
@@ -224,7 +234,7 @@ bool periodic(const mbs_ctx* c) { return c->prm.box > 0.0; }
 double per_xi(const mbs_ctx* c, int64_t n) {
   if (c->prm.ewald_xi > 0.0) return c->prm.ewald_xi;
   if (c->prm.ewald_mesh)
-    return std::max(10.0 / c->prm.box, std::min(M_PI * c->prm.ewald_mesh / (14.0 * c->prm.box), 0.5 / c->prm.a));
+    return std::max(10.0 / c->prm.box, std::min(M_PI * mesh_M(c) / (14.0 * c->prm.box), 0.5 / c->prm.a));
   return std::max(13.0, 13.0 * pow((double)n / 1e4, 0.15)) / c->prm.box;
 }
 // the real-space cutoff: 6.5/xi for the direct sums (below 1e-13 of the blocks), 5/xi with a mesh
@@ -239,12 +249,12 @@ PerBox per_box(const mbs_ctx* c, int64_t n) {
   const double xi = per_xi(c, n);
   const int2* seg = reinterpret_cast<const int2*>(c->per_seg.p);
   return PerBox{c->prm.box, xi, per_rc(c, xi), c->per_K, c->per_kv.p, seg, c->per_nseg8,
-                seg ? seg + c->per_nseg8 : nullptr, c->per_nseg4, c->prm.ewald_mesh, per_nc(c, xi),
+                seg ? seg + c->per_nseg8 : nullptr, c->per_nseg4, mesh_M(c), per_nc(c, xi),
                 c->per_tab.p, c->per_mws.p, c->per_rtab.p, c->prm.ewald_mesh ? c->per_rt_np : 0};
 }
 // the mesh's tables and workspace for n sources (particle-mesh Ewald)
 int pm_prepare(mbs_ctx* c, int64_t n) {
-  const int M = c->prm.ewald_mesh;
+  const int M = mesh_M(c);
   if (c->per_tabM != M || !c->per_tab.p) {
     const std::vector<double> t = pm_tables(M);
     CHK(ensure(c, c->per_tab, t.size()));
@@ -491,7 +501,7 @@ StepGraphs* step_graphs(mbs_ctx* c, int prec, int64_t n, const double* R, bool p
       dbits(c->ph.P), dbits(c->ph.a2),
       dbits(c->ph.gamma), dbits(c->ph.inv_gamma), (uintptr_t)c->prm.plane, dbits(c->prm.plane_z),
       dbits(c->prm.box), dbits(c->prm.ewald_xi), (uintptr_t)c->per_kv.p, (uintptr_t)c->per_K,
-      (uintptr_t)c->per_seg.p, (uintptr_t)c->per_nseg8, (uintptr_t)c->prm.ewald_mesh, (uintptr_t)c->per_tab.p,
+      (uintptr_t)c->per_seg.p, (uintptr_t)c->per_nseg8, (uintptr_t)mesh_M(c), (uintptr_t)c->per_tab.p,
       (uintptr_t)c->per_mws.p};
   StepGraphs& G = c->sgraph[prec == MBS_FP64 ? 0 : 1];
   if (key == G.key) return &G;

@@ -186,7 +186,7 @@ def test_pme_operator_sampled_rows(ctx, n, M, nrows):
 
 def test_pme_parameter_checks(ctx):
     L = 30.0
-    for bad in ({"ewald_mesh": 48}, {"ewald_mesh": 8}, {"ewald_mesh": 1024}, {"ewald_mesh": -64},
+    for bad in ({"ewald_mesh": 48}, {"ewald_mesh": 8}, {"ewald_mesh": 1024}, {"ewald_mesh": -64}, {"ewald_mesh": -2},
                 {"ewald_mesh": 64, "ewald_xi": 9.0 / L}):  # real-space cutoff beyond L/2
         with pytest.raises(mbstokes.MbsError) as e:
             ctx.set_params(box=L, **bad)
@@ -235,3 +235,16 @@ def test_pme_stepper_min_dist_from_the_box_grid(ctx, layout):
         stats, md = ctx.mbs_step(_t(w.R), _t(w.p), 0.0, (1.0, 1.0, 1.0), 0.01, 1, order=1, want_min_dist=True)
     assert (want < 10.5) == (layout == "random")
     assert abs(md[0] - want) < 1e-12 * L
+
+
+def test_pme_automatic_mesh_equals_its_explicit_size(ctx):
+    """ewald_mesh = -1 takes the smallest power of 2 with spacing at most 1.25a: the same result, bit
+    for bit, as naming that mesh."""
+    n = 300
+    w, L = _workload(n, 4700)  # box 42.2a: 64 points would space them 0.66a, 32 points 1.32a
+    x = np.random.default_rng(8).standard_normal((n, 5))
+    with _Mesh(ctx, L, -1):
+        auto = ctx.mbs_matvec(_t(w.R), _t(x))
+    with _Mesh(ctx, L, 64):
+        named = ctx.mbs_matvec(_t(w.R), _t(x))
+    assert torch.equal(auto, named)
