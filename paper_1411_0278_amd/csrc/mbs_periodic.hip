@@ -1048,8 +1048,9 @@ __global__ void __launch_bounds__(256)
 // read once into LDS after the y and z transforms, transformed along x, multiplied point pair by
 // point pair (m on this line with -m on the mirror line, each thread reading its pairs before the
 // barrier and writing after it), transformed back along x and written to the output fields, which
-// then take the inverse y and z transforms. The workgroup of the lower of the two lines does both
-// (a line that is its own mirror, y and z each 0 or M/2, alone). Needs 2 NI M <= 4096 (LDS).
+// then take the inverse y and z transforms. Workgroups enumerate one line of each mirror pair: every y
+// for 0 < z < M/2, and 0 <= y <= M/2 for z = 0 and z = M/2 (a line that is its own mirror, y and z
+// each 0 or M/2, alone): (M/2 - 1) M + M + 2 of them. Needs 2 NI M <= 4096 (LDS).
 template <int TGT>
 __global__ void __launch_bounds__(256)
     k_pm_xmult(const double2* __restrict__ fin, int M, double dk, double xi, double a2, double invL3,
@@ -1058,9 +1059,10 @@ __global__ void __launch_bounds__(256)
   constexpr int NC = pnc(sft(TGT)), W = pw(TGT), NI = (NC + 1) / 2, NO = (W + 1) / 2;
   constexpr int PPT = 2;  // point pairs per thread (M <= 512)
   extern __shared__ double2 xs[];
-  const int y = blockIdx.x % M, z = blockIdx.x / M;
+  const int h = M >> 1, b = blockIdx.x, nmid = (h - 1) * M;
+  const int z = b < nmid ? 1 + b / M : ((b - nmid) < h + 1 ? 0 : h);
+  const int y = b < nmid ? b % M : (b - nmid) % (h + 1);
   const int yp = (M - y) & (M - 1), zp = (M - z) & (M - 1);
-  if (z * M + y > zp * M + yp) return;  // (uniform) the mirror line's workgroup does both
   const bool self = y == yp && z == zp;
   const int nl = self ? NI : 2 * NI;
   const int64_t M3 = (int64_t)M * M * M;
@@ -1322,7 +1324,8 @@ void pm_launch(const double* X, int64_t m, const double* R, int64_t n, const dou
   }
   if (2 * NI * M <= 4096) {  // the x transforms fused with the multiplier
     pm_fft(fin, NI, M, false, tw, s, 6);
-    hipLaunchKernelGGL(k_pm_xmult<TGT>, dim3((unsigned)(M * M)), dim3(256), (size_t)2 * NI * M * sizeof(double2), s,
+    hipLaunchKernelGGL(k_pm_xmult<TGT>, dim3((unsigned)((M / 2 - 1) * M + M + 2)), dim3(256),
+                       (size_t)2 * NI * M * sizeof(double2), s,
                        fin, M, 2.0 * M_PI / g.L, g.xi, ph.a2, 1.0 / (g.L * g.L * g.L), bmod, tw, fft_plan(M), fout);
     pm_fft(fout, NO, M, true, tw, s, 6);
   } else {
