@@ -89,6 +89,7 @@ struct mbs_ctx {
   DevBuf per_mws;  // particle-mesh Ewald: mesh fields, weights and the sources' box grid
   int per_tabM = 0;
   DevBuf per_rtab;  // particle-mesh Ewald: the operator's radial table for the real-space pass
+  DevBuf per_fws;   // particle-mesh Ewald: the flow's field-point box grid
   int per_rt_np = 0;
   double per_rt_xi = 0.0, per_rt_a2 = 0.0, per_rt_rc = 0.0;
   // a solve in the Morton order of the centres: the permutation and the reordered inputs/outputs
@@ -250,7 +251,7 @@ PerBox per_box(const mbs_ctx* c, int64_t n) {
   const int2* seg = reinterpret_cast<const int2*>(c->per_seg.p);
   return PerBox{c->prm.box, xi, per_rc(c, xi), c->per_K, c->per_kv.p, seg, c->per_nseg8,
                 seg ? seg + c->per_nseg8 : nullptr, c->per_nseg4, mesh_M(c), per_nc(c, xi),
-                c->per_tab.p, c->per_mws.p, c->per_rtab.p, c->prm.ewald_mesh ? c->per_rt_np : 0};
+                c->per_tab.p, c->per_mws.p, c->per_rtab.p, c->prm.ewald_mesh ? c->per_rt_np : 0, nullptr, 0};
 }
 // the mesh's tables and workspace for n sources (particle-mesh Ewald)
 int pm_prepare(mbs_ctx* c, int64_t n) {
@@ -1468,7 +1469,7 @@ void mbs_destroy(mbs_ctx* c) {
                     &c->small, &c->H, &c->zeros, &c->stepbuf, &c->srcbuf, &c->orig, &c->near, &c->zt,
                     &c->nt, &c->stepstate,
                     &c->mlp_w, &c->mlp_g, &c->mlp_m, &c->mlp_v, &c->mlp_wb, &c->mlp_ws,
-                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->ord, &c->r3, &c->per_kv, &c->per_seg, &c->per_tab, &c->per_mws, &c->per_rtab,
+                    &c->mlp_part, &c->mlp_loss, &c->mlp_idx, &c->knn_buf, &c->grid, &c->ord, &c->r3, &c->per_kv, &c->per_seg, &c->per_tab, &c->per_mws, &c->per_rtab, &c->per_fws,
                     &c->bat, &c->btune};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
@@ -1698,7 +1699,13 @@ int mbs_flow_ex(mbs_ctx* c, int64_t m, const double* X, int64_t n, const double*
   if (periodic(c)) {  // the periodic suspension's flow (Ewald sums)
     if (high_mask(hi)) return set_err(c, MBS_EUNSUPPORTED, "the higher slip modes do not support params.box");
     CHK(ensure(c, c->part, (size_t)per_part_elems(m, n, c->per_K, c->per_nseg8)));
-    launch_per_flow(X, m, R, n, Fe, Te, Sigma, v3t, U, c->part.p, per_box(c, n), c->ph, s);
+    PerBox g = per_box(c, n);
+    if (g.M > 0 && g.nc >= 3) {  // the field points binned like the spheres: real space over cells
+      g.fws_bytes = pm_flow_ws_bytes(m, g.nc);
+      CHK(ensure(c, c->per_fws, (g.fws_bytes + 7) / 8));
+      g.fws = c->per_fws.p;
+    }
+    launch_per_flow(X, m, R, n, Fe, Te, Sigma, v3t, U, c->part.p, g, c->ph, s);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(s));
     return MBS_OK;

@@ -133,7 +133,10 @@ struct PerBox {
   void* mws;          // pm_ws_bytes(M, n, nc) bytes of device workspace (256-byte aligned)
   const double* rtab; // the operator's radial functions tabulated for the real-space pass (npiece > 0)
   int npiece;
+  void* fws;          // the flow's field-point box grid: pm_flow_ws_bytes(m, nc) bytes, or NULL (all pairs)
+  size_t fws_bytes;
 };
+size_t pm_flow_ws_bytes(int64_t m, int nc);
 // pieces of the radial table for spheres of radius^2 a2 and cutoff rc (0: no table); device doubles
 // to hold any table; the table of splitting xi built on stream s
 int pm_radial_pieces(double a2, double rc);

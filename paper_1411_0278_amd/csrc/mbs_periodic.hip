@@ -684,7 +684,8 @@ __global__ void __launch_bounds__(256) k_pm_prep(const double* __restrict__ Rs, 
 }
 
 // the real-space pass over the sources' box grid (cells of edge >= rc, at least 3 per axis, so a
-// receiver's partners within rc lie in its own and the 26 neighbouring cells, each met once): a
+// receiver's partners within rc lie in its own and the 26 neighbouring cells, each met once), the
+// receivers from a box grid of the same cells (the spheres' own, or the field points'): a
 // workgroup per (cell, layer of neighbouring cells along z), its receivers 128 at a time, the 9 cells
 // of the layer staged through LDS with the same bit-mask evaluation as k_per_real; partial sums
 // part[(layer * m + i) * W] at the receivers' own indices
@@ -693,8 +694,10 @@ constexpr int kPmRT = 128;  // threads of the cell real-space kernel (receivers 
 
 template <int TGT>
 __global__ void __launch_bounds__(kPmRT)
-    k_pm_real(const double* __restrict__ Rs, const int32_t* __restrict__ perm, const int32_t* __restrict__ cstart,
-              const int32_t* __restrict__ cend, int nc, int m, const double* __restrict__ Fe,
+    k_pm_real(const double* __restrict__ RsR, const int32_t* __restrict__ permR, const int32_t* __restrict__ cstartR,
+              const int32_t* __restrict__ cendR, const double* __restrict__ Rs, const int32_t* __restrict__ perm,
+              const int32_t* __restrict__ cstart, const int32_t* __restrict__ cend, int nc, int m,
+              const double* __restrict__ Fe,
               const double* __restrict__ Te, const double* __restrict__ Sig, const double* __restrict__ D, double L,
               double rc2, double xi, double a2, double P, double a5_20, const double* __restrict__ rtab,
               int npiece, double inv_slo, double* __restrict__ part) {
@@ -710,11 +713,11 @@ __global__ void __launch_bounds__(kPmRT)
   const int jzr = iz + (int)blockIdx.y - 1;
   const int jz = (jzr + nc) % nc;
   const double shz = jzr < 0 ? -L : (jzr >= nc ? L : 0.0);
-  const int r0 = cstart[cell], r1 = cend[cell];
+  const int r0 = cstartR[cell], r1 = cendR[cell];
   for (int rb = r0; rb < r1; rb += kPmRT) {
     const int k = rb + threadIdx.x;
     const int kk = k < r1 ? k : r1 - 1;
-    const double xi0 = Rs[4 * (int64_t)kk], yi0 = Rs[4 * (int64_t)kk + 1], zi0 = Rs[4 * (int64_t)kk + 2];
+    const double xi0 = RsR[4 * (int64_t)kk], yi0 = RsR[4 * (int64_t)kk + 1], zi0 = RsR[4 * (int64_t)kk + 2];
     double acc[W];
 #pragma unroll
     for (int c = 0; c < W; ++c) acc[c] = 0.0;
@@ -761,7 +764,7 @@ __global__ void __launch_bounds__(kPmRT)
       }
     }
     if (k < r1) {
-      double* o = part + ((int64_t)blockIdx.y * m + perm[k]) * W;
+      double* o = part + ((int64_t)blockIdx.y * m + permR[k]) * W;
 #pragma unroll
       for (int c = 0; c < W; ++c) o[c] = acc[c];
     }
@@ -1336,17 +1339,20 @@ void pm_launch(const double* X, int64_t m, const double* R, int64_t n, const dou
   }
   // real space: over the box grid's neighbouring cells when it has at least 3 cells per axis (the
   // spheres as receivers), else over all pairs; the mesh part interpolated at the receivers
-  const bool cells = TGT != kPFlow && g.nc >= 3;
+  // (field points take the cells too when the caller gave a workspace for their box grid)
+  const bool cells = g.nc >= 3 && (TGT != kPFlow || g.fws);
   const PerShape sh = per_shape(m, 0, 0);
   const int nreal = cells ? 3 : sh.nreal;
   double* preal = part;
   double* precip = preal + (int64_t)nreal * W * m;
   if (cells) {
+    GridView gr = gv;
+    if (TGT == kPFlow) (void)grid_build_box(X, (int)m, g.L, g.nc, g.fws, g.fws_bytes, &gr, s);
     const double* rtab = TGT == kPOp && g.npiece > 0 ? g.rtab : nullptr;
     hipLaunchKernelGGL(k_pm_real<TGT>, dim3((unsigned)g.nc * g.nc * g.nc, 3), dim3(kPmRT),
-                       rtab ? (size_t)g.npiece * kRtC * sizeof(double) : 0, s, gv.Rs, gv.perm, gv.start, gv.end, g.nc,
-                       (int)m, Fe, Te, Sig, D, g.L, g.rc * g.rc, g.xi, ph.a2, ph.P, a5_20, rtab, g.npiece,
-                       1.0 / ph.a2, preal);
+                       rtab ? (size_t)g.npiece * kRtC * sizeof(double) : 0, s, gr.Rs, gr.perm, gr.start, gr.end,
+                       gv.Rs, gv.perm, gv.start, gv.end, g.nc, (int)m, Fe, Te, Sig, D, g.L, g.rc * g.rc, g.xi, ph.a2,
+                       ph.P, a5_20, rtab, g.npiece, 1.0 / ph.a2, preal);
   } else {
     const int creal = (int)((n + sh.nreal - 1) / sh.nreal);
     hipLaunchKernelGGL(k_per_real<TGT>, dim3(nblk_p(m, kPBlk), sh.nreal), dim3(kPBlk), 0, s, X, (int)m, R, (int)n,
@@ -1453,6 +1459,8 @@ int64_t per_part_elems(int64_t m, int64_t n, int K, int nseg) {
 }
 
 size_t pm_ws_bytes(int M, int64_t n, int nc) { return pm_layout(M, n, nc).total; }
+
+size_t pm_flow_ws_bytes(int64_t m, int nc) { return grid_ws_bytes((int)m, (int64_t)nc * nc * nc); }
 
 int pm_radial_pieces(double a2, double rc) {
   const double ratio = rc * rc / a2;

@@ -157,9 +157,12 @@ def test_pme_solve_matches_oracle(ctx):
         assert torch.equal(V, V2) and torch.equal(W, W2)  # the second solve replays the captured steps
 
 
-def test_pme_flow_field_matches_oracle(ctx):
-    n, m, M = 97, 240, 64
-    w, L = _workload(n, 4300)
+@pytest.mark.parametrize("n,M", [(97, 64), (300, 128)])
+def test_pme_flow_field_matches_oracle(ctx, n, M):
+    # 300 spheres: the field points binned in a box grid like the spheres, real space over cells
+    print(f"pme flow n={n} M={M}", flush=True)
+    m = 240
+    w, L = _workload(n, 4300 + n)
     Sig = np.random.default_rng(21).standard_normal((n, 5))
     X = np.random.default_rng(22).uniform(-0.5 * L, 1.5 * L, (m, 3))  # anywhere: taken modulo the box
     want = periodic.flow_field(X, w.R, w.Fe, w.Te, Sig, w.v3t, PRM, _ew(L))
