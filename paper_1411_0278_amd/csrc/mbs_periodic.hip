@@ -284,6 +284,90 @@ __device__ __forceinline__ void real_pair(const RecP& s, double xi0, double yi0,
   real_pair_d<TGT>(s, wrap(xi0 - s.x, L, invL), wrap(yi0 - s.y, L, invL), wrap(zi0 - s.z, L, invL), xi, a2, acc);
 }
 
+// position of the k-th (from 0) set bit of m
+__device__ __forceinline__ int kth_bit(uint64_t m, int k) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const uint64_t low = (1ull << w) - 1ull;
+    const int c = __popcll(m & low);
+    if (k >= c) {
+      k -= c;
+      m >>= w;
+      pos += w;
+    } else {
+      m &= low;
+    }
+  }
+  return pos;
+}
+
+// A wavefront's hits (receiver lane, record of the LDS tile) dealt out evenly over its 64 lanes, 64
+// per round, in the order of the lanes and then of the records, each lane evaluating one pair; the
+// contributions summed back per receiver by a segmented scan across the lanes and added to the
+// receiver's sums (a fixed order: bitwise reproducible). Every lane of the wavefront must call it.
+// WRAP: the separation taken as the minimum image (else the records already stand at it).
+template <int TGT, bool WRAP>
+__device__ __forceinline__ void tile_hits(const RecP* tile, uint64_t hits, double xi0, double yi0, double zi0,
+                                          double L, double invL, double xi, double a2, double* acc,
+                                          const double* rt, int npiece, double inv_slo) {
+  constexpr int W = pw(TGT);
+  const int lane = threadIdx.x & 63;
+  const int c = __popcll(hits);
+  int inc = c;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += t;
+  }
+  const int off = inc - c;
+  const int T = __shfl(inc, 63, 64);
+  for (int base = 0; base < T; base += 64) {
+    const int e = base + lane;
+    int src = 0;  // the receiver lane holding entry e: the last lane with off <= e
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+      const int cand = src + w;
+      const int o = __shfl(off, cand < 64 ? cand : 63, 64);
+      if (cand < 64 && o <= e) src = cand;
+    }
+    const int osrc = __shfl(off, src, 64);
+    const uint64_t hsrc = __shfl(hits, src, 64);
+    const double xr = __shfl(xi0, src, 64), yr = __shfl(yi0, src, 64), zr = __shfl(zi0, src, 64);
+    double v[W];
+#pragma unroll
+    for (int cc = 0; cc < W; ++cc) v[cc] = 0.0;
+    if (e < T) {
+      const RecP& s = tile[kth_bit(hsrc, e - osrc)];
+      double dx = xr - s.x, dy = yr - s.y, dz = zr - s.z;
+      if (WRAP) {
+        dx = wrap(dx, L, invL);
+        dy = wrap(dy, L, invL);
+        dz = wrap(dz, L, invL);
+      }
+      real_pair_d<TGT>(s, dx, dy, dz, xi, a2, v, rt, npiece, inv_slo);
+    }
+    // inclusive scan within each receiver's run of entries (runs are contiguous)
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int sup = __shfl_up(src, d, 64);
+#pragma unroll
+      for (int cc = 0; cc < W; ++cc) {
+        const double t = __shfl_up(v[cc], d, 64);
+        if (lane >= d && sup == src) v[cc] += t;
+      }
+    }
+    // each receiver takes the sum at the last of its entries in this round
+    const int lo = max(off, base), hi = min(off + c, base + 64);
+    const int last = hi > lo ? hi - 1 - base : 0;
+#pragma unroll
+    for (int cc = 0; cc < W; ++cc) {
+      const double t = __shfl(v[cc], last, 64);
+      if (hi > lo) acc[cc] += t;
+    }
+  }
+}
+
 template <int TGT>
 __global__ void __launch_bounds__(kPBlk)
     k_per_real(const double* __restrict__ X, int m, const double* __restrict__ R, int n,
@@ -316,6 +400,9 @@ __global__ void __launch_bounds__(kPBlk)
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
       hits |= (uint64_t)(r2 < rc2 && r2 > 0.0) << jj;
     }
+    // (each lane its own hits: with the exact pair arithmetic and the larger share of pairs within rc
+    // of the direct sums, dealing the hits out evenly, as the mesh's cell pass does, was slower here:
+    // 70.7 -> 89.4 ms at 10^5 spheres)
     while (hits) {
       const int jj = __ffsll((unsigned long long)hits) - 1;
       hits &= hits - 1;
@@ -692,6 +779,7 @@ __global__ void __launch_bounds__(256) k_pm_prep(const double* __restrict__ Rs, 
 constexpr int kPmRT = 128;  // threads of the cell real-space kernel (receivers per round)
 
 
+
 template <int TGT>
 __global__ void __launch_bounds__(kPmRT)
     k_pm_real(const double* __restrict__ RsR, const int32_t* __restrict__ permR, const int32_t* __restrict__ cstartR,
@@ -755,12 +843,8 @@ __global__ void __launch_bounds__(kPmRT)
           const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
           hits |= (uint64_t)(r2 < rc2 && r2 > 0.0) << q;
         }
-        while (hits) {
-          const int q = __ffsll((unsigned long long)hits) - 1;
-          hits &= hits - 1;
-          real_pair_d<TGT>(tile[q], xi0 - tile[q].x, yi0 - tile[q].y, zi0 - tile[q].z, xi, a2, acc,
-                           rtab ? rt : nullptr, npiece, inv_slo);
-        }
+        if (k >= r1) hits = 0;  // (a lane past the cell's last receiver)
+        tile_hits<TGT, false>(tile, hits, xi0, yi0, zi0, L, 0.0, xi, a2, acc, rtab ? rt : nullptr, npiece, inv_slo);
       }
     }
     if (k < r1) {
