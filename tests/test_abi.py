@@ -40,10 +40,25 @@ def test_default_params_and_struct_layout():
     p = mbstokes.default_params()
     assert p.lmax == 2 and p.restart == 30 and abs(p.tol - 1e-10) < 1e-25
     assert abs(p.eta * 6 * 3.141592653589793 - 1) < 1e-15 and p.a == 1.0
-    assert p.plane == 0 and p.plane_z == 0.0 and p.box == 0.0 and p.ewald_xi == 0.0
+    assert p.plane == 0 and p.plane_z == 0.0 and p.box == 0.0 and p.ewald_xi == 0.0 and p.ewald_mesh == 0
     assert ctypes.sizeof(mbstokes.Params) == 9 * 8 + 14 * 4
     assert ctypes.sizeof(mbstokes.Stats) == 4 * 4 + 8 * 8 + 2 * 4
     assert ctypes.sizeof(mbstokes.SlipEx) == 3 * 8
+
+
+def _struct_fields(name):
+    """Field names of `typedef struct name { ... } name;` in the header, in order."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), txt, flags=re.S).group(1)
+    return re.findall(r"\b(?:const\s+)?(?:int32_t|int64_t|double|float|uint32_t)\s*\*?\s*([a-z_0-9]+)\s*;", body)
+
+
+def test_binding_structs_match_the_header_field_by_field():
+    """The ctypes mirrors of the parameter, statistics and slip structs name the header's fields in the
+    header's order (a field added, renamed or moved on one side only would shift the others)."""
+    for cname, py in (("mbs_params", mbstokes.Params), ("mbs_stats", mbstokes.Stats),
+                      ("mbs_slip_ex", mbstokes.SlipEx)):
+        assert _struct_fields(cname) == [f[0] for f in py._fields_], cname
 
 
 def test_create_without_gpu_fails_cleanly():
