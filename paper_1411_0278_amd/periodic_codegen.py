@@ -4,7 +4,8 @@ periodic cubic box (Ewald summation of the periodic Oseen tensor).
 Run from the repository root after changing the derivation (the header is committed; the library
 build only compiles it):
 
-    python -m paper_1411_0278_amd.periodic_codegen
+    python -m paper_1411_0278_amd.periodic_codegen            (--check: compare only, exit status 1 if
+                                                                the committed header differs)
 
 The periodic Oseen tensor with zero mean velocity over the box (Hasimoto's procedure) is split with
 a parameter xi into a real-space part summed over the images within a cutoff and a Fourier part
@@ -534,6 +535,10 @@ def generate():
 def main(argv=None):
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "mbs_periodic_gen.h")
     text = generate()
+    if argv and "--check" in argv:  # the committed header is what the derivation writes
+        same = open(out).read() == text
+        print("up to date" if same else "differs from the derivation", out)
+        sys.exit(0 if same else 1)
     with open(out, "w") as fh:
         fh.write(text)
     print("wrote", out)
