@@ -161,7 +161,7 @@ typedef struct mbs_params {
                             vectors (O(N K), the default); -1: M chosen as the smallest power of 2
                             from 16 to 512 with box/M <= 1.25 a; M = a power of 2 from 16 to 512: smooth
                             particle-mesh Ewald on an M^3 mesh of spacing box/M, the fast
-                            matrix-vector product that the paper leaves to future work (SIV): every
+                            matrix-vector product that the paper leaves to future work (section IV): every
                             sphere's coefficients spread onto the mesh by cardinal B-splines of
                             order 8, one 3D FFT, the same Fourier multipliers per mesh wave vector
                             (|m| < M/2 per axis), the inverse FFT interpolated back with the same
@@ -172,7 +172,8 @@ typedef struct mbs_params {
                             Fourier part at the default xi (smaller xi or larger M: smaller), instead
                             of the direct sums' 1e-13; it grows roughly as (xi a)^7 once xi a exceeds
                             about 0.5 (boxes under 20a). Device memory: 160 M^3
-                            bytes of mesh fields plus about 270 bytes per sphere. Other values are
+                            bytes of mesh fields plus about 270 bytes per sphere (and about 60 per
+                            field point in mbs_flow). Other values are
                             MBS_EINVAL, as is a mesh without a box */
   double  plane_z;       /* height of the plane (plane != 0) */
   double  box;           /* > 0: the spheres fill a periodic cubic box of this side (the paper's remark
